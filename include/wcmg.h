@@ -1,0 +1,203 @@
+/*
+ * wcmg.h -- C ABI of the Wilson-clover adaptive-multigrid library for AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The library solves the lattice Dirac equation of Osborn et al.,
+ * "Multigrid solver for clover fermions" (Lattice 2010), Eq.(1):
+ *
+ *     [D(U) + m] psi = eta        for varying sources eta and gauge fields U,
+ *
+ * with GCR preconditioned by an adaptive multigrid cycle built on the
+ * red-black preconditioned operator of Eqs.(2)-(4).  All arithmetic runs in
+ * hand-written HIP kernels on one GPU; the host code only sequences kernels.
+ *
+ * Conventions (the paper leaves them open; these are the library's choice):
+ *   D psi(x) = (4+m0) psi(x)
+ *            - 1/2 sum_mu [ (1-gamma_mu) U_mu(x) psi(x+mu)
+ *                         + (1+gamma_mu) U_mu(x-mu)^dag psi(x-mu) ]
+ *            + csw (i/4) sum_{mu!=nu} sigma_mu_nu Fhat_mu_nu(x) psi(x)
+ *   sigma_mu_nu = (i/2)[gamma_mu, gamma_nu], Fhat = (Q - Q^dag)/8 with Q the
+ *   sum of the four plaquette leaves; chiral gamma basis with
+ *   gamma5 = diag(1,1,-1,-1); directions mu = x,y,z,t; periodic in space,
+ *   time boundary phase t_bc (-1 antiperiodic, +1 periodic).
+ *
+ * Canonical layouts (interleaved complex, little endian):
+ *   gauge   complex128 [Lt][Lz][Ly][Lx][4 mu][3][3]
+ *   spinor  complex128 [nrhs][Lt][Lz][Ly][Lx][4 spin][3 colour]
+ *   coarse  complex128 [nrhs][Vc][2*Nv]   coarse site lex order, component
+ *           s*Nv + k (s = 0: gamma5 = +1 chirality, s = 1: -1)
+ *   coarse operator complex128 [Vc][9][2Nv][2Nv]: slot 0 the site block X,
+ *           slot 1+d the hop to direction d = 2*mu (+mu) or 2*mu+1 (-mu).
+ *
+ * Ownership: every buffer argument belongs to the caller.  Pointers marked
+ * "device" must be device memory of the context's GPU; "host" pointers are
+ * read or written before the call returns.  The library keeps its own
+ * copies (in its internal even-odd layouts) of everything it is given and
+ * never retains a caller pointer.  Work is enqueued on the stream given to
+ * wcmg_create; apply/restrict/prolong return without synchronising, solve
+ * and the setup calls synchronise the stream before returning.
+ *
+ * Errors: every call returns an int status, 0 = WCMG_OK.  No exception or
+ * abort crosses the ABI.  Arguments are validated before any device call;
+ * on error wcmg_last_error() returns a message (thread-local).
+ */
+#ifndef WCMG_H
+#define WCMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  WCMG_OK = 0,
+  WCMG_EINVAL = 1,          /* bad argument (null pointer, bad enum, range) */
+  WCMG_EDIM = 2,            /* odd extent, block does not divide, Nv too large */
+  WCMG_ESTATE = 3,          /* call made before its prerequisites */
+  WCMG_ENOCONV = 4,         /* solver hit max_iter; x holds the last iterate */
+  WCMG_EBREAKDOWN = 5,      /* Krylov breakdown (rho or omega = 0) */
+  WCMG_ENAN = 6,            /* NaN/Inf met in a residual norm */
+  WCMG_ECLOVER_NOT_PD = 7,  /* clover block not positive definite */
+  WCMG_ERANK = 8,           /* null vectors linearly dependent on a block */
+  WCMG_ENOMEM = 9,          /* device allocation failed */
+  WCMG_EHIP = 10,           /* HIP runtime error */
+  WCMG_ENODEV = 11          /* no usable GPU */
+};
+
+typedef enum { WCMG_F64 = 0, WCMG_F32 = 1, WCMG_F16 = 2 } wcmg_prec;
+
+/* operator forms (red-black paragraph, Eqs.(2)-(3)):
+ *   FULL  D of Eq.(1), both parities;
+ *   SCHUR D_r = 1 - D_eo D_oo^-1 D_oe D_ee^-1 acting on even sites (odd
+ *         sites of the input are ignored, odd sites of the output are zero);
+ *   DP    D_p = D diag(D_ee, D_oo)^-1, both parities. */
+typedef enum { WCMG_OP_FULL = 0, WCMG_OP_SCHUR = 1, WCMG_OP_DP = 2 } wcmg_op;
+
+typedef enum { WCMG_MG_GCR = 0, WCMG_GCR = 1, WCMG_BICGSTAB = 2 } wcmg_solver;
+
+typedef struct {
+  int dims[4]; /* Lx, Ly, Lz, Lt; each even and >= 2 */
+  int t_bc;    /* -1 antiperiodic (default), +1 periodic */
+} wcmg_lattice;
+
+#define WCMG_MAX_LEVELS 3
+
+/* Multigrid parameters (Implementation paragraph, Table 1, Setup section).
+ * Level l = 0 is the fine lattice; coarse level l+1 is built from level l
+ * with block[l] and nvec[l]. */
+typedef struct {
+  int nlevels;                      /* number of coarse levels, 1..WCMG_MAX_LEVELS */
+  int block[WCMG_MAX_LEVELS][4];    /* aggregate (block) extents per level */
+  int nvec[WCMG_MAX_LEVELS];        /* null vectors per level (coarse dim 2*nvec) */
+  double tol[WCMG_MAX_LEVELS];      /* relative tolerance of the GCR on coarse level l+1 */
+  int max_iter[WCMG_MAX_LEVELS];    /* cap of that GCR */
+  int restart[WCMG_MAX_LEVELS];     /* its restart length */
+  int nu_post;                      /* MR smoothing steps after the coarse correction */
+  int outer_restart;                /* restart length of the outer FP64 GCR */
+  int outer_max_iter;               /* cap of the outer GCR */
+  wcmg_prec smoother_prec;          /* precision of the preconditioner (F32 or F64) */
+  int setup_relax;                  /* GCR steps per relaxation in the setup */
+  int setup_max_steps;              /* max relaxations per vector */
+  double setup_rq_tol;              /* stop when |d rho| / rho < this */
+  uint64_t seed;                    /* Philox4x32-10 key for the random start vectors */
+  int coarsest;                     /* 0: unpreconditioned GCR (paper), 1: dense LU (FP64) */
+} wcmg_mg_params;
+
+typedef struct {
+  int iters;               /* outer iterations (GCR) or BiCGStab iterations */
+  double inner_iters[WCMG_MAX_LEVELS]; /* mean inner GCR iterations per call, coarse level l+1 */
+  double true_rel_res;     /* ||b - D x|| / ||b|| recomputed in FP64 after the solve */
+  double t_solve_s;        /* wall time of the solve on the host clock */
+  int status;              /* WCMG_OK or the failure code for this right-hand side */
+} wcmg_stats;
+
+/* Fill *p with the library defaults (2 levels, 4^4 blocks, Nv = 24,
+ * tol 0.1, MR(4) post-smoothing, FP32 preconditioner). */
+int wcmg_mg_params_default(wcmg_mg_params* p);
+
+/* Create a context for nlat lattices on the current HIP device.
+ * lats: host array of nlat descriptors.  hip_stream: a hipStream_t or NULL
+ * for the null stream.  *out receives the handle.  Fails with ENODEV when
+ * no GPU is visible, EDIM for an odd or too small extent. */
+int wcmg_create(const wcmg_lattice* lats, int nlat, void* hip_stream, void** out);
+int wcmg_destroy(void* ctx);
+
+/* Gauge field U of Eq.(1) in the canonical layout (host or device per
+ * on_device).  The library converts it to its internal layouts in every
+ * precision.  Invalidates clover and multigrid state of that lattice. */
+int wcmg_set_gauge(void* ctx, int lat, const void* U, int on_device);
+
+/* Site-diagonal part D_ee / D_oo (red-black paragraph): (4+m0) + clover.
+ * A == NULL: computed on the GPU from the gauge field with coefficient csw.
+ * Otherwise A is complex128 [V][12][12] (host/device per on_device) and
+ * csw is ignored.  The inverse comes from a per-chirality Cholesky; fails
+ * with ECLOVER_NOT_PD if a block is not positive definite. */
+int wcmg_set_clover(void* ctx, int lat, double m0, double csw, const void* A, int on_device);
+
+/* Fix the multigrid shape (blocks, Nv, tolerances) for a lattice. EDIM if
+ * a block does not divide its level or 2*Nv exceeds the block's degrees of
+ * freedom per chirality. */
+int wcmg_set_mg_params(void* ctx, int lat, const wcmg_mg_params* p);
+
+/* Setup section: for each vector, repeated relaxation (inverse iteration)
+ * on a Philox random start vector while the Rayleigh quotient
+ * ||D_p v||^2/||v||^2 is monitored, keeping v globally orthogonal to the
+ * vectors already found.  Level 0 relaxes on the fine D_p; level l > 0 on
+ * the coarse D_p of level l (which must be built).  Synchronises. */
+int wcmg_build_null_vectors(void* ctx, int lat, int level);
+
+/* Import or export raw null vectors of a level (saved setups, Results
+ * section).  Level 0: nvec fine spinors in the canonical spinor layout;
+ * level l > 0: nvec coarse vectors of level l.  nvec must equal the
+ * parameters' nvec[level]. */
+int wcmg_set_null_vectors(void* ctx, int lat, int level, const void* v, int nvec, int on_device);
+int wcmg_get_null_vectors(void* ctx, int lat, int level, void* v, int on_device);
+
+/* Coarse operator of level+1: block x chirality split and orthonormalise
+ * the level's vectors (P), then Yhat = R D_p P with R = P^dag gamma5
+ * (red-black paragraph), its site-block inverses and the red-black
+ * preconditioned hops.  Synchronises. */
+int wcmg_build_coarse(void* ctx, int lat, int level);
+/* Copy Yhat of coarse level level+1 (canonical coarse-operator layout). */
+int wcmg_get_coarse(void* ctx, int lat, int level, void* Y, int on_device);
+
+/* out = op(in) or op^dag(in) for nrhs canonical spinors (device).  prec is
+ * the storage/arithmetic precision of the internal apply (F16 stores
+ * fields in half precision with FP32 arithmetic).  Asynchronous. */
+int wcmg_apply_D(void* ctx, int lat, int op, int prec, void* out, const void* in, int nrhs);
+int wcmg_apply_Ddag(void* ctx, int lat, int op, int prec, void* out, const void* in, int nrhs);
+
+/* Transfer operators between level and level+1 (device buffers):
+ * restrict: coarse = R fine = P^dag gamma5 fine;  prolong: fine = P coarse.
+ * Level 0 fine vectors are canonical spinors (both parities). */
+int wcmg_restrict(void* ctx, int lat, int level, int prec, void* coarse_out, const void* fine_in, int nrhs);
+int wcmg_prolong(void* ctx, int lat, int level, int prec, void* fine_out, const void* coarse_in, int nrhs);
+
+/* Coarse stencil of coarse level `level` (>= 1) in form op (FULL: Yhat,
+ * SCHUR: 1 - Yhat_eo X_oo^-1 Yhat_oe X_ee^-1, DP: Yhat X^-1). */
+int wcmg_apply_coarse(void* ctx, int lat, int level, int op, int prec, void* out, const void* in, int nrhs);
+
+/* Solve D x = b for nrhs canonical right-hand sides (device).  x is the
+ * initial guess on entry if nonzero.  Stops when ||b - D x|| <= tol ||b||
+ * (true residual recomputed in FP64).  stats: host array of nrhs entries
+ * or NULL.  MG_GCR: outer FP64 GCR on D_r preconditioned by the cycle;
+ * GCR / BICGSTAB: unpreconditioned FP64 on D_r.  Synchronises.  Returns the
+ * worst status over the right-hand sides. */
+int wcmg_solve(void* ctx, int lat, int solver, void* x, const void* b, int nrhs, double tol, wcmg_stats* stats);
+
+/* Per-kernel timing with HIP events on the context's stream.
+ * wcmg_timer_enable(ctx, 1) starts recording each launch of the fine
+ * Dslash kernels; wcmg_timer_read returns the launch count and the summed
+ * duration in milliseconds for kernel class `which` (0 = fine Dslash hop,
+ * 1 = coarse stencil) since the last reset, synchronising the stream. */
+int wcmg_timer_enable(void* ctx, int on);
+int wcmg_timer_read(void* ctx, int which, long* count, double* total_ms);
+
+const char* wcmg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WCMG_H */

@@ -1,0 +1,351 @@
+// BLAS-1 kernels for the Krylov solvers (GCR, BiCGStab, MR).
+//
+// Vectors are flat arrays of complex numbers in double or float storage;
+// every reduction accumulates in double, first per wavefront with lane
+// shuffles, then across the 4 wavefronts of a block in LDS, then in a
+// single-block second pass over the per-block partials.  The grid size is
+// fixed, so results are bitwise reproducible run to run.
+#include "kernels.h"
+
+namespace wcmg {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kMaxK = 16;
+
+template <typename T>
+struct C2;
+template <>
+struct C2<double> {
+  using V = double2;
+};
+template <>
+struct C2<float> {
+  using V = float2;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<double> ld(const void* p, size_t i) {
+  auto v = reinterpret_cast<const typename C2<T>::V*>(p)[i];
+  return mk((double)v.x, (double)v.y);
+}
+template <typename T>
+__device__ __forceinline__ void st(void* p, size_t i, cpx<double> c) {
+  using V = typename C2<T>::V;
+  V v;
+  v.x = (T)c.r;
+  v.y = (T)c.i;
+  reinterpret_cast<V*>(p)[i] = v;
+}
+
+// reduce NR doubles over the block, write partial[blockIdx.x*NR + k]
+template <int NR>
+__device__ __forceinline__ void block_reduce(double (&v)[NR], double* partial) {
+  __shared__ double sh[NR][kThreads / 64];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NR; ++k) sh[k][wave] = v[k];
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < NR) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) s += sh[threadIdx.x][w];
+    partial[(size_t)blockIdx.x * NR + threadIdx.x] = s;
+  }
+}
+
+// one block: res[k] = sum_b partial[b*nr + k], fixed order
+__global__ void __launch_bounds__(kThreads) finalize_kernel(const double* partial, int nblocks, int nr,
+                                                            double* res) {
+  __shared__ double sh[kThreads];
+  for (int k = 0; k < nr; ++k) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += kThreads) s += partial[(size_t)b * nr + k];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) res[k] = sh[0];
+    __syncthreads();
+  }
+}
+
+void finalize(const double* partial, int nr, double* res, hipStream_t st) {
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kThreads), 0, st, partial, kRedBlocks, nr, res);
+  HIPCHK(hipGetLastError());
+}
+
+inline dim3 red_grid() { return dim3(kRedBlocks); }
+inline dim3 ew_grid(size_t n) {
+  size_t b = (n + kThreads - 1) / kThreads;
+  if (b > 65536) b = 65536;
+  if (b == 0) b = 1;
+  return dim3((unsigned)b);
+}
+
+#define GRID_STRIDE(i, n) \
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (size_t)gridDim.x * blockDim.x)
+
+template <typename T>
+__global__ void k_zero(void* x, size_t n) {
+  GRID_STRIDE(i, n) st<T>(x, i, mk(0.0, 0.0));
+}
+template <typename T>
+__global__ void k_copy(void* y, const void* x, size_t n) {
+  GRID_STRIDE(i, n) st<T>(y, i, ld<T>(x, i));
+}
+template <typename T>
+__global__ void k_axpby(double ar, double ai, const void* x, double br, double bi, void* y, size_t n) {
+  cpx<double> a = mk(ar, ai), b = mk(br, bi);
+  GRID_STRIDE(i, n) st<T>(y, i, a * ld<T>(x, i) + b * ld<T>(y, i));
+}
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_norm2(const void* x, size_t n, double* partial) {
+  double v[1] = {0.0};
+  GRID_STRIDE(i, n) {
+    cpx<double> a = ld<T>(x, i);
+    v[0] += a.r * a.r + a.i * a.i;
+  }
+  block_reduce<1>(v, partial);
+}
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_cdot(const void* x, const void* y, size_t n, double* partial) {
+  double v[2] = {0.0, 0.0};
+  GRID_STRIDE(i, n) {
+    cpx<double> a = ld<T>(x, i), b = ld<T>(y, i);
+    v[0] += a.r * b.r + a.i * b.i;
+    v[1] += a.r * b.i - a.i * b.r;
+  }
+  block_reduce<2>(v, partial);
+}
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_cdot_norm(const void* x, const void* y, size_t n, double* partial) {
+  double v[3] = {0.0, 0.0, 0.0};
+  GRID_STRIDE(i, n) {
+    cpx<double> a = ld<T>(x, i), b = ld<T>(y, i);
+    v[0] += a.r * b.r + a.i * b.i;
+    v[1] += a.r * b.i - a.i * b.r;
+    v[2] += a.r * a.r + a.i * a.i;
+  }
+  block_reduce<3>(v, partial);
+}
+
+struct MultiArgs {
+  const void* v[kMaxK];
+  const void* w[kMaxK];
+  double c[2 * kMaxK];
+};
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_multi_cdot(MultiArgs m, int k, const void* y, size_t n,
+                                                         double* partial) {
+  double v[2 * kMaxK];
+#pragma unroll
+  for (int j = 0; j < 2 * kMaxK; ++j) v[j] = 0.0;
+  GRID_STRIDE(i, n) {
+    cpx<double> b = ld<T>(y, i);
+#pragma unroll
+    for (int j = 0; j < kMaxK; ++j) {
+      if (j < k) {
+        cpx<double> a = ld<T>(m.v[j], i);
+        v[2 * j] += a.r * b.r + a.i * b.i;
+        v[2 * j + 1] += a.r * b.i - a.i * b.r;
+      }
+    }
+  }
+  block_reduce<2 * kMaxK>(v, partial);
+}
+
+template <typename T>
+__global__ void k_multi_axpy(MultiArgs m, int k, void* y, size_t n) {
+  GRID_STRIDE(i, n) {
+    cpx<double> acc = ld<T>(y, i);
+#pragma unroll
+    for (int j = 0; j < kMaxK; ++j)
+      if (j < k) acc = acc + mk(m.c[2 * j], m.c[2 * j + 1]) * ld<T>(m.v[j], i);
+    st<T>(y, i, acc);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_gcr_orth(MultiArgs m, int k, void* y, void* z, const void* r,
+                                                       size_t n, int do_red, double* partial) {
+  double v[3] = {0.0, 0.0, 0.0};
+  GRID_STRIDE(i, n) {
+    cpx<double> a = ld<T>(y, i), b = ld<T>(z, i);
+#pragma unroll
+    for (int j = 0; j < kMaxK; ++j) {
+      if (j < k) {
+        cpx<double> c = mk(m.c[2 * j], m.c[2 * j + 1]);
+        a = a - c * ld<T>(m.v[j], i);
+        b = b - c * ld<T>(m.w[j], i);
+      }
+    }
+    st<T>(y, i, a);
+    st<T>(z, i, b);
+    if (do_red) {
+      // reduce the rounded (stored) values so the norms match the vectors
+      cpx<double> as = ld<T>(y, i), rr = ld<T>(r, i);
+      v[0] += as.r * as.r + as.i * as.i;
+      v[1] += as.r * rr.r + as.i * rr.i;
+      v[2] += as.r * rr.i - as.i * rr.r;
+    }
+  }
+  if (do_red) block_reduce<3>(v, partial);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_axpy_norm(double ar, double ai, const void* x, void* y, size_t n,
+                                                        double* partial) {
+  double v[1] = {0.0};
+  cpx<double> a = mk(ar, ai);
+  GRID_STRIDE(i, n) {
+    cpx<double> b = ld<T>(y, i) + a * ld<T>(x, i);
+    st<T>(y, i, b);
+    cpx<double> bs = ld<T>(y, i);
+    v[0] += bs.r * bs.r + bs.i * bs.i;
+  }
+  block_reduce<1>(v, partial);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_bicg_update(double ar, double ai, double wr, double wi, const void* p,
+                                                          const void* s, const void* t, void* x, void* r,
+                                                          const void* rhat, size_t n, double* partial) {
+  double v[3] = {0.0, 0.0, 0.0};
+  cpx<double> a = mk(ar, ai), w = mk(wr, wi);
+  GRID_STRIDE(i, n) {
+    cpx<double> sv = ld<T>(s, i);
+    st<T>(x, i, ld<T>(x, i) + a * ld<T>(p, i) + w * sv);
+    st<T>(r, i, sv - w * ld<T>(t, i));
+    cpx<double> rv = ld<T>(r, i), h = ld<T>(rhat, i);
+    v[0] += rv.r * rv.r + rv.i * rv.i;
+    v[1] += h.r * rv.r + h.i * rv.i;
+    v[2] += h.r * rv.i - h.i * rv.r;
+  }
+  block_reduce<3>(v, partial);
+}
+
+template <typename T>
+__global__ void k_bicg_p(double br, double bi, double wr, double wi, const void* r, const void* v, void* p,
+                         size_t n) {
+  cpx<double> b = mk(br, bi), w = mk(wr, wi);
+  GRID_STRIDE(i, n) st<T>(p, i, ld<T>(r, i) + b * (ld<T>(p, i) - w * ld<T>(v, i)));
+}
+
+template <typename T>
+__global__ void k_mr_update(double ar, double ai, void* x, void* r, const void* Ar, size_t n) {
+  cpx<double> a = mk(ar, ai);
+  GRID_STRIDE(i, n) {
+    st<T>(x, i, ld<T>(x, i) + a * ld<T>(r, i));
+    st<T>(r, i, ld<T>(r, i) - a * ld<T>(Ar, i));
+  }
+}
+
+}  // namespace
+
+#define DISPATCH(prec, KERNEL, grid, ...)                                                       \
+  do {                                                                                          \
+    if ((prec) == WCMG_F64)                                                                     \
+      hipLaunchKernelGGL(KERNEL<double>, grid, dim3(kThreads), 0, st, __VA_ARGS__);             \
+    else                                                                                        \
+      hipLaunchKernelGGL(KERNEL<float>, grid, dim3(kThreads), 0, st, __VA_ARGS__);              \
+    HIPCHK(hipGetLastError());                                                                  \
+  } while (0)
+
+void blas_zero(int prec, void* x, size_t n, hipStream_t st) { DISPATCH(prec, k_zero, ew_grid(n), x, n); }
+void blas_copy(int prec, void* y, const void* x, size_t n, hipStream_t st) {
+  DISPATCH(prec, k_copy, ew_grid(n), y, x, n);
+}
+void blas_axpby(int prec, double ar, double ai, const void* x, double br, double bi, void* y, size_t n,
+                hipStream_t st) {
+  DISPATCH(prec, k_axpby, ew_grid(n), ar, ai, x, br, bi, y, n);
+}
+void blas_norm2(int prec, const void* x, size_t n, double* res, double* partial, hipStream_t st) {
+  DISPATCH(prec, k_norm2, red_grid(), x, n, partial);
+  finalize(partial, 1, res, st);
+}
+void blas_cdot(int prec, const void* x, const void* y, size_t n, double* res, double* partial, hipStream_t st) {
+  DISPATCH(prec, k_cdot, red_grid(), x, y, n, partial);
+  finalize(partial, 2, res, st);
+}
+void blas_cdot_norm(int prec, const void* x, const void* y, size_t n, double* res, double* partial,
+                    hipStream_t st) {
+  DISPATCH(prec, k_cdot_norm, red_grid(), x, y, n, partial);
+  finalize(partial, 3, res, st);
+}
+void blas_multi_cdot(int prec, const void* const* v, int k, const void* y, size_t n, double* res,
+                     double* partial, hipStream_t st) {
+  for (int j0 = 0; j0 < k; j0 += kMaxK) {
+    int kk = std::min(kMaxK, k - j0);
+    MultiArgs m{};
+    for (int j = 0; j < kk; ++j) m.v[j] = v[j0 + j];
+    DISPATCH(prec, k_multi_cdot, red_grid(), m, kk, y, n, partial);
+    // finalize all 2*kMaxK slots; only the first 2*kk are meaningful
+    finalize(partial, 2 * kMaxK, res + 2 * j0, st);
+  }
+}
+void blas_multi_axpy(int prec, const double* c, const void* const* v, int k, void* y, size_t n, hipStream_t st) {
+  for (int j0 = 0; j0 < k; j0 += kMaxK) {
+    int kk = std::min(kMaxK, k - j0);
+    MultiArgs m{};
+    for (int j = 0; j < kk; ++j) {
+      m.v[j] = v[j0 + j];
+      m.c[2 * j] = c[2 * (j0 + j)];
+      m.c[2 * j + 1] = c[2 * (j0 + j) + 1];
+    }
+    DISPATCH(prec, k_multi_axpy, ew_grid(n), m, kk, y, n);
+  }
+}
+void blas_gcr_orth(int prec, const double* c, const void* const* q, const void* const* w, int k, void* y,
+                   void* z, const void* r, size_t n, double* res, double* partial, hipStream_t st) {
+  if (k == 0) {
+    MultiArgs m{};
+    DISPATCH(prec, k_gcr_orth, red_grid(), m, 0, y, z, r, n, 1, partial);
+    finalize(partial, 3, res, st);
+    return;
+  }
+  for (int j0 = 0; j0 < k; j0 += kMaxK) {
+    int kk = std::min(kMaxK, k - j0);
+    MultiArgs m{};
+    for (int j = 0; j < kk; ++j) {
+      m.v[j] = q[j0 + j];
+      m.w[j] = w[j0 + j];
+      m.c[2 * j] = c[2 * (j0 + j)];
+      m.c[2 * j + 1] = c[2 * (j0 + j) + 1];
+    }
+    int last = (j0 + kk == k);
+    DISPATCH(prec, k_gcr_orth, red_grid(), m, kk, y, z, r, n, last, partial);
+    if (last) finalize(partial, 3, res, st);
+  }
+}
+void blas_axpy_norm(int prec, double ar, double ai, const void* x, void* y, size_t n, double* res,
+                    double* partial, hipStream_t st) {
+  DISPATCH(prec, k_axpy_norm, red_grid(), ar, ai, x, y, n, partial);
+  finalize(partial, 1, res, st);
+}
+void blas_bicg_update(int prec, double ar, double ai, double wr, double wi, const void* p, const void* s,
+                      const void* t, void* x, void* r, const void* rhat, size_t n, double* res, double* partial,
+                      hipStream_t st) {
+  DISPATCH(prec, k_bicg_update, red_grid(), ar, ai, wr, wi, p, s, t, x, r, rhat, n, partial);
+  finalize(partial, 3, res, st);
+}
+void blas_bicg_p(int prec, double br, double bi, double wr, double wi, const void* r, const void* v, void* p,
+                 size_t n, hipStream_t st) {
+  DISPATCH(prec, k_bicg_p, ew_grid(n), br, bi, wr, wi, r, v, p, n);
+}
+void blas_mr_update(int prec, double ar, double ai, void* x, void* r, const void* Ar, size_t n, hipStream_t st) {
+  DISPATCH(prec, k_mr_update, ew_grid(n), ar, ai, x, r, Ar, n);
+}
+
+}  // namespace wcmg

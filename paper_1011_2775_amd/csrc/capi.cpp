@@ -1,0 +1,622 @@
+// C ABI of the wcmg library: argument validation, canonical <-> internal
+// layout conversion, and dispatch to the runtime.  No exception crosses the
+// boundary; every entry point returns a status code.
+#include <cmath>
+#include <cstring>
+
+#include "runtime.h"
+
+using namespace wcmg;
+
+namespace {
+
+thread_local std::string g_err;
+
+int set_err(int code, const std::string& m) {
+  g_err = m;
+  return code;
+}
+
+template <typename F>
+int guarded(F&& f) {
+  try {
+    f();
+    return WCMG_OK;
+  } catch (const Error& e) {
+    return set_err(e.code, e.msg);
+  } catch (const std::bad_alloc&) {
+    return set_err(WCMG_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return set_err(WCMG_EINVAL, e.what());
+  } catch (...) {
+    return set_err(WCMG_EINVAL, "unknown error");
+  }
+}
+
+#define CHECK(cond, code, msg) \
+  do {                         \
+    if (!(cond)) return set_err((code), (msg)); \
+  } while (0)
+
+Ctx* as_ctx(void* p) { return reinterpret_cast<Ctx*>(p); }
+
+bool valid_prec(int p) { return p == WCMG_F64 || p == WCMG_F32 || p == WCMG_F16; }
+bool valid_op(int o) { return o == WCMG_OP_FULL || o == WCMG_OP_SCHUR || o == WCMG_OP_DP; }
+
+// copies `bytes` of host or device data into a device scratch slot
+const void* to_device(Ctx& c, int slot, const void* src, size_t bytes, int on_device) {
+  if (on_device) return src;
+  void* d = c.scratch_buf(slot, bytes);
+  HIPCHK(hipMemcpyAsync(d, src, bytes, hipMemcpyHostToDevice, c.st));
+  return d;
+}
+
+CloverCoef clover_coef(double csw) {
+  // chiral gamma basis: gamma_k = [[0,-i s_k],[i s_k,0]], gamma_4 = [[0,1],[1,0]]
+  typedef double cd[2];
+  auto cm = [](const cd a, const cd b, cd o) {
+    o[0] = a[0] * b[0] - a[1] * b[1];
+    o[1] = a[0] * b[1] + a[1] * b[0];
+  };
+  static const double sig[3][2][2][2] = {{{{0, 0}, {1, 0}}, {{1, 0}, {0, 0}}},
+                                         {{{0, 0}, {0, -1}}, {{0, 1}, {0, 0}}},
+                                         {{{1, 0}, {0, 0}}, {{0, 0}, {-1, 0}}}};
+  double G[4][4][4][2];
+  std::memset(G, 0, sizeof(G));
+  for (int k = 0; k < 3; ++k)
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) {
+        // upper-right block -i sigma_k, lower-left i sigma_k
+        const double* s = sig[k][a][b];
+        G[k][a][2 + b][0] = s[1];
+        G[k][a][2 + b][1] = -s[0];
+        G[k][2 + a][b][0] = -s[1];
+        G[k][2 + a][b][1] = s[0];
+      }
+  for (int a = 0; a < 2; ++a) {
+    G[3][a][2 + a][0] = 1;
+    G[3][2 + a][a][0] = 1;
+  }
+  CloverCoef cc;
+  int plane = 0;
+  for (int mu = 0; mu < 4; ++mu)
+    for (int nu = mu + 1; nu < 4; ++nu, ++plane) {
+      // sigma = (i/2)(g_mu g_nu - g_nu g_mu); coefficient csw (i/2) -> -csw/4 (g g - g g)
+      double C[4][4][2];
+      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+          double s1[2] = {0, 0}, s2[2] = {0, 0};
+          for (int k = 0; k < 4; ++k) {
+            double t[2];
+            cm(G[mu][i][k], G[nu][k][j], t);
+            s1[0] += t[0];
+            s1[1] += t[1];
+            cm(G[nu][i][k], G[mu][k][j], t);
+            s2[0] += t[0];
+            s2[1] += t[1];
+          }
+          C[i][j][0] = -0.25 * csw * (s1[0] - s2[0]);
+          C[i][j][1] = -0.25 * csw * (s1[1] - s2[1]);
+        }
+      for (int chi = 0; chi < 2; ++chi)
+        for (int a = 0; a < 2; ++a)
+          for (int b = 0; b < 2; ++b) {
+            cc.s[plane][chi][a * 2 + b][0] = C[2 * chi + a][2 * chi + b][0];
+            cc.s[plane][chi][a * 2 + b][1] = C[2 * chi + a][2 * chi + b][1];
+          }
+    }
+  return cc;
+}
+
+int check_lat(Ctx* c, int lat) {
+  if (!c) return set_err(WCMG_EINVAL, "null context");
+  if (lat < 0 || lat >= (int)c->lats.size()) return set_err(WCMG_EINVAL, "lattice index out of range");
+  return WCMG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* wcmg_last_error(void) { return g_err.c_str(); }
+
+int wcmg_mg_params_default(wcmg_mg_params* p) {
+  CHECK(p, WCMG_EINVAL, "null params");
+  std::memset(p, 0, sizeof(*p));
+  p->nlevels = 1;
+  for (int l = 0; l < WCMG_MAX_LEVELS; ++l) {
+    for (int k = 0; k < 4; ++k) p->block[l][k] = l == 0 ? 4 : 2;
+    p->nvec[l] = l == 0 ? 24 : 32;
+    p->tol[l] = 0.1;
+    p->max_iter[l] = 50;
+    p->restart[l] = 10;
+  }
+  p->nu_post = 4;
+  p->outer_restart = 16;
+  p->outer_max_iter = 1000;
+  p->smoother_prec = WCMG_F32;
+  p->setup_relax = 10;
+  p->setup_max_steps = 10;
+  p->setup_rq_tol = 0.05;
+  p->seed = 0;
+  p->coarsest = 0;
+  return WCMG_OK;
+}
+
+int wcmg_create(const wcmg_lattice* lats, int nlat, void* hip_stream, void** out) {
+  CHECK(out, WCMG_EINVAL, "null output handle");
+  *out = nullptr;
+  CHECK(lats && nlat > 0, WCMG_EINVAL, "need at least one lattice");
+  for (int l = 0; l < nlat; ++l) {
+    for (int k = 0; k < 4; ++k) {
+      int L = lats[l].dims[k];
+      CHECK(L >= 2 && L % 2 == 0, WCMG_EDIM, "lattice extents must be even and >= 2");
+    }
+    CHECK(lats[l].t_bc == 1 || lats[l].t_bc == -1, WCMG_EINVAL, "t_bc must be +1 or -1");
+    double v = 1;
+    for (int k = 0; k < 4; ++k) v *= lats[l].dims[k];
+    CHECK(v < 2.0e9, WCMG_EDIM, "lattice too large");
+  }
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    return set_err(WCMG_ENODEV, "no HIP device available");
+  }
+  return guarded([&] {
+    auto c = new Ctx();
+    try {
+      HIPCHK(hipGetDevice(&c->device));
+      c->st = reinterpret_cast<hipStream_t>(hip_stream);
+      c->timer.st = c->st;
+      c->red.init(c->st);
+      for (int l = 0; l < nlat; ++l) {
+        auto L = new LatticeState();
+        L->F.g = make_geom(lats[l].dims, lats[l].t_bc);
+        c->lats.emplace_back(L);
+      }
+    } catch (...) {
+      delete c;
+      throw;
+    }
+    *out = c;
+  });
+}
+
+int wcmg_destroy(void* ctx) {
+  CHECK(ctx, WCMG_EINVAL, "null context");
+  return guarded([&] {
+    Ctx* c = as_ctx(ctx);
+    (void)hipStreamSynchronize(c->st);
+    delete c;
+  });
+}
+
+int wcmg_set_gauge(void* ctx, int lat, const void* U, int on_device) {
+  Ctx* c = as_ctx(ctx);
+  if (int r = check_lat(c, lat)) return r;
+  CHECK(U, WCMG_EINVAL, "null gauge field");
+  return guarded([&] {
+    LatticeState& L = *c->lats[lat];
+    const Geom& g = L.F.g;
+    const void* src = to_device(*c, 40, U, (size_t)g.V * 4 * 9 * 16, on_device);
+    for (int p = 0; p < 3; ++p) {
+      L.F.gauge[p].alloc(gauge_bytes(p, g.V));
+      gauge_to_internal(p, L.F.gauge[p].p, src, g, c->st);
+    }
+    HIPCHK(hipStreamSynchronize(c->st));
+    L.F.have_gauge = true;
+    L.F.have_clover = false;
+    L.T0 = FineTransfer();
+    L.levels.clear();
+    L.mg.reset();
+  });
+}
+
+int wcmg_set_clover(void* ctx, int lat, double m0, double csw, const void* A, int on_device) {
+  Ctx* c = as_ctx(ctx);
+  if (int r = check_lat(c, lat)) return r;
+  CHECK(std::isfinite(m0) && std::isfinite(csw), WCMG_EINVAL, "m0 and csw must be finite");
+  LatticeState& L = *c->lats[lat];
+  CHECK(A || L.F.have_gauge, WCMG_ESTATE, "gauge field not set");
+  return guarded([&] {
+    const Geom& g = L.F.g;
+    DBuf c64;
+    c64.alloc(clover_bytes(WCMG_F64, g.V));
+    int* flag = (int*)c->scratch_buf(12, 64);
+    HIPCHK(hipMemsetAsync(flag, 0, 64, c->st));
+    if (A) {
+      const void* src = to_device(*c, 40, A, (size_t)g.V * 144 * 16, on_device);
+      clover_from_matrix(c64.p, src, g, flag, c->st);
+    } else {
+      clover_compute(c64.p, L.F.gauge[WCMG_F64].p, g, m0, clover_coef(csw), flag, c->st);
+    }
+    int hf = 0;
+    HIPCHK(hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    if (hf) fail(WCMG_ECLOVER_NOT_PD, "clover block not positive definite");
+    size_t nreal = (size_t)g.V * 144;
+    L.F.clov[WCMG_F64] = std::move(c64);
+    for (int p = 1; p < 3; ++p) {
+      L.F.clov[p].alloc(clover_bytes(p, g.V));
+      reals_convert(p, L.F.clov[p].p, L.F.clov[WCMG_F64].as<double>(), nreal, c->st);
+    }
+    HIPCHK(hipStreamSynchronize(c->st));
+    L.F.m0 = m0;
+    L.F.csw = csw;
+    L.F.have_clover = true;
+    for (auto& lv : L.levels) lv->built = false;
+    L.mg.reset();
+  });
+}
+
+int wcmg_set_mg_params(void* ctx, int lat, const wcmg_mg_params* p) {
+  Ctx* c = as_ctx(ctx);
+  if (int r = check_lat(c, lat)) return r;
+  CHECK(p, WCMG_EINVAL, "null params");
+  CHECK(p->nlevels >= 1 && p->nlevels <= WCMG_MAX_LEVELS, WCMG_EINVAL, "nlevels out of range");
+  CHECK(p->nlevels == 1, WCMG_EINVAL, "only two-level hierarchies (nlevels = 1) are available");
+  LatticeState& L = *c->lats[lat];
+  const Geom& g = L.F.g;
+  for (int k = 0; k < 4; ++k) {
+    int b = p->block[0][k];
+    CHECK(b >= 2 && b % 2 == 0, WCMG_EDIM, "block extents must be even and >= 2");
+    CHECK(g.L[k] % b == 0, WCMG_EDIM, "block does not divide the lattice");
+  }
+  int bvol = p->block[0][0] * p->block[0][1] * p->block[0][2] * p->block[0][3];
+  CHECK(bvol <= 1024, WCMG_EDIM, "block volume above 1024");
+  CHECK(p->nvec[0] >= 1 && p->nvec[0] <= 64, WCMG_EDIM, "nvec must be in 1..64");
+  CHECK(p->nvec[0] <= 6 * bvol, WCMG_EDIM, "nvec exceeds the block's degrees of freedom per chirality");
+  CHECK(p->tol[0] > 0 && p->tol[0] < 1, WCMG_EINVAL, "inner tolerance must be in (0,1)");
+  CHECK(p->max_iter[0] >= 1 && p->restart[0] >= 1, WCMG_EINVAL, "inner max_iter and restart must be >= 1");
+  CHECK(p->outer_restart >= 1 && p->outer_max_iter >= 1, WCMG_EINVAL, "outer restart and max_iter must be >= 1");
+  CHECK(p->outer_restart <= 64 && p->restart[0] <= 64 && p->setup_relax <= 64, WCMG_EINVAL,
+        "restart lengths are limited to 64");
+  CHECK(p->nu_post >= 0, WCMG_EINVAL, "nu_post must be >= 0");
+  CHECK(p->smoother_prec == WCMG_F64 || p->smoother_prec == WCMG_F32, WCMG_EINVAL,
+        "smoother precision must be F64 or F32");
+  CHECK(p->setup_relax >= 1 && p->setup_max_steps >= 1, WCMG_EINVAL, "setup iteration counts must be >= 1");
+  CHECK(p->coarsest == 0, WCMG_EINVAL, "only the GCR coarsest solver is available");
+  return guarded([&] {
+    bool same_shape = L.have_params && L.params.nvec[0] == p->nvec[0] &&
+                      std::memcmp(L.params.block[0], p->block[0], sizeof(p->block[0])) == 0;
+    L.params = *p;
+    L.have_params = true;
+    if (!same_shape) {
+      L.T0 = FineTransfer();
+      L.levels.clear();
+    }
+    L.mg.reset();
+  });
+}
+
+int wcmg_build_null_vectors(void* ctx, int lat, int level) {
+  Ctx* c = as_ctx(ctx);
+  if (int r = check_lat(c, lat)) return r;
+  CHECK(level == 0, WCMG_EINVAL, "level out of range");
+  return guarded([&] { mg_setup_null_vectors(*c, *c->lats[lat], level); });
+}
+
+int wcmg_set_null_vectors(void* ctx, int lat, int level, const void* v, int nvec, int on_device) {
+  Ctx* c = as_ctx(ctx);
+  if (int r = check_lat(c, lat)) return r;
+  CHECK(v, WCMG_EINVAL, "null vectors pointer");
+  CHECK(level == 0, WCMG_EINVAL, "level out of range");
+  LatticeState& L = *c->lats[lat];
+  CHECK(L.have_params, WCMG_ESTATE, "multigrid parameters not set");
+  CHECK(nvec == L.params.nvec[0], WCMG_EINVAL, "nvec differs from the parameters");
+  return guarded([&] {
+    const Geom& g = L.F.g;
+    const size_t hb = spinor_bytes(WCMG_F64, g.Vh);
+    const size_t one = (size_t)g.V * 12 * 16;
+    L.T0.raw.alloc((size_t)nvec * 2 * hb);
+    for (int k = 0; k < nvec; ++k) {
+      const void* src = to_device(*c, 41, (const char*)v + (size_t)k * one, one, on_device);
+      char* dst = (char*)L.T0.raw.p + (size_t)k * 2 * hb;
+      spinor_to_internal(WCMG_F64, dst, dst + hb, src, g, false, c->st);
+      if (!on_device) HIPCHK(hipStreamSynchronize(c->st));
+    }
+    HIPCHK(hipStreamSynchronize(c->st));
+    L.T0.nvec = nvec;
+    L.T0.have_vecs = true;
+    L.T0.orth = false;
+    for (auto& lv : L.levels) lv->built = false;
+    L.mg.reset();
+  });
+}
+
+int wcmg_get_null_vectors(void* ctx, int lat, int level, void* v, int on_device) {
+  Ctx* c = as_ctx(ctx);
+  if (int r = check_lat(c, lat)) return r;
+  CHECK(v, WCMG_EINVAL, "null vectors pointer");
+  CHECK(level == 0, WCMG_EINVAL, "level out of range");
+  LatticeState& L = *c->lats[lat];
+  CHECK(L.T0.have_vecs, WCMG_ESTATE, "null vectors not available");
+  return guarded([&] {
+    const Geom& g = L.F.g;
+    const size_t hb = spinor_bytes(WCMG_F64, g.Vh);
+    const size_t one = (size_t)g.V * 12 * 16;
+    for (int k = 0; k < L.T0.nvec; ++k) {
+      const char* src = (const char*)L.T0.raw.p + (size_t)k * 2 * hb;
+      void* dst = on_device ? (char*)v + (size_t)k * one : c->scratch_buf(41, one);
+      spinor_from_internal(WCMG_F64, dst, src, src + hb, g, false, c->st);
+      if (!on_device)
+        HIPCHK(hipMemcpyAsync((char*)v + (size_t)k * one, dst, one, hipMemcpyDeviceToHost, c->st));
+    }
+    HIPCHK(hipStreamSynchronize(c->st));
+  });
+}
+
+int wcmg_build_coarse(void* ctx, int lat, int level) {
+  Ctx* c = as_ctx(ctx);
+  if (int r = check_lat(c, lat)) return r;
+  CHECK(level == 0, WCMG_EINVAL, "level out of range");
+  return guarded([&] { mg_build_coarse(*c, *c->lats[lat], level); });
+}
+
+int wcmg_get_coarse(void* ctx, int lat, int level, void* Y, int on_device) {
+  Ctx* c = as_ctx(ctx);
+  if (int r = check_lat(c, lat)) return r;
+  CHECK(Y, WCMG_EINVAL, "null output");
+  CHECK(level == 0, WCMG_EINVAL, "level out of range");
+  LatticeState& L = *c->lats[lat];
+  CHECK(!L.levels.empty() && L.levels[0]->built, WCMG_ESTATE, "coarse operator not built");
+  return guarded([&] {
+    CoarseLevel& C = *L.levels[0];
+    const int n = C.cg.n, V = C.cg.V;
+    const size_t nn = (size_t)n * n;
+    std::vector<double> h((size_t)V * 9 * nn * 2), o(h.size());
+    HIPCHK(hipMemcpyAsync(h.data(), C.Y9.p, h.size() * 8, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    for (int l = 0; l < V; ++l) {
+      const int ci = C.perm_host[l];
+      for (int s = 0; s < 9; ++s)
+        for (int i = 0; i < n; ++i)
+          for (int j = 0; j < n; ++j) {
+            size_t src = (((size_t)ci * 9 + s) * n + j) * n + i;  // column-major
+            size_t dst = (((size_t)l * 9 + s) * n + i) * n + j;   // row-major
+            o[2 * dst] = h[2 * src];
+            o[2 * dst + 1] = h[2 * src + 1];
+          }
+    }
+    if (on_device)
+      HIPCHK(hipMemcpyAsync(Y, o.data(), o.size() * 8, hipMemcpyHostToDevice, c->st));
+    else
+      std::memcpy(Y, o.data(), o.size() * 8);
+    HIPCHK(hipStreamSynchronize(c->st));
+  });
+}
+
+static int apply_common(void* ctx, int lat, int op, int prec, void* out, const void* in, int nrhs, bool dag) {
+  Ctx* c = as_ctx(ctx);
+  if (int r = check_lat(c, lat)) return r;
+  CHECK(out && in, WCMG_EINVAL, "null buffer");
+  CHECK(valid_op(op), WCMG_EINVAL, "bad operator");
+  CHECK(valid_prec(prec), WCMG_EINVAL, "bad precision");
+  CHECK(nrhs >= 1, WCMG_EINVAL, "nrhs must be >= 1");
+  CHECK(out != in, WCMG_EINVAL, "out and in must not alias");
+  LatticeState& L = *c->lats[lat];
+  CHECK(L.F.have_clover, WCMG_ESTATE, "clover not set");
+  return guarded([&] {
+    const Geom& g = L.F.g;
+    const size_t hb = spinor_bytes(prec, g.Vh);
+    const size_t one = (size_t)g.V * 12 * 16;
+    void* ie = c->scratch_buf(42, hb);
+    void* io = c->scratch_buf(43, hb);
+    void* oe = c->scratch_buf(44, hb);
+    void* oo = c->scratch_buf(45, hb);
+    FineOp fo{c, &L.F, prec, &c->fw[prec], c->st};
+    for (int r = 0; r < nrhs; ++r) {
+      const void* src = (const char*)in + (size_t)r * one;
+      void* dst = (char*)out + (size_t)r * one;
+      spinor_to_internal(prec, ie, io, src, g, dag && op != WCMG_OP_SCHUR, c->st);
+      if (op == WCMG_OP_FULL) {
+        fo.D(oe, oo, ie, io);
+        spinor_from_internal(prec, dst, oe, oo, g, dag, c->st);
+      } else if (op == WCMG_OP_DP) {
+        if (!dag) {
+          fo.Dp(oe, oo, ie, io);
+          spinor_from_internal(prec, dst, oe, oo, g, false, c->st);
+        } else {
+          // D_p^dag = A^-1 gamma5 D gamma5
+          fo.D(oe, oo, ie, io);
+          spinor_gamma5(prec, oe, g.Vh, c->st);
+          spinor_gamma5(prec, oo, g.Vh, c->st);
+          fo.clover(ie, oe, 0, 1);
+          fo.clover(io, oo, 1, 1);
+          spinor_from_internal(prec, dst, ie, io, g, false, c->st);
+        }
+      } else {
+        if (!dag)
+          fo.Dr(oe, ie);
+        else
+          fo.Dr_dag(oe, ie);
+        spinor_from_internal(prec, dst, oe, nullptr, g, false, c->st);
+      }
+    }
+  });
+}
+
+int wcmg_apply_D(void* ctx, int lat, int op, int prec, void* out, const void* in, int nrhs) {
+  return apply_common(ctx, lat, op, prec, out, in, nrhs, false);
+}
+
+int wcmg_apply_Ddag(void* ctx, int lat, int op, int prec, void* out, const void* in, int nrhs) {
+  return apply_common(ctx, lat, op, prec, out, in, nrhs, true);
+}
+
+int wcmg_restrict(void* ctx, int lat, int level, int prec, void* coarse_out, const void* fine_in, int nrhs) {
+  Ctx* c = as_ctx(ctx);
+  if (int r = check_lat(c, lat)) return r;
+  CHECK(coarse_out && fine_in, WCMG_EINVAL, "null buffer");
+  CHECK(level == 0, WCMG_EINVAL, "level out of range");
+  CHECK(valid_prec(prec), WCMG_EINVAL, "bad precision");
+  CHECK(nrhs >= 1, WCMG_EINVAL, "nrhs must be >= 1");
+  LatticeState& L = *c->lats[lat];
+  CHECK(!L.levels.empty() && L.levels[0]->built, WCMG_ESTATE, "coarse operator not built");
+  return guarded([&] {
+    const Geom& g = L.F.g;
+    CoarseLevel& C = *L.levels[0];
+    const int cprec = prec == WCMG_F64 ? WCMG_F64 : WCMG_F32;
+    const size_t hb = spinor_bytes(prec, g.Vh);
+    void* fe = c->scratch_buf(42, hb);
+    void* fo = c->scratch_buf(43, hb);
+    void* cv = c->scratch_buf(46, (size_t)C.cg.V * C.cg.n * 16);
+    const void* vecs = L.T0.v64.p;
+    DBuf v16;
+    if (prec == WCMG_F32) vecs = L.T0.v32.p;
+    if (prec == WCMG_F16) {
+      const size_t h64 = spinor_bytes(WCMG_F64, g.Vh), h16 = spinor_bytes(WCMG_F16, g.Vh);
+      v16.alloc((size_t)2 * L.T0.nvec * h16);
+      for (int k = 0; k < 2 * L.T0.nvec; ++k)
+        spinor_convert(WCMG_F16, (char*)v16.p + k * h16, WCMG_F64, (const char*)L.T0.v64.p + k * h64, g.Vh, c->st);
+      vecs = v16.p;
+    }
+    const size_t one = (size_t)g.V * 12 * 16, cone = (size_t)C.cg.V * C.cg.n * 16;
+    for (int r = 0; r < nrhs; ++r) {
+      spinor_to_internal(prec, fe, fo, (const char*)fine_in + r * one, g, false, c->st);
+      launch_restrict(prec, cv, C.cg.n, 1, fe, vecs, L.T0.nvec, 0, g, L.T0.bg, false, c->st);
+      launch_restrict(prec, cv, C.cg.n, 1, fo, vecs, L.T0.nvec, 1, g, L.T0.bg, true, c->st);
+      launch_coarse_canon(cprec, cv, (char*)coarse_out + r * cone, C.perm.as<int>(), C.cg.V, C.cg.n, false, c->st);
+    }
+    HIPCHK(hipStreamSynchronize(c->st));
+  });
+}
+
+int wcmg_prolong(void* ctx, int lat, int level, int prec, void* fine_out, const void* coarse_in, int nrhs) {
+  Ctx* c = as_ctx(ctx);
+  if (int r = check_lat(c, lat)) return r;
+  CHECK(fine_out && coarse_in, WCMG_EINVAL, "null buffer");
+  CHECK(level == 0, WCMG_EINVAL, "level out of range");
+  CHECK(valid_prec(prec), WCMG_EINVAL, "bad precision");
+  CHECK(nrhs >= 1, WCMG_EINVAL, "nrhs must be >= 1");
+  LatticeState& L = *c->lats[lat];
+  CHECK(!L.levels.empty() && L.levels[0]->built, WCMG_ESTATE, "coarse operator not built");
+  return guarded([&] {
+    const Geom& g = L.F.g;
+    CoarseLevel& C = *L.levels[0];
+    const int cprec = prec == WCMG_F64 ? WCMG_F64 : WCMG_F32;
+    const size_t hb = spinor_bytes(prec, g.Vh);
+    void* fe = c->scratch_buf(42, hb);
+    void* fo = c->scratch_buf(43, hb);
+    void* cv = c->scratch_buf(46, (size_t)C.cg.V * C.cg.n * 16);
+    const void* vecs = L.T0.v64.p;
+    DBuf v16;
+    if (prec == WCMG_F32) vecs = L.T0.v32.p;
+    if (prec == WCMG_F16) {
+      const size_t h64 = spinor_bytes(WCMG_F64, g.Vh), h16 = spinor_bytes(WCMG_F16, g.Vh);
+      v16.alloc((size_t)2 * L.T0.nvec * h16);
+      for (int k = 0; k < 2 * L.T0.nvec; ++k)
+        spinor_convert(WCMG_F16, (char*)v16.p + k * h16, WCMG_F64, (const char*)L.T0.v64.p + k * h64, g.Vh, c->st);
+      vecs = v16.p;
+    }
+    const size_t one = (size_t)g.V * 12 * 16, cone = (size_t)C.cg.V * C.cg.n * 16;
+    for (int r = 0; r < nrhs; ++r) {
+      launch_coarse_canon(cprec, cv, (char*)coarse_in + r * cone, C.perm.as<int>(), C.cg.V, C.cg.n, true, c->st);
+      launch_prolong(prec, fe, cv, vecs, L.T0.nvec, 0, g, L.T0.bg, c->st);
+      launch_prolong(prec, fo, cv, vecs, L.T0.nvec, 1, g, L.T0.bg, c->st);
+      spinor_from_internal(prec, (char*)fine_out + r * one, fe, fo, g, false, c->st);
+    }
+    HIPCHK(hipStreamSynchronize(c->st));
+  });
+}
+
+int wcmg_apply_coarse(void* ctx, int lat, int level, int op, int prec, void* out, const void* in, int nrhs) {
+  Ctx* c = as_ctx(ctx);
+  if (int r = check_lat(c, lat)) return r;
+  CHECK(out && in, WCMG_EINVAL, "null buffer");
+  CHECK(out != in, WCMG_EINVAL, "out and in must not alias");
+  CHECK(level == 1, WCMG_EINVAL, "level out of range");
+  CHECK(valid_op(op), WCMG_EINVAL, "bad operator");
+  CHECK(prec == WCMG_F64 || prec == WCMG_F32, WCMG_EINVAL, "coarse precision must be F64 or F32");
+  CHECK(nrhs >= 1, WCMG_EINVAL, "nrhs must be >= 1");
+  LatticeState& L = *c->lats[lat];
+  CHECK(!L.levels.empty() && L.levels[0]->built, WCMG_ESTATE, "coarse operator not built");
+  CoarseLevel& C = *L.levels[0];
+  CHECK(op != WCMG_OP_SCHUR || C.cg.split, WCMG_EDIM, "coarse lattice has an odd extent: no red-black form");
+  return guarded([&] {
+    const size_t cs = prec == WCMG_F64 ? 16 : 8;
+    const size_t nall = (size_t)C.cg.V * C.cg.n;
+    void* vi = c->scratch_buf(46, nall * 16);
+    void* vo = c->scratch_buf(47, nall * 16);
+    blas_zero(prec, vo, nall, c->st);
+    CoarseOp cop{&C, prec, &c->cw[prec == WCMG_F64 ? 0 : 1], c->st};
+    const size_t cone = nall * 16;
+    for (int r = 0; r < nrhs; ++r) {
+      launch_coarse_canon(prec, vi, (char*)const_cast<void*>(in) + r * cone, C.perm.as<int>(), C.cg.V, C.cg.n, true,
+                          c->st);
+      if (op == WCMG_OP_FULL)
+        cop.Dfull(vo, vi);
+      else if (op == WCMG_OP_DP)
+        cop.Dp(vo, vi);
+      else {
+        blas_zero(prec, (char*)vo + cop.neven() * cs, nall - cop.neven(), c->st);
+        cop.Dr(vo, vi);
+      }
+      launch_coarse_canon(prec, vo, (char*)out + r * cone, C.perm.as<int>(), C.cg.V, C.cg.n, false, c->st);
+    }
+  });
+}
+
+int wcmg_solve(void* ctx, int lat, int solver, void* x, const void* b, int nrhs, double tol, wcmg_stats* stats) {
+  Ctx* c = as_ctx(ctx);
+  if (int r = check_lat(c, lat)) return r;
+  CHECK(x && b, WCMG_EINVAL, "null buffer");
+  CHECK(x != b, WCMG_EINVAL, "x and b must not alias");
+  CHECK(solver == WCMG_MG_GCR || solver == WCMG_GCR || solver == WCMG_BICGSTAB, WCMG_EINVAL, "bad solver");
+  CHECK(nrhs >= 1, WCMG_EINVAL, "nrhs must be >= 1");
+  CHECK(tol > 0 && tol < 1, WCMG_EINVAL, "tol must be in (0,1)");
+  LatticeState& L = *c->lats[lat];
+  CHECK(L.F.have_clover, WCMG_ESTATE, "clover not set");
+  if (solver == WCMG_MG_GCR)
+    CHECK(L.have_params && !L.levels.empty() && L.levels[0]->built, WCMG_ESTATE, "multigrid hierarchy not built");
+  int worst = WCMG_OK;
+  int rc = guarded([&] {
+    const Geom& g = L.F.g;
+    const size_t hb = spinor_bytes(WCMG_F64, g.Vh);
+    const size_t one = (size_t)g.V * 12 * 16;
+    void* be = c->scratch_buf(48, hb);
+    void* bo = c->scratch_buf(49, hb);
+    void* xe = c->scratch_buf(50, hb);
+    void* xo = c->scratch_buf(51, hb);
+    for (int r = 0; r < nrhs; ++r) {
+      const void* bs = (const char*)b + (size_t)r * one;
+      void* xs = (char*)x + (size_t)r * one;
+      spinor_to_internal(WCMG_F64, be, bo, bs, g, false, c->st);
+      spinor_to_internal(WCMG_F64, xe, xo, xs, g, false, c->st);
+      double xn = norm2(*c, WCMG_F64, xe, (size_t)12 * g.Vh) + norm2(*c, WCMG_F64, xo, (size_t)12 * g.Vh);
+      wcmg_stats s{};
+      solve_rhs(*c, L, solver, xe, xo, be, bo, xn == 0.0, tol, &s);
+      spinor_from_internal(WCMG_F64, xs, xe, xo, g, false, c->st);
+      if (stats) stats[r] = s;
+      if (s.status != WCMG_OK && worst == WCMG_OK) worst = s.status;
+    }
+    HIPCHK(hipStreamSynchronize(c->st));
+  });
+  if (rc != WCMG_OK) return rc;
+  if (worst != WCMG_OK) return set_err(worst, "solver did not reach the tolerance for every right-hand side");
+  return WCMG_OK;
+}
+
+int wcmg_timer_enable(void* ctx, int on) {
+  CHECK(ctx, WCMG_EINVAL, "null context");
+  return guarded([&] {
+    Ctx* c = as_ctx(ctx);
+    c->timer.reset();
+    c->timer.on = on != 0;
+  });
+}
+
+int wcmg_timer_read(void* ctx, int which, long* count, double* total_ms) {
+  CHECK(ctx, WCMG_EINVAL, "null context");
+  CHECK(which == 0 || which == 1, WCMG_EINVAL, "bad timer class");
+  CHECK(count && total_ms, WCMG_EINVAL, "null output");
+  return guarded([&] {
+    Ctx* c = as_ctx(ctx);
+    c->timer.drain();
+    *count = c->timer.count[which];
+    *total_ms = c->timer.ms[which];
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,141 @@
+// Launchers of the device kernels (one translation unit per kernel family).
+#pragma once
+
+#include "wcmg_internal.h"
+
+namespace wcmg {
+
+// ------------------------------------------------------------ fine Dslash
+struct DslashArgs {
+  void* out;           // output parity spinor
+  const void* in;      // opposite-parity spinor (hopping input)
+  const void* x;       // same-parity spinor for the DIAG term
+  const void* gauge;   // links of this precision
+  const void* clov;    // packed clover of this precision
+  DGeom g;
+  int parity;          // output parity
+  int nblocks;         // filled by the launcher
+  double coeff;        // multiplies the (post-processed) hopping term
+};
+void launch_dslash(int prec, int diag, bool postinv, const DslashArgs& a, hipStream_t st);
+void launch_clover(int prec, void* out, const void* in, const void* clov, int Vh, int p, int kind,
+                   hipStream_t st);
+
+// ------------------------------------------------------------ fields
+// canonical complex128 gauge [V][4][3][3] (device) -> internal links
+void gauge_to_internal(int prec, void* dst, const void* canon, const Geom& g, hipStream_t st);
+// canonical complex128 spinor [V][12] (device) <-> two internal parity halves
+void spinor_to_internal(int prec, void* even, void* odd, const void* canon, const Geom& g, bool g5,
+                        hipStream_t st);
+// odd == nullptr writes zeros on odd sites; even == nullptr writes zeros on even sites
+void spinor_from_internal(int prec, void* canon, const void* even, const void* odd, const Geom& g, bool g5,
+                          hipStream_t st);
+// one parity, any precision pair
+void spinor_convert(int prec_dst, void* dst, int prec_src, const void* src, int Vh, hipStream_t st);
+void spinor_gamma5(int prec, void* v, int Vh, hipStream_t st);
+// keep only the components of chirality chi (0: spins 0,1; 1: spins 2,3)
+void spinor_chiral_project(int prec, void* dst, const void* src, int Vh, int chi, hipStream_t st);
+
+struct CloverCoef {
+  double s[6][2][4][2];  // [plane][chirality][2x2 entry][re,im] = csw (i/2) sigma_mu_nu block
+};
+// packed A and A^-1 (FP64) for both parities from the gauge field; flag[0]
+// is set to 1 if a block is not positive definite
+void clover_compute(void* clov64, const void* gauge64, const Geom& g, double m0, const CloverCoef& cc,
+                    int* flag, hipStream_t st);
+// packed A and A^-1 from a canonical complex128 [V][12][12] matrix
+void clover_from_matrix(void* clov64, const void* A, const Geom& g, int* flag, hipStream_t st);
+void reals_convert(int prec_dst, void* dst, const double* src, size_t n, hipStream_t st);
+
+// ------------------------------------------------------------ BLAS-1
+// Flat complex vectors of n elements, storage double (prec F64) or float (F32).
+// Reductions accumulate in double and are deterministic (fixed grid,
+// fixed-order second pass).  Results go to device memory `res`.
+constexpr int kRedBlocks = 512;
+void blas_zero(int prec, void* x, size_t n, hipStream_t st);
+void blas_copy(int prec, void* y, const void* x, size_t n, hipStream_t st);
+// y = a*x + b*y (complex a, b)
+void blas_axpby(int prec, double ar, double ai, const void* x, double br, double bi, void* y, size_t n,
+                hipStream_t st);
+// res[0] = ||x||^2
+void blas_norm2(int prec, const void* x, size_t n, double* res, double* partial, hipStream_t st);
+// res[0..1] = <x,y> = sum conj(x) y
+void blas_cdot(int prec, const void* x, const void* y, size_t n, double* res, double* partial, hipStream_t st);
+// res[0..1] = <x,y>, res[2] = ||x||^2
+void blas_cdot_norm(int prec, const void* x, const void* y, size_t n, double* res, double* partial,
+                    hipStream_t st);
+// res[2j..2j+1] = <v_j, y> for j < k
+void blas_multi_cdot(int prec, const void* const* v, int k, const void* y, size_t n, double* res,
+                     double* partial, hipStream_t st);
+// y += sum_j c_j v_j  (c on host, k <= 32)
+void blas_multi_axpy(int prec, const double* c, const void* const* v, int k, void* y, size_t n, hipStream_t st);
+// y -= sum_j c_j q_j ; z -= sum_j c_j w_j ; res = [ ||y||^2, <y, r> ]
+void blas_gcr_orth(int prec, const double* c, const void* const* q, const void* const* w, int k, void* y,
+                   void* z, const void* r, size_t n, double* res, double* partial, hipStream_t st);
+// y += a x ; res[0] = ||y||^2
+void blas_axpy_norm(int prec, double ar, double ai, const void* x, void* y, size_t n, double* res,
+                    double* partial, hipStream_t st);
+// BiCGStab: x += a p + w s ; r = s - w t ; res = [||r||^2, <rhat, r>]
+void blas_bicg_update(int prec, double ar, double ai, double wr, double wi, const void* p, const void* s,
+                      const void* t, void* x, void* r, const void* rhat, size_t n, double* res, double* partial,
+                      hipStream_t st);
+// BiCGStab: p = r + b (p - w v)
+void blas_bicg_p(int prec, double br, double bi, double wr, double wi, const void* r, const void* v, void* p,
+                 size_t n, hipStream_t st);
+// res = [ <t,s>, ||t||^2 ]   (identical to cdot_norm(t, s))
+// MR: x += a r ; r -= a Ar
+void blas_mr_update(int prec, double ar, double ai, void* x, void* r, const void* Ar, size_t n, hipStream_t st);
+
+// ------------------------------------------------------------ transfer (fine level)
+struct BlockGeom {
+  int b[4];    // block extents
+  int nb[4];   // coarse extents
+  int Vc;      // coarse sites
+  int bvol;    // block volume
+  int coarse_cb;  // 1 if coarse sites are stored parity-split (all nb even)
+};
+// coarse internal index of coarse lexicographic site
+int coarse_internal_index_host(const BlockGeom& bg, int lex);
+
+// R: coarse[c][s*Nv+k] (+)= sign(s) sum conj(V_k) in over fine sites of parity p
+// vecs: Nv full-lattice spinors (precision prec) in internal layout
+// out_site_stride/out_row_stride are in complex elements; accumulate: add into out
+void launch_restrict(int prec, void* out, size_t out_site_stride, size_t out_row_stride, const void* in,
+                     const void* vecs, int nvec, int p, const Geom& g, const BlockGeom& bg, bool accumulate,
+                     hipStream_t st);
+// P: out_p(x) = sum_k V_k(x) coarse[c(x)][s*Nv+k]
+void launch_prolong(int prec, void* out, const void* coarse, const void* vecs, int nvec, int p, const Geom& g,
+                    const BlockGeom& bg, hipStream_t st);
+// block x chirality Gram-Schmidt (twice) of Nv full-lattice FP64 spinors in place
+void launch_block_orthonormalize(void* vecs, int nvec, const Geom& g, const BlockGeom& bg, int* flag,
+                                 hipStream_t st);
+// coarse build: nine direction buckets of the D_p hop of u = A^-1 v (both parities)
+void launch_hop_split(void* const* buckets /*9 full spinors F64*/, const void* v, const void* u,
+                      const void* gauge64, const Geom& g, const BlockGeom& bg, hipStream_t st);
+
+// ------------------------------------------------------------ coarse level
+struct CoarseGeom {
+  int L[4];
+  int V;
+  int Vh;      // V/2 when parity split, else V
+  int split;   // sites stored parity-split
+  int n;       // 2*Nv
+};
+// out(c) = DIAG + coeff * sum_d M_d(c) in(nb(c, d)) over sites of `parity`
+// (parity -1: all sites, requires split == 0 or both halves contiguous)
+// M: [site][8][n][n] column-major blocks.  diag 0 none, 1 x, 2 X(c) x with Xmat
+void launch_coarse_hop(int prec, void* out, const void* in, const void* x, const void* M, const void* Xmat,
+                       int diag, double coeff, int parity, const CoarseGeom& cg, const int* nbr, hipStream_t st);
+// out(c) = M(c) in(c) with M [site][n][n] column-major, sites of `parity` (-1 all)
+void launch_coarse_local(int prec, void* out, const void* in, const void* M, int parity, const CoarseGeom& cg,
+                         hipStream_t st);
+void launch_batched_inverse(double* M, int nmat, int n, int* flag, hipStream_t st);
+// Yt[c][d] = Y[c][d] * Xinv[nb(c,d)]   (all column-major n x n)
+void launch_coarse_right_mul(double* Yt, const double* Y, const double* Xinv, const int* nbr, int V, int n,
+                             hipStream_t st);
+// canonical complex128 [lex][n] <-> internal [perm[lex]][n] (F64 or F32)
+void launch_coarse_canon(int prec, void* internal, void* canon, const int* perm, int V, int n, bool to_internal,
+                         hipStream_t st);
+void launch_reals_convert(int prec_dst, void* dst, const double* src, size_t n, hipStream_t st);
+
+}  // namespace wcmg

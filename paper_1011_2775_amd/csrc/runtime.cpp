@@ -1,0 +1,254 @@
+// Host runtime: errors, buffers, timers, reductions, and the operator
+// wrappers that sequence the kernels of the fine and coarse levels.
+#include "runtime.h"
+
+#include <cmath>
+#include <cstring>
+
+namespace wcmg {
+
+[[noreturn]] void fail(int code, const std::string& msg) { throw Error{code, msg}; }
+
+void hip_check(hipError_t e, const char* what, const char* file, int line) {
+  if (e == hipSuccess) return;
+  std::string m = std::string(what) + ": " + hipGetErrorString(e) + " (" + file + ":" + std::to_string(line) + ")";
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) fail(WCMG_ENOMEM, m);
+  if (e == hipErrorNoDevice || e == hipErrorInvalidDevice) fail(WCMG_ENODEV, m);
+  fail(WCMG_EHIP, m);
+}
+
+void DBuf::alloc(size_t bytes) {
+  if (bytes == n && p) return;
+  release();
+  if (bytes) HIPCHK(hipMalloc(&p, bytes));
+  n = bytes;
+}
+void DBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  n = 0;
+}
+
+Geom make_geom(const int dims[4], int t_bc) {
+  Geom g;
+  long v = 1;
+  for (int k = 0; k < 4; ++k) {
+    g.L[k] = dims[k];
+    v *= dims[k];
+  }
+  g.V = (int)v;
+  g.Vh = (int)(v / 2);
+  g.Lxh = dims[0] / 2;
+  g.t_bc = (double)t_bc;
+  return g;
+}
+
+BlockGeom make_block_geom(const int L[4], const int b[4]) {
+  BlockGeom bg{};
+  bg.Vc = 1;
+  bg.bvol = 1;
+  bool even = true;
+  for (int k = 0; k < 4; ++k) {
+    bg.b[k] = b[k];
+    bg.nb[k] = L[k] / b[k];
+    bg.Vc *= bg.nb[k];
+    bg.bvol *= b[k];
+    even = even && (bg.nb[k] % 2 == 0);
+  }
+  bg.coarse_cb = even ? 1 : 0;
+  return bg;
+}
+
+CoarseGeom make_coarse_geom(const BlockGeom& bg, int nvec) {
+  CoarseGeom cg{};
+  for (int k = 0; k < 4; ++k) cg.L[k] = bg.nb[k];
+  cg.V = bg.Vc;
+  cg.split = bg.coarse_cb;
+  cg.Vh = cg.split ? cg.V / 2 : cg.V;
+  cg.n = 2 * nvec;
+  return cg;
+}
+
+// ------------------------------------------------------------------ timers
+hipEvent_t KernelTimer::get() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HIPCHK(hipEventCreate(&e));
+  return e;
+}
+void KernelTimer::begin(int cls, hipEvent_t* a) {
+  (void)cls;
+  *a = get();
+  HIPCHK(hipEventRecord(*a, st));
+}
+void KernelTimer::end(int cls, hipEvent_t a) {
+  hipEvent_t b = get();
+  HIPCHK(hipEventRecord(b, st));
+  pending.push_back({cls, {a, b}});
+}
+void KernelTimer::drain() {
+  if (pending.empty()) return;
+  HIPCHK(hipStreamSynchronize(st));
+  for (auto& pe : pending) {
+    float ms_ = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms_, pe.second.first, pe.second.second));
+    count[pe.first] += 1;
+    ms[pe.first] += ms_;
+    pool.push_back(pe.second.first);
+    pool.push_back(pe.second.second);
+  }
+  pending.clear();
+}
+void KernelTimer::reset() {
+  drain();
+  count[0] = count[1] = 0;
+  ms[0] = ms[1] = 0.0;
+}
+KernelTimer::~KernelTimer() {
+  for (auto& pe : pending) {
+    (void)hipEventDestroy(pe.second.first);
+    (void)hipEventDestroy(pe.second.second);
+  }
+  for (auto e : pool) (void)hipEventDestroy(e);
+}
+
+// ------------------------------------------------------------------ reducer
+void Reducer::init(hipStream_t s) {
+  st = s;
+  partial.alloc((size_t)kRedBlocks * 64 * sizeof(double));
+  res.alloc(256 * sizeof(double));
+  HIPCHK(hipHostMalloc((void**)&host, 256 * sizeof(double), hipHostMallocDefault));
+}
+const double* Reducer::fetch(int n) {
+  HIPCHK(hipMemcpyAsync(host, res.p, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return host;
+}
+Reducer::~Reducer() {
+  if (host) (void)hipHostFree(host);
+}
+
+double norm2(Ctx& c, int prec, const void* x, size_t n) {
+  blas_norm2(prec, x, n, c.red.dres(), c.red.dpart(), c.st);
+  return c.red.fetch(1)[0];
+}
+
+void* Ctx::scratch_buf(int slot, size_t bytes) {
+  if ((int)scratch.size() <= slot) scratch.resize(slot + 1);
+  if (scratch[slot].n < bytes) scratch[slot].alloc(bytes);
+  return scratch[slot].p;
+}
+
+// ------------------------------------------------------------------ fine level
+void FineWork::ensure(int p, const Geom& g) {
+  size_t b = spinor_bytes(p, g.Vh);
+  if (prec == p && hb == b) return;
+  prec = p;
+  hb = b;
+  t1.alloc(b);
+  t2.alloc(b);
+  t3.alloc(b);
+}
+
+void FineOp::hop(void* out, const void* in, const void* x, int parity, int diag, bool postinv, double coeff) {
+  DslashArgs a;
+  a.out = out;
+  a.in = in;
+  a.x = x;
+  a.gauge = F->gauge[prec].p;
+  a.clov = F->clov[prec].p;
+  a.g = dgeom(F->g);
+  a.parity = parity;
+  a.nblocks = 0;
+  a.coeff = coeff;
+  hipEvent_t e = nullptr;
+  if (ctx->timer.on) ctx->timer.begin(0, &e);
+  launch_dslash(prec, diag, postinv, a, st);
+  if (e) ctx->timer.end(0, e);
+}
+
+void FineOp::clover(void* out, const void* in, int parity, int kind) {
+  launch_clover(prec, out, in, F->clov[prec].p, F->g.Vh, parity, kind, st);
+}
+
+void FineOp::Dr(void* out, const void* y) {
+  w->ensure(prec, F->g);
+  clover(w->t1.p, y, 0, 1);                   // z = A_ee^-1 y
+  hop(w->t2.p, w->t1.p, nullptr, 1, 0, true, 1.0);  // w = A_oo^-1 H_oe z
+  hop(out, w->t2.p, y, 0, 1, false, -1.0);    // out = y - H_eo w
+}
+
+void FineOp::Dr_dag(void* out, const void* y) {
+  // D_r^dag = gamma5 (1 - A_ee^-1 H_eo A_oo^-1 H_oe) gamma5
+  w->ensure(prec, F->g);
+  spinor_convert(prec, w->t1.p, prec, y, F->g.Vh, st);
+  spinor_gamma5(prec, w->t1.p, F->g.Vh, st);
+  hop(w->t2.p, w->t1.p, nullptr, 1, 0, true, 1.0);
+  hop(out, w->t2.p, w->t1.p, 0, 1, true, -1.0);
+  spinor_gamma5(prec, out, F->g.Vh, st);
+}
+
+void FineOp::D(void* oe, void* oo, const void* ie, const void* io) {
+  hop(oe, io, ie, 0, 2, false, 1.0);
+  hop(oo, ie, io, 1, 2, false, 1.0);
+}
+
+void FineOp::Dp(void* oe, void* oo, const void* ie, const void* io) {
+  w->ensure(prec, F->g);
+  clover(w->t1.p, ie, 0, 1);
+  clover(w->t2.p, io, 1, 1);
+  hop(oe, w->t2.p, ie, 0, 1, false, 1.0);
+  hop(oo, w->t1.p, io, 1, 1, false, 1.0);
+}
+
+void FineOp::reduced_source(void* br, const void* be, const void* bo) {
+  w->ensure(prec, F->g);
+  clover(w->t1.p, bo, 1, 1);
+  hop(br, w->t1.p, be, 0, 1, false, -1.0);
+}
+
+void FineOp::reconstruct(void* xe, void* xo, const void* ye, const void* bo) {
+  w->ensure(prec, F->g);
+  clover(xe, ye, 0, 1);
+  hop(w->t1.p, xe, bo, 1, 1, false, -1.0);
+  clover(xo, w->t1.p, 1, 1);
+}
+
+// ------------------------------------------------------------------ coarse level
+void CoarseWork::ensure(size_t bytes) {
+  if (t1.n < bytes) {
+    t1.alloc(bytes);
+    t2.alloc(bytes);
+  }
+}
+
+void CoarseOp::Dfull(void* out, const void* in) {
+  launch_coarse_hop(prec, out, in, in, C->Yhop[pi()].p, C->X[pi()].p, 2, 1.0, -1, C->cg, C->nbr.as<int>(), st);
+}
+
+void CoarseOp::Dp(void* out, const void* in) {
+  launch_coarse_hop(prec, out, in, in, C->Yt[pi()].p, nullptr, 1, 1.0, -1, C->cg, C->nbr.as<int>(), st);
+}
+
+void CoarseOp::Dr(void* out, const void* y) {
+  w->ensure(nall() * csize());
+  launch_coarse_hop(prec, w->t1.p, y, nullptr, C->Yt[pi()].p, nullptr, 0, 1.0, 1, C->cg, C->nbr.as<int>(), st);
+  launch_coarse_hop(prec, out, w->t1.p, y, C->Yt[pi()].p, nullptr, 1, -1.0, 0, C->cg, C->nbr.as<int>(), st);
+}
+
+void CoarseOp::reduced_source(void* br, const void* b) {
+  launch_coarse_hop(prec, br, b, b, C->Yt[pi()].p, nullptr, 1, -1.0, 0, C->cg, C->nbr.as<int>(), st);
+}
+
+void CoarseOp::reconstruct(void* c, const void* y, const void* b) {
+  w->ensure(nall() * csize());
+  launch_coarse_local(prec, c, y, C->Xinv[pi()].p, 0, C->cg, st);
+  launch_coarse_hop(prec, w->t1.p, y, b, C->Yt[pi()].p, nullptr, 1, -1.0, 1, C->cg, C->nbr.as<int>(), st);
+  launch_coarse_local(prec, c, w->t1.p, C->Xinv[pi()].p, 1, C->cg, st);
+}
+
+}  // namespace wcmg

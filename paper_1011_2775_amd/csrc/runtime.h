@@ -1,0 +1,186 @@
+// Host-side state of a wcmg context: per-lattice fields, the multigrid
+// hierarchy, the operator wrappers that sequence kernel launches, and the
+// solvers.
+#pragma once
+
+#include <functional>
+#include <memory>
+
+#include "kernels.h"
+
+namespace wcmg {
+
+// ------------------------------------------------------------------ timers
+// HIP-event timing of selected kernel classes on the context stream.
+struct KernelTimer {
+  bool on = false;
+  hipStream_t st = nullptr;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;  // (class, (start, stop))
+  long count[2] = {0, 0};
+  double ms[2] = {0.0, 0.0};
+  hipEvent_t get();
+  void begin(int cls, hipEvent_t* a);
+  void end(int cls, hipEvent_t a);
+  void drain();  // synchronises and accumulates
+  void reset();
+  ~KernelTimer();
+};
+
+// ------------------------------------------------------------------ reductions
+struct Reducer {
+  hipStream_t st = nullptr;
+  DBuf partial, res;
+  double* host = nullptr;
+  void init(hipStream_t s);
+  double* dres() { return res.as<double>(); }
+  double* dpart() { return partial.as<double>(); }
+  const double* fetch(int n);  // copy n results to the host and synchronise
+  ~Reducer();
+};
+
+struct Ctx;
+
+// ------------------------------------------------------------------ fine level
+struct FineFields {
+  Geom g;
+  bool have_gauge = false, have_clover = false;
+  double m0 = 0.0, csw = 0.0;
+  DBuf gauge[3];   // per precision
+  DBuf clov[3];    // per precision, packed A and A^-1
+};
+
+// temporaries of one precision on the fine lattice
+struct FineWork {
+  int prec = -1;
+  size_t hb = 0;
+  DBuf t1, t2, t3;  // parity halves
+  void ensure(int p, const Geom& g);
+};
+
+struct FineOp {
+  Ctx* ctx;
+  FineFields* F;
+  int prec;
+  FineWork* w;
+  hipStream_t st;
+  const Geom& g() const { return F->g; }
+  size_t hb() const { return spinor_bytes(prec, F->g.Vh); }
+  size_t nelem() const { return (size_t)12 * F->g.Vh; }
+  void hop(void* out, const void* in, const void* x, int parity, int diag, bool postinv, double coeff);
+  void clover(void* out, const void* in, int parity, int kind);
+  // reduced operator D_r y = y - H_eo A_oo^-1 H_oe A_ee^-1 y on even halves
+  void Dr(void* out, const void* y);
+  void Dr_dag(void* out, const void* y);
+  // full-lattice operators on (even, odd) halves
+  void D(void* oe, void* oo, const void* ie, const void* io);
+  void Dp(void* oe, void* oo, const void* ie, const void* io);
+  void reduced_source(void* br, const void* be, const void* bo);
+  void reconstruct(void* xe, void* xo, const void* ye, const void* bo);
+};
+
+// ------------------------------------------------------------------ coarse level
+struct CoarseLevel {
+  CoarseGeom cg{};
+  BlockGeom bg{};       // blocking of the finer level that produced it
+  int nvec = 0;
+  bool built = false;
+  std::vector<int> perm_host;  // lex -> internal
+  DBuf nbr, perm;              // device int arrays
+  DBuf Y9;                     // FP64 [site][9][n][n]
+  DBuf X[2], Xinv[2], Yhop[2], Yt[2];  // [0] FP64, [1] FP32
+};
+
+struct CoarseWork {
+  DBuf t1, t2;
+  void ensure(size_t bytes);
+};
+
+struct CoarseOp {
+  CoarseLevel* C;
+  int prec;     // F64 or F32
+  CoarseWork* w;
+  hipStream_t st;
+  int pi() const { return prec == WCMG_F64 ? 0 : 1; }
+  size_t csize() const { return prec == WCMG_F64 ? 16 : 8; }
+  size_t nall() const { return (size_t)C->cg.V * C->cg.n; }
+  size_t neven() const { return (size_t)C->cg.Vh * C->cg.n; }
+  void Dfull(void* out, const void* in);
+  void Dp(void* out, const void* in);
+  void Dr(void* out, const void* y);  // full-size buffers, even half meaningful
+  void reduced_source(void* br, const void* b);
+  void reconstruct(void* c, const void* y, const void* b);
+};
+
+// ------------------------------------------------------------------ hierarchy
+struct FineTransfer {
+  BlockGeom bg{};
+  int nvec = 0;
+  bool have_vecs = false, orth = false;
+  DBuf raw;       // FP64 full spinors (as given / found by the setup)
+  DBuf v64, v32;  // block-orthonormalised copies
+};
+
+struct MGSolver;
+
+struct LatticeState {
+  std::shared_ptr<MGSolver> mg;  // preconditioner buffers, rebuilt with the hierarchy
+  FineFields F;
+  bool have_params = false;
+  wcmg_mg_params params{};
+  FineTransfer T0;
+  std::vector<std::unique_ptr<CoarseLevel>> levels;  // levels[0] = coarse level 1
+};
+
+// flexible restarted GCR on flat vectors of n complex elements in `prec`
+struct GcrSpace {
+  int prec;
+  size_t n;      // complex elements
+  size_t bytes;  // bytes per vector
+  std::vector<DBuf> Z, Q;
+  DBuf r;
+  void ensure(int restart);
+};
+// ------------------------------------------------------------------ context
+struct Ctx {
+  hipStream_t st = nullptr;
+  int device = 0;
+  std::vector<std::unique_ptr<LatticeState>> lats;
+  Reducer red;
+  KernelTimer timer;
+  FineWork fw[3];
+  CoarseWork cw[2];
+  GcrSpace outer{};  // Krylov basis of the outer FP64 solver
+  // scratch pools reused across calls (keyed by purpose)
+  std::vector<DBuf> scratch;
+  void* scratch_buf(int slot, size_t bytes);
+};
+
+// ------------------------------------------------------------------ solvers
+using OpFn = std::function<void(void* out, const void* in)>;
+
+struct KrylovResult {
+  int iters = 0;
+  int status = WCMG_OK;
+  double rel_res = 0.0;
+};
+
+KrylovResult gcr(Ctx& c, GcrSpace& S, const OpFn& A, const OpFn* K, void* x, const void* b, bool x_zero,
+                 double tol, double target_norm, int restart, int maxiter, bool fixed_iters = false);
+KrylovResult bicgstab(Ctx& c, int prec, size_t n, const OpFn& A, void* x, const void* b, double tol,
+                      double target_norm, int maxiter);
+
+// vector helpers
+double norm2(Ctx& c, int prec, const void* x, size_t n);
+
+// multigrid driver
+void mg_setup_null_vectors(Ctx& c, LatticeState& L, int level);
+void mg_build_coarse(Ctx& c, LatticeState& L, int level);
+struct MGSolver;
+void solve_rhs(Ctx& c, LatticeState& L, int solver, void* x_e, void* x_o, const void* b_e, const void* b_o,
+               bool x_zero, double tol, wcmg_stats* st);
+
+CoarseGeom make_coarse_geom(const BlockGeom& bg, int nvec);
+BlockGeom make_block_geom(const int L[4], const int b[4]);
+
+}  // namespace wcmg

@@ -1,0 +1,534 @@
+// Solvers: flexible GCR, BiCGStab, the multigrid setup (Setup procedure
+// section), the coarse-operator construction Yhat = R D_p P and the
+// recursive GCR cycle (Implementation paragraph).
+#include <chrono>
+#include <cmath>
+
+#include "random.h"
+#include "runtime.h"
+
+namespace wcmg {
+
+void GcrSpace::ensure(int restart) {
+  if ((int)Z.size() < restart) {
+    Z.resize(restart);
+    Q.resize(restart);
+  }
+  for (int k = 0; k < restart; ++k) {
+    if (Z[k].n < bytes) Z[k].alloc(bytes);
+    if (Q[k].n < bytes) Q[k].alloc(bytes);
+  }
+  if (r.n < bytes) r.alloc(bytes);
+}
+
+static bool finite(double v) { return std::isfinite(v); }
+
+// Flexible GCR with classical Gram-Schmidt against the unnormalised basis
+// q_j = A z_j, residual update r -= alpha q, and the solution update
+// x += sum alpha_j z_j deferred to the end of each restart cycle.
+KrylovResult gcr(Ctx& c, GcrSpace& S, const OpFn& A, const OpFn* K, void* x, const void* b, bool x_zero, double tol,
+                 double target_norm, int restart, int maxiter, bool fixed) {
+  S.ensure(restart);
+  const int prec = S.prec;
+  const size_t n = S.n;
+  hipStream_t st = c.st;
+  Reducer& R = c.red;
+  void* r = S.r.p;
+  KrylovResult res;
+  if (x_zero) {
+    blas_zero(prec, x, n, st);
+    blas_copy(prec, r, b, n, st);
+  } else {
+    A(r, x);
+    blas_axpby(prec, 1.0, 0.0, b, -1.0, 0.0, r, n, st);
+  }
+  double rn2 = norm2(c, prec, r, n);
+  const double target = tol * target_norm;
+  if (!finite(rn2)) {
+    res.status = WCMG_ENAN;
+    return res;
+  }
+  if (!fixed && std::sqrt(rn2) <= target) {
+    res.rel_res = target_norm > 0 ? std::sqrt(rn2) / target_norm : 0.0;
+    return res;
+  }
+  std::vector<double> coef(2 * restart), alpha(2 * restart), qq(restart);
+  std::vector<const void*> Qp(restart), Zp(restart);
+  bool converged = false;
+  while (res.iters < maxiter) {
+    int k = 0;
+    for (; k < restart;) {
+      void* z = S.Z[k].p;
+      void* q = S.Q[k].p;
+      Qp[k] = q;
+      Zp[k] = z;
+      if (K)
+        (*K)(z, r);
+      else
+        blas_copy(prec, z, r, n, st);
+      A(q, z);
+      if (k > 0) {
+        blas_multi_cdot(prec, Qp.data(), k, q, n, R.dres(), R.dpart(), st);
+        const double* d = R.fetch(2 * k);
+        for (int j = 0; j < k; ++j) {
+          coef[2 * j] = d[2 * j] / qq[j];
+          coef[2 * j + 1] = d[2 * j + 1] / qq[j];
+        }
+      }
+      blas_gcr_orth(prec, coef.data(), Qp.data(), Zp.data(), k, q, z, r, n, R.dres(), R.dpart(), st);
+      const double* o = R.fetch(3);
+      qq[k] = o[0];
+      if (!(qq[k] > 0.0) || !finite(qq[k])) {
+        res.status = finite(qq[k]) ? WCMG_EBREAKDOWN : WCMG_ENAN;
+        break;
+      }
+      alpha[2 * k] = o[1] / qq[k];
+      alpha[2 * k + 1] = o[2] / qq[k];
+      blas_axpy_norm(prec, -alpha[2 * k], -alpha[2 * k + 1], q, r, n, R.dres(), R.dpart(), st);
+      rn2 = R.fetch(1)[0];
+      ++k;
+      ++res.iters;
+      if (!finite(rn2)) {
+        res.status = WCMG_ENAN;
+        break;
+      }
+      if ((!fixed && std::sqrt(rn2) <= target) || res.iters >= maxiter) break;
+    }
+    if (k > 0) blas_multi_axpy(prec, alpha.data(), Zp.data(), k, x, n, st);
+    if (res.status != WCMG_OK) break;
+    if (fixed) break;
+    // true residual at the end of every cycle
+    A(r, x);
+    blas_axpby(prec, 1.0, 0.0, b, -1.0, 0.0, r, n, st);
+    rn2 = norm2(c, prec, r, n);
+    if (!finite(rn2)) {
+      res.status = WCMG_ENAN;
+      break;
+    }
+    if (std::sqrt(rn2) <= target) {
+      converged = true;
+      break;
+    }
+  }
+  res.rel_res = target_norm > 0 ? std::sqrt(rn2) / target_norm : 0.0;
+  if (!fixed && !converged && res.status == WCMG_OK) res.status = WCMG_ENOCONV;
+  return res;
+}
+
+// BiCGStab (van der Vorst); s is formed in place of r.
+KrylovResult bicgstab(Ctx& c, int prec, size_t n, const OpFn& A, void* x, const void* b, double tol,
+                      double target_norm, int maxiter) {
+  const size_t bytes = n * (prec == WCMG_F64 ? 16 : 8);
+  void* r = c.scratch_buf(4, bytes);
+  void* rhat = c.scratch_buf(5, bytes);
+  void* p = c.scratch_buf(6, bytes);
+  void* v = c.scratch_buf(7, bytes);
+  void* t = c.scratch_buf(8, bytes);
+  hipStream_t st = c.st;
+  Reducer& R = c.red;
+  KrylovResult res;
+  const double target = tol * target_norm;
+  int restarts = 0;
+  auto start = [&]() -> double {
+    A(r, x);
+    blas_axpby(prec, 1.0, 0.0, b, -1.0, 0.0, r, n, st);
+    blas_copy(prec, rhat, r, n, st);
+    blas_zero(prec, p, n, st);
+    blas_zero(prec, v, n, st);
+    return norm2(c, prec, r, n);
+  };
+  double rn2 = start();
+  double rho_r = 1.0, rho_i = 0.0, al_r = 1.0, al_i = 0.0, om_r = 1.0, om_i = 0.0;
+  double rn_r = rn2, rn_i = 0.0;  // <rhat, r>
+  auto cdiv = [](double ar, double ai, double br, double bi, double& cr, double& ci) {
+    double d = br * br + bi * bi;
+    cr = (ar * br + ai * bi) / d;
+    ci = (ai * br - ar * bi) / d;
+  };
+  auto cmul = [](double ar, double ai, double br, double bi, double& cr, double& ci) {
+    cr = ar * br - ai * bi;
+    ci = ar * bi + ai * br;
+  };
+  while (std::sqrt(rn2) > target && res.iters < maxiter) {
+    if (!finite(rn2)) {
+      res.status = WCMG_ENAN;
+      break;
+    }
+    double t1r, t1i, t2r, t2i, br, bi;
+    cdiv(rn_r, rn_i, rho_r, rho_i, t1r, t1i);
+    cdiv(al_r, al_i, om_r, om_i, t2r, t2i);
+    cmul(t1r, t1i, t2r, t2i, br, bi);
+    blas_bicg_p(prec, br, bi, om_r, om_i, r, v, p, n, st);
+    A(v, p);
+    blas_cdot(prec, rhat, v, n, R.dres(), R.dpart(), st);
+    const double* d = R.fetch(2);
+    double rv_r = d[0], rv_i = d[1];
+    const double scale = std::sqrt(rn2) * std::sqrt(norm2(c, prec, rhat, n));
+    if (std::hypot(rv_r, rv_i) <= 1e-30 * scale || std::hypot(rn_r, rn_i) <= 1e-30 * scale) {
+      // breakdown: restart from the current iterate
+      if (++restarts > 20) {
+        res.status = WCMG_EBREAKDOWN;
+        break;
+      }
+      rn2 = start();
+      rho_r = al_r = om_r = 1.0;
+      rho_i = al_i = om_i = 0.0;
+      rn_r = rn2;
+      rn_i = 0.0;
+      continue;
+    }
+    cdiv(rn_r, rn_i, rv_r, rv_i, al_r, al_i);
+    blas_axpby(prec, -al_r, -al_i, v, 1.0, 0.0, r, n, st);  // r <- s = r - alpha v
+    A(t, r);
+    blas_cdot_norm(prec, t, r, n, R.dres(), R.dpart(), st);
+    d = R.fetch(3);
+    if (!(d[2] > 0.0)) {
+      // s = 0: x += alpha p solves the system
+      blas_axpby(prec, al_r, al_i, p, 1.0, 0.0, x, n, st);
+      rn2 = norm2(c, prec, r, n);
+      ++res.iters;
+      break;
+    }
+    om_r = d[0] / d[2];
+    om_i = d[1] / d[2];
+    rho_r = rn_r;
+    rho_i = rn_i;
+    blas_bicg_update(prec, al_r, al_i, om_r, om_i, p, r, t, x, r, rhat, n, R.dres(), R.dpart(), st);
+    d = R.fetch(3);
+    rn2 = d[0];
+    rn_r = d[1];
+    rn_i = d[2];
+    ++res.iters;
+  }
+  res.rel_res = target_norm > 0 ? std::sqrt(rn2) / target_norm : 0.0;
+  if (res.status == WCMG_OK && std::sqrt(rn2) > target) res.status = WCMG_ENOCONV;
+  return res;
+}
+
+// ---------------------------------------------------------------------------
+// multigrid preconditioner (two levels: fine Wilson-clover, coarse stencil)
+// ---------------------------------------------------------------------------
+struct MGSolver {
+  Ctx& c;
+  LatticeState& L;
+  int sp;  // precision of the fine part of the preconditioner
+  int cp;  // precision of the coarse level
+  DBuf r_s, e_s, res_s, Ar_s;
+  DBuf cb, cc, cbr, cy;
+  GcrSpace cspace{};
+  long calls = 0, iters = 0;
+
+  MGSolver(Ctx& ctx, LatticeState& lat) : c(ctx), L(lat) {
+    sp = L.params.smoother_prec == WCMG_F64 ? WCMG_F64 : WCMG_F32;
+    cp = sp;
+    const Geom& g = L.F.g;
+    size_t hb = spinor_bytes(sp, g.Vh);
+    r_s.alloc(hb);
+    e_s.alloc(hb);
+    res_s.alloc(hb);
+    Ar_s.alloc(hb);
+    CoarseLevel& C = *L.levels[0];
+    size_t cs = (cp == WCMG_F64 ? 16 : 8);
+    size_t nall = (size_t)C.cg.V * C.cg.n;
+    cb.alloc(nall * cs);
+    cc.alloc(nall * cs);
+    cbr.alloc(nall * cs);
+    cy.alloc(nall * cs);
+    cspace.prec = cp;
+    cspace.n = C.cg.split ? (size_t)C.cg.Vh * C.cg.n : nall;
+    cspace.bytes = cspace.n * cs;
+  }
+
+  const void* vecs(int prec) const { return prec == WCMG_F64 ? L.T0.v64.p : L.T0.v32.p; }
+
+  void coarse_solve(void* out, void* in) {
+    CoarseLevel& C = *L.levels[0];
+    CoarseOp cop{&C, cp, &c.cw[cp == WCMG_F64 ? 0 : 1], c.st};
+    const wcmg_mg_params& p = L.params;
+    KrylovResult kr;
+    if (C.cg.split) {
+      cop.reduced_source(cbr.p, in);
+      double bn = std::sqrt(norm2(c, cp, cbr.p, cop.neven()));
+      OpFn A = [&](void* o, const void* i) { cop.Dr(o, i); };
+      kr = gcr(c, cspace, A, nullptr, cy.p, cbr.p, true, p.tol[0], bn, p.restart[0], p.max_iter[0]);
+      cop.reconstruct(out, cy.p, in);
+    } else {
+      double bn = std::sqrt(norm2(c, cp, in, cop.nall()));
+      OpFn A = [&](void* o, const void* i) { cop.Dfull(o, i); };
+      kr = gcr(c, cspace, A, nullptr, out, in, true, p.tol[0], bn, p.restart[0], p.max_iter[0]);
+    }
+    ++calls;
+    iters += kr.iters;
+  }
+
+  // K(r_e): even part of P (coarse solve) R (r_e, 0), then MR smoothing on D_r
+  void precondition(void* z64, const void* r64) {
+    const Geom& g = L.F.g;
+    hipStream_t st = c.st;
+    FineOp op{&c, &L.F, sp, &c.fw[sp], st};
+    const size_t n = (size_t)12 * g.Vh;
+    CoarseLevel& C = *L.levels[0];
+    spinor_convert(sp, r_s.p, WCMG_F64, r64, g.Vh, st);
+    launch_restrict(sp, cb.p, C.cg.n, 1, r_s.p, vecs(sp), L.T0.nvec, 0, g, L.T0.bg, false, st);
+    coarse_solve(cc.p, cb.p);
+    launch_prolong(sp, e_s.p, cc.p, vecs(sp), L.T0.nvec, 0, g, L.T0.bg, st);
+    const int nu = L.params.nu_post;
+    if (nu > 0) {
+      op.Dr(Ar_s.p, e_s.p);
+      blas_copy(sp, res_s.p, r_s.p, n, st);
+      blas_axpby(sp, -1.0, 0.0, Ar_s.p, 1.0, 0.0, res_s.p, n, st);
+      for (int i = 0; i < nu; ++i) {
+        op.Dr(Ar_s.p, res_s.p);
+        blas_cdot_norm(sp, Ar_s.p, res_s.p, n, c.red.dres(), c.red.dpart(), st);
+        const double* d = c.red.fetch(3);
+        if (!(d[2] > 0.0)) break;
+        blas_mr_update(sp, d[0] / d[2], d[1] / d[2], e_s.p, res_s.p, Ar_s.p, n, st);
+      }
+    }
+    spinor_convert(WCMG_F64, z64, sp, e_s.p, g.Vh, st);
+  }
+};
+
+static void require_hierarchy(LatticeState& L) {
+  if (!L.have_params) fail(WCMG_ESTATE, "multigrid parameters not set");
+  if (L.levels.empty() || !L.levels[0]->built) fail(WCMG_ESTATE, "coarse operator not built");
+}
+
+// ---------------------------------------------------------------------------
+// setup: inverse iteration on D_p with Rayleigh-quotient monitoring
+// ---------------------------------------------------------------------------
+void mg_setup_null_vectors(Ctx& c, LatticeState& L, int level) {
+  if (level != 0) fail(WCMG_EINVAL, "null-vector setup on coarse levels is not available");
+  if (!L.F.have_clover) fail(WCMG_ESTATE, "clover not set");
+  if (!L.have_params) fail(WCMG_ESTATE, "multigrid parameters not set");
+  const wcmg_mg_params& p = L.params;
+  const Geom& g = L.F.g;
+  hipStream_t st = c.st;
+  const int nvec = p.nvec[0];
+  const size_t hb = spinor_bytes(WCMG_F64, g.Vh);
+  const size_t n = (size_t)24 * g.Vh;
+  FineOp op{&c, &L.F, WCMG_F64, &c.fw[0], st};
+  OpFn Dp = [&](void* o, const void* i) {
+    op.Dp(o, (char*)o + hb, i, (const char*)i + hb);
+  };
+  L.T0.raw.alloc((size_t)nvec * 2 * hb);
+  void* v = c.scratch_buf(9, 2 * hb);
+  void* x = c.scratch_buf(10, 2 * hb);
+  void* w = c.scratch_buf(11, 2 * hb);
+  GcrSpace S{WCMG_F64, n, 2 * hb, {}, {}, DBuf()};
+  std::vector<const void*> found;
+  std::vector<double> cf(2 * nvec);
+  for (int k = 0; k < nvec; ++k) {
+    random_fine_vector(v, p.seed, k, 0, g, st);
+    double rho_old = -1.0;
+    for (int step = 0; step < p.setup_max_steps; ++step) {
+      gcr(c, S, Dp, nullptr, x, v, true, 0.0, 1.0, p.setup_relax, p.setup_relax, true);
+      blas_copy(WCMG_F64, v, x, n, st);
+      for (int pass = 0; pass < 2 && k > 0; ++pass) {
+        blas_multi_cdot(WCMG_F64, found.data(), k, v, n, c.red.dres(), c.red.dpart(), st);
+        const double* d = c.red.fetch(2 * k);
+        for (int j = 0; j < 2 * k; ++j) cf[j] = -d[j];
+        blas_multi_axpy(WCMG_F64, cf.data(), found.data(), k, v, n, st);
+      }
+      double nv = std::sqrt(norm2(c, WCMG_F64, v, n));
+      if (!(nv > 0.0) || !finite(nv)) fail(WCMG_ENAN, "setup vector vanished");
+      blas_axpby(WCMG_F64, 0.0, 0.0, v, 1.0 / nv, 0.0, v, n, st);
+      Dp(w, v);
+      double rho = norm2(c, WCMG_F64, w, n);
+      if (rho_old > 0.0 && std::fabs(rho - rho_old) / rho < p.setup_rq_tol) break;
+      rho_old = rho;
+    }
+    void* dst = (char*)L.T0.raw.p + (size_t)k * 2 * hb;
+    blas_copy(WCMG_F64, dst, v, n, st);
+    found.push_back(dst);
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  L.T0.nvec = nvec;
+  L.T0.have_vecs = true;
+  L.T0.orth = false;
+  for (auto& lv : L.levels) lv->built = false;
+  L.mg.reset();
+}
+
+// ---------------------------------------------------------------------------
+// coarse operator  Yhat = R D_p P, direction resolved
+// ---------------------------------------------------------------------------
+static void build_coarse_tables(CoarseLevel& C) {
+  const BlockGeom& bg = C.bg;
+  const int V = bg.Vc;
+  C.perm_host.resize(V);
+  for (int l = 0; l < V; ++l) C.perm_host[l] = coarse_internal_index_host(bg, l);
+  std::vector<int> nbr((size_t)V * 8);
+  for (int l = 0; l < V; ++l) {
+    int c[4] = {l % bg.nb[0], (l / bg.nb[0]) % bg.nb[1], (l / (bg.nb[0] * bg.nb[1])) % bg.nb[2],
+                l / (bg.nb[0] * bg.nb[1] * bg.nb[2])};
+    for (int mu = 0; mu < 4; ++mu)
+      for (int back = 0; back < 2; ++back) {
+        int o[4] = {c[0], c[1], c[2], c[3]};
+        o[mu] = (o[mu] + (back ? -1 : 1) + bg.nb[mu]) % bg.nb[mu];
+        int ol = ((o[3] * bg.nb[2] + o[2]) * bg.nb[1] + o[1]) * bg.nb[0] + o[0];
+        nbr[(size_t)C.perm_host[l] * 8 + 2 * mu + back] = C.perm_host[ol];
+      }
+  }
+  C.nbr.alloc(nbr.size() * sizeof(int));
+  HIPCHK(hipMemcpy(C.nbr.p, nbr.data(), nbr.size() * sizeof(int), hipMemcpyHostToDevice));
+  C.perm.alloc((size_t)V * sizeof(int));
+  HIPCHK(hipMemcpy(C.perm.p, C.perm_host.data(), (size_t)V * sizeof(int), hipMemcpyHostToDevice));
+}
+
+void mg_build_coarse(Ctx& c, LatticeState& L, int level) {
+  if (level != 0) fail(WCMG_EINVAL, "coarse build beyond the first level is not available");
+  if (!L.F.have_clover) fail(WCMG_ESTATE, "clover not set");
+  if (!L.have_params) fail(WCMG_ESTATE, "multigrid parameters not set");
+  if (!L.T0.have_vecs) fail(WCMG_ESTATE, "null vectors not set");
+  const wcmg_mg_params& p = L.params;
+  const Geom& g = L.F.g;
+  hipStream_t st = c.st;
+  const int nvec = p.nvec[0];
+  const size_t hb64 = spinor_bytes(WCMG_F64, g.Vh);
+  const size_t hb32 = spinor_bytes(WCMG_F32, g.Vh);
+  FineTransfer& T = L.T0;
+  T.bg = make_block_geom(g.L, p.block[0]);
+  T.nvec = nvec;
+  // P: block x chirality orthonormalisation
+  T.v64.alloc((size_t)nvec * 2 * hb64);
+  HIPCHK(hipMemcpyAsync(T.v64.p, T.raw.p, (size_t)nvec * 2 * hb64, hipMemcpyDeviceToDevice, st));
+  int* flag = (int*)c.scratch_buf(12, 64);
+  HIPCHK(hipMemsetAsync(flag, 0, 64, st));
+  launch_block_orthonormalize(T.v64.p, nvec, g, T.bg, flag, st);
+  int hflag[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (hflag[0]) fail(WCMG_ERANK, "null vectors are linearly dependent on a block");
+  T.v32.alloc((size_t)nvec * 2 * hb32);
+  for (int k = 0; k < 2 * nvec; ++k)
+    spinor_convert(WCMG_F32, (char*)T.v32.p + (size_t)k * hb32, WCMG_F64, (const char*)T.v64.p + (size_t)k * hb64,
+                   g.Vh, st);
+  T.orth = true;
+
+  if (L.levels.empty()) L.levels.emplace_back(new CoarseLevel());
+  CoarseLevel& C = *L.levels[0];
+  C.bg = T.bg;
+  C.nvec = nvec;
+  C.cg = make_coarse_geom(T.bg, nvec);
+  build_coarse_tables(C);
+  const int n = C.cg.n, V = C.cg.V;
+  const size_t nn = (size_t)n * n;
+  C.Y9.alloc((size_t)V * 9 * nn * 16);
+
+  FineOp op{&c, &L.F, WCMG_F64, &c.fw[0], st};
+  void* bucket[9];
+  for (int s = 0; s < 9; ++s) bucket[s] = c.scratch_buf(20 + s, 2 * hb64);
+  void* vcol = c.scratch_buf(30, 2 * hb64);
+  void* u = c.scratch_buf(31, 2 * hb64);
+  for (int s = 0; s < 2; ++s)
+    for (int k = 0; k < nvec; ++k) {
+      const int j = s * nvec + k;
+      const char* vk = (const char*)T.v64.p + (size_t)k * 2 * hb64;
+      spinor_chiral_project(WCMG_F64, vcol, vk, g.Vh, s, st);
+      spinor_chiral_project(WCMG_F64, (char*)vcol + hb64, vk + hb64, g.Vh, s, st);
+      op.clover(u, vcol, 0, 1);
+      op.clover((char*)u + hb64, (char*)vcol + hb64, 1, 1);
+      launch_hop_split(bucket, vcol, u, L.F.gauge[WCMG_F64].p, g, T.bg, st);
+      for (int slot = 0; slot < 9; ++slot) {
+        void* out = (char*)C.Y9.p + ((size_t)slot * n + j) * n * 16;
+        launch_restrict(WCMG_F64, out, 9 * nn, 1, bucket[slot], T.v64.p, nvec, 0, g, T.bg, false, st);
+        launch_restrict(WCMG_F64, out, 9 * nn, 1, (char*)bucket[slot] + hb64, T.v64.p, nvec, 1, g, T.bg, true, st);
+      }
+    }
+  // split into X and the eight hops, invert X, form Ytilde = Y X^-1
+  C.X[0].alloc((size_t)V * nn * 16);
+  C.Yhop[0].alloc((size_t)V * 8 * nn * 16);
+  HIPCHK(hipMemcpy2DAsync(C.X[0].p, nn * 16, C.Y9.p, 9 * nn * 16, nn * 16, V, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpy2DAsync(C.Yhop[0].p, 8 * nn * 16, (char*)C.Y9.p + nn * 16, 9 * nn * 16, 8 * nn * 16, V,
+                          hipMemcpyDeviceToDevice, st));
+  C.Xinv[0].alloc((size_t)V * nn * 16);
+  HIPCHK(hipMemcpyAsync(C.Xinv[0].p, C.X[0].p, (size_t)V * nn * 16, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemsetAsync(flag, 0, 64, st));
+  launch_batched_inverse(C.Xinv[0].as<double>(), V, n, flag, st);
+  C.Yt[0].alloc((size_t)V * 8 * nn * 16);
+  launch_coarse_right_mul(C.Yt[0].as<double>(), C.Yhop[0].as<double>(), C.Xinv[0].as<double>(), C.nbr.as<int>(), V,
+                          n, st);
+  // FP32 copies for the mixed-precision cycle
+  C.X[1].alloc((size_t)V * nn * 8);
+  C.Xinv[1].alloc((size_t)V * nn * 8);
+  C.Yhop[1].alloc((size_t)V * 8 * nn * 8);
+  C.Yt[1].alloc((size_t)V * 8 * nn * 8);
+  launch_reals_convert(WCMG_F32, C.X[1].p, C.X[0].as<double>(), (size_t)V * nn * 2, st);
+  launch_reals_convert(WCMG_F32, C.Xinv[1].p, C.Xinv[0].as<double>(), (size_t)V * nn * 2, st);
+  launch_reals_convert(WCMG_F32, C.Yhop[1].p, C.Yhop[0].as<double>(), (size_t)V * 8 * nn * 2, st);
+  launch_reals_convert(WCMG_F32, C.Yt[1].p, C.Yt[0].as<double>(), (size_t)V * 8 * nn * 2, st);
+  HIPCHK(hipMemcpyAsync(hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (hflag[0]) fail(WCMG_ERANK, "singular coarse site block");
+  C.built = true;
+  L.mg.reset();
+}
+
+// ---------------------------------------------------------------------------
+// one right-hand side:  b_r (Eq.(4)), solve D_r y = b_r, reconstruct x
+// ---------------------------------------------------------------------------
+void solve_rhs(Ctx& c, LatticeState& L, int solver, void* x_e, void* x_o, const void* b_e, const void* b_o,
+               bool x_zero, double tol, wcmg_stats* stats) {
+  auto t0 = std::chrono::steady_clock::now();
+  const Geom& g = L.F.g;
+  hipStream_t st = c.st;
+  const size_t hb = spinor_bytes(WCMG_F64, g.Vh);
+  const size_t n = (size_t)12 * g.Vh;
+  FineOp op{&c, &L.F, WCMG_F64, &c.fw[0], st};
+  double bn2 = norm2(c, WCMG_F64, b_e, n) + norm2(c, WCMG_F64, b_o, n);
+  wcmg_stats s{};
+  if (!finite(bn2)) fail(WCMG_ENAN, "right-hand side is not finite");
+  if (bn2 == 0.0) {
+    blas_zero(WCMG_F64, x_e, n, st);
+    blas_zero(WCMG_F64, x_o, n, st);
+    if (stats) *stats = s;
+    return;
+  }
+  const double bn = std::sqrt(bn2);
+  void* br = c.scratch_buf(0, hb);
+  void* y = c.scratch_buf(1, hb);
+  op.reduced_source(br, b_e, b_o);
+  if (!x_zero) op.clover(y, x_e, 0, 0);  // y_e = D_ee x_e
+  OpFn Dr = [&](void* o, const void* i) { op.Dr(o, i); };
+  const wcmg_mg_params& p = L.params;
+  const int restart = L.have_params ? p.outer_restart : 16;
+  const int maxiter = L.have_params ? p.outer_max_iter : 100000;
+  KrylovResult kr;
+  if (solver == WCMG_BICGSTAB) {
+    if (x_zero) blas_zero(WCMG_F64, y, n, st);
+    kr = bicgstab(c, WCMG_F64, n, Dr, y, br, tol, bn, L.have_params ? std::max(maxiter, 100000) : 100000);
+  } else {
+    GcrSpace& S64 = c.outer;
+    S64.prec = WCMG_F64;
+    S64.n = n;
+    S64.bytes = hb;
+    if (solver == WCMG_GCR) {
+      kr = gcr(c, S64, Dr, nullptr, y, br, x_zero, tol, bn, restart, L.have_params ? std::max(maxiter, 100000) : 100000);
+    } else {
+      require_hierarchy(L);
+      if (!L.mg) L.mg = std::make_shared<MGSolver>(c, L);
+      MGSolver& mg = *L.mg;
+      mg.calls = mg.iters = 0;
+      OpFn K = [&](void* o, const void* i) { mg.precondition(o, i); };
+      kr = gcr(c, S64, Dr, &K, y, br, x_zero, tol, bn, restart, maxiter);
+      s.inner_iters[0] = mg.calls ? (double)mg.iters / mg.calls : 0.0;
+    }
+  }
+  op.reconstruct(x_e, x_o, y, b_o);
+  // true residual of the full system in FP64
+  void* te = c.scratch_buf(2, hb);
+  void* to = c.scratch_buf(3, hb);
+  op.D(te, to, x_e, x_o);
+  blas_axpby(WCMG_F64, 1.0, 0.0, b_e, -1.0, 0.0, te, n, st);
+  blas_axpby(WCMG_F64, 1.0, 0.0, b_o, -1.0, 0.0, to, n, st);
+  double rr = norm2(c, WCMG_F64, te, n) + norm2(c, WCMG_F64, to, n);
+  s.iters = kr.iters;
+  s.true_rel_res = std::sqrt(rr) / bn;
+  s.status = kr.status;
+  if (s.status == WCMG_OK && !(s.true_rel_res <= tol * 1.0000001)) s.status = WCMG_ENOCONV;
+  s.t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (stats) *stats = s;
+}
+
+}  // namespace wcmg
