@@ -1,0 +1,281 @@
+#!/usr/bin/env python3
+"""Time-to-solution of the multigrid-preconditioned GCR against plain FP64
+BiCGStab for the Wilson-clover equation, and the fine Dslash roofline.
+
+Workload: 16^3x32 lattice, links exp(0.5 i H) followed by 5 APE sweeps
+(alpha 0.5), csw = 1.0, m0 swept over {-0.15, -0.25, -0.30}, 4^4 blocks,
+Nv = 24, FP32 preconditioner inside an FP64 outer GCR, one Z2 source,
+stopping at a true relative residual of 1e-10.  One step = one MG-GCR solve
+of the source at every mass of the sweep; the setup (null vectors and
+coarse operator) happens before the timed region, as in the paper's
+speedups.  All inputs are synthetic and seeded.
+
+Prints ONE JSON line.  --gpus N with N > 1 is refused: this measures one GPU.
+"""
+import argparse
+import json
+import os
+import resource
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def dslash_bytes_per_site(prec, diag, postinv):
+    """Compulsory HBM bytes per output site of one hop launch (single RHS):
+    neighbour spinor field once, all 8 links touching the site's parity
+    once, the output, the DIAG input and clover blocks when used."""
+    size = {0: 8, 1: 4, 2: 2}[prec]
+    reals = 24 + 144 + 24 + (24 if diag >= 1 else 0) + (72 if diag == 2 else 0) + (72 if postinv else 0)
+    b = reals * size
+    if prec == 2:  # one FP32 scale per spinor site read or written
+        b += 4 * (2 + (1 if diag >= 1 else 0))
+    return b
+
+
+def dslash_flops_per_site(diag, postinv):
+    f = 1320  # 8 directions: projection, 2 SU(3) half-spinor products, reconstruction
+    if postinv:
+        f += 504
+    if diag == 2:
+        f += 504 + 24
+    elif diag == 1:
+        f += 24
+    return f
+
+
+def kernel_table(ctxs, vh, coarse_sites_h, coarse_n):
+    """Per timed kernel id: launches, mean duration, algorithmic bytes per launch."""
+    rows = []
+    for kid in list(range(18)) + [20, 21]:
+        n, ms = 0, 0.0
+        for c in ctxs:
+            cn, cms = c.timer_read(kid)
+            n += cn
+            ms += cms
+        if n == 0:
+            continue
+        if kid < 18:
+            prec, rest = divmod(kid, 6)
+            diag, postinv = divmod(rest, 2)
+            name = "dslash_kernel<%s,%d,%s>" % (["double", "float", "__half"][prec], diag, str(bool(postinv)).lower())
+            bytes_launch = dslash_bytes_per_site(prec, diag, postinv) * vh
+            flops = dslash_flops_per_site(diag, postinv) * vh
+        else:
+            cs = 16 if kid == 20 else 8
+            name = "k_coarse_hop<%s>" % ("double" if kid == 20 else "float")
+            bytes_launch = coarse_sites_h * (8 * coarse_n * coarse_n + 2.5 * coarse_n) * cs
+            flops = coarse_sites_h * 8 * coarse_n * coarse_n * 8
+        avg_ms = ms / n
+        rows.append(dict(id=kid, kernel=name, launches=n, total_ms=round(ms, 3), avg_us=round(avg_ms * 1e3, 3),
+                         bytes_per_launch=int(bytes_launch), GBps=round(bytes_launch / (avg_ms * 1e-3) / 1e9, 1),
+                         TFLOPs=round(flops / (avg_ms * 1e-3) / 1e12, 3)))
+    rows.sort(key=lambda r: -r["total_ms"])
+    return rows
+
+
+def cpu_baseline(dims, U, m0, csw, b, bicg_iters_gpu):
+    """Oracle (FP64 NumPy) BiCGStab on the same D_r, timed for a few iterations
+    on the host and scaled to the iteration count the solve needs."""
+    from oracle.dirac import WilsonClover
+    from oracle.krylov import bicgstab, norm, SolveInfo
+    op = WilsonClover(dims, U, m0, csw)
+    bb = b.reshape(op.shape)
+    br = op.reduced_source(bb)
+    iters = 3
+    r0 = resource.getrusage(resource.RUSAGE_SELF)
+    t0 = time.perf_counter()
+    info = SolveInfo()
+    bicgstab(op.apply_Dr, br, tol=1e-10, target_norm=norm(bb), maxiter=iters, info=info)
+    wall = time.perf_counter() - t0
+    r1 = resource.getrusage(resource.RUSAGE_SELF)
+    cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
+    per_iter = wall / max(info.iters, 1)
+    return {"value": round(per_iter * bicg_iters_gpu, 3), "unit": "s", "cores": max(1, round(cpu / wall)),
+            "kind": "oracle",
+            "sample": "%d iterations of the FP64 NumPy oracle BiCGStab on D_r (16^3x32, m0=%g) in %.1f s, scaled "
+                      "by the %d iterations the same FP64 BiCGStab needs to reach 1e-10; host has %d cores"
+                      % (info.iters, m0, wall, bicg_iters_gpu, os.cpu_count() or 0)}
+
+
+def dslash_headline(w, torch, inputs):
+    """Fine D_r applies on the 24^3x64 lattice (working set above the 256 MB
+    Infinity Cache): per-launch duration and compulsory-byte bandwidth."""
+    dims = (24, 24, 24, 64)
+    U = inputs.random_links(dims, 0.5, 1003)
+    ctx = w.Context(dims)
+    ctx.set_gauge(torch.from_numpy(U).cuda())
+    ctx.set_clover(-0.25, 1.0)
+    g = torch.Generator(device="cuda").manual_seed(1)
+    v = torch.randn((1,) + tuple(reversed(dims)) + (4, 3), dtype=torch.complex128, device="cuda", generator=g)
+    out = {}
+    vh = inputs.volume(dims) // 2
+    for prec, name in ((w.F64, "f64"), (w.F32, "f32"), (w.F16, "f16")):
+        for _ in range(3):
+            ctx.apply_D(v, w.OP_SCHUR, prec)
+        torch.cuda.synchronize()
+        ctx.timer_enable(True)
+        for _ in range(20):
+            ctx.apply_D(v, w.OP_SCHUR, prec)
+        rows = kernel_table([ctx], vh, 0, 0)
+        ctx.timer_enable(False)
+        tot_b = sum(r["bytes_per_launch"] * r["launches"] for r in rows)
+        tot_ms = sum(r["total_ms"] for r in rows)
+        out[name] = {"GBps": round(tot_b / (tot_ms * 1e-3) / 1e9, 1),
+                     "frac_of_8TBps": round(tot_b / (tot_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 3),
+                     "kernels": [{k: r[k] for k in ("kernel", "avg_us", "GBps")} for r in rows]}
+    ctx.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-headline", action="store_true", help="skip the 24^3x64 Dslash measurement")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures a single GPU: --gpus %d is not supported (the path shards by right-hand side or "
+              "by 4D domain decomposition, which is not built here)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import inputs
+    import paper_1011_2775_amd as w
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    cfg = inputs.config("c2_16x16x16x32")
+    dims = cfg["dims"]
+    t = time.perf_counter()
+    U = inputs.gauge_field(dims, cfg["eps"], cfg["gauge_seed"], ape_sweeps=cfg["ape"])
+    b = inputs.z2_source(dims, cfg["source_seeds"][0])
+    t_inputs = time.perf_counter() - t
+    Ut = torch.from_numpy(U).cuda()
+    bt = torch.from_numpy(b[None]).cuda()
+    masses = cfg["m0"]
+    ctxs, setup = [], {}
+    for m0 in masses:
+        ctx = w.Context(dims)
+        ctx.set_gauge(Ut)
+        ctx.set_clover(m0, cfg["csw"])
+        ctx.set_mg_params(w.default_params(block=cfg["blocks"], nvec=cfg["nvec"], seed=cfg["setup_seed"]))
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ctx.build_null_vectors()
+        ctx.build_coarse()
+        torch.cuda.synchronize()
+        setup[m0] = time.perf_counter() - t
+        ctxs.append(ctx)
+    print("setup done %s" % {k: round(v, 2) for k, v in setup.items()}, file=sys.stderr, flush=True)
+
+    # plain FP64 BiCGStab on the same D_r, same stopping rule
+    bicg = {}
+    for m0, ctx in zip(masses, ctxs):
+        ctx.solve(bt, w.BICGSTAB, cfg["tol"], raise_on_error=False)  # warm
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        xb, st = ctx.solve(bt, w.BICGSTAB, cfg["tol"], raise_on_error=False)
+        torch.cuda.synchronize()
+        bicg[m0] = dict(s=time.perf_counter() - t, iters=st[0]["iters"], res=st[0]["true_rel_res"],
+                        status=st[0]["status"], x=xb)
+    print("bicgstab done", file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        for ctx in ctxs:
+            ctx.solve(bt, w.MG_GCR, cfg["tol"])
+    torch.cuda.synchronize()
+
+    for ctx in ctxs:
+        ctx.timer_enable(True)
+    per = {m0: [] for m0 in masses}
+    last = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for m0, ctx in zip(masses, ctxs):
+            ts = time.perf_counter()
+            x, st = ctx.solve(bt, w.MG_GCR, cfg["tol"])
+            per[m0].append(time.perf_counter() - ts)
+            last[m0] = (x, st[0])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    print("timed region done", file=sys.stderr, flush=True)
+
+    vh = inputs.volume(dims) // 2
+    bl = cfg["blocks"][0]
+    vc = inputs.volume(dims) // int(np.prod(bl))
+    rows = kernel_table(ctxs, vh, vc // 2, 2 * cfg["nvec"][0])
+    for ctx in ctxs:
+        ctx.timer_enable(False)
+    dom = rows[0]
+    roofline = {"bound": "hbm", "kernel": dom["kernel"], "achieved": dom["GBps"], "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(dom["GBps"] / PEAK_HBM_GBS, 4), "traffic": None,
+                "bytes_per_launch": dom["bytes_per_launch"], "avg_launch_us": dom["avg_us"],
+                "note": "working set fits the 256 MB Infinity Cache at 16^3x32; see dslash_24x24x24x64"}
+
+    mass_rows = {}
+    for m0 in masses:
+        x, st = last[m0]
+        mg_s = float(np.median(per[m0]))
+        xb = bicg[m0]["x"]
+        diff = float(torch.linalg.vector_norm(x - xb) / torch.linalg.vector_norm(xb))
+        mass_rows[str(m0)] = dict(mg_s=round(mg_s, 4), mg_outer_iters=st["iters"],
+                                  mg_inner_iters_mean=round(st["inner_iters"][0], 2),
+                                  mg_true_rel_res=st["true_rel_res"], bicgstab_s=round(bicg[m0]["s"], 4),
+                                  bicgstab_iters=bicg[m0]["iters"], bicgstab_true_rel_res=bicg[m0]["res"],
+                                  bicgstab_status=bicg[m0]["status"],
+                                  speedup=round(bicg[m0]["s"] / mg_s, 2), setup_s=round(setup[m0], 3),
+                                  setup_in_bicgstab_solves=round(setup[m0] / bicg[m0]["s"], 2),
+                                  rel_diff_mg_vs_bicgstab=diff)
+
+    headline = None if args.no_headline else dslash_headline(w, torch, inputs)
+    cpu = None
+    if not args.no_cpu:
+        mref = -0.25
+        cpu = cpu_baseline(dims, U, mref, cfg["csw"], b, bicg[mref]["iters"])
+
+    steps_solves = args.steps * len(masses)
+    value = elapsed / steps_solves
+    line = {
+        "metric": "time-to-solution @ rel.res 1e-10 (MG vs plain BiCGStab); Dslash GB/s",
+        "value": round(value, 5),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": "wilson-clover 16^3x32 MG-GCR vs BiCGStab, m0 sweep", "lattice": "16x16x16x32",
+                   "gauge": "exp(0.5iH) + 5 APE sweeps (alpha 0.5)", "csw": cfg["csw"], "m0": masses,
+                   "blocks": list(bl), "nvec": cfg["nvec"][0], "precision": "FP32 preconditioner, FP64 outer GCR",
+                   "rhs": "1 Z2 source", "tol": cfg["tol"], "step": "one MG-GCR solve at each mass",
+                   "parallelism": "1 GPU"},
+        "per_mass": mass_rows,
+        "speedup_vs_bicgstab_mean": round(float(np.mean([r["speedup"] for r in mass_rows.values()])), 2),
+        "roofline": roofline,
+        "kernels": rows[:8],
+        "dslash_24x24x24x64": headline,
+        "cpu_baseline": cpu,
+        "inputs_s": round(t_inputs, 2),
+    }
+    for ctx in ctxs:
+        ctx.close()
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -187,10 +187,12 @@ int wcmg_apply_coarse(void* ctx, int lat, int level, int op, int prec, void* out
 int wcmg_solve(void* ctx, int lat, int solver, void* x, const void* b, int nrhs, double tol, wcmg_stats* stats);
 
 /* Per-kernel timing with HIP events on the context's stream.
- * wcmg_timer_enable(ctx, 1) starts recording each launch of the fine
- * Dslash kernels; wcmg_timer_read returns the launch count and the summed
- * duration in milliseconds for kernel class `which` (0 = fine Dslash hop,
- * 1 = coarse stencil) since the last reset, synchronising the stream. */
+ * wcmg_timer_enable(ctx, 1) resets the counters and starts recording every
+ * launch of the timed kernels; wcmg_timer_read returns the launch count and
+ * the summed duration in milliseconds for kernel id `which` (synchronising
+ * the stream).  Ids: fine hop kernel  prec*6 + diag*2 + clover_inverse
+ * (prec 0 F64, 1 F32, 2 F16; diag 0 none, 1 x, 2 A x; see the DIAG/POST
+ * modes of the Dslash), coarse red-black hop 20 (F64) and 21 (F32). */
 int wcmg_timer_enable(void* ctx, int on);
 int wcmg_timer_read(void* ctx, int which, long* count, double* total_ms);
 

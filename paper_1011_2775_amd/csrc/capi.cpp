@@ -609,7 +609,7 @@ int wcmg_timer_enable(void* ctx, int on) {
 
 int wcmg_timer_read(void* ctx, int which, long* count, double* total_ms) {
   CHECK(ctx, WCMG_EINVAL, "null context");
-  CHECK(which == 0 || which == 1, WCMG_EINVAL, "bad timer class");
+  CHECK(which >= 0 && which < KernelTimer::kIds, WCMG_EINVAL, "bad timer id");
   CHECK(count && total_ms, WCMG_EINVAL, "null output");
   return guarded([&] {
     Ctx* c = as_ctx(ctx);

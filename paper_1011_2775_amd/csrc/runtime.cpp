@@ -105,8 +105,8 @@ void KernelTimer::drain() {
 }
 void KernelTimer::reset() {
   drain();
-  count[0] = count[1] = 0;
-  ms[0] = ms[1] = 0.0;
+  for (int k = 0; k < kIds; ++k) count[k] = 0;
+  for (int k = 0; k < kIds; ++k) ms[k] = 0.0;
 }
 KernelTimer::~KernelTimer() {
   for (auto& pe : pending) {
@@ -165,10 +165,12 @@ void FineOp::hop(void* out, const void* in, const void* x, int parity, int diag,
   a.parity = parity;
   a.nblocks = 0;
   a.coeff = coeff;
+  // timer id: precision x DIAG mode x clover-inverse post-multiply
+  const int id = prec * 6 + diag * 2 + (postinv ? 1 : 0);
   hipEvent_t e = nullptr;
-  if (ctx->timer.on) ctx->timer.begin(0, &e);
+  if (ctx->timer.on) ctx->timer.begin(id, &e);
   launch_dslash(prec, diag, postinv, a, st);
-  if (e) ctx->timer.end(0, e);
+  if (e) ctx->timer.end(id, e);
 }
 
 void FineOp::clover(void* out, const void* in, int parity, int kind) {
@@ -236,8 +238,15 @@ void CoarseOp::Dp(void* out, const void* in) {
 
 void CoarseOp::Dr(void* out, const void* y) {
   w->ensure(nall() * csize());
+  const int id = 20 + pi();
+  hipEvent_t e = nullptr;
+  if (timer && timer->on) timer->begin(id, &e);
   launch_coarse_hop(prec, w->t1.p, y, nullptr, C->Yt[pi()].p, nullptr, 0, 1.0, 1, C->cg, C->nbr.as<int>(), st);
+  if (e) timer->end(id, e);
+  e = nullptr;
+  if (timer && timer->on) timer->begin(id, &e);
   launch_coarse_hop(prec, out, w->t1.p, y, C->Yt[pi()].p, nullptr, 1, -1.0, 0, C->cg, C->nbr.as<int>(), st);
+  if (e) timer->end(id, e);
 }
 
 void CoarseOp::reduced_source(void* br, const void* b) {

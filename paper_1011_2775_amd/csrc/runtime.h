@@ -17,8 +17,9 @@ struct KernelTimer {
   hipStream_t st = nullptr;
   std::vector<hipEvent_t> pool;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;  // (class, (start, stop))
-  long count[2] = {0, 0};
-  double ms[2] = {0.0, 0.0};
+  static constexpr int kIds = 64;
+  long count[kIds] = {};
+  double ms[kIds] = {};
   hipEvent_t get();
   void begin(int cls, hipEvent_t* a);
   void end(int cls, hipEvent_t a);
@@ -101,6 +102,7 @@ struct CoarseOp {
   int prec;     // F64 or F32
   CoarseWork* w;
   hipStream_t st;
+  KernelTimer* timer = nullptr;  // times the red-black hop launches (ids 20 F64, 21 F32)
   int pi() const { return prec == WCMG_F64 ? 0 : 1; }
   size_t csize() const { return prec == WCMG_F64 ? 16 : 8; }
   size_t nall() const { return (size_t)C->cg.V * C->cg.n; }

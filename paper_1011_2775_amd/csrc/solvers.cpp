@@ -243,7 +243,7 @@ struct MGSolver {
 
   void coarse_solve(void* out, void* in) {
     CoarseLevel& C = *L.levels[0];
-    CoarseOp cop{&C, cp, &c.cw[cp == WCMG_F64 ? 0 : 1], c.st};
+    CoarseOp cop{&C, cp, &c.cw[cp == WCMG_F64 ? 0 : 1], c.st, &c.timer};
     const wcmg_mg_params& p = L.params;
     KrylovResult kr;
     if (C.cg.split) {
