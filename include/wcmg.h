@@ -186,6 +186,14 @@ int wcmg_apply_coarse(void* ctx, int lat, int level, int op, int prec, void* out
  * worst status over the right-hand sides. */
 int wcmg_solve(void* ctx, int lat, int solver, void* x, const void* b, int nrhs, double tol, wcmg_stats* stats);
 
+/* The global sum behind every inner product of the Krylov solvers (the
+ * GCR orthogonalisation of the adaptive multigrid paragraph):
+ * out[0] + i out[1] = sum_k conj(x_k) y_k over n complex elements of
+ * device arrays x, y (prec F64: complex128, F32: complex64), accumulated in
+ * FP64 with the same deterministic two-pass reduction the solvers use.
+ * out is a host array of 2 doubles.  Synchronises. */
+int wcmg_dot(void* ctx, int prec, const void* x, const void* y, long n, double* out);
+
 /* Per-kernel timing with HIP events on the context's stream.
  * wcmg_timer_enable(ctx, 1) resets the counters and starts recording every
  * launch of the timed kernels; wcmg_timer_read returns the launch count and

@@ -177,6 +177,15 @@ class Context:
             check(rc)
         return x, [s.as_dict() for s in st]
 
+    # -- global sums -------------------------------------------------------------
+    def dot(self, x, y):
+        """sum conj(x) y of two device tensors (complex128 or complex64), in FP64."""
+        prec = F64 if x.dtype == torch.complex128 else F32
+        out = (ctypes.c_double * 2)()
+        check(_lib.LIB.wcmg_dot(self.h, prec, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                x.numel(), out))
+        return complex(out[0], out[1])
+
     # -- timing --------------------------------------------------------------------
     def timer_enable(self, on=True):
         check(_lib.LIB.wcmg_timer_enable(self.h, int(bool(on))))

@@ -78,6 +78,7 @@ SIGNATURES = {
     "wcmg_prolong": [_vp, _i, _i, _i, _vp, _vp, _i],
     "wcmg_apply_coarse": [_vp, _i, _i, _i, _i, _vp, _vp, _i],
     "wcmg_solve": [_vp, _i, _i, _vp, _vp, _i, _d, ctypes.POINTER(Stats)],
+    "wcmg_dot": [_vp, _i, _vp, _vp, ctypes.c_long, ctypes.POINTER(_d)],
     "wcmg_timer_enable": [_vp, _i],
     "wcmg_timer_read": [_vp, _i, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(_d)],
 }
@@ -96,7 +97,21 @@ def load():
     return lib
 
 
-LIB = load()
+_LIB = None
+
+
+def get():
+    """The loaded library (loaded on first use, so the package imports without it)."""
+    global _LIB
+    if _LIB is None:
+        _LIB = load()
+    return _LIB
+
+
+def __getattr__(name):
+    if name == "LIB":
+        return get()
+    raise AttributeError(name)
 
 
 class WcmgError(RuntimeError):
@@ -107,5 +122,5 @@ class WcmgError(RuntimeError):
 
 def check(rc):
     if rc != OK:
-        raise WcmgError(rc, LIB.wcmg_last_error().decode())
+        raise WcmgError(rc, get().wcmg_last_error().decode())
     return rc

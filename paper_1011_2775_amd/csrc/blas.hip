@@ -2,9 +2,10 @@
 //
 // Vectors are flat arrays of complex numbers in double or float storage;
 // every reduction accumulates in double, first per wavefront with lane
-// shuffles, then across the 4 wavefronts of a block in LDS, then in a
-// single-block second pass over the per-block partials.  The grid size is
-// fixed, so results are bitwise reproducible run to run.
+// shuffles, then across the 4 wavefronts of a block in LDS; a one-block
+// second pass sums the per-block partials in block order and writes the
+// result to device memory.  The grid depends only on the vector length, so
+// results are bitwise reproducible run to run.
 #include "kernels.h"
 
 namespace wcmg {
@@ -39,9 +40,9 @@ __device__ __forceinline__ void st(void* p, size_t i, cpx<double> c) {
   reinterpret_cast<V*>(p)[i] = v;
 }
 
-// reduce NR doubles over the block, write partial[blockIdx.x*NR + k]
+// Reduce NR doubles over the block into partial[blockIdx.x*NR + k].
 template <int NR>
-__device__ __forceinline__ void block_reduce(double (&v)[NR], double* partial) {
+__device__ __forceinline__ void block_reduce(double (&v)[NR], const RedOut& o) {
   __shared__ double sh[NR][kThreads / 64];
 #pragma unroll
   for (int k = 0; k < NR; ++k) {
@@ -58,34 +59,28 @@ __device__ __forceinline__ void block_reduce(double (&v)[NR], double* partial) {
     double s = 0.0;
 #pragma unroll
     for (int w = 0; w < kThreads / 64; ++w) s += sh[threadIdx.x][w];
-    partial[(size_t)blockIdx.x * NR + threadIdx.x] = s;
+    o.partial[(size_t)blockIdx.x * NR + threadIdx.x] = s;
   }
 }
 
-// one block: res[k] = sum_b partial[b*nr + k], fixed order
-__global__ void __launch_bounds__(kThreads) finalize_kernel(const double* partial, int nblocks, int nr,
-                                                            double* res) {
-  __shared__ double sh[kThreads];
-  for (int k = 0; k < nr; ++k) {
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += kThreads) s += partial[(size_t)b * nr + k];
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = kThreads / 2; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) res[k] = sh[0];
-    __syncthreads();
-  }
+// Second pass (one block, one lane per output): res[k] = sum over blocks of
+// partial[b*nr + k] in block order.
+__global__ void __launch_bounds__(64) k_finalize(const RedOut o, int nr, int stride, int nblocks) {
+  const int k = threadIdx.x;
+  if (k >= nr) return;
+  double s = 0.0;
+  for (int b = 0; b < nblocks; ++b) s += o.partial[(size_t)b * stride + k];
+  o.res[k] = s;
+  if (o.hres) o.hres[k] = s;
 }
 
-void finalize(const double* partial, int nr, double* res, hipStream_t st) {
-  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kThreads), 0, st, partial, kRedBlocks, nr, res);
-  HIPCHK(hipGetLastError());
+// enough blocks that every thread handles about 8 elements, at most kRedBlocks
+inline dim3 red_grid(size_t n) {
+  size_t b = (n + 8 * kThreads - 1) / (8 * kThreads);
+  if (b < 1) b = 1;
+  if (b > (size_t)kRedBlocks) b = kRedBlocks;
+  return dim3((unsigned)b);
 }
-
-inline dim3 red_grid() { return dim3(kRedBlocks); }
 inline dim3 ew_grid(size_t n) {
   size_t b = (n + kThreads - 1) / kThreads;
   if (b > 65536) b = 65536;
@@ -110,26 +105,26 @@ __global__ void k_axpby(double ar, double ai, const void* x, double br, double b
   GRID_STRIDE(i, n) st<T>(y, i, a * ld<T>(x, i) + b * ld<T>(y, i));
 }
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_norm2(const void* x, size_t n, double* partial) {
+__global__ void __launch_bounds__(kThreads) k_norm2(const void* x, size_t n, const RedOut o) {
   double v[1] = {0.0};
   GRID_STRIDE(i, n) {
     cpx<double> a = ld<T>(x, i);
     v[0] += a.r * a.r + a.i * a.i;
   }
-  block_reduce<1>(v, partial);
+  block_reduce<1>(v, o);
 }
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_cdot(const void* x, const void* y, size_t n, double* partial) {
+__global__ void __launch_bounds__(kThreads) k_cdot(const void* x, const void* y, size_t n, const RedOut o) {
   double v[2] = {0.0, 0.0};
   GRID_STRIDE(i, n) {
     cpx<double> a = ld<T>(x, i), b = ld<T>(y, i);
     v[0] += a.r * b.r + a.i * b.i;
     v[1] += a.r * b.i - a.i * b.r;
   }
-  block_reduce<2>(v, partial);
+  block_reduce<2>(v, o);
 }
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_cdot_norm(const void* x, const void* y, size_t n, double* partial) {
+__global__ void __launch_bounds__(kThreads) k_cdot_norm(const void* x, const void* y, size_t n, const RedOut o) {
   double v[3] = {0.0, 0.0, 0.0};
   GRID_STRIDE(i, n) {
     cpx<double> a = ld<T>(x, i), b = ld<T>(y, i);
@@ -137,7 +132,7 @@ __global__ void __launch_bounds__(kThreads) k_cdot_norm(const void* x, const voi
     v[1] += a.r * b.i - a.i * b.r;
     v[2] += a.r * a.r + a.i * a.i;
   }
-  block_reduce<3>(v, partial);
+  block_reduce<3>(v, o);
 }
 
 struct MultiArgs {
@@ -148,7 +143,7 @@ struct MultiArgs {
 
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_multi_cdot(MultiArgs m, int k, const void* y, size_t n,
-                                                         double* partial) {
+                                                         const RedOut o) {
   double v[2 * kMaxK];
 #pragma unroll
   for (int j = 0; j < 2 * kMaxK; ++j) v[j] = 0.0;
@@ -163,7 +158,7 @@ __global__ void __launch_bounds__(kThreads) k_multi_cdot(MultiArgs m, int k, con
       }
     }
   }
-  block_reduce<2 * kMaxK>(v, partial);
+  block_reduce<2 * kMaxK>(v, o);
 }
 
 template <typename T>
@@ -178,35 +173,8 @@ __global__ void k_multi_axpy(MultiArgs m, int k, void* y, size_t n) {
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_gcr_orth(MultiArgs m, int k, void* y, void* z, const void* r,
-                                                       size_t n, int do_red, double* partial) {
-  double v[3] = {0.0, 0.0, 0.0};
-  GRID_STRIDE(i, n) {
-    cpx<double> a = ld<T>(y, i), b = ld<T>(z, i);
-#pragma unroll
-    for (int j = 0; j < kMaxK; ++j) {
-      if (j < k) {
-        cpx<double> c = mk(m.c[2 * j], m.c[2 * j + 1]);
-        a = a - c * ld<T>(m.v[j], i);
-        b = b - c * ld<T>(m.w[j], i);
-      }
-    }
-    st<T>(y, i, a);
-    st<T>(z, i, b);
-    if (do_red) {
-      // reduce the rounded (stored) values so the norms match the vectors
-      cpx<double> as = ld<T>(y, i), rr = ld<T>(r, i);
-      v[0] += as.r * as.r + as.i * as.i;
-      v[1] += as.r * rr.r + as.i * rr.i;
-      v[2] += as.r * rr.i - as.i * rr.r;
-    }
-  }
-  if (do_red) block_reduce<3>(v, partial);
-}
-
-template <typename T>
 __global__ void __launch_bounds__(kThreads) k_axpy_norm(double ar, double ai, const void* x, void* y, size_t n,
-                                                        double* partial) {
+                                                        const RedOut o) {
   double v[1] = {0.0};
   cpx<double> a = mk(ar, ai);
   GRID_STRIDE(i, n) {
@@ -215,13 +183,13 @@ __global__ void __launch_bounds__(kThreads) k_axpy_norm(double ar, double ai, co
     cpx<double> bs = ld<T>(y, i);
     v[0] += bs.r * bs.r + bs.i * bs.i;
   }
-  block_reduce<1>(v, partial);
+  block_reduce<1>(v, o);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_bicg_update(double ar, double ai, double wr, double wi, const void* p,
                                                           const void* s, const void* t, void* x, void* r,
-                                                          const void* rhat, size_t n, double* partial) {
+                                                          const void* rhat, size_t n, const RedOut o) {
   double v[3] = {0.0, 0.0, 0.0};
   cpx<double> a = mk(ar, ai), w = mk(wr, wi);
   GRID_STRIDE(i, n) {
@@ -233,7 +201,7 @@ __global__ void __launch_bounds__(kThreads) k_bicg_update(double ar, double ai, 
     v[1] += h.r * rv.r + h.i * rv.i;
     v[2] += h.r * rv.i - h.i * rv.r;
   }
-  block_reduce<3>(v, partial);
+  block_reduce<3>(v, o);
 }
 
 template <typename T>
@@ -241,6 +209,85 @@ __global__ void k_bicg_p(double br, double bi, double wr, double wi, const void*
                          size_t n) {
   cpx<double> b = mk(br, bi), w = mk(wr, wi);
   GRID_STRIDE(i, n) st<T>(p, i, ld<T>(r, i) + b * (ld<T>(p, i) - w * ld<T>(v, i)));
+}
+
+// ---- device-resident coefficients (no host round trip between kernels) ----
+// GCR basis slot j keeps qa[4j..4j+3] = { ||q_j||^2, re <q_j,r>, im <q_j,r>, ||r||^2 after step j };
+// beta[2j..2j+1] = <q_j, q_new> from the multi-dot.
+__device__ __forceinline__ cpx<double> gcr_alpha(const double* qa) {
+  double d = qa[0];
+  return d > 0.0 ? mk(qa[1] / d, qa[2] / d) : mk(0.0, 0.0);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_gcr_orth_dev(MultiArgs m, int k, void* y, void* z, const void* r,
+                                                           size_t n, const double* beta, const double* qa,
+                                                           int do_red, const RedOut o) {
+  double v[3] = {0.0, 0.0, 0.0};
+  cpx<double> c[kMaxK];
+#pragma unroll
+  for (int j = 0; j < kMaxK; ++j) {
+    double d = j < k ? qa[4 * j] : 0.0;
+    c[j] = (j < k && d > 0.0) ? mk(beta[2 * j] / d, beta[2 * j + 1] / d) : mk(0.0, 0.0);
+  }
+  GRID_STRIDE(i, n) {
+    cpx<double> a = ld<T>(y, i), b = ld<T>(z, i);
+#pragma unroll
+    for (int j = 0; j < kMaxK; ++j) {
+      if (j < k) {
+        a = a - c[j] * ld<T>(m.v[j], i);
+        b = b - c[j] * ld<T>(m.w[j], i);
+      }
+    }
+    st<T>(y, i, a);
+    st<T>(z, i, b);
+    if (do_red) {
+      cpx<double> as = ld<T>(y, i), rr = ld<T>(r, i);
+      v[0] += as.r * as.r + as.i * as.i;
+      v[1] += as.r * rr.r + as.i * rr.i;
+      v[2] += as.r * rr.i - as.i * rr.r;
+    }
+  }
+  if (do_red) block_reduce<3>(v, o);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_gcr_update_r_dev(const void* q, void* r, size_t n, const double* qa,
+                                                               const RedOut o) {
+  double v[1] = {0.0};
+  cpx<double> a = gcr_alpha(qa);
+  GRID_STRIDE(i, n) {
+    cpx<double> b = ld<T>(r, i) - a * ld<T>(q, i);
+    st<T>(r, i, b);
+    cpx<double> bs = ld<T>(r, i);
+    v[0] += bs.r * bs.r + bs.i * bs.i;
+  }
+  block_reduce<1>(v, o);
+}
+
+template <typename T>
+__global__ void k_gcr_update_x_dev(MultiArgs m, int k, void* x, size_t n, const double* qa) {
+  cpx<double> c[kMaxK];
+#pragma unroll
+  for (int j = 0; j < kMaxK; ++j) c[j] = j < k ? gcr_alpha(qa + 4 * j) : mk(0.0, 0.0);
+  GRID_STRIDE(i, n) {
+    cpx<double> acc = ld<T>(x, i);
+#pragma unroll
+    for (int j = 0; j < kMaxK; ++j)
+      if (j < k) acc = acc + c[j] * ld<T>(m.v[j], i);
+    st<T>(x, i, acc);
+  }
+}
+
+// MR step with alpha = <Ar, r> / ||Ar||^2 read from coef = [re, im, ||Ar||^2]
+template <typename T>
+__global__ void k_mr_update_dev(const double* coef, void* x, void* r, const void* Ar, size_t n) {
+  const double d = coef[2];
+  cpx<double> a = d > 0.0 ? mk(coef[0] / d, coef[1] / d) : mk(0.0, 0.0);
+  GRID_STRIDE(i, n) {
+    st<T>(x, i, ld<T>(x, i) + a * ld<T>(r, i));
+    st<T>(r, i, ld<T>(r, i) - a * ld<T>(Ar, i));
+  }
 }
 
 template <typename T>
@@ -263,6 +310,12 @@ __global__ void k_mr_update(double ar, double ai, void* x, void* r, const void* 
     HIPCHK(hipGetLastError());                                                                  \
   } while (0)
 
+// nr results, partials laid out with `stride` doubles per block (the kernel's NR)
+void finalize(const RedOut& o, int nr, size_t n, hipStream_t st, int stride = 0) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, o, nr, stride ? stride : nr, (int)red_grid(n).x);
+  HIPCHK(hipGetLastError());
+}
+
 void blas_zero(int prec, void* x, size_t n, hipStream_t st) { DISPATCH(prec, k_zero, ew_grid(n), x, n); }
 void blas_copy(int prec, void* y, const void* x, size_t n, hipStream_t st) {
   DISPATCH(prec, k_copy, ew_grid(n), y, x, n);
@@ -271,28 +324,27 @@ void blas_axpby(int prec, double ar, double ai, const void* x, double br, double
                 hipStream_t st) {
   DISPATCH(prec, k_axpby, ew_grid(n), ar, ai, x, br, bi, y, n);
 }
-void blas_norm2(int prec, const void* x, size_t n, double* res, double* partial, hipStream_t st) {
-  DISPATCH(prec, k_norm2, red_grid(), x, n, partial);
-  finalize(partial, 1, res, st);
+void blas_norm2(int prec, const void* x, size_t n, const RedOut& o, hipStream_t st) {
+  DISPATCH(prec, k_norm2, red_grid(n), x, n, o);
+  finalize(o, 1, n, st);
 }
-void blas_cdot(int prec, const void* x, const void* y, size_t n, double* res, double* partial, hipStream_t st) {
-  DISPATCH(prec, k_cdot, red_grid(), x, y, n, partial);
-  finalize(partial, 2, res, st);
+void blas_cdot(int prec, const void* x, const void* y, size_t n, const RedOut& o, hipStream_t st) {
+  DISPATCH(prec, k_cdot, red_grid(n), x, y, n, o);
+  finalize(o, 2, n, st);
 }
-void blas_cdot_norm(int prec, const void* x, const void* y, size_t n, double* res, double* partial,
-                    hipStream_t st) {
-  DISPATCH(prec, k_cdot_norm, red_grid(), x, y, n, partial);
-  finalize(partial, 3, res, st);
+void blas_cdot_norm(int prec, const void* x, const void* y, size_t n, const RedOut& o, hipStream_t st) {
+  DISPATCH(prec, k_cdot_norm, red_grid(n), x, y, n, o);
+  finalize(o, 3, n, st);
 }
-void blas_multi_cdot(int prec, const void* const* v, int k, const void* y, size_t n, double* res,
-                     double* partial, hipStream_t st) {
+void blas_multi_cdot(int prec, const void* const* v, int k, const void* y, size_t n, const RedOut& o,
+                     hipStream_t st) {
   for (int j0 = 0; j0 < k; j0 += kMaxK) {
     int kk = std::min(kMaxK, k - j0);
     MultiArgs m{};
     for (int j = 0; j < kk; ++j) m.v[j] = v[j0 + j];
-    DISPATCH(prec, k_multi_cdot, red_grid(), m, kk, y, n, partial);
-    // finalize all 2*kMaxK slots; only the first 2*kk are meaningful
-    finalize(partial, 2 * kMaxK, res + 2 * j0, st);
+    // all 2*kMaxK slots are written; only the first 2*kk are meaningful
+    DISPATCH(prec, k_multi_cdot, red_grid(n), m, kk, y, n, o.at(2 * j0));
+    finalize(o.at(2 * j0), 2 * kk, n, st, 2 * kMaxK);
   }
 }
 void blas_multi_axpy(int prec, const double* c, const void* const* v, int k, void* y, size_t n, hipStream_t st) {
@@ -307,12 +359,30 @@ void blas_multi_axpy(int prec, const double* c, const void* const* v, int k, voi
     DISPATCH(prec, k_multi_axpy, ew_grid(n), m, kk, y, n);
   }
 }
-void blas_gcr_orth(int prec, const double* c, const void* const* q, const void* const* w, int k, void* y,
-                   void* z, const void* r, size_t n, double* res, double* partial, hipStream_t st) {
+void blas_axpy_norm(int prec, double ar, double ai, const void* x, void* y, size_t n, const RedOut& o,
+                    hipStream_t st) {
+  DISPATCH(prec, k_axpy_norm, red_grid(n), ar, ai, x, y, n, o);
+  finalize(o, 1, n, st);
+}
+void blas_bicg_update(int prec, double ar, double ai, double wr, double wi, const void* p, const void* s,
+                      const void* t, void* x, void* r, const void* rhat, size_t n, const RedOut& o, hipStream_t st) {
+  DISPATCH(prec, k_bicg_update, red_grid(n), ar, ai, wr, wi, p, s, t, x, r, rhat, n, o);
+  finalize(o, 3, n, st);
+}
+void blas_bicg_p(int prec, double br, double bi, double wr, double wi, const void* r, const void* v, void* p,
+                 size_t n, hipStream_t st) {
+  DISPATCH(prec, k_bicg_p, ew_grid(n), br, bi, wr, wi, r, v, p, n);
+}
+void blas_mr_update(int prec, double ar, double ai, void* x, void* r, const void* Ar, size_t n, hipStream_t st) {
+  DISPATCH(prec, k_mr_update, ew_grid(n), ar, ai, x, r, Ar, n);
+}
+
+void blas_gcr_orth_dev(int prec, const void* const* q, const void* const* w, int k, void* y, void* z, const void* r,
+                       size_t n, const double* beta, const double* qa, const RedOut& o, hipStream_t st) {
   if (k == 0) {
     MultiArgs m{};
-    DISPATCH(prec, k_gcr_orth, red_grid(), m, 0, y, z, r, n, 1, partial);
-    finalize(partial, 3, res, st);
+    DISPATCH(prec, k_gcr_orth_dev, red_grid(n), m, 0, y, z, r, n, beta, qa, 1, o);
+    finalize(o, 3, n, st);
     return;
   }
   for (int j0 = 0; j0 < k; j0 += kMaxK) {
@@ -321,31 +391,31 @@ void blas_gcr_orth(int prec, const double* c, const void* const* q, const void* 
     for (int j = 0; j < kk; ++j) {
       m.v[j] = q[j0 + j];
       m.w[j] = w[j0 + j];
-      m.c[2 * j] = c[2 * (j0 + j)];
-      m.c[2 * j + 1] = c[2 * (j0 + j) + 1];
     }
     int last = (j0 + kk == k);
-    DISPATCH(prec, k_gcr_orth, red_grid(), m, kk, y, z, r, n, last, partial);
-    if (last) finalize(partial, 3, res, st);
+    DISPATCH(prec, k_gcr_orth_dev, red_grid(n), m, kk, y, z, r, n, beta + 2 * j0, qa + 4 * j0, last, o);
+    if (last) finalize(o, 3, n, st);
   }
 }
-void blas_axpy_norm(int prec, double ar, double ai, const void* x, void* y, size_t n, double* res,
-                    double* partial, hipStream_t st) {
-  DISPATCH(prec, k_axpy_norm, red_grid(), ar, ai, x, y, n, partial);
-  finalize(partial, 1, res, st);
+
+void blas_gcr_update_r_dev(int prec, const void* q, void* r, size_t n, const double* qa_k, const RedOut& o,
+                           hipStream_t st) {
+  DISPATCH(prec, k_gcr_update_r_dev, red_grid(n), q, r, n, qa_k, o);
+  finalize(o, 1, n, st);
 }
-void blas_bicg_update(int prec, double ar, double ai, double wr, double wi, const void* p, const void* s,
-                      const void* t, void* x, void* r, const void* rhat, size_t n, double* res, double* partial,
-                      hipStream_t st) {
-  DISPATCH(prec, k_bicg_update, red_grid(), ar, ai, wr, wi, p, s, t, x, r, rhat, n, partial);
-  finalize(partial, 3, res, st);
+
+void blas_gcr_update_x_dev(int prec, const void* const* z, int k, void* x, size_t n, const double* qa,
+                           hipStream_t st) {
+  for (int j0 = 0; j0 < k; j0 += kMaxK) {
+    int kk = std::min(kMaxK, k - j0);
+    MultiArgs m{};
+    for (int j = 0; j < kk; ++j) m.v[j] = z[j0 + j];
+    DISPATCH(prec, k_gcr_update_x_dev, ew_grid(n), m, kk, x, n, qa + 4 * j0);
+  }
 }
-void blas_bicg_p(int prec, double br, double bi, double wr, double wi, const void* r, const void* v, void* p,
-                 size_t n, hipStream_t st) {
-  DISPATCH(prec, k_bicg_p, ew_grid(n), br, bi, wr, wi, r, v, p, n);
-}
-void blas_mr_update(int prec, double ar, double ai, void* x, void* r, const void* Ar, size_t n, hipStream_t st) {
-  DISPATCH(prec, k_mr_update, ew_grid(n), ar, ai, x, r, Ar, n);
+
+void blas_mr_update_dev(int prec, const double* coef, void* x, void* r, const void* Ar, size_t n, hipStream_t st) {
+  DISPATCH(prec, k_mr_update_dev, ew_grid(n), coef, x, r, Ar, n);
 }
 
 }  // namespace wcmg

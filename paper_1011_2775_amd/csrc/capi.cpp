@@ -598,6 +598,20 @@ int wcmg_solve(void* ctx, int lat, int solver, void* x, const void* b, int nrhs,
   return WCMG_OK;
 }
 
+int wcmg_dot(void* ctx, int prec, const void* x, const void* y, long n, double* out) {
+  CHECK(ctx, WCMG_EINVAL, "null context");
+  CHECK(x && y && out, WCMG_EINVAL, "null buffer");
+  CHECK(prec == WCMG_F64 || prec == WCMG_F32, WCMG_EINVAL, "precision must be F64 or F32");
+  CHECK(n >= 1, WCMG_EINVAL, "n must be >= 1");
+  return guarded([&] {
+    Ctx* c = as_ctx(ctx);
+    blas_cdot(prec, x, y, (size_t)n, c->red.out(), c->st);
+    const double* h = c->red.fetch(2);
+    out[0] = h[0];
+    out[1] = h[1];
+  });
+}
+
 int wcmg_timer_enable(void* ctx, int on) {
   CHECK(ctx, WCMG_EINVAL, "null context");
   return guarded([&] {

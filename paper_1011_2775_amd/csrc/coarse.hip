@@ -12,24 +12,42 @@
 //   c_e = X_ee^-1 y_e,  c_o = X_oo^-1 (b_o - Ytilde_oe y_e).
 //
 // One workgroup computes one coarse site: the 8 neighbour vectors are
-// gathered into LDS, G = blockDim / n groups of n lanes split the 8n
-// columns, and the partial rows are summed in LDS.
+// gathered into LDS, G column groups of n/2 lanes (two rows per lane) split
+// the 8n columns, and the partial rows are summed in LDS.
 #include "kernels.h"
 
 namespace wcmg {
 
 namespace {
 
+// two consecutive complex entries (rows 2r, 2r+1 of one column)
+__device__ __forceinline__ void load2(const float2* p, cpx<float>& e0, cpx<float>& e1) {
+  float4 t = *reinterpret_cast<const float4*>(p);
+  e0 = mk(t.x, t.y);
+  e1 = mk(t.z, t.w);
+}
+__device__ __forceinline__ void load2(const double2* p, cpx<double>& e0, cpx<double>& e1) {
+  double2 t0 = p[0], t1 = p[1];
+  e0 = mk(t0.x, t0.y);
+  e1 = mk(t1.x, t1.y);
+}
+
+// Thread t owns the row pair (2r, 2r+1), r = t mod n/2, and the column
+// group g = t div n/2; the G groups stride over the 8n hop columns (and the
+// n columns of X for DIAG 2), so each lane keeps several 16-byte loads in
+// flight.  Up to 1024 lanes (16 wavefronts) work on one coarse site.
 template <typename S>
-__global__ void k_coarse_hop(void* out, const void* in, const void* x, const void* M, const void* Xm, int diag,
-                             double coeff, int site0, int n, const int* nbr) {
+__global__ void __launch_bounds__(1024) k_coarse_hop(void* out, const void* in, const void* x, const void* M,
+                                                     const void* Xm, int diag, double coeff, int site0, int n,
+                                                     const int* nbr) {
   using C = typename Compute<S>::T;
   using V2 = typename Vec2<S>::T;
   extern __shared__ char smem[];
-  cpx<C>* vin = reinterpret_cast<cpx<C>*>(smem);   // 9n
-  cpx<C>* part = vin + 9 * n;                        // G*n
+  cpx<C>* vin = reinterpret_cast<cpx<C>*>(smem);  // 9n: 8 neighbour vectors, then x(c)
+  cpx<C>* part = vin + 9 * n;                       // G * n partial rows
   const int c = site0 + blockIdx.x;
-  const int G = blockDim.x / n;
+  const int R2 = n >> 1;
+  const int G = blockDim.x / R2;
   const V2* vi = reinterpret_cast<const V2*>(in);
   const V2* vx = reinterpret_cast<const V2*>(x);
   if (M) {
@@ -46,27 +64,36 @@ __global__ void k_coarse_hop(void* out, const void* in, const void* x, const voi
     }
   }
   __syncthreads();
-  const int g = threadIdx.x / n, i = threadIdx.x - g * n;
-  cpx<C> acc = mk((C)0, (C)0), accd = mk((C)0, (C)0);
+  const int g = threadIdx.x / R2, rp = threadIdx.x - g * R2;
   if (g < G) {
+    cpx<C> a0 = mk((C)0, (C)0), a1 = a0, d0 = a0, d1 = a0;
     if (M) {
-      const V2* m = reinterpret_cast<const V2*>(M) + (size_t)c * 8 * n * n;
+      const V2* m = reinterpret_cast<const V2*>(M) + (size_t)c * 8 * n * n + 2 * rp;
+#pragma unroll 4
       for (int col = g; col < 8 * n; col += G) {
-        V2 e = m[(size_t)col * n + i];
-        cfma(acc, mk((C)e.x, (C)e.y), vin[col]);
+        cpx<C> e0, e1;
+        load2(m + (size_t)col * n, e0, e1);
+        const cpx<C> v = vin[col];
+        cfma(a0, e0, v);
+        cfma(a1, e1, v);
       }
     }
     if (diag == 2) {
-      const V2* m = reinterpret_cast<const V2*>(Xm) + (size_t)c * n * n;
+      const V2* m = reinterpret_cast<const V2*>(Xm) + (size_t)c * n * n + 2 * rp;
       for (int col = g; col < n; col += G) {
-        V2 e = m[(size_t)col * n + i];
-        cfma(accd, mk((C)e.x, (C)e.y), vin[8 * n + col]);
+        cpx<C> e0, e1;
+        load2(m + (size_t)col * n, e0, e1);
+        const cpx<C> v = vin[8 * n + col];
+        cfma(d0, e0, v);
+        cfma(d1, e1, v);
       }
     }
-    part[g * n + i] = (C)coeff * acc + accd;
+    part[g * n + 2 * rp] = (C)coeff * a0 + d0;
+    part[g * n + 2 * rp + 1] = (C)coeff * a1 + d1;
   }
   __syncthreads();
-  if (g == 0) {
+  if ((int)threadIdx.x < n) {
+    const int i = threadIdx.x;
     cpx<C> s = part[i];
     for (int h = 1; h < G; ++h) s = s + part[h * n + i];
     if (diag == 1) {
@@ -203,17 +230,19 @@ void launch_coarse_canon(int prec, void* internal, void* canon, const int* perm,
 void launch_coarse_hop(int prec, void* out, const void* in, const void* x, const void* M, const void* Xmat,
                        int diag, double coeff, int parity, const CoarseGeom& cg, const int* nbr, hipStream_t st) {
   const int n = cg.n;
-  int G = 256 / n;
+  if (n % 2 || n > 256) fail(WCMG_EDIM, "coarse block size must be even and <= 256");
+  const int R2 = n / 2;
+  int G = std::min(1024 / R2, 9 * n);
   if (G < 1) G = 1;
-  int threads = n * G;
-  threads = ((threads + 63) / 64) * 64;
+  const int threads = std::min(1024, ((G * R2 + 63) / 64) * 64);
+  G = threads / R2;  // the kernel derives G the same way
   int site0 = 0, nsites = cg.V;
   if (parity >= 0) {
     site0 = parity * cg.Vh;
     nsites = cg.Vh;
   }
-  size_t cb = (prec == WCMG_F64) ? 16 : 8;
-  size_t shm = (size_t)(9 * n + G * n) * cb;
+  const size_t cb = (prec == WCMG_F64) ? 16 : 8;
+  const size_t shm = (size_t)(9 * n + G * n) * cb;
   if (nsites == 0) return;
   if (prec == WCMG_F64)
     hipLaunchKernelGGL(k_coarse_hop<double>, dim3(nsites), dim3(threads), shm, st, out, in, x, M, Xmat, diag, coeff,

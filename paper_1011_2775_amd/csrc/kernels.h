@@ -49,42 +49,57 @@ void reals_convert(int prec_dst, void* dst, const double* src, size_t n, hipStre
 
 // ------------------------------------------------------------ BLAS-1
 // Flat complex vectors of n elements, storage double (prec F64) or float (F32).
-// Reductions accumulate in double and are deterministic (fixed grid,
-// fixed-order second pass).  Results go to device memory `res`.
+// Reductions accumulate in double and are deterministic (grid fixed by n,
+// per-block partials summed in block order by a one-block second pass).
 constexpr int kRedBlocks = 512;
+struct RedOut {
+  double* res;        // device result
+  double* partial;    // kRedBlocks * 32 doubles of per-block partials
+  unsigned* counter;  // unused (reserved)
+  double* hres;       // optional second destination of the result (nullptr: none)
+  RedOut at(int off) const { return RedOut{res + off, partial, counter, hres ? hres + off : nullptr}; }
+};
 void blas_zero(int prec, void* x, size_t n, hipStream_t st);
 void blas_copy(int prec, void* y, const void* x, size_t n, hipStream_t st);
 // y = a*x + b*y (complex a, b)
 void blas_axpby(int prec, double ar, double ai, const void* x, double br, double bi, void* y, size_t n,
                 hipStream_t st);
 // res[0] = ||x||^2
-void blas_norm2(int prec, const void* x, size_t n, double* res, double* partial, hipStream_t st);
+void blas_norm2(int prec, const void* x, size_t n, const RedOut& o, hipStream_t st);
 // res[0..1] = <x,y> = sum conj(x) y
-void blas_cdot(int prec, const void* x, const void* y, size_t n, double* res, double* partial, hipStream_t st);
+void blas_cdot(int prec, const void* x, const void* y, size_t n, const RedOut& o, hipStream_t st);
 // res[0..1] = <x,y>, res[2] = ||x||^2
-void blas_cdot_norm(int prec, const void* x, const void* y, size_t n, double* res, double* partial,
-                    hipStream_t st);
-// res[2j..2j+1] = <v_j, y> for j < k
-void blas_multi_cdot(int prec, const void* const* v, int k, const void* y, size_t n, double* res,
-                     double* partial, hipStream_t st);
-// y += sum_j c_j v_j  (c on host, k <= 32)
+void blas_cdot_norm(int prec, const void* x, const void* y, size_t n, const RedOut& o, hipStream_t st);
+// res[2j..2j+1] = <v_j, y> for j < k (writes up to 2*(k rounded up to 16) slots)
+void blas_multi_cdot(int prec, const void* const* v, int k, const void* y, size_t n, const RedOut& o,
+                     hipStream_t st);
+// y += sum_j c_j v_j  (c on host)
 void blas_multi_axpy(int prec, const double* c, const void* const* v, int k, void* y, size_t n, hipStream_t st);
-// y -= sum_j c_j q_j ; z -= sum_j c_j w_j ; res = [ ||y||^2, <y, r> ]
-void blas_gcr_orth(int prec, const double* c, const void* const* q, const void* const* w, int k, void* y,
-                   void* z, const void* r, size_t n, double* res, double* partial, hipStream_t st);
 // y += a x ; res[0] = ||y||^2
-void blas_axpy_norm(int prec, double ar, double ai, const void* x, void* y, size_t n, double* res,
-                    double* partial, hipStream_t st);
+void blas_axpy_norm(int prec, double ar, double ai, const void* x, void* y, size_t n, const RedOut& o,
+                    hipStream_t st);
 // BiCGStab: x += a p + w s ; r = s - w t ; res = [||r||^2, <rhat, r>]
 void blas_bicg_update(int prec, double ar, double ai, double wr, double wi, const void* p, const void* s,
-                      const void* t, void* x, void* r, const void* rhat, size_t n, double* res, double* partial,
-                      hipStream_t st);
+                      const void* t, void* x, void* r, const void* rhat, size_t n, const RedOut& o, hipStream_t st);
 // BiCGStab: p = r + b (p - w v)
 void blas_bicg_p(int prec, double br, double bi, double wr, double wi, const void* r, const void* v, void* p,
                  size_t n, hipStream_t st);
-// res = [ <t,s>, ||t||^2 ]   (identical to cdot_norm(t, s))
 // MR: x += a r ; r -= a Ar
 void blas_mr_update(int prec, double ar, double ai, void* x, void* r, const void* Ar, size_t n, hipStream_t st);
+
+// Device-resident GCR coefficients: slot j of qa holds {||q_j||^2, <q_j,r>, ||r||^2
+// after step j}; beta holds the multi-dot <q_j, y>.  No host round trip.
+// y -= sum_j (beta_j/||q_j||^2) q_j, z likewise with w_j; res = {||y||^2, <y,r>}
+void blas_gcr_orth_dev(int prec, const void* const* q, const void* const* w, int k, void* y, void* z, const void* r,
+                       size_t n, const double* beta, const double* qa, const RedOut& o, hipStream_t st);
+// r -= alpha_k q with alpha_k = <q,r>/||q||^2 from qa_k; res[0] = ||r||^2
+void blas_gcr_update_r_dev(int prec, const void* q, void* r, size_t n, const double* qa_k, const RedOut& o,
+                           hipStream_t st);
+// x += sum_j alpha_j z_j
+void blas_gcr_update_x_dev(int prec, const void* const* z, int k, void* x, size_t n, const double* qa,
+                           hipStream_t st);
+// MR with alpha = coef[0..1] / coef[2] (the output of blas_cdot_norm(Ar, r))
+void blas_mr_update_dev(int prec, const double* coef, void* x, void* r, const void* Ar, size_t n, hipStream_t st);
 
 // ------------------------------------------------------------ transfer (fine level)
 struct BlockGeom {

@@ -121,10 +121,15 @@ void Reducer::init(hipStream_t s) {
   st = s;
   partial.alloc((size_t)kRedBlocks * 64 * sizeof(double));
   res.alloc(256 * sizeof(double));
+  counter.alloc(256);
+  HIPCHK(hipMemset(counter.p, 0, 256));
   HIPCHK(hipHostMalloc((void**)&host, 256 * sizeof(double), hipHostMallocDefault));
 }
-const double* Reducer::fetch(int n) {
-  HIPCHK(hipMemcpyAsync(host, res.p, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, st));
+// The copy is ordered after the reduction on the stream; values written by a
+// kernel straight into host-mapped memory were not reliably visible to the
+// host at stream synchronisation, so results always come back this way.
+const double* Reducer::fetch_from(const double* dev, int n) {
+  HIPCHK(hipMemcpyAsync(host, dev, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   return host;
 }
@@ -133,7 +138,7 @@ Reducer::~Reducer() {
 }
 
 double norm2(Ctx& c, int prec, const void* x, size_t n) {
-  blas_norm2(prec, x, n, c.red.dres(), c.red.dpart(), c.st);
+  blas_norm2(prec, x, n, c.red.out(), c.st);
   return c.red.fetch(1)[0];
 }
 

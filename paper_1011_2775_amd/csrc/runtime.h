@@ -31,12 +31,17 @@ struct KernelTimer {
 // ------------------------------------------------------------------ reductions
 struct Reducer {
   hipStream_t st = nullptr;
-  DBuf partial, res;
-  double* host = nullptr;
+  DBuf partial, res, counter;
+  double* host = nullptr;  // pinned staging buffer for results read on the host
   void init(hipStream_t s);
   double* dres() { return res.as<double>(); }
-  double* dpart() { return partial.as<double>(); }
-  const double* fetch(int n);  // copy n results to the host and synchronise
+  // reduction result to the device buffer `dst` (default: res)
+  RedOut out(double* dst = nullptr) {
+    return RedOut{dst ? dst : res.as<double>(), partial.as<double>(), counter.as<unsigned>(), nullptr};
+  }
+  // copy n results (from res, or from any device address) to the host and synchronise
+  const double* fetch(int n) { return fetch_from(res.as<double>(), n); }
+  const double* fetch_from(const double* dev, int n);
   ~Reducer();
 };
 
@@ -141,8 +146,10 @@ struct GcrSpace {
   size_t bytes;  // bytes per vector
   std::vector<DBuf> Z, Q;
   DBuf r;
+  DBuf scal;  // device-resident GCR coefficients
   void ensure(int restart);
 };
+constexpr int kMaxRestart = 64;
 // ------------------------------------------------------------------ context
 struct Ctx {
   hipStream_t st = nullptr;

@@ -3,6 +3,8 @@
 // recursive GCR cycle (Implementation paragraph).
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 
 #include "random.h"
 #include "runtime.h"
@@ -19,9 +21,19 @@ void GcrSpace::ensure(int restart) {
     if (Q[k].n < bytes) Q[k].alloc(bytes);
   }
   if (r.n < bytes) r.alloc(bytes);
+  if (!scal.p) scal.alloc((2 * (kMaxRestart + 16) + 4 * kMaxRestart) * sizeof(double));
 }
 
 static bool finite(double v) { return std::isfinite(v); }
+
+// WCMG_LOG=0..3 selects progress messages on stderr (0: none)
+static int log_level() {
+  static int lvl = [] {
+    const char* e = std::getenv("WCMG_LOG");
+    return e ? std::atoi(e) : 0;
+  }();
+  return lvl;
+}
 
 // Flexible GCR with classical Gram-Schmidt against the unnormalised basis
 // q_j = A z_j, residual update r -= alpha q, and the solution update
@@ -52,7 +64,9 @@ KrylovResult gcr(Ctx& c, GcrSpace& S, const OpFn& A, const OpFn* K, void* x, con
     res.rel_res = target_norm > 0 ? std::sqrt(rn2) / target_norm : 0.0;
     return res;
   }
-  std::vector<double> coef(2 * restart), alpha(2 * restart), qq(restart);
+  // device scalars: beta (multi-dot results) and per-step {||q||^2, <q,r>, ||r||^2}
+  double* beta = S.scal.as<double>();
+  double* qa = beta + 2 * (kMaxRestart + 16);
   std::vector<const void*> Qp(restart), Zp(restart);
   bool converged = false;
   while (res.iters < maxiter) {
@@ -67,25 +81,16 @@ KrylovResult gcr(Ctx& c, GcrSpace& S, const OpFn& A, const OpFn* K, void* x, con
       else
         blas_copy(prec, z, r, n, st);
       A(q, z);
-      if (k > 0) {
-        blas_multi_cdot(prec, Qp.data(), k, q, n, R.dres(), R.dpart(), st);
-        const double* d = R.fetch(2 * k);
-        for (int j = 0; j < k; ++j) {
-          coef[2 * j] = d[2 * j] / qq[j];
-          coef[2 * j + 1] = d[2 * j + 1] / qq[j];
-        }
-      }
-      blas_gcr_orth(prec, coef.data(), Qp.data(), Zp.data(), k, q, z, r, n, R.dres(), R.dpart(), st);
-      const double* o = R.fetch(3);
-      qq[k] = o[0];
-      if (!(qq[k] > 0.0) || !finite(qq[k])) {
-        res.status = finite(qq[k]) ? WCMG_EBREAKDOWN : WCMG_ENAN;
+      if (k > 0) blas_multi_cdot(prec, Qp.data(), k, q, n, R.out(beta), st);
+      blas_gcr_orth_dev(prec, Qp.data(), Zp.data(), k, q, z, r, n, beta, qa, R.out(qa + 4 * k), st);
+      blas_gcr_update_r_dev(prec, q, r, n, qa + 4 * k, R.out(qa + 4 * k + 3), st);
+      const double* o = R.fetch_from(qa + 4 * k, 4);  // one host round trip: {||q||^2, <q,r>, ||r||^2}
+      const double qq = o[0];
+      rn2 = o[3];
+      if (!(qq > 0.0) || !finite(qq)) {
+        res.status = finite(qq) ? WCMG_EBREAKDOWN : WCMG_ENAN;
         break;
       }
-      alpha[2 * k] = o[1] / qq[k];
-      alpha[2 * k + 1] = o[2] / qq[k];
-      blas_axpy_norm(prec, -alpha[2 * k], -alpha[2 * k + 1], q, r, n, R.dres(), R.dpart(), st);
-      rn2 = R.fetch(1)[0];
       ++k;
       ++res.iters;
       if (!finite(rn2)) {
@@ -94,7 +99,7 @@ KrylovResult gcr(Ctx& c, GcrSpace& S, const OpFn& A, const OpFn* K, void* x, con
       }
       if ((!fixed && std::sqrt(rn2) <= target) || res.iters >= maxiter) break;
     }
-    if (k > 0) blas_multi_axpy(prec, alpha.data(), Zp.data(), k, x, n, st);
+    if (k > 0) blas_gcr_update_x_dev(prec, Zp.data(), k, x, n, qa, st);
     if (res.status != WCMG_OK) break;
     if (fixed) break;
     // true residual at the end of every cycle
@@ -129,13 +134,16 @@ KrylovResult bicgstab(Ctx& c, int prec, size_t n, const OpFn& A, void* x, const 
   KrylovResult res;
   const double target = tol * target_norm;
   int restarts = 0;
+  double rhat_n = 0.0;
   auto start = [&]() -> double {
     A(r, x);
     blas_axpby(prec, 1.0, 0.0, b, -1.0, 0.0, r, n, st);
     blas_copy(prec, rhat, r, n, st);
     blas_zero(prec, p, n, st);
     blas_zero(prec, v, n, st);
-    return norm2(c, prec, r, n);
+    double r2 = norm2(c, prec, r, n);
+    rhat_n = std::sqrt(r2);
+    return r2;
   };
   double rn2 = start();
   double rho_r = 1.0, rho_i = 0.0, al_r = 1.0, al_i = 0.0, om_r = 1.0, om_i = 0.0;
@@ -149,24 +157,43 @@ KrylovResult bicgstab(Ctx& c, int prec, size_t n, const OpFn& A, void* x, const 
     cr = ar * br - ai * bi;
     ci = ar * bi + ai * br;
   };
-  while (std::sqrt(rn2) > target && res.iters < maxiter) {
+  int verifications = 0;
+  for (;;) {
     if (!finite(rn2)) {
       res.status = WCMG_ENAN;
       break;
     }
+    if (std::sqrt(rn2) <= target) {
+      // the recursive residual drifts from b - A x over long runs: confirm with
+      // the true residual and continue from the current iterate if needed
+      const double tr2 = start();
+      if (std::sqrt(tr2) <= target || ++verifications > 50) {
+        rn2 = tr2;
+        break;
+      }
+      rn2 = tr2;
+      rho_r = al_r = om_r = 1.0;
+      rho_i = al_i = om_i = 0.0;
+      rn_r = rn2;
+      rn_i = 0.0;
+    }
+    if (res.iters >= maxiter) break;
+    if (log_level() >= 2 && res.iters % 1000 == 0)
+      std::fprintf(stderr, "[wcmg] bicgstab iter %d rel.res %.3e restarts %d checks %d\n", res.iters,
+                   std::sqrt(rn2) / target_norm, restarts, verifications);
     double t1r, t1i, t2r, t2i, br, bi;
     cdiv(rn_r, rn_i, rho_r, rho_i, t1r, t1i);
     cdiv(al_r, al_i, om_r, om_i, t2r, t2i);
     cmul(t1r, t1i, t2r, t2i, br, bi);
     blas_bicg_p(prec, br, bi, om_r, om_i, r, v, p, n, st);
     A(v, p);
-    blas_cdot(prec, rhat, v, n, R.dres(), R.dpart(), st);
+    blas_cdot(prec, rhat, v, n, R.out(), st);
     const double* d = R.fetch(2);
     double rv_r = d[0], rv_i = d[1];
-    const double scale = std::sqrt(rn2) * std::sqrt(norm2(c, prec, rhat, n));
+    const double scale = std::sqrt(rn2) * rhat_n;
     if (std::hypot(rv_r, rv_i) <= 1e-30 * scale || std::hypot(rn_r, rn_i) <= 1e-30 * scale) {
       // breakdown: restart from the current iterate
-      if (++restarts > 20) {
+      if (++restarts > 1000) {
         res.status = WCMG_EBREAKDOWN;
         break;
       }
@@ -180,7 +207,7 @@ KrylovResult bicgstab(Ctx& c, int prec, size_t n, const OpFn& A, void* x, const 
     cdiv(rn_r, rn_i, rv_r, rv_i, al_r, al_i);
     blas_axpby(prec, -al_r, -al_i, v, 1.0, 0.0, r, n, st);  // r <- s = r - alpha v
     A(t, r);
-    blas_cdot_norm(prec, t, r, n, R.dres(), R.dpart(), st);
+    blas_cdot_norm(prec, t, r, n, R.out(), st);
     d = R.fetch(3);
     if (!(d[2] > 0.0)) {
       // s = 0: x += alpha p solves the system
@@ -193,7 +220,7 @@ KrylovResult bicgstab(Ctx& c, int prec, size_t n, const OpFn& A, void* x, const 
     om_i = d[1] / d[2];
     rho_r = rn_r;
     rho_i = rn_i;
-    blas_bicg_update(prec, al_r, al_i, om_r, om_i, p, r, t, x, r, rhat, n, R.dres(), R.dpart(), st);
+    blas_bicg_update(prec, al_r, al_i, om_r, om_i, p, r, t, x, r, rhat, n, R.out(), st);
     d = R.fetch(3);
     rn2 = d[0];
     rn_r = d[1];
@@ -277,12 +304,11 @@ struct MGSolver {
       op.Dr(Ar_s.p, e_s.p);
       blas_copy(sp, res_s.p, r_s.p, n, st);
       blas_axpby(sp, -1.0, 0.0, Ar_s.p, 1.0, 0.0, res_s.p, n, st);
+      // alpha = <Ar, r> / ||Ar||^2 stays on the device: no host round trip
       for (int i = 0; i < nu; ++i) {
         op.Dr(Ar_s.p, res_s.p);
-        blas_cdot_norm(sp, Ar_s.p, res_s.p, n, c.red.dres(), c.red.dpart(), st);
-        const double* d = c.red.fetch(3);
-        if (!(d[2] > 0.0)) break;
-        blas_mr_update(sp, d[0] / d[2], d[1] / d[2], e_s.p, res_s.p, Ar_s.p, n, st);
+        blas_cdot_norm(sp, Ar_s.p, res_s.p, n, c.red.out(), st);
+        blas_mr_update_dev(sp, c.red.dres(), e_s.p, res_s.p, Ar_s.p, n, st);
       }
     }
     spinor_convert(WCMG_F64, z64, sp, e_s.p, g.Vh, st);
@@ -325,7 +351,7 @@ void mg_setup_null_vectors(Ctx& c, LatticeState& L, int level) {
       gcr(c, S, Dp, nullptr, x, v, true, 0.0, 1.0, p.setup_relax, p.setup_relax, true);
       blas_copy(WCMG_F64, v, x, n, st);
       for (int pass = 0; pass < 2 && k > 0; ++pass) {
-        blas_multi_cdot(WCMG_F64, found.data(), k, v, n, c.red.dres(), c.red.dpart(), st);
+        blas_multi_cdot(WCMG_F64, found.data(), k, v, n, c.red.out(), st);
         const double* d = c.red.fetch(2 * k);
         for (int j = 0; j < 2 * k; ++j) cf[j] = -d[j];
         blas_multi_axpy(WCMG_F64, cf.data(), found.data(), k, v, n, st);

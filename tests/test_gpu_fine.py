@@ -177,3 +177,20 @@ def test_gamma5_hermiticity_16x16x16x32():
     rhs = torch.vdot(ctx.apply_Ddag(phi).flatten(), psi.flatten())
     assert abs(lhs - rhs) / abs(lhs) < 1e-13
     ctx.close()
+
+
+@pytest.mark.parametrize("n", [1, 5, 2047, 2049, 12288, 786432, 3_000_001])
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_global_sum_matches_torch(n, dtype):
+    """The deterministic two-pass reduction behind every solver inner product,
+    at lengths from one element to beyond the 512-block grid cap."""
+    ctx = w.Context((4, 4, 4, 4))
+    g = torch.Generator(device="cuda").manual_seed(n)
+    x = torch.randn(n, dtype=dtype, device="cuda", generator=g)
+    y = torch.randn(n, dtype=dtype, device="cuda", generator=g)
+    got = ctx.dot(x, y)
+    want = complex(torch.vdot(x.to(torch.complex128), y.to(torch.complex128)).item())
+    assert abs(got - want) <= 1e-12 * (float(torch.linalg.vector_norm(x.to(torch.complex128))) *
+                                       float(torch.linalg.vector_norm(y.to(torch.complex128))))
+    assert ctx.dot(x, y) == got   # bitwise reproducible
+    ctx.close()
