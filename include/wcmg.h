@@ -87,7 +87,7 @@ typedef struct {
  * Level l = 0 is the fine lattice; coarse level l+1 is built from level l
  * with block[l] and nvec[l]. */
 typedef struct {
-  int nlevels;                      /* number of coarse levels, 1..WCMG_MAX_LEVELS */
+  int nlevels;                      /* number of coarse levels: 1 (two-level) or 2 (three-level) */
   int block[WCMG_MAX_LEVELS][4];    /* aggregate (block) extents per level */
   int nvec[WCMG_MAX_LEVELS];        /* null vectors per level (coarse dim 2*nvec) */
   double tol[WCMG_MAX_LEVELS];      /* relative tolerance of the GCR on coarse level l+1 */
@@ -101,7 +101,9 @@ typedef struct {
   int setup_max_steps;              /* max relaxations per vector */
   double setup_rq_tol;              /* stop when |d rho| / rho < this */
   uint64_t seed;                    /* Philox4x32-10 key for the random start vectors */
-  int coarsest;                     /* 0: unpreconditioned GCR (paper), 1: dense LU (FP64) */
+  int coarsest;                     /* 0: unpreconditioned GCR (paper); 1: direct solve with the
+                                       dense FP64 inverse of the coarsest full operator (Gauss-Jordan
+                                       with partial pivoting; dimension <= 16384) */
 } wcmg_mg_params;
 
 typedef struct {
@@ -136,8 +138,11 @@ int wcmg_set_gauge(void* ctx, int lat, const void* U, int on_device);
 int wcmg_set_clover(void* ctx, int lat, double m0, double csw, const void* A, int on_device);
 
 /* Fix the multigrid shape (blocks, Nv, tolerances) for a lattice. EDIM if
- * a block does not divide its level or 2*Nv exceeds the block's degrees of
- * freedom per chirality. */
+ * a block does not divide its level, Nv exceeds the block's degrees of
+ * freedom per chirality, or (coarsest = 1) the coarsest dimension exceeds
+ * 16384.  With nlevels = 2 each intermediate level runs GCR preconditioned
+ * by the next level's correction followed by MR smoothing (the recursive
+ * cycle of the Implementation paragraph). */
 int wcmg_set_mg_params(void* ctx, int lat, const wcmg_mg_params* p);
 
 /* Setup section: for each vector, repeated relaxation (inverse iteration)
@@ -170,7 +175,9 @@ int wcmg_apply_Ddag(void* ctx, int lat, int op, int prec, void* out, const void*
 
 /* Transfer operators between level and level+1 (device buffers):
  * restrict: coarse = R fine = P^dag gamma5 fine;  prolong: fine = P coarse.
- * Level 0 fine vectors are canonical spinors (both parities). */
+ * Level 0 fine vectors are canonical spinors (both parities); coarse
+ * vectors of level l >= 1 are complex128 [Vc][2 Nv] in lexicographic
+ * coarse-site order.  prec (F64/F32 on coarse levels) is the arithmetic. */
 int wcmg_restrict(void* ctx, int lat, int level, int prec, void* coarse_out, const void* fine_in, int nrhs);
 int wcmg_prolong(void* ctx, int lat, int level, int prec, void* fine_out, const void* coarse_in, int nrhs);
 
@@ -185,6 +192,29 @@ int wcmg_apply_coarse(void* ctx, int lat, int level, int op, int prec, void* out
  * GCR / BICGSTAB: unpreconditioned FP64 on D_r.  Synchronises.  Returns the
  * worst status over the right-hand sides. */
 int wcmg_solve(void* ctx, int lat, int solver, void* x, const void* b, int nrhs, double tol, wcmg_stats* stats);
+
+/* Solve the adjoint system D^dag x = b (device, canonical layout), for the
+ * backward pass of a loss through x = D^-1 eta.  Uses the gamma5-hermiticity
+ * of Eq.(1), D^dag = gamma5 D gamma5: x = gamma5 D^-1 (gamma5 b), so the same
+ * solver and multigrid hierarchy serve.  Arguments, initial guess, stopping
+ * rule, stats and errors as for wcmg_solve (the residual reported is that of
+ * the transformed system, equal in norm to ||b - D^dag x||). */
+int wcmg_solve_dag(void* ctx, int lat, int solver, void* x, const void* b, int nrhs, double tol,
+                   wcmg_stats* stats);
+
+/* Gauge-link gradient of a real loss L through x = D(U)^-1 eta, given the
+ * solutions psi (x) and lam = D^-dag g (g the gradient of L with respect to
+ * x), both device arrays of nrhs canonical spinors:
+ *   dU[y][mu] = -dRe<lam, D(U) psi>/dU_mu(y), summed over the nrhs pairs,
+ * in PyTorch's complex convention (dL = Re sum conj(dU) delta U); canonical
+ * complex128 [Lt][Lz][Ly][Lx][4][3][3], overwritten.  The hopping part comes
+ * from the hop of Eq.(1) (with the time boundary phase of each link); with
+ * include_clover != 0 the clover part (derivative of the plaquette leaves)
+ * is added, which needs a clover computed from the gauge field by
+ * wcmg_set_clover(A = NULL).  FP64.  Asynchronous on the context stream.
+ * Errors: EINVAL (null buffer, nrhs < 1), ESTATE (no gauge field, or the
+ * clover part requested for a caller-supplied clover matrix). */
+int wcmg_force(void* ctx, int lat, void* dU, const void* psi, const void* lam, int nrhs, int include_clover);
 
 /* The global sum behind every inner product of the Krylov solvers (the
  * GCR orthogonalisation of the adaptive multigrid paragraph):

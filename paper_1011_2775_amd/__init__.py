@@ -106,8 +106,7 @@ class Context:
 
     def get_null_vectors(self, level=0, lat=0):
         nv = self.params[lat].nvec[level]
-        out = torch.empty((nv,) + tuple(reversed(self.dims[lat])) + (4, 3), dtype=torch.complex128,
-                          device="cuda")
+        out = torch.empty((nv,) + self._level_shape(level, lat), dtype=torch.complex128, device="cuda")
         check(_lib.LIB.wcmg_get_null_vectors(self.h, lat, level, ctypes.c_void_p(out.data_ptr()), 1))
         return out
 
@@ -115,8 +114,18 @@ class Context:
         check(_lib.LIB.wcmg_build_coarse(self.h, lat, level))
 
     def coarse_dims(self, level=0, lat=0):
-        b = self.params[lat].block[level]
-        return tuple(self.dims[lat][m] // b[m] for m in range(4))
+        """Extents of coarse level level+1."""
+        d = list(self.dims[lat])
+        for l in range(level + 1):
+            b = self.params[lat].block[l]
+            d = [d[m] // b[m] for m in range(4)]
+        return tuple(d)
+
+    def _level_shape(self, level, lat=0):
+        """Canonical shape of one vector on level `level` (0: fine spinor, l >= 1: [Vc][2 Nv])."""
+        if level == 0:
+            return tuple(reversed(self.dims[lat])) + (4, 3)
+        return (int(np.prod(self.coarse_dims(level - 1, lat))), 2 * self.params[lat].nvec[level - 1])
 
     def get_coarse(self, level=0, lat=0):
         n = 2 * self.params[lat].nvec[level]
@@ -139,18 +148,17 @@ class Context:
         return self._apply(_lib.LIB.wcmg_apply_Ddag, op, prec, inp.contiguous(), lat)
 
     def restrict(self, fine, level=0, prec=F64, lat=0):
-        n = 2 * self.params[lat].nvec[level]
-        Vc = int(np.prod(self.coarse_dims(level, lat)))
-        nrhs = fine.numel() // (self.volume(lat) * 12)
-        out = torch.empty((nrhs, Vc, n), dtype=torch.complex128, device=fine.device)
+        """Level level -> level+1 restriction R = P^dag gamma5 (prec: arithmetic; complex128 I/O)."""
+        shp = self._level_shape(level + 1, lat)
+        nrhs = fine.numel() // int(np.prod(self._level_shape(level, lat)))
+        out = torch.empty((nrhs,) + shp, dtype=torch.complex128, device=fine.device)
         check(_lib.LIB.wcmg_restrict(self.h, lat, level, prec, ctypes.c_void_p(out.data_ptr()),
                                      ctypes.c_void_p(fine.contiguous().data_ptr()), nrhs))
         return out
 
     def prolong(self, coarse, level=0, prec=F64, lat=0):
         nrhs = coarse.shape[0] if coarse.dim() == 3 else 1
-        out = torch.empty((nrhs,) + tuple(reversed(self.dims[lat])) + (4, 3), dtype=torch.complex128,
-                          device=coarse.device)
+        out = torch.empty((nrhs,) + self._level_shape(level, lat), dtype=torch.complex128, device=coarse.device)
         check(_lib.LIB.wcmg_prolong(self.h, lat, level, prec, ctypes.c_void_p(out.data_ptr()),
                                     ctypes.c_void_p(coarse.contiguous().data_ptr()), nrhs))
         return out
@@ -167,15 +175,37 @@ class Context:
 
     # -- solve -------------------------------------------------------------------
     def solve(self, b, solver=MG_GCR, tol=1e-10, x0=None, lat=0, raise_on_error=True):
+        """x with D x = b (canonical complex128 device tensor of nrhs spinors)."""
+        return self._solve(_lib.LIB.wcmg_solve, b, solver, tol, x0, lat, raise_on_error)
+
+    def solve_dag(self, b, solver=MG_GCR, tol=1e-10, x0=None, lat=0, raise_on_error=True):
+        """x with D^dag x = b, through D^dag = gamma5 D gamma5 (same solver and hierarchy)."""
+        return self._solve(_lib.LIB.wcmg_solve_dag, b, solver, tol, x0, lat, raise_on_error)
+
+    def _solve(self, fn, b, solver, tol, x0, lat, raise_on_error):
         b = b.contiguous()
         x = torch.zeros_like(b) if x0 is None else x0.clone().contiguous()
         nrhs = b.numel() // (self.volume(lat) * 12)
         st = (_lib.Stats * nrhs)()
-        rc = _lib.LIB.wcmg_solve(self.h, lat, solver, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(b.data_ptr()),
-                                 nrhs, float(tol), st)
+        rc = fn(self.h, lat, solver, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(b.data_ptr()), nrhs, float(tol),
+                st)
         if raise_on_error:
             check(rc)
         return x, [s.as_dict() for s in st]
+
+    def force(self, psi, lam, include_clover=True, lat=0):
+        """Gauge-link gradient -dRe<lam, D(U) psi>/dU (complex128 [Lt][Lz][Ly][Lx][4][3][3]),
+        summed over the right-hand sides of psi and lam."""
+        psi = psi.contiguous()
+        lam = lam.contiguous()
+        if psi.shape != lam.shape or psi.dtype != torch.complex128 or lam.dtype != torch.complex128:
+            raise ValueError("psi and lam must be complex128 tensors of the same shape")
+        nrhs = psi.numel() // (self.volume(lat) * 12)
+        dims = self.dims[lat]
+        dU = torch.empty((dims[3], dims[2], dims[1], dims[0], 4, 3, 3), dtype=torch.complex128, device=psi.device)
+        check(_lib.LIB.wcmg_force(self.h, lat, ctypes.c_void_p(dU.data_ptr()), ctypes.c_void_p(psi.data_ptr()),
+                                  ctypes.c_void_p(lam.data_ptr()), nrhs, int(bool(include_clover))))
+        return dU
 
     # -- global sums -------------------------------------------------------------
     def dot(self, x, y):

@@ -78,6 +78,8 @@ SIGNATURES = {
     "wcmg_prolong": [_vp, _i, _i, _i, _vp, _vp, _i],
     "wcmg_apply_coarse": [_vp, _i, _i, _i, _i, _vp, _vp, _i],
     "wcmg_solve": [_vp, _i, _i, _vp, _vp, _i, _d, ctypes.POINTER(Stats)],
+    "wcmg_solve_dag": [_vp, _i, _i, _vp, _vp, _i, _d, ctypes.POINTER(Stats)],
+    "wcmg_force": [_vp, _i, _vp, _vp, _vp, _i, _i],
     "wcmg_dot": [_vp, _i, _vp, _vp, ctypes.c_long, ctypes.POINTER(_d)],
     "wcmg_timer_enable": [_vp, _i],
     "wcmg_timer_read": [_vp, _i, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(_d)],

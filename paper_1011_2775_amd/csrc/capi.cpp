@@ -207,9 +207,7 @@ int wcmg_set_gauge(void* ctx, int lat, const void* U, int on_device) {
     HIPCHK(hipStreamSynchronize(c->st));
     L.F.have_gauge = true;
     L.F.have_clover = false;
-    L.T0 = FineTransfer();
-    L.levels.clear();
-    L.mg.reset();
+    L.clear_hierarchy();
   });
 }
 
@@ -244,6 +242,7 @@ int wcmg_set_clover(void* ctx, int lat, double m0, double csw, const void* A, in
     HIPCHK(hipStreamSynchronize(c->st));
     L.F.m0 = m0;
     L.F.csw = csw;
+    L.F.clover_from_u = (A == nullptr);
     L.F.have_clover = true;
     for (auto& lv : L.levels) lv->built = false;
     L.mg.reset();
@@ -255,7 +254,7 @@ int wcmg_set_mg_params(void* ctx, int lat, const wcmg_mg_params* p) {
   if (int r = check_lat(c, lat)) return r;
   CHECK(p, WCMG_EINVAL, "null params");
   CHECK(p->nlevels >= 1 && p->nlevels <= WCMG_MAX_LEVELS, WCMG_EINVAL, "nlevels out of range");
-  CHECK(p->nlevels == 1, WCMG_EINVAL, "only two-level hierarchies (nlevels = 1) are available");
+  CHECK(p->nlevels <= 2, WCMG_EINVAL, "at most two coarse levels (nlevels <= 2) are available");
   LatticeState& L = *c->lats[lat];
   const Geom& g = L.F.g;
   for (int k = 0; k < 4; ++k) {
@@ -276,24 +275,60 @@ int wcmg_set_mg_params(void* ctx, int lat, const wcmg_mg_params* p) {
   CHECK(p->smoother_prec == WCMG_F64 || p->smoother_prec == WCMG_F32, WCMG_EINVAL,
         "smoother precision must be F64 or F32");
   CHECK(p->setup_relax >= 1 && p->setup_max_steps >= 1, WCMG_EINVAL, "setup iteration counts must be >= 1");
-  CHECK(p->coarsest == 0, WCMG_EINVAL, "only the GCR coarsest solver is available");
+  CHECK(p->coarsest == 0 || p->coarsest == 1, WCMG_EINVAL, "coarsest must be 0 (GCR) or 1 (dense FP64 inverse)");
+  // coarse extents and degrees of freedom of every level
+  int ext[4], nf = 2 * p->nvec[0];
+  for (int k = 0; k < 4; ++k) ext[k] = g.L[k] / p->block[0][k];
+  long vc = (long)ext[0] * ext[1] * ext[2] * ext[3];
+  for (int l = 1; l < p->nlevels; ++l) {
+    long bv = 1;
+    for (int k = 0; k < 4; ++k) {
+      int b = p->block[l][k];
+      CHECK(b >= 1 && ext[k] % b == 0, WCMG_EDIM, "coarse block does not divide the coarse lattice");
+      ext[k] /= b;
+      bv *= b;
+    }
+    CHECK(bv >= 2 && bv <= 1024, WCMG_EDIM, "coarse block volume must be in 2..1024");
+    CHECK(p->nvec[l] >= 1 && p->nvec[l] <= 64, WCMG_EDIM, "nvec must be in 1..64");
+    CHECK(p->nvec[l] <= bv * (nf / 2), WCMG_EDIM, "nvec exceeds the block's degrees of freedom per chirality");
+    CHECK(p->tol[l] > 0 && p->tol[l] < 1, WCMG_EINVAL, "inner tolerance must be in (0,1)");
+    CHECK(p->max_iter[l] >= 1 && p->restart[l] >= 1 && p->restart[l] <= 64, WCMG_EINVAL,
+          "inner max_iter and restart must be >= 1 (restart <= 64)");
+    vc = (long)ext[0] * ext[1] * ext[2] * ext[3];
+    nf = 2 * p->nvec[l];
+  }
+  if (p->coarsest == 1)
+    CHECK(vc * nf <= kMaxDense, WCMG_EDIM, "coarsest level too large for the dense solve");
   return guarded([&] {
-    bool same_shape = L.have_params && L.params.nvec[0] == p->nvec[0] &&
-                      std::memcmp(L.params.block[0], p->block[0], sizeof(p->block[0])) == 0;
+    bool same_shape = L.have_params && L.params.nlevels == p->nlevels;
+    for (int l = 0; same_shape && l < p->nlevels; ++l)
+      same_shape = L.params.nvec[l] == p->nvec[l] &&
+                   std::memcmp(L.params.block[l], p->block[l], sizeof(p->block[l])) == 0;
+    const bool same_coarsest = L.have_params && L.params.coarsest == p->coarsest;
     L.params = *p;
     L.have_params = true;
     if (!same_shape) {
-      L.T0 = FineTransfer();
-      L.levels.clear();
+      L.clear_hierarchy();
+    } else if (!same_coarsest) {
+      L.dense.release();
+      L.dense_n = 0;
+      for (auto& lv : L.levels) lv->built = false;
     }
     L.mg.reset();
   });
 }
 
+static int check_level(Ctx* c, int lat, int level) {
+  LatticeState& L = *c->lats[lat];
+  CHECK(L.have_params, WCMG_ESTATE, "multigrid parameters not set");
+  CHECK(level >= 0 && level < L.params.nlevels, WCMG_EINVAL, "level out of range");
+  return WCMG_OK;
+}
+
 int wcmg_build_null_vectors(void* ctx, int lat, int level) {
   Ctx* c = as_ctx(ctx);
   if (int r = check_lat(c, lat)) return r;
-  CHECK(level == 0, WCMG_EINVAL, "level out of range");
+  if (int r = check_level(c, lat, level)) return r;
   return guarded([&] { mg_setup_null_vectors(*c, *c->lats[lat], level); });
 }
 
@@ -301,10 +336,34 @@ int wcmg_set_null_vectors(void* ctx, int lat, int level, const void* v, int nvec
   Ctx* c = as_ctx(ctx);
   if (int r = check_lat(c, lat)) return r;
   CHECK(v, WCMG_EINVAL, "null vectors pointer");
-  CHECK(level == 0, WCMG_EINVAL, "level out of range");
+  if (int r = check_level(c, lat, level)) return r;
   LatticeState& L = *c->lats[lat];
-  CHECK(L.have_params, WCMG_ESTATE, "multigrid parameters not set");
-  CHECK(nvec == L.params.nvec[0], WCMG_EINVAL, "nvec differs from the parameters");
+  CHECK(nvec == L.params.nvec[level], WCMG_EINVAL, "nvec differs from the parameters");
+  if (level == 1) {
+    CHECK(!L.levels.empty() && L.levels[0]->built, WCMG_ESTATE, "first coarse level not built");
+    return guarded([&] {
+      CoarseLevel& C1 = *L.levels[0];
+      const size_t one = (size_t)C1.cg.V * C1.cg.n * 16;
+      if (L.ctr.empty()) L.ctr.emplace_back(new CoarseTransfer());
+      CoarseTransfer& T = *L.ctr[0];
+      T.nf = C1.cg.n;
+      T.nsites = C1.cg.V;
+      T.raw.alloc((size_t)nvec * one);
+      for (int k = 0; k < nvec; ++k) {
+        const void* src = to_device(*c, 41, (const char*)v + (size_t)k * one, one, on_device);
+        launch_coarse_canon(WCMG_F64, (char*)T.raw.p + (size_t)k * one, const_cast<void*>(src), C1.perm.as<int>(),
+                            C1.cg.V, C1.cg.n, true, c->st);
+        if (!on_device) HIPCHK(hipStreamSynchronize(c->st));
+      }
+      HIPCHK(hipStreamSynchronize(c->st));
+      T.nvec = nvec;
+      T.have_vecs = true;
+      T.orth = false;
+      if (L.levels.size() > 1) L.levels[1]->built = false;
+      L.dense_n = 0;
+      L.mg.reset();
+    });
+  }
   return guarded([&] {
     const Geom& g = L.F.g;
     const size_t hb = spinor_bytes(WCMG_F64, g.Vh);
@@ -329,8 +388,24 @@ int wcmg_get_null_vectors(void* ctx, int lat, int level, void* v, int on_device)
   Ctx* c = as_ctx(ctx);
   if (int r = check_lat(c, lat)) return r;
   CHECK(v, WCMG_EINVAL, "null vectors pointer");
-  CHECK(level == 0, WCMG_EINVAL, "level out of range");
+  if (int r = check_level(c, lat, level)) return r;
   LatticeState& L = *c->lats[lat];
+  if (level == 1) {
+    CHECK(!L.ctr.empty() && L.ctr[0]->have_vecs && !L.levels.empty(), WCMG_ESTATE, "null vectors not available");
+    return guarded([&] {
+      CoarseLevel& C1 = *L.levels[0];
+      CoarseTransfer& T = *L.ctr[0];
+      const size_t one = (size_t)C1.cg.V * C1.cg.n * 16;
+      for (int k = 0; k < T.nvec; ++k) {
+        void* dst = on_device ? (char*)v + (size_t)k * one : c->scratch_buf(41, one);
+        launch_coarse_canon(WCMG_F64, (char*)T.raw.p + (size_t)k * one, dst, C1.perm.as<int>(), C1.cg.V, C1.cg.n,
+                            false, c->st);
+        if (!on_device)
+          HIPCHK(hipMemcpyAsync((char*)v + (size_t)k * one, dst, one, hipMemcpyDeviceToHost, c->st));
+        HIPCHK(hipStreamSynchronize(c->st));
+      }
+    });
+  }
   CHECK(L.T0.have_vecs, WCMG_ESTATE, "null vectors not available");
   return guarded([&] {
     const Geom& g = L.F.g;
@@ -350,7 +425,7 @@ int wcmg_get_null_vectors(void* ctx, int lat, int level, void* v, int on_device)
 int wcmg_build_coarse(void* ctx, int lat, int level) {
   Ctx* c = as_ctx(ctx);
   if (int r = check_lat(c, lat)) return r;
-  CHECK(level == 0, WCMG_EINVAL, "level out of range");
+  if (int r = check_level(c, lat, level)) return r;
   return guarded([&] { mg_build_coarse(*c, *c->lats[lat], level); });
 }
 
@@ -358,11 +433,11 @@ int wcmg_get_coarse(void* ctx, int lat, int level, void* Y, int on_device) {
   Ctx* c = as_ctx(ctx);
   if (int r = check_lat(c, lat)) return r;
   CHECK(Y, WCMG_EINVAL, "null output");
-  CHECK(level == 0, WCMG_EINVAL, "level out of range");
+  if (int r = check_level(c, lat, level)) return r;
   LatticeState& L = *c->lats[lat];
-  CHECK(!L.levels.empty() && L.levels[0]->built, WCMG_ESTATE, "coarse operator not built");
+  CHECK((int)L.levels.size() > level && L.levels[level]->built, WCMG_ESTATE, "coarse operator not built");
   return guarded([&] {
-    CoarseLevel& C = *L.levels[0];
+    CoarseLevel& C = *L.levels[level];
     const int n = C.cg.n, V = C.cg.V;
     const size_t nn = (size_t)n * n;
     std::vector<double> h((size_t)V * 9 * nn * 2), o(h.size());
@@ -445,14 +520,47 @@ int wcmg_apply_Ddag(void* ctx, int lat, int op, int prec, void* out, const void*
   return apply_common(ctx, lat, op, prec, out, in, nrhs, true);
 }
 
+// restrict (to_coarse) or prolong between coarse level 1 and level 2, canonical layouts
+static int transfer_level1(Ctx* c, LatticeState& L, int prec, void* out, const void* in, int nrhs, bool to_coarse) {
+  CHECK(prec == WCMG_F64 || prec == WCMG_F32, WCMG_EINVAL, "coarse transfer precision must be F64 or F32");
+  CHECK(L.levels.size() > 1 && L.levels[1]->built && !L.ctr.empty() && L.ctr[0]->orth, WCMG_ESTATE,
+        "second coarse level not built");
+  return guarded([&] {
+    CoarseLevel& C1 = *L.levels[0];
+    CoarseLevel& C2 = *L.levels[1];
+    CoarseTransfer& T = *L.ctr[0];
+    const size_t one1 = (size_t)C1.cg.V * C1.cg.n, one2 = (size_t)C2.cg.V * C2.cg.n;
+    const size_t cs = 16;  // canonical side is complex128
+    void* a = c->scratch_buf(46, one1 * 16);
+    void* b = c->scratch_buf(47, one2 * 16);
+    const void* P = prec == WCMG_F64 ? T.v64.p : T.v32.p;
+    for (int r = 0; r < nrhs; ++r) {
+      if (to_coarse) {
+        launch_coarse_canon(prec, a, (char*)const_cast<void*>(in) + r * one1 * cs, C1.perm.as<int>(), C1.cg.V,
+                            C1.cg.n, true, c->st);
+        launch_ctr_restrict(prec, b, C2.cg.n, 0, a, 0, P, T.vstride(), T.members.as<int>(), C2.cg.V, T.bg.bvol,
+                            C1.cg.n, T.nvec, 1, c->st);
+        launch_coarse_canon(prec, b, (char*)out + r * one2 * cs, C2.perm.as<int>(), C2.cg.V, C2.cg.n, false, c->st);
+      } else {
+        launch_coarse_canon(prec, b, (char*)const_cast<void*>(in) + r * one2 * cs, C2.perm.as<int>(), C2.cg.V,
+                            C2.cg.n, true, c->st);
+        launch_ctr_prolong(prec, a, 0, b, 0, P, T.vstride(), T.blk.as<int>(), C1.cg.V, C1.cg.n, T.nvec, 1, c->st);
+        launch_coarse_canon(prec, a, (char*)out + r * one1 * cs, C1.perm.as<int>(), C1.cg.V, C1.cg.n, false, c->st);
+      }
+    }
+    HIPCHK(hipStreamSynchronize(c->st));
+  });
+}
+
 int wcmg_restrict(void* ctx, int lat, int level, int prec, void* coarse_out, const void* fine_in, int nrhs) {
   Ctx* c = as_ctx(ctx);
   if (int r = check_lat(c, lat)) return r;
   CHECK(coarse_out && fine_in, WCMG_EINVAL, "null buffer");
-  CHECK(level == 0, WCMG_EINVAL, "level out of range");
+  if (int r = check_level(c, lat, level)) return r;
   CHECK(valid_prec(prec), WCMG_EINVAL, "bad precision");
   CHECK(nrhs >= 1, WCMG_EINVAL, "nrhs must be >= 1");
   LatticeState& L = *c->lats[lat];
+  if (level == 1) return transfer_level1(c, L, prec, coarse_out, fine_in, nrhs, true);
   CHECK(!L.levels.empty() && L.levels[0]->built, WCMG_ESTATE, "coarse operator not built");
   return guarded([&] {
     const Geom& g = L.F.g;
@@ -487,10 +595,11 @@ int wcmg_prolong(void* ctx, int lat, int level, int prec, void* fine_out, const 
   Ctx* c = as_ctx(ctx);
   if (int r = check_lat(c, lat)) return r;
   CHECK(fine_out && coarse_in, WCMG_EINVAL, "null buffer");
-  CHECK(level == 0, WCMG_EINVAL, "level out of range");
+  if (int r = check_level(c, lat, level)) return r;
   CHECK(valid_prec(prec), WCMG_EINVAL, "bad precision");
   CHECK(nrhs >= 1, WCMG_EINVAL, "nrhs must be >= 1");
   LatticeState& L = *c->lats[lat];
+  if (level == 1) return transfer_level1(c, L, prec, fine_out, coarse_in, nrhs, false);
   CHECK(!L.levels.empty() && L.levels[0]->built, WCMG_ESTATE, "coarse operator not built");
   return guarded([&] {
     const Geom& g = L.F.g;
@@ -526,13 +635,13 @@ int wcmg_apply_coarse(void* ctx, int lat, int level, int op, int prec, void* out
   if (int r = check_lat(c, lat)) return r;
   CHECK(out && in, WCMG_EINVAL, "null buffer");
   CHECK(out != in, WCMG_EINVAL, "out and in must not alias");
-  CHECK(level == 1, WCMG_EINVAL, "level out of range");
   CHECK(valid_op(op), WCMG_EINVAL, "bad operator");
   CHECK(prec == WCMG_F64 || prec == WCMG_F32, WCMG_EINVAL, "coarse precision must be F64 or F32");
   CHECK(nrhs >= 1, WCMG_EINVAL, "nrhs must be >= 1");
   LatticeState& L = *c->lats[lat];
-  CHECK(!L.levels.empty() && L.levels[0]->built, WCMG_ESTATE, "coarse operator not built");
-  CoarseLevel& C = *L.levels[0];
+  CHECK(L.have_params && level >= 1 && level <= L.params.nlevels, WCMG_EINVAL, "level out of range");
+  CHECK((int)L.levels.size() >= level && L.levels[level - 1]->built, WCMG_ESTATE, "coarse operator not built");
+  CoarseLevel& C = *L.levels[level - 1];
   CHECK(op != WCMG_OP_SCHUR || C.cg.split, WCMG_EDIM, "coarse lattice has an odd extent: no red-black form");
   return guarded([&] {
     const size_t cs = prec == WCMG_F64 ? 16 : 8;
@@ -558,7 +667,8 @@ int wcmg_apply_coarse(void* ctx, int lat, int level, int op, int prec, void* out
   });
 }
 
-int wcmg_solve(void* ctx, int lat, int solver, void* x, const void* b, int nrhs, double tol, wcmg_stats* stats) {
+static int solve_impl(void* ctx, int lat, int solver, void* x, const void* b, int nrhs, double tol, wcmg_stats* stats,
+               bool dag) {
   Ctx* c = as_ctx(ctx);
   if (int r = check_lat(c, lat)) return r;
   CHECK(x && b, WCMG_EINVAL, "null buffer");
@@ -584,9 +694,17 @@ int wcmg_solve(void* ctx, int lat, int solver, void* x, const void* b, int nrhs,
       void* xs = (char*)x + (size_t)r * one;
       spinor_to_internal(WCMG_F64, be, bo, bs, g, false, c->st);
       spinor_to_internal(WCMG_F64, xe, xo, xs, g, false, c->st);
+      if (dag) {
+        // D^dag x = b  <=>  D (gamma5 x) = gamma5 b
+        for (void* v : {be, bo, xe, xo}) spinor_gamma5(WCMG_F64, v, g.Vh, c->st);
+      }
       double xn = norm2(*c, WCMG_F64, xe, (size_t)12 * g.Vh) + norm2(*c, WCMG_F64, xo, (size_t)12 * g.Vh);
       wcmg_stats s{};
       solve_rhs(*c, L, solver, xe, xo, be, bo, xn == 0.0, tol, &s);
+      if (dag) {
+        spinor_gamma5(WCMG_F64, xe, g.Vh, c->st);
+        spinor_gamma5(WCMG_F64, xo, g.Vh, c->st);
+      }
       spinor_from_internal(WCMG_F64, xs, xe, xo, g, false, c->st);
       if (stats) stats[r] = s;
       if (s.status != WCMG_OK && worst == WCMG_OK) worst = s.status;
@@ -596,6 +714,34 @@ int wcmg_solve(void* ctx, int lat, int solver, void* x, const void* b, int nrhs,
   if (rc != WCMG_OK) return rc;
   if (worst != WCMG_OK) return set_err(worst, "solver did not reach the tolerance for every right-hand side");
   return WCMG_OK;
+}
+
+int wcmg_solve(void* ctx, int lat, int solver, void* x, const void* b, int nrhs, double tol, wcmg_stats* stats) {
+  return solve_impl(ctx, lat, solver, x, b, nrhs, tol, stats, false);
+}
+
+int wcmg_solve_dag(void* ctx, int lat, int solver, void* x, const void* b, int nrhs, double tol,
+                   wcmg_stats* stats) {
+  return solve_impl(ctx, lat, solver, x, b, nrhs, tol, stats, true);
+}
+
+int wcmg_force(void* ctx, int lat, void* dU, const void* psi, const void* lam, int nrhs, int include_clover) {
+  Ctx* c = as_ctx(ctx);
+  if (int r = check_lat(c, lat)) return r;
+  CHECK(dU && psi && lam, WCMG_EINVAL, "null buffer");
+  CHECK(nrhs >= 1, WCMG_EINVAL, "nrhs must be >= 1");
+  LatticeState& L = *c->lats[lat];
+  CHECK(L.F.have_gauge, WCMG_ESTATE, "gauge field not set");
+  if (include_clover)
+    CHECK(L.F.have_clover && L.F.clover_from_u, WCMG_ESTATE,
+          "the clover force needs a clover term computed from the gauge field");
+  return guarded([&] {
+    const Geom& g = L.F.g;
+    const bool clov = include_clover && L.F.csw != 0.0;
+    const CloverCoef cc = clover_coef(L.F.csw);
+    void* z = clov ? c->scratch_buf(52, (size_t)g.V * 54 * 16) : nullptr;
+    force_compute(dU, psi, lam, nrhs, L.F.gauge[WCMG_F64].p, g, clov ? &cc : nullptr, z, c->st);
+  });
 }
 
 int wcmg_dot(void* ctx, int prec, const void* x, const void* y, long n, double* out) {

@@ -23,6 +23,19 @@
 
 namespace wcmg {
 
+// The direction terms are pure arithmetic, so the compiler is free to sink
+// them all below the last load, which keeps every direction's spinor and
+// link live at once (hundreds of registers, one wave per SIMD).  An empty
+// asm that reads and redefines the accumulator after each direction forces
+// that direction's arithmetic to complete there, so its operands die; loads
+// of the next direction may still be issued early.  The arithmetic and its
+// order are unchanged.
+template <typename C>
+__device__ __forceinline__ void pin_acc(cpx<C> acc[12]) {
+#pragma unroll
+  for (int k = 0; k < 12; ++k) asm volatile("" : "+v"(acc[k].r), "+v"(acc[k].i));
+}
+
 template <typename S, int MU>
 __device__ __forceinline__ void hop_mu(const DslashArgs& a, int p, int i, const int c[4],
                                        cpx<typename Compute<S>::T> acc[12]) {
@@ -46,6 +59,7 @@ __device__ __forceinline__ void hop_mu(const DslashArgs& a, int p, int i, const 
       }
     }
     accumulate<C, MU, false>(acc, hu);
+    pin_acc(acc);
   }
   // backward: (1 + gamma_mu) U_mu(x - mu)^dag in(x - mu)
   {
@@ -64,6 +78,7 @@ __device__ __forceinline__ void hop_mu(const DslashArgs& a, int p, int i, const 
       }
     }
     accumulate<C, MU, true>(acc, hu);
+    pin_acc(acc);
   }
 }
 

@@ -45,6 +45,10 @@ void clover_compute(void* clov64, const void* gauge64, const Geom& g, double m0,
                     int* flag, hipStream_t st);
 // packed A and A^-1 from a canonical complex128 [V][12][12] matrix
 void clover_from_matrix(void* clov64, const void* A, const Geom& g, int* flag, hipStream_t st);
+// gauge-link gradient from (x, lambda) pairs in canonical layout; cc = null
+// skips the clover part; zbuf holds 6*9*V complex doubles
+void force_compute(void* G, const void* x, const void* lam, int nrhs, const void* gauge64, const Geom& g,
+                   const CloverCoef* cc, void* zbuf, hipStream_t st);
 void reals_convert(int prec_dst, void* dst, const double* src, size_t n, hipStream_t st);
 
 // ------------------------------------------------------------ BLAS-1
@@ -127,6 +131,28 @@ void launch_block_orthonormalize(void* vecs, int nvec, const Geom& g, const Bloc
 // coarse build: nine direction buckets of the D_p hop of u = A^-1 v (both parities)
 void launch_hop_split(void* const* buckets /*9 full spinors F64*/, const void* v, const void* u,
                       const void* gauge64, const Geom& g, const BlockGeom& bg, hipStream_t st);
+
+// ------------------------------------------------------------ deeper levels
+// transfer between coarse level l and l+1 (vectors [site][nf], V: nvec such
+// vectors with stride vstride; members [nblocks][bvol], blk [nsites])
+void launch_ctr_restrict(int prec, void* out, size_t out_site_stride, size_t out_rhs_stride, const void* in,
+                         size_t in_rhs_stride, const void* V, size_t vstride, const int* members, int nblocks,
+                         int bvol, int nf, int nvec, int nrhs, hipStream_t st);
+void launch_ctr_prolong(int prec, void* out, size_t out_rhs_stride, const void* in, size_t in_rhs_stride,
+                        const void* V, size_t vstride, const int* blk, int nsites, int nf, int nvec, int nrhs,
+                        hipStream_t st);
+// block x chirality Gram-Schmidt (twice) of FP64 level vectors in place
+void launch_ctr_block_ortho(void* V, size_t vstride, const int* members, int nblocks, int bvol, int nf, int nvec,
+                            int* flag, hipStream_t st);
+// nine direction buckets of the level-l hop of u (Yhop [site][8][n][n] column-major, FP64), bucket 0 += v
+void launch_chop_split(void* const* buckets, const void* v, const void* u, const void* Yhop, const int* nbr,
+                       const int* blk, int nsites, int n, hipStream_t st);
+void launch_unit_fill(void* e, int nsites, int n, int j, hipStream_t st);
+// dense FP64 inverse of the full stencil Y9 into the augmented M [N][2N] (right half)
+void dense_inverse_build(void* M, const void* Y9, const int* nbr, int nsites, int n, int* piv, void* pval, void* f,
+                         int* flag, hipStream_t st);
+// x = M^-1 b (b, x in prec F64 or F32)
+void dense_inverse_apply(int prec, const void* M, int N, const void* b, void* x, hipStream_t st);
 
 // ------------------------------------------------------------ coarse level
 struct CoarseGeom {

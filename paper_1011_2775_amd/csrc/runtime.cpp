@@ -243,7 +243,7 @@ void CoarseOp::Dp(void* out, const void* in) {
 
 void CoarseOp::Dr(void* out, const void* y) {
   w->ensure(nall() * csize());
-  const int id = 20 + pi();
+  const int id = timer_base + pi();
   hipEvent_t e = nullptr;
   if (timer && timer->on) timer->begin(id, &e);
   launch_coarse_hop(prec, w->t1.p, y, nullptr, C->Yt[pi()].p, nullptr, 0, 1.0, 1, C->cg, C->nbr.as<int>(), st);

@@ -51,6 +51,7 @@ struct Ctx;
 struct FineFields {
   Geom g;
   bool have_gauge = false, have_clover = false;
+  bool clover_from_u = false;  // clover computed from the gauge field (not a caller matrix)
   double m0 = 0.0, csw = 0.0;
   DBuf gauge[3];   // per precision
   DBuf clov[3];    // per precision, packed A and A^-1
@@ -107,7 +108,8 @@ struct CoarseOp {
   int prec;     // F64 or F32
   CoarseWork* w;
   hipStream_t st;
-  KernelTimer* timer = nullptr;  // times the red-black hop launches (ids 20 F64, 21 F32)
+  KernelTimer* timer = nullptr;  // times the red-black hop launches (ids timer_base + 0 F64, + 1 F32)
+  int timer_base = 20;
   int pi() const { return prec == WCMG_F64 ? 0 : 1; }
   size_t csize() const { return prec == WCMG_F64 ? 16 : 8; }
   size_t nall() const { return (size_t)C->cg.V * C->cg.n; }
@@ -128,6 +130,20 @@ struct FineTransfer {
   DBuf v64, v32;  // block-orthonormalised copies
 };
 
+// transfer between coarse level l (>= 1) and level l+1; vectors in the
+// finer level's internal site order, [k][site][nf]
+struct CoarseTransfer {
+  BlockGeom bg{};  // blocking of the finer coarse lattice
+  int nvec = 0;    // vectors (Nv of the coarser level)
+  int nf = 0;      // components per site of the finer level
+  int nsites = 0;  // sites of the finer level
+  bool have_vecs = false, orth = false;
+  DBuf raw, v64, v32;
+  DBuf blk;      // int [nsites]: coarser internal site of each finer internal site
+  DBuf members;  // int [coarser sites][bvol]: finer internal sites of each block
+  size_t vstride() const { return (size_t)nsites * nf; }
+};
+
 struct MGSolver;
 
 struct LatticeState {
@@ -137,6 +153,17 @@ struct LatticeState {
   wcmg_mg_params params{};
   FineTransfer T0;
   std::vector<std::unique_ptr<CoarseLevel>> levels;  // levels[0] = coarse level 1
+  std::vector<std::unique_ptr<CoarseTransfer>> ctr;  // ctr[0]: coarse level 1 -> level 2
+  DBuf dense;       // coarsest level: augmented [N][2N] FP64, right half = inverse (coarsest == 1)
+  int dense_n = 0;  // N (0: not built)
+  void clear_hierarchy() {
+    T0 = FineTransfer();
+    levels.clear();
+    ctr.clear();
+    dense.release();
+    dense_n = 0;
+    mg.reset();
+  }
 };
 
 // flexible restarted GCR on flat vectors of n complex elements in `prec`
@@ -150,6 +177,7 @@ struct GcrSpace {
   void ensure(int restart);
 };
 constexpr int kMaxRestart = 64;
+constexpr int kMaxDense = 16384;  // largest coarsest dimension for the dense solve
 // ------------------------------------------------------------------ context
 struct Ctx {
   hipStream_t st = nullptr;

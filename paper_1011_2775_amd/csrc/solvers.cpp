@@ -121,6 +121,12 @@ KrylovResult gcr(Ctx& c, GcrSpace& S, const OpFn& A, const OpFn* K, void* x, con
 }
 
 // BiCGStab (van der Vorst); s is formed in place of r.
+// relative size of <rhat, r> or <rhat, A p> below which BiCGStab restarts
+// (exact breakdown only: restarting on near-breakdown made the iteration
+// diverge on operators whose spectrum surrounds the origin)
+constexpr double kBicgBreakdown = 1e-30;
+constexpr int kBicgMaxRestarts = 1000;
+
 KrylovResult bicgstab(Ctx& c, int prec, size_t n, const OpFn& A, void* x, const void* b, double tol,
                       double target_norm, int maxiter) {
   const size_t bytes = n * (prec == WCMG_F64 ? 16 : 8);
@@ -191,9 +197,9 @@ KrylovResult bicgstab(Ctx& c, int prec, size_t n, const OpFn& A, void* x, const 
     const double* d = R.fetch(2);
     double rv_r = d[0], rv_i = d[1];
     const double scale = std::sqrt(rn2) * rhat_n;
-    if (std::hypot(rv_r, rv_i) <= 1e-30 * scale || std::hypot(rn_r, rn_i) <= 1e-30 * scale) {
-      // breakdown: restart from the current iterate
-      if (++restarts > 1000) {
+    if (std::hypot(rv_r, rv_i) <= kBicgBreakdown * scale || std::hypot(rn_r, rn_i) <= kBicgBreakdown * scale) {
+      // breakdown: restart from the current iterate with a fresh shadow residual
+      if (++restarts > kBicgMaxRestarts) {
         res.status = WCMG_EBREAKDOWN;
         break;
       }
@@ -233,16 +239,22 @@ KrylovResult bicgstab(Ctx& c, int prec, size_t n, const OpFn& A, void* x, const 
 }
 
 // ---------------------------------------------------------------------------
-// multigrid preconditioner (two levels: fine Wilson-clover, coarse stencil)
+// multigrid preconditioner: fine Wilson-clover level and one or two coarse
+// stencil levels, recursive flexible GCR ("Implementation" paragraph)
 // ---------------------------------------------------------------------------
 struct MGSolver {
   Ctx& c;
   LatticeState& L;
   int sp;  // precision of the fine part of the preconditioner
-  int cp;  // precision of the coarse level
+  int cp;  // precision of the coarse levels
   DBuf r_s, e_s, res_s, Ar_s;
-  DBuf cb, cc, cbr, cy;
-  GcrSpace cspace{};
+  struct Level {
+    DBuf cb, cc, cbr, cy;       // right-hand side, solution, reduced forms
+    DBuf rfull, e, res, Ar;     // preconditioner and smoother work of this level
+    GcrSpace space{};
+    long calls = 0, iters = 0;
+  };
+  std::vector<Level> lv;  // lv[li]: coarse level li + 1
   long calls = 0, iters = 0;
 
   MGSolver(Ctx& ctx, LatticeState& lat) : c(ctx), L(lat) {
@@ -254,38 +266,93 @@ struct MGSolver {
     e_s.alloc(hb);
     res_s.alloc(hb);
     Ar_s.alloc(hb);
-    CoarseLevel& C = *L.levels[0];
-    size_t cs = (cp == WCMG_F64 ? 16 : 8);
-    size_t nall = (size_t)C.cg.V * C.cg.n;
-    cb.alloc(nall * cs);
-    cc.alloc(nall * cs);
-    cbr.alloc(nall * cs);
-    cy.alloc(nall * cs);
-    cspace.prec = cp;
-    cspace.n = C.cg.split ? (size_t)C.cg.Vh * C.cg.n : nall;
-    cspace.bytes = cspace.n * cs;
+    const size_t cs = (cp == WCMG_F64 ? 16 : 8);
+    lv.resize(L.params.nlevels);
+    for (size_t li = 0; li < lv.size(); ++li) {
+      CoarseLevel& C = *L.levels[li];
+      Level& V = lv[li];
+      const size_t nall = (size_t)C.cg.V * C.cg.n;
+      for (DBuf* b : {&V.cb, &V.cc, &V.cbr, &V.cy, &V.rfull, &V.e, &V.res, &V.Ar}) b->alloc(nall * cs);
+      V.space.prec = cp;
+      V.space.n = C.cg.split ? (size_t)C.cg.Vh * C.cg.n : nall;
+      V.space.bytes = V.space.n * cs;
+    }
   }
 
+  int nlev() const { return L.params.nlevels; }
   const void* vecs(int prec) const { return prec == WCMG_F64 ? L.T0.v64.p : L.T0.v32.p; }
+  CoarseOp cop(int li) {
+    CoarseOp o{L.levels[li].get(), cp, &c.cw[cp == WCMG_F64 ? 0 : 1], c.st, &c.timer};
+    o.timer_base = 20 + 2 * li;
+    return o;
+  }
 
-  void coarse_solve(void* out, void* in) {
-    CoarseLevel& C = *L.levels[0];
-    CoarseOp cop{&C, cp, &c.cw[cp == WCMG_F64 ? 0 : 1], c.st, &c.timer};
+  // approximate solution of coarse level li + 1: out = Dhat^-1 in (full vectors)
+  void coarse_solve(int li, void* out, void* in) {
+    CoarseLevel& C = *L.levels[li];
+    Level& V = lv[li];
+    CoarseOp op = cop(li);
     const wcmg_mg_params& p = L.params;
+    const bool last = li + 1 == nlev();
+    ++V.calls;
+    if (last && p.coarsest == 1) {
+      dense_inverse_apply(cp, L.dense.p, L.dense_n, in, out, c.st);
+      V.iters += 1;
+      return;
+    }
+    OpFn Kf = [this, li](void* o, const void* i) { precondition_coarse(li, o, i); };
+    const OpFn* K = (!last && C.cg.split) ? &Kf : nullptr;
     KrylovResult kr;
     if (C.cg.split) {
-      cop.reduced_source(cbr.p, in);
-      double bn = std::sqrt(norm2(c, cp, cbr.p, cop.neven()));
-      OpFn A = [&](void* o, const void* i) { cop.Dr(o, i); };
-      kr = gcr(c, cspace, A, nullptr, cy.p, cbr.p, true, p.tol[0], bn, p.restart[0], p.max_iter[0]);
-      cop.reconstruct(out, cy.p, in);
+      op.reduced_source(V.cbr.p, in);
+      double bn = std::sqrt(norm2(c, cp, V.cbr.p, op.neven()));
+      OpFn A = [&](void* o, const void* i) { op.Dr(o, i); };
+      kr = gcr(c, V.space, A, K, V.cy.p, V.cbr.p, true, p.tol[li], bn, p.restart[li], p.max_iter[li]);
+      op.reconstruct(out, V.cy.p, in);
     } else {
-      double bn = std::sqrt(norm2(c, cp, in, cop.nall()));
-      OpFn A = [&](void* o, const void* i) { cop.Dfull(o, i); };
-      kr = gcr(c, cspace, A, nullptr, out, in, true, p.tol[0], bn, p.restart[0], p.max_iter[0]);
+      double bn = std::sqrt(norm2(c, cp, in, op.nall()));
+      OpFn A = [&](void* o, const void* i) { op.Dfull(o, i); };
+      kr = gcr(c, V.space, A, nullptr, out, in, true, p.tol[li], bn, p.restart[li], p.max_iter[li]);
     }
-    ++calls;
-    iters += kr.iters;
+    V.iters += kr.iters;
+  }
+
+  // MR smoothing of e towards D_r e = r on the even half of n elements
+  template <typename DrFn>
+  void mr_smooth(const DrFn& Dr, int prec, void* e, const void* r, void* res, void* Ar, size_t n) {
+    const int nu = L.params.nu_post;
+    if (nu <= 0) return;
+    hipStream_t st = c.st;
+    Dr(Ar, e);
+    blas_copy(prec, res, r, n, st);
+    blas_axpby(prec, -1.0, 0.0, Ar, 1.0, 0.0, res, n, st);
+    // alpha = <Ar, r> / ||Ar||^2 stays on the device: no host round trip
+    for (int i = 0; i < nu; ++i) {
+      Dr(Ar, res);
+      blas_cdot_norm(prec, Ar, res, n, c.red.out(), st);
+      blas_mr_update_dev(prec, c.red.dres(), e, res, Ar, n, st);
+    }
+  }
+
+  // K_li(r_e) on coarse level li + 1: even part of P (next-level solve) R (r_e, 0), then MR
+  void precondition_coarse(int li, void* z, const void* r) {
+    hipStream_t st = c.st;
+    CoarseLevel& C = *L.levels[li];
+    CoarseTransfer& T = *L.ctr[li];
+    CoarseLevel& Cn = *L.levels[li + 1];
+    Level& V = lv[li];
+    Level& W = lv[li + 1];
+    CoarseOp op = cop(li);
+    const size_t ne = op.neven(), na = op.nall();
+    const void* P = cp == WCMG_F64 ? T.v64.p : T.v32.p;
+    blas_copy(cp, V.rfull.p, r, ne, st);
+    blas_zero(cp, (char*)V.rfull.p + ne * op.csize(), na - ne, st);
+    launch_ctr_restrict(cp, W.cb.p, Cn.cg.n, 0, V.rfull.p, 0, P, T.vstride(), T.members.as<int>(), Cn.cg.V,
+                        T.bg.bvol, C.cg.n, T.nvec, 1, st);
+    coarse_solve(li + 1, W.cc.p, W.cb.p);
+    launch_ctr_prolong(cp, V.e.p, 0, W.cc.p, 0, P, T.vstride(), T.blk.as<int>(), C.cg.V, C.cg.n, T.nvec, 1, st);
+    mr_smooth([&](void* o, const void* i) { op.Dr(o, i); }, cp, V.e.p, r, V.res.p, V.Ar.p, ne);
+    blas_copy(cp, z, V.e.p, ne, st);
   }
 
   // K(r_e): even part of P (coarse solve) R (r_e, 0), then MR smoothing on D_r
@@ -295,36 +362,87 @@ struct MGSolver {
     FineOp op{&c, &L.F, sp, &c.fw[sp], st};
     const size_t n = (size_t)12 * g.Vh;
     CoarseLevel& C = *L.levels[0];
+    Level& V = lv[0];
     spinor_convert(sp, r_s.p, WCMG_F64, r64, g.Vh, st);
-    launch_restrict(sp, cb.p, C.cg.n, 1, r_s.p, vecs(sp), L.T0.nvec, 0, g, L.T0.bg, false, st);
-    coarse_solve(cc.p, cb.p);
-    launch_prolong(sp, e_s.p, cc.p, vecs(sp), L.T0.nvec, 0, g, L.T0.bg, st);
-    const int nu = L.params.nu_post;
-    if (nu > 0) {
-      op.Dr(Ar_s.p, e_s.p);
-      blas_copy(sp, res_s.p, r_s.p, n, st);
-      blas_axpby(sp, -1.0, 0.0, Ar_s.p, 1.0, 0.0, res_s.p, n, st);
-      // alpha = <Ar, r> / ||Ar||^2 stays on the device: no host round trip
-      for (int i = 0; i < nu; ++i) {
-        op.Dr(Ar_s.p, res_s.p);
-        blas_cdot_norm(sp, Ar_s.p, res_s.p, n, c.red.out(), st);
-        blas_mr_update_dev(sp, c.red.dres(), e_s.p, res_s.p, Ar_s.p, n, st);
-      }
-    }
+    launch_restrict(sp, V.cb.p, C.cg.n, 1, r_s.p, vecs(sp), L.T0.nvec, 0, g, L.T0.bg, false, st);
+    coarse_solve(0, V.cc.p, V.cb.p);
+    launch_prolong(sp, e_s.p, V.cc.p, vecs(sp), L.T0.nvec, 0, g, L.T0.bg, st);
+    mr_smooth([&](void* o, const void* i) { op.Dr(o, i); }, sp, e_s.p, r_s.p, res_s.p, Ar_s.p, n);
     spinor_convert(WCMG_F64, z64, sp, e_s.p, g.Vh, st);
+    ++calls;
   }
 };
 
 static void require_hierarchy(LatticeState& L) {
   if (!L.have_params) fail(WCMG_ESTATE, "multigrid parameters not set");
-  if (L.levels.empty() || !L.levels[0]->built) fail(WCMG_ESTATE, "coarse operator not built");
+  const int nl = L.params.nlevels;
+  if ((int)L.levels.size() < nl) fail(WCMG_ESTATE, "coarse operator not built");
+  for (int l = 0; l < nl; ++l)
+    if (!L.levels[l]->built) fail(WCMG_ESTATE, "coarse operator not built");
+  if (L.params.coarsest == 1 && L.dense_n == 0) fail(WCMG_ESTATE, "coarsest dense inverse not built");
 }
 
 // ---------------------------------------------------------------------------
 // setup: inverse iteration on D_p with Rayleigh-quotient monitoring
 // ---------------------------------------------------------------------------
+// inverse iteration on the level-1 Dhat_p = Dhat X^-1 for the level-2 vectors
+static void mg_setup_null_vectors_level1(Ctx& c, LatticeState& L) {
+  const wcmg_mg_params& p = L.params;
+  if (p.nlevels < 2) fail(WCMG_EINVAL, "the parameters have a single coarse level");
+  if (L.levels.empty() || !L.levels[0]->built) fail(WCMG_ESTATE, "first coarse level not built");
+  hipStream_t st = c.st;
+  CoarseLevel& C1 = *L.levels[0];
+  const int nvec = p.nvec[1];
+  const size_t n = (size_t)C1.cg.V * C1.cg.n;
+  CoarseOp cop{&C1, WCMG_F64, &c.cw[0], st};
+  OpFn Dp = [&](void* o, const void* i) { cop.Dp(o, i); };
+  if (L.ctr.empty()) L.ctr.emplace_back(new CoarseTransfer());
+  CoarseTransfer& T = *L.ctr[0];
+  T.nf = C1.cg.n;
+  T.nsites = C1.cg.V;
+  T.raw.alloc((size_t)nvec * n * 16);
+  void* v = c.scratch_buf(9, n * 16);
+  void* x = c.scratch_buf(10, n * 16);
+  void* w = c.scratch_buf(11, n * 16);
+  GcrSpace S{WCMG_F64, n, n * 16, {}, {}, DBuf()};
+  std::vector<const void*> found;
+  std::vector<double> cf(2 * nvec);
+  for (int k = 0; k < nvec; ++k) {
+    random_coarse_vector(v, p.seed, k, 1, C1.perm.as<int>(), C1.cg.V, C1.cg.n, st);
+    double rho_old = -1.0;
+    for (int step = 0; step < p.setup_max_steps; ++step) {
+      gcr(c, S, Dp, nullptr, x, v, true, 0.0, 1.0, p.setup_relax, p.setup_relax, true);
+      blas_copy(WCMG_F64, v, x, n, st);
+      for (int pass = 0; pass < 2 && k > 0; ++pass) {
+        blas_multi_cdot(WCMG_F64, found.data(), k, v, n, c.red.out(), st);
+        const double* d = c.red.fetch(2 * k);
+        for (int j = 0; j < 2 * k; ++j) cf[j] = -d[j];
+        blas_multi_axpy(WCMG_F64, cf.data(), found.data(), k, v, n, st);
+      }
+      double nv = std::sqrt(norm2(c, WCMG_F64, v, n));
+      if (!(nv > 0.0) || !finite(nv)) fail(WCMG_ENAN, "setup vector vanished");
+      blas_axpby(WCMG_F64, 1.0 / nv, 0.0, v, 0.0, 0.0, v, n, st);
+      Dp(w, v);
+      double rho = norm2(c, WCMG_F64, w, n);
+      if (rho_old > 0.0 && std::fabs(rho - rho_old) / rho < p.setup_rq_tol) break;
+      rho_old = rho;
+    }
+    void* dst = (char*)T.raw.p + (size_t)k * n * 16;
+    blas_copy(WCMG_F64, dst, v, n, st);
+    found.push_back(dst);
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  T.nvec = nvec;
+  T.have_vecs = true;
+  T.orth = false;
+  if (L.levels.size() > 1) L.levels[1]->built = false;
+  L.dense_n = 0;
+  L.mg.reset();
+}
+
 void mg_setup_null_vectors(Ctx& c, LatticeState& L, int level) {
-  if (level != 0) fail(WCMG_EINVAL, "null-vector setup on coarse levels is not available");
+  if (level == 1) return mg_setup_null_vectors_level1(c, L);
+  if (level != 0) fail(WCMG_EINVAL, "level out of range");
   if (!L.F.have_clover) fail(WCMG_ESTATE, "clover not set");
   if (!L.have_params) fail(WCMG_ESTATE, "multigrid parameters not set");
   const wcmg_mg_params& p = L.params;
@@ -402,8 +520,143 @@ static void build_coarse_tables(CoarseLevel& C) {
   HIPCHK(hipMemcpy(C.perm.p, C.perm_host.data(), (size_t)V * sizeof(int), hipMemcpyHostToDevice));
 }
 
+// X, the eight hops, X^-1, Ytilde = Y X^-1 and the FP32 copies from Y9
+static void finalize_coarse(Ctx& c, CoarseLevel& C, int* flag) {
+  hipStream_t st = c.st;
+  const int n = C.cg.n, V = C.cg.V;
+  const size_t nn = (size_t)n * n;
+  int hflag[2] = {0, 0};
+  // split into X and the eight hops, invert X, form Ytilde = Y X^-1
+  C.X[0].alloc((size_t)V * nn * 16);
+  C.Yhop[0].alloc((size_t)V * 8 * nn * 16);
+  HIPCHK(hipMemcpy2DAsync(C.X[0].p, nn * 16, C.Y9.p, 9 * nn * 16, nn * 16, V, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpy2DAsync(C.Yhop[0].p, 8 * nn * 16, (char*)C.Y9.p + nn * 16, 9 * nn * 16, 8 * nn * 16, V,
+                          hipMemcpyDeviceToDevice, st));
+  C.Xinv[0].alloc((size_t)V * nn * 16);
+  HIPCHK(hipMemcpyAsync(C.Xinv[0].p, C.X[0].p, (size_t)V * nn * 16, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemsetAsync(flag, 0, 64, st));
+  launch_batched_inverse(C.Xinv[0].as<double>(), V, n, flag, st);
+  C.Yt[0].alloc((size_t)V * 8 * nn * 16);
+  launch_coarse_right_mul(C.Yt[0].as<double>(), C.Yhop[0].as<double>(), C.Xinv[0].as<double>(), C.nbr.as<int>(), V,
+                          n, st);
+  // FP32 copies for the mixed-precision cycle
+  C.X[1].alloc((size_t)V * nn * 8);
+  C.Xinv[1].alloc((size_t)V * nn * 8);
+  C.Yhop[1].alloc((size_t)V * 8 * nn * 8);
+  C.Yt[1].alloc((size_t)V * 8 * nn * 8);
+  launch_reals_convert(WCMG_F32, C.X[1].p, C.X[0].as<double>(), (size_t)V * nn * 2, st);
+  launch_reals_convert(WCMG_F32, C.Xinv[1].p, C.Xinv[0].as<double>(), (size_t)V * nn * 2, st);
+  launch_reals_convert(WCMG_F32, C.Yhop[1].p, C.Yhop[0].as<double>(), (size_t)V * 8 * nn * 2, st);
+  launch_reals_convert(WCMG_F32, C.Yt[1].p, C.Yt[0].as<double>(), (size_t)V * 8 * nn * 2, st);
+  HIPCHK(hipMemcpyAsync(hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (hflag[0]) fail(WCMG_ERANK, "singular coarse site block");
+}
+
+// dense FP64 inverse of the full operator of coarse level index li (the coarsest)
+static void build_dense(Ctx& c, LatticeState& L, int li) {
+  CoarseLevel& C = *L.levels[li];
+  const int N = C.cg.V * C.cg.n;
+  if (N > kMaxDense) fail(WCMG_EDIM, "coarsest level too large for the dense solve");
+  hipStream_t st = c.st;
+  L.dense.alloc((size_t)N * 2 * N * 16);
+  int* piv = (int*)c.scratch_buf(13, 64);
+  void* pval = c.scratch_buf(14, 64);
+  void* f = c.scratch_buf(15, (size_t)N * 16);
+  int* flag = (int*)c.scratch_buf(12, 64);
+  HIPCHK(hipMemsetAsync(flag, 0, 64, st));
+  dense_inverse_build(L.dense.p, C.Y9.p, C.nbr.as<int>(), C.cg.V, C.cg.n, piv, pval, f, flag, st);
+  int hflag = 0;
+  HIPCHK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (hflag) fail(WCMG_ERANK, "coarsest operator is singular");
+  L.dense_n = N;
+}
+
+// level-2 operator R2 Dhat_p P2 from the level-1 stencil (direction resolved)
+static void mg_build_coarse_level1(Ctx& c, LatticeState& L) {
+  const wcmg_mg_params& p = L.params;
+  if (p.nlevels < 2) fail(WCMG_EINVAL, "the parameters have a single coarse level");
+  if (L.levels.empty() || !L.levels[0]->built) fail(WCMG_ESTATE, "first coarse level not built");
+  if (L.ctr.empty() || !L.ctr[0]->have_vecs) fail(WCMG_ESTATE, "level-1 null vectors not set");
+  hipStream_t st = c.st;
+  CoarseLevel& C1 = *L.levels[0];
+  CoarseTransfer& T = *L.ctr[0];
+  T.bg = make_block_geom(C1.cg.L, p.block[1]);
+  T.nvec = p.nvec[1];
+  T.nf = C1.cg.n;
+  T.nsites = C1.cg.V;
+  if (L.levels.size() < 2) L.levels.emplace_back(new CoarseLevel());
+  CoarseLevel& C2 = *L.levels[1];
+  C2.bg = T.bg;
+  C2.nvec = T.nvec;
+  C2.cg = make_coarse_geom(T.bg, T.nvec);
+  build_coarse_tables(C2);
+  // block membership of the level-1 sites (internal orders on both levels)
+  const int V1 = C1.cg.V, V2 = C2.cg.V, bvol = T.bg.bvol;
+  std::vector<int> lex1(V1), blk(V1), members((size_t)V2 * bvol), fill(V2, 0);
+  for (int l = 0; l < V1; ++l) lex1[C1.perm_host[l]] = l;
+  for (int i = 0; i < V1; ++i) {
+    int l = lex1[i];
+    int x[4];
+    for (int k = 0; k < 4; ++k) {
+      x[k] = l % C1.cg.L[k];
+      l /= C1.cg.L[k];
+    }
+    const int b2 = (((x[3] / T.bg.b[3]) * T.bg.nb[2] + x[2] / T.bg.b[2]) * T.bg.nb[1] + x[1] / T.bg.b[1]) * T.bg.nb[0] +
+                   x[0] / T.bg.b[0];
+    const int c2 = C2.perm_host[b2];
+    blk[i] = c2;
+    members[(size_t)c2 * bvol + fill[c2]++] = i;
+  }
+  T.blk.alloc(V1 * sizeof(int));
+  T.members.alloc(members.size() * sizeof(int));
+  HIPCHK(hipMemcpy(T.blk.p, blk.data(), V1 * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(T.members.p, members.data(), members.size() * sizeof(int), hipMemcpyHostToDevice));
+  // P2: block x chirality orthonormalisation
+  const size_t vbytes = T.vstride() * 16;
+  T.v64.alloc((size_t)T.nvec * vbytes);
+  HIPCHK(hipMemcpyAsync(T.v64.p, T.raw.p, (size_t)T.nvec * vbytes, hipMemcpyDeviceToDevice, st));
+  int* flag = (int*)c.scratch_buf(12, 64);
+  HIPCHK(hipMemsetAsync(flag, 0, 64, st));
+  launch_ctr_block_ortho(T.v64.p, T.vstride(), T.members.as<int>(), V2, bvol, T.nf, T.nvec, flag, st);
+  int hflag = 0;
+  HIPCHK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (hflag) fail(WCMG_ERANK, "level-1 null vectors are linearly dependent on a block");
+  T.v32.alloc((size_t)T.nvec * T.vstride() * 8);
+  launch_reals_convert(WCMG_F32, T.v32.p, T.v64.as<double>(), (size_t)T.nvec * T.vstride() * 2, st);
+  T.orth = true;
+  // Y9 column by column
+  const int n1 = C1.cg.n, n2 = C2.cg.n;
+  const size_t nn2 = (size_t)n2 * n2;
+  C2.Y9.alloc((size_t)V2 * 9 * nn2 * 16);
+  const size_t b1 = (size_t)V1 * n1 * 16;
+  void* bucket[9];
+  for (int k = 0; k < 9; ++k) bucket[k] = c.scratch_buf(20 + k, b1);
+  void* vcol = c.scratch_buf(30, b1);
+  void* u = c.scratch_buf(31, b1);
+  void* e = c.scratch_buf(32, (size_t)V2 * n2 * 16);
+  for (int j = 0; j < n2; ++j) {
+    launch_unit_fill(e, V2, n2, j, st);
+    launch_ctr_prolong(WCMG_F64, vcol, 0, e, 0, T.v64.p, T.vstride(), T.blk.as<int>(), V1, n1, T.nvec, 1, st);
+    launch_coarse_local(WCMG_F64, u, vcol, C1.Xinv[0].p, -1, C1.cg, st);
+    launch_chop_split(bucket, vcol, u, C1.Yhop[0].p, C1.nbr.as<int>(), T.blk.as<int>(), V1, n1, st);
+    for (int slot = 0; slot < 9; ++slot) {
+      void* out = (char*)C2.Y9.p + ((size_t)slot * n2 + j) * n2 * 16;
+      launch_ctr_restrict(WCMG_F64, out, 9 * nn2, 0, bucket[slot], 0, T.v64.p, T.vstride(), T.members.as<int>(), V2,
+                          bvol, n1, T.nvec, 1, st);
+    }
+  }
+  finalize_coarse(c, C2, flag);
+  C2.built = true;
+  if (p.coarsest == 1) build_dense(c, L, 1);
+  L.mg.reset();
+}
+
 void mg_build_coarse(Ctx& c, LatticeState& L, int level) {
-  if (level != 0) fail(WCMG_EINVAL, "coarse build beyond the first level is not available");
+  if (level == 1) return mg_build_coarse_level1(c, L);
+  if (level != 0) fail(WCMG_EINVAL, "level out of range");
   if (!L.F.have_clover) fail(WCMG_ESTATE, "clover not set");
   if (!L.have_params) fail(WCMG_ESTATE, "multigrid parameters not set");
   if (!L.T0.have_vecs) fail(WCMG_ESTATE, "null vectors not set");
@@ -462,32 +715,9 @@ void mg_build_coarse(Ctx& c, LatticeState& L, int level) {
         launch_restrict(WCMG_F64, out, 9 * nn, 1, (char*)bucket[slot] + hb64, T.v64.p, nvec, 1, g, T.bg, true, st);
       }
     }
-  // split into X and the eight hops, invert X, form Ytilde = Y X^-1
-  C.X[0].alloc((size_t)V * nn * 16);
-  C.Yhop[0].alloc((size_t)V * 8 * nn * 16);
-  HIPCHK(hipMemcpy2DAsync(C.X[0].p, nn * 16, C.Y9.p, 9 * nn * 16, nn * 16, V, hipMemcpyDeviceToDevice, st));
-  HIPCHK(hipMemcpy2DAsync(C.Yhop[0].p, 8 * nn * 16, (char*)C.Y9.p + nn * 16, 9 * nn * 16, 8 * nn * 16, V,
-                          hipMemcpyDeviceToDevice, st));
-  C.Xinv[0].alloc((size_t)V * nn * 16);
-  HIPCHK(hipMemcpyAsync(C.Xinv[0].p, C.X[0].p, (size_t)V * nn * 16, hipMemcpyDeviceToDevice, st));
-  HIPCHK(hipMemsetAsync(flag, 0, 64, st));
-  launch_batched_inverse(C.Xinv[0].as<double>(), V, n, flag, st);
-  C.Yt[0].alloc((size_t)V * 8 * nn * 16);
-  launch_coarse_right_mul(C.Yt[0].as<double>(), C.Yhop[0].as<double>(), C.Xinv[0].as<double>(), C.nbr.as<int>(), V,
-                          n, st);
-  // FP32 copies for the mixed-precision cycle
-  C.X[1].alloc((size_t)V * nn * 8);
-  C.Xinv[1].alloc((size_t)V * nn * 8);
-  C.Yhop[1].alloc((size_t)V * 8 * nn * 8);
-  C.Yt[1].alloc((size_t)V * 8 * nn * 8);
-  launch_reals_convert(WCMG_F32, C.X[1].p, C.X[0].as<double>(), (size_t)V * nn * 2, st);
-  launch_reals_convert(WCMG_F32, C.Xinv[1].p, C.Xinv[0].as<double>(), (size_t)V * nn * 2, st);
-  launch_reals_convert(WCMG_F32, C.Yhop[1].p, C.Yhop[0].as<double>(), (size_t)V * 8 * nn * 2, st);
-  launch_reals_convert(WCMG_F32, C.Yt[1].p, C.Yt[0].as<double>(), (size_t)V * 8 * nn * 2, st);
-  HIPCHK(hipMemcpyAsync(hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  if (hflag[0]) fail(WCMG_ERANK, "singular coarse site block");
+  finalize_coarse(c, C, flag);
   C.built = true;
+  if (p.nlevels == 1 && p.coarsest == 1) build_dense(c, L, 0);
   L.mg.reset();
 }
 
@@ -535,10 +765,12 @@ void solve_rhs(Ctx& c, LatticeState& L, int solver, void* x_e, void* x_o, const 
       require_hierarchy(L);
       if (!L.mg) L.mg = std::make_shared<MGSolver>(c, L);
       MGSolver& mg = *L.mg;
-      mg.calls = mg.iters = 0;
+      mg.calls = 0;
+      for (auto& lvl : mg.lv) lvl.calls = lvl.iters = 0;
       OpFn K = [&](void* o, const void* i) { mg.precondition(o, i); };
       kr = gcr(c, S64, Dr, &K, y, br, x_zero, tol, bn, restart, maxiter);
-      s.inner_iters[0] = mg.calls ? (double)mg.iters / mg.calls : 0.0;
+      for (size_t l = 0; l < mg.lv.size() && l < 3; ++l)
+        s.inner_iters[l] = mg.lv[l].calls ? (double)mg.lv[l].iters / mg.lv[l].calls : 0.0;
     }
   }
   op.reconstruct(x_e, x_o, y, b_o);
