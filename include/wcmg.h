@@ -104,6 +104,10 @@ typedef struct {
   int coarsest;                     /* 0: unpreconditioned GCR (paper); 1: direct solve with the
                                        dense FP64 inverse of the coarsest full operator (Gauss-Jordan
                                        with partial pivoting; dimension <= 16384) */
+  int cycle_mode;                   /* 0: inner GCRs stop at their tolerance (paper); 1: every inner
+                                       GCR runs exactly max_iter[l] steps with no host round trip;
+                                       2: as 1, with the whole preconditioner captured once into a
+                                       HIP graph and replayed at every outer iteration */
 } wcmg_mg_params;
 
 typedef struct {
@@ -215,6 +219,18 @@ int wcmg_solve_dag(void* ctx, int lat, int solver, void* x, const void* b, int n
  * Errors: EINVAL (null buffer, nrhs < 1), ESTATE (no gauge field, or the
  * clover part requested for a caller-supplied clover matrix). */
 int wcmg_force(void* ctx, int lat, void* dU, const void* psi, const void* lam, int nrhs, int include_clover);
+
+/* Project autotuner (on != 0: enable, 0: disable; choices are kept): the
+ * first launch of each fine hop kernel variant for a given lattice,
+ * precision and batch size times every candidate launch shape (64/128/256
+ * threads per block x 1/2/4 right-hand sides per thread) on the context
+ * stream and keeps the fastest.  Every candidate gives bitwise the same
+ * result, so tuning never changes an answer.  Not during graph capture. */
+int wcmg_autotune(void* ctx, int on);
+/* The tuner's choices as text, one line per kernel variant
+ * ("prec diag postinv Vh nrhs threads group microseconds"), written to buf
+ * (NUL-terminated, truncated to len bytes). */
+int wcmg_autotune_report(void* ctx, char* buf, int len);
 
 /* The global sum behind every inner product of the Krylov solvers (the
  * GCR orthogonalisation of the adaptive multigrid paragraph):

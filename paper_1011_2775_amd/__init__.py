@@ -216,6 +216,21 @@ class Context:
                                 x.numel(), out))
         return complex(out[0], out[1])
 
+    # -- autotuner -----------------------------------------------------------------
+    def autotune(self, on=True):
+        check(_lib.LIB.wcmg_autotune(self.h, int(bool(on))))
+
+    def autotune_report(self):
+        """The tuned launch shapes: list of dicts (prec, diag, postinv, Vh, nrhs, threads, group, us)."""
+        buf = ctypes.create_string_buffer(1 << 16)
+        check(_lib.LIB.wcmg_autotune_report(self.h, buf, len(buf)))
+        keys = ("prec", "diag", "postinv", "Vh", "nrhs", "threads", "group", "us")
+        out = []
+        for line in buf.value.decode().splitlines():
+            vals = line.split()
+            out.append({k: (float(v) if k == "us" else int(v)) for k, v in zip(keys, vals)})
+        return out
+
     # -- timing --------------------------------------------------------------------
     def timer_enable(self, on=True):
         check(_lib.LIB.wcmg_timer_enable(self.h, int(bool(on))))

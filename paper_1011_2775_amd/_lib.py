@@ -41,7 +41,8 @@ class MGParams(ctypes.Structure):
                 ("setup_max_steps", ctypes.c_int),
                 ("setup_rq_tol", ctypes.c_double),
                 ("seed", ctypes.c_uint64),
-                ("coarsest", ctypes.c_int)]
+                ("coarsest", ctypes.c_int),
+                ("cycle_mode", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -80,6 +81,8 @@ SIGNATURES = {
     "wcmg_solve": [_vp, _i, _i, _vp, _vp, _i, _d, ctypes.POINTER(Stats)],
     "wcmg_solve_dag": [_vp, _i, _i, _vp, _vp, _i, _d, ctypes.POINTER(Stats)],
     "wcmg_force": [_vp, _i, _vp, _vp, _vp, _i, _i],
+    "wcmg_autotune": [_vp, _i],
+    "wcmg_autotune_report": [_vp, ctypes.c_char_p, _i],
     "wcmg_dot": [_vp, _i, _vp, _vp, ctypes.c_long, ctypes.POINTER(_d)],
     "wcmg_timer_enable": [_vp, _i],
     "wcmg_timer_read": [_vp, _i, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(_d)],

@@ -1,0 +1,278 @@
+// Batched BLAS-1 kernels for the lockstep multi-right-hand-side solvers.
+//
+// A batch holds nrhs vectors of n complex elements, vstride elements apart.
+// Grid row blockIdx.y is the right-hand side; every reduction of a batch
+// writes its per-block partials to part[rhs][block][NR] and a second pass
+// (one block per right-hand side, in block order, as in the single-vector
+// kernels) writes res[rhs * rs + k].  The GCR coefficients of right-hand
+// side r live at beta + r * bs and qa + r * qs (device memory), so no
+// right-hand side shares a scalar with another.
+#include "blas_common.h"
+
+namespace wcmg {
+
+namespace {
+
+using namespace blas_detail;
+
+__device__ __forceinline__ double* part_row(const RedB& o, int nr) {
+  return o.part + (size_t)blockIdx.y * gridDim.x * nr;
+}
+template <typename T>
+__device__ __forceinline__ const void* row(const void* p, size_t vs) {
+  return reinterpret_cast<const char*>(p) + (size_t)blockIdx.y * vs * sizeof(typename C2<T>::V);
+}
+template <typename T>
+__device__ __forceinline__ void* row(void* p, size_t vs) {
+  return reinterpret_cast<char*>(p) + (size_t)blockIdx.y * vs * sizeof(typename C2<T>::V);
+}
+
+__global__ void __launch_bounds__(64) k_finalize_b(RedB o, int nr, int stride, int nblocks) {
+  const int k = threadIdx.x, r = blockIdx.x;
+  if (k >= nr) return;
+  const double* p = o.part + (size_t)r * nblocks * stride;
+  double s = 0.0;
+  for (int b = 0; b < nblocks; ++b) s += p[(size_t)b * stride + k];
+  o.res[(size_t)r * o.rs + k] = s;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_norm2_b(const void* x, size_t vs, size_t n, RedB o) {
+  double v[1] = {0.0};
+  const void* xr = row<T>(x, vs);
+  GRID_STRIDE(i, n) {
+    cpx<double> a = ld<T>(xr, i);
+    v[0] += a.r * a.r + a.i * a.i;
+  }
+  block_reduce_to<1>(v, part_row(o, 1));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_cdot_norm_b(const void* x, const void* y, size_t vs, size_t n, RedB o) {
+  double v[3] = {0.0, 0.0, 0.0};
+  const void* xr = row<T>(x, vs);
+  const void* yr = row<T>(y, vs);
+  GRID_STRIDE(i, n) {
+    cpx<double> a = ld<T>(xr, i), b = ld<T>(yr, i);
+    v[0] += a.r * b.r + a.i * b.i;
+    v[1] += a.r * b.i - a.i * b.r;
+    v[2] += a.r * a.r + a.i * a.i;
+  }
+  block_reduce_to<3>(v, part_row(o, 3));
+}
+
+struct MultiB {
+  const void* v[kMaxK];
+  const void* w[kMaxK];
+};
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_multi_cdot_b(MultiB m, int k, const void* y, size_t vs, size_t n,
+                                                           RedB o) {
+  double v[2 * kMaxK];
+#pragma unroll
+  for (int j = 0; j < 2 * kMaxK; ++j) v[j] = 0.0;
+  const void* yr = row<T>(y, vs);
+  GRID_STRIDE(i, n) {
+    cpx<double> b = ld<T>(yr, i);
+#pragma unroll
+    for (int j = 0; j < kMaxK; ++j) {
+      if (j < k) {
+        cpx<double> a = ld<T>(row<T>(m.v[j], vs), i);
+        v[2 * j] += a.r * b.r + a.i * b.i;
+        v[2 * j + 1] += a.r * b.i - a.i * b.r;
+      }
+    }
+  }
+  block_reduce_to<2 * kMaxK>(v, part_row(o, 2 * kMaxK));
+}
+
+__device__ __forceinline__ cpx<double> alpha_of(const double* qa) {
+  const double d = qa[0];
+  return d > 0.0 ? mk(qa[1] / d, qa[2] / d) : mk(0.0, 0.0);
+}
+
+// y -= sum_j (beta_j / ||q_j||^2) q_j, z likewise with w_j; optionally
+// partials of {||y||^2, <y, r>}
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_gcr_orth_b(MultiB m, int k, void* y, void* z, const void* r, size_t vs,
+                                                         size_t n, const double* beta, size_t bs, const double* qa,
+                                                         size_t qs, int do_red, RedB o) {
+  const double* be = beta + (size_t)blockIdx.y * bs;
+  const double* q4 = qa + (size_t)blockIdx.y * qs;
+  cpx<double> c[kMaxK];
+#pragma unroll
+  for (int j = 0; j < kMaxK; ++j) {
+    const double d = j < k ? q4[4 * j] : 0.0;
+    c[j] = (j < k && d > 0.0) ? mk(be[2 * j] / d, be[2 * j + 1] / d) : mk(0.0, 0.0);
+  }
+  double v[3] = {0.0, 0.0, 0.0};
+  void* yr = row<T>(y, vs);
+  void* zr = row<T>(z, vs);
+  const void* rr = row<T>(r, vs);
+  GRID_STRIDE(i, n) {
+    cpx<double> a = ld<T>(yr, i), b = ld<T>(zr, i);
+#pragma unroll
+    for (int j = 0; j < kMaxK; ++j) {
+      if (j < k) {
+        a = a - c[j] * ld<T>(row<T>(m.v[j], vs), i);
+        b = b - c[j] * ld<T>(row<T>(m.w[j], vs), i);
+      }
+    }
+    st<T>(yr, i, a);
+    st<T>(zr, i, b);
+    if (do_red) {
+      cpx<double> as = ld<T>(yr, i), rv = ld<T>(rr, i);
+      v[0] += as.r * as.r + as.i * as.i;
+      v[1] += as.r * rv.r + as.i * rv.i;
+      v[2] += as.r * rv.i - as.i * rv.r;
+    }
+  }
+  if (do_red) block_reduce_to<3>(v, part_row(o, 3));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_gcr_update_r_b(const void* q, void* r, size_t vs, size_t n,
+                                                             const double* qa, size_t qs, RedB o) {
+  const cpx<double> a = alpha_of(qa + (size_t)blockIdx.y * qs);
+  double v[1] = {0.0};
+  const void* qr = row<T>(q, vs);
+  void* rr = row<T>(r, vs);
+  GRID_STRIDE(i, n) {
+    st<T>(rr, i, ld<T>(rr, i) - a * ld<T>(qr, i));
+    cpx<double> bs = ld<T>(rr, i);
+    v[0] += bs.r * bs.r + bs.i * bs.i;
+  }
+  block_reduce_to<1>(v, part_row(o, 1));
+}
+
+// x += sum_j alpha_j z_j with alpha_j from qa slot j
+template <typename T>
+__global__ void k_gcr_update_x_b(MultiB m, int k, void* x, size_t vs, size_t n, const double* qa, size_t qs) {
+  const double* q4 = qa + (size_t)blockIdx.y * qs;
+  cpx<double> c[kMaxK];
+#pragma unroll
+  for (int j = 0; j < kMaxK; ++j) c[j] = j < k ? alpha_of(q4 + 4 * j) : mk(0.0, 0.0);
+  void* xr = row<T>(x, vs);
+  GRID_STRIDE(i, n) {
+    cpx<double> acc = ld<T>(xr, i);
+#pragma unroll
+    for (int j = 0; j < kMaxK; ++j)
+      if (j < k) acc = acc + c[j] * ld<T>(row<T>(m.v[j], vs), i);
+    st<T>(xr, i, acc);
+  }
+}
+
+// MR step of every right-hand side with alpha = coef[0..1] / coef[2] (row r at coef + r * cs)
+template <typename T>
+__global__ void k_mr_update_b(const double* coef, size_t cs, void* x, void* r, const void* Ar, size_t vs, size_t n) {
+  const double* cf = coef + (size_t)blockIdx.y * cs;
+  const double d = cf[2];
+  const cpx<double> a = d > 0.0 ? mk(cf[0] / d, cf[1] / d) : mk(0.0, 0.0);
+  void* xr = row<T>(x, vs);
+  void* rr = row<T>(r, vs);
+  const void* ar = row<T>(Ar, vs);
+  GRID_STRIDE(i, n) {
+    st<T>(xr, i, ld<T>(xr, i) + a * ld<T>(rr, i));
+    st<T>(rr, i, ld<T>(rr, i) - a * ld<T>(ar, i));
+  }
+}
+
+}  // namespace
+
+#define DISPATCH_B(prec, KERNEL, grid, ...)                                                 \
+  do {                                                                                      \
+    if ((prec) == WCMG_F64)                                                                 \
+      hipLaunchKernelGGL(KERNEL<double>, grid, dim3(kThreads), 0, st, __VA_ARGS__);         \
+    else                                                                                    \
+      hipLaunchKernelGGL(KERNEL<float>, grid, dim3(kThreads), 0, st, __VA_ARGS__);          \
+    HIPCHK(hipGetLastError());                                                              \
+  } while (0)
+
+static dim3 red_grid_b(size_t n, int nrhs) { return dim3(red_grid(n).x, nrhs); }
+static dim3 ew_grid_b(size_t n, int nrhs) { return dim3(ew_grid(n).x, nrhs); }
+
+static void finalize_b(const RedB& o, int nr, int stride, size_t n, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize_b, dim3(nrhs), dim3(64), 0, st, o, nr, stride, (int)red_grid(n).x);
+  HIPCHK(hipGetLastError());
+}
+
+static void check_batch(int nrhs) {
+  if (nrhs < 1 || nrhs > kMaxBatch) fail(WCMG_EINVAL, "batch size out of range");
+}
+
+void blas_norm2_b(int prec, const void* x, size_t vs, size_t n, int nrhs, const RedB& o, hipStream_t st) {
+  check_batch(nrhs);
+  DISPATCH_B(prec, k_norm2_b, red_grid_b(n, nrhs), x, vs, n, o);
+  finalize_b(o, 1, 1, n, nrhs, st);
+}
+
+void blas_cdot_norm_b(int prec, const void* x, const void* y, size_t vs, size_t n, int nrhs, const RedB& o,
+                      hipStream_t st) {
+  check_batch(nrhs);
+  DISPATCH_B(prec, k_cdot_norm_b, red_grid_b(n, nrhs), x, y, vs, n, o);
+  finalize_b(o, 3, 3, n, nrhs, st);
+}
+
+void blas_multi_cdot_b(int prec, const void* const* v, int k, const void* y, size_t vs, size_t n, int nrhs,
+                       const RedB& o, hipStream_t st) {
+  check_batch(nrhs);
+  for (int j0 = 0; j0 < k; j0 += kMaxK) {
+    const int kk = std::min(kMaxK, k - j0);
+    MultiB m{};
+    for (int j = 0; j < kk; ++j) m.v[j] = v[j0 + j];
+    RedB oo{o.res + 2 * j0, o.rs, o.part};
+    DISPATCH_B(prec, k_multi_cdot_b, red_grid_b(n, nrhs), m, kk, y, vs, n, oo);
+    finalize_b(oo, 2 * kk, 2 * kMaxK, n, nrhs, st);
+  }
+}
+
+void blas_gcr_orth_b(int prec, const void* const* q, const void* const* w, int k, void* y, void* z, const void* r,
+                     size_t vs, size_t n, int nrhs, const double* beta, size_t bs, const double* qa, size_t qs,
+                     const RedB& o, hipStream_t st) {
+  check_batch(nrhs);
+  if (k == 0) {
+    MultiB m{};
+    DISPATCH_B(prec, k_gcr_orth_b, red_grid_b(n, nrhs), m, 0, y, z, r, vs, n, beta, bs, qa, qs, 1, o);
+    finalize_b(o, 3, 3, n, nrhs, st);
+    return;
+  }
+  for (int j0 = 0; j0 < k; j0 += kMaxK) {
+    const int kk = std::min(kMaxK, k - j0);
+    MultiB m{};
+    for (int j = 0; j < kk; ++j) {
+      m.v[j] = q[j0 + j];
+      m.w[j] = w[j0 + j];
+    }
+    const int last = j0 + kk == k;
+    DISPATCH_B(prec, k_gcr_orth_b, red_grid_b(n, nrhs), m, kk, y, z, r, vs, n, beta + 2 * j0, bs, qa + 4 * j0, qs,
+               last, o);
+    if (last) finalize_b(o, 3, 3, n, nrhs, st);
+  }
+}
+
+void blas_gcr_update_r_b(int prec, const void* q, void* r, size_t vs, size_t n, int nrhs, const double* qa_k,
+                         size_t qs, const RedB& o, hipStream_t st) {
+  check_batch(nrhs);
+  DISPATCH_B(prec, k_gcr_update_r_b, red_grid_b(n, nrhs), q, r, vs, n, qa_k, qs, o);
+  finalize_b(o, 1, 1, n, nrhs, st);
+}
+
+void blas_gcr_update_x_b(int prec, const void* const* z, int k, void* x, size_t vs, size_t n, int nrhs,
+                         const double* qa, size_t qs, hipStream_t st) {
+  check_batch(nrhs);
+  for (int j0 = 0; j0 < k; j0 += kMaxK) {
+    const int kk = std::min(kMaxK, k - j0);
+    MultiB m{};
+    for (int j = 0; j < kk; ++j) m.v[j] = z[j0 + j];
+    DISPATCH_B(prec, k_gcr_update_x_b, ew_grid_b(n, nrhs), m, kk, x, vs, n, qa + 4 * j0, qs);
+  }
+}
+
+void blas_mr_update_b(int prec, const double* coef, size_t cs, void* x, void* r, const void* Ar, size_t vs, size_t n,
+                      int nrhs, hipStream_t st) {
+  check_batch(nrhs);
+  DISPATCH_B(prec, k_mr_update_b, ew_grid_b(n, nrhs), coef, cs, x, r, Ar, vs, n);
+}
+
+}  // namespace wcmg

@@ -2,6 +2,7 @@
 // layout conversion, and dispatch to the runtime.  No exception crosses the
 // boundary; every entry point returns a status code.
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 
 #include "runtime.h"
@@ -244,6 +245,7 @@ int wcmg_set_clover(void* ctx, int lat, double m0, double csw, const void* A, in
     L.F.csw = csw;
     L.F.clover_from_u = (A == nullptr);
     L.F.have_clover = true;
+    L.mg.reset();  // the preconditioner (and any captured graph) holds the old clover
     for (auto& lv : L.levels) lv->built = false;
     L.mg.reset();
   });
@@ -276,6 +278,7 @@ int wcmg_set_mg_params(void* ctx, int lat, const wcmg_mg_params* p) {
         "smoother precision must be F64 or F32");
   CHECK(p->setup_relax >= 1 && p->setup_max_steps >= 1, WCMG_EINVAL, "setup iteration counts must be >= 1");
   CHECK(p->coarsest == 0 || p->coarsest == 1, WCMG_EINVAL, "coarsest must be 0 (GCR) or 1 (dense FP64 inverse)");
+  CHECK(p->cycle_mode >= 0 && p->cycle_mode <= 2, WCMG_EINVAL, "cycle_mode must be 0, 1 or 2");
   // coarse extents and degrees of freedom of every level
   int ext[4], nf = 2 * p->nvec[0];
   for (int k = 0; k < 4; ++k) ext[k] = g.L[k] / p->block[0][k];
@@ -476,39 +479,46 @@ static int apply_common(void* ctx, int lat, int op, int prec, void* out, const v
     const Geom& g = L.F.g;
     const size_t hb = spinor_bytes(prec, g.Vh);
     const size_t one = (size_t)g.V * 12 * 16;
-    void* ie = c->scratch_buf(42, hb);
-    void* io = c->scratch_buf(43, hb);
-    void* oe = c->scratch_buf(44, hb);
-    void* oo = c->scratch_buf(45, hb);
+    // all right-hand sides go through each kernel in one batched launch
+    char* ie = (char*)c->scratch_buf(42, hb * nrhs);
+    char* io = (char*)c->scratch_buf(43, hb * nrhs);
+    char* oe = (char*)c->scratch_buf(44, hb * nrhs);
+    char* oo = (char*)c->scratch_buf(45, hb * nrhs);
     FineOp fo{c, &L.F, prec, &c->fw[prec], c->st};
-    for (int r = 0; r < nrhs; ++r) {
-      const void* src = (const char*)in + (size_t)r * one;
-      void* dst = (char*)out + (size_t)r * one;
-      spinor_to_internal(prec, ie, io, src, g, dag && op != WCMG_OP_SCHUR, c->st);
-      if (op == WCMG_OP_FULL) {
-        fo.D(oe, oo, ie, io);
-        spinor_from_internal(prec, dst, oe, oo, g, dag, c->st);
-      } else if (op == WCMG_OP_DP) {
-        if (!dag) {
-          fo.Dp(oe, oo, ie, io);
-          spinor_from_internal(prec, dst, oe, oo, g, false, c->st);
-        } else {
-          // D_p^dag = A^-1 gamma5 D gamma5
-          fo.D(oe, oo, ie, io);
-          spinor_gamma5(prec, oe, g.Vh, c->st);
-          spinor_gamma5(prec, oo, g.Vh, c->st);
-          fo.clover(ie, oe, 0, 1);
-          fo.clover(io, oo, 1, 1);
-          spinor_from_internal(prec, dst, ie, io, g, false, c->st);
-        }
+    for (int r = 0; r < nrhs; ++r)
+      spinor_to_internal(prec, ie + r * hb, io + r * hb, (const char*)in + (size_t)r * one, g,
+                         dag && op != WCMG_OP_SCHUR, c->st);
+    bool flip_out = false;
+    char* re = oe;
+    char* ro = oo;
+    if (op == WCMG_OP_FULL) {
+      fo.D(oe, oo, ie, io, nrhs);
+      flip_out = dag;
+    } else if (op == WCMG_OP_DP) {
+      if (!dag) {
+        fo.Dp(oe, oo, ie, io, nrhs);
       } else {
-        if (!dag)
-          fo.Dr(oe, ie);
-        else
-          fo.Dr_dag(oe, ie);
-        spinor_from_internal(prec, dst, oe, nullptr, g, false, c->st);
+        // D_p^dag = A^-1 gamma5 D gamma5
+        fo.D(oe, oo, ie, io, nrhs);
+        for (int r = 0; r < nrhs; ++r) {
+          spinor_gamma5(prec, oe + r * hb, g.Vh, c->st);
+          spinor_gamma5(prec, oo + r * hb, g.Vh, c->st);
+        }
+        fo.clover(ie, oe, 0, 1, nrhs);
+        fo.clover(io, oo, 1, 1, nrhs);
+        re = ie;
+        ro = io;
       }
+    } else {
+      if (!dag)
+        fo.Dr(oe, ie, nrhs);
+      else
+        fo.Dr_dag(oe, ie, nrhs);
+      ro = nullptr;
     }
+    for (int r = 0; r < nrhs; ++r)
+      spinor_from_internal(prec, (char*)out + (size_t)r * one, re + r * hb, ro ? ro + r * hb : nullptr, g, flip_out,
+                           c->st);
   });
 }
 
@@ -644,26 +654,27 @@ int wcmg_apply_coarse(void* ctx, int lat, int level, int op, int prec, void* out
   CoarseLevel& C = *L.levels[level - 1];
   CHECK(op != WCMG_OP_SCHUR || C.cg.split, WCMG_EDIM, "coarse lattice has an odd extent: no red-black form");
   return guarded([&] {
+    // all right-hand sides in one batched application (FP32 red-black batches
+    // run on the matrix cores)
     const size_t cs = prec == WCMG_F64 ? 16 : 8;
     const size_t nall = (size_t)C.cg.V * C.cg.n;
-    void* vi = c->scratch_buf(46, nall * 16);
-    void* vo = c->scratch_buf(47, nall * 16);
-    blas_zero(prec, vo, nall, c->st);
+    char* vi = (char*)c->scratch_buf(46, nall * 16 * nrhs);
+    char* vo = (char*)c->scratch_buf(47, nall * 16 * nrhs);
+    blas_zero(prec, vo, nall * nrhs, c->st);
     CoarseOp cop{&C, prec, &c->cw[prec == WCMG_F64 ? 0 : 1], c->st};
     const size_t cone = nall * 16;
-    for (int r = 0; r < nrhs; ++r) {
-      launch_coarse_canon(prec, vi, (char*)const_cast<void*>(in) + r * cone, C.perm.as<int>(), C.cg.V, C.cg.n, true,
+    for (int r = 0; r < nrhs; ++r)
+      launch_coarse_canon(prec, vi + r * nall * cs, (char*)const_cast<void*>(in) + r * cone, C.perm.as<int>(),
+                          C.cg.V, C.cg.n, true, c->st);
+    if (op == WCMG_OP_FULL)
+      cop.Dfull(vo, vi, nrhs);
+    else if (op == WCMG_OP_DP)
+      cop.Dp(vo, vi, nrhs);
+    else
+      cop.Dr(vo, vi, nrhs);
+    for (int r = 0; r < nrhs; ++r)
+      launch_coarse_canon(prec, vo + r * nall * cs, (char*)out + r * cone, C.perm.as<int>(), C.cg.V, C.cg.n, false,
                           c->st);
-      if (op == WCMG_OP_FULL)
-        cop.Dfull(vo, vi);
-      else if (op == WCMG_OP_DP)
-        cop.Dp(vo, vi);
-      else {
-        blas_zero(prec, (char*)vo + cop.neven() * cs, nall - cop.neven(), c->st);
-        cop.Dr(vo, vi);
-      }
-      launch_coarse_canon(prec, vo, (char*)out + r * cone, C.perm.as<int>(), C.cg.V, C.cg.n, false, c->st);
-    }
   });
 }
 
@@ -685,6 +696,43 @@ static int solve_impl(void* ctx, int lat, int solver, void* x, const void* b, in
     const Geom& g = L.F.g;
     const size_t hb = spinor_bytes(WCMG_F64, g.Vh);
     const size_t one = (size_t)g.V * 12 * 16;
+    if (solver == WCMG_MG_GCR && nrhs > 1) {
+      // lockstep batches of up to kMaxBatch right-hand sides
+      const int bmax = std::min(nrhs, kMaxBatch);
+      char* be = (char*)c->scratch_buf(48, hb * bmax);
+      char* bo = (char*)c->scratch_buf(49, hb * bmax);
+      char* xe = (char*)c->scratch_buf(50, hb * bmax);
+      char* xo = (char*)c->scratch_buf(51, hb * bmax);
+      for (int r0 = 0; r0 < nrhs; r0 += kMaxBatch) {
+        const int nb = std::min(kMaxBatch, nrhs - r0);
+        bool x_zero = true;
+        for (int i = 0; i < nb; ++i) {
+          const void* bs = (const char*)b + (size_t)(r0 + i) * one;
+          void* xs = (char*)x + (size_t)(r0 + i) * one;
+          spinor_to_internal(WCMG_F64, be + i * hb, bo + i * hb, bs, g, false, c->st);
+          spinor_to_internal(WCMG_F64, xe + i * hb, xo + i * hb, xs, g, false, c->st);
+          if (dag)
+            for (char* v : {be, bo, xe, xo}) spinor_gamma5(WCMG_F64, v + i * hb, g.Vh, c->st);
+          x_zero = x_zero && norm2(*c, WCMG_F64, xe + i * hb, (size_t)12 * g.Vh) +
+                                     norm2(*c, WCMG_F64, xo + i * hb, (size_t)12 * g.Vh) ==
+                                 0.0;
+        }
+        std::vector<wcmg_stats> s(nb);
+        solve_batch(*c, L, xe, xo, be, bo, nb, x_zero, tol, s.data());
+        for (int i = 0; i < nb; ++i) {
+          if (dag) {
+            spinor_gamma5(WCMG_F64, xe + i * hb, g.Vh, c->st);
+            spinor_gamma5(WCMG_F64, xo + i * hb, g.Vh, c->st);
+          }
+          spinor_from_internal(WCMG_F64, (char*)x + (size_t)(r0 + i) * one, xe + i * hb, xo + i * hb, g, false,
+                               c->st);
+          if (stats) stats[r0 + i] = s[i];
+          if (s[i].status != WCMG_OK && worst == WCMG_OK) worst = s[i].status;
+        }
+      }
+      HIPCHK(hipStreamSynchronize(c->st));
+      return;
+    }
     void* be = c->scratch_buf(48, hb);
     void* bo = c->scratch_buf(49, hb);
     void* xe = c->scratch_buf(50, hb);
@@ -755,6 +803,26 @@ int wcmg_dot(void* ctx, int prec, const void* x, const void* y, long n, double* 
     const double* h = c->red.fetch(2);
     out[0] = h[0];
     out[1] = h[1];
+  });
+}
+
+int wcmg_autotune(void* ctx, int on) {
+  CHECK(ctx, WCMG_EINVAL, "null context");
+  return guarded([&] { as_ctx(ctx)->tuner.on = on != 0; });
+}
+
+int wcmg_autotune_report(void* ctx, char* buf, int len) {
+  CHECK(ctx, WCMG_EINVAL, "null context");
+  CHECK(buf && len > 0, WCMG_EINVAL, "null buffer");
+  return guarded([&] {
+    std::string out;
+    for (const auto& kv : as_ctx(ctx)->tuner.best) {
+      char line[160];
+      std::snprintf(line, sizeof(line), "%d %d %d %d %d %d %d %.3f\n", kv.first[0], kv.first[1], kv.first[2],
+                    kv.first[3], kv.first[4], kv.second.threads, kv.second.group, kv.second.us);
+      out += line;
+    }
+    std::snprintf(buf, (size_t)len, "%s", out.c_str());
   });
 }
 

@@ -39,7 +39,7 @@ __device__ __forceinline__ void load2(const double2* p, cpx<double>& e0, cpx<dou
 template <typename S>
 __global__ void __launch_bounds__(1024) k_coarse_hop(void* out, const void* in, const void* x, const void* M,
                                                      const void* Xm, int diag, double coeff, int site0, int n,
-                                                     const int* nbr) {
+                                                     const int* nbr, size_t vs) {
   using C = typename Compute<S>::T;
   using V2 = typename Vec2<S>::T;
   extern __shared__ char smem[];
@@ -48,8 +48,11 @@ __global__ void __launch_bounds__(1024) k_coarse_hop(void* out, const void* in, 
   const int c = site0 + blockIdx.x;
   const int R2 = n >> 1;
   const int G = blockDim.x / R2;
-  const V2* vi = reinterpret_cast<const V2*>(in);
-  const V2* vx = reinterpret_cast<const V2*>(x);
+  // right-hand side blockIdx.y of a batch, vs elements apart
+  const size_t ro = (size_t)blockIdx.y * vs;
+  const V2* vi = reinterpret_cast<const V2*>(in) + (in ? ro : 0);
+  const V2* vx = reinterpret_cast<const V2*>(x) + (x ? ro : 0);
+  out = reinterpret_cast<V2*>(out) + ro;
   if (M) {
     for (int t = threadIdx.x; t < 8 * n; t += blockDim.x) {
       int d = t / n, j = t - d * n;
@@ -228,7 +231,8 @@ void launch_coarse_canon(int prec, void* internal, void* canon, const int* perm,
 }
 
 void launch_coarse_hop(int prec, void* out, const void* in, const void* x, const void* M, const void* Xmat,
-                       int diag, double coeff, int parity, const CoarseGeom& cg, const int* nbr, hipStream_t st) {
+                       int diag, double coeff, int parity, const CoarseGeom& cg, const int* nbr, hipStream_t st,
+                       int nrhs, size_t vs) {
   const int n = cg.n;
   if (n % 2 || n > 256) fail(WCMG_EDIM, "coarse block size must be even and <= 256");
   const int R2 = n / 2;
@@ -245,17 +249,17 @@ void launch_coarse_hop(int prec, void* out, const void* in, const void* x, const
   const size_t shm = (size_t)(9 * n + G * n) * cb;
   if (nsites == 0) return;
   if (prec == WCMG_F64)
-    hipLaunchKernelGGL(k_coarse_hop<double>, dim3(nsites), dim3(threads), shm, st, out, in, x, M, Xmat, diag, coeff,
-                       site0, n, nbr);
+    hipLaunchKernelGGL(k_coarse_hop<double>, dim3(nsites, nrhs), dim3(threads), shm, st, out, in, x, M, Xmat, diag,
+                       coeff, site0, n, nbr, vs);
   else
-    hipLaunchKernelGGL(k_coarse_hop<float>, dim3(nsites), dim3(threads), shm, st, out, in, x, M, Xmat, diag, coeff,
-                       site0, n, nbr);
+    hipLaunchKernelGGL(k_coarse_hop<float>, dim3(nsites, nrhs), dim3(threads), shm, st, out, in, x, M, Xmat, diag,
+                       coeff, site0, n, nbr, vs);
   HIPCHK(hipGetLastError());
 }
 
 void launch_coarse_local(int prec, void* out, const void* in, const void* M, int parity, const CoarseGeom& cg,
-                         hipStream_t st) {
-  launch_coarse_hop(prec, out, nullptr, in, nullptr, M, 2, 0.0, parity, cg, nullptr, st);
+                         hipStream_t st, int nrhs, size_t vs) {
+  launch_coarse_hop(prec, out, nullptr, in, nullptr, M, 2, 0.0, parity, cg, nullptr, st, nrhs, vs);
 }
 
 void launch_batched_inverse(double* M, int nmat, int n, int* flag, hipStream_t st) {

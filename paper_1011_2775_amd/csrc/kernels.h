@@ -16,10 +16,15 @@ struct DslashArgs {
   int parity;          // output parity
   int nblocks;         // filled by the launcher
   double coeff;        // multiplies the (post-processed) hopping term
+  int nrhs = 1;        // right-hand sides: out, in, x hold nrhs spinors
+  size_t rstride = 0;  // bytes between consecutive right-hand sides
+  int threads = 0;     // launch shape: threads per block (64, 128, 256; 0 = 256)
+  int group = 0;       // right-hand sides per thread (1, 2, 4; 0 = largest that fits)
 };
 void launch_dslash(int prec, int diag, bool postinv, const DslashArgs& a, hipStream_t st);
+// out_r = A^(kind) in_r for nrhs spinors rstride bytes apart
 void launch_clover(int prec, void* out, const void* in, const void* clov, int Vh, int p, int kind,
-                   hipStream_t st);
+                   hipStream_t st, int nrhs = 1, size_t rstride = 0);
 
 // ------------------------------------------------------------ fields
 // canonical complex128 gauge [V][4][3][3] (device) -> internal links
@@ -105,6 +110,30 @@ void blas_gcr_update_x_dev(int prec, const void* const* z, int k, void* x, size_
 // MR with alpha = coef[0..1] / coef[2] (the output of blas_cdot_norm(Ar, r))
 void blas_mr_update_dev(int prec, const double* coef, void* x, void* r, const void* Ar, size_t n, hipStream_t st);
 
+// ------------------------------------------------------------ batched BLAS-1
+// nrhs vectors of n complex elements, vstride elements apart; results of right-hand
+// side r at res + r * rs; part: scratch of kMaxBatch * kRedBlocks * 32 doubles
+constexpr int kMaxBatch = 16;
+struct RedB {
+  double* res;
+  size_t rs;
+  double* part;
+};
+void blas_norm2_b(int prec, const void* x, size_t vs, size_t n, int nrhs, const RedB& o, hipStream_t st);
+void blas_cdot_norm_b(int prec, const void* x, const void* y, size_t vs, size_t n, int nrhs, const RedB& o,
+                      hipStream_t st);
+void blas_multi_cdot_b(int prec, const void* const* v, int k, const void* y, size_t vs, size_t n, int nrhs,
+                       const RedB& o, hipStream_t st);
+void blas_gcr_orth_b(int prec, const void* const* q, const void* const* w, int k, void* y, void* z, const void* r,
+                     size_t vs, size_t n, int nrhs, const double* beta, size_t bs, const double* qa, size_t qs,
+                     const RedB& o, hipStream_t st);
+void blas_gcr_update_r_b(int prec, const void* q, void* r, size_t vs, size_t n, int nrhs, const double* qa_k,
+                         size_t qs, const RedB& o, hipStream_t st);
+void blas_gcr_update_x_b(int prec, const void* const* z, int k, void* x, size_t vs, size_t n, int nrhs,
+                         const double* qa, size_t qs, hipStream_t st);
+void blas_mr_update_b(int prec, const double* coef, size_t cs, void* x, void* r, const void* Ar, size_t vs, size_t n,
+                      int nrhs, hipStream_t st);
+
 // ------------------------------------------------------------ transfer (fine level)
 struct BlockGeom {
   int b[4];    // block extents
@@ -131,6 +160,18 @@ void launch_block_orthonormalize(void* vecs, int nvec, const Geom& g, const Bloc
 // coarse build: nine direction buckets of the D_p hop of u = A^-1 v (both parities)
 void launch_hop_split(void* const* buckets /*9 full spinors F64*/, const void* v, const void* u,
                       const void* gauge64, const Geom& g, const BlockGeom& bg, hipStream_t st);
+
+// ------------------------------------------------------------ matrix-core coarse stencil
+struct CoarseGeom;
+// FP16 operand fragments of Yt (from the FP64 [site][8][n][n] column-major blocks);
+// flag[0] = 1 if an entry is outside the FP16 range
+bool mfma_coarse_supported(int n);
+size_t mfma_fragment_bytes(int nsites, int n);
+void build_mfma_fragments(void* frag, const void* Yt64, int nsites, int n, int* flag, hipStream_t st);
+// red-black coarse hop of nrhs FP32 right-hand sides (vs elements apart) on the matrix cores:
+// out(c) = x(c) (if x) + coeff sum_d Yt_d(c) in(nb(c, d)) over the sites of `parity`
+void launch_coarse_hop_mfma(void* out, const void* in, const void* x, const void* frag, double coeff, int parity,
+                            const CoarseGeom& cg, const int* nbr, int nrhs, size_t vs, hipStream_t st);
 
 // ------------------------------------------------------------ deeper levels
 // transfer between coarse level l and l+1 (vectors [site][nf], V: nvec such
@@ -166,10 +207,11 @@ struct CoarseGeom {
 // (parity -1: all sites, requires split == 0 or both halves contiguous)
 // M: [site][8][n][n] column-major blocks.  diag 0 none, 1 x, 2 X(c) x with Xmat
 void launch_coarse_hop(int prec, void* out, const void* in, const void* x, const void* M, const void* Xmat,
-                       int diag, double coeff, int parity, const CoarseGeom& cg, const int* nbr, hipStream_t st);
+                       int diag, double coeff, int parity, const CoarseGeom& cg, const int* nbr, hipStream_t st,
+                       int nrhs = 1, size_t vs = 0);
 // out(c) = M(c) in(c) with M [site][n][n] column-major, sites of `parity` (-1 all)
 void launch_coarse_local(int prec, void* out, const void* in, const void* M, int parity, const CoarseGeom& cg,
-                         hipStream_t st);
+                         hipStream_t st, int nrhs = 1, size_t vs = 0);
 void launch_batched_inverse(double* M, int nmat, int n, int* flag, hipStream_t st);
 // Yt[c][d] = Y[c][d] * Xinv[nb(c,d)]   (all column-major n x n)
 void launch_coarse_right_mul(double* Yt, const double* Y, const double* Xinv, const int* nbr, int V, int n,

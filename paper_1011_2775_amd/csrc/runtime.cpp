@@ -124,6 +124,14 @@ void Reducer::init(hipStream_t s) {
   counter.alloc(256);
   HIPCHK(hipMemset(counter.p, 0, 256));
   HIPCHK(hipHostMalloc((void**)&host, 256 * sizeof(double), hipHostMallocDefault));
+  part_b.alloc((size_t)kMaxBatch * kRedBlocks * 32 * sizeof(double));
+}
+const double* Reducer::fetch_rows(const double* dev, size_t pitch, int width, int rows) {
+  if (width * rows > 256) fail(WCMG_EINVAL, "too many scalars for the host staging buffer");
+  HIPCHK(hipMemcpy2DAsync(host, (size_t)width * sizeof(double), dev, pitch * sizeof(double),
+                          (size_t)width * sizeof(double), rows, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return host;
 }
 // The copy is ordered after the reduction on the stream; values written by a
 // kernel straight into host-mapped memory were not reliably visible to the
@@ -149,9 +157,9 @@ void* Ctx::scratch_buf(int slot, size_t bytes) {
 }
 
 // ------------------------------------------------------------------ fine level
-void FineWork::ensure(int p, const Geom& g) {
-  size_t b = spinor_bytes(p, g.Vh);
-  if (prec == p && hb == b) return;
+void FineWork::ensure(int p, const Geom& g, int nrhs) {
+  size_t b = spinor_bytes(p, g.Vh) * (size_t)nrhs;
+  if (prec == p && hb >= b) return;
   prec = p;
   hb = b;
   t1.alloc(b);
@@ -159,7 +167,8 @@ void FineWork::ensure(int p, const Geom& g) {
   t3.alloc(b);
 }
 
-void FineOp::hop(void* out, const void* in, const void* x, int parity, int diag, bool postinv, double coeff) {
+void FineOp::hop(void* out, const void* in, const void* x, int parity, int diag, bool postinv, double coeff,
+                 int nrhs) {
   DslashArgs a;
   a.out = out;
   a.in = in;
@@ -170,59 +179,101 @@ void FineOp::hop(void* out, const void* in, const void* x, int parity, int diag,
   a.parity = parity;
   a.nblocks = 0;
   a.coeff = coeff;
-  // timer id: precision x DIAG mode x clover-inverse post-multiply
-  const int id = prec * 6 + diag * 2 + (postinv ? 1 : 0);
+  a.nrhs = nrhs;
+  a.rstride = hb();
+  if (ctx->tuner.on) {
+    const std::array<int, 5> key{prec, diag, postinv ? 1 : 0, F->g.Vh, nrhs};
+    auto it = ctx->tuner.best.find(key);
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIPCHK(hipStreamIsCapturing(st, &cs));
+    if (it == ctx->tuner.best.end() && cs == hipStreamCaptureStatusNone) {
+      // time every candidate shape on this very launch (the kernel only writes `out`)
+      Tuner::Choice bestc{256, 0, 1e30};
+      hipEvent_t e0, e1;
+      HIPCHK(hipEventCreate(&e0));
+      HIPCHK(hipEventCreate(&e1));
+      const int max_g = prec == WCMG_F64 ? 2 : 4;
+      for (int threads : {64, 128, 256})
+        for (int group : {1, 2, 4}) {
+          if (group > max_g || (group > 1 && group > nrhs)) continue;
+          DslashArgs t = a;
+          t.threads = threads;
+          t.group = group;
+          launch_dslash(prec, diag, postinv, t, st);
+          HIPCHK(hipEventRecord(e0, st));
+          for (int rep = 0; rep < 3; ++rep) launch_dslash(prec, diag, postinv, t, st);
+          HIPCHK(hipEventRecord(e1, st));
+          HIPCHK(hipEventSynchronize(e1));
+          float ms = 0.f;
+          HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+          const double us = ms * 1e3 / 3.0;
+          if (us < bestc.us) bestc = Tuner::Choice{threads, group, us};
+        }
+      HIPCHK(hipEventDestroy(e0));
+      HIPCHK(hipEventDestroy(e1));
+      it = ctx->tuner.best.emplace(key, bestc).first;
+    }
+    if (it != ctx->tuner.best.end()) {
+      a.threads = it->second.threads;
+      a.group = it->second.group;
+    }
+  }
+  // timer id: precision x DIAG mode x clover-inverse post-multiply; batched launches from 32
+  const int id = (nrhs > 1 ? 32 : 0) + prec * 6 + diag * 2 + (postinv ? 1 : 0);
   hipEvent_t e = nullptr;
   if (ctx->timer.on) ctx->timer.begin(id, &e);
   launch_dslash(prec, diag, postinv, a, st);
   if (e) ctx->timer.end(id, e);
 }
 
-void FineOp::clover(void* out, const void* in, int parity, int kind) {
-  launch_clover(prec, out, in, F->clov[prec].p, F->g.Vh, parity, kind, st);
+void FineOp::clover(void* out, const void* in, int parity, int kind, int nrhs) {
+  launch_clover(prec, out, in, F->clov[prec].p, F->g.Vh, parity, kind, st, nrhs, hb());
 }
 
-void FineOp::Dr(void* out, const void* y) {
-  w->ensure(prec, F->g);
-  clover(w->t1.p, y, 0, 1);                   // z = A_ee^-1 y
-  hop(w->t2.p, w->t1.p, nullptr, 1, 0, true, 1.0);  // w = A_oo^-1 H_oe z
-  hop(out, w->t2.p, y, 0, 1, false, -1.0);    // out = y - H_eo w
+void FineOp::Dr(void* out, const void* y, int nrhs) {
+  w->ensure(prec, F->g, nrhs);
+  clover(w->t1.p, y, 0, 1, nrhs);                          // z = A_ee^-1 y
+  hop(w->t2.p, w->t1.p, nullptr, 1, 0, true, 1.0, nrhs);   // w = A_oo^-1 H_oe z
+  hop(out, w->t2.p, y, 0, 1, false, -1.0, nrhs);           // out = y - H_eo w
 }
 
-void FineOp::Dr_dag(void* out, const void* y) {
+void FineOp::Dr_dag(void* out, const void* y, int nrhs) {
   // D_r^dag = gamma5 (1 - A_ee^-1 H_eo A_oo^-1 H_oe) gamma5
-  w->ensure(prec, F->g);
-  spinor_convert(prec, w->t1.p, prec, y, F->g.Vh, st);
-  spinor_gamma5(prec, w->t1.p, F->g.Vh, st);
-  hop(w->t2.p, w->t1.p, nullptr, 1, 0, true, 1.0);
-  hop(out, w->t2.p, w->t1.p, 0, 1, true, -1.0);
-  spinor_gamma5(prec, out, F->g.Vh, st);
+  w->ensure(prec, F->g, nrhs);
+  const size_t h = hb();
+  for (int r = 0; r < nrhs; ++r) {
+    spinor_convert(prec, (char*)w->t1.p + r * h, prec, (const char*)y + r * h, F->g.Vh, st);
+    spinor_gamma5(prec, (char*)w->t1.p + r * h, F->g.Vh, st);
+  }
+  hop(w->t2.p, w->t1.p, nullptr, 1, 0, true, 1.0, nrhs);
+  hop(out, w->t2.p, w->t1.p, 0, 1, true, -1.0, nrhs);
+  for (int r = 0; r < nrhs; ++r) spinor_gamma5(prec, (char*)out + r * h, F->g.Vh, st);
 }
 
-void FineOp::D(void* oe, void* oo, const void* ie, const void* io) {
-  hop(oe, io, ie, 0, 2, false, 1.0);
-  hop(oo, ie, io, 1, 2, false, 1.0);
+void FineOp::D(void* oe, void* oo, const void* ie, const void* io, int nrhs) {
+  hop(oe, io, ie, 0, 2, false, 1.0, nrhs);
+  hop(oo, ie, io, 1, 2, false, 1.0, nrhs);
 }
 
-void FineOp::Dp(void* oe, void* oo, const void* ie, const void* io) {
-  w->ensure(prec, F->g);
-  clover(w->t1.p, ie, 0, 1);
-  clover(w->t2.p, io, 1, 1);
-  hop(oe, w->t2.p, ie, 0, 1, false, 1.0);
-  hop(oo, w->t1.p, io, 1, 1, false, 1.0);
+void FineOp::Dp(void* oe, void* oo, const void* ie, const void* io, int nrhs) {
+  w->ensure(prec, F->g, nrhs);
+  clover(w->t1.p, ie, 0, 1, nrhs);
+  clover(w->t2.p, io, 1, 1, nrhs);
+  hop(oe, w->t2.p, ie, 0, 1, false, 1.0, nrhs);
+  hop(oo, w->t1.p, io, 1, 1, false, 1.0, nrhs);
 }
 
-void FineOp::reduced_source(void* br, const void* be, const void* bo) {
-  w->ensure(prec, F->g);
-  clover(w->t1.p, bo, 1, 1);
-  hop(br, w->t1.p, be, 0, 1, false, -1.0);
+void FineOp::reduced_source(void* br, const void* be, const void* bo, int nrhs) {
+  w->ensure(prec, F->g, nrhs);
+  clover(w->t1.p, bo, 1, 1, nrhs);
+  hop(br, w->t1.p, be, 0, 1, false, -1.0, nrhs);
 }
 
-void FineOp::reconstruct(void* xe, void* xo, const void* ye, const void* bo) {
-  w->ensure(prec, F->g);
-  clover(xe, ye, 0, 1);
-  hop(w->t1.p, xe, bo, 1, 1, false, -1.0);
-  clover(xo, w->t1.p, 1, 1);
+void FineOp::reconstruct(void* xe, void* xo, const void* ye, const void* bo, int nrhs) {
+  w->ensure(prec, F->g, nrhs);
+  clover(xe, ye, 0, 1, nrhs);
+  hop(w->t1.p, xe, bo, 1, 1, false, -1.0, nrhs);
+  clover(xo, w->t1.p, 1, 1, nrhs);
 }
 
 // ------------------------------------------------------------------ coarse level
@@ -233,36 +284,50 @@ void CoarseWork::ensure(size_t bytes) {
   }
 }
 
-void CoarseOp::Dfull(void* out, const void* in) {
-  launch_coarse_hop(prec, out, in, in, C->Yhop[pi()].p, C->X[pi()].p, 2, 1.0, -1, C->cg, C->nbr.as<int>(), st);
+void CoarseOp::Dfull(void* out, const void* in, int nrhs) {
+  launch_coarse_hop(prec, out, in, in, C->Yhop[pi()].p, C->X[pi()].p, 2, 1.0, -1, C->cg, C->nbr.as<int>(), st, nrhs,
+                    nall());
 }
 
-void CoarseOp::Dp(void* out, const void* in) {
-  launch_coarse_hop(prec, out, in, in, C->Yt[pi()].p, nullptr, 1, 1.0, -1, C->cg, C->nbr.as<int>(), st);
+void CoarseOp::Dp(void* out, const void* in, int nrhs) {
+  launch_coarse_hop(prec, out, in, in, C->Yt[pi()].p, nullptr, 1, 1.0, -1, C->cg, C->nbr.as<int>(), st, nrhs, nall());
 }
 
-void CoarseOp::Dr(void* out, const void* y) {
-  w->ensure(nall() * csize());
-  const int id = timer_base + pi();
+void CoarseOp::Dr(void* out, const void* y, int nrhs) {
+  w->ensure(nall() * csize() * nrhs);
+  if (prec == WCMG_F32 && nrhs >= 2 && C->has_frag) {
+    // batches run on the matrix cores (FP16 operands, FP32 accumulation)
+    const int id = timer_base + 24;
+    hipEvent_t e = nullptr;
+    if (timer && timer->on) timer->begin(id, &e);
+    launch_coarse_hop_mfma(w->t1.p, y, nullptr, C->frag.p, 1.0, 1, C->cg, C->nbr.as<int>(), nrhs, nall(), st);
+    launch_coarse_hop_mfma(out, w->t1.p, y, C->frag.p, -1.0, 0, C->cg, C->nbr.as<int>(), nrhs, nall(), st);
+    if (e) timer->end(id, e);
+    return;
+  }
+  const int id = timer_base + pi() + (nrhs > 1 ? 16 : 0);
   hipEvent_t e = nullptr;
   if (timer && timer->on) timer->begin(id, &e);
-  launch_coarse_hop(prec, w->t1.p, y, nullptr, C->Yt[pi()].p, nullptr, 0, 1.0, 1, C->cg, C->nbr.as<int>(), st);
+  launch_coarse_hop(prec, w->t1.p, y, nullptr, C->Yt[pi()].p, nullptr, 0, 1.0, 1, C->cg, C->nbr.as<int>(), st, nrhs,
+                    nall());
   if (e) timer->end(id, e);
   e = nullptr;
   if (timer && timer->on) timer->begin(id, &e);
-  launch_coarse_hop(prec, out, w->t1.p, y, C->Yt[pi()].p, nullptr, 1, -1.0, 0, C->cg, C->nbr.as<int>(), st);
+  launch_coarse_hop(prec, out, w->t1.p, y, C->Yt[pi()].p, nullptr, 1, -1.0, 0, C->cg, C->nbr.as<int>(), st, nrhs,
+                    nall());
   if (e) timer->end(id, e);
 }
 
-void CoarseOp::reduced_source(void* br, const void* b) {
-  launch_coarse_hop(prec, br, b, b, C->Yt[pi()].p, nullptr, 1, -1.0, 0, C->cg, C->nbr.as<int>(), st);
+void CoarseOp::reduced_source(void* br, const void* b, int nrhs) {
+  launch_coarse_hop(prec, br, b, b, C->Yt[pi()].p, nullptr, 1, -1.0, 0, C->cg, C->nbr.as<int>(), st, nrhs, nall());
 }
 
-void CoarseOp::reconstruct(void* c, const void* y, const void* b) {
-  w->ensure(nall() * csize());
-  launch_coarse_local(prec, c, y, C->Xinv[pi()].p, 0, C->cg, st);
-  launch_coarse_hop(prec, w->t1.p, y, b, C->Yt[pi()].p, nullptr, 1, -1.0, 1, C->cg, C->nbr.as<int>(), st);
-  launch_coarse_local(prec, c, w->t1.p, C->Xinv[pi()].p, 1, C->cg, st);
+void CoarseOp::reconstruct(void* c, const void* y, const void* b, int nrhs) {
+  w->ensure(nall() * csize() * nrhs);
+  launch_coarse_local(prec, c, y, C->Xinv[pi()].p, 0, C->cg, st, nrhs, nall());
+  launch_coarse_hop(prec, w->t1.p, y, b, C->Yt[pi()].p, nullptr, 1, -1.0, 1, C->cg, C->nbr.as<int>(), st, nrhs,
+                    nall());
+  launch_coarse_local(prec, c, w->t1.p, C->Xinv[pi()].p, 1, C->cg, st, nrhs, nall());
 }
 
 }  // namespace wcmg

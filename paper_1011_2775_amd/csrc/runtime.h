@@ -3,7 +3,9 @@
 // solvers.
 #pragma once
 
+#include <array>
 #include <functional>
+#include <map>
 #include <memory>
 
 #include "kernels.h"
@@ -28,10 +30,25 @@ struct KernelTimer {
   ~KernelTimer();
 };
 
+// ------------------------------------------------------------------ autotuner
+// Launch shape of the fine hop kernels (threads per block, right-hand sides
+// per thread), chosen by timing every candidate on the first launch of each
+// (precision, kernel variant, lattice, batch) and kept for the context.  All
+// candidates compute bitwise the same result.
+struct Tuner {
+  bool on = false;
+  struct Choice {
+    int threads, group;
+    double us;
+  };
+  std::map<std::array<int, 5>, Choice> best;
+};
+
 // ------------------------------------------------------------------ reductions
 struct Reducer {
   hipStream_t st = nullptr;
   DBuf partial, res, counter;
+  DBuf part_b;  // per-block partials of the batched reductions
   double* host = nullptr;  // pinned staging buffer for results read on the host
   void init(hipStream_t s);
   double* dres() { return res.as<double>(); }
@@ -42,6 +59,9 @@ struct Reducer {
   // copy n results (from res, or from any device address) to the host and synchronise
   const double* fetch(int n) { return fetch_from(res.as<double>(), n); }
   const double* fetch_from(const double* dev, int n);
+  // rows doubles at dev + r * pitch (r < rows), `width` each, packed to host[r * width]
+  const double* fetch_rows(const double* dev, size_t pitch, int width, int rows);
+  RedB outb(double* dst, size_t rs) { return RedB{dst, rs, part_b.as<double>()}; }
   ~Reducer();
 };
 
@@ -61,8 +81,8 @@ struct FineFields {
 struct FineWork {
   int prec = -1;
   size_t hb = 0;
-  DBuf t1, t2, t3;  // parity halves
-  void ensure(int p, const Geom& g);
+  DBuf t1, t2, t3;  // parity halves (nrhs of them when batched)
+  void ensure(int p, const Geom& g, int nrhs = 1);
 };
 
 struct FineOp {
@@ -74,16 +94,18 @@ struct FineOp {
   const Geom& g() const { return F->g; }
   size_t hb() const { return spinor_bytes(prec, F->g.Vh); }
   size_t nelem() const { return (size_t)12 * F->g.Vh; }
-  void hop(void* out, const void* in, const void* x, int parity, int diag, bool postinv, double coeff);
-  void clover(void* out, const void* in, int parity, int kind);
+  // every operator below acts on nrhs parity halves stored hb() bytes apart
+  void hop(void* out, const void* in, const void* x, int parity, int diag, bool postinv, double coeff,
+           int nrhs = 1);
+  void clover(void* out, const void* in, int parity, int kind, int nrhs = 1);
   // reduced operator D_r y = y - H_eo A_oo^-1 H_oe A_ee^-1 y on even halves
-  void Dr(void* out, const void* y);
-  void Dr_dag(void* out, const void* y);
+  void Dr(void* out, const void* y, int nrhs = 1);
+  void Dr_dag(void* out, const void* y, int nrhs = 1);
   // full-lattice operators on (even, odd) halves
-  void D(void* oe, void* oo, const void* ie, const void* io);
-  void Dp(void* oe, void* oo, const void* ie, const void* io);
-  void reduced_source(void* br, const void* be, const void* bo);
-  void reconstruct(void* xe, void* xo, const void* ye, const void* bo);
+  void D(void* oe, void* oo, const void* ie, const void* io, int nrhs = 1);
+  void Dp(void* oe, void* oo, const void* ie, const void* io, int nrhs = 1);
+  void reduced_source(void* br, const void* be, const void* bo, int nrhs = 1);
+  void reconstruct(void* xe, void* xo, const void* ye, const void* bo, int nrhs = 1);
 };
 
 // ------------------------------------------------------------------ coarse level
@@ -96,6 +118,8 @@ struct CoarseLevel {
   DBuf nbr, perm;              // device int arrays
   DBuf Y9;                     // FP64 [site][9][n][n]
   DBuf X[2], Xinv[2], Yhop[2], Yt[2];  // [0] FP64, [1] FP32
+  DBuf frag;              // FP16 matrix-core fragments of Yt (batched stencil)
+  bool has_frag = false;
 };
 
 struct CoarseWork {
@@ -114,11 +138,12 @@ struct CoarseOp {
   size_t csize() const { return prec == WCMG_F64 ? 16 : 8; }
   size_t nall() const { return (size_t)C->cg.V * C->cg.n; }
   size_t neven() const { return (size_t)C->cg.Vh * C->cg.n; }
-  void Dfull(void* out, const void* in);
-  void Dp(void* out, const void* in);
-  void Dr(void* out, const void* y);  // full-size buffers, even half meaningful
-  void reduced_source(void* br, const void* b);
-  void reconstruct(void* c, const void* y, const void* b);
+  // nrhs right-hand sides of nall() elements each, stored back to back
+  void Dfull(void* out, const void* in, int nrhs = 1);
+  void Dp(void* out, const void* in, int nrhs = 1);
+  void Dr(void* out, const void* y, int nrhs = 1);  // full-size buffers, even half meaningful
+  void reduced_source(void* br, const void* b, int nrhs = 1);
+  void reconstruct(void* c, const void* y, const void* b, int nrhs = 1);
 };
 
 // ------------------------------------------------------------------ hierarchy
@@ -177,6 +202,20 @@ struct GcrSpace {
   void ensure(int restart);
 };
 constexpr int kMaxRestart = 64;
+// per right-hand side coefficient block of the batched GCR: beta then qa
+constexpr size_t kGcrCoefs = 2 * (kMaxRestart + 16) + 4 * kMaxRestart;
+
+// lockstep GCR over nrhs right-hand sides: vectors of n complex elements,
+// vs elements apart (vs >= n)
+struct GcrSpaceB {
+  int prec = WCMG_F64;
+  size_t n = 0, vs = 0;
+  int nrhs = 0;
+  std::vector<DBuf> Z, Q;
+  DBuf r, scal;
+  size_t bytes() const { return (size_t)nrhs * vs * (prec == WCMG_F64 ? 16 : 8); }
+  void ensure(int restart);
+};
 constexpr int kMaxDense = 16384;  // largest coarsest dimension for the dense solve
 // ------------------------------------------------------------------ context
 struct Ctx {
@@ -185,9 +224,11 @@ struct Ctx {
   std::vector<std::unique_ptr<LatticeState>> lats;
   Reducer red;
   KernelTimer timer;
+  Tuner tuner;
   FineWork fw[3];
   CoarseWork cw[2];
   GcrSpace outer{};  // Krylov basis of the outer FP64 solver
+  GcrSpaceB outer_b{};  // the same for batches of right-hand sides
   // scratch pools reused across calls (keyed by purpose)
   std::vector<DBuf> scratch;
   void* scratch_buf(int slot, size_t bytes);
@@ -206,6 +247,10 @@ KrylovResult gcr(Ctx& c, GcrSpace& S, const OpFn& A, const OpFn* K, void* x, con
                  double tol, double target_norm, int restart, int maxiter, bool fixed_iters = false);
 KrylovResult bicgstab(Ctx& c, int prec, size_t n, const OpFn& A, void* x, const void* b, double tol,
                       double target_norm, int maxiter);
+// batched flexible GCR: A and K act on S.nrhs right-hand sides at once
+std::vector<KrylovResult> gcr_b(Ctx& c, GcrSpaceB& S, const OpFn& A, const OpFn* K, void* x, const void* b,
+                                bool x_zero, double tol, const double* target_norm, int restart, int maxiter,
+                                bool fixed = false);
 
 // vector helpers
 double norm2(Ctx& c, int prec, const void* x, size_t n);
@@ -216,6 +261,10 @@ void mg_build_coarse(Ctx& c, LatticeState& L, int level);
 struct MGSolver;
 void solve_rhs(Ctx& c, LatticeState& L, int solver, void* x_e, void* x_o, const void* b_e, const void* b_o,
                bool x_zero, double tol, wcmg_stats* st);
+// multigrid solve of nrhs (<= kMaxBatch) right-hand sides in lockstep; halves
+// stored contiguously (nrhs even halves, then nrhs odd halves in separate buffers)
+void solve_batch(Ctx& c, LatticeState& L, void* x_e, void* x_o, const void* b_e, const void* b_o, int nrhs,
+                 bool x_zero, double tol, wcmg_stats* st);
 
 CoarseGeom make_coarse_geom(const BlockGeom& bg, int nvec);
 BlockGeom make_block_geom(const int L[4], const int b[4]);

@@ -54,7 +54,8 @@ KrylovResult gcr(Ctx& c, GcrSpace& S, const OpFn& A, const OpFn* K, void* x, con
     A(r, x);
     blas_axpby(prec, 1.0, 0.0, b, -1.0, 0.0, r, n, st);
   }
-  double rn2 = norm2(c, prec, r, n);
+  // fixed-length runs never read a scalar back (they can be captured into a graph)
+  double rn2 = fixed ? 0.0 : norm2(c, prec, r, n);
   const double target = tol * target_norm;
   if (!finite(rn2)) {
     res.status = WCMG_ENAN;
@@ -84,6 +85,12 @@ KrylovResult gcr(Ctx& c, GcrSpace& S, const OpFn& A, const OpFn* K, void* x, con
       if (k > 0) blas_multi_cdot(prec, Qp.data(), k, q, n, R.out(beta), st);
       blas_gcr_orth_dev(prec, Qp.data(), Zp.data(), k, q, z, r, n, beta, qa, R.out(qa + 4 * k), st);
       blas_gcr_update_r_dev(prec, q, r, n, qa + 4 * k, R.out(qa + 4 * k + 3), st);
+      if (fixed) {
+        ++k;
+        ++res.iters;
+        if (res.iters >= maxiter) break;
+        continue;
+      }
       const double* o = R.fetch_from(qa + 4 * k, 4);  // one host round trip: {||q||^2, <q,r>, ||r||^2}
       const double qq = o[0];
       rn2 = o[3];
@@ -121,6 +128,157 @@ KrylovResult gcr(Ctx& c, GcrSpace& S, const OpFn& A, const OpFn* K, void* x, con
 }
 
 // BiCGStab (van der Vorst); s is formed in place of r.
+// ---------------------------------------------------------------------------
+// lockstep flexible GCR over a batch of right-hand sides: every step applies
+// K and A to the whole batch in one pass; orthogonalisation and updates use
+// per-right-hand-side coefficients held on the device (one host read of the
+// nrhs x {||q||^2, <q,r>, ||r||^2} per step).  A right-hand side that has
+// reached its tolerance keeps taking steps (its corrections are tiny) until
+// the whole batch has converged.
+// ---------------------------------------------------------------------------
+void GcrSpaceB::ensure(int restart) {
+  const size_t b = bytes();
+  if ((int)Z.size() < restart) {
+    Z.resize(restart);
+    Q.resize(restart);
+  }
+  for (int k = 0; k < restart; ++k) {
+    if (Z[k].n < b) Z[k].alloc(b);
+    if (Q[k].n < b) Q[k].alloc(b);
+  }
+  if (r.n < b) r.alloc(b);
+  const size_t sb = (size_t)kMaxBatch * kGcrCoefs * sizeof(double);
+  if (scal.n < sb) scal.alloc(sb);
+}
+
+std::vector<KrylovResult> gcr_b(Ctx& c, GcrSpaceB& S, const OpFn& A, const OpFn* K, void* x, const void* b,
+                                bool x_zero, double tol, const double* target_norm, int restart, int maxiter,
+                                bool fixed) {
+  const int nr = S.nrhs;
+  if (nr < 1 || nr > kMaxBatch) fail(WCMG_EINVAL, "batch size out of range");
+  S.ensure(restart);
+  const int prec = S.prec;
+  const size_t n = S.n, vs = S.vs;
+  const size_t es = prec == WCMG_F64 ? 16 : 8;
+  hipStream_t st = c.st;
+  Reducer& R = c.red;
+  void* r = S.r.p;
+  std::vector<KrylovResult> res(nr);
+  auto each = [&](auto&& f) {
+    for (int i = 0; i < nr; ++i) f(i, (size_t)i * vs * es);
+  };
+  if (x_zero) {
+    each([&](int, size_t o) {
+      blas_zero(prec, (char*)x + o, n, st);
+      blas_copy(prec, (char*)r + o, (const char*)b + o, n, st);
+    });
+  } else {
+    A(r, x);
+    each([&](int, size_t o) { blas_axpby(prec, 1.0, 0.0, (const char*)b + o, -1.0, 0.0, (char*)r + o, n, st); });
+  }
+  std::vector<double> rn2(nr), target(nr);
+  std::vector<char> done(nr, 0), conv(nr, 0);
+  if (!fixed) {
+    blas_norm2_b(prec, r, vs, n, nr, R.outb(R.dres(), 1), st);
+    const double* h = R.fetch(nr);
+    for (int i = 0; i < nr; ++i) rn2[i] = h[i];
+  }
+  bool all = true;
+  for (int i = 0; i < nr; ++i) {
+    target[i] = tol * target_norm[i];
+    if (!finite(rn2[i])) {
+      res[i].status = WCMG_ENAN;
+      done[i] = 1;
+    } else if (std::sqrt(rn2[i]) <= target[i]) {
+      done[i] = conv[i] = 1;
+    }
+    all = all && done[i];
+  }
+  double* cbase = S.scal.as<double>();
+  double* beta = cbase;
+  double* qa = cbase + 2 * (kMaxRestart + 16);
+  const size_t cs = kGcrCoefs;
+  std::vector<const void*> Qp(restart), Zp(restart);
+  int iters = 0;
+  if (!(all && !fixed)) {
+    while (iters < maxiter) {
+      int k = 0;
+      bool stop = false;
+      for (; k < restart;) {
+        void* z = S.Z[k].p;
+        void* q = S.Q[k].p;
+        Qp[k] = q;
+        Zp[k] = z;
+        if (K)
+          (*K)(z, r);
+        else
+          each([&](int, size_t o) { blas_copy(prec, (char*)z + o, (const char*)r + o, n, st); });
+        A(q, z);
+        if (k > 0) blas_multi_cdot_b(prec, Qp.data(), k, q, vs, n, nr, R.outb(beta, cs), st);
+        blas_gcr_orth_b(prec, Qp.data(), Zp.data(), k, q, z, r, vs, n, nr, beta, cs, qa, cs, R.outb(qa + 4 * k, cs),
+                        st);
+        blas_gcr_update_r_b(prec, q, r, vs, n, nr, qa + 4 * k, cs, R.outb(qa + 4 * k + 3, cs), st);
+        ++k;
+        ++iters;
+        if (fixed) {
+          for (int i = 0; i < nr; ++i) res[i].iters = iters;
+          if (iters >= maxiter) {
+            stop = true;
+            break;
+          }
+          continue;
+        }
+        const double* o = R.fetch_rows(qa + 4 * k - 4, cs, 4, nr);
+        all = true;
+        for (int i = 0; i < nr; ++i) {
+          const double qq = o[4 * i];
+          rn2[i] = o[4 * i + 3];
+          if (!done[i]) {
+            res[i].iters = iters;
+            if (!finite(qq) || !finite(rn2[i])) {
+              res[i].status = WCMG_ENAN;
+              done[i] = 1;
+            } else if (!(qq > 0.0)) {
+              res[i].status = WCMG_EBREAKDOWN;
+              done[i] = 1;
+            } else if (!fixed && std::sqrt(rn2[i]) <= target[i]) {
+              done[i] = 1;
+            }
+          }
+          all = all && done[i];
+        }
+        if ((!fixed && all) || iters >= maxiter) {
+          stop = true;
+          break;
+        }
+      }
+      if (k > 0) blas_gcr_update_x_b(prec, Zp.data(), k, x, vs, n, nr, qa, cs, st);
+      if (fixed) break;
+      // true residuals at the end of every cycle
+      A(r, x);
+      each([&](int, size_t o) { blas_axpby(prec, 1.0, 0.0, (const char*)b + o, -1.0, 0.0, (char*)r + o, n, st); });
+      blas_norm2_b(prec, r, vs, n, nr, R.outb(R.dres(), 1), st);
+      const double* h = R.fetch(nr);
+      all = true;
+      for (int i = 0; i < nr; ++i) {
+        rn2[i] = h[i];
+        if (res[i].status == WCMG_OK) {
+          conv[i] = finite(rn2[i]) && std::sqrt(rn2[i]) <= target[i];
+          done[i] = conv[i];
+        }
+        all = all && (done[i] || res[i].status != WCMG_OK);
+      }
+      if (all) break;
+      (void)stop;
+    }
+  }
+  for (int i = 0; i < nr; ++i) {
+    res[i].rel_res = target_norm[i] > 0 ? std::sqrt(rn2[i]) / target_norm[i] : 0.0;
+    if (!fixed && !conv[i] && res[i].status == WCMG_OK) res[i].status = WCMG_ENOCONV;
+  }
+  return res;
+}
+
 // relative size of <rhat, r> or <rhat, A p> below which BiCGStab restarts
 // (exact breakdown only: restarting on near-breakdown made the iteration
 // diverge on operators whose spectrum surrounds the origin)
@@ -252,10 +410,29 @@ struct MGSolver {
     DBuf cb, cc, cbr, cy;       // right-hand side, solution, reduced forms
     DBuf rfull, e, res, Ar;     // preconditioner and smoother work of this level
     GcrSpace space{};
+    GcrSpaceB bspace{};         // lockstep space for batches
+    int batch = 1;              // right-hand sides the buffers hold
     long calls = 0, iters = 0;
   };
+  int batch = 1;  // right-hand sides the fine buffers hold
   std::vector<Level> lv;  // lv[li]: coarse level li + 1
   long calls = 0, iters = 0;
+  // work buffers owned by the preconditioner: a captured graph keeps their
+  // addresses, so nothing outside may reallocate them
+  FineWork fwork;
+  CoarseWork cwork;
+  // graph mode (cycle_mode 2): the preconditioner captured once and replayed
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  DBuf g_r, g_z;
+
+  ~MGSolver() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+  bool fixed() const { return L.params.cycle_mode > 0; }
 
   MGSolver(Ctx& ctx, LatticeState& lat) : c(ctx), L(lat) {
     sp = L.params.smoother_prec == WCMG_F64 ? WCMG_F64 : WCMG_F32;
@@ -282,7 +459,7 @@ struct MGSolver {
   int nlev() const { return L.params.nlevels; }
   const void* vecs(int prec) const { return prec == WCMG_F64 ? L.T0.v64.p : L.T0.v32.p; }
   CoarseOp cop(int li) {
-    CoarseOp o{L.levels[li].get(), cp, &c.cw[cp == WCMG_F64 ? 0 : 1], c.st, &c.timer};
+    CoarseOp o{L.levels[li].get(), cp, &cwork, c.st, &c.timer};
     o.timer_base = 20 + 2 * li;
     return o;
   }
@@ -303,16 +480,17 @@ struct MGSolver {
     OpFn Kf = [this, li](void* o, const void* i) { precondition_coarse(li, o, i); };
     const OpFn* K = (!last && C.cg.split) ? &Kf : nullptr;
     KrylovResult kr;
+    const bool fx = fixed();
     if (C.cg.split) {
       op.reduced_source(V.cbr.p, in);
-      double bn = std::sqrt(norm2(c, cp, V.cbr.p, op.neven()));
+      double bn = fx ? 1.0 : std::sqrt(norm2(c, cp, V.cbr.p, op.neven()));
       OpFn A = [&](void* o, const void* i) { op.Dr(o, i); };
-      kr = gcr(c, V.space, A, K, V.cy.p, V.cbr.p, true, p.tol[li], bn, p.restart[li], p.max_iter[li]);
+      kr = gcr(c, V.space, A, K, V.cy.p, V.cbr.p, true, p.tol[li], bn, p.restart[li], p.max_iter[li], fx);
       op.reconstruct(out, V.cy.p, in);
     } else {
-      double bn = std::sqrt(norm2(c, cp, in, op.nall()));
+      double bn = fx ? 1.0 : std::sqrt(norm2(c, cp, in, op.nall()));
       OpFn A = [&](void* o, const void* i) { op.Dfull(o, i); };
-      kr = gcr(c, V.space, A, nullptr, out, in, true, p.tol[li], bn, p.restart[li], p.max_iter[li]);
+      kr = gcr(c, V.space, A, nullptr, out, in, true, p.tol[li], bn, p.restart[li], p.max_iter[li], fx);
     }
     V.iters += kr.iters;
   }
@@ -357,9 +535,45 @@ struct MGSolver {
 
   // K(r_e): even part of P (coarse solve) R (r_e, 0), then MR smoothing on D_r
   void precondition(void* z64, const void* r64) {
+    if (L.params.cycle_mode == 2) return precondition_graph(z64, r64);
+    precondition_body(z64, r64);
+  }
+
+  // cycle_mode 2: the body (kernels only: fixed inner lengths, device
+  // scalars) is captured once on a side stream into a graph that works on
+  // buffers of its own, and replayed on the context stream
+  void precondition_graph(void* z64, const void* r64) {
+    const Geom& g = L.F.g;
+    const size_t n = (size_t)12 * g.Vh;
+    if (!gexec) {
+      const size_t hb = spinor_bytes(WCMG_F64, g.Vh);
+      g_r.alloc(hb);
+      g_z.alloc(hb);
+      blas_copy(WCMG_F64, g_r.p, r64, n, c.st);
+      precondition_body(g_z.p, g_r.p);  // eager run: every buffer is allocated before the capture
+      HIPCHK(hipStreamSynchronize(c.st));
+      if (!cap) HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+      hipStream_t keep = c.st;
+      const bool timer_on = c.timer.on;
+      c.timer.on = false;
+      c.st = cap;
+      HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+      precondition_body(g_z.p, g_r.p);
+      hipError_t e = hipStreamEndCapture(cap, &graph);
+      c.st = keep;
+      c.timer.on = timer_on;
+      HIPCHK(e);
+      HIPCHK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+    }
+    blas_copy(WCMG_F64, g_r.p, r64, n, c.st);
+    HIPCHK(hipGraphLaunch(gexec, c.st));
+    blas_copy(WCMG_F64, z64, g_z.p, n, c.st);
+  }
+
+  void precondition_body(void* z64, const void* r64) {
     const Geom& g = L.F.g;
     hipStream_t st = c.st;
-    FineOp op{&c, &L.F, sp, &c.fw[sp], st};
+    FineOp op{&c, &L.F, sp, &fwork, st};
     const size_t n = (size_t)12 * g.Vh;
     CoarseLevel& C = *L.levels[0];
     Level& V = lv[0];
@@ -369,6 +583,148 @@ struct MGSolver {
     launch_prolong(sp, e_s.p, V.cc.p, vecs(sp), L.T0.nvec, 0, g, L.T0.bg, st);
     mr_smooth([&](void* o, const void* i) { op.Dr(o, i); }, sp, e_s.p, r_s.p, res_s.p, Ar_s.p, n);
     spinor_convert(WCMG_F64, z64, sp, e_s.p, g.Vh, st);
+    ++calls;
+  }
+
+  // ---- batches of right-hand sides (lockstep) ----
+  void ensure_batch(int nrhs) {
+    const Geom& g = L.F.g;
+    if (batch < nrhs) {
+      const size_t hb = spinor_bytes(sp, g.Vh) * nrhs;
+      for (DBuf* b : {&r_s, &e_s, &res_s, &Ar_s}) b->alloc(hb);
+      batch = nrhs;
+    }
+    const size_t cs = (cp == WCMG_F64 ? 16 : 8);
+    for (size_t li = 0; li < lv.size(); ++li) {
+      Level& V = lv[li];
+      if (V.batch >= nrhs) continue;
+      CoarseLevel& C = *L.levels[li];
+      const size_t nall = (size_t)C.cg.V * C.cg.n;
+      for (DBuf* b : {&V.cb, &V.cc, &V.cbr, &V.cy, &V.rfull, &V.e, &V.res, &V.Ar}) b->alloc(nall * cs * nrhs);
+      V.batch = nrhs;
+    }
+  }
+
+  // MR smoothing of nrhs right-hand sides (n elements each, vs apart) in lockstep
+  template <typename DrFn>
+  void mr_smooth_b(const DrFn& Dr, int prec, void* e, const void* r, void* res, void* Ar, size_t n, size_t vs,
+                   int nrhs) {
+    const int nu = L.params.nu_post;
+    if (nu <= 0) return;
+    hipStream_t st = c.st;
+    const size_t es = prec == WCMG_F64 ? 16 : 8;
+    Dr(Ar, e);
+    for (int i = 0; i < nrhs; ++i) {
+      const size_t o = (size_t)i * vs * es;
+      blas_copy(prec, (char*)res + o, (const char*)r + o, n, st);
+      blas_axpby(prec, -1.0, 0.0, (char*)Ar + o, 1.0, 0.0, (char*)res + o, n, st);
+    }
+    for (int it = 0; it < nu; ++it) {
+      Dr(Ar, res);
+      blas_cdot_norm_b(prec, Ar, res, vs, n, nrhs, c.red.outb(c.red.dres(), 3), st);
+      blas_mr_update_b(prec, c.red.dres(), 3, e, res, Ar, vs, n, nrhs, st);
+    }
+  }
+
+  void coarse_solve_b(int li, void* out, void* in, int nrhs) {
+    CoarseLevel& C = *L.levels[li];
+    Level& V = lv[li];
+    CoarseOp op = cop(li);
+    const wcmg_mg_params& p = L.params;
+    const bool last = li + 1 == nlev();
+    const size_t cs = op.csize(), na = op.nall();
+    ++V.calls;
+    if (last && p.coarsest == 1) {
+      for (int i = 0; i < nrhs; ++i)
+        dense_inverse_apply(cp, L.dense.p, L.dense_n, (char*)in + i * na * cs, (char*)out + i * na * cs, c.st);
+      V.iters += 1;
+      return;
+    }
+    OpFn Kf = [this, li, nrhs](void* o, const void* i) { precondition_coarse_b(li, o, i, nrhs); };
+    const OpFn* K = (!last && C.cg.split) ? &Kf : nullptr;
+    V.bspace.prec = cp;
+    V.bspace.nrhs = nrhs;
+    V.bspace.vs = na;
+    std::vector<double> bn(nrhs);
+    std::vector<KrylovResult> kr;
+    const bool fx = fixed();
+    auto norms = [&](const void* v, size_t cnt) {
+      if (fx) {
+        std::fill(bn.begin(), bn.end(), 1.0);
+        return;
+      }
+      blas_norm2_b(cp, v, na, cnt, nrhs, c.red.outb(c.red.dres(), 1), c.st);
+      const double* h = c.red.fetch(nrhs);
+      for (int i = 0; i < nrhs; ++i) bn[i] = std::sqrt(h[i]);
+    };
+    if (C.cg.split) {
+      op.reduced_source(V.cbr.p, in, nrhs);
+      V.bspace.n = op.neven();
+      norms(V.cbr.p, op.neven());
+      OpFn A = [&](void* o, const void* i) { op.Dr(o, i, nrhs); };
+      kr = gcr_b(c, V.bspace, A, K, V.cy.p, V.cbr.p, true, p.tol[li], bn.data(), p.restart[li], p.max_iter[li], fx);
+      op.reconstruct(out, V.cy.p, in, nrhs);
+    } else {
+      V.bspace.n = na;
+      norms(in, na);
+      OpFn A = [&](void* o, const void* i) { op.Dfull(o, i, nrhs); };
+      kr = gcr_b(c, V.bspace, A, nullptr, out, in, true, p.tol[li], bn.data(), p.restart[li], p.max_iter[li], fx);
+    }
+    int mx = 0;
+    for (auto& k : kr) mx = std::max(mx, k.iters);
+    V.iters += mx;
+  }
+
+  void precondition_coarse_b(int li, void* z, const void* r, int nrhs) {
+    hipStream_t st = c.st;
+    CoarseLevel& C = *L.levels[li];
+    CoarseTransfer& T = *L.ctr[li];
+    CoarseLevel& Cn = *L.levels[li + 1];
+    Level& V = lv[li];
+    Level& W = lv[li + 1];
+    CoarseOp op = cop(li);
+    const size_t ne = op.neven(), na = op.nall(), cs = op.csize();
+    const size_t nan = (size_t)Cn.cg.V * Cn.cg.n;
+    const void* P = cp == WCMG_F64 ? T.v64.p : T.v32.p;
+    for (int i = 0; i < nrhs; ++i) {
+      const size_t o = (size_t)i * na * cs;
+      blas_copy(cp, (char*)V.rfull.p + o, (const char*)r + o, ne, st);
+      blas_zero(cp, (char*)V.rfull.p + o + ne * cs, na - ne, st);
+    }
+    launch_ctr_restrict(cp, W.cb.p, Cn.cg.n, nan, V.rfull.p, na, P, T.vstride(), T.members.as<int>(), Cn.cg.V,
+                        T.bg.bvol, C.cg.n, T.nvec, nrhs, st);
+    coarse_solve_b(li + 1, W.cc.p, W.cb.p, nrhs);
+    launch_ctr_prolong(cp, V.e.p, na, W.cc.p, nan, P, T.vstride(), T.blk.as<int>(), C.cg.V, C.cg.n, T.nvec, nrhs, st);
+    mr_smooth_b([&](void* o, const void* i) { op.Dr(o, i, nrhs); }, cp, V.e.p, r, V.res.p, V.Ar.p, ne, na, nrhs);
+    for (int i = 0; i < nrhs; ++i) {
+      const size_t o = (size_t)i * na * cs;
+      blas_copy(cp, (char*)z + o, (const char*)V.e.p + o, ne, st);
+    }
+  }
+
+  // batched K(r_e) on nrhs FP64 even halves stored back to back
+  void precondition_b(void* z64, const void* r64, int nrhs) {
+    ensure_batch(nrhs);
+    const Geom& g = L.F.g;
+    hipStream_t st = c.st;
+    FineOp op{&c, &L.F, sp, &fwork, st};
+    const size_t n = (size_t)12 * g.Vh;
+    const size_t h64 = spinor_bytes(WCMG_F64, g.Vh), hs = spinor_bytes(sp, g.Vh);
+    CoarseLevel& C = *L.levels[0];
+    Level& V = lv[0];
+    const size_t na = (size_t)C.cg.V * C.cg.n, cs = cp == WCMG_F64 ? 16 : 8;
+    for (int i = 0; i < nrhs; ++i) {
+      spinor_convert(sp, (char*)r_s.p + i * hs, WCMG_F64, (const char*)r64 + i * h64, g.Vh, st);
+      launch_restrict(sp, (char*)V.cb.p + i * na * cs, C.cg.n, 1, (char*)r_s.p + i * hs, vecs(sp), L.T0.nvec, 0, g,
+                      L.T0.bg, false, st);
+    }
+    coarse_solve_b(0, V.cc.p, V.cb.p, nrhs);
+    for (int i = 0; i < nrhs; ++i)
+      launch_prolong(sp, (char*)e_s.p + i * hs, (char*)V.cc.p + i * na * cs, vecs(sp), L.T0.nvec, 0, g, L.T0.bg,
+                     st);
+    mr_smooth_b([&](void* o, const void* i) { op.Dr(o, i, nrhs); }, sp, e_s.p, r_s.p, res_s.p, Ar_s.p, n, n, nrhs);
+    for (int i = 0; i < nrhs; ++i)
+      spinor_convert(WCMG_F64, (char*)z64 + i * h64, sp, (char*)e_s.p + i * hs, g.Vh, st);
     ++calls;
   }
 };
@@ -551,6 +907,16 @@ static void finalize_coarse(Ctx& c, CoarseLevel& C, int* flag) {
   HIPCHK(hipMemcpyAsync(hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   if (hflag[0]) fail(WCMG_ERANK, "singular coarse site block");
+  // FP16 fragments for the batched stencil on the matrix cores (red-black levels)
+  C.has_frag = false;
+  if (C.cg.split && mfma_coarse_supported(n)) {
+    C.frag.alloc(mfma_fragment_bytes(V, n));
+    HIPCHK(hipMemsetAsync(flag, 0, 64, st));
+    build_mfma_fragments(C.frag.p, C.Yt[0].p, V, n, flag, st);
+    HIPCHK(hipMemcpyAsync(hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    C.has_frag = hflag[0] == 0;
+  }
 }
 
 // dense FP64 inverse of the full operator of coarse level index li (the coarsest)
@@ -787,6 +1153,76 @@ void solve_rhs(Ctx& c, LatticeState& L, int solver, void* x_e, void* x_o, const 
   if (s.status == WCMG_OK && !(s.true_rel_res <= tol * 1.0000001)) s.status = WCMG_ENOCONV;
   s.t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (stats) *stats = s;
+}
+
+// Multigrid solve of a batch of right-hand sides in lockstep: one FP64 outer
+// GCR per right-hand side, every operator and preconditioner application done
+// for the whole batch at once (links, clover and coarse matrices read once per
+// kernel for all right-hand sides of a group).
+void solve_batch(Ctx& c, LatticeState& L, void* x_e, void* x_o, const void* b_e, const void* b_o, int nrhs,
+                 bool x_zero, double tol, wcmg_stats* stats) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (nrhs < 1 || nrhs > kMaxBatch) fail(WCMG_EINVAL, "batch size out of range");
+  require_hierarchy(L);
+  const Geom& g = L.F.g;
+  hipStream_t st = c.st;
+  const size_t hb = spinor_bytes(WCMG_F64, g.Vh);
+  const size_t n = (size_t)12 * g.Vh;
+  FineOp op{&c, &L.F, WCMG_F64, &c.fw[0], st};
+  std::vector<double> bn(nrhs);
+  blas_norm2_b(WCMG_F64, b_e, n, n, nrhs, c.red.outb(c.red.dres(), 1), st);
+  blas_norm2_b(WCMG_F64, b_o, n, n, nrhs, c.red.outb(c.red.dres() + 32, 1), st);
+  {
+    const double* h = c.red.fetch(64);
+    for (int i = 0; i < nrhs; ++i) bn[i] = std::sqrt(h[i] + h[32 + i]);
+  }
+  for (int i = 0; i < nrhs; ++i)
+    if (!finite(bn[i])) fail(WCMG_ENAN, "right-hand side is not finite");
+  void* br = c.scratch_buf(0, hb * nrhs);
+  void* y = c.scratch_buf(1, hb * nrhs);
+  op.reduced_source(br, b_e, b_o, nrhs);
+  if (!x_zero) op.clover(y, x_e, 0, 0, nrhs);  // y_e = D_ee x_e
+  const wcmg_mg_params& p = L.params;
+  if (!L.mg) L.mg = std::make_shared<MGSolver>(c, L);
+  MGSolver& mg = *L.mg;
+  mg.calls = 0;
+  for (auto& lvl : mg.lv) lvl.calls = lvl.iters = 0;
+  OpFn Dr = [&](void* o, const void* i) { op.Dr(o, i, nrhs); };
+  OpFn K = [&](void* o, const void* i) { mg.precondition_b(o, i, nrhs); };
+  GcrSpaceB& outer = c.outer_b;
+  outer.prec = WCMG_F64;
+  outer.n = n;
+  outer.vs = n;
+  outer.nrhs = nrhs;
+  // a zero right-hand side has a zero solution; give it a unit target so the
+  // batch does not wait for it
+  std::vector<double> tn(bn);
+  for (double& v : tn)
+    if (v == 0.0) v = 1.0;
+  std::vector<KrylovResult> kr = gcr_b(c, outer, Dr, &K, y, br, x_zero, tol, tn.data(), p.outer_restart,
+                                       p.outer_max_iter);
+  op.reconstruct(x_e, x_o, y, b_o, nrhs);
+  // true residuals of the full system in FP64
+  void* te = c.scratch_buf(2, hb * nrhs);
+  void* to = c.scratch_buf(3, hb * nrhs);
+  op.D(te, to, x_e, x_o, nrhs);
+  blas_axpby(WCMG_F64, 1.0, 0.0, b_e, -1.0, 0.0, te, n * nrhs, st);
+  blas_axpby(WCMG_F64, 1.0, 0.0, b_o, -1.0, 0.0, to, n * nrhs, st);
+  blas_norm2_b(WCMG_F64, te, n, n, nrhs, c.red.outb(c.red.dres(), 1), st);
+  blas_norm2_b(WCMG_F64, to, n, n, nrhs, c.red.outb(c.red.dres() + 32, 1), st);
+  const double* h = c.red.fetch(64);
+  const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  for (int i = 0; i < nrhs; ++i) {
+    wcmg_stats s{};
+    s.iters = kr[i].iters;
+    s.status = kr[i].status;
+    s.true_rel_res = bn[i] > 0 ? std::sqrt(h[i] + h[32 + i]) / bn[i] : 0.0;
+    for (size_t l = 0; l < mg.lv.size() && l < 3; ++l)
+      s.inner_iters[l] = mg.lv[l].calls ? (double)mg.lv[l].iters / mg.lv[l].calls : 0.0;
+    if (s.status == WCMG_OK && !(s.true_rel_res <= tol * 1.0000001)) s.status = WCMG_ENOCONV;
+    s.t_solve_s = dt;
+    if (stats) stats[i] = s;
+  }
 }
 
 }  // namespace wcmg

@@ -194,3 +194,51 @@ def test_global_sum_matches_torch(n, dtype):
                                        float(torch.linalg.vector_norm(y.to(torch.complex128))))
     assert ctx.dot(x, y) == got   # bitwise reproducible
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", [w.F64, w.F32, w.F16])
+def test_batched_apply_equals_single(setup, prec):
+    """Five right-hand sides in one batched launch (groups of 4/2 plus a
+    partial group) give the per-right-hand-side results to rounding."""
+    c, op, ctx = setup
+    dims = c["dims"]
+    V = int(np.prod(dims))
+    rng = np.random.default_rng(21)
+    v = rng.standard_normal((5, V, 4, 3)) + 1j * rng.standard_normal((5, V, 4, 3))
+    vt = torch.from_numpy(v.reshape((5,) + tuple(reversed(dims)) + (4, 3))).cuda()
+    tol = {w.F64: 1e-14, w.F32: 1e-6, w.F16: 1e-3}[prec]
+    for which in (w.OP_FULL, w.OP_SCHUR, w.OP_DP):
+        for dag in (False, True):
+            f = ctx.apply_Ddag if dag else ctx.apply_D
+            src = vt
+            if which == w.OP_SCHUR:
+                src = vt.clone()
+                m = torch.from_numpy((op.lat.parity == 1).reshape(tuple(reversed(dims)))).cuda()
+                src[:, m] = 0
+            got = f(src, which, prec).cpu().numpy()
+            for r in range(5):
+                one = f(src[r:r + 1].contiguous(), which, prec).cpu().numpy()[0]
+                err = np.linalg.norm(got[r] - one) / np.linalg.norm(one)
+                assert err < tol, (which, dag, r, err)
+
+
+def test_autotuned_launches_are_bitwise_identical(setup):
+    """The autotuner only picks a launch shape: results must not change."""
+    c, op, ctx = setup
+    dims = c["dims"]
+    V = int(np.prod(dims))
+    rng = np.random.default_rng(23)
+    v = rng.standard_normal((5, V, 4, 3)) + 1j * rng.standard_normal((5, V, 4, 3))
+    vt = torch.from_numpy(v.reshape((5,) + tuple(reversed(dims)) + (4, 3))).cuda()
+    ref = {}
+    for prec in (w.F64, w.F32, w.F16):
+        for nr in (1, 5):
+            ref[(prec, nr)] = ctx.apply_D(vt[:nr].contiguous(), w.OP_FULL, prec).cpu()
+    ctx.autotune(True)
+    for prec in (w.F64, w.F32, w.F16):
+        for nr in (1, 5):
+            got = ctx.apply_D(vt[:nr].contiguous(), w.OP_FULL, prec).cpu()
+            assert torch.equal(got, ref[(prec, nr)]), (prec, nr)
+    rep = ctx.autotune_report()
+    assert len(rep) >= 6 and all(r["threads"] in (64, 128, 256) for r in rep)
+    ctx.autotune(False)

@@ -227,3 +227,32 @@ def test_mg_solve_16x16x16x32_full_size():
     x2r = x2.cpu().numpy().reshape(op.shape)
     assert norm(xr - x2r) / norm(x2r) < 1e-7
     ctx.close()
+
+
+def test_batched_coarse_stencil_on_matrix_cores():
+    """Batches of FP32 coarse red-black applies run on the matrix cores with
+    FP16 operands: they must agree with the FP64 single applies to FP16
+    accuracy, for a full group of 16 and a partial second group."""
+    cfg = inputs.config("c2_16x16x16x32")
+    dims = cfg["dims"]
+    U = inputs.gauge_field(dims, cfg["eps"], cfg["gauge_seed"], ape_sweeps=cfg["ape"])
+    ctx = w.Context(dims)
+    ctx.set_gauge(torch.from_numpy(U).cuda())
+    ctx.set_clover(-0.25, cfg["csw"])
+    ctx.set_mg_params(w.default_params(block=cfg["blocks"], nvec=cfg["nvec"], seed=cfg["setup_seed"]))
+    ctx.build_null_vectors()
+    ctx.build_coarse()
+    Vc = int(np.prod(ctx.coarse_dims()))
+    n = 2 * cfg["nvec"][0]
+    rng = np.random.default_rng(31)
+    nrhs = 19
+    v = rng.standard_normal((nrhs, Vc, n)) + 1j * rng.standard_normal((nrhs, Vc, n))
+    # scale the right-hand sides differently: the per-block FP16 scaling must follow each
+    v *= np.logspace(-6, 3, nrhs)[:, None, None]
+    vt = torch.from_numpy(v).cuda()
+    got = ctx.apply_coarse(vt, level=1, op=w.OP_SCHUR, prec=w.F32).cpu().numpy()
+    for r in range(nrhs):
+        want = ctx.apply_coarse(vt[r:r + 1].contiguous(), level=1, op=w.OP_SCHUR, prec=w.F64).cpu().numpy()[0]
+        err = np.linalg.norm(got[r] - want) / np.linalg.norm(want)
+        assert err < 5e-3, (r, err)
+    ctx.close()
