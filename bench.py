@@ -73,7 +73,7 @@ def kernel_table(ctxs, vh, coarse_sites_h, coarse_n):
             flops = dslash_flops_per_site(diag, postinv) * vh
         else:
             cs = 16 if kid == 20 else 8
-            name = "k_coarse_hop<%s>" % ("double" if kid == 20 else "float")
+            name = "k_coarse_hop<%s, 1>" % ("double" if kid == 20 else "float")
             bytes_launch = coarse_sites_h * (8 * coarse_n * coarse_n + 2.5 * coarse_n) * cs
             flops = coarse_sites_h * 8 * coarse_n * coarse_n * 8
         avg_ms = ms / n
@@ -138,6 +138,68 @@ def dslash_headline(w, torch, inputs):
     return out
 
 
+def batched_leg(w, torch, inputs, np):
+    """24^3x64, m0 = -0.25, 12 Z2 sources: lockstep multi-right-hand-side MG-GCR
+    (batched fine kernels, coarse stencil on the matrix cores) against the
+    same 12 right-hand sides solved one at a time; every solution checked
+    against a true relative residual of 1e-10 in FP64."""
+    cfg = inputs.config("c3_24x24x24x64")
+    dims = cfg["dims"]
+    U = inputs.gauge_field(dims, cfg["eps"], cfg["gauge_seed"], ape_sweeps=cfg["ape"])
+    ctx = w.Context(dims)
+    ctx.set_gauge(torch.from_numpy(U).cuda())
+    ctx.set_clover(cfg["m0"][0], cfg["csw"])
+    ctx.set_mg_params(mg_params(w, cfg))
+    t = time.perf_counter()
+    ctx.build_null_vectors()
+    ctx.build_coarse()
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t
+    print("batched leg: setup %.1f s" % setup_s, file=sys.stderr, flush=True)
+    nrhs = cfg["nrhs"]
+    b = np.stack([inputs.z2_source(dims, s) for s in cfg["source_seeds"][:nrhs]])
+    bt = torch.from_numpy(b.reshape((nrhs,) + tuple(reversed(dims)) + (4, 3))).cuda()
+    ctx.solve(bt[:2].contiguous(), w.MG_GCR, cfg["tol"])  # warm-up of the batched path
+    torch.cuda.synchronize()
+    ctx.timer_enable(True)
+    t = time.perf_counter()
+    xb, sb = ctx.solve(bt, w.MG_GCR, cfg["tol"])
+    torch.cuda.synchronize()
+    batched_s = time.perf_counter() - t
+    # matrix-core coarse stencil: one timer entry per red-black apply (two launches)
+    n_dr, ms_dr = ctx.timer_read(50)
+    ctx.timer_enable(False)
+    n = 2 * cfg["nvec"][0]
+    vch = int(np.prod(dims)) // int(np.prod(cfg["blocks"][0])) // 2
+    k = nrhs
+    bytes_dr = 2 * vch * (8 * n * n * 4 + k * (9 * n + n) * 8)
+    flops_dr = 2 * vch * 8 * n * n * 8 * k
+    mfma = None
+    if n_dr:
+        us = ms_dr / n_dr * 1e3
+        mfma = {"kernel": "k_coarse_hop_mfma<%d>" % (n // 16), "applies": n_dr, "avg_apply_us": round(us, 2),
+                "GBps": round(bytes_dr / (us * 1e-6) / 1e9, 1), "TFLOPs": round(flops_dr / (us * 1e-6) / 1e12, 2),
+                "mfma_utilisation_vs_fp16_dense_2500": round(flops_dr / (us * 1e-6) / 1e12 / 2500.0, 4),
+                "bytes_per_apply": bytes_dr, "flops_per_apply": flops_dr}
+    print("batched leg: lockstep %.2f s" % batched_s, file=sys.stderr, flush=True)
+    t = time.perf_counter()
+    single = []
+    for r in range(nrhs):
+        _, s1 = ctx.solve(bt[r:r + 1].contiguous(), w.MG_GCR, cfg["tol"])
+        single.append(s1[0])
+    torch.cuda.synchronize()
+    single_s = time.perf_counter() - t
+    print("batched leg: one at a time %.2f s" % single_s, file=sys.stderr, flush=True)
+    ctx.close()
+    return {"workload": "24^3x64, m0=-0.25, 12 Z2 sources, 4^4 blocks, Nv=24",
+            "setup_s": round(setup_s, 2), "lockstep_s": round(batched_s, 3),
+            "one_at_a_time_s": round(single_s, 3), "speedup": round(single_s / batched_s, 2),
+            "lockstep_outer_iters": [s["iters"] for s in sb],
+            "one_at_a_time_outer_iters": [s["iters"] for s in single],
+            "max_true_rel_res": max(max(s["true_rel_res"] for s in sb), max(s["true_rel_res"] for s in single)),
+            "coarse_stencil_matrix_cores": mfma}
+
+
 def mg_params(w, cfg):
     """Multigrid parameters used for the timed solves.  The paper reports the
     best parameter set per case and a per-level tolerance near 0.1; these
@@ -157,6 +219,12 @@ def main():
     ap.add_argument("--no-headline", action="store_true", help="skip the 24^3x64 Dslash measurement")
     ap.add_argument("--no-bicgstab", action="store_true",
                     help="skip the BiCGStab comparison (short runs under a profiler)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the 24^3x64 Dslash measurement (runs under a profiler)")
+    ap.add_argument("--batched", action="store_true",
+                    help="add the 24^3x64 multi-right-hand-side leg: 12 Z2 sources in lockstep vs one at a time")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (the reference kernel of the traffic counters)")
     ap.add_argument("--masses", type=str, default=None, help="comma-separated subset of the m0 sweep")
     ap.add_argument("--near-critical", type=str, default="-0.02",
                     help="comma-separated supplementary masses close to the critical mass of this ensemble, "
@@ -176,6 +244,16 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.calibrate_copy:
+        src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if args.headline_only:
+        print(json.dumps({"dslash_24x24x24x64": dslash_headline(w, torch, inputs)}))
+        return
     cfg = inputs.config("c2_16x16x16x32")
     dims = cfg["dims"]
     t = time.perf_counter()
@@ -284,6 +362,7 @@ def main():
     near_rows = {str(m0): mass_row(m0) for m0 in all_masses[len(masses):]}
 
     headline = None if args.no_headline else dslash_headline(w, torch, inputs)
+    batched = batched_leg(w, torch, inputs, np) if args.batched else None
     cpu = None
     if not args.no_cpu and bicg:
         conv_m = [m for m in all_masses if bicg[m]["status"] == "OK"]
@@ -320,6 +399,7 @@ def main():
         "roofline": roofline,
         "kernels": rows[:8],
         "dslash_24x24x24x64": headline,
+        "batched_24x24x24x64": batched,
         "cpu_baseline": cpu,
         "inputs_s": round(t_inputs, 2),
     }

@@ -96,7 +96,9 @@ typedef struct {
   int nu_post;                      /* MR smoothing steps after the coarse correction */
   int outer_restart;                /* restart length of the outer FP64 GCR */
   int outer_max_iter;               /* cap of the outer GCR */
-  wcmg_prec smoother_prec;          /* precision of the preconditioner (F32 or F64) */
+  wcmg_prec smoother_prec;          /* precision of the preconditioner: F64, F32, or F16 (FP32
+                                       vectors and arithmetic, half-precision links and clover in
+                                       the fine smoother; coarse levels FP32) */
   int setup_relax;                  /* GCR steps per relaxation in the setup */
   int setup_max_steps;              /* max relaxations per vector */
   double setup_rq_tol;              /* stop when |d rho| / rho < this */
@@ -173,7 +175,12 @@ int wcmg_get_coarse(void* ctx, int lat, int level, void* Y, int on_device);
 
 /* out = op(in) or op^dag(in) for nrhs canonical spinors (device).  prec is
  * the storage/arithmetic precision of the internal apply (F16 stores
- * fields in half precision with FP32 arithmetic).  Asynchronous. */
+ * fields in half precision with FP32 arithmetic).  All right-hand sides go
+ * through each kernel in one batched launch.  lat = -1 (wcmg_apply_D, op
+ * FULL or SCHUR, nrhs = 1): every lattice of the context (at most 4, of any
+ * volumes), buffers concatenated in lattice order, each kernel one launch
+ * over all lattices (a work list of per-lattice block ranges).
+ * Asynchronous. */
 int wcmg_apply_D(void* ctx, int lat, int op, int prec, void* out, const void* in, int nrhs);
 int wcmg_apply_Ddag(void* ctx, int lat, int op, int prec, void* out, const void* in, int nrhs);
 

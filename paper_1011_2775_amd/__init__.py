@@ -137,7 +137,8 @@ class Context:
     # -- operators -------------------------------------------------------------
     def _apply(self, fn, op, prec, inp, lat):
         out = torch.empty_like(inp)
-        nrhs = inp.numel() // (self.volume(lat) * 12)
+        # lat = -1: all lattices, one right-hand side each, concatenated in lattice order
+        nrhs = 1 if lat == -1 else inp.numel() // (self.volume(lat) * 12)
         check(fn(self.h, lat, op, prec, ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(inp.data_ptr()), nrhs))
         return out
 

@@ -2,10 +2,10 @@
 //
 // Vectors are flat arrays of complex numbers in double or float storage;
 // every reduction accumulates in double, first per wavefront with lane
-// shuffles, then across the 4 wavefronts of a block in LDS; a one-block
-// second pass sums the per-block partials in block order and writes the
-// result to device memory.  The grid depends only on the vector length, so
-// results are bitwise reproducible run to run.
+// shuffles, then across the 4 wavefronts of a block in LDS; a second pass
+// (one block per result) sums the per-block partials in a fixed tree and
+// writes the result to device memory.  The grids depend only on the vector
+// length, so results are bitwise reproducible run to run.
 #include "blas_common.h"
 
 namespace wcmg {
@@ -14,15 +14,24 @@ namespace {
 
 using namespace blas_detail;
 
-// Second pass (one block, one lane per output): res[k] = sum over blocks of
-// partial[b*nr + k] in block order.
-__global__ void __launch_bounds__(64) k_finalize(const RedOut o, int nr, int stride, int nblocks) {
-  const int k = threadIdx.x;
-  if (k >= nr) return;
+// Second pass, one block per output k: res[k] = sum over blocks of
+// partial[b*stride + k], each thread summing a fixed strided subset and the
+// block combining them in a fixed tree, so the order never depends on timing.
+__global__ void __launch_bounds__(kThreads) k_finalize(const RedOut o, int nr, int stride, int nblocks) {
+  const int k = blockIdx.x;
   double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) s += o.partial[(size_t)b * stride + k];
-  o.res[k] = s;
-  if (o.hres) o.hres[k] = s;
+  for (int b = threadIdx.x; b < nblocks; b += kThreads) s += o.partial[(size_t)b * stride + k];
+  __shared__ double sh[kThreads];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    o.res[k] = sh[0];
+    if (o.hres) o.hres[k] = sh[0];
+  }
 }
 
 template <typename T>
@@ -246,7 +255,7 @@ __global__ void k_mr_update(double ar, double ai, void* x, void* r, const void* 
 
 // nr results, partials laid out with `stride` doubles per block (the kernel's NR)
 void finalize(const RedOut& o, int nr, size_t n, hipStream_t st, int stride = 0) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, o, nr, stride ? stride : nr, (int)red_grid(n).x);
+  hipLaunchKernelGGL(k_finalize, dim3(nr), dim3(kThreads), 0, st, o, nr, stride ? stride : nr, (int)red_grid(n).x);
   HIPCHK(hipGetLastError());
 }
 

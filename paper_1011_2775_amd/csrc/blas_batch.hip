@@ -3,8 +3,8 @@
 // A batch holds nrhs vectors of n complex elements, vstride elements apart.
 // Grid row blockIdx.y is the right-hand side; every reduction of a batch
 // writes its per-block partials to part[rhs][block][NR] and a second pass
-// (one block per right-hand side, in block order, as in the single-vector
-// kernels) writes res[rhs * rs + k].  The GCR coefficients of right-hand
+// (one block per result and right-hand side, fixed tree, as in the
+// single-vector kernels) writes res[rhs * rs + k].  The GCR coefficients of right-hand
 // side r live at beta + r * bs and qa + r * qs (device memory), so no
 // right-hand side shares a scalar with another.
 #include "blas_common.h"
@@ -27,13 +27,20 @@ __device__ __forceinline__ void* row(void* p, size_t vs) {
   return reinterpret_cast<char*>(p) + (size_t)blockIdx.y * vs * sizeof(typename C2<T>::V);
 }
 
-__global__ void __launch_bounds__(64) k_finalize_b(RedB o, int nr, int stride, int nblocks) {
-  const int k = threadIdx.x, r = blockIdx.x;
-  if (k >= nr) return;
+// one block per (output k, right-hand side r), fixed-order tree as in the single-vector kernels
+__global__ void __launch_bounds__(kThreads) k_finalize_b(RedB o, int nr, int stride, int nblocks) {
+  const int k = blockIdx.x, r = blockIdx.y;
   const double* p = o.part + (size_t)r * nblocks * stride;
   double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) s += p[(size_t)b * stride + k];
-  o.res[(size_t)r * o.rs + k] = s;
+  for (int b = threadIdx.x; b < nblocks; b += kThreads) s += p[(size_t)b * stride + k];
+  __shared__ double sh[kThreads];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) o.res[(size_t)r * o.rs + k] = sh[0];
 }
 
 template <typename T>
@@ -193,7 +200,7 @@ static dim3 red_grid_b(size_t n, int nrhs) { return dim3(red_grid(n).x, nrhs); }
 static dim3 ew_grid_b(size_t n, int nrhs) { return dim3(ew_grid(n).x, nrhs); }
 
 static void finalize_b(const RedB& o, int nr, int stride, size_t n, int nrhs, hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize_b, dim3(nrhs), dim3(64), 0, st, o, nr, stride, (int)red_grid(n).x);
+  hipLaunchKernelGGL(k_finalize_b, dim3(nr, nrhs), dim3(kThreads), 0, st, o, nr, stride, (int)red_grid(n).x);
   HIPCHK(hipGetLastError());
 }
 

@@ -4,6 +4,8 @@
 // reproducible run to run).
 #pragma once
 
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace wcmg {
@@ -64,9 +66,14 @@ __device__ __forceinline__ void block_reduce(double (&v)[NR], const RedOut& o) {
   block_reduce_to<NR>(v, o.partial);
 }
 
-// enough blocks that every thread handles about 8 elements, at most kRedBlocks
+// enough blocks that every thread handles about 8 elements, at most
+// kRedBlocks; short vectors (the coarse levels) spread over up to 64 blocks
+// with at least one element per thread, so that a pass is not limited by the
+// latency of a handful of compute units
 inline dim3 red_grid(size_t n) {
   size_t b = (n + 8 * kThreads - 1) / (8 * kThreads);
+  const size_t spread = std::min<size_t>((n + kThreads - 1) / kThreads, 64);
+  if (b < spread) b = spread;
   if (b < 1) b = 1;
   if (b > (size_t)kRedBlocks) b = kRedBlocks;
   return dim3((unsigned)b);

@@ -238,7 +238,7 @@ int wcmg_set_clover(void* ctx, int lat, double m0, double csw, const void* A, in
     L.F.clov[WCMG_F64] = std::move(c64);
     for (int p = 1; p < 3; ++p) {
       L.F.clov[p].alloc(clover_bytes(p, g.V));
-      reals_convert(p, L.F.clov[p].p, L.F.clov[WCMG_F64].as<double>(), nreal, c->st);
+      clover_relayout(p, L.F.clov[p].p, L.F.clov[WCMG_F64].as<double>(), g.Vh, c->st);
     }
     HIPCHK(hipStreamSynchronize(c->st));
     L.F.m0 = m0;
@@ -274,8 +274,8 @@ int wcmg_set_mg_params(void* ctx, int lat, const wcmg_mg_params* p) {
   CHECK(p->outer_restart <= 64 && p->restart[0] <= 64 && p->setup_relax <= 64, WCMG_EINVAL,
         "restart lengths are limited to 64");
   CHECK(p->nu_post >= 0, WCMG_EINVAL, "nu_post must be >= 0");
-  CHECK(p->smoother_prec == WCMG_F64 || p->smoother_prec == WCMG_F32, WCMG_EINVAL,
-        "smoother precision must be F64 or F32");
+  CHECK(p->smoother_prec == WCMG_F64 || p->smoother_prec == WCMG_F32 || p->smoother_prec == WCMG_F16, WCMG_EINVAL,
+        "smoother precision must be F64, F32 or F16 (FP16 fields, FP32 arithmetic)");
   CHECK(p->setup_relax >= 1 && p->setup_max_steps >= 1, WCMG_EINVAL, "setup iteration counts must be >= 1");
   CHECK(p->coarsest == 0 || p->coarsest == 1, WCMG_EINVAL, "coarsest must be 0 (GCR) or 1 (dense FP64 inverse)");
   CHECK(p->cycle_mode >= 0 && p->cycle_mode <= 2, WCMG_EINVAL, "cycle_mode must be 0, 1 or 2");
@@ -465,8 +465,76 @@ int wcmg_get_coarse(void* ctx, int lat, int level, void* Y, int on_device) {
   });
 }
 
+// every lattice of the context, one right-hand side each, buffers concatenated in
+// lattice order: each kernel of the operator is one launch over all lattices
+static int apply_all_lattices(Ctx* c, int op, int prec, void* out, const void* in) {
+  const int nl = (int)c->lats.size();
+  CHECK(nl <= kMaxMulti, WCMG_EINVAL, "too many lattices for one launch");
+  CHECK(op == WCMG_OP_FULL || op == WCMG_OP_SCHUR, WCMG_EINVAL, "all-lattice applies support FULL and SCHUR");
+  for (auto& L : c->lats) CHECK(L->F.have_clover, WCMG_ESTATE, "clover not set");
+  return guarded([&] {
+    std::vector<char*> ie(nl), io(nl), oe(nl), oo(nl), t1(nl), t2(nl);
+    std::vector<size_t> off(nl + 1, 0);
+    for (int l = 0; l < nl; ++l) {
+      const Geom& g = c->lats[l]->F.g;
+      const size_t hb = spinor_bytes(prec, g.Vh);
+      char** bufs[6] = {&ie[l], &io[l], &oe[l], &oo[l], &t1[l], &t2[l]};
+      for (int k = 0; k < 6; ++k) *bufs[k] = (char*)c->scratch_buf(60 + 6 * l + k, hb);
+      off[l + 1] = off[l] + (size_t)g.V * 12 * 16;
+      spinor_to_internal(prec, ie[l], io[l], (const char*)in + off[l], g, false, c->st);
+    }
+    auto args = [&](int l, void* o, const void* i, const void* x, int parity, double coeff) {
+      FineFields& F = c->lats[l]->F;
+      DslashArgs a;
+      a.out = o;
+      a.in = i;
+      a.x = x;
+      a.gauge = F.gauge[prec].p;
+      a.clov = F.clov[prec].p;
+      a.g = dgeom(F.g);
+      a.parity = parity;
+      a.nblocks = 0;
+      a.coeff = coeff;
+      return a;
+    };
+    DslashMulti m{};
+    m.nl = nl;
+    if (op == WCMG_OP_FULL) {
+      for (int l = 0; l < nl; ++l) m.a[l] = args(l, oe[l], io[l], ie[l], 0, 1.0);
+      launch_dslash_multi(prec, 2, false, m, c->st);
+      for (int l = 0; l < nl; ++l) m.a[l] = args(l, oo[l], ie[l], io[l], 1, 1.0);
+      launch_dslash_multi(prec, 2, false, m, c->st);
+    } else {
+      CloverMulti cm{};
+      cm.nl = nl;
+      cm.parity = 0;
+      cm.kind = 1;
+      for (int l = 0; l < nl; ++l) {
+        cm.out[l] = t1[l];
+        cm.in[l] = ie[l];
+        cm.clov[l] = c->lats[l]->F.clov[prec].p;
+        cm.Vh[l] = c->lats[l]->F.g.Vh;
+      }
+      launch_clover_multi(prec, cm, c->st);  // z = A_ee^-1 y
+      for (int l = 0; l < nl; ++l) m.a[l] = args(l, t2[l], t1[l], nullptr, 1, 1.0);
+      launch_dslash_multi(prec, 0, true, m, c->st);  // w = A_oo^-1 H_oe z
+      for (int l = 0; l < nl; ++l) m.a[l] = args(l, oe[l], t2[l], ie[l], 0, -1.0);
+      launch_dslash_multi(prec, 1, false, m, c->st);  // out = y - H_eo w
+    }
+    for (int l = 0; l < nl; ++l)
+      spinor_from_internal(prec, (char*)out + off[l], oe[l], op == WCMG_OP_FULL ? oo[l] : nullptr, c->lats[l]->F.g,
+                           false, c->st);
+  });
+}
+
 static int apply_common(void* ctx, int lat, int op, int prec, void* out, const void* in, int nrhs, bool dag) {
   Ctx* c = as_ctx(ctx);
+  if (lat == -1 && c && !dag) {
+    CHECK(out && in && out != in, WCMG_EINVAL, "null or aliased buffer");
+    CHECK(valid_op(op) && valid_prec(prec), WCMG_EINVAL, "bad operator or precision");
+    CHECK(nrhs == 1, WCMG_EINVAL, "all-lattice applies take one right-hand side per lattice");
+    return apply_all_lattices(c, op, prec, out, in);
+  }
   if (int r = check_lat(c, lat)) return r;
   CHECK(out && in, WCMG_EINVAL, "null buffer");
   CHECK(valid_op(op), WCMG_EINVAL, "bad operator");

@@ -11,9 +11,11 @@
 //   b_r_hat = b_e - Ytilde_eo b_o
 //   c_e = X_ee^-1 y_e,  c_o = X_oo^-1 (b_o - Ytilde_oe y_e).
 //
-// One workgroup computes one coarse site: the 8 neighbour vectors are
-// gathered into LDS, G column groups of n/2 lanes (two rows per lane) split
-// the 8n columns, and the partial rows are summed in LDS.
+// A coarse site is computed by `split` workgroups (1, 2 or 4), each owning
+// n/split consecutive rows, so that small coarse lattices still occupy every
+// CU: the 8 neighbour vectors are gathered into LDS, G column groups of
+// n/(2 split) lanes (two rows per lane) split the 8n columns, and the
+// partial rows are summed in LDS.
 #include "kernels.h"
 
 namespace wcmg {
@@ -36,18 +38,20 @@ __device__ __forceinline__ void load2(const double2* p, cpx<double>& e0, cpx<dou
 // group g = t div n/2; the G groups stride over the 8n hop columns (and the
 // n columns of X for DIAG 2), so each lane keeps several 16-byte loads in
 // flight.  Up to 1024 lanes (16 wavefronts) work on one coarse site.
-template <typename S>
+// RB = 1 marks the launches of the red-black reduced operator (the solver's
+// hot path), so that profiles separate them from the other uses
+template <typename S, int RB>
 __global__ void __launch_bounds__(1024) k_coarse_hop(void* out, const void* in, const void* x, const void* M,
                                                      const void* Xm, int diag, double coeff, int site0, int n,
-                                                     const int* nbr, size_t vs) {
+                                                     const int* nbr, size_t vs, int split, int G) {
   using C = typename Compute<S>::T;
   using V2 = typename Vec2<S>::T;
   extern __shared__ char smem[];
   cpx<C>* vin = reinterpret_cast<cpx<C>*>(smem);  // 9n: 8 neighbour vectors, then x(c)
-  cpx<C>* part = vin + 9 * n;                       // G * n partial rows
-  const int c = site0 + blockIdx.x;
-  const int R2 = n >> 1;
-  const int G = blockDim.x / R2;
+  cpx<C>* part = vin + 9 * n;                       // G * rows partial rows
+  const int c = site0 + blockIdx.x / split;
+  const int rows = n / split, row0 = (blockIdx.x % split) * rows;
+  const int R2 = rows >> 1;  // lanes g * R2 .. g * R2 + R2 - 1 form column group g < G
   // right-hand side blockIdx.y of a batch, vs elements apart
   const size_t ro = (size_t)blockIdx.y * vs;
   const V2* vi = reinterpret_cast<const V2*>(in) + (in ? ro : 0);
@@ -71,7 +75,7 @@ __global__ void __launch_bounds__(1024) k_coarse_hop(void* out, const void* in, 
   if (g < G) {
     cpx<C> a0 = mk((C)0, (C)0), a1 = a0, d0 = a0, d1 = a0;
     if (M) {
-      const V2* m = reinterpret_cast<const V2*>(M) + (size_t)c * 8 * n * n + 2 * rp;
+      const V2* m = reinterpret_cast<const V2*>(M) + (size_t)c * 8 * n * n + row0 + 2 * rp;
 #pragma unroll 4
       for (int col = g; col < 8 * n; col += G) {
         cpx<C> e0, e1;
@@ -82,7 +86,7 @@ __global__ void __launch_bounds__(1024) k_coarse_hop(void* out, const void* in, 
       }
     }
     if (diag == 2) {
-      const V2* m = reinterpret_cast<const V2*>(Xm) + (size_t)c * n * n + 2 * rp;
+      const V2* m = reinterpret_cast<const V2*>(Xm) + (size_t)c * n * n + row0 + 2 * rp;
       for (int col = g; col < n; col += G) {
         cpx<C> e0, e1;
         load2(m + (size_t)col * n, e0, e1);
@@ -91,22 +95,31 @@ __global__ void __launch_bounds__(1024) k_coarse_hop(void* out, const void* in, 
         cfma(d1, e1, v);
       }
     }
-    part[g * n + 2 * rp] = (C)coeff * a0 + d0;
-    part[g * n + 2 * rp + 1] = (C)coeff * a1 + d1;
+    part[g * rows + 2 * rp] = (C)coeff * a0 + d0;
+    part[g * rows + 2 * rp + 1] = (C)coeff * a1 + d1;
   }
-  __syncthreads();
-  if ((int)threadIdx.x < n) {
-    const int i = threadIdx.x;
-    cpx<C> s = part[i];
-    for (int h = 1; h < G; ++h) s = s + part[h * n + i];
-    if (diag == 1) {
-      V2 w = vx[(size_t)c * n + i];
-      s = s + mk((C)w.x, (C)w.y);
+  // fixed-order tree over the G (a power of two) column groups
+  for (int h = G >> 1; h > 0; h >>= 1) {
+    __syncthreads();
+    if (g < h) {
+      part[g * rows + 2 * rp] = part[g * rows + 2 * rp] + part[(g + h) * rows + 2 * rp];
+      part[g * rows + 2 * rp + 1] = part[g * rows + 2 * rp + 1] + part[(g + h) * rows + 2 * rp + 1];
     }
-    V2 o;
-    o.x = (S)s.r;
-    o.y = (S)s.i;
-    reinterpret_cast<V2*>(out)[(size_t)c * n + i] = o;
+  }
+  if (g == 0) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int i = row0 + 2 * rp + k;
+      cpx<C> s = part[2 * rp + k];
+      if (diag == 1) {
+        V2 w = vx[(size_t)c * n + i];
+        s = s + mk((C)w.x, (C)w.y);
+      }
+      V2 o;
+      o.x = (S)s.r;
+      o.y = (S)s.i;
+      reinterpret_cast<V2*>(out)[(size_t)c * n + i] = o;
+    }
   }
 }
 
@@ -232,28 +245,37 @@ void launch_coarse_canon(int prec, void* internal, void* canon, const int* perm,
 
 void launch_coarse_hop(int prec, void* out, const void* in, const void* x, const void* M, const void* Xmat,
                        int diag, double coeff, int parity, const CoarseGeom& cg, const int* nbr, hipStream_t st,
-                       int nrhs, size_t vs) {
+                       int nrhs, size_t vs, bool rb) {
   const int n = cg.n;
   if (n % 2 || n > 256) fail(WCMG_EDIM, "coarse block size must be even and <= 256");
-  const int R2 = n / 2;
-  int G = std::min(1024 / R2, 9 * n);
-  if (G < 1) G = 1;
-  const int threads = std::min(1024, ((G * R2 + 63) / 64) * 64);
-  G = threads / R2;  // the kernel derives G the same way
   int site0 = 0, nsites = cg.V;
   if (parity >= 0) {
     site0 = parity * cg.Vh;
     nsites = cg.Vh;
   }
+  // rows per workgroup: split small lattices until about 1024 workgroups are in flight
+  int split = 1;
+  while (split < 4 && nsites * nrhs * split < 1024 && n % (4 * split) == 0) split *= 2;
+  const int rows = n / split;
+  const int R2 = rows / 2;
+  // G column groups: the largest power of two with G * R2 <= 1024 and G <= 64
+  int G = 1;
+  while (G < 64 && 2 * G * R2 <= 1024) G *= 2;
+  const int threads = ((G * R2 + 63) / 64) * 64;  // lanes beyond G * R2 idle
   const size_t cb = (prec == WCMG_F64) ? 16 : 8;
-  const size_t shm = (size_t)(9 * n + G * n) * cb;
+  const size_t shm = (size_t)(9 * n + G * rows) * cb;
   if (nsites == 0) return;
-  if (prec == WCMG_F64)
-    hipLaunchKernelGGL(k_coarse_hop<double>, dim3(nsites, nrhs), dim3(threads), shm, st, out, in, x, M, Xmat, diag,
-                       coeff, site0, n, nbr, vs);
-  else
-    hipLaunchKernelGGL(k_coarse_hop<float>, dim3(nsites, nrhs), dim3(threads), shm, st, out, in, x, M, Xmat, diag,
-                       coeff, site0, n, nbr, vs);
+#define WCMG_CH(S, R)                                                                                          \
+  hipLaunchKernelGGL((k_coarse_hop<S, R>), dim3(nsites * split, nrhs), dim3(threads), shm, st, out, in, x, M, Xmat, \
+                     diag, coeff, site0, n, nbr, vs, split, G)
+  if (prec == WCMG_F64) {
+    if (rb) WCMG_CH(double, 1);
+    else WCMG_CH(double, 0);
+  } else {
+    if (rb) WCMG_CH(float, 1);
+    else WCMG_CH(float, 0);
+  }
+#undef WCMG_CH
   HIPCHK(hipGetLastError());
 }
 

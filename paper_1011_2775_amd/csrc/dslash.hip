@@ -52,7 +52,7 @@ __device__ __forceinline__ const void* rhs_ptr(const void* base, size_t stride, 
   return reinterpret_cast<const char*>(base) + (size_t)r * stride;
 }
 
-template <typename S, int MU, int NR>
+template <typename S, typename G, int MU, int NR>
 __device__ __forceinline__ void hop_mu(const DslashArgs& a, int p, int i, const int c[4], int g0, int nr,
                                        cpx<typename Compute<S>::T> (&acc)[NR][12]) {
   using C = typename Compute<S>::T;
@@ -63,7 +63,7 @@ __device__ __forceinline__ void hop_mu(const DslashArgs& a, int p, int i, const 
     int n[4] = {c[0], c[1], c[2], c[3]};
     n[MU] = (n[MU] + 1 == g.L[MU]) ? 0 : n[MU] + 1;
     const int nb = cb_index(g, n);
-    load_link<S, C>(a.gauge, g.Vh, p, MU, i, U);
+    load_link<G, C>(a.gauge, g.Vh, p, MU, i, U);
     const bool edge = MU == 3 && c[3] == g.L[3] - 1;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -86,7 +86,7 @@ __device__ __forceinline__ void hop_mu(const DslashArgs& a, int p, int i, const 
     int n[4] = {c[0], c[1], c[2], c[3]};
     n[MU] = (n[MU] == 0) ? g.L[MU] - 1 : n[MU] - 1;
     const int nb = cb_index(g, n);
-    load_link<S, C>(a.gauge, g.Vh, 1 - p, MU, nb, U);
+    load_link<G, C>(a.gauge, g.Vh, 1 - p, MU, nb, U);
     const bool edge = MU == 3 && c[3] == 0;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -106,15 +106,57 @@ __device__ __forceinline__ void hop_mu(const DslashArgs& a, int p, int i, const 
   }
 }
 
-// one 36-real chirality block of the packed clover, loaded once, applied to NR vectors
-template <typename S, typename C, int NR>
-__device__ __forceinline__ void clover_block_multi(const void* clov, int Vh, int p, int kind, int chi, int i,
-                                                   int nr, const cpx<C> (&in)[NR][12], cpx<C> (&out)[NR][12]) {
-  const S* c = reinterpret_cast<const S*>(clov) + ((size_t)(p * 2 + kind) * 72 + chi * 36) * Vh;
-  const int o = 6 * chi;
-  C d[6];
+// Packed clover (kind 0 = A, 1 = A^-1) of one site: per chirality 6 real
+// diagonal entries then 15 strictly lower complex entries (36 reals), both
+// chiralities in 72 reals stored as 16-byte chunks [p][kind][chunk][Vh].
+template <typename G>
+struct CloverChunk;
+template <>
+struct CloverChunk<double> {
+  using V = double2;
+  static constexpr int E = 2;
+};
+template <>
+struct CloverChunk<float> {
+  using V = float4;
+  static constexpr int E = 4;
+};
+template <>
+struct CloverChunk<__half> {
+  using V = uint4;
+  static constexpr int E = 8;
+};
+
+template <typename G, typename C>
+__device__ __forceinline__ void unpack_chunk(const typename CloverChunk<G>::V& v, C* d);
+template <>
+__device__ __forceinline__ void unpack_chunk<double, double>(const double2& v, double* d) {
+  d[0] = v.x;
+  d[1] = v.y;
+}
+template <>
+__device__ __forceinline__ void unpack_chunk<float, float>(const float4& v, float* d) {
+  d[0] = v.x;
+  d[1] = v.y;
+  d[2] = v.z;
+  d[3] = v.w;
+}
+template <>
+__device__ __forceinline__ void unpack_chunk<__half, float>(const uint4& v, float* d) {
+  const unsigned w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-  for (int k = 0; k < 6; ++k) d[k] = (C)to_f_or_d<S, C>(c[(size_t)k * Vh + i]);
+  for (int k = 0; k < 4; ++k) {
+    const float2 f = __half22float2(*reinterpret_cast<const __half2*>(&w[k]));
+    d[2 * k] = f.x;
+    d[2 * k + 1] = f.y;
+  }
+}
+
+// apply one chirality block (36 reals in d) to NR vectors
+template <typename C, int NR>
+__device__ __forceinline__ void clover_block_apply_d(const C* d, int chi, int nr, const cpx<C> (&in)[NR][12],
+                                                     cpx<C> (&out)[NR][12]) {
+  const int o = 6 * chi;
 #pragma unroll
   for (int r = 0; r < NR; ++r)
     if (r < nr)
@@ -125,8 +167,7 @@ __device__ __forceinline__ void clover_block_multi(const void* clov, int Vh, int
   for (int rr = 1; rr < 6; ++rr) {
 #pragma unroll
     for (int s = 0; s < rr; ++s) {
-      const cpx<C> L = mk((C)to_f_or_d<S, C>(c[(size_t)(6 + 2 * t) * Vh + i]),
-                          (C)to_f_or_d<S, C>(c[(size_t)(7 + 2 * t) * Vh + i]));
+      const cpx<C> L = mk(d[6 + 2 * t], d[7 + 2 * t]);
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         if (r < nr) {
@@ -139,17 +180,36 @@ __device__ __forceinline__ void clover_block_multi(const void* clov, int Vh, int
   }
 }
 
-template <typename S, typename C, int NR>
+template <typename G, typename C, int NR>
 __device__ __forceinline__ void clover_multi(const void* clov, int Vh, int p, int kind, int i, int nr,
                                              const cpx<C> (&in)[NR][12], cpx<C> (&out)[NR][12]) {
-  clover_block_multi<S, C, NR>(clov, Vh, p, kind, 0, i, nr, in, out);
-  clover_block_multi<S, C, NR>(clov, Vh, p, kind, 1, i, nr, in, out);
+  using V = typename CloverChunk<G>::V;
+  constexpr int E = CloverChunk<G>::E;
+  constexpr int NCH = 72 / E;
+  const V* base = reinterpret_cast<const V*>(clov) + (size_t)(p * 2 + kind) * NCH * Vh + i;
+  if constexpr (E == 8) {
+    // FP16: the two chirality blocks share a chunk, load all 72 reals at once
+    C d[72];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) unpack_chunk<G, C>(base[(size_t)c * Vh], d + E * c);
+    clover_block_apply_d<C, NR>(d, 0, nr, in, out);
+    clover_block_apply_d<C, NR>(d + 36, 1, nr, in, out);
+  } else {
+#pragma unroll
+    for (int chi = 0; chi < 2; ++chi) {
+      C d[36];
+#pragma unroll
+      for (int c = 0; c < 36 / E; ++c) unpack_chunk<G, C>(base[(size_t)(chi * (36 / E) + c) * Vh], d + E * c);
+      clover_block_apply_d<C, NR>(d, chi, nr, in, out);
+    }
+  }
 }
 
-template <typename S, int DIAG, bool POSTINV, int NR>
-__global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a) {
+// S: spinor storage, G: link and clover storage (G = S, or FP16 fields with
+// FP32 spinors); lb: the lattice's logical block
+template <typename S, typename G, int DIAG, bool POSTINV, int NR>
+__device__ __forceinline__ void dslash_site(const DslashArgs& a, int lb) {
   using C = typename Compute<S>::T;
-  const int lb = xcd_block(a.nblocks);
   const int i = lb * blockDim.x + threadIdx.x;
   if (lb >= a.nblocks || i >= a.g.Vh) return;
   const int g0 = blockIdx.y * NR;
@@ -163,10 +223,10 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a) {
   for (int r = 0; r < NR; ++r)
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[r][k] = mk((C)0, (C)0);
-  hop_mu<S, 0, NR>(a, p, i, c, g0, nr, acc);
-  hop_mu<S, 1, NR>(a, p, i, c, g0, nr, acc);
-  hop_mu<S, 2, NR>(a, p, i, c, g0, nr, acc);
-  hop_mu<S, 3, NR>(a, p, i, c, g0, nr, acc);
+  hop_mu<S, G, 0, NR>(a, p, i, c, g0, nr, acc);
+  hop_mu<S, G, 1, NR>(a, p, i, c, g0, nr, acc);
+  hop_mu<S, G, 2, NR>(a, p, i, c, g0, nr, acc);
+  hop_mu<S, G, 3, NR>(a, p, i, c, g0, nr, acc);
 
   const C f = (C)(-0.5 * a.coeff);
 #pragma unroll
@@ -176,7 +236,7 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a) {
 
   cpx<C> out[NR][12];
   if constexpr (POSTINV) {
-    clover_multi<S, C, NR>(a.clov, a.g.Vh, p, 1, i, nr, acc, out);
+    clover_multi<G, C, NR>(a.clov, a.g.Vh, p, 1, i, nr, acc, out);
   } else {
 #pragma unroll
     for (int r = 0; r < NR; ++r)
@@ -190,7 +250,7 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a) {
       if (r < nr) SpinorIO<S>::load(rhs_ptr<S>(a.x, a.rstride, g0 + r), a.g.Vh, i, xv[r]);
     if constexpr (DIAG == 2) {
       cpx<C> ax[NR][12];
-      clover_multi<S, C, NR>(a.clov, a.g.Vh, p, 0, i, nr, xv, ax);
+      clover_multi<G, C, NR>(a.clov, a.g.Vh, p, 0, i, nr, xv, ax);
 #pragma unroll
       for (int r = 0; r < NR; ++r)
 #pragma unroll
@@ -208,8 +268,22 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a) {
       SpinorIO<S>::store(const_cast<void*>(rhs_ptr<S>(a.out, a.rstride, g0 + r)), a.g.Vh, i, out[r]);
 }
 
+template <typename S, typename G, int DIAG, bool POSTINV, int NR>
+__global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a) {
+  dslash_site<S, G, DIAG, POSTINV, NR>(a, xcd_block(a.nblocks));
+}
+
+// Several lattices of different volumes in one launch: a work list of block
+// ranges, workgroup b serving lattice l with off[l] <= b < off[l+1].
+template <typename S, typename G, int DIAG, bool POSTINV>
+__global__ void __launch_bounds__(256) dslash_multi_kernel(DslashMulti m) {
+  int l = 0;
+  while (l + 1 < m.nl && (int)blockIdx.x >= m.off[l + 1]) ++l;
+  dslash_site<S, G, DIAG, POSTINV, 1>(m.a[l], (int)blockIdx.x - m.off[l]);
+}
+
 // out_p = A_p^(kind) in_p   (site-local clover or clover inverse), NR right-hand sides per thread
-template <typename S, int NR>
+template <typename S, typename G, int NR>
 __global__ void __launch_bounds__(256) clover_kernel(void* out, const void* in, const void* clov, int Vh, int p,
                                                      int kind, int nrhs, size_t rstride) {
   using C = typename Compute<S>::T;
@@ -221,7 +295,7 @@ __global__ void __launch_bounds__(256) clover_kernel(void* out, const void* in, 
 #pragma unroll
   for (int r = 0; r < NR; ++r)
     if (r < nr) SpinorIO<S>::load(rhs_ptr<S>(in, rstride, g0 + r), Vh, i, v[r]);
-  clover_multi<S, C, NR>(clov, Vh, p, kind, i, nr, v, o);
+  clover_multi<G, C, NR>(clov, Vh, p, kind, i, nr, v, o);
 #pragma unroll
   for (int r = 0; r < NR; ++r)
     if (r < nr) SpinorIO<S>::store(const_cast<void*>(rhs_ptr<S>(out, rstride, g0 + r)), Vh, i, o[r]);
@@ -233,13 +307,13 @@ constexpr int max_group() {
   return sizeof(S) == 8 ? 2 : 4;
 }
 
-template <typename S, int NR>
+template <typename S, typename G, int NR>
 static void launch_dslash_nr(int diag, bool postinv, DslashArgs a, hipStream_t st) {
   const int threads = a.threads > 0 ? a.threads : 256;
   if (threads != 64 && threads != 128 && threads != 256) fail(WCMG_EINVAL, "unsupported Dslash block size");
   a.nblocks = (a.g.Vh + threads - 1) / threads;
   dim3 grid(xcd_grid(a.nblocks), (a.nrhs + NR - 1) / NR);
-#define WCMG_DS(D, P) hipLaunchKernelGGL((dslash_kernel<S, D, P, NR>), grid, dim3(threads), 0, st, a)
+#define WCMG_DS(D, P) hipLaunchKernelGGL((dslash_kernel<S, G, D, P, NR>), grid, dim3(threads), 0, st, a)
   if (diag == 0 && !postinv) WCMG_DS(0, false);
   else if (diag == 0 && postinv) WCMG_DS(0, true);
   else if (diag == 1 && !postinv) WCMG_DS(1, false);
@@ -250,43 +324,107 @@ static void launch_dslash_nr(int diag, bool postinv, DslashArgs a, hipStream_t s
   HIPCHK(hipGetLastError());
 }
 
-template <typename S>
+template <typename S, typename G>
 static void launch_dslash_t(int diag, bool postinv, const DslashArgs& a, hipStream_t st) {
   int g = a.nrhs >= max_group<S>() ? max_group<S>() : (a.nrhs >= 2 ? 2 : 1);
   if (a.group > 0) g = std::min(a.group, max_group<S>());
-  if (g == 1) launch_dslash_nr<S, 1>(diag, postinv, a, st);
-  else if (g == 2) launch_dslash_nr<S, 2>(diag, postinv, a, st);
-  else launch_dslash_nr<S, max_group<S>()>(diag, postinv, a, st);
+  if (g == 1) launch_dslash_nr<S, G, 1>(diag, postinv, a, st);
+  else if (g == 2) launch_dslash_nr<S, G, 2>(diag, postinv, a, st);
+  else launch_dslash_nr<S, G, max_group<S>()>(diag, postinv, a, st);
 }
 
 void launch_dslash(int prec, int diag, bool postinv, const DslashArgs& a, hipStream_t st) {
   if (a.nrhs < 1) fail(WCMG_EINVAL, "nrhs must be >= 1");
-  if (prec == WCMG_F64) launch_dslash_t<double>(diag, postinv, a, st);
-  else if (prec == WCMG_F32) launch_dslash_t<float>(diag, postinv, a, st);
-  else launch_dslash_t<__half>(diag, postinv, a, st);
+  const int fp = a.fprec < 0 ? prec : a.fprec;
+  if (prec == WCMG_F64 && fp == WCMG_F64) launch_dslash_t<double, double>(diag, postinv, a, st);
+  else if (prec == WCMG_F32 && fp == WCMG_F32) launch_dslash_t<float, float>(diag, postinv, a, st);
+  else if (prec == WCMG_F32 && fp == WCMG_F16) launch_dslash_t<float, __half>(diag, postinv, a, st);
+  else if (prec == WCMG_F16 && fp == WCMG_F16) launch_dslash_t<__half, __half>(diag, postinv, a, st);
+  else fail(WCMG_EINVAL, "unsupported spinor / field precision pair");
 }
 
-template <typename S, int NR>
+template <typename S, typename G, int NR>
 static void launch_clover_nr(void* out, const void* in, const void* clov, int Vh, int p, int kind, int nrhs,
                              size_t rstride, hipStream_t st) {
   dim3 grid((Vh + 255) / 256, (nrhs + NR - 1) / NR);
-  hipLaunchKernelGGL((clover_kernel<S, NR>), grid, dim3(256), 0, st, out, in, clov, Vh, p, kind, nrhs, rstride);
+  hipLaunchKernelGGL((clover_kernel<S, G, NR>), grid, dim3(256), 0, st, out, in, clov, Vh, p, kind, nrhs, rstride);
 }
 
-template <typename S>
+template <typename S, typename G>
 static void launch_clover_t(void* out, const void* in, const void* clov, int Vh, int p, int kind, int nrhs,
                             size_t rstride, hipStream_t st) {
-  if (nrhs >= max_group<S>()) launch_clover_nr<S, max_group<S>()>(out, in, clov, Vh, p, kind, nrhs, rstride, st);
-  else if (nrhs >= 2) launch_clover_nr<S, 2>(out, in, clov, Vh, p, kind, nrhs, rstride, st);
-  else launch_clover_nr<S, 1>(out, in, clov, Vh, p, kind, nrhs, rstride, st);
+  if (nrhs >= max_group<S>()) launch_clover_nr<S, G, max_group<S>()>(out, in, clov, Vh, p, kind, nrhs, rstride, st);
+  else if (nrhs >= 2) launch_clover_nr<S, G, 2>(out, in, clov, Vh, p, kind, nrhs, rstride, st);
+  else launch_clover_nr<S, G, 1>(out, in, clov, Vh, p, kind, nrhs, rstride, st);
 }
 
 void launch_clover(int prec, void* out, const void* in, const void* clov, int Vh, int p, int kind, hipStream_t st,
-                   int nrhs, size_t rstride) {
+                   int nrhs, size_t rstride, int fprec) {
   if (nrhs < 1) fail(WCMG_EINVAL, "nrhs must be >= 1");
-  if (prec == WCMG_F64) launch_clover_t<double>(out, in, clov, Vh, p, kind, nrhs, rstride, st);
-  else if (prec == WCMG_F32) launch_clover_t<float>(out, in, clov, Vh, p, kind, nrhs, rstride, st);
-  else launch_clover_t<__half>(out, in, clov, Vh, p, kind, nrhs, rstride, st);
+  const int fp = fprec < 0 ? prec : fprec;
+  if (prec == WCMG_F64 && fp == WCMG_F64) launch_clover_t<double, double>(out, in, clov, Vh, p, kind, nrhs, rstride, st);
+  else if (prec == WCMG_F32 && fp == WCMG_F32) launch_clover_t<float, float>(out, in, clov, Vh, p, kind, nrhs, rstride, st);
+  else if (prec == WCMG_F32 && fp == WCMG_F16) launch_clover_t<float, __half>(out, in, clov, Vh, p, kind, nrhs, rstride, st);
+  else if (prec == WCMG_F16 && fp == WCMG_F16) launch_clover_t<__half, __half>(out, in, clov, Vh, p, kind, nrhs, rstride, st);
+  else fail(WCMG_EINVAL, "unsupported spinor / field precision pair");
+  HIPCHK(hipGetLastError());
+}
+
+template <typename S, typename G>
+__global__ void __launch_bounds__(256) clover_multi_kernel(CloverMulti m) {
+  using C = typename Compute<S>::T;
+  int l = 0;
+  while (l + 1 < m.nl && (int)blockIdx.x >= m.off[l + 1]) ++l;
+  const int i = ((int)blockIdx.x - m.off[l]) * blockDim.x + threadIdx.x;
+  if (i >= m.Vh[l]) return;
+  cpx<C> v[1][12], o[1][12];
+  SpinorIO<S>::load(m.in[l], m.Vh[l], i, v[0]);
+  clover_multi<G, C, 1>(m.clov[l], m.Vh[l], m.parity, m.kind, i, 1, v, o);
+  SpinorIO<S>::store(m.out[l], m.Vh[l], i, o[0]);
+}
+
+template <typename S, typename G>
+static void launch_multi_t(int diag, bool postinv, DslashMulti m, hipStream_t st) {
+  int total = 0;
+  for (int l = 0; l < m.nl; ++l) {
+    m.a[l].nblocks = (m.a[l].g.Vh + 255) / 256;
+    m.a[l].nrhs = 1;
+    m.off[l] = total;
+    total += m.a[l].nblocks;
+  }
+  m.off[m.nl] = total;
+#define WCMG_DM(D, P) hipLaunchKernelGGL((dslash_multi_kernel<S, G, D, P>), dim3(total), dim3(256), 0, st, m)
+  if (diag == 0 && !postinv) WCMG_DM(0, false);
+  else if (diag == 0 && postinv) WCMG_DM(0, true);
+  else if (diag == 1 && !postinv) WCMG_DM(1, false);
+  else if (diag == 1 && postinv) WCMG_DM(1, true);
+  else if (diag == 2 && !postinv) WCMG_DM(2, false);
+  else WCMG_DM(2, true);
+#undef WCMG_DM
+  HIPCHK(hipGetLastError());
+}
+
+void launch_dslash_multi(int prec, int diag, bool postinv, const DslashMulti& m, hipStream_t st) {
+  if (m.nl < 1 || m.nl > kMaxMulti) fail(WCMG_EINVAL, "lattice count out of range");
+  if (prec == WCMG_F64) launch_multi_t<double, double>(diag, postinv, m, st);
+  else if (prec == WCMG_F32) launch_multi_t<float, float>(diag, postinv, m, st);
+  else launch_multi_t<__half, __half>(diag, postinv, m, st);
+}
+
+void launch_clover_multi(int prec, CloverMulti m, hipStream_t st) {
+  if (m.nl < 1 || m.nl > kMaxMulti) fail(WCMG_EINVAL, "lattice count out of range");
+  int total = 0;
+  for (int l = 0; l < m.nl; ++l) {
+    m.off[l] = total;
+    total += (m.Vh[l] + 255) / 256;
+  }
+  m.off[m.nl] = total;
+  if (prec == WCMG_F64)
+    hipLaunchKernelGGL((clover_multi_kernel<double, double>), dim3(total), dim3(256), 0, st, m);
+  else if (prec == WCMG_F32)
+    hipLaunchKernelGGL((clover_multi_kernel<float, float>), dim3(total), dim3(256), 0, st, m);
+  else
+    hipLaunchKernelGGL((clover_multi_kernel<__half, __half>), dim3(total), dim3(256), 0, st, m);
   HIPCHK(hipGetLastError());
 }
 

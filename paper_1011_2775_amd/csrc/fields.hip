@@ -210,13 +210,32 @@ __device__ bool herm6_inverse(const Herm6& A, Herm6& Ainv) {
   return true;
 }
 
+// Packed clover record of a site: 72 reals per (parity, kind), chirality
+// block chi at reals chi*36 .. chi*36+35 (6 diagonal, then the 15 strictly
+// lower complex entries), stored as 16-byte chunks [p][kind][chunk][Vh]
+// holding E = 16 / sizeof(real) consecutive reals (FP64 2, FP32 4, FP16 8).
+__device__ __forceinline__ size_t clover_real_index(int pk, int K, int Vh, int i, int E) {
+  return (((size_t)pk * (72 / E) + K / E) * Vh + i) * E + K % E;
+}
+
 __device__ void store_herm6(double* clov, const DGeom& g, int p, int kind, int chi, int i, const Herm6& h) {
-  double* c = clov + ((size_t)(p * 2 + kind) * 72 + chi * 36) * g.Vh;
-  for (int k = 0; k < 6; ++k) c[(size_t)k * g.Vh + i] = h.d[k];
+  const int pk = p * 2 + kind, o = chi * 36;
+  for (int k = 0; k < 6; ++k) clov[clover_real_index(pk, o + k, g.Vh, i, 2)] = h.d[k];
   for (int t = 0; t < 15; ++t) {
-    c[(size_t)(6 + 2 * t) * g.Vh + i] = h.l[t].r;
-    c[(size_t)(7 + 2 * t) * g.Vh + i] = h.l[t].i;
+    clov[clover_real_index(pk, o + 6 + 2 * t, g.Vh, i, 2)] = h.l[t].r;
+    clov[clover_real_index(pk, o + 7 + 2 * t, g.Vh, i, 2)] = h.l[t].i;
   }
+}
+
+// FP64 chunked clover -> the chunked layout of precision S
+template <typename S>
+__global__ void k_clover_relayout(S* dst, const double* src, int Vh) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (size_t)4 * 72 * Vh) return;
+  const int i = (int)(t % Vh);
+  const int K = (int)((t / Vh) % 72);
+  const int pk = (int)(t / ((size_t)Vh * 72));
+  dst[clover_real_index(pk, K, Vh, i, 16 / sizeof(S))] = (S)src[clover_real_index(pk, K, Vh, i, 2)];
 }
 
 __global__ void __launch_bounds__(128) k_clover(double* clov, const double2* gauge, DGeom g, int V, double diag,
@@ -410,6 +429,18 @@ void reals_convert(int prec, void* dst, const double* src, size_t n, hipStream_t
     hipLaunchKernelGGL(k_reals_convert<float>, dim3(b), dim3(kT), 0, st, (float*)dst, src, n);
   else
     hipLaunchKernelGGL(k_reals_convert<__half>, dim3(b), dim3(kT), 0, st, (__half*)dst, src, n);
+  HIPCHK(hipGetLastError());
+}
+
+void clover_relayout(int prec, void* dst, const double* src, int Vh, hipStream_t st) {
+  const size_t n = (size_t)4 * 72 * Vh;
+  const dim3 gr((unsigned)((n + kT - 1) / kT));
+  if (prec == WCMG_F32)
+    hipLaunchKernelGGL(k_clover_relayout<float>, gr, dim3(kT), 0, st, (float*)dst, src, Vh);
+  else if (prec == WCMG_F16)
+    hipLaunchKernelGGL(k_clover_relayout<__half>, gr, dim3(kT), 0, st, (__half*)dst, src, Vh);
+  else
+    fail(WCMG_EINVAL, "clover relayout targets F32 or F16");
   HIPCHK(hipGetLastError());
 }
 

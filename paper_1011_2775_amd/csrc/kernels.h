@@ -20,11 +20,29 @@ struct DslashArgs {
   size_t rstride = 0;  // bytes between consecutive right-hand sides
   int threads = 0;     // launch shape: threads per block (64, 128, 256; 0 = 256)
   int group = 0;       // right-hand sides per thread (1, 2, 4; 0 = largest that fits)
+  int fprec = -1;      // storage of gauge and clover (-1: as the spinors; F16 with F32 spinors)
 };
 void launch_dslash(int prec, int diag, bool postinv, const DslashArgs& a, hipStream_t st);
+// several lattices (one right-hand side each, same precision and kernel variant) in one launch
+constexpr int kMaxMulti = 4;
+struct DslashMulti {
+  DslashArgs a[kMaxMulti];
+  int nl;
+  int off[kMaxMulti + 1];  // block offsets, filled by the launcher
+};
+void launch_dslash_multi(int prec, int diag, bool postinv, const DslashMulti& m, hipStream_t st);
+struct CloverMulti {
+  void* out[kMaxMulti];
+  const void* in[kMaxMulti];
+  const void* clov[kMaxMulti];
+  int Vh[kMaxMulti];
+  int nl, parity, kind;
+  int off[kMaxMulti + 1];
+};
+void launch_clover_multi(int prec, CloverMulti m, hipStream_t st);
 // out_r = A^(kind) in_r for nrhs spinors rstride bytes apart
 void launch_clover(int prec, void* out, const void* in, const void* clov, int Vh, int p, int kind,
-                   hipStream_t st, int nrhs = 1, size_t rstride = 0);
+                   hipStream_t st, int nrhs = 1, size_t rstride = 0, int fprec = -1);
 
 // ------------------------------------------------------------ fields
 // canonical complex128 gauge [V][4][3][3] (device) -> internal links
@@ -55,6 +73,8 @@ void clover_from_matrix(void* clov64, const void* A, const Geom& g, int* flag, h
 void force_compute(void* G, const void* x, const void* lam, int nrhs, const void* gauge64, const Geom& g,
                    const CloverCoef* cc, void* zbuf, hipStream_t st);
 void reals_convert(int prec_dst, void* dst, const double* src, size_t n, hipStream_t st);
+// packed FP64 clover (both parities, A and A^-1) -> the chunked layout of prec (F32, F16)
+void clover_relayout(int prec, void* dst, const double* src, int Vh, hipStream_t st);
 
 // ------------------------------------------------------------ BLAS-1
 // Flat complex vectors of n elements, storage double (prec F64) or float (F32).
@@ -208,7 +228,7 @@ struct CoarseGeom {
 // M: [site][8][n][n] column-major blocks.  diag 0 none, 1 x, 2 X(c) x with Xmat
 void launch_coarse_hop(int prec, void* out, const void* in, const void* x, const void* M, const void* Xmat,
                        int diag, double coeff, int parity, const CoarseGeom& cg, const int* nbr, hipStream_t st,
-                       int nrhs = 1, size_t vs = 0);
+                       int nrhs = 1, size_t vs = 0, bool rb = false);
 // out(c) = M(c) in(c) with M [site][n][n] column-major, sites of `parity` (-1 all)
 void launch_coarse_local(int prec, void* out, const void* in, const void* M, int parity, const CoarseGeom& cg,
                          hipStream_t st, int nrhs = 1, size_t vs = 0);

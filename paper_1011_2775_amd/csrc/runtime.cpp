@@ -173,8 +173,9 @@ void FineOp::hop(void* out, const void* in, const void* x, int parity, int diag,
   a.out = out;
   a.in = in;
   a.x = x;
-  a.gauge = F->gauge[prec].p;
-  a.clov = F->clov[prec].p;
+  a.gauge = F->gauge[fp()].p;
+  a.clov = F->clov[fp()].p;
+  a.fprec = fp();
   a.g = dgeom(F->g);
   a.parity = parity;
   a.nblocks = 0;
@@ -182,7 +183,7 @@ void FineOp::hop(void* out, const void* in, const void* x, int parity, int diag,
   a.nrhs = nrhs;
   a.rstride = hb();
   if (ctx->tuner.on) {
-    const std::array<int, 5> key{prec, diag, postinv ? 1 : 0, F->g.Vh, nrhs};
+    const std::array<int, 5> key{prec * 3 + fp(), diag, postinv ? 1 : 0, F->g.Vh, nrhs};
     auto it = ctx->tuner.best.find(key);
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     HIPCHK(hipStreamIsCapturing(st, &cs));
@@ -218,8 +219,10 @@ void FineOp::hop(void* out, const void* in, const void* x, int parity, int diag,
       a.group = it->second.group;
     }
   }
-  // timer id: precision x DIAG mode x clover-inverse post-multiply; batched launches from 32
-  const int id = (nrhs > 1 ? 32 : 0) + prec * 6 + diag * 2 + (postinv ? 1 : 0);
+  // timer id: precision x DIAG mode x clover-inverse post-multiply; batched launches
+  // from 32, FP32 spinors with FP16 fields from 56
+  const int id = fp() != prec ? 56 + diag * 2 + (postinv ? 1 : 0)
+                              : (nrhs > 1 ? 32 : 0) + prec * 6 + diag * 2 + (postinv ? 1 : 0);
   hipEvent_t e = nullptr;
   if (ctx->timer.on) ctx->timer.begin(id, &e);
   launch_dslash(prec, diag, postinv, a, st);
@@ -227,7 +230,7 @@ void FineOp::hop(void* out, const void* in, const void* x, int parity, int diag,
 }
 
 void FineOp::clover(void* out, const void* in, int parity, int kind, int nrhs) {
-  launch_clover(prec, out, in, F->clov[prec].p, F->g.Vh, parity, kind, st, nrhs, hb());
+  launch_clover(prec, out, in, F->clov[fp()].p, F->g.Vh, parity, kind, st, nrhs, hb(), fp());
 }
 
 void FineOp::Dr(void* out, const void* y, int nrhs) {
@@ -297,7 +300,7 @@ void CoarseOp::Dr(void* out, const void* y, int nrhs) {
   w->ensure(nall() * csize() * nrhs);
   if (prec == WCMG_F32 && nrhs >= 2 && C->has_frag) {
     // batches run on the matrix cores (FP16 operands, FP32 accumulation)
-    const int id = timer_base + 24;
+    const int id = timer_base + 30;  // 50 (level 1), 52 (level 2)
     hipEvent_t e = nullptr;
     if (timer && timer->on) timer->begin(id, &e);
     launch_coarse_hop_mfma(w->t1.p, y, nullptr, C->frag.p, 1.0, 1, C->cg, C->nbr.as<int>(), nrhs, nall(), st);
@@ -309,12 +312,12 @@ void CoarseOp::Dr(void* out, const void* y, int nrhs) {
   hipEvent_t e = nullptr;
   if (timer && timer->on) timer->begin(id, &e);
   launch_coarse_hop(prec, w->t1.p, y, nullptr, C->Yt[pi()].p, nullptr, 0, 1.0, 1, C->cg, C->nbr.as<int>(), st, nrhs,
-                    nall());
+                    nall(), true);
   if (e) timer->end(id, e);
   e = nullptr;
   if (timer && timer->on) timer->begin(id, &e);
   launch_coarse_hop(prec, out, w->t1.p, y, C->Yt[pi()].p, nullptr, 1, -1.0, 0, C->cg, C->nbr.as<int>(), st, nrhs,
-                    nall());
+                    nall(), true);
   if (e) timer->end(id, e);
 }
 

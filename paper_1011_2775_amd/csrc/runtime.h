@@ -91,6 +91,8 @@ struct FineOp {
   int prec;
   FineWork* w;
   hipStream_t st;
+  int fprec = -1;  // storage of links and clover (-1: prec; F16 with F32 spinors)
+  int fp() const { return fprec < 0 ? prec : fprec; }
   const Geom& g() const { return F->g; }
   size_t hb() const { return spinor_bytes(prec, F->g.Vh); }
   size_t nelem() const { return (size_t)12 * F->g.Vh; }

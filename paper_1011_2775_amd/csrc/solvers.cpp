@@ -405,6 +405,7 @@ struct MGSolver {
   LatticeState& L;
   int sp;  // precision of the fine part of the preconditioner
   int cp;  // precision of the coarse levels
+  int fprec = -1;  // storage of the fields in the fine smoother (F16 or as sp)
   DBuf r_s, e_s, res_s, Ar_s;
   struct Level {
     DBuf cb, cc, cbr, cy;       // right-hand side, solution, reduced forms
@@ -436,6 +437,8 @@ struct MGSolver {
 
   MGSolver(Ctx& ctx, LatticeState& lat) : c(ctx), L(lat) {
     sp = L.params.smoother_prec == WCMG_F64 ? WCMG_F64 : WCMG_F32;
+    // F16: FP32 spinors and arithmetic with half-precision links and clover
+    fprec = L.params.smoother_prec == WCMG_F16 ? WCMG_F16 : -1;
     cp = sp;
     const Geom& g = L.F.g;
     size_t hb = spinor_bytes(sp, g.Vh);
@@ -573,7 +576,7 @@ struct MGSolver {
   void precondition_body(void* z64, const void* r64) {
     const Geom& g = L.F.g;
     hipStream_t st = c.st;
-    FineOp op{&c, &L.F, sp, &fwork, st};
+    FineOp op{&c, &L.F, sp, &fwork, st, fprec};
     const size_t n = (size_t)12 * g.Vh;
     CoarseLevel& C = *L.levels[0];
     Level& V = lv[0];
@@ -707,7 +710,7 @@ struct MGSolver {
     ensure_batch(nrhs);
     const Geom& g = L.F.g;
     hipStream_t st = c.st;
-    FineOp op{&c, &L.F, sp, &fwork, st};
+    FineOp op{&c, &L.F, sp, &fwork, st, fprec};
     const size_t n = (size_t)12 * g.Vh;
     const size_t h64 = spinor_bytes(WCMG_F64, g.Vh), hs = spinor_bytes(sp, g.Vh);
     CoarseLevel& C = *L.levels[0];

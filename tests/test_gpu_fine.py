@@ -242,3 +242,30 @@ def test_autotuned_launches_are_bitwise_identical(setup):
     rep = ctx.autotune_report()
     assert len(rep) >= 6 and all(r["threads"] in (64, 128, 256) for r in rep)
     ctx.autotune(False)
+
+
+def test_all_lattices_in_one_launch():
+    """Three lattices of different volumes through one launch per kernel
+    (lat = -1) give bitwise the per-lattice results."""
+    specs = [((4, 4, 4, 8), -1), ((6, 4, 8, 10), -1), ((8, 8, 8, 8), 1)]
+    ctx = w.Context(specs)
+    rng = np.random.default_rng(29)
+    parts = []
+    for l, (dims, tbc) in enumerate(specs):
+        U = inputs.gauge_field(dims, 0.4, 1100 + l)
+        ctx.set_gauge(torch.from_numpy(U).cuda(), lat=l)
+        ctx.set_clover(-0.1 * l, 1.0, lat=l)
+        V = int(np.prod(dims))
+        parts.append(rng.standard_normal((V, 4, 3)) + 1j * rng.standard_normal((V, 4, 3)))
+    flat = torch.from_numpy(np.concatenate([p.reshape(-1) for p in parts])).cuda()
+    for prec in (w.F64, w.F32):
+        for which in (w.OP_FULL, w.OP_SCHUR):
+            got = ctx.apply_D(flat, which, prec, lat=-1).cpu().numpy()
+            o = 0
+            for l, (dims, _) in enumerate(specs):
+                V = int(np.prod(dims))
+                one = torch.from_numpy(parts[l].reshape((1,) + tuple(reversed(dims)) + (4, 3))).cuda()
+                want = ctx.apply_D(one, which, prec, lat=l).cpu().numpy().reshape(-1)
+                assert np.array_equal(got[o * 12:(o + V) * 12], want), (prec, which, l)
+                o += V
+    ctx.close()

@@ -256,3 +256,32 @@ def test_batched_coarse_stencil_on_matrix_cores():
         err = np.linalg.norm(got[r] - want) / np.linalg.norm(want)
         assert err < 5e-3, (r, err)
     ctx.close()
+
+
+def test_fp16_field_smoother_16x16x16x32():
+    """Half-precision links and clover in the smoother (FP32 vectors and
+    arithmetic): the FP64 outer GCR still reaches 1e-10, within a few outer
+    iterations of the FP32 smoother."""
+    cfg = inputs.config("c2_16x16x16x32")
+    dims = cfg["dims"]
+    U = inputs.gauge_field(dims, cfg["eps"], cfg["gauge_seed"], ape_sweeps=cfg["ape"])
+    ctx = w.Context(dims)
+    ctx.set_gauge(torch.from_numpy(U).cuda())
+    ctx.set_clover(-0.25, cfg["csw"])
+    base = dict(block=cfg["blocks"], nvec=cfg["nvec"], seed=cfg["setup_seed"])
+    ctx.set_mg_params(w.default_params(**base))
+    ctx.build_null_vectors()
+    ctx.build_coarse()
+    vecs = ctx.get_null_vectors()
+    b = torch.from_numpy(inputs.z2_source(dims, cfg["source_seeds"][0])[None]).cuda()
+    its = {}
+    for sp in (w.F32, w.F16):
+        ctx.set_mg_params(w.default_params(smoother_prec=sp, **base))
+        ctx.set_null_vectors(vecs)
+        ctx.build_coarse()
+        x, st = ctx.solve(b, w.MG_GCR, 1e-10)
+        assert st[0]["true_rel_res"] <= 1.0000001e-10
+        its[sp] = st[0]["iters"]
+    print("outer iterations F32 / F16 fields:", its, flush=True)
+    assert its[w.F16] <= its[w.F32] + 3
+    ctx.close()
