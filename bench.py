@@ -54,10 +54,19 @@ def dslash_flops_per_site(diag, postinv):
     return f
 
 
-def kernel_table(ctxs, vh, coarse_sites_h, coarse_n):
-    """Per timed kernel id: launches, mean duration, algorithmic bytes per launch."""
+def coarse_step_bytes(coarse_sites_h, coarse_n, cs=8):
+    """Algorithmic bytes of one step of the red-black coarse GCR: the two
+    half hops read the 8 hop blocks (n x n complex) of every site once, and
+    the step makes about ten passes over length-Vh/2*n vectors (gathers,
+    the new basis pair, the update of x and r)."""
+    return coarse_sites_h * (2 * 8 * coarse_n * coarse_n + 10 * coarse_n) * cs
+
+
+def kernel_table(ctxs, vh, coarse_sites_h, coarse_n, coarse_steps=0):
+    """Per timed kernel id: launches, mean duration, algorithmic bytes per launch.
+    coarse_steps: GCR steps the persistent coarse solves took in total."""
     rows = []
-    for kid in list(range(18)) + [20, 21]:
+    for kid in list(range(18)) + [20, 21, 28]:
         n, ms = 0, 0.0
         for c in ctxs:
             cn, cms = c.timer_read(kid)
@@ -71,6 +80,12 @@ def kernel_table(ctxs, vh, coarse_sites_h, coarse_n):
             name = "dslash_kernel<%s,%d,%s>" % (["double", "float", "__half"][prec], diag, str(bool(postinv)).lower())
             bytes_launch = dslash_bytes_per_site(prec, diag, postinv) * vh
             flops = dslash_flops_per_site(diag, postinv) * vh
+        elif kid == 28:
+            # the whole coarse solve in one launch: bytes and flops of its GCR steps
+            name = "k_coarse_gcr<float>"
+            steps = coarse_steps / n
+            bytes_launch = steps * coarse_step_bytes(coarse_sites_h, coarse_n)
+            flops = steps * 2 * coarse_sites_h * 8 * coarse_n * coarse_n * 8
         else:
             cs = 16 if kid == 20 else 8
             name = "k_coarse_hop<%s, 1>" % ("double" if kid == 20 else "float")
@@ -82,6 +97,32 @@ def kernel_table(ctxs, vh, coarse_sites_h, coarse_n):
                          TFLOPs=round(flops / (avg_ms * 1e-3) / 1e12, 3)))
     rows.sort(key=lambda r: -r["total_ms"])
     return rows
+
+
+# kernel -> source files whose text the traffic counters were taken with
+KERNEL_SOURCES = {"k_coarse_gcr<float>": ["coarse_persist.hip"],
+                  "k_coarse_hop<float, 1>": ["coarse.hip"]}
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the same counter
+    reads for a plain copy of known size), or None when there is none or the
+    kernel's source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    srcs = KERNEL_SOURCES.get(kernel)
+    if not srcs or not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get("kernels", {}).get(kernel)
+    if not rec:
+        return None
+    h = hashlib.sha256()
+    for f in srcs:
+        h.update(open(os.path.join(ROOT, "paper_1011_2775_amd", "csrc", f), "rb").read())
+    if h.hexdigest() != rec.get("source_sha256"):
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def cpu_baseline(dims, U, m0, csw, b, bicg_iters_gpu):
@@ -303,6 +344,7 @@ def main():
         ctx.timer_enable(True)
     per = {m0: [] for m0 in all_masses}
     last = {}
+    timed_stats = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -311,6 +353,7 @@ def main():
             x, st = ctx.solve(bt, w.MG_GCR, cfg["tol"])
             per[m0].append(time.perf_counter() - ts)
             last[m0] = (x, st[0])
+            timed_stats.append(st[0])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     print("timed region done", file=sys.stderr, flush=True)
@@ -327,12 +370,15 @@ def main():
     vh = inputs.volume(dims) // 2
     bl = cfg["blocks"][0]
     vc = inputs.volume(dims) // int(np.prod(bl))
-    rows = kernel_table(main_ctxs, vh, vc // 2, 2 * cfg["nvec"][0])
+    # coarse GCR steps of the timed solves (one coarse solve per outer iteration)
+    coarse_steps = sum(st["inner_iters"][0] * st["iters"] for st in timed_stats)
+    rows = kernel_table(main_ctxs, vh, vc // 2, 2 * cfg["nvec"][0], coarse_steps)
     for ctx in main_ctxs:
         ctx.timer_enable(False)
     dom = rows[0]
     roofline = {"bound": "hbm", "kernel": dom["kernel"], "achieved": dom["GBps"], "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": round(dom["GBps"] / PEAK_HBM_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(dom["GBps"] / PEAK_HBM_GBS, 4),
+                "traffic": measured_traffic(dom["kernel"]),
                 "bytes_per_launch": dom["bytes_per_launch"], "avg_launch_us": dom["avg_us"],
                 "note": "working set fits the 256 MB Infinity Cache at 16^3x32; see dslash_24x24x24x64"}
 

@@ -110,6 +110,10 @@ typedef struct {
                                        GCR runs exactly max_iter[l] steps with no host round trip;
                                        2: as 1, with the whole preconditioner captured once into a
                                        HIP graph and replayed at every outer iteration */
+  int coarse_launch;                /* unpreconditioned GCR on the coarsest level: 0 (default) the
+                                       whole solve in one cooperative launch with grid barriers,
+                                       where the device supports it and cycle_mode != 2; 1 one
+                                       launch per kernel of every step */
 } wcmg_mg_params;
 
 typedef struct {
@@ -195,6 +199,21 @@ int wcmg_prolong(void* ctx, int lat, int level, int prec, void* fine_out, const 
 /* Coarse stencil of coarse level `level` (>= 1) in form op (FULL: Yhat,
  * SCHUR: 1 - Yhat_eo X_oo^-1 Yhat_oe X_ee^-1, DP: Yhat X^-1). */
 int wcmg_apply_coarse(void* ctx, int lat, int level, int op, int prec, void* out, const void* in, int nrhs);
+
+/* Approximate solve of coarse level `level` (>= 1), as inside the cycle
+ * (coarse even-odd paragraph, GCR of the solver paragraph): red-black GCR
+ * with restart length `restart` (1..64) on the reduced coarse operator from
+ * a zero start, stopping when ||r_r|| <= tol ||b_r|| (true reduced residual
+ * recomputed at the end of every cycle) or after max_iter steps, then the
+ * odd half reconstructed.  b and x: one complex128 [Vc][2 Nv] device vector
+ * each (lexicographic coarse sites).  prec: F64 or F32 arithmetic and
+ * storage.  launch 0: the whole solve in one cooperative launch with grid
+ * barriers (WCMG_ENODEV if the device cannot run the grid at once); launch 1:
+ * one launch per kernel of every step.  stats (optional): iters, status, and
+ * true_rel_res = ||b - Yhat x|| / ||b|| of the full coarse system in prec.
+ * Requires a lattice with every coarse extent even (EDIM otherwise). */
+int wcmg_coarse_solve(void* ctx, int lat, int level, int prec, void* x, const void* b, double tol, int max_iter,
+                      int restart, int launch, wcmg_stats* stats);
 
 /* Solve D x = b for nrhs canonical right-hand sides (device).  x is the
  * initial guess on entry if nonzero.  Stops when ||b - D x|| <= tol ||b||

@@ -174,6 +174,17 @@ class Context:
                                          ctypes.c_void_p(inp.data_ptr()), nrhs))
         return out
 
+    def coarse_solve(self, b, level=1, prec=F64, tol=0.1, max_iter=100, restart=30, launch=0, lat=0):
+        """Approximate Dhat^-1 b on coarse level `level` (complex128 [Vc][2Nv] device
+        vector) by the red-black GCR of the cycle; launch 0: one cooperative launch."""
+        b = b.contiguous()
+        x = torch.empty_like(b)
+        st = _lib.Stats()
+        check(_lib.LIB.wcmg_coarse_solve(self.h, lat, level, prec, ctypes.c_void_p(x.data_ptr()),
+                                         ctypes.c_void_p(b.data_ptr()), float(tol), int(max_iter), int(restart),
+                                         int(launch), ctypes.byref(st)))
+        return x, st.as_dict()
+
     # -- solve -------------------------------------------------------------------
     def solve(self, b, solver=MG_GCR, tol=1e-10, x0=None, lat=0, raise_on_error=True):
         """x with D x = b (canonical complex128 device tensor of nrhs spinors)."""

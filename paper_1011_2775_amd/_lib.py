@@ -42,7 +42,8 @@ class MGParams(ctypes.Structure):
                 ("setup_rq_tol", ctypes.c_double),
                 ("seed", ctypes.c_uint64),
                 ("coarsest", ctypes.c_int),
-                ("cycle_mode", ctypes.c_int)]
+                ("cycle_mode", ctypes.c_int),
+                ("coarse_launch", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -78,6 +79,7 @@ SIGNATURES = {
     "wcmg_restrict": [_vp, _i, _i, _i, _vp, _vp, _i],
     "wcmg_prolong": [_vp, _i, _i, _i, _vp, _vp, _i],
     "wcmg_apply_coarse": [_vp, _i, _i, _i, _i, _vp, _vp, _i],
+    "wcmg_coarse_solve": [_vp, _i, _i, _i, _vp, _vp, _d, _i, _i, _i, _vp],
     "wcmg_solve": [_vp, _i, _i, _vp, _vp, _i, _d, ctypes.POINTER(Stats)],
     "wcmg_solve_dag": [_vp, _i, _i, _vp, _vp, _i, _d, ctypes.POINTER(Stats)],
     "wcmg_force": [_vp, _i, _vp, _vp, _vp, _i, _i],

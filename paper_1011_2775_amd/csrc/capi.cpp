@@ -1,6 +1,7 @@
 // C ABI of the wcmg library: argument validation, canonical <-> internal
 // layout conversion, and dispatch to the runtime.  No exception crosses the
 // boundary; every entry point returns a status code.
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -279,6 +280,7 @@ int wcmg_set_mg_params(void* ctx, int lat, const wcmg_mg_params* p) {
   CHECK(p->setup_relax >= 1 && p->setup_max_steps >= 1, WCMG_EINVAL, "setup iteration counts must be >= 1");
   CHECK(p->coarsest == 0 || p->coarsest == 1, WCMG_EINVAL, "coarsest must be 0 (GCR) or 1 (dense FP64 inverse)");
   CHECK(p->cycle_mode >= 0 && p->cycle_mode <= 2, WCMG_EINVAL, "cycle_mode must be 0, 1 or 2");
+  CHECK(p->coarse_launch == 0 || p->coarse_launch == 1, WCMG_EINVAL, "coarse_launch must be 0 or 1");
   // coarse extents and degrees of freedom of every level
   int ext[4], nf = 2 * p->nvec[0];
   for (int k = 0; k < 4; ++k) ext[k] = g.L[k] / p->block[0][k];
@@ -743,6 +745,68 @@ int wcmg_apply_coarse(void* ctx, int lat, int level, int op, int prec, void* out
     for (int r = 0; r < nrhs; ++r)
       launch_coarse_canon(prec, vo + r * nall * cs, (char*)out + r * cone, C.perm.as<int>(), C.cg.V, C.cg.n, false,
                           c->st);
+  });
+}
+
+int wcmg_coarse_solve(void* ctx, int lat, int level, int prec, void* x, const void* b, double tol, int max_iter,
+                      int restart, int launch, wcmg_stats* stats) {
+  Ctx* c = as_ctx(ctx);
+  if (int r = check_lat(c, lat)) return r;
+  CHECK(x && b, WCMG_EINVAL, "null buffer");
+  CHECK(x != b, WCMG_EINVAL, "x and b must not alias");
+  CHECK(prec == WCMG_F64 || prec == WCMG_F32, WCMG_EINVAL, "coarse precision must be F64 or F32");
+  CHECK(tol > 0 && tol < 1, WCMG_EINVAL, "tol must be in (0,1)");
+  CHECK(max_iter >= 1 && restart >= 1 && restart <= kMaxRestart, WCMG_EINVAL,
+        "max_iter must be >= 1 and restart in 1..64");
+  CHECK(launch == 0 || launch == 1, WCMG_EINVAL, "launch must be 0 or 1");
+  LatticeState& L = *c->lats[lat];
+  CHECK(L.have_params && level >= 1 && level <= L.params.nlevels, WCMG_EINVAL, "level out of range");
+  CHECK((int)L.levels.size() >= level && L.levels[level - 1]->built, WCMG_ESTATE, "coarse operator not built");
+  CoarseLevel& C = *L.levels[level - 1];
+  CHECK(C.cg.split, WCMG_EDIM, "coarse lattice has an odd extent: no red-black form");
+  return guarded([&] {
+    const size_t cs = prec == WCMG_F64 ? 16 : 8;
+    const size_t nall = (size_t)C.cg.V * C.cg.n;
+    void* vb = c->scratch_buf(40, nall * cs);
+    void* vx = c->scratch_buf(41, nall * cs);
+    void* t = c->scratch_buf(42, nall * cs);
+    void* y = c->scratch_buf(43, nall * cs);
+    void* r = c->scratch_buf(44, nall * cs);
+    void* br = c->scratch_buf(45, nall * cs);
+    launch_coarse_canon(prec, vb, const_cast<void*>(b), C.perm.as<int>(), C.cg.V, C.cg.n, true, c->st);
+    wcmg_stats s{};
+    auto t0 = std::chrono::steady_clock::now();
+    CoarseOp op{&C, prec, &c->cw[prec == WCMG_F64 ? 0 : 1], c->st};
+    if (launch == 0) {
+      PersistWork pw;
+      if (!persistent_available(pw, prec, C, restart))
+        fail(WCMG_ENODEV, "the device cannot run the persistent coarse solve");
+      persistent_launch(*c, pw, C, prec, vx, vb, t, y, r, br, tol, restart, max_iter, false);
+      int code = WCMG_OK;
+      s.iters = (int)persistent_collect(*c, pw, &code);
+      s.status = code;
+    } else {
+      op.reduced_source(br, vb);
+      const double bn = std::sqrt(norm2(*c, prec, br, op.neven()));
+      GcrSpace S;
+      S.prec = prec;
+      S.n = op.neven();
+      S.bytes = S.n * cs;
+      OpFn A = [&](void* o, const void* i) { op.Dr(o, i); };
+      KrylovResult kr = gcr(*c, S, A, nullptr, y, br, true, tol, bn, restart, max_iter, false);
+      op.reconstruct(vx, y, vb);
+      s.iters = kr.iters;
+      s.status = kr.status;
+    }
+    HIPCHK(hipStreamSynchronize(c->st));
+    s.t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    launch_coarse_canon(prec, vx, x, C.perm.as<int>(), C.cg.V, C.cg.n, false, c->st);
+    // ||b - Yhat x|| / ||b|| of the full coarse system
+    op.Dfull(t, vx);
+    blas_axpby(prec, 1.0, 0.0, vb, -1.0, 0.0, t, nall, c->st);
+    const double rr = norm2(*c, prec, t, nall), bb = norm2(*c, prec, vb, nall);
+    s.true_rel_res = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+    if (stats) *stats = s;
   });
 }
 

@@ -233,6 +233,41 @@ void launch_coarse_hop(int prec, void* out, const void* in, const void* x, const
 void launch_coarse_local(int prec, void* out, const void* in, const void* M, int parity, const CoarseGeom& cg,
                          hipStream_t st, int nrhs = 1, size_t vs = 0);
 void launch_batched_inverse(double* M, int nmat, int n, int* flag, hipStream_t st);
+// Whole approximate coarse solve (red-black reduced operator, GCR(restart)
+// from zero, stopping at ||r|| <= tol ||b_r|| or after maxiter steps; fixed:
+// exactly min(restart, maxiter) steps) in one cooperative launch of `grid`
+// (<= 256) workgroups.  Buffers: b, c, t [V][n]; y, br [Vh][n]; r [2][Vh][n];
+// Q, Z [restart][Vh][n]; part 2 * grid * coarse_gcr_persistent_part_doubles();
+// bar: kPersistCtlBytes of barrier lines (zeroed before the first launch;
+// consistent after every completed launch, zeroed again after an abort); info
+// [3] (at bar + kPersistInfoOffset bytes in the library's use): iterations are
+// added to info[0], a failure code goes to info[1], info[2] is raised when a
+// grid barrier timed out.
+constexpr size_t kPersistCtlBytes = 36 * 1024;
+constexpr size_t kPersistInfoOffset = 34 * 1024;
+struct CoarseGcrArgs {
+  const void* Yt;
+  const void* Xinv;
+  const int* nbr;
+  const void* b;
+  void* c;
+  void* t;
+  void* y;
+  void* r;
+  void* br;
+  void* Q;
+  void* Z;
+  double* part;
+  unsigned* bar;
+  int* info;
+  double tol;
+  int Vh, n, restart, maxiter, fixed, grid;
+};
+size_t coarse_gcr_persistent_part_doubles();
+// workgroups of the persistent coarse solve on this device (0: not available)
+int coarse_gcr_persistent_grid(int prec, int n, int Vh);
+void launch_coarse_gcr_persistent(int prec, const CoarseGcrArgs& a, hipStream_t st);
+
 // Yt[c][d] = Y[c][d] * Xinv[nb(c,d)]   (all column-major n x n)
 void launch_coarse_right_mul(double* Yt, const double* Y, const double* Xinv, const int* nbr, int V, int n,
                              hipStream_t st);

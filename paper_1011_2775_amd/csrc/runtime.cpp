@@ -308,7 +308,8 @@ void CoarseOp::Dr(void* out, const void* y, int nrhs) {
     if (e) timer->end(id, e);
     return;
   }
-  const int id = timer_base + pi() + (nrhs > 1 ? 16 : 0);
+  // single right-hand side: 20 + 2 level + precision; batches: 24 + 2 level + precision
+  const int id = timer_base + pi() + (nrhs > 1 ? 4 : 0);
   hipEvent_t e = nullptr;
   if (timer && timer->on) timer->begin(id, &e);
   launch_coarse_hop(prec, w->t1.p, y, nullptr, C->Yt[pi()].p, nullptr, 0, 1.0, 1, C->cg, C->nbr.as<int>(), st, nrhs,

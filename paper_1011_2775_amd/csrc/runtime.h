@@ -247,6 +247,20 @@ struct KrylovResult {
 
 KrylovResult gcr(Ctx& c, GcrSpace& S, const OpFn& A, const OpFn* K, void* x, const void* b, bool x_zero,
                  double tol, double target_norm, int restart, int maxiter, bool fixed_iters = false);
+// The unpreconditioned red-black GCR of a coarse level in one cooperative
+// launch: buffers of its own, iterations and failures counted on the device
+// and read back by persistent_collect (one host synchronisation).
+struct PersistWork {
+  DBuf q, z, part, ctl;  // Krylov bases, partial sums, {barrier[2], info[3]}
+  int grid = -1;         // workgroups (0: not available; -1: not yet queried)
+  bool pending = false;  // device counters not yet read back
+};
+bool persistent_available(PersistWork& w, int prec, const CoarseLevel& C, int restart);
+// out = approximate Dhat^-1 in (full coarse vectors); t: full scratch, y, r, br: >= half vectors
+void persistent_launch(Ctx& c, PersistWork& w, CoarseLevel& C, int prec, void* out, const void* in, void* t, void* y,
+                       void* r, void* br, double tol, int restart, int maxiter, bool fixed);
+// iterations since the last collect; status (optional) gets the first failure code
+long persistent_collect(Ctx& c, PersistWork& w, int* status = nullptr);
 KrylovResult bicgstab(Ctx& c, int prec, size_t n, const OpFn& A, void* x, const void* b, double tol,
                       double target_norm, int maxiter);
 // batched flexible GCR: A and K act on S.nrhs right-hand sides at once

@@ -397,6 +397,72 @@ KrylovResult bicgstab(Ctx& c, int prec, size_t n, const OpFn& A, void* x, const 
 }
 
 // ---------------------------------------------------------------------------
+// coarse red-black GCR in one cooperative launch
+// ---------------------------------------------------------------------------
+bool persistent_available(PersistWork& w, int prec, const CoarseLevel& C, int restart) {
+  if (!C.cg.split || restart < 1 || restart > kMaxRestart) return false;
+  if (w.grid < 0) w.grid = coarse_gcr_persistent_grid(prec, C.cg.n, C.cg.Vh);
+  return w.grid > 0;
+}
+
+void persistent_launch(Ctx& c, PersistWork& w, CoarseLevel& C, int prec, void* out, const void* in, void* t, void* y,
+                       void* r, void* br, double tol, int restart, int maxiter, bool fixed) {
+  const size_t cs = prec == WCMG_F64 ? 16 : 8;
+  const size_t hv = (size_t)C.cg.Vh * C.cg.n;
+  restart = std::min(restart, std::max(1, maxiter));
+  w.q.alloc((size_t)restart * hv * cs);
+  w.z.alloc((size_t)restart * hv * cs);
+  if (!w.ctl.p) {
+    w.part.alloc(2 * (size_t)w.grid * coarse_gcr_persistent_part_doubles() * sizeof(double));
+    w.ctl.alloc(kPersistCtlBytes);
+    HIPCHK(hipMemsetAsync(w.ctl.p, 0, kPersistCtlBytes, c.st));
+  }
+  CoarseGcrArgs a{};
+  const int pi = prec == WCMG_F64 ? 0 : 1;
+  a.Yt = C.Yt[pi].p;
+  a.Xinv = C.Xinv[pi].p;
+  a.nbr = C.nbr.as<int>();
+  a.b = in;
+  a.c = out;
+  a.t = t;
+  a.y = y;
+  a.r = r;
+  a.br = br;
+  a.Q = w.q.p;
+  a.Z = w.z.p;
+  a.part = w.part.as<double>();
+  a.bar = w.ctl.as<unsigned>();
+  a.info = reinterpret_cast<int*>(w.ctl.as<char>() + kPersistInfoOffset);
+  a.tol = tol;
+  a.Vh = C.cg.Vh;
+  a.n = C.cg.n;
+  a.restart = restart;
+  a.maxiter = maxiter;
+  a.fixed = fixed ? 1 : 0;
+  a.grid = w.grid;
+  launch_coarse_gcr_persistent(prec, a, c.st);
+  w.pending = true;
+}
+
+long persistent_collect(Ctx& c, PersistWork& w, int* status) {
+  if (status) *status = WCMG_OK;
+  if (!w.pending) return 0;
+  w.pending = false;
+  int info[3] = {0, 0, 0};
+  char* ctl = w.ctl.as<char>();
+  HIPCHK(hipMemcpyAsync(info, ctl + kPersistInfoOffset, sizeof(info), hipMemcpyDeviceToHost, c.st));
+  HIPCHK(hipStreamSynchronize(c.st));
+  HIPCHK(hipMemsetAsync(ctl + kPersistInfoOffset, 0, sizeof(info), c.st));
+  if (info[2]) {
+    // barrier flags of an aborted launch are inconsistent: start again from zero
+    HIPCHK(hipMemsetAsync(ctl, 0, kPersistCtlBytes, c.st));
+    fail(WCMG_EHIP, "persistent coarse solve: a grid barrier timed out");
+  }
+  if (status) *status = info[1];
+  return info[0];
+}
+
+// ---------------------------------------------------------------------------
 // multigrid preconditioner: fine Wilson-clover level and one or two coarse
 // stencil levels, recursive flexible GCR ("Implementation" paragraph)
 // ---------------------------------------------------------------------------
@@ -414,6 +480,7 @@ struct MGSolver {
     GcrSpaceB bspace{};         // lockstep space for batches
     int batch = 1;              // right-hand sides the buffers hold
     long calls = 0, iters = 0;
+    PersistWork pw;             // the coarsest GCR as one cooperative launch (coarse_launch 0)
   };
   int batch = 1;  // right-hand sides the fine buffers hold
   std::vector<Level> lv;  // lv[li]: coarse level li + 1
@@ -480,6 +547,10 @@ struct MGSolver {
       V.iters += 1;
       return;
     }
+    if (last && C.cg.split && persistent_ok(li)) {
+      persistent_solve(li, out, in);
+      return;
+    }
     OpFn Kf = [this, li](void* o, const void* i) { precondition_coarse(li, o, i); };
     const OpFn* K = (!last && C.cg.split) ? &Kf : nullptr;
     KrylovResult kr;
@@ -496,6 +567,31 @@ struct MGSolver {
       kr = gcr(c, V.space, A, nullptr, out, in, true, p.tol[li], bn, p.restart[li], p.max_iter[li], fx);
     }
     V.iters += kr.iters;
+  }
+
+  // unpreconditioned coarsest GCR in one cooperative launch: not under graph
+  // capture (cycle_mode 2), and only where the device runs the whole grid at once
+  bool persistent_ok(int li) {
+    const wcmg_mg_params& p = L.params;
+    if (p.coarse_launch != 0 || p.cycle_mode == 2) return false;
+    return persistent_available(lv[li].pw, cp, *L.levels[li], p.restart[li]);
+  }
+
+  void persistent_solve(int li, void* out, void* in) {
+    Level& V = lv[li];
+    const wcmg_mg_params& p = L.params;
+    const int id = 28 + li;
+    hipEvent_t e = nullptr;
+    if (c.timer.on) c.timer.begin(id, &e);
+    persistent_launch(c, V.pw, *L.levels[li], cp, out, in, V.rfull.p, V.cy.p, V.res.p, V.cbr.p, p.tol[li],
+                      p.restart[li], p.max_iter[li], fixed());
+    if (e) c.timer.end(id, e);
+  }
+
+  // iterations the persistent coarse solves counted on the device (raises
+  // if one of them lost its grid barrier)
+  void collect_device_stats() {
+    for (Level& V : lv) V.iters += persistent_collect(c, V.pw);
   }
 
   // MR smoothing of e towards D_r e = r on the even half of n elements
@@ -1138,6 +1234,7 @@ void solve_rhs(Ctx& c, LatticeState& L, int solver, void* x_e, void* x_o, const 
       for (auto& lvl : mg.lv) lvl.calls = lvl.iters = 0;
       OpFn K = [&](void* o, const void* i) { mg.precondition(o, i); };
       kr = gcr(c, S64, Dr, &K, y, br, x_zero, tol, bn, restart, maxiter);
+      mg.collect_device_stats();
       for (size_t l = 0; l < mg.lv.size() && l < 3; ++l)
         s.inner_iters[l] = mg.lv[l].calls ? (double)mg.lv[l].iters / mg.lv[l].calls : 0.0;
     }
@@ -1204,6 +1301,7 @@ void solve_batch(Ctx& c, LatticeState& L, void* x_e, void* x_o, const void* b_e,
     if (v == 0.0) v = 1.0;
   std::vector<KrylovResult> kr = gcr_b(c, outer, Dr, &K, y, br, x_zero, tol, tn.data(), p.outer_restart,
                                        p.outer_max_iter);
+  mg.collect_device_stats();
   op.reconstruct(x_e, x_o, y, b_o, nrhs);
   // true residuals of the full system in FP64
   void* te = c.scratch_buf(2, hb * nrhs);

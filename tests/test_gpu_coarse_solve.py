@@ -1,0 +1,181 @@
+"""The coarse solve of the cycle in one cooperative launch (persistent GCR).
+
+The whole red-black GCR of a coarse level (reduced source, GCR(m) with
+classical Gram-Schmidt and a true residual at the end of every cycle,
+reconstruction) runs in one launch with grid barriers.  Checked against
+the oracle's coarse stencil, built from the operator the GPU itself
+assembled (so the test pins the solve, not the coarse build):
+
+* tight tolerance: the solution equals the dense FP64 solve of the coarse
+  system (small lattice) and the full coarse residual, recomputed by the
+  oracle, is within the tolerance; FP32 to its own accuracy;
+* the same solve issued one kernel at a time (launch 1) reaches the same
+  tolerance in the same number of steps (within 2: the two sum in
+  different orders), and the two solutions agree;
+* the cycle's own setting (tol 0.1), ragged site counts (coarse sites not
+  a multiple of the workgroup count), restart 1 and 64, a zero source;
+* multigrid solves with coarse_launch 0 and 1 reach 1e-10 (oracle D) in
+  outer iteration counts within 1 of each other, and the persistent kernel
+  is the one that ran (its timer counts launches).
+"""
+import numpy as np
+import pytest
+import torch
+
+import inputs
+from oracle.dirac import WilsonClover
+from oracle.multigrid import CoarseOperator
+
+pytestmark = pytest.mark.gpu
+
+w = pytest.importorskip("paper_1011_2775_amd")
+
+# (fine dims, block, nvec): coarse sites 32 (16 per parity), 512, 1728 (864 per parity: ragged)
+CASES = [((8, 8, 8, 16), (4, 4, 4, 4), 8), ((8, 8, 8, 16), (2, 2, 2, 2), 12), ((12, 12, 12, 16), (2, 2, 2, 2), 8)]
+
+
+def canon(v, shape):
+    return torch.from_numpy(np.ascontiguousarray(v).reshape(shape)).cuda()
+
+
+def build(dims, block, nvec, m0=-0.2, csw=1.0, seed=11):
+    U = inputs.gauge_field(dims, 0.3, 1000 + seed)
+    ctx = w.Context(dims)
+    ctx.set_gauge(torch.from_numpy(U).cuda())
+    ctx.set_clover(m0, csw)
+    ctx.set_mg_params(w.default_params(block=[block], nvec=[nvec]))
+    rng = np.random.default_rng(seed)
+    V = int(np.prod(dims))
+    v = rng.standard_normal((nvec, V, 4, 3)) + 1j * rng.standard_normal((nvec, V, 4, 3))
+    ctx.set_null_vectors(canon(v, (nvec,) + tuple(reversed(dims)) + (4, 3)), level=0)
+    ctx.build_coarse(0)
+    cdims = tuple(d // b for d, b in zip(dims, block))
+    cop = CoarseOperator(cdims, ctx.get_coarse(0))
+    return ctx, cop, U
+
+
+def rhs(cop, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(cop.shape) + 1j * rng.standard_normal(cop.shape)
+
+
+def full_res(cop, x, b):
+    return np.linalg.norm(b - cop.apply_D(x)) / np.linalg.norm(b)
+
+
+@pytest.fixture(scope="module", params=range(len(CASES)), ids=["32sites", "512sites", "1728sites"])
+def case(request):
+    dims, block, nvec = CASES[request.param]
+    print("case", dims, block, nvec, flush=True)
+    ctx, cop, U = build(dims, block, nvec)
+    yield ctx, cop
+    ctx.close()
+
+
+def test_tight_solve_fp64(case):
+    ctx, cop = case
+    b = rhs(cop, 1)
+    bt = torch.from_numpy(b).cuda()
+    xp, sp = ctx.coarse_solve(bt, prec=w.F64, tol=1e-12, max_iter=2000, restart=30, launch=0)
+    xs, ss = ctx.coarse_solve(bt, prec=w.F64, tol=1e-12, max_iter=2000, restart=30, launch=1)
+    xp, xs = xp.cpu().numpy(), xs.cpu().numpy()
+    print("iters persistent %d, per-kernel %d" % (sp["iters"], ss["iters"]), flush=True)
+    assert sp["status"] == "OK" and ss["status"] == "OK"
+    assert full_res(cop, xp, b) < 1e-11
+    assert full_res(cop, xs, b) < 1e-11
+    assert abs(sp["true_rel_res"] - full_res(cop, xp, b)) < 1e-12
+    assert abs(sp["iters"] - ss["iters"]) <= 2
+    assert np.linalg.norm(xp - xs) / np.linalg.norm(xs) < 1e-9
+    if cop.lat.V * cop.n <= 1024:
+        x = np.linalg.solve(cop.dense(), b.reshape(-1)).reshape(cop.shape)
+        assert np.linalg.norm(xp - x) / np.linalg.norm(x) < 1e-10
+
+
+def test_fp32_solve(case):
+    ctx, cop = case
+    b = rhs(cop, 2)
+    bt = torch.from_numpy(b).cuda()
+    xp, sp = ctx.coarse_solve(bt, prec=w.F32, tol=1e-5, max_iter=2000, restart=30, launch=0)
+    xs, ss = ctx.coarse_solve(bt, prec=w.F32, tol=1e-5, max_iter=2000, restart=30, launch=1)
+    rp, rs = full_res(cop, xp.cpu().numpy(), b), full_res(cop, xs.cpu().numpy(), b)
+    print("F32 iters %d / %d, residuals %.2e / %.2e" % (sp["iters"], ss["iters"], rp, rs), flush=True)
+    assert rp < 2e-5 and rs < 2e-5
+    assert abs(sp["iters"] - ss["iters"]) <= 2
+
+
+@pytest.mark.parametrize("prec", ["F64", "F32"])
+def test_cycle_setting(case, prec):
+    """tol 0.1, the cycle's setting: same step count as the per-kernel solve."""
+    ctx, cop = case
+    b = rhs(cop, 3)
+    bt = torch.from_numpy(b).cuda()
+    xp, sp = ctx.coarse_solve(bt, prec=getattr(w, prec), tol=0.1, max_iter=100, restart=30, launch=0)
+    xs, ss = ctx.coarse_solve(bt, prec=getattr(w, prec), tol=0.1, max_iter=100, restart=30, launch=1)
+    assert sp["iters"] == ss["iters"] or abs(sp["iters"] - ss["iters"]) <= 1
+    br = cop.reduced_source(b)
+    bound = 0.1 * np.linalg.norm(br) / np.linalg.norm(b)
+    assert full_res(cop, xp.cpu().numpy(), b) <= bound * 1.01
+
+
+@pytest.mark.parametrize("restart", [1, 64])
+def test_restart_extremes(case, restart):
+    ctx, cop = case
+    b = rhs(cop, 4)
+    bt = torch.from_numpy(b).cuda()
+    xp, sp = ctx.coarse_solve(bt, prec=w.F64, tol=1e-8, max_iter=5000, restart=restart, launch=0)
+    xs, ss = ctx.coarse_solve(bt, prec=w.F64, tol=1e-8, max_iter=5000, restart=restart, launch=1)
+    assert full_res(cop, xp.cpu().numpy(), b) < 1e-7
+    assert abs(sp["iters"] - ss["iters"]) <= max(2, ss["iters"] // 50)
+
+
+def test_zero_source(case):
+    ctx, cop = case
+    bt = torch.zeros(cop.shape, dtype=torch.complex128, device="cuda")
+    x, st = ctx.coarse_solve(bt, prec=w.F64, tol=0.1, max_iter=100, restart=30, launch=0)
+    assert st["iters"] == 0
+    assert torch.count_nonzero(x).item() == 0
+
+
+@pytest.mark.parametrize("nlevels", [1, 2])
+def test_multigrid_with_persistent_coarse_solve(nlevels):
+    dims = (8, 8, 8, 16)
+    U = inputs.gauge_field(dims, 0.3, 1021)
+    m0, csw = -0.2, 1.0
+    ctx = w.Context(dims)
+    ctx.set_gauge(torch.from_numpy(U).cuda())
+    ctx.set_clover(m0, csw)
+    if nlevels == 1:
+        kw = dict(block=[(2, 2, 2, 2)], nvec=[12], max_iter=[100], restart=[30])
+    else:
+        kw = dict(nlevels=2, block=[(2, 2, 2, 2), (2, 2, 2, 2)], nvec=[12, 16], max_iter=[20, 100],
+                  restart=[20, 30])
+    ctx.set_mg_params(w.default_params(seed=5, **kw))
+    for lvl in range(nlevels):
+        ctx.build_null_vectors(lvl)
+        ctx.build_coarse(lvl)
+    vecs = [ctx.get_null_vectors(level=l) for l in range(nlevels)]
+    b = canon(inputs.z2_source(dims, 3200), (1,) + tuple(reversed(dims)) + (4, 3))
+    op = WilsonClover(dims, U, m0, csw)
+    iters = {}
+    for launch in (0, 1):
+        ctx.set_mg_params(w.default_params(seed=5, coarse_launch=launch, **kw))
+        for l in range(nlevels):
+            ctx.set_null_vectors(vecs[l], level=l)
+            ctx.build_coarse(l)
+        ctx.timer_enable(True)
+        x, st = ctx.solve(b, w.MG_GCR, 1e-10)
+        n_persist, _ = ctx.timer_read(28 + nlevels - 1)
+        ctx.timer_enable(False)
+        xv = x.cpu().numpy().reshape(op.shape)
+        bv = b.cpu().numpy().reshape(op.shape)
+        res = np.linalg.norm(bv - op.apply_D(xv)) / np.linalg.norm(bv)
+        print("launch %d: outer %d, inner %s, res %.2e, persistent launches %d"
+              % (launch, st[0]["iters"], st[0]["inner_iters"][:nlevels], res, n_persist), flush=True)
+        assert res <= 1.0000001e-10
+        assert (n_persist > 0) == (launch == 0)
+        iters[launch] = st[0]
+    assert abs(iters[0]["iters"] - iters[1]["iters"]) <= 1
+    last = nlevels - 1
+    assert abs(iters[0]["inner_iters"][last] - iters[1]["inner_iters"][last]) <= \
+        0.1 * iters[1]["inner_iters"][last] + 1
+    ctx.close()
