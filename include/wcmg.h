@@ -110,6 +110,10 @@ typedef struct {
                                        GCR runs exactly max_iter[l] steps with no host round trip;
                                        2: as 1, with the whole preconditioner captured once into a
                                        HIP graph and replayed at every outer iteration */
+  wcmg_prec setup_prec;             /* arithmetic of the null-vector setup (inverse iteration, Setup
+                                       section): F32 (default), F64, or F16 (FP32 vectors and
+                                       arithmetic with half-precision links and clover); the
+                                       vectors are block-orthonormalised in FP64 afterwards */
   int coarse_launch;                /* unpreconditioned GCR on the coarsest level: 0 (default) the
                                        whole solve in one cooperative launch with grid barriers,
                                        where the device supports it and cycle_mode != 2; 1 one

@@ -43,6 +43,7 @@ class MGParams(ctypes.Structure):
                 ("seed", ctypes.c_uint64),
                 ("coarsest", ctypes.c_int),
                 ("cycle_mode", ctypes.c_int),
+                ("setup_prec", ctypes.c_int),
                 ("coarse_launch", ctypes.c_int)]
 
 

@@ -34,6 +34,12 @@ __global__ void __launch_bounds__(kThreads) k_finalize(const RedOut o, int nr, i
   }
 }
 
+// complex vector in storage D from storage T (rounding to nearest)
+template <typename D, typename T>
+__global__ void k_convert(void* y, const void* x, size_t n) {
+  GRID_STRIDE(i, n) st<D>(y, i, ld<T>(x, i));
+}
+
 template <typename T>
 __global__ void k_zero(void* x, size_t n) {
   GRID_STRIDE(i, n) st<T>(x, i, mk(0.0, 0.0));
@@ -260,6 +266,18 @@ void finalize(const RedOut& o, int nr, size_t n, hipStream_t st, int stride = 0)
 }
 
 void blas_zero(int prec, void* x, size_t n, hipStream_t st) { DISPATCH(prec, k_zero, ew_grid(n), x, n); }
+void blas_convert(int prec_dst, void* y, int prec_src, const void* x, size_t n, hipStream_t st) {
+  const dim3 g = ew_grid(n);
+  if (prec_dst == WCMG_F64 && prec_src == WCMG_F64)
+    hipLaunchKernelGGL((k_convert<double, double>), g, dim3(kThreads), 0, st, y, x, n);
+  else if (prec_dst == WCMG_F64)
+    hipLaunchKernelGGL((k_convert<double, float>), g, dim3(kThreads), 0, st, y, x, n);
+  else if (prec_src == WCMG_F64)
+    hipLaunchKernelGGL((k_convert<float, double>), g, dim3(kThreads), 0, st, y, x, n);
+  else
+    hipLaunchKernelGGL((k_convert<float, float>), g, dim3(kThreads), 0, st, y, x, n);
+  HIPCHK(hipGetLastError());
+}
 void blas_copy(int prec, void* y, const void* x, size_t n, hipStream_t st) {
   DISPATCH(prec, k_copy, ew_grid(n), y, x, n);
 }

@@ -137,6 +137,7 @@ int wcmg_mg_params_default(wcmg_mg_params* p) {
   p->outer_restart = 16;
   p->outer_max_iter = 1000;
   p->smoother_prec = WCMG_F32;
+  p->setup_prec = WCMG_F32;
   p->setup_relax = 10;
   p->setup_max_steps = 10;
   p->setup_rq_tol = 0.05;
@@ -281,6 +282,8 @@ int wcmg_set_mg_params(void* ctx, int lat, const wcmg_mg_params* p) {
   CHECK(p->coarsest == 0 || p->coarsest == 1, WCMG_EINVAL, "coarsest must be 0 (GCR) or 1 (dense FP64 inverse)");
   CHECK(p->cycle_mode >= 0 && p->cycle_mode <= 2, WCMG_EINVAL, "cycle_mode must be 0, 1 or 2");
   CHECK(p->coarse_launch == 0 || p->coarse_launch == 1, WCMG_EINVAL, "coarse_launch must be 0 or 1");
+  CHECK(p->setup_prec == WCMG_F64 || p->setup_prec == WCMG_F32 || p->setup_prec == WCMG_F16, WCMG_EINVAL,
+        "setup precision must be F64, F32 or F16 (FP16 fields, FP32 arithmetic)");
   // coarse extents and degrees of freedom of every level
   int ext[4], nf = 2 * p->nvec[0];
   for (int k = 0; k < 4; ++k) ext[k] = g.L[k] / p->block[0][k];

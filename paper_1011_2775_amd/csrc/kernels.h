@@ -89,6 +89,8 @@ struct RedOut {
   RedOut at(int off) const { return RedOut{res + off, partial, counter, hres ? hres + off : nullptr}; }
 };
 void blas_zero(int prec, void* x, size_t n, hipStream_t st);
+// y (storage prec_dst) = x (storage prec_src), n complex elements
+void blas_convert(int prec_dst, void* y, int prec_src, const void* x, size_t n, hipStream_t st);
 void blas_copy(int prec, void* y, const void* x, size_t n, hipStream_t st);
 // y = a*x + b*y (complex a, b)
 void blas_axpby(int prec, double ar, double ai, const void* x, double br, double bi, void* y, size_t n,

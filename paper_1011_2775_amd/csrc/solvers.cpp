@@ -849,42 +849,50 @@ static void mg_setup_null_vectors_level1(Ctx& c, LatticeState& L) {
   CoarseLevel& C1 = *L.levels[0];
   const int nvec = p.nvec[1];
   const size_t n = (size_t)C1.cg.V * C1.cg.n;
-  CoarseOp cop{&C1, WCMG_F64, &c.cw[0], st};
+  // coarse levels have no half-precision operator: F16 runs as F32 here
+  const int sp = p.setup_prec == WCMG_F64 ? WCMG_F64 : WCMG_F32;
+  const size_t cs = sp == WCMG_F64 ? 16 : 8;
+  CoarseOp cop{&C1, sp, &c.cw[sp == WCMG_F64 ? 0 : 1], st};
   OpFn Dp = [&](void* o, const void* i) { cop.Dp(o, i); };
   if (L.ctr.empty()) L.ctr.emplace_back(new CoarseTransfer());
   CoarseTransfer& T = *L.ctr[0];
   T.nf = C1.cg.n;
   T.nsites = C1.cg.V;
   T.raw.alloc((size_t)nvec * n * 16);
-  void* v = c.scratch_buf(9, n * 16);
-  void* x = c.scratch_buf(10, n * 16);
-  void* w = c.scratch_buf(11, n * 16);
-  GcrSpace S{WCMG_F64, n, n * 16, {}, {}, DBuf()};
+  void* v = c.scratch_buf(9, n * cs);
+  void* x = c.scratch_buf(10, n * cs);
+  void* w = c.scratch_buf(11, n * cs);
+  void* v64 = c.scratch_buf(16, n * 16);
+  void* prev = c.scratch_buf(17, (size_t)nvec * n * cs);
+  GcrSpace S{sp, n, n * cs, {}, {}, DBuf()};
   std::vector<const void*> found;
   std::vector<double> cf(2 * nvec);
   for (int k = 0; k < nvec; ++k) {
-    random_coarse_vector(v, p.seed, k, 1, C1.perm.as<int>(), C1.cg.V, C1.cg.n, st);
+    random_coarse_vector(v64, p.seed, k, 1, C1.perm.as<int>(), C1.cg.V, C1.cg.n, st);
+    reals_convert(sp, v, reinterpret_cast<const double*>(v64), 2 * n, st);
     double rho_old = -1.0;
     for (int step = 0; step < p.setup_max_steps; ++step) {
       gcr(c, S, Dp, nullptr, x, v, true, 0.0, 1.0, p.setup_relax, p.setup_relax, true);
-      blas_copy(WCMG_F64, v, x, n, st);
+      blas_copy(sp, v, x, n, st);
       for (int pass = 0; pass < 2 && k > 0; ++pass) {
-        blas_multi_cdot(WCMG_F64, found.data(), k, v, n, c.red.out(), st);
+        blas_multi_cdot(sp, found.data(), k, v, n, c.red.out(), st);
         const double* d = c.red.fetch(2 * k);
         for (int j = 0; j < 2 * k; ++j) cf[j] = -d[j];
-        blas_multi_axpy(WCMG_F64, cf.data(), found.data(), k, v, n, st);
+        blas_multi_axpy(sp, cf.data(), found.data(), k, v, n, st);
       }
-      double nv = std::sqrt(norm2(c, WCMG_F64, v, n));
+      double nv = std::sqrt(norm2(c, sp, v, n));
       if (!(nv > 0.0) || !finite(nv)) fail(WCMG_ENAN, "setup vector vanished");
-      blas_axpby(WCMG_F64, 1.0 / nv, 0.0, v, 0.0, 0.0, v, n, st);
+      blas_axpby(sp, 1.0 / nv, 0.0, v, 0.0, 0.0, v, n, st);
       Dp(w, v);
-      double rho = norm2(c, WCMG_F64, w, n);
+      double rho = norm2(c, sp, w, n);
       if (rho_old > 0.0 && std::fabs(rho - rho_old) / rho < p.setup_rq_tol) break;
       rho_old = rho;
     }
+    void* keep = (char*)prev + (size_t)k * n * cs;
+    blas_copy(sp, keep, v, n, st);
+    found.push_back(keep);
     void* dst = (char*)T.raw.p + (size_t)k * n * 16;
-    blas_copy(WCMG_F64, dst, v, n, st);
-    found.push_back(dst);
+    blas_convert(WCMG_F64, dst, sp, v, n, st);
   }
   HIPCHK(hipStreamSynchronize(st));
   T.nvec = nvec;
@@ -904,42 +912,53 @@ void mg_setup_null_vectors(Ctx& c, LatticeState& L, int level) {
   const Geom& g = L.F.g;
   hipStream_t st = c.st;
   const int nvec = p.nvec[0];
-  const size_t hb = spinor_bytes(WCMG_F64, g.Vh);
+  // arithmetic of the inverse iteration: F64, F32, or F32 vectors with F16 fields
+  const int sp = p.setup_prec == WCMG_F64 ? WCMG_F64 : WCMG_F32;
+  const int fp = p.setup_prec == WCMG_F16 ? WCMG_F16 : -1;
+  const size_t hb = spinor_bytes(sp, g.Vh), hb64 = spinor_bytes(WCMG_F64, g.Vh);
   const size_t n = (size_t)24 * g.Vh;
-  FineOp op{&c, &L.F, WCMG_F64, &c.fw[0], st};
+  FineOp op{&c, &L.F, sp, &c.fw[sp], st, fp};
   OpFn Dp = [&](void* o, const void* i) {
     op.Dp(o, (char*)o + hb, i, (const char*)i + hb);
   };
-  L.T0.raw.alloc((size_t)nvec * 2 * hb);
+  L.T0.raw.alloc((size_t)nvec * 2 * hb64);
   void* v = c.scratch_buf(9, 2 * hb);
   void* x = c.scratch_buf(10, 2 * hb);
   void* w = c.scratch_buf(11, 2 * hb);
-  GcrSpace S{WCMG_F64, n, 2 * hb, {}, {}, DBuf()};
+  void* v64 = c.scratch_buf(16, 2 * hb64);
+  // the vectors found so far, in the setup's precision
+  void* prev = c.scratch_buf(17, (size_t)nvec * 2 * hb);
+  GcrSpace S{sp, n, 2 * hb, {}, {}, DBuf()};
   std::vector<const void*> found;
   std::vector<double> cf(2 * nvec);
   for (int k = 0; k < nvec; ++k) {
-    random_fine_vector(v, p.seed, k, 0, g, st);
+    random_fine_vector(v64, p.seed, k, 0, g, st);
+    spinor_convert(sp, v, WCMG_F64, v64, g.Vh, st);
+    spinor_convert(sp, (char*)v + hb, WCMG_F64, (char*)v64 + hb64, g.Vh, st);
     double rho_old = -1.0;
     for (int step = 0; step < p.setup_max_steps; ++step) {
       gcr(c, S, Dp, nullptr, x, v, true, 0.0, 1.0, p.setup_relax, p.setup_relax, true);
-      blas_copy(WCMG_F64, v, x, n, st);
+      blas_copy(sp, v, x, n, st);
       for (int pass = 0; pass < 2 && k > 0; ++pass) {
-        blas_multi_cdot(WCMG_F64, found.data(), k, v, n, c.red.out(), st);
+        blas_multi_cdot(sp, found.data(), k, v, n, c.red.out(), st);
         const double* d = c.red.fetch(2 * k);
         for (int j = 0; j < 2 * k; ++j) cf[j] = -d[j];
-        blas_multi_axpy(WCMG_F64, cf.data(), found.data(), k, v, n, st);
+        blas_multi_axpy(sp, cf.data(), found.data(), k, v, n, st);
       }
-      double nv = std::sqrt(norm2(c, WCMG_F64, v, n));
+      double nv = std::sqrt(norm2(c, sp, v, n));
       if (!(nv > 0.0) || !finite(nv)) fail(WCMG_ENAN, "setup vector vanished");
-      blas_axpby(WCMG_F64, 0.0, 0.0, v, 1.0 / nv, 0.0, v, n, st);
+      blas_axpby(sp, 0.0, 0.0, v, 1.0 / nv, 0.0, v, n, st);
       Dp(w, v);
-      double rho = norm2(c, WCMG_F64, w, n);
+      double rho = norm2(c, sp, w, n);
       if (rho_old > 0.0 && std::fabs(rho - rho_old) / rho < p.setup_rq_tol) break;
       rho_old = rho;
     }
-    void* dst = (char*)L.T0.raw.p + (size_t)k * 2 * hb;
-    blas_copy(WCMG_F64, dst, v, n, st);
-    found.push_back(dst);
+    void* keep = (char*)prev + (size_t)k * 2 * hb;
+    blas_copy(sp, keep, v, n, st);
+    found.push_back(keep);
+    void* dst = (char*)L.T0.raw.p + (size_t)k * 2 * hb64;
+    spinor_convert(WCMG_F64, dst, sp, v, g.Vh, st);
+    spinor_convert(WCMG_F64, (char*)dst + hb64, sp, (char*)v + hb, g.Vh, st);
   }
   HIPCHK(hipStreamSynchronize(st));
   L.T0.nvec = nvec;

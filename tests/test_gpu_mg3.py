@@ -127,7 +127,8 @@ def test_three_level_gpu_setup_invariants(hier):
     ctx.build_coarse(1)
     v = ctx.get_null_vectors(level=1).cpu().numpy().reshape(NVEC[1], -1)
     G = v.conj() @ v.T
-    assert np.abs(G - np.eye(NVEC[1])).max() < 1e-10
+    # the default setup runs in FP32: orthonormal to FP32 accuracy
+    assert np.abs(G - np.eye(NVEC[1])).max() < 5e-6
     b = inputs.z2_source(DIMS, 2005)
     x, st = ctx.solve(canon(b, (1,) + tuple(reversed(DIMS)) + (4, 3)), w.MG_GCR, 1e-10)
     xv = x.cpu().numpy().reshape(op.shape)
