@@ -105,7 +105,11 @@ typedef struct {
   uint64_t seed;                    /* Philox4x32-10 key for the random start vectors */
   int coarsest;                     /* 0: unpreconditioned GCR (paper); 1: direct solve with the
                                        dense FP64 inverse of the coarsest full operator (Gauss-Jordan
-                                       with partial pivoting; dimension <= 16384) */
+                                       with partial pivoting; dimension <= 16384); 2: deflated FP64
+                                       GCR: nvec[nlevels] (1..48) low modes of the coarsest
+                                       (red-black where possible) operator, found by inverse
+                                       iteration when the coarsest level is built, stay at the head
+                                       of the GCR basis (nvec[nlevels] + restart <= 64) */
   int cycle_mode;                   /* 0: inner GCRs stop at their tolerance (paper); 1: every inner
                                        GCR runs exactly max_iter[l] steps with no host round trip;
                                        2: as 1, with the whole preconditioner captured once into a

@@ -29,8 +29,12 @@ def _ptr(t):
 
 
 def default_params(**kw):
+    """Library defaults with keyword overrides; list-valued fields (block, nvec,
+    tol, max_iter, restart) per level.  nvec_defl: the number of deflation
+    vectors of the coarsest level (coarsest = 2), stored in nvec[nlevels]."""
     p = _lib.MGParams()
     check(_lib.LIB.wcmg_mg_params_default(ctypes.byref(p)))
+    defl = kw.pop("nvec_defl", None)
     for k, v in kw.items():
         if k == "block":
             for l, b in enumerate(v):
@@ -42,6 +46,8 @@ def default_params(**kw):
                 arr[l] = x
         else:
             setattr(p, k, v)
+    if defl is not None:
+        p.nvec[p.nlevels] = int(defl)
     return p
 
 

@@ -40,6 +40,16 @@ __global__ void k_convert(void* y, const void* x, size_t n) {
   GRID_STRIDE(i, n) st<D>(y, i, ld<T>(x, i));
 }
 
+__global__ void k_defl_coefs(const double* dots, double* qa, int K) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < K) {
+    qa[4 * j] = 1.0;
+    qa[4 * j + 1] = dots[2 * j];
+    qa[4 * j + 2] = dots[2 * j + 1];
+    qa[4 * j + 3] = 0.0;
+  }
+}
+
 template <typename T>
 __global__ void k_zero(void* x, size_t n) {
   GRID_STRIDE(i, n) st<T>(x, i, mk(0.0, 0.0));
@@ -266,6 +276,10 @@ void finalize(const RedOut& o, int nr, size_t n, hipStream_t st, int stride = 0)
 }
 
 void blas_zero(int prec, void* x, size_t n, hipStream_t st) { DISPATCH(prec, k_zero, ew_grid(n), x, n); }
+void blas_defl_coefs(const double* dots, double* qa, int K, hipStream_t st) {
+  hipLaunchKernelGGL(k_defl_coefs, dim3((K + 63) / 64), dim3(64), 0, st, dots, qa, K);
+  HIPCHK(hipGetLastError());
+}
 void blas_convert(int prec_dst, void* y, int prec_src, const void* x, size_t n, hipStream_t st) {
   const dim3 g = ew_grid(n);
   if (prec_dst == WCMG_F64 && prec_src == WCMG_F64)

@@ -279,7 +279,8 @@ int wcmg_set_mg_params(void* ctx, int lat, const wcmg_mg_params* p) {
   CHECK(p->smoother_prec == WCMG_F64 || p->smoother_prec == WCMG_F32 || p->smoother_prec == WCMG_F16, WCMG_EINVAL,
         "smoother precision must be F64, F32 or F16 (FP16 fields, FP32 arithmetic)");
   CHECK(p->setup_relax >= 1 && p->setup_max_steps >= 1, WCMG_EINVAL, "setup iteration counts must be >= 1");
-  CHECK(p->coarsest == 0 || p->coarsest == 1, WCMG_EINVAL, "coarsest must be 0 (GCR) or 1 (dense FP64 inverse)");
+  CHECK(p->coarsest >= 0 && p->coarsest <= 2, WCMG_EINVAL,
+        "coarsest must be 0 (GCR), 1 (dense FP64 inverse) or 2 (deflated FP64 GCR)");
   CHECK(p->cycle_mode >= 0 && p->cycle_mode <= 2, WCMG_EINVAL, "cycle_mode must be 0, 1 or 2");
   CHECK(p->coarse_launch == 0 || p->coarse_launch == 1, WCMG_EINVAL, "coarse_launch must be 0 or 1");
   CHECK(p->setup_prec == WCMG_F64 || p->setup_prec == WCMG_F32 || p->setup_prec == WCMG_F16, WCMG_EINVAL,
@@ -307,12 +308,20 @@ int wcmg_set_mg_params(void* ctx, int lat, const wcmg_mg_params* p) {
   }
   if (p->coarsest == 1)
     CHECK(vc * nf <= kMaxDense, WCMG_EDIM, "coarsest level too large for the dense solve");
+  if (p->coarsest == 2) {
+    const int K = p->nvec[p->nlevels];
+    CHECK(K >= 1 && K <= 48, WCMG_EINVAL, "deflation vectors (nvec[nlevels]) must be in 1..48");
+    CHECK(K + p->restart[p->nlevels - 1] <= 64, WCMG_EINVAL,
+          "deflation vectors plus the coarsest restart length must not exceed 64");
+    CHECK((long)K * 4 <= vc * nf, WCMG_EDIM, "too many deflation vectors for the coarsest dimension");
+  }
   return guarded([&] {
     bool same_shape = L.have_params && L.params.nlevels == p->nlevels;
     for (int l = 0; same_shape && l < p->nlevels; ++l)
       same_shape = L.params.nvec[l] == p->nvec[l] &&
                    std::memcmp(L.params.block[l], p->block[l], sizeof(p->block[l])) == 0;
-    const bool same_coarsest = L.have_params && L.params.coarsest == p->coarsest;
+    const bool same_coarsest = L.have_params && L.params.coarsest == p->coarsest &&
+                               (p->coarsest != 2 || L.params.nvec[p->nlevels] == p->nvec[p->nlevels]);
     L.params = *p;
     L.have_params = true;
     if (!same_shape) {
@@ -320,6 +329,7 @@ int wcmg_set_mg_params(void* ctx, int lat, const wcmg_mg_params* p) {
     } else if (!same_coarsest) {
       L.dense.release();
       L.dense_n = 0;
+      L.defl_k = 0;
       for (auto& lv : L.levels) lv->built = false;
     }
     L.mg.reset();

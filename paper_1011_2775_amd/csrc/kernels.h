@@ -127,6 +127,9 @@ void blas_gcr_orth_dev(int prec, const void* const* q, const void* const* w, int
 void blas_gcr_update_r_dev(int prec, const void* q, void* r, size_t n, const double* qa_k, const RedOut& o,
                            hipStream_t st);
 // x += sum_j alpha_j z_j
+// qa[4j..4j+3] = {1, dots[2j], dots[2j+1], 0} for j < K (coefficients x += sum_j dots_j z_j
+// for blas_gcr_update_x_dev)
+void blas_defl_coefs(const double* dots, double* qa, int K, hipStream_t st);
 void blas_gcr_update_x_dev(int prec, const void* const* z, int k, void* x, size_t n, const double* qa,
                            hipStream_t st);
 // MR with alpha = coef[0..1] / coef[2] (the output of blas_cdot_norm(Ar, r))

@@ -183,12 +183,20 @@ struct LatticeState {
   std::vector<std::unique_ptr<CoarseTransfer>> ctr;  // ctr[0]: coarse level 1 -> level 2
   DBuf dense;       // coarsest level: augmented [N][2N] FP64, right half = inverse (coarsest == 1)
   int dense_n = 0;  // N (0: not built)
+  // coarsest == 2: K deflation pairs (Q_j = A Z_j, Q orthonormal) of the coarsest
+  // operator A (reduced red-black form where the extents allow), FP64 full-size
+  // buffers; qa: the pairs' GCR coefficient slots; tmp: scratch coefficients
+  DBuf defl_q, defl_z, defl_qa, defl_tmp;
+  int defl_k = 0;  // K (0: not built)
   void clear_hierarchy() {
     T0 = FineTransfer();
     levels.clear();
     ctr.clear();
     dense.release();
     dense_n = 0;
+    defl_q.release();
+    defl_z.release();
+    defl_k = 0;
     mg.reset();
   }
 };
@@ -245,8 +253,19 @@ struct KrylovResult {
   double rel_res = 0.0;
 };
 
+// A fixed set of K direction pairs (Q_j = A Z_j, the Q_j orthonormal) kept at
+// the head of the GCR basis through every restart: GCR then never explores
+// those directions again (deflation of the modes they span).  qa holds the
+// 4K coefficient slots of the pairs ({1, 0, 0, 0} each) to copy into the
+// solver's slots.
+struct GcrDeflation {
+  std::vector<const void*> Q, Z;
+  const double* qa = nullptr;
+  int K() const { return (int)Q.size(); }
+};
 KrylovResult gcr(Ctx& c, GcrSpace& S, const OpFn& A, const OpFn* K, void* x, const void* b, bool x_zero,
-                 double tol, double target_norm, int restart, int maxiter, bool fixed_iters = false);
+                 double tol, double target_norm, int restart, int maxiter, bool fixed_iters = false,
+                 const GcrDeflation* defl = nullptr);
 // The unpreconditioned red-black GCR of a coarse level in one cooperative
 // launch: buffers of its own, iterations and failures counted on the device
 // and read back by persistent_collect (one host synchronisation).

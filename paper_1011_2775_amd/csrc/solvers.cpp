@@ -7,6 +7,7 @@
 #include <cstdlib>
 
 #include "random.h"
+#include "herm_eig.h"
 #include "runtime.h"
 
 namespace wcmg {
@@ -39,7 +40,9 @@ static int log_level() {
 // q_j = A z_j, residual update r -= alpha q, and the solution update
 // x += sum alpha_j z_j deferred to the end of each restart cycle.
 KrylovResult gcr(Ctx& c, GcrSpace& S, const OpFn& A, const OpFn* K, void* x, const void* b, bool x_zero, double tol,
-                 double target_norm, int restart, int maxiter, bool fixed) {
+                 double target_norm, int restart, int maxiter, bool fixed, const GcrDeflation* defl) {
+  const int nf = defl ? defl->K() : 0;  // fixed pairs at the head of the basis
+  if (nf + restart > kMaxRestart) fail(WCMG_EINVAL, "deflation vectors plus restart length exceed 64");
   S.ensure(restart);
   const int prec = S.prec;
   const size_t n = S.n;
@@ -65,33 +68,40 @@ KrylovResult gcr(Ctx& c, GcrSpace& S, const OpFn& A, const OpFn* K, void* x, con
     res.rel_res = target_norm > 0 ? std::sqrt(rn2) / target_norm : 0.0;
     return res;
   }
-  // device scalars: beta (multi-dot results) and per-step {||q||^2, <q,r>, ||r||^2}
+  // device scalars: beta (multi-dot results) and per-step {||q||^2, <q,r>, ||r||^2};
+  // slots 0..nf-1 belong to the fixed pairs (alpha 0: r is orthogonal to them)
   double* beta = S.scal.as<double>();
   double* qa = beta + 2 * (kMaxRestart + 16);
-  std::vector<const void*> Qp(restart), Zp(restart);
+  std::vector<const void*> Qp(nf + restart), Zp(nf + restart);
+  for (int j = 0; j < nf; ++j) {
+    Qp[j] = defl->Q[j];
+    Zp[j] = defl->Z[j];
+  }
+  if (nf) blas_copy(WCMG_F64, qa, defl->qa, (size_t)2 * nf, st);
   bool converged = false;
   while (res.iters < maxiter) {
     int k = 0;
     for (; k < restart;) {
       void* z = S.Z[k].p;
       void* q = S.Q[k].p;
-      Qp[k] = q;
-      Zp[k] = z;
+      const int kk = nf + k;  // basis slot of this step
+      Qp[kk] = q;
+      Zp[kk] = z;
       if (K)
         (*K)(z, r);
       else
         blas_copy(prec, z, r, n, st);
       A(q, z);
-      if (k > 0) blas_multi_cdot(prec, Qp.data(), k, q, n, R.out(beta), st);
-      blas_gcr_orth_dev(prec, Qp.data(), Zp.data(), k, q, z, r, n, beta, qa, R.out(qa + 4 * k), st);
-      blas_gcr_update_r_dev(prec, q, r, n, qa + 4 * k, R.out(qa + 4 * k + 3), st);
+      if (kk > 0) blas_multi_cdot(prec, Qp.data(), kk, q, n, R.out(beta), st);
+      blas_gcr_orth_dev(prec, Qp.data(), Zp.data(), kk, q, z, r, n, beta, qa, R.out(qa + 4 * kk), st);
+      blas_gcr_update_r_dev(prec, q, r, n, qa + 4 * kk, R.out(qa + 4 * kk + 3), st);
       if (fixed) {
         ++k;
         ++res.iters;
         if (res.iters >= maxiter) break;
         continue;
       }
-      const double* o = R.fetch_from(qa + 4 * k, 4);  // one host round trip: {||q||^2, <q,r>, ||r||^2}
+      const double* o = R.fetch_from(qa + 4 * kk, 4);  // one host round trip: {||q||^2, <q,r>, ||r||^2}
       const double qq = o[0];
       rn2 = o[3];
       if (!(qq > 0.0) || !finite(qq)) {
@@ -106,7 +116,7 @@ KrylovResult gcr(Ctx& c, GcrSpace& S, const OpFn& A, const OpFn* K, void* x, con
       }
       if ((!fixed && std::sqrt(rn2) <= target) || res.iters >= maxiter) break;
     }
-    if (k > 0) blas_gcr_update_x_dev(prec, Zp.data(), k, x, n, qa, st);
+    if (k > 0) blas_gcr_update_x_dev(prec, Zp.data() + nf, k, x, n, qa + 4 * nf, st);
     if (res.status != WCMG_OK) break;
     if (fixed) break;
     // true residual at the end of every cycle
@@ -481,6 +491,8 @@ struct MGSolver {
     int batch = 1;              // right-hand sides the buffers hold
     long calls = 0, iters = 0;
     PersistWork pw;             // the coarsest GCR as one cooperative launch (coarse_launch 0)
+    DBuf d_in, d_out, d_br, d_y;  // FP64 vectors of the deflated coarsest solve (coarsest 2)
+    GcrSpace space64{};
   };
   int batch = 1;  // right-hand sides the fine buffers hold
   std::vector<Level> lv;  // lv[li]: coarse level li + 1
@@ -547,6 +559,10 @@ struct MGSolver {
       V.iters += 1;
       return;
     }
+    if (last && p.coarsest == 2) {
+      deflated_solve(li, out, in);
+      return;
+    }
     if (last && C.cg.split && persistent_ok(li)) {
       persistent_solve(li, out, in);
       return;
@@ -586,6 +602,56 @@ struct MGSolver {
     persistent_launch(c, V.pw, *L.levels[li], cp, out, in, V.rfull.p, V.cy.p, V.res.p, V.cbr.p, p.tol[li],
                       p.restart[li], p.max_iter[li], fixed());
     if (e) c.timer.end(id, e);
+  }
+
+  // coarsest == 2: FP64 GCR on the coarsest operator with the deflation pairs
+  // at the head of its basis, started from the deflated guess Z (Q^dag b)
+  void deflated_solve(int li, void* out, void* in) {
+    CoarseLevel& C = *L.levels[li];
+    Level& V = lv[li];
+    const wcmg_mg_params& p = L.params;
+    hipStream_t st = c.st;
+    CoarseOp op{&C, WCMG_F64, &cwork, st};
+    const bool split = C.cg.split;
+    const size_t nall = op.nall(), n = split ? op.neven() : nall, vb = nall * 16;
+    for (DBuf* b : {&V.d_in, &V.d_out, &V.d_br, &V.d_y}) b->alloc(vb);
+    V.space64.prec = WCMG_F64;
+    V.space64.n = n;
+    V.space64.bytes = vb;
+    blas_convert(WCMG_F64, V.d_in.p, cp, in, nall, st);
+    void* rhs = V.d_in.p;
+    if (split) {
+      op.reduced_source(V.d_br.p, V.d_in.p);
+      rhs = V.d_br.p;
+    }
+    GcrDeflation D;
+    for (int j = 0; j < L.defl_k; ++j) {
+      D.Q.push_back((char*)L.defl_q.p + (size_t)j * vb);
+      D.Z.push_back((char*)L.defl_z.p + (size_t)j * vb);
+    }
+    D.qa = L.defl_qa.as<double>();
+    double* dots = L.defl_tmp.as<double>();
+    double* coef = dots + 2 * (kMaxRestart + 16);
+    blas_multi_cdot(WCMG_F64, D.Q.data(), L.defl_k, rhs, n, c.red.out(dots), st);
+    blas_defl_coefs(dots, coef, L.defl_k, st);
+    blas_zero(WCMG_F64, V.d_y.p, n, st);
+    blas_gcr_update_x_dev(WCMG_F64, D.Z.data(), L.defl_k, V.d_y.p, n, coef, st);
+    const bool fx = fixed();
+    const double bn = fx ? 1.0 : std::sqrt(norm2(c, WCMG_F64, rhs, n));
+    OpFn A = [&](void* o, const void* i) {
+      if (split)
+        op.Dr(o, i);
+      else
+        op.Dfull(o, i);
+    };
+    KrylovResult kr = gcr(c, V.space64, A, nullptr, V.d_y.p, rhs, false, p.tol[li], bn, p.restart[li],
+                          p.max_iter[li], fx, &D);
+    if (split)
+      op.reconstruct(V.d_out.p, V.d_y.p, V.d_in.p);
+    else
+      blas_copy(WCMG_F64, V.d_out.p, V.d_y.p, nall, st);
+    blas_convert(cp, out, WCMG_F64, V.d_out.p, nall, st);
+    V.iters += kr.iters;
   }
 
   // iterations the persistent coarse solves counted on the device (raises
@@ -835,6 +901,7 @@ static void require_hierarchy(LatticeState& L) {
   for (int l = 0; l < nl; ++l)
     if (!L.levels[l]->built) fail(WCMG_ESTATE, "coarse operator not built");
   if (L.params.coarsest == 1 && L.dense_n == 0) fail(WCMG_ESTATE, "coarsest dense inverse not built");
+  if (L.params.coarsest == 2 && L.defl_k == 0) fail(WCMG_ESTATE, "coarsest deflation space not built");
 }
 
 // ---------------------------------------------------------------------------
@@ -1057,6 +1124,117 @@ static void build_dense(Ctx& c, LatticeState& L, int li) {
   L.dense_n = N;
 }
 
+// Deflation pairs of the coarsest operator A (coarsest == 2): block inverse
+// iteration on m = min(2K, 96) random vectors (three steps, each vector
+// solved to 1e-4 by GCR and the block orthonormalised), then a Rayleigh-Ritz
+// step for the smallest singular values inside that subspace: with H =
+// (AW)^dag (AW) = Y diag(s^2) Y^dag, the K pairs Z_j = W y_j / s_j and
+// Q_j = (AW) y_j / s_j satisfy Q_j = A Z_j with the Q orthonormal (once more
+// Gram-Schmidt, twice, against rounding).  Inverse iteration alone (the
+// Setup section's relaxation) gives subspaces too far from the low modes:
+// deflating with them made the coarsest GCR slower, not faster.
+static void build_deflation(Ctx& c, LatticeState& L, int li) {
+  const wcmg_mg_params& p = L.params;
+  CoarseLevel& C = *L.levels[li];
+  const int K = p.nvec[p.nlevels];
+  hipStream_t st = c.st;
+  CoarseOp op{&C, WCMG_F64, &c.cw[0], st};
+  const bool split = C.cg.split;
+  const size_t nall = op.nall();
+  const size_t n = split ? op.neven() : nall;
+  const size_t vb = nall * 16;  // full-size buffers: the red-black operator works on them
+  const int m = std::min(2 * K, 96);
+  if ((size_t)m > n) fail(WCMG_EDIM, "too many deflation vectors for the coarsest dimension");
+  OpFn A = [&](void* o, const void* i) {
+    if (split)
+      op.Dr(o, i);
+    else
+      op.Dfull(o, i);
+  };
+  L.defl_k = 0;
+  DBuf wbuf, awbuf;
+  wbuf.alloc((size_t)m * vb);
+  awbuf.alloc((size_t)m * vb);
+  std::vector<const void*> W(m), AW(m);
+  for (int i = 0; i < m; ++i) {
+    W[i] = (char*)wbuf.p + (size_t)i * vb;
+    AW[i] = (char*)awbuf.p + (size_t)i * vb;
+  }
+  auto wv = [&](int i) { return const_cast<void*>(W[i]); };
+  auto awv = [&](int i) { return const_cast<void*>(AW[i]); };
+  std::vector<double> cf(2 * m);
+  // orthonormalise a list of vectors in place (classical Gram-Schmidt, twice), applying the
+  // same combinations to a second list when given
+  auto orthonormalise = [&](std::vector<const void*>& X, std::vector<const void*>* Y, int cnt) {
+    for (int k = 0; k < cnt; ++k) {
+      void* xk = const_cast<void*>(X[k]);
+      for (int pass = 0; pass < 2 && k > 0; ++pass) {
+        blas_multi_cdot(WCMG_F64, X.data(), k, xk, n, c.red.out(), st);
+        const double* d = c.red.fetch(2 * k);
+        for (int j = 0; j < 2 * k; ++j) cf[j] = -d[j];
+        blas_multi_axpy(WCMG_F64, cf.data(), X.data(), k, xk, n, st);
+        if (Y) blas_multi_axpy(WCMG_F64, cf.data(), Y->data(), k, const_cast<void*>((*Y)[k]), n, st);
+      }
+      const double s = std::sqrt(norm2(c, WCMG_F64, xk, n));
+      if (!(s > 0.0) || !finite(s)) fail(WCMG_ERANK, "deflation vectors are linearly dependent");
+      blas_axpby(WCMG_F64, 1.0 / s, 0.0, xk, 0.0, 0.0, xk, n, st);
+      if (Y) {
+        void* yk = const_cast<void*>((*Y)[k]);
+        blas_axpby(WCMG_F64, 1.0 / s, 0.0, yk, 0.0, 0.0, yk, n, st);
+      }
+    }
+  };
+  for (int i = 0; i < m; ++i)
+    random_coarse_vector(wv(i), p.seed, i, 8 + li, C.perm.as<int>(), C.cg.V, C.cg.n, st);
+  orthonormalise(W, nullptr, m);
+  void* x = c.scratch_buf(19, vb);
+  GcrSpace S{WCMG_F64, n, vb, {}, {}, DBuf()};
+  for (int step = 0; step < 3; ++step) {
+    for (int i = 0; i < m; ++i) {
+      gcr(c, S, A, nullptr, x, wv(i), true, 1e-4, 1.0, 30, 1000, false);
+      blas_copy(WCMG_F64, wv(i), x, n, st);
+    }
+    orthonormalise(W, nullptr, m);
+  }
+  // Rayleigh-Ritz for the smallest singular values of A on span(W)
+  for (int i = 0; i < m; ++i) A(awv(i), wv(i));
+  std::vector<std::complex<double>> H((size_t)m * m);
+  for (int j = 0; j < m; ++j) {
+    blas_multi_cdot(WCMG_F64, AW.data(), m, awv(j), n, c.red.out(), st);
+    const double* d = c.red.fetch(2 * m);
+    for (int i = 0; i < m; ++i) H[(size_t)i * m + j] = std::complex<double>(d[2 * i], d[2 * i + 1]);
+  }
+  std::vector<double> ev;
+  std::vector<std::complex<double>> Yv;
+  hermitian_eig(H, m, ev, Yv);
+  L.defl_q.alloc((size_t)K * vb);
+  L.defl_z.alloc((size_t)K * vb);
+  std::vector<const void*> Zs(K), Qs(K);
+  for (int j = 0; j < K; ++j) {
+    Zs[j] = (char*)L.defl_z.p + (size_t)j * vb;
+    Qs[j] = (char*)L.defl_q.p + (size_t)j * vb;
+    if (!(ev[j] > 0.0)) fail(WCMG_ERANK, "coarsest operator is singular on the deflation subspace");
+    const double inv = 1.0 / std::sqrt(ev[j]);
+    for (int i = 0; i < m; ++i) {
+      const std::complex<double> yv = Yv[(size_t)i * m + j] * inv;
+      cf[2 * i] = yv.real();
+      cf[2 * i + 1] = yv.imag();
+    }
+    blas_zero(WCMG_F64, const_cast<void*>(Zs[j]), n, st);
+    blas_zero(WCMG_F64, const_cast<void*>(Qs[j]), n, st);
+    blas_multi_axpy(WCMG_F64, cf.data(), W.data(), m, const_cast<void*>(Zs[j]), n, st);
+    blas_multi_axpy(WCMG_F64, cf.data(), AW.data(), m, const_cast<void*>(Qs[j]), n, st);
+  }
+  orthonormalise(Qs, &Zs, K);
+  std::vector<double> qa(4 * (size_t)K, 0.0);
+  for (int j = 0; j < K; ++j) qa[4 * j] = 1.0;
+  L.defl_qa.alloc(qa.size() * sizeof(double));
+  L.defl_tmp.alloc((2 * (kMaxRestart + 16) + 4 * kMaxRestart) * sizeof(double));
+  HIPCHK(hipMemcpyAsync(L.defl_qa.p, qa.data(), qa.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  L.defl_k = K;
+}
+
 // level-2 operator R2 Dhat_p P2 from the level-1 stencil (direction resolved)
 static void mg_build_coarse_level1(Ctx& c, LatticeState& L) {
   const wcmg_mg_params& p = L.params;
@@ -1135,6 +1313,7 @@ static void mg_build_coarse_level1(Ctx& c, LatticeState& L) {
   finalize_coarse(c, C2, flag);
   C2.built = true;
   if (p.coarsest == 1) build_dense(c, L, 1);
+  if (p.coarsest == 2) build_deflation(c, L, 1);
   L.mg.reset();
 }
 
@@ -1202,6 +1381,7 @@ void mg_build_coarse(Ctx& c, LatticeState& L, int level) {
   finalize_coarse(c, C, flag);
   C.built = true;
   if (p.nlevels == 1 && p.coarsest == 1) build_dense(c, L, 0);
+  if (p.nlevels == 1 && p.coarsest == 2) build_deflation(c, L, 0);
   L.mg.reset();
 }
 

@@ -99,10 +99,14 @@ def test_level2_apply_matches_oracle(hier, which):
     assert rel(got, want) < 1e-12
 
 
-@pytest.mark.parametrize("coarsest", ["gcr", "lu"])
+@pytest.mark.parametrize("coarsest", ["gcr", "lu", "deflated"])
 def test_three_level_solve_matches_oracle(hier, coarsest):
+    """The deflated FP64 coarsest GCR (no oracle counterpart: it solves the same
+    coarsest system to the same tolerance) is compared with the oracle's GCR."""
     op, H, ctx, load = hier
-    load(0 if coarsest == "gcr" else 1)
+    load({"gcr": 0, "lu": 1, "deflated": 2}[coarsest])
+    if coarsest == "deflated":
+        coarsest = "gcr"
     b = inputs.z2_source(DIMS, 2004)
     x, st = ctx.solve(canon(b, (1,) + tuple(reversed(DIMS)) + (4, 3)), w.MG_GCR, 1e-10)
     xv = x.cpu().numpy().reshape(op.shape)
@@ -137,7 +141,7 @@ def test_three_level_gpu_setup_invariants(hier):
     load(0)
 
 
-@pytest.mark.parametrize("coarsest", [0, 1])
+@pytest.mark.parametrize("coarsest", [0, 1, 2])
 def test_three_level_16x16x16x32(coarsest):
     cfg = inputs.config("c5_16x16x16x32")
     dims = cfg["dims"]
