@@ -52,7 +52,7 @@ __device__ __forceinline__ const void* rhs_ptr(const void* base, size_t stride, 
   return reinterpret_cast<const char*>(base) + (size_t)r * stride;
 }
 
-template <typename S, typename G, int MU, int NR>
+template <typename S, typename G, int MU, int NR, bool STREAM>
 __device__ __forceinline__ void hop_mu(const DslashArgs& a, int p, int i, const int c[4], int g0, int nr,
                                        cpx<typename Compute<S>::T> (&acc)[NR][12]) {
   using C = typename Compute<S>::T;
@@ -63,7 +63,7 @@ __device__ __forceinline__ void hop_mu(const DslashArgs& a, int p, int i, const 
     int n[4] = {c[0], c[1], c[2], c[3]};
     n[MU] = (n[MU] + 1 == g.L[MU]) ? 0 : n[MU] + 1;
     const int nb = cb_index(g, n);
-    load_link<G, C>(a.gauge, g.Vh, p, MU, i, U);
+    load_link<G, C, STREAM>(a.gauge, g.Vh, p, MU, i, U);
     const bool edge = MU == 3 && c[3] == g.L[3] - 1;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -86,7 +86,7 @@ __device__ __forceinline__ void hop_mu(const DslashArgs& a, int p, int i, const 
     int n[4] = {c[0], c[1], c[2], c[3]};
     n[MU] = (n[MU] == 0) ? g.L[MU] - 1 : n[MU] - 1;
     const int nb = cb_index(g, n);
-    load_link<G, C>(a.gauge, g.Vh, 1 - p, MU, nb, U);
+    load_link<G, C, STREAM>(a.gauge, g.Vh, 1 - p, MU, nb, U);
     const bool edge = MU == 3 && c[3] == 0;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -180,7 +180,7 @@ __device__ __forceinline__ void clover_block_apply_d(const C* d, int chi, int nr
   }
 }
 
-template <typename G, typename C, int NR>
+template <typename G, typename C, int NR, bool STREAM = false>
 __device__ __forceinline__ void clover_multi(const void* clov, int Vh, int p, int kind, int i, int nr,
                                              const cpx<C> (&in)[NR][12], cpx<C> (&out)[NR][12]) {
   using V = typename CloverChunk<G>::V;
@@ -191,7 +191,7 @@ __device__ __forceinline__ void clover_multi(const void* clov, int Vh, int p, in
     // FP16: the two chirality blocks share a chunk, load all 72 reals at once
     C d[72];
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) unpack_chunk<G, C>(base[(size_t)c * Vh], d + E * c);
+    for (int c = 0; c < NCH; ++c) unpack_chunk<G, C>(ld_maybe<STREAM>(base + (size_t)c * Vh), d + E * c);
     clover_block_apply_d<C, NR>(d, 0, nr, in, out);
     clover_block_apply_d<C, NR>(d + 36, 1, nr, in, out);
   } else {
@@ -199,7 +199,8 @@ __device__ __forceinline__ void clover_multi(const void* clov, int Vh, int p, in
     for (int chi = 0; chi < 2; ++chi) {
       C d[36];
 #pragma unroll
-      for (int c = 0; c < 36 / E; ++c) unpack_chunk<G, C>(base[(size_t)(chi * (36 / E) + c) * Vh], d + E * c);
+      for (int c = 0; c < 36 / E; ++c)
+        unpack_chunk<G, C>(ld_maybe<STREAM>(base + (size_t)(chi * (36 / E) + c) * Vh), d + E * c);
       clover_block_apply_d<C, NR>(d, chi, nr, in, out);
     }
   }
@@ -207,7 +208,7 @@ __device__ __forceinline__ void clover_multi(const void* clov, int Vh, int p, in
 
 // S: spinor storage, G: link and clover storage (G = S, or FP16 fields with
 // FP32 spinors); lb: the lattice's logical block
-template <typename S, typename G, int DIAG, bool POSTINV, int NR>
+template <typename S, typename G, int DIAG, bool POSTINV, int NR, bool STREAM = false>
 __device__ __forceinline__ void dslash_site(const DslashArgs& a, int lb) {
   using C = typename Compute<S>::T;
   const int i = lb * blockDim.x + threadIdx.x;
@@ -223,10 +224,10 @@ __device__ __forceinline__ void dslash_site(const DslashArgs& a, int lb) {
   for (int r = 0; r < NR; ++r)
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[r][k] = mk((C)0, (C)0);
-  hop_mu<S, G, 0, NR>(a, p, i, c, g0, nr, acc);
-  hop_mu<S, G, 1, NR>(a, p, i, c, g0, nr, acc);
-  hop_mu<S, G, 2, NR>(a, p, i, c, g0, nr, acc);
-  hop_mu<S, G, 3, NR>(a, p, i, c, g0, nr, acc);
+  hop_mu<S, G, 0, NR, STREAM>(a, p, i, c, g0, nr, acc);
+  hop_mu<S, G, 1, NR, STREAM>(a, p, i, c, g0, nr, acc);
+  hop_mu<S, G, 2, NR, STREAM>(a, p, i, c, g0, nr, acc);
+  hop_mu<S, G, 3, NR, STREAM>(a, p, i, c, g0, nr, acc);
 
   const C f = (C)(-0.5 * a.coeff);
 #pragma unroll
@@ -236,7 +237,7 @@ __device__ __forceinline__ void dslash_site(const DslashArgs& a, int lb) {
 
   cpx<C> out[NR][12];
   if constexpr (POSTINV) {
-    clover_multi<G, C, NR>(a.clov, a.g.Vh, p, 1, i, nr, acc, out);
+    clover_multi<G, C, NR, STREAM>(a.clov, a.g.Vh, p, 1, i, nr, acc, out);
   } else {
 #pragma unroll
     for (int r = 0; r < NR; ++r)
@@ -247,10 +248,10 @@ __device__ __forceinline__ void dslash_site(const DslashArgs& a, int lb) {
     cpx<C> xv[NR][12];
 #pragma unroll
     for (int r = 0; r < NR; ++r)
-      if (r < nr) SpinorIO<S>::load(rhs_ptr<S>(a.x, a.rstride, g0 + r), a.g.Vh, i, xv[r]);
+      if (r < nr) SpinorIO<S>::template load<STREAM>(rhs_ptr<S>(a.x, a.rstride, g0 + r), a.g.Vh, i, xv[r]);
     if constexpr (DIAG == 2) {
       cpx<C> ax[NR][12];
-      clover_multi<G, C, NR>(a.clov, a.g.Vh, p, 0, i, nr, xv, ax);
+      clover_multi<G, C, NR, STREAM>(a.clov, a.g.Vh, p, 0, i, nr, xv, ax);
 #pragma unroll
       for (int r = 0; r < NR; ++r)
 #pragma unroll
@@ -268,9 +269,9 @@ __device__ __forceinline__ void dslash_site(const DslashArgs& a, int lb) {
       SpinorIO<S>::store(const_cast<void*>(rhs_ptr<S>(a.out, a.rstride, g0 + r)), a.g.Vh, i, out[r]);
 }
 
-template <typename S, typename G, int DIAG, bool POSTINV, int NR>
+template <typename S, typename G, int DIAG, bool POSTINV, int NR, bool STREAM>
 __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a) {
-  dslash_site<S, G, DIAG, POSTINV, NR>(a, xcd_block(a.nblocks));
+  dslash_site<S, G, DIAG, POSTINV, NR, STREAM>(a, xcd_block(a.nblocks));
 }
 
 // Several lattices of different volumes in one launch: a work list of block
@@ -313,7 +314,16 @@ static void launch_dslash_nr(int diag, bool postinv, DslashArgs a, hipStream_t s
   if (threads != 64 && threads != 128 && threads != 256) fail(WCMG_EINVAL, "unsupported Dslash block size");
   a.nblocks = (a.g.Vh + threads - 1) / threads;
   dim3 grid(xcd_grid(a.nblocks), (a.nrhs + NR - 1) / NR);
-#define WCMG_DS(D, P) hipLaunchKernelGGL((dslash_kernel<S, G, D, P, NR>), grid, dim3(threads), 0, st, a)
+  // stream the fields when they (links and both clover records, both parities) exceed
+  // three quarters of the 256 MB Infinity Cache
+  const bool stream = a.stream >= 0 ? a.stream != 0 : (double)a.g.Vh * 432.0 * sizeof(G) > 192.0e6;
+#define WCMG_DS(D, P)                                                                                  \
+  do {                                                                                               \
+    if (stream)                                                                                      \
+      hipLaunchKernelGGL((dslash_kernel<S, G, D, P, NR, true>), grid, dim3(threads), 0, st, a);    \
+    else                                                                                             \
+      hipLaunchKernelGGL((dslash_kernel<S, G, D, P, NR, false>), grid, dim3(threads), 0, st, a);   \
+  } while (0)
   if (diag == 0 && !postinv) WCMG_DS(0, false);
   else if (diag == 0 && postinv) WCMG_DS(0, true);
   else if (diag == 1 && !postinv) WCMG_DS(1, false);

@@ -21,6 +21,7 @@ struct DslashArgs {
   int threads = 0;     // launch shape: threads per block (64, 128, 256; 0 = 256)
   int group = 0;       // right-hand sides per thread (1, 2, 4; 0 = largest that fits)
   int fprec = -1;      // storage of gauge and clover (-1: as the spinors; F16 with F32 spinors)
+  int stream = -1;     // non-temporal field loads: 1 on, 0 off, -1 when the fields exceed the Infinity Cache
 };
 void launch_dslash(int prec, int diag, bool postinv, const DslashArgs& a, hipStream_t st);
 // several lattices (one right-hand side each, same precision and kernel variant) in one launch

@@ -138,44 +138,92 @@ struct Compute<double> {
 // ---------------------------------------------------------------------------
 // spinor chunk I/O (one parity, 12 complex per site)
 // ---------------------------------------------------------------------------
+// Loads of data a launch reads exactly once (links, clover, the diagonal
+// input): non-temporal when the fields exceed the Infinity Cache, so that
+// they do not evict the spinors that neighbouring sites read again; plain
+// when the fields fit there and every launch finds them again.
+typedef unsigned int ws_u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int ws_u32x4 __attribute__((ext_vector_type(4)));
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T* p) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8 || sizeof(T) == 16, "16, 8 or 4 bytes");
+  if constexpr (sizeof(T) == 16) {
+    return __builtin_bit_cast(T, __builtin_nontemporal_load(reinterpret_cast<const ws_u32x4*>(p)));
+  } else if constexpr (sizeof(T) == 8) {
+    return __builtin_bit_cast(T, __builtin_nontemporal_load(reinterpret_cast<const ws_u32x2*>(p)));
+  } else {
+    return __builtin_bit_cast(T, __builtin_nontemporal_load(reinterpret_cast<const unsigned int*>(p)));
+  }
+}
+template <typename T>
+__device__ __forceinline__ void st_stream(T* p, T v) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8 || sizeof(T) == 16, "16, 8 or 4 bytes");
+  if constexpr (sizeof(T) == 16) {
+    __builtin_nontemporal_store(__builtin_bit_cast(ws_u32x4, v), reinterpret_cast<ws_u32x4*>(p));
+  } else if constexpr (sizeof(T) == 8) {
+    __builtin_nontemporal_store(__builtin_bit_cast(ws_u32x2, v), reinterpret_cast<ws_u32x2*>(p));
+  } else {
+    __builtin_nontemporal_store(__builtin_bit_cast(unsigned int, v), reinterpret_cast<unsigned int*>(p));
+  }
+}
+// plain or streamed element access
+template <bool NT, typename T>
+__device__ __forceinline__ T ld_maybe(const T* p) {
+  if constexpr (NT)
+    return ld_stream(p);
+  else
+    return *p;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void st_maybe(T* p, T v) {
+  if constexpr (NT)
+    st_stream(p, v);
+  else
+    *p = v;
+}
+
 template <typename S>
 struct SpinorIO;
 
 template <>
 struct SpinorIO<double> {
   static constexpr int kPrec = WCMG_F64;
+  template <bool NT = false>
   __device__ __forceinline__ static void load(const void* base, int Vh, int i, cpx<double> v[12]) {
     const double2* p = reinterpret_cast<const double2*>(base);
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
-      double2 t = p[(size_t)c * Vh + i];
+      double2 t = ld_maybe<NT>(p + (size_t)c * Vh + i);
       v[c] = mk(t.x, t.y);
     }
   }
+  template <bool NT = false>
   __device__ __forceinline__ static void store(void* base, int Vh, int i, const cpx<double> v[12]) {
     double2* p = reinterpret_cast<double2*>(base);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) p[(size_t)c * Vh + i] = make_double2(v[c].r, v[c].i);
+    for (int c = 0; c < 12; ++c) st_maybe<NT>(p + (size_t)c * Vh + i, make_double2(v[c].r, v[c].i));
   }
 };
 
 template <>
 struct SpinorIO<float> {
   static constexpr int kPrec = WCMG_F32;
+  template <bool NT = false>
   __device__ __forceinline__ static void load(const void* base, int Vh, int i, cpx<float> v[12]) {
     const float4* p = reinterpret_cast<const float4*>(base);
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-      float4 t = p[(size_t)c * Vh + i];
+      float4 t = ld_maybe<NT>(p + (size_t)c * Vh + i);
       v[2 * c] = mk(t.x, t.y);
       v[2 * c + 1] = mk(t.z, t.w);
     }
   }
+  template <bool NT = false>
   __device__ __forceinline__ static void store(void* base, int Vh, int i, const cpx<float> v[12]) {
     float4* p = reinterpret_cast<float4*>(base);
 #pragma unroll
     for (int c = 0; c < 6; ++c)
-      p[(size_t)c * Vh + i] = make_float4(v[2 * c].r, v[2 * c].i, v[2 * c + 1].r, v[2 * c + 1].i);
+      st_maybe<NT>(p + (size_t)c * Vh + i, make_float4(v[2 * c].r, v[2 * c].i, v[2 * c + 1].r, v[2 * c + 1].i));
   }
 };
 
@@ -186,12 +234,13 @@ struct SpinorIO<__half> {
   __device__ __forceinline__ static const float* scales(const void* base, int Vh) {
     return reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + (size_t)Vh * 48);
   }
+  template <bool NT = false>
   __device__ __forceinline__ static void load(const void* base, int Vh, int i, cpx<float> v[12]) {
     const uint4* p = reinterpret_cast<const uint4*>(base);
-    float s = scales(base, Vh)[i];
+    float s = ld_maybe<NT>(scales(base, Vh) + i);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      uint4 t = p[(size_t)c * Vh + i];
+      uint4 t = ld_maybe<NT>(p + (size_t)c * Vh + i);
       unsigned w[4] = {t.x, t.y, t.z, t.w};
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -201,6 +250,7 @@ struct SpinorIO<__half> {
       }
     }
   }
+  template <bool NT = false>
   __device__ __forceinline__ static void store(void* base, int Vh, int i, const cpx<float> v[12]) {
     float m = 0.f;
 #pragma unroll
@@ -216,9 +266,9 @@ struct SpinorIO<__half> {
         __half2 h = __floats2half2_rn(v[4 * c + k].r * inv, v[4 * c + k].i * inv);
         w[k] = *reinterpret_cast<unsigned*>(&h);
       }
-      p[(size_t)c * Vh + i] = make_uint4(w[0], w[1], w[2], w[3]);
+      st_maybe<NT>(p + (size_t)c * Vh + i, make_uint4(w[0], w[1], w[2], w[3]));
     }
-    const_cast<float*>(scales(base, Vh))[i] = s;
+    st_maybe<NT>(const_cast<float*>(scales(base, Vh)) + i, s);
   }
 };
 
@@ -251,12 +301,12 @@ __device__ __forceinline__ cpx<C> to_cpx(__half2 v) {
 }
 
 // link U[a][b] of (parity p, direction mu) at checkerboard site i
-template <typename S, typename C>
+template <typename S, typename C, bool STREAM = false>
 __device__ __forceinline__ void load_link(const void* gauge, int Vh, int p, int mu, int i, cpx<C> U[9]) {
   using V2 = typename Vec2<S>::T;
   const V2* g = reinterpret_cast<const V2*>(gauge) + ((size_t)(p * 4 + mu) * 9) * Vh;
 #pragma unroll
-  for (int k = 0; k < 9; ++k) U[k] = to_cpx<C>(g[(size_t)k * Vh + i]);
+  for (int k = 0; k < 9; ++k) U[k] = to_cpx<C>(ld_maybe<STREAM>(g + (size_t)k * Vh + i));
 }
 
 template <typename S>
