@@ -18,12 +18,17 @@
 // takes the same decisions (convergence, breakdown) from bitwise the same
 // numbers, and results do not depend on timing.
 //
-// A step takes three grid barriers: after the even-site hop (with the
-// Gram-Schmidt dot products), after the orthogonalisation (with ||q||^2 and
-// <q, r>), and after the update, whose odd-site hop for the next step reads
-// r_{k+1} at neighbouring sites as r_k - alpha q_k (two residual buffers
-// alternate, and both sides round that expression the same way, so the hop
-// sees exactly the stored r_{k+1}).
+// A step takes two grid barriers.  The even-site hop q = D_r z_k is followed
+// by the sums <q_j, q>, ||q||^2 and <q, r> (one barrier); since the q_j are
+// orthonormal up to their norms and r is orthogonal to all of them,
+// ||q_k||^2 = ||q||^2 - sum_j |<q_j, q>|^2 / ||q_j||^2 and <q_k, r> = <q, r>
+// give alpha at once.  The update then needs no second reduction: the
+// workgroup orthogonalises its own part of q_k and z_k, updates y and r, and
+// builds the next odd-site hop by linearity, t <- t - alpha T_k with
+// T_k = Ytilde_oe q_k = Ytilde_oe q - sum_j c_j T_j (the hop of q reads the
+// neighbours' q, complete after the first barrier); the second barrier
+// publishes t and ||r||^2.  The true residual at the end of every cycle
+// removes what rounding these recurrences add.
 //
 // The grid barrier is a flag barrier: every workgroup stores the barrier's
 // epoch to a cache line of its own, workgroup 0 waits for all of them and
@@ -227,10 +232,12 @@ struct PArgs {
   void* c;           // [V][n] solution
   void* t;           // [V][n] scratch (odd half)
   void* y;           // [Vh][n]
-  void* r;           // [2][Vh][n] (current and next residual)
+  void* r;           // [Vh][n]
+  void* qraw;        // [Vh][n] D_r z of the current step, before orthogonalisation
   void* br;          // [Vh][n]
   void* Q;           // [restart][Vh][n]
   void* Z;           // [restart][Vh][n]
+  void* T;           // [restart][V][n]: Ytilde_oe q_j on the odd sites
   double* part;      // [2][W][stride]: written before a barrier, read by all after it (two buffers
                      // alternate, so a fast workgroup never overwrites what a slow one still reads)
   unsigned* bar;     // barrier lines: generation, then one arrival flag per workgroup
@@ -409,16 +416,17 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr(PArgs a) {
   auto el = [&](int idx) -> size_t { return (size_t)(w + (idx / n) * W) * n + (idx % n); };
   V2* y = reinterpret_cast<V2*>(a.y);
   V2* br = reinterpret_cast<V2*>(a.br);
-  int rp = 0;  // residual buffer holding the current r
-  auto rbuf = [&](int which) { return reinterpret_cast<V2*>(a.r) + (size_t)which * hv; };
   auto Qv = [&](int j) { return reinterpret_cast<V2*>(a.Q) + (size_t)j * hv; };
   auto Zv = [&](int j) { return reinterpret_cast<V2*>(a.Z) + (size_t)j * hv; };
 
   // reduced source, r = b_r, y = 0, ||b_r||^2
   for (int i = w; i < Vh; i += W) site_hop<S>(a, i, a.b, a.b, -1.0, nullptr, a.br, vin, hp);
   __syncthreads();
+  V2* r = reinterpret_cast<V2*>(a.r);
+  V2* qraw = reinterpret_cast<V2*>(a.qraw);
+  V2* t = reinterpret_cast<V2*>(a.t);
+  auto Tv = [&](int j) { return reinterpret_cast<V2*>(a.T) + (size_t)j * 2 * hv; };  // full-size, odd half used
   {
-    V2* r = rbuf(rp);
     double v[1] = {0.0};
     for (int idx = threadIdx.x; idx < nel; idx += kPT) {
       const size_t e = el(idx);
@@ -439,24 +447,22 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr(PArgs a) {
     status = WCMG_ENAN;
     conv = true;
   }
+  __shared__ double salpha[3];  // alpha (re, im) and ||q_k||^2 of the current step
   while (!conv && iters < a.maxiter) {
     // cycle start: z_0 = r, t = Ytilde_oe r
-    {
-      V2* r = rbuf(rp);
-      for (int i = w; i < Vh; i += W) site_hop<S>(a, Vh + i, r, nullptr, 1.0, nullptr, a.t, vin, hp);
-      for (int idx = threadIdx.x; idx < nel; idx += kPT) {
-        const size_t e = el(idx);
-        stc(Zv(0) + e, ldc(r + e));
-      }
+    for (int i = w; i < Vh; i += W) site_hop<S>(a, Vh + i, r, nullptr, 1.0, nullptr, a.t, vin, hp);
+    for (int idx = threadIdx.x; idx < nel; idx += kPT) {
+      const size_t e = el(idx);
+      stc(Zv(0) + e, ldc(r + e));
     }
     if (!sync_sum(0)) return;
     int k = 0;
     for (;;) {
-      V2* r = rbuf(rp);
       V2* Qk = Qv(k);
       V2* Zk = Zv(k);
-      // q_k = r - Ytilde_eo t, then <q_j, q_k> for j < k over the owned sites
-      for (int i = w; i < Vh; i += W) site_hop<S>(a, i, a.t, r, -1.0, nullptr, Qk, vin, hp);
+      V2* Tk = Tv(k);
+      // q = D_r z_k = r - Ytilde_eo t; <q_j, q> for j < k, ||q||^2 and <q, r> over the owned sites
+      for (int i = w; i < Vh; i += W) site_hop<S>(a, i, a.t, r, -1.0, nullptr, a.qraw, vin, hp);
       __syncthreads();
       {
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -465,7 +471,7 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr(PArgs a) {
           double sr = 0.0, si = 0.0;
           for (int idx = lane; idx < nel; idx += 64) {
             const size_t e = el(idx);
-            cpx<double> u = ldo(Qj, e), qv = ldo(Qk, e);
+            cpx<double> u = ldo(Qj, e), qv = ldd(qraw, e);
             sr += u.r * qv.r + u.i * qv.i;
             si += u.r * qv.i - u.i * qv.r;
           }
@@ -476,19 +482,47 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr(PArgs a) {
             stc(mine() + 2 * j + 1, si);
           }
         }
-      }
-      if (!sync_sum(2 * k)) return;
-      // classical Gram-Schmidt against q_0..q_{k-1} (z alongside), then ||q||^2, <q, r>.
-      // The sum over j is split over NS slices of threads (j = sl, sl + NS, ...) whose
-      // partial sums are combined in LDS in slice order.
-      {
         double v[3] = {0.0, 0.0, 0.0};
+        for (int idx = threadIdx.x; idx < nel; idx += kPT) {
+          const size_t e = el(idx);
+          const cpx<double> qv = ldd(qraw, e), rr = ldd(r, e);
+          v[0] += qv.r * qv.r + qv.i * qv.i;
+          v[1] += qv.r * rr.r + qv.i * rr.i;
+          v[2] += qv.r * rr.i - qv.i * rr.r;
+        }
+        block_partial<3>(v, mine() + 2 * k, sh);
+      }
+      if (!sync_sum(2 * k + 3)) return;
+      // q_k = q - sum_j c_j q_j with c_j = <q_j, q> / ||q_j||^2, the q_j orthogonal:
+      // ||q_k||^2 = ||q||^2 - sum_j |<q_j, q>|^2 / ||q_j||^2, and <q_k, r> = <q, r>
+      // (r is orthogonal to every q_j)
+      if (threadIdx.x == 0) {
+        double qq = sv[2 * k];
+        for (int j = 0; j < k; ++j)
+          if (sqq[j] > 0.0) qq -= (sv[2 * j] * sv[2 * j] + sv[2 * j + 1] * sv[2 * j + 1]) / sqq[j];
+        salpha[2] = qq;
+        salpha[0] = qq > 0.0 ? sv[2 * k + 1] / qq : 0.0;
+        salpha[1] = qq > 0.0 ? sv[2 * k + 2] / qq : 0.0;
+      }
+      __syncthreads();
+      const double qq = salpha[2];
+      if (!(qq > 0.0) || !isfinite(qq)) {
+        status = isfinite(qq) ? WCMG_EBREAKDOWN : WCMG_ENAN;
+        break;
+      }
+      const cpx<double> alpha = mk(salpha[0], salpha[1]);
+      // the pair (q_k, z_k) by classical Gram-Schmidt (the sum over j split over NS slices
+      // of threads, combined in LDS in slice order); y += alpha z_k, r -= alpha q_k,
+      // z_{k+1} = r, ||r||^2
+      double vr[1] = {0.0};
+      {
         cpx<double>* acc = reinterpret_cast<cpx<double>*>(smem);  // [2][kPT]
+        V2* Zn = k + 1 < a.restart ? Zv(k + 1) : nullptr;
         const int CH = nel < kPT ? nel : kPT;
         for (int base = 0; base < nel; base += CH) {
           const int NS = k > 0 ? max(1, min(kPT / CH, k)) : 1;
-          const int t = threadIdx.x;
-          const int sl = t / CH, idx = base + (t - sl * CH);
+          const int tt = threadIdx.x;
+          const int sl = tt / CH, idx = base + (tt - sl * CH);
           if (k > 0 && sl < NS && idx < nel) {
             const size_t e = el(idx);
             cpx<double> aq = mk(0.0, 0.0), az = aq;
@@ -498,57 +532,74 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr(PArgs a) {
               aq = aq + cj * ldo(Qv(j), e);
               az = az + cj * ldo(Zv(j), e);
             }
-            acc[t] = aq;
-            acc[kPT + t] = az;
+            acc[tt] = aq;
+            acc[kPT + tt] = az;
           }
           __syncthreads();
-          if (t < CH && idx < nel) {
+          if (tt < CH && idx < nel) {
             const size_t e = el(idx);
+            cpx<double> q = ldd(qraw, e), z = ldo(Zk, e);
             if (k > 0) {
-              cpx<double> sq = acc[t], sz = acc[kPT + t];
+              cpx<double> sq = acc[tt], sz = acc[kPT + tt];
               for (int u = 1; u < NS; ++u) {
-                sq = sq + acc[u * CH + t];
-                sz = sz + acc[kPT + u * CH + t];
+                sq = sq + acc[u * CH + tt];
+                sz = sz + acc[kPT + u * CH + tt];
               }
-              std_(Qk, e, ldo(Qk, e) - sq);
-              std_(Zk, e, ldo(Zk, e) - sz);
+              q = q - sq;
+              z = z - sz;
             }
-            const cpx<double> qs = ldd(Qk, e), rr = ldd(r, e);
-            v[0] += qs.r * qs.r + qs.i * qs.i;
-            v[1] += qs.r * rr.r + qs.i * rr.i;
-            v[2] += qs.r * rr.i - qs.i * rr.r;
+            // the stored (rounded) values, without reading them back
+            const cpx<double> qs = mk((double)(S)q.r, (double)(S)q.i), zs = mk((double)(S)z.r, (double)(S)z.i);
+            std_(Qk, e, qs);
+            std_(Zk, e, zs);
+            std_(y, e, ldd(y, e) + alpha * zs);
+            const cpx<double> rs = axpy_round<S>(ldd(r, e), alpha, qs);
+            std_(r, e, rs);
+            if (Zn) std_(Zn, e, rs);
+            vr[0] += rs.r * rs.r + rs.i * rs.i;
           }
           __syncthreads();
         }
-        block_partial<3>(v, mine(), sh);
       }
-      if (!sync_sum(3)) return;
-      const double qq = sv[0];
-      if (!(qq > 0.0) || !isfinite(qq)) {
-        status = isfinite(qq) ? WCMG_EBREAKDOWN : WCMG_ENAN;
-        break;
-      }
-      const cpx<double> alpha = mk(sv[1] / qq, sv[2] / qq);
-      // y += alpha z_k, r' = r - alpha q_k (other buffer), z_{k+1} = r', ||r'||^2, and the
-      // odd-site hop of the next step from r - alpha q_k at the neighbours
+      // odd sites: T_k = Ytilde_oe q_k = Ytilde_oe q - sum_j c_j T_j, and t -= alpha T_k
+      for (int i = w; i < Vh; i += W) site_hop<S>(a, Vh + i, a.qraw, nullptr, 1.0, nullptr, Tk, vin, hp);
+      __syncthreads();
       {
-        V2* rn = rbuf(rp ^ 1);
-        V2* Zn = k + 1 < a.restart ? Zv(k + 1) : nullptr;
-        double v[1] = {0.0};
-        for (int idx = threadIdx.x; idx < nel; idx += kPT) {
-          const size_t e = el(idx);
-          std_(y, e, ldd(y, e) + alpha * ldd(Zk, e));
-          const cpx<double> rs = axpy_round<S>(ldd(r, e), alpha, ldd(Qk, e));
-          std_(rn, e, rs);
-          if (Zn) std_(Zn, e, rs);
-          v[0] += rs.r * rs.r + rs.i * rs.i;
+        cpx<double>* acc = reinterpret_cast<cpx<double>*>(smem);  // [kPT]
+        const int CH = nel < kPT ? nel : kPT;
+        for (int base = 0; base < nel; base += CH) {
+          const int NS = k > 0 ? max(1, min(kPT / CH, k)) : 1;
+          const int tt = threadIdx.x;
+          const int sl = tt / CH, idx = base + (tt - sl * CH);
+          if (k > 0 && sl < NS && idx < nel) {
+            const size_t e = el(idx) + hv;  // odd element of the owned odd site
+            cpx<double> at = mk(0.0, 0.0);
+            for (int j = sl; j < k; j += NS) {
+              const double d = sqq[j];
+              const cpx<double> cj = d > 0.0 ? mk(sv[2 * j] / d, sv[2 * j + 1] / d) : mk(0.0, 0.0);
+              at = at + cj * ldo(Tv(j), e);
+            }
+            acc[tt] = at;
+          }
+          __syncthreads();
+          if (tt < CH && idx < nel) {
+            const size_t e = el(idx) + hv;
+            cpx<double> tk = ldd(Tk, e);
+            if (k > 0) {
+              cpx<double> st = acc[tt];
+              for (int u = 1; u < NS; ++u) st = st + acc[u * CH + tt];
+              tk = tk - st;
+            }
+            const cpx<double> tks = mk((double)(S)tk.r, (double)(S)tk.i);
+            std_(Tk, e, tks);
+            std_(t, e, ldd(t, e) - alpha * tks);
+          }
+          __syncthreads();
         }
-        if (threadIdx.x == 0) sqq[k] = qq;
-        block_partial<1>(v, mine(), sh);
-        for (int i = w; i < Vh; i += W) site_hop<S>(a, Vh + i, r, nullptr, 1.0, nullptr, a.t, vin, hp, Qk, alpha);
       }
+      if (threadIdx.x == 0) sqq[k] = qq;
+      block_partial<1>(vr, mine(), sh);
       if (!sync_sum(1)) return;
-      rp ^= 1;
       rn2 = sv[0];
       ++k;
       ++iters;
@@ -559,18 +610,16 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr(PArgs a) {
       if (k >= a.restart || iters >= a.maxiter || (!a.fixed && sqrt(rn2) <= target)) break;
     }
     if (status || a.fixed) break;
-    // true residual r = b_r - D_r y at the end of the cycle (q_0 as scratch)
+    // true residual r = b_r - D_r y at the end of the cycle (q_raw as scratch)
     for (int i = w; i < Vh; i += W) site_hop<S>(a, Vh + i, a.y, nullptr, 1.0, nullptr, a.t, vin, hp);
     if (!sync_sum(0)) return;
-    for (int i = w; i < Vh; i += W) site_hop<S>(a, i, a.t, a.y, -1.0, nullptr, Qv(0), vin, hp);
+    for (int i = w; i < Vh; i += W) site_hop<S>(a, i, a.t, a.y, -1.0, nullptr, a.qraw, vin, hp);
     __syncthreads();
     {
-      V2* r = rbuf(rp);
-      const V2* q0 = Qv(0);
       double v[1] = {0.0};
       for (int idx = threadIdx.x; idx < nel; idx += kPT) {
         const size_t e = el(idx);
-        std_(r, e, ldd(br, e) - ldd(q0, e));
+        std_(r, e, ldd(br, e) - ldd(qraw, e));
         const cpx<double> rs = ldd(r, e);
         v[0] += rs.r * rs.r + rs.i * rs.i;
       }
@@ -635,6 +684,8 @@ void launch_coarse_gcr_persistent(int prec, const CoarseGcrArgs& g, hipStream_t 
   a.br = g.br;
   a.Q = g.Q;
   a.Z = g.Z;
+  a.T = g.T;
+  a.qraw = g.qraw;
   a.part = g.part;
   a.bar = g.bar;
   a.info = g.info;

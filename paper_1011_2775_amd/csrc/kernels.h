@@ -242,8 +242,8 @@ void launch_batched_inverse(double* M, int nmat, int n, int* flag, hipStream_t s
 // Whole approximate coarse solve (red-black reduced operator, GCR(restart)
 // from zero, stopping at ||r|| <= tol ||b_r|| or after maxiter steps; fixed:
 // exactly min(restart, maxiter) steps) in one cooperative launch of `grid`
-// (<= 256) workgroups.  Buffers: b, c, t [V][n]; y, br [Vh][n]; r [2][Vh][n];
-// Q, Z [restart][Vh][n]; part 2 * grid * coarse_gcr_persistent_part_doubles();
+// (<= 256) workgroups.  Buffers: b, c, t [V][n]; y, br, r, qraw [Vh][n];
+// Q, Z [restart][Vh][n]; T [restart][V][n]; part 2 * grid * coarse_gcr_persistent_part_doubles();
 // bar: kPersistCtlBytes of barrier lines (zeroed before the first launch;
 // consistent after every completed launch, zeroed again after an abort); info
 // [3] (at bar + kPersistInfoOffset bytes in the library's use): iterations are
@@ -263,6 +263,8 @@ struct CoarseGcrArgs {
   void* br;
   void* Q;
   void* Z;
+  void* T;
+  void* qraw;
   double* part;
   unsigned* bar;
   int* info;

@@ -270,7 +270,7 @@ KrylovResult gcr(Ctx& c, GcrSpace& S, const OpFn& A, const OpFn* K, void* x, con
 // launch: buffers of its own, iterations and failures counted on the device
 // and read back by persistent_collect (one host synchronisation).
 struct PersistWork {
-  DBuf q, z, part, ctl;  // Krylov bases, partial sums, {barrier[2], info[3]}
+  DBuf q, z, t, qraw, part, ctl;  // Krylov bases, odd-site hops of q, partial sums, barrier lines + info
   int grid = -1;         // workgroups (0: not available; -1: not yet queried)
   bool pending = false;  // device counters not yet read back
 };

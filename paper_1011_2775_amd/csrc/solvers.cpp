@@ -422,6 +422,8 @@ void persistent_launch(Ctx& c, PersistWork& w, CoarseLevel& C, int prec, void* o
   restart = std::min(restart, std::max(1, maxiter));
   w.q.alloc((size_t)restart * hv * cs);
   w.z.alloc((size_t)restart * hv * cs);
+  w.t.alloc((size_t)restart * 2 * hv * cs);
+  w.qraw.alloc(hv * cs);
   if (!w.ctl.p) {
     w.part.alloc(2 * (size_t)w.grid * coarse_gcr_persistent_part_doubles() * sizeof(double));
     w.ctl.alloc(kPersistCtlBytes);
@@ -440,6 +442,8 @@ void persistent_launch(Ctx& c, PersistWork& w, CoarseLevel& C, int prec, void* o
   a.br = br;
   a.Q = w.q.p;
   a.Z = w.z.p;
+  a.T = w.t.p;
+  a.qraw = w.qraw.p;
   a.part = w.part.as<double>();
   a.bar = w.ctl.as<unsigned>();
   a.info = reinterpret_cast<int*>(w.ctl.as<char>() + kPersistInfoOffset);
