@@ -275,12 +275,14 @@ def batched_leg(w, torch, inputs, np, m0=None):
 
 def mg_params(w, cfg):
     """Multigrid parameters used for the timed solves.  The paper reports the
-    best parameter set per case and a per-level tolerance near 0.1; these
-    were chosen by a sweep on this workload: 60 GCR steps per relaxation and
-    at most 5 relaxations per vector in the setup, and a coarse GCR(30)
-    capped at 100 iterations."""
+    best parameter set per case with per-level tolerances of order 0.1; these
+    were chosen by sweeps on this workload: 60 GCR steps per relaxation and
+    at most 5 relaxations per vector in the setup, a coarse GCR(30) to a
+    relative 0.2 capped at 100 iterations, 4 MR post-smoothing steps (coarse
+    tolerance 0.05-0.3 x smoothing 2-8 at the three masses: 0.2 with 4 steps
+    is 11% faster in total than 0.1, once the coarse solve is one launch)."""
     return w.default_params(block=cfg["blocks"], nvec=cfg["nvec"], seed=cfg["setup_seed"], setup_relax=60,
-                            setup_max_steps=5, restart=[30], max_iter=[100])
+                            setup_max_steps=5, restart=[30], max_iter=[100], tol=[0.2], nu_post=4)
 
 
 def main():
@@ -478,6 +480,7 @@ def main():
         "config": {"workload": "wilson-clover 16^3x32 MG-GCR vs BiCGStab, m0 sweep", "lattice": "16x16x16x32",
                    "gauge": "exp(0.5iH) + 5 APE sweeps (alpha 0.5)", "csw": cfg["csw"], "m0": masses,
                    "blocks": list(bl), "nvec": cfg["nvec"][0], "precision": "FP32 preconditioner, FP64 outer GCR",
+                   "coarse_tol": 0.2, "nu_post": 4,
                    "rhs": "1 Z2 source", "tol": cfg["tol"], "step": "one MG-GCR solve at each mass",
                    "parallelism": "1 GPU"},
         "per_mass": mass_rows,

@@ -52,13 +52,18 @@ __device__ __forceinline__ void block_sum(double (&v)[NR]) {
   }
 }
 
+// KB vectors per workgroup: the input spinor of each site is loaded once and
+// dotted with the KB vectors (the sum over the block's sites in a fixed tree)
+constexpr int kRestrictKB = 4;
+
 template <typename S>
 __global__ void __launch_bounds__(128) k_restrict(void* out, size_t site_stride, size_t row_stride, const void* in,
                                                   const void* vecs, size_t vec_bytes, size_t half_bytes, int nvec,
                                                   int p, DGeom g, BlockGeom bg, int accumulate) {
   using C = typename Compute<S>::T;
   using V2 = typename Vec2<C>::T;
-  const int clex = blockIdx.x, k = blockIdx.y;
+  const int clex = blockIdx.x, k0 = blockIdx.y * kRestrictKB;
+  const int kb = min(kRestrictKB, nvec - k0);
   int cc[4];
   {
     int r = clex;
@@ -69,8 +74,9 @@ __global__ void __launch_bounds__(128) k_restrict(void* out, size_t site_stride,
     cc[2] = r % bg.nb[2];
     cc[3] = r / bg.nb[2];
   }
-  const void* vk = reinterpret_cast<const char*>(vecs) + (size_t)k * vec_bytes + (size_t)p * half_bytes;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  double acc[4 * kRestrictKB];
+#pragma unroll
+  for (int j = 0; j < 4 * kRestrictKB; ++j) acc[j] = 0.0;
   const int half = bg.bvol / 2, bxh = bg.b[0] / 2;
   for (int l = threadIdx.x; l < half; l += blockDim.x) {
     int lxh = l % bxh, r = l / bxh;
@@ -84,22 +90,30 @@ __global__ void __launch_bounds__(128) k_restrict(void* out, size_t site_stride,
     c[3] = cc[3] * bg.b[3] + lt;
     c[0] = cc[0] * bg.b[0] + 2 * lxh + ((p + c[1] + c[2] + c[3]) & 1);
     int i = cb_index(g, c);
-    cpx<C> v[12], w[12];
-    SpinorIO<S>::load(vk, g.Vh, i, v);
+    cpx<C> w[12];
     SpinorIO<S>::load(in, g.Vh, i, w);
 #pragma unroll
-    for (int a = 0; a < 12; ++a) {
-      int s = a >= 6;
-      acc[2 * s] += (double)v[a].r * (double)w[a].r + (double)v[a].i * (double)w[a].i;
-      acc[2 * s + 1] += (double)v[a].r * (double)w[a].i - (double)v[a].i * (double)w[a].r;
+    for (int kk = 0; kk < kRestrictKB; ++kk) {
+      if (kk < kb) {
+        const void* vk = reinterpret_cast<const char*>(vecs) + (size_t)(k0 + kk) * vec_bytes + (size_t)p * half_bytes;
+        cpx<C> v[12];
+        SpinorIO<S>::load(vk, g.Vh, i, v);
+#pragma unroll
+        for (int a = 0; a < 12; ++a) {
+          const int s = a >= 6;
+          acc[4 * kk + 2 * s] += (double)v[a].r * (double)w[a].r + (double)v[a].i * (double)w[a].i;
+          acc[4 * kk + 2 * s + 1] += (double)v[a].r * (double)w[a].i - (double)v[a].i * (double)w[a].r;
+        }
+      }
     }
   }
-  block_sum<4>(acc);
-  if (threadIdx.x == 0) {
+  block_sum<4 * kRestrictKB>(acc);
+  if ((int)threadIdx.x < kb) {
+    const int kk = threadIdx.x, k = k0 + kk;
     V2* o = reinterpret_cast<V2*>(out) + (size_t)coarse_internal(bg, clex) * site_stride;
     V2* o0 = o + (size_t)k * row_stride;
     V2* o1 = o + (size_t)(nvec + k) * row_stride;
-    double r0 = acc[0], i0 = acc[1], r1 = -acc[2], i1 = -acc[3];
+    double r0 = acc[4 * kk], i0 = acc[4 * kk + 1], r1 = -acc[4 * kk + 2], i1 = -acc[4 * kk + 3];
     if (accumulate) {
       r0 += (double)o0->x;
       i0 += (double)o0->y;
@@ -317,7 +331,7 @@ int coarse_internal_index_host(const BlockGeom& bg, int clex) {
 
 void launch_restrict(int prec, void* out, size_t site_stride, size_t row_stride, const void* in, const void* vecs,
                      int nvec, int p, const Geom& g, const BlockGeom& bg, bool accumulate, hipStream_t st) {
-  dim3 grid(bg.Vc, nvec), block(128);
+  dim3 grid(bg.Vc, (nvec + kRestrictKB - 1) / kRestrictKB), block(128);
   size_t hb = spinor_bytes(prec, g.Vh);
   if (prec == WCMG_F64)
     hipLaunchKernelGGL(k_restrict<double>, grid, block, 0, st, out, site_stride, row_stride, in, vecs, 2 * hb, hb,
