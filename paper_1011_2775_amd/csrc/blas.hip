@@ -2,10 +2,11 @@
 //
 // Vectors are flat arrays of complex numbers in double or float storage;
 // every reduction accumulates in double, first per wavefront with lane
-// shuffles, then across the 4 wavefronts of a block in LDS; a second pass
-// (one block per result) sums the per-block partials in a fixed tree and
-// writes the result to device memory.  The grids depend only on the vector
-// length, so results are bitwise reproducible run to run.
+// shuffles, then across the 4 wavefronts of a block in LDS; the last block
+// of the grid to finish then sums the per-block partials in a fixed tree and
+// writes the result to device memory, all in the one launch.  The grids
+// depend only on the vector length, so results are bitwise reproducible run
+// to run.
 #include "blas_common.h"
 
 namespace wcmg {
@@ -13,26 +14,6 @@ namespace wcmg {
 namespace {
 
 using namespace blas_detail;
-
-// Second pass, one block per output k: res[k] = sum over blocks of
-// partial[b*stride + k], each thread summing a fixed strided subset and the
-// block combining them in a fixed tree, so the order never depends on timing.
-__global__ void __launch_bounds__(kThreads) k_finalize(const RedOut o, int nr, int stride, int nblocks) {
-  const int k = blockIdx.x;
-  double s = 0.0;
-  for (int b = threadIdx.x; b < nblocks; b += kThreads) s += o.partial[(size_t)b * stride + k];
-  __shared__ double sh[kThreads];
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = kThreads / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    o.res[k] = sh[0];
-    if (o.hres) o.hres[k] = sh[0];
-  }
-}
 
 // complex vector in storage D from storage T (rounding to nearest)
 template <typename D, typename T>
@@ -117,7 +98,7 @@ __global__ void __launch_bounds__(kThreads) k_multi_cdot(MultiArgs m, int k, con
       }
     }
   }
-  block_reduce<2 * kMaxK>(v, o);
+  block_reduce<2 * kMaxK>(v, o, 2 * k);
 }
 
 template <typename T>
@@ -269,11 +250,6 @@ __global__ void k_mr_update(double ar, double ai, void* x, void* r, const void* 
     HIPCHK(hipGetLastError());                                                                  \
   } while (0)
 
-// nr results, partials laid out with `stride` doubles per block (the kernel's NR)
-void finalize(const RedOut& o, int nr, size_t n, hipStream_t st, int stride = 0) {
-  hipLaunchKernelGGL(k_finalize, dim3(nr), dim3(kThreads), 0, st, o, nr, stride ? stride : nr, (int)red_grid(n).x);
-  HIPCHK(hipGetLastError());
-}
 
 void blas_zero(int prec, void* x, size_t n, hipStream_t st) { DISPATCH(prec, k_zero, ew_grid(n), x, n); }
 void blas_defl_coefs(const double* dots, double* qa, int K, hipStream_t st) {
@@ -301,15 +277,12 @@ void blas_axpby(int prec, double ar, double ai, const void* x, double br, double
 }
 void blas_norm2(int prec, const void* x, size_t n, const RedOut& o, hipStream_t st) {
   DISPATCH(prec, k_norm2, red_grid(n), x, n, o);
-  finalize(o, 1, n, st);
 }
 void blas_cdot(int prec, const void* x, const void* y, size_t n, const RedOut& o, hipStream_t st) {
   DISPATCH(prec, k_cdot, red_grid(n), x, y, n, o);
-  finalize(o, 2, n, st);
 }
 void blas_cdot_norm(int prec, const void* x, const void* y, size_t n, const RedOut& o, hipStream_t st) {
   DISPATCH(prec, k_cdot_norm, red_grid(n), x, y, n, o);
-  finalize(o, 3, n, st);
 }
 void blas_multi_cdot(int prec, const void* const* v, int k, const void* y, size_t n, const RedOut& o,
                      hipStream_t st) {
@@ -319,7 +292,6 @@ void blas_multi_cdot(int prec, const void* const* v, int k, const void* y, size_
     for (int j = 0; j < kk; ++j) m.v[j] = v[j0 + j];
     // all 2*kMaxK slots are written; only the first 2*kk are meaningful
     DISPATCH(prec, k_multi_cdot, red_grid(n), m, kk, y, n, o.at(2 * j0));
-    finalize(o.at(2 * j0), 2 * kk, n, st, 2 * kMaxK);
   }
 }
 void blas_multi_axpy(int prec, const double* c, const void* const* v, int k, void* y, size_t n, hipStream_t st) {
@@ -337,12 +309,10 @@ void blas_multi_axpy(int prec, const double* c, const void* const* v, int k, voi
 void blas_axpy_norm(int prec, double ar, double ai, const void* x, void* y, size_t n, const RedOut& o,
                     hipStream_t st) {
   DISPATCH(prec, k_axpy_norm, red_grid(n), ar, ai, x, y, n, o);
-  finalize(o, 1, n, st);
 }
 void blas_bicg_update(int prec, double ar, double ai, double wr, double wi, const void* p, const void* s,
                       const void* t, void* x, void* r, const void* rhat, size_t n, const RedOut& o, hipStream_t st) {
   DISPATCH(prec, k_bicg_update, red_grid(n), ar, ai, wr, wi, p, s, t, x, r, rhat, n, o);
-  finalize(o, 3, n, st);
 }
 void blas_bicg_p(int prec, double br, double bi, double wr, double wi, const void* r, const void* v, void* p,
                  size_t n, hipStream_t st) {
@@ -357,7 +327,6 @@ void blas_gcr_orth_dev(int prec, const void* const* q, const void* const* w, int
   if (k == 0) {
     MultiArgs m{};
     DISPATCH(prec, k_gcr_orth_dev, red_grid(n), m, 0, y, z, r, n, beta, qa, 1, o);
-    finalize(o, 3, n, st);
     return;
   }
   for (int j0 = 0; j0 < k; j0 += kMaxK) {
@@ -369,14 +338,12 @@ void blas_gcr_orth_dev(int prec, const void* const* q, const void* const* w, int
     }
     int last = (j0 + kk == k);
     DISPATCH(prec, k_gcr_orth_dev, red_grid(n), m, kk, y, z, r, n, beta + 2 * j0, qa + 4 * j0, last, o);
-    if (last) finalize(o, 3, n, st);
   }
 }
 
 void blas_gcr_update_r_dev(int prec, const void* q, void* r, size_t n, const double* qa_k, const RedOut& o,
                            hipStream_t st) {
   DISPATCH(prec, k_gcr_update_r_dev, red_grid(n), q, r, n, qa_k, o);
-  finalize(o, 1, n, st);
 }
 
 void blas_gcr_update_x_dev(int prec, const void* const* z, int k, void* x, size_t n, const double* qa,
