@@ -120,8 +120,10 @@ typedef struct {
                                        vectors are block-orthonormalised in FP64 afterwards */
   int coarse_launch;                /* unpreconditioned GCR on the coarsest level: 0 (default) the
                                        whole solve in one cooperative launch with grid barriers,
-                                       where the device supports it and cycle_mode != 2; 1 one
-                                       launch per kernel of every step */
+                                       where the device supports it and cycle_mode != 2 (the
+                                       one-site kernel where it applies, as wcmg_coarse_solve
+                                       launch 0); 2 the same with the strided kernel always; 1
+                                       one launch per kernel of every step */
 } wcmg_mg_params;
 
 typedef struct {
@@ -216,8 +218,12 @@ int wcmg_apply_coarse(void* ctx, int lat, int level, int op, int prec, void* out
  * odd half reconstructed.  b and x: one complex128 [Vc][2 Nv] device vector
  * each (lexicographic coarse sites).  prec: F64 or F32 arithmetic and
  * storage.  launch 0: the whole solve in one cooperative launch with grid
- * barriers (WCMG_ENODEV if the device cannot run the grid at once); launch 1:
- * one launch per kernel of every step.  stats (optional): iters, status, and
+ * barriers (WCMG_ENODEV if the device cannot run the grid at once): with at
+ * most one even site per workgroup the one-site kernel (Krylov basis in LDS,
+ * a neighbour wait in place of the second grid barrier of a step), else sites
+ * strided over the workgroups; launch 2: the strided kernel always (the same
+ * bits); launch 1: one launch per kernel of every step.  stats (optional):
+ * iters, status, and
  * true_rel_res = ||b - Yhat x|| / ||b|| of the full coarse system in prec.
  * Requires a lattice with every coarse extent even (EDIM otherwise). */
 int wcmg_coarse_solve(void* ctx, int lat, int level, int prec, void* x, const void* b, double tol, int max_iter,

@@ -182,7 +182,9 @@ class Context:
 
     def coarse_solve(self, b, level=1, prec=F64, tol=0.1, max_iter=100, restart=30, launch=0, lat=0):
         """Approximate Dhat^-1 b on coarse level `level` (complex128 [Vc][2Nv] device
-        vector) by the red-black GCR of the cycle; launch 0: one cooperative launch."""
+        vector) by the red-black GCR of the cycle; launch 0: one cooperative launch (the
+        one-site kernel where it applies), 1: one launch per kernel, 2: the strided
+        cooperative kernel."""
         b = b.contiguous()
         x = torch.empty_like(b)
         st = _lib.Stats()

@@ -282,7 +282,7 @@ int wcmg_set_mg_params(void* ctx, int lat, const wcmg_mg_params* p) {
   CHECK(p->coarsest >= 0 && p->coarsest <= 2, WCMG_EINVAL,
         "coarsest must be 0 (GCR), 1 (dense FP64 inverse) or 2 (deflated FP64 GCR)");
   CHECK(p->cycle_mode >= 0 && p->cycle_mode <= 2, WCMG_EINVAL, "cycle_mode must be 0, 1 or 2");
-  CHECK(p->coarse_launch == 0 || p->coarse_launch == 1, WCMG_EINVAL, "coarse_launch must be 0 or 1");
+  CHECK(p->coarse_launch >= 0 && p->coarse_launch <= 2, WCMG_EINVAL, "coarse_launch must be 0, 1 or 2");
   CHECK(p->setup_prec == WCMG_F64 || p->setup_prec == WCMG_F32 || p->setup_prec == WCMG_F16, WCMG_EINVAL,
         "setup precision must be F64, F32 or F16 (FP16 fields, FP32 arithmetic)");
   // coarse extents and degrees of freedom of every level
@@ -771,7 +771,7 @@ int wcmg_coarse_solve(void* ctx, int lat, int level, int prec, void* x, const vo
   CHECK(tol > 0 && tol < 1, WCMG_EINVAL, "tol must be in (0,1)");
   CHECK(max_iter >= 1 && restart >= 1 && restart <= kMaxRestart, WCMG_EINVAL,
         "max_iter must be >= 1 and restart in 1..64");
-  CHECK(launch == 0 || launch == 1, WCMG_EINVAL, "launch must be 0 or 1");
+  CHECK(launch >= 0 && launch <= 2, WCMG_EINVAL, "launch must be 0, 1 or 2");
   LatticeState& L = *c->lats[lat];
   CHECK(L.have_params && level >= 1 && level <= L.params.nlevels, WCMG_EINVAL, "level out of range");
   CHECK((int)L.levels.size() >= level && L.levels[level - 1]->built, WCMG_ESTATE, "coarse operator not built");
@@ -790,11 +790,11 @@ int wcmg_coarse_solve(void* ctx, int lat, int level, int prec, void* x, const vo
     wcmg_stats s{};
     auto t0 = std::chrono::steady_clock::now();
     CoarseOp op{&C, prec, &c->cw[prec == WCMG_F64 ? 0 : 1], c->st};
-    if (launch == 0) {
+    if (launch != 1) {
       PersistWork pw;
       if (!persistent_available(pw, prec, C, restart))
         fail(WCMG_ENODEV, "the device cannot run the persistent coarse solve");
-      persistent_launch(*c, pw, C, prec, vx, vb, t, y, r, br, tol, restart, max_iter, false);
+      persistent_launch(*c, pw, C, prec, vx, vb, t, y, r, br, tol, restart, max_iter, false, launch == 2);
       int code = WCMG_OK;
       s.iters = (int)persistent_collect(*c, pw, &code);
       s.status = code;

@@ -38,6 +38,11 @@
 // polls, so all workgroups leave the kernel and the host reports the failure.
 #include "kernels.h"
 
+// No implicit multiply-add contraction in this file: the two kernels below
+// evaluate the same expressions in different surroundings, and with only the
+// explicit fma of the matrix products their results agree bit for bit.
+#pragma clang fp contract(off)
+
 namespace wcmg {
 
 namespace {
@@ -152,6 +157,12 @@ __device__ bool grid_barrier(unsigned* ctl, int* abort_flag, unsigned epoch) {
   return ok_s != 0;
 }
 
+// complex product evaluated under this file's no-contraction rule (the
+// operator of the common header may be fused differently in each caller)
+__device__ __forceinline__ cpx<double> cmul(cpx<double> a, cpx<double> b) {
+  return mk(a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r);
+}
+
 // r - a q rounded to the storage type, without contraction, so that the
 // owner of a site and the neighbours that rebuild it get the same bits
 template <typename S>
@@ -242,8 +253,10 @@ struct PArgs {
                      // alternate, so a fast workgroup never overwrites what a slow one still reads)
   unsigned* bar;     // barrier lines: generation, then one arrival flag per workgroup
   int* info;         // [0] iterations (accumulated), [1] status, [2] abort
+  unsigned* lflags;  // neighbour-wait lines of the one-site kernel, one per workgroup
   double tol;
   int Vh, n, restart, maxiter, fixed, G, stride;
+  int sbytes;  // one-site kernel: LDS bytes before the Krylov basis
 };
 
 // Rows of M v for one site (M: n x ncols column-major, v in LDS): lanes with
@@ -529,8 +542,8 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr(PArgs a) {
             for (int j = sl; j < k; j += NS) {
               const double d = sqq[j];
               const cpx<double> cj = d > 0.0 ? mk(sv[2 * j] / d, sv[2 * j + 1] / d) : mk(0.0, 0.0);
-              aq = aq + cj * ldo(Qv(j), e);
-              az = az + cj * ldo(Zv(j), e);
+              aq = aq + cmul(cj, ldo(Qv(j), e));
+              az = az + cmul(cj, ldo(Zv(j), e));
             }
             acc[tt] = aq;
             acc[kPT + tt] = az;
@@ -552,7 +565,7 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr(PArgs a) {
             const cpx<double> qs = mk((double)(S)q.r, (double)(S)q.i), zs = mk((double)(S)z.r, (double)(S)z.i);
             std_(Qk, e, qs);
             std_(Zk, e, zs);
-            std_(y, e, ldd(y, e) + alpha * zs);
+            std_(y, e, ldd(y, e) + cmul(alpha, zs));
             const cpx<double> rs = axpy_round<S>(ldd(r, e), alpha, qs);
             std_(r, e, rs);
             if (Zn) std_(Zn, e, rs);
@@ -577,7 +590,7 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr(PArgs a) {
             for (int j = sl; j < k; j += NS) {
               const double d = sqq[j];
               const cpx<double> cj = d > 0.0 ? mk(sv[2 * j] / d, sv[2 * j + 1] / d) : mk(0.0, 0.0);
-              at = at + cj * ldo(Tv(j), e);
+              at = at + cmul(cj, ldo(Tv(j), e));
             }
             acc[tt] = at;
           }
@@ -592,7 +605,7 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr(PArgs a) {
             }
             const cpx<double> tks = mk((double)(S)tk.r, (double)(S)tk.i);
             std_(Tk, e, tks);
-            std_(t, e, ldd(t, e) - alpha * tks);
+            std_(t, e, ldd(t, e) - cmul(alpha, tks));
           }
           __syncthreads();
         }
@@ -644,6 +657,404 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr(PArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// One site per workgroup (grid == Vh): workgroup w owns the even site w and
+// the odd site Vh + w.  What only the owner reads stays on chip: the Krylov
+// basis (q_j and z_j of the even site, T_j of the odd site) lives in LDS, and
+// so do copies of the owned parts of y, r, b_r, t and q, so a step reads from
+// memory only the hop matrices and the neighbours' values.  The vectors that
+// other workgroups gather are still stored: q and t at every step, y for the
+// true residual and the solution, r at the start of a cycle.
+//
+// The second barrier of a step becomes a neighbour wait: t on an odd site is
+// read only by the even sites next to it, so every workgroup publishes an
+// epoch on a line of its own and waits for the owners of the eight odd
+// neighbours of its even site.  ||r_k||^2 joins the sums of the next step's
+// grid barrier, so a cycle ends one even-site hop after the step that
+// converged (that hop's result is dropped).  The arithmetic of every vector
+// element and of every grid sum is that of the strided kernel above: both
+// produce the same bits, and only the grid sum behind the stopping test runs
+// in another order.
+// ---------------------------------------------------------------------------
+
+// publish epoch on this workgroup's line, then wait until the line of
+// workgroup nbw (a distinct neighbour per thread, -1 for none) has reached it
+__device__ bool neighbour_wait(unsigned* lines, int* abort_flag, int nbw, unsigned epoch) {
+  __shared__ int okl;
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    okl = 1;
+    __hip_atomic_store(lines + 32 * blockIdx.x, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  if (nbw >= 0) {
+    unsigned spins = 0;
+    while ((int)(__hip_atomic_load(lines + 32 * nbw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - epoch) < 0) {
+      if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || ++spins > kSpinLimit) {
+        __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        okl = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  __syncthreads();
+  return okl != 0;
+}
+
+template <typename V2>
+__device__ __forceinline__ cpx<double> cvt(V2 v) {
+  return mk((double)v.x, (double)v.y);
+}
+template <typename V2>
+__device__ __forceinline__ V2 tov2(cpx<double> c) {
+  V2 v;
+  v.x = c.r;
+  v.y = c.i;
+  return v;
+}
+
+// Hop of the one-site kernel:
+//   out(c) = xd(c) + coeff * sum_d Ytilde_d(c) in(nb(c, d))   (then Xl(c) [...])
+// thread t < 8n gathers element t % n of its neighbour nb (the t / n-th of c);
+// xd is an LDS copy of the site's elements (xdl) or a global field (xdg) or
+// absent; the result goes to a global field (outg, coherent stores) and/or an
+// LDS copy (outl).  The first PF columns of the thread's share of the hop
+// matrix are loaded before the gather, so the two latencies overlap; the sums
+// run in the order of site_matvec.
+template <typename S>
+__device__ void hop1(const PArgs& a, int c, int nb, const typename Vec2<S>::T* in, const typename Vec2<S>::T* xdl,
+                     const typename Vec2<S>::T* xdg, double coeff, const void* Xl, typename Vec2<S>::T* outg,
+                     typename Vec2<S>::T* outl, cpx<typename Compute<S>::T>* vin,
+                     cpx<typename Compute<S>::T>* part) {
+  using C = typename Compute<S>::T;
+  using V2 = typename Vec2<S>::T;
+  constexpr int PF = sizeof(S) == 8 ? 1 : 2;
+  const int n = a.n, G = a.G, R2 = n >> 1, ncols = 8 * n;
+  const int tid = threadIdx.x, g = tid / R2, rp = tid - g * R2;
+  const V2* M = reinterpret_cast<const V2*>(a.Yt) + (size_t)c * 8 * n * n + 2 * rp;
+  cpx<C> p0[PF], p1[PF];
+  if (g < G) {
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const int col = g + u * G;
+      if (col < ncols) ld2(M + (size_t)col * n, p0[u], p1[u]);
+    }
+  }
+  __syncthreads();  // the previous task is done with vin and part
+  if (tid < ncols) {
+    const V2 v = ldc(in + (size_t)nb * n + (tid - (tid / n) * n));
+    vin[tid] = mk((C)v.x, (C)v.y);
+  }
+  __syncthreads();
+  if (g < G) {
+    cpx<C> a0 = mk((C)0, (C)0), a1 = a0;
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const int col = g + u * G;
+      if (col < ncols) {
+        const cpx<C> x = vin[col];
+        cfma(a0, p0[u], x);
+        cfma(a1, p1[u], x);
+      }
+    }
+#pragma unroll 8
+    for (int col = g + PF * G; col < ncols; col += G) {
+      cpx<C> e0, e1;
+      ld2(M + (size_t)col * n, e0, e1);
+      const cpx<C> x = vin[col];
+      cfma(a0, e0, x);
+      cfma(a1, e1, x);
+    }
+    part[g * n + 2 * rp] = a0;
+    part[g * n + 2 * rp + 1] = a1;
+  }
+  for (int h = G >> 1; h > 0; h >>= 1) {
+    __syncthreads();
+    if (g < h) {
+      part[g * n + 2 * rp] = part[g * n + 2 * rp] + part[(g + h) * n + 2 * rp];
+      part[g * n + 2 * rp + 1] = part[g * n + 2 * rp + 1] + part[(g + h) * n + 2 * rp + 1];
+    }
+  }
+  cpx<C> s[2];
+  if (g == 0) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int i = 2 * rp + k;
+      s[k] = (C)coeff * part[i];
+      if (xdl) s[k] = s[k] + mk((C)xdl[i].x, (C)xdl[i].y);
+      if (xdg) {
+        const V2 w = ldc(xdg + (size_t)c * n + i);
+        s[k] = s[k] + mk((C)w.x, (C)w.y);
+      }
+    }
+  }
+  if (Xl) {
+    // local matrix on the hop result, staged in vin (rounded to storage precision)
+    __syncthreads();
+    if (g == 0) {
+#pragma unroll
+      for (int k = 0; k < 2; ++k) vin[2 * rp + k] = mk((C)(S)s[k].r, (C)(S)s[k].i);
+    }
+    __syncthreads();
+    site_matvec<C, V2>(reinterpret_cast<const V2*>(Xl) + (size_t)c * n * n, vin, n, n, G, part, s[0], s[1]);
+  }
+  if (g == 0) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      V2 w;
+      w.x = (S)s[k].r;
+      w.y = (S)s[k].i;
+      if (outg) stc(outg + (size_t)c * n + 2 * rp + k, w);
+      if (outl) outl[2 * rp + k] = w;
+    }
+  }
+}
+
+template <typename S>
+__global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
+  using C = typename Compute<S>::T;
+  using V2 = typename Vec2<S>::T;
+  extern __shared__ char smem[];  // hop operands or Gram-Schmidt slice sums, then basis and copies
+  const int n = a.n, Vh = a.Vh, R = a.restart, w = blockIdx.x, W = gridDim.x, tid = threadIdx.x;
+  cpx<C>* vin = reinterpret_cast<cpx<C>*>(smem);  // 8n
+  cpx<C>* hp = vin + 8 * n;                       // G * n
+  V2* Qs = reinterpret_cast<V2*>(smem + a.sbytes);  // [R][n] q_j (even site)
+  V2* Zs = Qs + (size_t)R * n;                      // [R][n] z_j (even site)
+  V2* Ts = Zs + (size_t)R * n;                      // [R][n] T_j (odd site)
+  V2* ym = Ts + (size_t)R * n;                      // owned elements: y, r, b_r (even), t (odd), q (even)
+  V2* rm = ym + n;
+  V2* bm = rm + n;
+  V2* tm = bm + n;
+  V2* qm = tm + n;
+  __shared__ double sv[2 * kPMaxRestart + 8];  // grid sums
+  __shared__ double sqq[kPMaxRestart];         // ||q_j||^2
+  __shared__ double sh[4 * kPWaves];
+  __shared__ double salpha[3];
+  const V2* b = reinterpret_cast<const V2*>(a.b);
+  V2* y = reinterpret_cast<V2*>(a.y);
+  V2* r = reinterpret_cast<V2*>(a.r);
+  V2* t = reinterpret_cast<V2*>(a.t);
+  V2* qraw = reinterpret_cast<V2*>(a.qraw);
+  const size_t eo = (size_t)w * n, oo = (size_t)(Vh + w) * n;  // owned even / odd elements
+  int* abort_flag = a.info + 2;
+  // neighbours of the owned sites; owners of the odd neighbours of the even site
+  int nbE = 0, nbO = 0, nbw = -1;
+  if (tid < 8 * n) {
+    nbE = a.nbr[(size_t)w * 8 + tid / n];
+    nbO = a.nbr[(size_t)(Vh + w) * 8 + tid / n];
+  }
+  if (tid < 8) {
+    nbw = a.nbr[(size_t)w * 8 + tid] - Vh;
+    for (int d = 0; d < tid; ++d)  // wait once per distinct owner
+      if (a.nbr[(size_t)w * 8 + d] - Vh == nbw) nbw = -1;
+  }
+  // epochs continue from what the previous launch left (the same in every line)
+  unsigned epoch = __hip_atomic_load(a.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  unsigned lep = __hip_atomic_load(a.lflags + 32 * w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  int cur = 0;
+  auto mine = [&]() { return a.part + ((size_t)cur * W + w) * a.stride; };
+  auto sync_sum = [&](int nv) -> bool {
+    if (!grid_barrier(a.bar, abort_flag, ++epoch)) return false;
+    if (nv > 0) grid_sum(a.part + (size_t)cur * W * a.stride, a.stride, nv, sv, sh);
+    cur ^= 1;
+    return true;
+  };
+
+  // b_r = b_e - Ytilde_eo b_o, r = b_r, y = 0, ||b_r||^2
+  hop1<S>(a, w, nbE, b, nullptr, b, -1.0, nullptr, nullptr, bm, vin, hp);
+  __syncthreads();
+  {
+    double v[1] = {0.0};
+    if (tid < n) {
+      const cpx<double> x = cvt(bm[tid]);
+      rm[tid] = bm[tid];
+      stc(r + eo + tid, bm[tid]);
+      ym[tid] = tov2<V2>(mk(0.0, 0.0));
+      stc(y + eo + tid, ym[tid]);
+      v[0] += x.r * x.r + x.i * x.i;
+    }
+    block_partial<1>(v, mine(), sh);
+  }
+  if (!sync_sum(1)) return;
+  const double bn2 = sv[0];
+  const double target = a.tol * sqrt(bn2);
+  int iters = 0, status = 0;
+  bool conv = !(bn2 > 0.0) || (!a.fixed && sqrt(bn2) <= target);
+  if (!isfinite(bn2)) {
+    status = WCMG_ENAN;
+    conv = true;
+  }
+  while (!conv && iters < a.maxiter) {
+    // cycle start: z_0 = r, t = Ytilde_oe r
+    hop1<S>(a, Vh + w, nbO, r, nullptr, nullptr, 1.0, nullptr, t, tm, vin, hp);
+    if (tid < n) Zs[tid] = rm[tid];
+    if (!sync_sum(0)) return;
+    int k = 0;
+    for (;;) {
+      // q = D_r z_k = r - Ytilde_eo t on the even site (stored for the odd neighbours);
+      // <q_j, q>, ||q||^2, <q, r> and ||r_k||^2
+      hop1<S>(a, w, nbE, t, rm, nullptr, -1.0, nullptr, qraw, qm, vin, hp);
+      __syncthreads();
+      {
+        const int lane = tid & 63, wave = tid >> 6;
+        for (int j = wave; j < k; j += kPWaves) {
+          const V2* Qj = Qs + (size_t)j * n;
+          double sr = 0.0, si = 0.0;
+          for (int idx = lane; idx < n; idx += 64) {
+            const cpx<double> u = cvt(Qj[idx]), qv = cvt(qm[idx]);
+            sr += u.r * qv.r + u.i * qv.i;
+            si += u.r * qv.i - u.i * qv.r;
+          }
+          sr = wave_sum(sr);
+          si = wave_sum(si);
+          if (lane == 0) {
+            stc(mine() + 2 * j, sr);
+            stc(mine() + 2 * j + 1, si);
+          }
+        }
+        double v[4] = {0.0, 0.0, 0.0, 0.0};
+        if (tid < n) {
+          const cpx<double> qv = cvt(qm[tid]), rr = cvt(rm[tid]);
+          v[0] += qv.r * qv.r + qv.i * qv.i;
+          v[1] += qv.r * rr.r + qv.i * rr.i;
+          v[2] += qv.r * rr.i - qv.i * rr.r;
+          v[3] += rr.r * rr.r + rr.i * rr.i;
+        }
+        block_partial<4>(v, mine() + 2 * k, sh);
+      }
+      if (!sync_sum(2 * k + 4)) return;
+      if (k > 0) {  // r_k, the residual after the previous step
+        const double rn2 = sv[2 * k + 3];
+        if (!isfinite(rn2)) {
+          status = WCMG_ENAN;
+          break;
+        }
+        if (!a.fixed && sqrt(rn2) <= target) break;
+      }
+      if (tid == 0) {
+        double qq = sv[2 * k];
+        for (int j = 0; j < k; ++j)
+          if (sqq[j] > 0.0) qq -= (sv[2 * j] * sv[2 * j] + sv[2 * j + 1] * sv[2 * j + 1]) / sqq[j];
+        salpha[2] = qq;
+        salpha[0] = qq > 0.0 ? sv[2 * k + 1] / qq : 0.0;
+        salpha[1] = qq > 0.0 ? sv[2 * k + 2] / qq : 0.0;
+      }
+      __syncthreads();
+      const double qq = salpha[2];
+      if (!(qq > 0.0) || !isfinite(qq)) {
+        status = isfinite(qq) ? WCMG_EBREAKDOWN : WCMG_ENAN;
+        break;
+      }
+      const cpx<double> alpha = mk(salpha[0], salpha[1]);
+      const int NS = k > 0 ? max(1, min(kPT / n, k)) : 1;
+      const int sl = tid / n, idx = tid - sl * n;
+      cpx<double>* acc = reinterpret_cast<cpx<double>*>(smem);  // [2][kPT]
+      // q_k, z_k by classical Gram-Schmidt (slices of j, added in slice order);
+      // y += alpha z_k, r -= alpha q_k, z_{k+1} = r
+      if (k > 0 && sl < NS) {
+        cpx<double> aq = mk(0.0, 0.0), az = aq;
+        for (int j = sl; j < k; j += NS) {
+          const double d = sqq[j];
+          const cpx<double> cj = d > 0.0 ? mk(sv[2 * j] / d, sv[2 * j + 1] / d) : mk(0.0, 0.0);
+          aq = aq + cmul(cj, cvt(Qs[(size_t)j * n + idx]));
+          az = az + cmul(cj, cvt(Zs[(size_t)j * n + idx]));
+        }
+        acc[tid] = aq;
+        acc[kPT + tid] = az;
+      }
+      __syncthreads();
+      if (tid < n) {
+        cpx<double> q = cvt(qm[tid]), z = cvt(Zs[(size_t)k * n + tid]);
+        if (k > 0) {
+          cpx<double> sq = acc[tid], sz = acc[kPT + tid];
+          for (int u = 1; u < NS; ++u) {
+            sq = sq + acc[u * n + tid];
+            sz = sz + acc[kPT + u * n + tid];
+          }
+          q = q - sq;
+          z = z - sz;
+        }
+        const cpx<double> qs = mk((double)(S)q.r, (double)(S)q.i), zs = mk((double)(S)z.r, (double)(S)z.i);
+        Qs[(size_t)k * n + tid] = tov2<V2>(qs);
+        Zs[(size_t)k * n + tid] = tov2<V2>(zs);
+        const V2 yv = tov2<V2>(cvt(ym[tid]) + cmul(alpha, zs));
+        ym[tid] = yv;
+        stc(y + eo + tid, yv);
+        const V2 rv = tov2<V2>(axpy_round<S>(cvt(rm[tid]), alpha, qs));
+        rm[tid] = rv;
+        if (k + 1 < R) Zs[(size_t)(k + 1) * n + tid] = rv;
+      }
+      // odd site: T_k = Ytilde_oe q - sum_j c_j T_j, t -= alpha T_k
+      hop1<S>(a, Vh + w, nbO, qraw, nullptr, nullptr, 1.0, nullptr, nullptr, Ts + (size_t)k * n, vin, hp);
+      __syncthreads();
+      if (k > 0 && sl < NS) {
+        cpx<double> at = mk(0.0, 0.0);
+        for (int j = sl; j < k; j += NS) {
+          const double d = sqq[j];
+          const cpx<double> cj = d > 0.0 ? mk(sv[2 * j] / d, sv[2 * j + 1] / d) : mk(0.0, 0.0);
+          at = at + cmul(cj, cvt(Ts[(size_t)j * n + idx]));
+        }
+        acc[tid] = at;
+      }
+      __syncthreads();
+      if (tid < n) {
+        cpx<double> tk = cvt(Ts[(size_t)k * n + tid]);
+        if (k > 0) {
+          cpx<double> st = acc[tid];
+          for (int u = 1; u < NS; ++u) st = st + acc[u * n + tid];
+          tk = tk - st;
+        }
+        const cpx<double> tks = mk((double)(S)tk.r, (double)(S)tk.i);
+        Ts[(size_t)k * n + tid] = tov2<V2>(tks);
+        const V2 tv = tov2<V2>(cvt(tm[tid]) - cmul(alpha, tks));
+        tm[tid] = tv;
+        stc(t + oo + tid, tv);
+      }
+      if (tid == 0) sqq[k] = qq;
+      ++k;
+      ++iters;
+      if (k >= R || iters >= a.maxiter) break;
+      // t of the owned odd site is published; the next even hop reads the neighbours' t
+      if (!neighbour_wait(a.lflags, abort_flag, nbw, ++lep)) return;
+    }
+    // y and t complete everywhere
+    if (!sync_sum(0)) return;
+    if (status || a.fixed) break;
+    // true residual r = b_r - D_r y at the end of the cycle
+    hop1<S>(a, Vh + w, nbO, y, nullptr, nullptr, 1.0, nullptr, t, tm, vin, hp);
+    if (!sync_sum(0)) return;
+    hop1<S>(a, w, nbE, t, ym, nullptr, -1.0, nullptr, nullptr, qm, vin, hp);
+    __syncthreads();
+    {
+      double v[1] = {0.0};
+      if (tid < n) {
+        const V2 rv = tov2<V2>(cvt(bm[tid]) - cvt(qm[tid]));
+        rm[tid] = rv;
+        stc(r + eo + tid, rv);
+        const cpx<double> rs = cvt(rv);
+        v[0] += rs.r * rs.r + rs.i * rs.i;
+      }
+      block_partial<1>(v, mine(), sh);
+    }
+    if (!sync_sum(1)) return;
+    const double rn2 = sv[0];
+    if (!isfinite(rn2)) {
+      status = WCMG_ENAN;
+      break;
+    }
+    if (sqrt(rn2) <= target) conv = true;
+  }
+  // c_e = X_ee^-1 y,  c_o = X_oo^-1 (b_o - Ytilde_oe y)   (y is complete after the last grid barrier)
+  site_local<S>(a, w, a.y, a.Xinv, a.c, vin, hp);
+  hop1<S>(a, Vh + w, nbO, y, nullptr, b, -1.0, a.Xinv, reinterpret_cast<V2*>(a.c), nullptr, vin, hp);
+  if (w == 0 && tid == 0) {
+    a.info[0] += iters;
+    if (status) a.info[1] = status;
+  }
+}
+
 }  // namespace
 
 size_t coarse_gcr_persistent_part_doubles() { return 2 * kPMaxRestart + 8; }
@@ -665,6 +1076,22 @@ int coarse_gcr_persistent_grid(int prec, int n, int Vh) {
     HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_coarse_gcr<float>, kPT, shm));
   if (per < 1) return 0;
   return std::min(std::min(ncu, Vh), 256);
+}
+
+// whether one workgroup of the one-site kernel with `bytes` of dynamic LDS fits a compute unit
+static bool site_kernel_fits(int prec, size_t bytes) {
+  const void* k = prec == WCMG_F64 ? reinterpret_cast<const void*>(k_coarse_gcr_site<double>)
+                                   : reinterpret_cast<const void*>(k_coarse_gcr_site<float>);
+  if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  int per = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, kPT, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return per >= 1;
 }
 
 void launch_coarse_gcr_persistent(int prec, const CoarseGcrArgs& g, hipStream_t st) {
@@ -701,7 +1128,20 @@ void launch_coarse_gcr_persistent(int prec, const CoarseGcrArgs& g, hipStream_t 
   a.G = G;
   const size_t cb = prec == WCMG_F64 ? 16 : 8;
   const size_t shm = std::max((size_t)(8 * n + G * n) * cb, (size_t)2 * kPT * 16);
+  a.lflags = reinterpret_cast<unsigned*>(reinterpret_cast<char*>(g.bar) + kPersistLocalOffset);
+  a.sbytes = (int)shm;
   void* args[] = {&a};
+  // one site per workgroup: the scratch, then the basis [3][restart][n] and five site copies
+  const size_t site_shm = shm + (size_t)(3 * g.restart + 5) * n * cb;
+  if (!g.general && g.grid == g.Vh && 8 * n <= kPT && site_kernel_fits(prec, site_shm)) {
+    if (prec == WCMG_F64)
+      HIPCHK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_coarse_gcr_site<double>), dim3(g.grid),
+                                        dim3(kPT), args, (unsigned)site_shm, st));
+    else
+      HIPCHK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_coarse_gcr_site<float>), dim3(g.grid),
+                                        dim3(kPT), args, (unsigned)site_shm, st));
+    return;
+  }
   if (prec == WCMG_F64)
     HIPCHK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_coarse_gcr<double>), dim3(g.grid), dim3(kPT),
                                       args, (unsigned)shm, st));

@@ -245,12 +245,18 @@ void launch_batched_inverse(double* M, int nmat, int n, int* flag, hipStream_t s
 // (<= 256) workgroups.  Buffers: b, c, t [V][n]; y, br, r, qraw [Vh][n];
 // Q, Z [restart][Vh][n]; T [restart][V][n]; part 2 * grid * coarse_gcr_persistent_part_doubles();
 // bar: kPersistCtlBytes of barrier lines (zeroed before the first launch;
-// consistent after every completed launch, zeroed again after an abort); info
-// [3] (at bar + kPersistInfoOffset bytes in the library's use): iterations are
-// added to info[0], a failure code goes to info[1], info[2] is raised when a
-// grid barrier timed out.
-constexpr size_t kPersistCtlBytes = 36 * 1024;
+// consistent after every completed launch, zeroed again after an abort): the
+// grid barrier below 33 KiB, the neighbour flags from kPersistLocalOffset;
+// info [3] (at bar + kPersistInfoOffset bytes in the library's use):
+// iterations are added to info[0], a failure code goes to info[1], info[2] is
+// raised when a barrier wait timed out.  With grid == Vh every workgroup owns
+// one even and one odd site and the one-site kernel runs (Krylov basis in
+// LDS, neighbour flags instead of a second grid barrier per step) unless
+// `general` is set or the basis does not fit; otherwise sites are strided
+// over the workgroups.
+constexpr size_t kPersistCtlBytes = 68 * 1024;
 constexpr size_t kPersistInfoOffset = 34 * 1024;
+constexpr size_t kPersistLocalOffset = 36 * 1024;
 struct CoarseGcrArgs {
   const void* Yt;
   const void* Xinv;
@@ -270,6 +276,7 @@ struct CoarseGcrArgs {
   int* info;
   double tol;
   int Vh, n, restart, maxiter, fixed, grid;
+  int general;  // always the strided kernel
 };
 size_t coarse_gcr_persistent_part_doubles();
 // workgroups of the persistent coarse solve on this device (0: not available)

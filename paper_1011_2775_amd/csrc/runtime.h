@@ -277,7 +277,8 @@ struct PersistWork {
 bool persistent_available(PersistWork& w, int prec, const CoarseLevel& C, int restart);
 // out = approximate Dhat^-1 in (full coarse vectors); t: full scratch, y, r, br: >= half vectors
 void persistent_launch(Ctx& c, PersistWork& w, CoarseLevel& C, int prec, void* out, const void* in, void* t, void* y,
-                       void* r, void* br, double tol, int restart, int maxiter, bool fixed);
+                       void* r, void* br, double tol, int restart, int maxiter, bool fixed,
+                       bool general = false);
 // iterations since the last collect; status (optional) gets the first failure code
 long persistent_collect(Ctx& c, PersistWork& w, int* status = nullptr);
 KrylovResult bicgstab(Ctx& c, int prec, size_t n, const OpFn& A, void* x, const void* b, double tol,

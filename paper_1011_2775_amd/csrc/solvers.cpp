@@ -416,7 +416,7 @@ bool persistent_available(PersistWork& w, int prec, const CoarseLevel& C, int re
 }
 
 void persistent_launch(Ctx& c, PersistWork& w, CoarseLevel& C, int prec, void* out, const void* in, void* t, void* y,
-                       void* r, void* br, double tol, int restart, int maxiter, bool fixed) {
+                       void* r, void* br, double tol, int restart, int maxiter, bool fixed, bool general) {
   const size_t cs = prec == WCMG_F64 ? 16 : 8;
   const size_t hv = (size_t)C.cg.Vh * C.cg.n;
   restart = std::min(restart, std::max(1, maxiter));
@@ -454,6 +454,7 @@ void persistent_launch(Ctx& c, PersistWork& w, CoarseLevel& C, int prec, void* o
   a.maxiter = maxiter;
   a.fixed = fixed ? 1 : 0;
   a.grid = w.grid;
+  a.general = general ? 1 : 0;
   launch_coarse_gcr_persistent(prec, a, c.st);
   w.pending = true;
 }
@@ -494,7 +495,7 @@ struct MGSolver {
     GcrSpaceB bspace{};         // lockstep space for batches
     int batch = 1;              // right-hand sides the buffers hold
     long calls = 0, iters = 0;
-    PersistWork pw;             // the coarsest GCR as one cooperative launch (coarse_launch 0)
+    PersistWork pw;             // the coarsest GCR as one cooperative launch (coarse_launch 0, 2)
     DBuf d_in, d_out, d_br, d_y;  // FP64 vectors of the deflated coarsest solve (coarsest 2)
     GcrSpace space64{};
   };
@@ -593,7 +594,7 @@ struct MGSolver {
   // capture (cycle_mode 2), and only where the device runs the whole grid at once
   bool persistent_ok(int li) {
     const wcmg_mg_params& p = L.params;
-    if (p.coarse_launch != 0 || p.cycle_mode == 2) return false;
+    if (p.coarse_launch == 1 || p.cycle_mode == 2) return false;
     return persistent_available(lv[li].pw, cp, *L.levels[li], p.restart[li]);
   }
 
@@ -604,7 +605,7 @@ struct MGSolver {
     hipEvent_t e = nullptr;
     if (c.timer.on) c.timer.begin(id, &e);
     persistent_launch(c, V.pw, *L.levels[li], cp, out, in, V.rfull.p, V.cy.p, V.res.p, V.cbr.p, p.tol[li],
-                      p.restart[li], p.max_iter[li], fixed());
+                      p.restart[li], p.max_iter[li], fixed(), p.coarse_launch == 2);
     if (e) c.timer.end(id, e);
   }
 

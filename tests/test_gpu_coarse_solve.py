@@ -14,9 +14,14 @@ assembled (so the test pins the solve, not the coarse build):
   different orders), and the two solutions agree;
 * the cycle's own setting (tol 0.1), ragged site counts (coarse sites not
   a multiple of the workgroup count), restart 1 and 64, a zero source;
+* with at most one even site per workgroup (32 and 512 coarse sites)
+  launch 0 runs the one-site kernel (basis in LDS, neighbour waits); it
+  must give bitwise the solution and the step count of the strided kernel
+  (launch 2), over several restart cycles, in FP64 and FP32;
 * multigrid solves with coarse_launch 0 and 1 reach 1e-10 (oracle D) in
-  outer iteration counts within 1 of each other, and the persistent kernel
-  is the one that ran (its timer counts launches).
+  outer iteration counts within 1 of each other, coarse_launch 2 gives
+  bitwise the solution of 0, and the persistent kernel is the one that ran
+  (its timer counts launches).
 """
 import numpy as np
 import pytest
@@ -128,6 +133,22 @@ def test_restart_extremes(case, restart):
     assert abs(sp["iters"] - ss["iters"]) <= max(2, ss["iters"] // 50)
 
 
+@pytest.mark.parametrize("prec,tol,restart", [("F64", 1e-9, 8), ("F64", 0.1, 30), ("F32", 1e-4, 6), ("F32", 0.2, 30)])
+def test_one_site_kernel_matches_strided(case, prec, tol, restart):
+    ctx, cop = case
+    b = rhs(cop, 6)
+    bt = torch.from_numpy(b).cuda()
+    xo, so = ctx.coarse_solve(bt, prec=getattr(w, prec), tol=tol, max_iter=3000, restart=restart, launch=0)
+    xg, sg = ctx.coarse_solve(bt, prec=getattr(w, prec), tol=tol, max_iter=3000, restart=restart, launch=2)
+    print("%s tol %g restart %d: iters %d / %d" % (prec, tol, restart, so["iters"], sg["iters"]), flush=True)
+    assert so["status"] == "OK" and sg["status"] == "OK"
+    assert so["iters"] == sg["iters"]
+    assert torch.equal(xo, xg)
+    br = cop.reduced_source(b)
+    assert full_res(cop, xo.cpu().numpy(), b) <= 1.01 * tol * np.linalg.norm(br) / np.linalg.norm(b) + \
+        (1e-5 if prec == "F32" else 0.0)
+
+
 def test_zero_source(case):
     ctx, cop = case
     bt = torch.zeros(cop.shape, dtype=torch.complex128, device="cuda")
@@ -156,8 +177,8 @@ def test_multigrid_with_persistent_coarse_solve(nlevels):
     vecs = [ctx.get_null_vectors(level=l) for l in range(nlevels)]
     b = canon(inputs.z2_source(dims, 3200), (1,) + tuple(reversed(dims)) + (4, 3))
     op = WilsonClover(dims, U, m0, csw)
-    iters = {}
-    for launch in (0, 1):
+    iters, sols = {}, {}
+    for launch in (0, 1, 2):
         ctx.set_mg_params(w.default_params(seed=5, coarse_launch=launch, **kw))
         for l in range(nlevels):
             ctx.set_null_vectors(vecs[l], level=l)
@@ -172,9 +193,11 @@ def test_multigrid_with_persistent_coarse_solve(nlevels):
         print("launch %d: outer %d, inner %s, res %.2e, persistent launches %d"
               % (launch, st[0]["iters"], st[0]["inner_iters"][:nlevels], res, n_persist), flush=True)
         assert res <= 1.0000001e-10
-        assert (n_persist > 0) == (launch == 0)
+        assert (n_persist > 0) == (launch != 1)
         iters[launch] = st[0]
+        sols[launch] = x
     assert abs(iters[0]["iters"] - iters[1]["iters"]) <= 1
+    assert iters[0]["iters"] == iters[2]["iters"] and torch.equal(sols[0], sols[2])
     last = nlevels - 1
     assert abs(iters[0]["inner_iters"][last] - iters[1]["inner_iters"][last]) <= \
         0.1 * iters[1]["inner_iters"][last] + 1
