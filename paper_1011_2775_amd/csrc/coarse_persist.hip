@@ -198,6 +198,20 @@ __device__ __forceinline__ void block_partial(double (&v)[NR], double* part, dou
   __syncthreads();
 }
 
+// block_partial when every nonzero value is in wavefront 0 (the other
+// wavefronts would add exact zeros): lane 0 stores the wavefront sums, with no
+// LDS round and no block barrier
+template <int NR>
+__device__ __forceinline__ void wave0_partial(double (&v)[NR], double* part) {
+  if (threadIdx.x < 64) {
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      const double s = wave_sum(v[k]);
+      if (threadIdx.x == 0) stc(part + k, s);
+    }
+  }
+}
+
 // out[v] (LDS) = sum over workgroups of part[w * stride + v], v < nv: TPV
 // threads per value (a power of two) each add a fixed strided subset of the
 // workgroups, then a fixed shuffle tree (and, past one wavefront, LDS) adds
@@ -208,8 +222,19 @@ __device__ void grid_sum(const double* part, int stride, int nv, double* out, do
   while (tpv * 2 * nv <= (int)blockDim.x && tpv < (int)gridDim.x) tpv *= 2;
   const int t = threadIdx.x, v = t / tpv, j = t - v * tpv;
   double s = 0.0;
-  if (v < nv)
-    for (int b = j; b < (int)gridDim.x; b += tpv) s += ldc(part + (size_t)b * stride + v);
+  if (v < nv) {
+    // eight loads in flight, then added in workgroup order
+    const int W = gridDim.x;
+    int b = j;
+    for (; b + 7 * tpv < W; b += 8 * tpv) {
+      double p[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) p[u] = ldc(part + (size_t)(b + u * tpv) * stride + v);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += p[u];
+    }
+    for (; b < W; b += tpv) s += ldc(part + (size_t)b * stride + v);
+  }
   const int width = tpv < 64 ? tpv : 64;
   for (int off = width >> 1; off > 0; off >>= 1) s += __shfl_down(s, off, width);
   if (tpv <= 64) {
@@ -257,7 +282,16 @@ struct PArgs {
   double tol;
   int Vh, n, restart, maxiter, fixed, G, stride;
   int sbytes;  // one-site kernel: LDS bytes before the Krylov basis
+  int pl;      // one-site kernel: hop matrix column rounds staged in LDS
 };
+
+// largest power of two below G (0 for G = 1): first step of the tree that adds
+// the G column-group partials
+__device__ __forceinline__ int tree_top(int G) {
+  int h = 1;
+  while (2 * h < G) h *= 2;
+  return G > 1 ? h : 0;
+}
 
 // Rows of M v for one site (M: n x ncols column-major, v in LDS): lanes with
 // column group 0 return rows 2rp, 2rp + 1; every lane of the block must call.
@@ -280,9 +314,9 @@ __device__ __forceinline__ void site_matvec(const V2* M, const cpx<C>* v, int n,
     part[g * n + 2 * rp] = a0;
     part[g * n + 2 * rp + 1] = a1;
   }
-  for (int h = G >> 1; h > 0; h >>= 1) {
+  for (int h = tree_top(G); h > 0; h >>= 1) {
     __syncthreads();
-    if (g < h) {
+    if (g < h && g + h < G) {
       part[g * n + 2 * rp] = part[g * n + 2 * rp] + part[(g + h) * n + 2 * rp];
       part[g * n + 2 * rp + 1] = part[g * n + 2 * rp + 1] + part[(g + h) * n + 2 * rp + 1];
     }
@@ -720,29 +754,38 @@ __device__ __forceinline__ V2 tov2(cpx<double> c) {
 // thread t < 8n gathers element t % n of its neighbour nb (the t / n-th of c);
 // xd is an LDS copy of the site's elements (xdl) or a global field (xdg) or
 // absent; the result goes to a global field (outg, coherent stores) and/or an
-// LDS copy (outl).  The first PF columns of the thread's share of the hop
-// matrix are loaded before the gather, so the two latencies overlap; the sums
-// run in the order of site_matvec.
+// LDS copy (outl).  The first a.pl columns of every thread's share of the
+// hop matrix go straight to LDS (global_load_lds, no registers) before the
+// gather is issued, so the matrix stream and the gather latency overlap; the
+// rest is loaded as in site_matvec, and the sums run in its order.
 template <typename S>
 __device__ void hop1(const PArgs& a, int c, int nb, const typename Vec2<S>::T* in, const typename Vec2<S>::T* xdl,
                      const typename Vec2<S>::T* xdg, double coeff, const void* Xl, typename Vec2<S>::T* outg,
                      typename Vec2<S>::T* outl, cpx<typename Compute<S>::T>* vin,
-                     cpx<typename Compute<S>::T>* part) {
+                     cpx<typename Compute<S>::T>* part, char* pre) {
   using C = typename Compute<S>::T;
   using V2 = typename Vec2<S>::T;
-  constexpr int PF = sizeof(S) == 8 ? 1 : 2;
-  const int n = a.n, G = a.G, R2 = n >> 1, ncols = 8 * n;
+  constexpr int NCH = sizeof(S) == 8 ? 2 : 1;  // 16-byte pieces of a thread's two entries of a column
+  const int n = a.n, G = a.G, R2 = n >> 1, ncols = 8 * n, PL = a.pl;
   const int tid = threadIdx.x, g = tid / R2, rp = tid - g * R2;
+  const int lane = tid & 63, wv = tid >> 6, NW = (G * R2 + 63) >> 6;
   const V2* M = reinterpret_cast<const V2*>(a.Yt) + (size_t)c * 8 * n * n + 2 * rp;
-  cpx<C> p0[PF], p1[PF];
+  __syncthreads();  // the previous task is done with vin, part and the prefetch area
   if (g < G) {
-#pragma unroll
-    for (int u = 0; u < PF; ++u) {
+    // piece ch of column round u of wavefront wv: 1 KiB at pre + ((u NCH + ch) NW + wv) KiB, lane order
+    for (int u = 0; u < PL; ++u) {
       const int col = g + u * G;
-      if (col < ncols) ld2(M + (size_t)col * n, p0[u], p1[u]);
+      if (col < ncols) {
+        const char* src = reinterpret_cast<const char*>(M + (size_t)col * n);
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch)
+          __builtin_amdgcn_global_load_lds(
+              src + 16 * ch,
+              (__attribute__((address_space(3))) void*)(pre + ((size_t)((u * NCH + ch) * NW + wv) << 10)), 16, 0,
+              0);
+      }
     }
   }
-  __syncthreads();  // the previous task is done with vin and part
   if (tid < ncols) {
     const V2 v = ldc(in + (size_t)nb * n + (tid - (tid / n) * n));
     vin[tid] = mk((C)v.x, (C)v.y);
@@ -750,17 +793,27 @@ __device__ void hop1(const PArgs& a, int c, int nb, const typename Vec2<S>::T* i
   __syncthreads();
   if (g < G) {
     cpx<C> a0 = mk((C)0, (C)0), a1 = a0;
-#pragma unroll
-    for (int u = 0; u < PF; ++u) {
+    // this thread's own pieces: complete once its wavefront's loads have returned
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    for (int u = 0; u < PL; ++u) {
       const int col = g + u * G;
       if (col < ncols) {
+        cpx<C> e0, e1;
+        const V2* q = reinterpret_cast<const V2*>(pre + ((size_t)(u * NCH * NW + wv) << 10) + 16 * lane);
+        if (NCH == 1) {
+          ld2(q, e0, e1);
+        } else {
+          const V2* q1 = reinterpret_cast<const V2*>(pre + ((size_t)((u * NCH + 1) * NW + wv) << 10) + 16 * lane);
+          e0 = mk((C)q[0].x, (C)q[0].y);
+          e1 = mk((C)q1[0].x, (C)q1[0].y);
+        }
         const cpx<C> x = vin[col];
-        cfma(a0, p0[u], x);
-        cfma(a1, p1[u], x);
+        cfma(a0, e0, x);
+        cfma(a1, e1, x);
       }
     }
 #pragma unroll 8
-    for (int col = g + PF * G; col < ncols; col += G) {
+    for (int col = g + PL * G; col < ncols; col += G) {
       cpx<C> e0, e1;
       ld2(M + (size_t)col * n, e0, e1);
       const cpx<C> x = vin[col];
@@ -770,9 +823,9 @@ __device__ void hop1(const PArgs& a, int c, int nb, const typename Vec2<S>::T* i
     part[g * n + 2 * rp] = a0;
     part[g * n + 2 * rp + 1] = a1;
   }
-  for (int h = G >> 1; h > 0; h >>= 1) {
+  for (int h = tree_top(G); h > 0; h >>= 1) {
     __syncthreads();
-    if (g < h) {
+    if (g < h && g + h < G) {
       part[g * n + 2 * rp] = part[g * n + 2 * rp] + part[(g + h) * n + 2 * rp];
       part[g * n + 2 * rp + 1] = part[g * n + 2 * rp + 1] + part[(g + h) * n + 2 * rp + 1];
     }
@@ -820,6 +873,7 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
   const int n = a.n, Vh = a.Vh, R = a.restart, w = blockIdx.x, W = gridDim.x, tid = threadIdx.x;
   cpx<C>* vin = reinterpret_cast<cpx<C>*>(smem);  // 8n
   cpx<C>* hp = vin + 8 * n;                       // G * n
+  char* pre = reinterpret_cast<char*>(hp + (size_t)a.G * n);  // hop matrix columns (a.pl rounds)
   V2* Qs = reinterpret_cast<V2*>(smem + a.sbytes);  // [R][n] q_j (even site)
   V2* Zs = Qs + (size_t)R * n;                      // [R][n] z_j (even site)
   V2* Ts = Zs + (size_t)R * n;                      // [R][n] T_j (odd site)
@@ -863,7 +917,7 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
   };
 
   // b_r = b_e - Ytilde_eo b_o, r = b_r, y = 0, ||b_r||^2
-  hop1<S>(a, w, nbE, b, nullptr, b, -1.0, nullptr, nullptr, bm, vin, hp);
+  hop1<S>(a, w, nbE, b, nullptr, b, -1.0, nullptr, nullptr, bm, vin, hp, pre);
   __syncthreads();
   {
     double v[1] = {0.0};
@@ -888,14 +942,14 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
   }
   while (!conv && iters < a.maxiter) {
     // cycle start: z_0 = r, t = Ytilde_oe r
-    hop1<S>(a, Vh + w, nbO, r, nullptr, nullptr, 1.0, nullptr, t, tm, vin, hp);
+    hop1<S>(a, Vh + w, nbO, r, nullptr, nullptr, 1.0, nullptr, t, tm, vin, hp, pre);
     if (tid < n) Zs[tid] = rm[tid];
     if (!sync_sum(0)) return;
     int k = 0;
     for (;;) {
       // q = D_r z_k = r - Ytilde_eo t on the even site (stored for the odd neighbours);
       // <q_j, q>, ||q||^2, <q, r> and ||r_k||^2
-      hop1<S>(a, w, nbE, t, rm, nullptr, -1.0, nullptr, qraw, qm, vin, hp);
+      hop1<S>(a, w, nbE, t, rm, nullptr, -1.0, nullptr, qraw, qm, vin, hp, pre);
       __syncthreads();
       {
         const int lane = tid & 63, wave = tid >> 6;
@@ -922,7 +976,10 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
           v[2] += qv.r * rr.i - qv.i * rr.r;
           v[3] += rr.r * rr.r + rr.i * rr.i;
         }
-        block_partial<4>(v, mine() + 2 * k, sh);
+        if (n <= 64)
+          wave0_partial<4>(v, mine() + 2 * k);
+        else
+          block_partial<4>(v, mine() + 2 * k, sh);
       }
       if (!sync_sum(2 * k + 4)) return;
       if (k > 0) {  // r_k, the residual after the previous step
@@ -987,7 +1044,7 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
         if (k + 1 < R) Zs[(size_t)(k + 1) * n + tid] = rv;
       }
       // odd site: T_k = Ytilde_oe q - sum_j c_j T_j, t -= alpha T_k
-      hop1<S>(a, Vh + w, nbO, qraw, nullptr, nullptr, 1.0, nullptr, nullptr, Ts + (size_t)k * n, vin, hp);
+      hop1<S>(a, Vh + w, nbO, qraw, nullptr, nullptr, 1.0, nullptr, nullptr, Ts + (size_t)k * n, vin, hp, pre);
       __syncthreads();
       if (k > 0 && sl < NS) {
         cpx<double> at = mk(0.0, 0.0);
@@ -1023,9 +1080,9 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
     if (!sync_sum(0)) return;
     if (status || a.fixed) break;
     // true residual r = b_r - D_r y at the end of the cycle
-    hop1<S>(a, Vh + w, nbO, y, nullptr, nullptr, 1.0, nullptr, t, tm, vin, hp);
+    hop1<S>(a, Vh + w, nbO, y, nullptr, nullptr, 1.0, nullptr, t, tm, vin, hp, pre);
     if (!sync_sum(0)) return;
-    hop1<S>(a, w, nbE, t, ym, nullptr, -1.0, nullptr, nullptr, qm, vin, hp);
+    hop1<S>(a, w, nbE, t, ym, nullptr, -1.0, nullptr, nullptr, qm, vin, hp, pre);
     __syncthreads();
     {
       double v[1] = {0.0};
@@ -1048,7 +1105,7 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
   }
   // c_e = X_ee^-1 y,  c_o = X_oo^-1 (b_o - Ytilde_oe y)   (y is complete after the last grid barrier)
   site_local<S>(a, w, a.y, a.Xinv, a.c, vin, hp);
-  hop1<S>(a, Vh + w, nbO, y, nullptr, b, -1.0, a.Xinv, reinterpret_cast<V2*>(a.c), nullptr, vin, hp);
+  hop1<S>(a, Vh + w, nbO, y, nullptr, b, -1.0, a.Xinv, reinterpret_cast<V2*>(a.c), nullptr, vin, hp, pre);
   if (w == 0 && tid == 0) {
     a.info[0] += iters;
     if (status) a.info[1] = status;
@@ -1059,6 +1116,15 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
 
 size_t coarse_gcr_persistent_part_doubles() { return 2 * kPMaxRestart + 8; }
 
+// column groups of the hop: a power of two (at most 64) with G * n / 2 <= kPT (a
+// power of two measured faster than using every thread, e.g. 32 rather than 42
+// groups for n = 48)
+static int persist_groups(int n) {
+  int G = 1;
+  while (G < 64 && 2 * G * (n / 2) <= kPT) G *= 2;
+  return G;
+}
+
 int coarse_gcr_persistent_grid(int prec, int n, int Vh) {
   int dev = 0, ncu = 0, coop = 0;
   HIPCHK(hipGetDevice(&dev));
@@ -1066,8 +1132,7 @@ int coarse_gcr_persistent_grid(int prec, int n, int Vh) {
   HIPCHK(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
   if (!coop || n % 2 || n > 256 || Vh <= 0) return 0;
   const size_t cb = prec == WCMG_F64 ? 16 : 8;
-  int R2 = n / 2, G = 1;
-  while (G < 64 && 2 * G * R2 <= kPT) G *= 2;
+  const int G = persist_groups(n);
   const size_t shm = std::max((size_t)(8 * n + G * n) * cb, (size_t)2 * kPT * 16);
   int per = 0;
   if (prec == WCMG_F64)
@@ -1123,17 +1188,28 @@ void launch_coarse_gcr_persistent(int prec, const CoarseGcrArgs& g, hipStream_t 
   a.maxiter = g.maxiter;
   a.fixed = g.fixed;
   a.stride = (int)coarse_gcr_persistent_part_doubles();
-  int R2 = n / 2, G = 1;
-  while (G < 64 && 2 * G * R2 <= kPT) G *= 2;
+  const int G = persist_groups(n);
   a.G = G;
   const size_t cb = prec == WCMG_F64 ? 16 : 8;
   const size_t shm = std::max((size_t)(8 * n + G * n) * cb, (size_t)2 * kPT * 16);
   a.lflags = reinterpret_cast<unsigned*>(reinterpret_cast<char*>(g.bar) + kPersistLocalOffset);
   a.sbytes = (int)shm;
   void* args[] = {&a};
-  // one site per workgroup: the scratch, then the basis [3][restart][n] and five site copies
-  const size_t site_shm = shm + (size_t)(3 * g.restart + 5) * n * cb;
-  if (!g.general && g.grid == g.Vh && 8 * n <= kPT && site_kernel_fits(prec, site_shm)) {
+  // one site per workgroup: vin, the column-group partials and as many rounds of
+  // hop matrix columns as fit, overlapped by the Gram-Schmidt slice sums; then
+  // the basis [3][restart][n] and five site copies
+  const size_t basis = (size_t)(3 * g.restart + 5) * n * cb;
+  const size_t hopb = (size_t)(8 * n + G * n) * cb;
+  const size_t round = (prec == WCMG_F64 ? 2 : 1) * (size_t)((G * (n / 2) + 63) / 64) * 1024;
+  const size_t lds_cap = 160 * 1024 - 4096;  // minus the kernel's static LDS, with margin
+  const int rounds = (8 * n + G - 1) / G;
+  int pl = 0;
+  if (lds_cap > basis + hopb) pl = (int)std::min<size_t>(rounds, (lds_cap - basis - hopb) / round);
+  const size_t sb = std::max(hopb + (size_t)pl * round, (size_t)2 * kPT * 16);
+  const size_t site_shm = sb + basis;
+  if (!g.general && g.grid == g.Vh && 8 * n <= kPT && site_shm <= lds_cap && site_kernel_fits(prec, site_shm)) {
+    a.sbytes = (int)sb;
+    a.pl = pl;
     if (prec == WCMG_F64)
       HIPCHK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_coarse_gcr_site<double>), dim3(g.grid),
                                         dim3(kPT), args, (unsigned)site_shm, st));
