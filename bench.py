@@ -81,8 +81,9 @@ def kernel_table(ctxs, vh, coarse_sites_h, coarse_n, coarse_steps=0):
             bytes_launch = dslash_bytes_per_site(prec, diag, postinv) * vh
             flops = dslash_flops_per_site(diag, postinv) * vh
         elif kid == 28:
-            # the whole coarse solve in one launch: bytes and flops of its GCR steps
-            name = "k_coarse_gcr<float>"
+            # the whole coarse solve in one launch: bytes and flops of its GCR steps (the
+            # one-site kernel when every workgroup of the 256 owns one even site)
+            name = "k_coarse_gcr_site<float>" if coarse_sites_h <= 256 else "k_coarse_gcr<float>"
             steps = coarse_steps / n
             bytes_launch = steps * coarse_step_bytes(coarse_sites_h, coarse_n)
             flops = steps * 2 * coarse_sites_h * 8 * coarse_n * coarse_n * 8
@@ -101,6 +102,7 @@ def kernel_table(ctxs, vh, coarse_sites_h, coarse_n, coarse_steps=0):
 
 # kernel -> source files whose text the traffic counters were taken with
 KERNEL_SOURCES = {"k_coarse_gcr<float>": ["coarse_persist.hip"],
+                  "k_coarse_gcr_site<float>": ["coarse_persist.hip"],
                   "k_coarse_hop<float, 1>": ["coarse.hip"]}
 for _p in ("double", "float", "__half"):
     for _k in ("0,true", "1,false"):

@@ -755,9 +755,10 @@ __device__ __forceinline__ V2 tov2(cpx<double> c) {
 // xd is an LDS copy of the site's elements (xdl) or a global field (xdg) or
 // absent; the result goes to a global field (outg, coherent stores) and/or an
 // LDS copy (outl).  The first a.pl columns of every thread's share of the
-// hop matrix go straight to LDS (global_load_lds, no registers) before the
-// gather is issued, so the matrix stream and the gather latency overlap; the
-// rest is loaded as in site_matvec, and the sums run in its order.
+// hop matrix go straight to LDS (global_load_lds, no registers) and the next
+// few into registers before the gather is issued, so the matrix stream and the
+// gather latency overlap; the rest is loaded as in site_matvec, and the sums
+// run in its order.
 template <typename S>
 __device__ void hop1(const PArgs& a, int c, int nb, const typename Vec2<S>::T* in, const typename Vec2<S>::T* xdl,
                      const typename Vec2<S>::T* xdg, double coeff, const void* Xl, typename Vec2<S>::T* outg,
@@ -767,7 +768,12 @@ __device__ void hop1(const PArgs& a, int c, int nb, const typename Vec2<S>::T* i
   using V2 = typename Vec2<S>::T;
   constexpr int NCH = sizeof(S) == 8 ? 2 : 1;  // 16-byte pieces of a thread's two entries of a column
   const int n = a.n, G = a.G, R2 = n >> 1, ncols = 8 * n, PL = a.pl;
-  const int tid = threadIdx.x, g = tid / R2, rp = tid - g * R2;
+  // the thread index passes through an empty asm, so that the addresses derived
+  // from it are formed here and not kept live across the whole solve (register
+  // pressure: the hop is inlined at seven call sites)
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  const int g = tid / R2, rp = tid - g * R2;
   const int lane = tid & 63, wv = tid >> 6, NW = (G * R2 + 63) >> 6;
   const V2* M = reinterpret_cast<const V2*>(a.Yt) + (size_t)c * 8 * n * n + 2 * rp;
   __syncthreads();  // the previous task is done with vin, part and the prefetch area
@@ -784,6 +790,16 @@ __device__ void hop1(const PArgs& a, int c, int nb, const typename Vec2<S>::T* i
               (__attribute__((address_space(3))) void*)(pre + ((size_t)((u * NCH + ch) * NW + wv) << 10)), 16, 0,
               0);
       }
+    }
+  }
+  // the next PR rounds into registers, also before the gather
+  constexpr int PR = sizeof(S) == 8 ? 1 : 4;
+  cpx<C> r0[PR], r1[PR];
+  if (g < G) {
+#pragma unroll
+    for (int u = 0; u < PR; ++u) {
+      const int col = g + (PL + u) * G;
+      if (col < ncols) ld2(M + (size_t)col * n, r0[u], r1[u]);
     }
   }
   if (tid < ncols) {
@@ -812,8 +828,17 @@ __device__ void hop1(const PArgs& a, int c, int nb, const typename Vec2<S>::T* i
         cfma(a1, e1, x);
       }
     }
+#pragma unroll
+    for (int u = 0; u < PR; ++u) {
+      const int col = g + (PL + u) * G;
+      if (col < ncols) {
+        const cpx<C> x = vin[col];
+        cfma(a0, r0[u], x);
+        cfma(a1, r1[u], x);
+      }
+    }
 #pragma unroll 8
-    for (int col = g + PL * G; col < ncols; col += G) {
+    for (int col = g + (PL + PR) * G; col < ncols; col += G) {
       cpx<C> e0, e1;
       ld2(M + (size_t)col * n, e0, e1);
       const cpx<C> x = vin[col];
@@ -886,6 +911,8 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
   __shared__ double sqq[kPMaxRestart];         // ||q_j||^2
   __shared__ double sh[4 * kPWaves];
   __shared__ double salpha[3];
+  __shared__ cpx<double> scj[kPMaxRestart];  // Gram-Schmidt coefficients of the step
+  __shared__ double sterm[kPMaxRestart];
   const V2* b = reinterpret_cast<const V2*>(a.b);
   V2* y = reinterpret_cast<V2*>(a.y);
   V2* r = reinterpret_cast<V2*>(a.r);
@@ -990,10 +1017,18 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
         }
         if (!a.fixed && sqrt(rn2) <= target) break;
       }
+      // per j < k in parallel: c_j = <q_j, q> / ||q_j||^2 and |<q_j, q>|^2 / ||q_j||^2
+      // (the same divisions as the strided kernel, done once instead of per thread)
+      if (tid < k) {
+        const double d = sqq[tid];
+        scj[tid] = d > 0.0 ? mk(sv[2 * tid] / d, sv[2 * tid + 1] / d) : mk(0.0, 0.0);
+        sterm[tid] = d > 0.0 ? (sv[2 * tid] * sv[2 * tid] + sv[2 * tid + 1] * sv[2 * tid + 1]) / d : 0.0;
+      }
+      __syncthreads();
       if (tid == 0) {
         double qq = sv[2 * k];
         for (int j = 0; j < k; ++j)
-          if (sqq[j] > 0.0) qq -= (sv[2 * j] * sv[2 * j] + sv[2 * j + 1] * sv[2 * j + 1]) / sqq[j];
+          if (sqq[j] > 0.0) qq -= sterm[j];
         salpha[2] = qq;
         salpha[0] = qq > 0.0 ? sv[2 * k + 1] / qq : 0.0;
         salpha[1] = qq > 0.0 ? sv[2 * k + 2] / qq : 0.0;
@@ -1013,8 +1048,7 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
       if (k > 0 && sl < NS) {
         cpx<double> aq = mk(0.0, 0.0), az = aq;
         for (int j = sl; j < k; j += NS) {
-          const double d = sqq[j];
-          const cpx<double> cj = d > 0.0 ? mk(sv[2 * j] / d, sv[2 * j + 1] / d) : mk(0.0, 0.0);
+          const cpx<double> cj = scj[j];
           aq = aq + cmul(cj, cvt(Qs[(size_t)j * n + idx]));
           az = az + cmul(cj, cvt(Zs[(size_t)j * n + idx]));
         }
@@ -1049,8 +1083,7 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
       if (k > 0 && sl < NS) {
         cpx<double> at = mk(0.0, 0.0);
         for (int j = sl; j < k; j += NS) {
-          const double d = sqq[j];
-          const cpx<double> cj = d > 0.0 ? mk(sv[2 * j] / d, sv[2 * j + 1] / d) : mk(0.0, 0.0);
+          const cpx<double> cj = scj[j];
           at = at + cmul(cj, cvt(Ts[(size_t)j * n + idx]));
         }
         acc[tid] = at;
