@@ -102,9 +102,21 @@ __device__ __forceinline__ void block_reduce(double (&v)[NR], const RedOut& o, i
   while (tpv * 2 * nvalid <= kThreads && tpv < nb) tpv *= 2;
   const int t = threadIdx.x, vv = t / tpv, j = t - vv * tpv;
   double s = 0.0;
-  if (vv < nvalid)
-    for (int b = j; b < nb; b += tpv)
+  if (vv < nvalid) {
+    // eight loads in flight, then added in block order
+    int b = j;
+    for (; b + 7 * tpv < nb; b += 8 * tpv) {
+      double p[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        p[u] = __hip_atomic_load(o.partial + (size_t)(b + u * tpv) * NR + vv, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += p[u];
+    }
+    for (; b < nb; b += tpv)
       s += __hip_atomic_load(o.partial + (size_t)b * NR + vv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
   const int width = tpv < 64 ? tpv : 64;
   for (int off = width >> 1; off > 0; off >>= 1) s += __shfl_down(s, off, width);
   if (tpv > 64) {

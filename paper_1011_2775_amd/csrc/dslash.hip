@@ -22,6 +22,7 @@
 #include "wcmg_internal.h"
 #include "kernels.h"
 #include "hop_core.h"
+#include "blas_common.h"
 
 namespace wcmg {
 
@@ -208,8 +209,10 @@ __device__ __forceinline__ void clover_multi(const void* clov, int Vh, int p, in
 
 // S: spinor storage, G: link and clover storage (G = S, or FP16 fields with
 // FP32 spinors); lb: the lattice's logical block
-template <typename S, typename G, int DIAG, bool POSTINV, int NR, bool STREAM = false>
-__device__ __forceinline__ void dslash_site(const DslashArgs& a, int lb) {
+// RED (DIAG = 1, one right-hand side): also add <out, x> and ||out||^2 of the
+// site, in FP64 from the stored values, to red[0..3)
+template <typename S, typename G, int DIAG, bool POSTINV, int NR, bool STREAM = false, bool RED = false>
+__device__ __forceinline__ void dslash_site(const DslashArgs& a, int lb, double* red = nullptr) {
   using C = typename Compute<S>::T;
   const int i = lb * blockDim.x + threadIdx.x;
   if (lb >= a.nblocks || i >= a.g.Vh) return;
@@ -261,6 +264,16 @@ __device__ __forceinline__ void dslash_site(const DslashArgs& a, int lb) {
       for (int r = 0; r < NR; ++r)
 #pragma unroll
         for (int k = 0; k < 12; ++k) out[r][k] = out[r][k] + xv[r][k];
+      if constexpr (RED) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+          const double orr = (double)(S)out[0][k].r, oi = (double)(S)out[0][k].i;
+          const double xr = (double)xv[0][k].r, xi = (double)xv[0][k].i;
+          red[0] += orr * xr + oi * xi;
+          red[1] += orr * xi - oi * xr;
+          red[2] += orr * orr + oi * oi;
+        }
+      }
     }
   }
 #pragma unroll
@@ -272,6 +285,17 @@ __device__ __forceinline__ void dslash_site(const DslashArgs& a, int lb) {
 template <typename S, typename G, int DIAG, bool POSTINV, int NR, bool STREAM>
 __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a) {
   dslash_site<S, G, DIAG, POSTINV, NR, STREAM>(a, xcd_block(a.nblocks));
+}
+
+// The DIAG = 1 hop of D_r with the minimal-residual sums of the smoother
+// fused in: out = x + coeff H in, and <out, x>, ||out||^2 reduced into o in
+// the same launch (every block, padding blocks included, takes part in the
+// reduction; the last to arrive finishes it).
+template <typename S, typename G, bool STREAM>
+__global__ void __launch_bounds__(256) dslash_red_kernel(DslashArgs a, RedOut o) {
+  double v[3] = {0.0, 0.0, 0.0};
+  dslash_site<S, G, 1, false, 1, STREAM, true>(a, xcd_block(a.nblocks), v);
+  blas_detail::block_reduce<3>(v, o);
 }
 
 // Several lattices of different volumes in one launch: a work list of block
@@ -300,6 +324,52 @@ __global__ void __launch_bounds__(256) clover_kernel(void* out, const void* in, 
 #pragma unroll
   for (int r = 0; r < NR; ++r)
     if (r < nr) SpinorIO<S>::store(const_cast<void*>(rhs_ptr<S>(out, rstride, g0 + r)), Vh, i, o[r]);
+}
+
+// The smoother's minimal-residual update of the previous step fused into the
+// first kernel of the next D_r: with a = coef[0..2) / coef[2] (0 when
+// coef[2] is not positive), per site e += a r, r -= a Ar (FP64 arithmetic on
+// the stored values, rounded back to storage), then out = A_ee^-1 r.
+template <typename S, typename G>
+__global__ void __launch_bounds__(256) clover_mr_kernel(void* out, void* r, void* e, const void* Ar,
+                                                        const double* coef, const void* clov, int Vh, int p) {
+  using C = typename Compute<S>::T;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Vh) return;
+  const double d = coef[2];
+  const cpx<double> a = d > 0.0 ? mk(coef[0] / d, coef[1] / d) : mk(0.0, 0.0);
+  cpx<C> rv[1][12], ev[12], av[12], o[1][12];
+  SpinorIO<S>::load(r, Vh, i, rv[0]);
+  SpinorIO<S>::load(e, Vh, i, ev);
+  SpinorIO<S>::load(Ar, Vh, i, av);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    const cpx<double> rk = mk((double)rv[0][k].r, (double)rv[0][k].i);
+    const cpx<double> ek = mk((double)ev[k].r, (double)ev[k].i) + a * rk;
+    const cpx<double> rn = rk - a * mk((double)av[k].r, (double)av[k].i);
+    ev[k] = mk((C)(S)ek.r, (C)(S)ek.i);
+    rv[0][k] = mk((C)(S)rn.r, (C)(S)rn.i);
+  }
+  SpinorIO<S>::store(e, Vh, i, ev);
+  SpinorIO<S>::store(r, Vh, i, rv[0]);
+  clover_multi<G, C, 1>(clov, Vh, p, 1, i, 1, rv, o);
+  SpinorIO<S>::store(out, Vh, i, o[0]);
+}
+
+bool launch_clover_mr(int prec, void* out, void* r, void* e, const void* Ar, const double* coef, const void* clov,
+                      int Vh, int p, int fprec, hipStream_t st) {
+  const int fp = fprec < 0 ? prec : fprec;
+  const dim3 grid((Vh + 255) / 256);
+  if (prec == WCMG_F64 && fp == WCMG_F64)
+    hipLaunchKernelGGL((clover_mr_kernel<double, double>), grid, dim3(256), 0, st, out, r, e, Ar, coef, clov, Vh, p);
+  else if (prec == WCMG_F32 && fp == WCMG_F32)
+    hipLaunchKernelGGL((clover_mr_kernel<float, float>), grid, dim3(256), 0, st, out, r, e, Ar, coef, clov, Vh, p);
+  else if (prec == WCMG_F32 && fp == WCMG_F16)
+    hipLaunchKernelGGL((clover_mr_kernel<float, __half>), grid, dim3(256), 0, st, out, r, e, Ar, coef, clov, Vh, p);
+  else
+    return false;
+  HIPCHK(hipGetLastError());
+  return true;
 }
 
 // right-hand sides per thread: FP64 keeps at most 2 in registers, FP32/FP16 4
@@ -351,6 +421,33 @@ void launch_dslash(int prec, int diag, bool postinv, const DslashArgs& a, hipStr
   else if (prec == WCMG_F32 && fp == WCMG_F16) launch_dslash_t<float, __half>(diag, postinv, a, st);
   else if (prec == WCMG_F16 && fp == WCMG_F16) launch_dslash_t<__half, __half>(diag, postinv, a, st);
   else fail(WCMG_EINVAL, "unsupported spinor / field precision pair");
+}
+
+template <typename S, typename G>
+static void launch_dslash_red_t(DslashArgs a, const RedOut& o, hipStream_t st) {
+  const bool stream = a.stream >= 0 ? a.stream != 0 : (double)a.g.Vh * 432.0 * sizeof(G) > 192.0e6;
+  dim3 grid(xcd_grid(a.nblocks));
+  if (stream)
+    hipLaunchKernelGGL((dslash_red_kernel<S, G, true>), grid, dim3(256), 0, st, a, o);
+  else
+    hipLaunchKernelGGL((dslash_red_kernel<S, G, false>), grid, dim3(256), 0, st, a, o);
+  HIPCHK(hipGetLastError());
+}
+
+bool launch_dslash_red(int prec, const DslashArgs& a0, const RedOut& o, hipStream_t st) {
+  if (a0.nrhs != 1) return false;
+  DslashArgs a = a0;
+  a.threads = 256;
+  a.group = 1;
+  a.nblocks = (a.g.Vh + 255) / 256;
+  // per-block partials: three doubles per block of the padded grid
+  if ((size_t)xcd_grid(a.nblocks) * 3 > (size_t)kRedBlocks * 64) return false;
+  const int fp = a.fprec < 0 ? prec : a.fprec;
+  if (prec == WCMG_F64 && fp == WCMG_F64) launch_dslash_red_t<double, double>(a, o, st);
+  else if (prec == WCMG_F32 && fp == WCMG_F32) launch_dslash_red_t<float, float>(a, o, st);
+  else if (prec == WCMG_F32 && fp == WCMG_F16) launch_dslash_red_t<float, __half>(a, o, st);
+  else return false;
+  return true;
 }
 
 template <typename S, typename G, int NR>

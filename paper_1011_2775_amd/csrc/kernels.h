@@ -24,6 +24,15 @@ struct DslashArgs {
   int stream = -1;     // non-temporal field loads: 1 on, 0 off, -1 when the fields exceed the Infinity Cache
 };
 void launch_dslash(int prec, int diag, bool postinv, const DslashArgs& a, hipStream_t st);
+struct RedOut;
+// DIAG = 1 hop (out = x + coeff H in, one right-hand side, F64 or F32 spinors)
+// that also reduces <out, x> (res[0..2)) and ||out||^2 (res[2]) into o in the
+// same launch; false (nothing launched) where it does not apply
+bool launch_dslash_red(int prec, const DslashArgs& a, const RedOut& o, hipStream_t st);
+// minimal-residual update e += a r, r -= a Ar (a = coef[0..2) / coef[2]) fused
+// with out = A_p^-1 r on parity p; false (nothing launched) for other precisions
+bool launch_clover_mr(int prec, void* out, void* r, void* e, const void* Ar, const double* coef, const void* clov,
+                      int Vh, int p, int fprec, hipStream_t st);
 // several lattices (one right-hand side each, same precision and kernel variant) in one launch
 constexpr int kMaxMulti = 4;
 struct DslashMulti {
@@ -85,7 +94,7 @@ constexpr int kRedBlocks = 512;
 struct RedOut {
   double* res;        // device result
   double* partial;    // kRedBlocks * 32 doubles of per-block partials
-  unsigned* counter;  // unused (reserved)
+  unsigned* counter;  // arrival counter of the in-launch finish (zero between launches)
   double* hres;       // optional second destination of the result (nullptr: none)
   RedOut at(int off) const { return RedOut{res + off, partial, counter, hres ? hres + off : nullptr}; }
 };

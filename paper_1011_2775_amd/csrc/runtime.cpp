@@ -240,6 +240,41 @@ void FineOp::Dr(void* out, const void* y, int nrhs) {
   hop(out, w->t2.p, y, 0, 1, false, -1.0, nrhs);           // out = y - H_eo w
 }
 
+bool FineOp::Dr_red(void* out, void* y, const RedOut& o, void* e, const double* coef) {
+  DslashArgs a;
+  a.out = out;
+  a.x = y;
+  a.gauge = F->gauge[fp()].p;
+  a.clov = F->clov[fp()].p;
+  a.fprec = fp();
+  a.g = dgeom(F->g);
+  a.parity = 0;
+  a.coeff = -1.0;
+  a.nrhs = 1;
+  a.rstride = hb();
+  const bool pair_ok = (prec == WCMG_F64 && fp() == WCMG_F64) ||
+                       (prec == WCMG_F32 && (fp() == WCMG_F32 || fp() == WCMG_F16));
+  if (!pair_ok) return false;
+  if ((size_t)xcd_grid((F->g.Vh + 255) / 256) * 3 > (size_t)kRedBlocks * 64) return false;
+  w->ensure(prec, F->g, 1);
+  a.in = w->t2.p;
+  if (e) {
+    // e += a y, y -= a out, z = A_ee^-1 y
+    if (!launch_clover_mr(prec, w->t1.p, y, e, out, coef, F->clov[fp()].p, F->g.Vh, 0, fp(), st))
+      fail(WCMG_EINVAL, "fused smoother update rejected after its checks passed");
+  } else {
+    clover(w->t1.p, y, 0, 1, 1);  // z = A_ee^-1 y
+  }
+  hop(w->t2.p, w->t1.p, nullptr, 1, 0, true, 1.0, 1);  // w = A_oo^-1 H_oe z
+  const int id = fp() != prec ? 56 + 2 : prec * 6 + 2;  // the DIAG = 1 hop's timer
+  hipEvent_t ev = nullptr;
+  if (ctx->timer.on) ctx->timer.begin(id, &ev);
+  const bool ok = launch_dslash_red(prec, a, o, st);  // out = y - H_eo w, and the sums
+  if (ev) ctx->timer.end(id, ev);
+  if (!ok) fail(WCMG_EINVAL, "fused smoother hop rejected after its checks passed");
+  return true;
+}
+
 void FineOp::Dr_dag(void* out, const void* y, int nrhs) {
   // D_r^dag = gamma5 (1 - A_ee^-1 H_eo A_oo^-1 H_oe) gamma5
   w->ensure(prec, F->g, nrhs);

@@ -102,6 +102,12 @@ struct FineOp {
   void clover(void* out, const void* in, int parity, int kind, int nrhs = 1);
   // reduced operator D_r y = y - H_eo A_oo^-1 H_oe A_ee^-1 y on even halves
   void Dr(void* out, const void* y, int nrhs = 1);
+  // Dr with <out, y> and ||out||^2 reduced into o by its last launch; false
+  // (nothing launched) where the fused launch does not apply
+  // With e and coef, the first launch also applies the pending minimal-residual
+  // update e += a y, y -= a out (a from coef, out still holding the previous
+  // D_r result) before D_r is applied to the updated y.
+  bool Dr_red(void* out, void* y, const RedOut& o, void* e = nullptr, const double* coef = nullptr);
   void Dr_dag(void* out, const void* y, int nrhs = 1);
   // full-lattice operators on (even, odd) halves
   void D(void* oe, void* oo, const void* ie, const void* io, int nrhs = 1);

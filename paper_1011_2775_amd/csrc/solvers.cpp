@@ -666,20 +666,32 @@ struct MGSolver {
   }
 
   // MR smoothing of e towards D_r e = r on the even half of n elements
-  template <typename DrFn>
-  void mr_smooth(const DrFn& Dr, int prec, void* e, const void* r, void* res, void* Ar, size_t n) {
+  // DrRed(out, in, o, e, coef): D_r with <out, in>, ||out||^2 reduced into o in
+  // its own last launch, the pending update of e and in (coefficients coef,
+  // previous D_r result in out) fused into its first (e null: none); returns
+  // false, launching nothing, where it does not apply
+  template <typename DrFn, typename DrRedFn>
+  void mr_smooth(const DrFn& Dr, const DrRedFn& DrRed, int prec, void* e, const void* r, void* res, void* Ar,
+                 size_t n) {
     const int nu = L.params.nu_post;
     if (nu <= 0) return;
     hipStream_t st = c.st;
     Dr(Ar, e);
     blas_copy(prec, res, r, n, st);
     blas_axpby(prec, -1.0, 0.0, Ar, 1.0, 0.0, res, n, st);
-    // alpha = <Ar, r> / ||Ar||^2 stays on the device: no host round trip
+    // alpha = <Ar, r> / ||Ar||^2 stays on the device: no host round trip; with the
+    // fused D_r the update of step i runs inside the first launch of step i + 1
+    bool pending = false;
     for (int i = 0; i < nu; ++i) {
+      if (DrRed(Ar, res, c.red.out(), pending ? e : nullptr, c.red.dres())) {
+        pending = true;
+        continue;
+      }
       Dr(Ar, res);
       blas_cdot_norm(prec, Ar, res, n, c.red.out(), st);
       blas_mr_update_dev(prec, c.red.dres(), e, res, Ar, n, st);
     }
+    if (pending) blas_mr_update_dev(prec, c.red.dres(), e, res, Ar, n, st);
   }
 
   // K_li(r_e) on coarse level li + 1: even part of P (next-level solve) R (r_e, 0), then MR
@@ -699,7 +711,9 @@ struct MGSolver {
                         T.bg.bvol, C.cg.n, T.nvec, 1, st);
     coarse_solve(li + 1, W.cc.p, W.cb.p);
     launch_ctr_prolong(cp, V.e.p, 0, W.cc.p, 0, P, T.vstride(), T.blk.as<int>(), C.cg.V, C.cg.n, T.nvec, 1, st);
-    mr_smooth([&](void* o, const void* i) { op.Dr(o, i); }, cp, V.e.p, r, V.res.p, V.Ar.p, ne);
+    mr_smooth([&](void* o, const void* i) { op.Dr(o, i); },
+              [](void*, void*, const RedOut&, void*, const double*) { return false; }, cp, V.e.p, r, V.res.p, V.Ar.p,
+              ne);
     blas_copy(cp, z, V.e.p, ne, st);
   }
 
@@ -751,7 +765,11 @@ struct MGSolver {
     launch_restrict(sp, V.cb.p, C.cg.n, 1, r_s.p, vecs(sp), L.T0.nvec, 0, g, L.T0.bg, false, st);
     coarse_solve(0, V.cc.p, V.cb.p);
     launch_prolong(sp, e_s.p, V.cc.p, vecs(sp), L.T0.nvec, 0, g, L.T0.bg, st);
-    mr_smooth([&](void* o, const void* i) { op.Dr(o, i); }, sp, e_s.p, r_s.p, res_s.p, Ar_s.p, n);
+    mr_smooth([&](void* o, const void* i) { op.Dr(o, i); },
+              [&](void* o, void* i, const RedOut& ro, void* ee, const double* cf) {
+                return op.Dr_red(o, i, ro, ee, cf);
+              },
+              sp, e_s.p, r_s.p, res_s.p, Ar_s.p, n);
     spinor_convert(WCMG_F64, z64, sp, e_s.p, g.Vh, st);
     ++calls;
   }

@@ -202,3 +202,26 @@ def test_multigrid_with_persistent_coarse_solve(nlevels):
     assert abs(iters[0]["inner_iters"][last] - iters[1]["inner_iters"][last]) <= \
         0.1 * iters[1]["inner_iters"][last] + 1
     ctx.close()
+
+
+@pytest.mark.parametrize("nvec,restart,prec", [(40, 30, "F32"), (40, 20, "F64"), (64, 64, "F64"), (64, 30, "F32")])
+def test_one_site_kernel_wide_blocks(nvec, restart, prec):
+    """n = 2 Nv of 80 and 128 on a 2^3x4 coarse lattice (16 even sites): the
+    one-site kernel's block-wide step sums (n > 64), fewer hop columns staged
+    in LDS, and, for n = 128 with restart 64 in FP64, a basis too large for
+    LDS (the strided kernel runs for both launches).  Bitwise equal to the
+    strided kernel; the full coarse residual (oracle) meets the tolerance."""
+    dims, block = (8, 8, 8, 16), (4, 4, 4, 4)
+    ctx, cop, U = build(dims, block, nvec, seed=13)
+    b = rhs(cop, 7)
+    bt = torch.from_numpy(b).cuda()
+    tol = 1e-8 if prec == "F64" else 1e-4
+    xo, so = ctx.coarse_solve(bt, prec=getattr(w, prec), tol=tol, max_iter=400, restart=restart, launch=0)
+    xg, sg = ctx.coarse_solve(bt, prec=getattr(w, prec), tol=tol, max_iter=400, restart=restart, launch=2)
+    print("n %d restart %d %s: iters %d / %d" % (2 * nvec, restart, prec, so["iters"], sg["iters"]), flush=True)
+    assert so["status"] == "OK" and sg["status"] == "OK"
+    assert so["iters"] == sg["iters"] and torch.equal(xo, xg)
+    br = cop.reduced_source(b)
+    slack = 1e-5 if prec == "F32" else 1e-12
+    assert full_res(cop, xo.cpu().numpy(), b) <= 1.01 * tol * np.linalg.norm(br) / np.linalg.norm(b) + slack
+    ctx.close()
