@@ -676,8 +676,9 @@ int wcmg_restrict(void* ctx, int lat, int level, int prec, void* coarse_out, con
     const size_t one = (size_t)g.V * 12 * 16, cone = (size_t)C.cg.V * C.cg.n * 16;
     for (int r = 0; r < nrhs; ++r) {
       spinor_to_internal(prec, fe, fo, (const char*)fine_in + r * one, g, false, c->st);
-      launch_restrict(prec, cv, C.cg.n, 1, fe, vecs, L.T0.nvec, 0, g, L.T0.bg, false, c->st);
-      launch_restrict(prec, cv, C.cg.n, 1, fo, vecs, L.T0.nvec, 1, g, L.T0.bg, true, c->st);
+      const void* vbm = prec == WCMG_F32 ? L.T0.vbm32.p : nullptr;
+      launch_restrict(prec, cv, C.cg.n, 1, fe, vecs, L.T0.nvec, 0, g, L.T0.bg, false, c->st, vbm);
+      launch_restrict(prec, cv, C.cg.n, 1, fo, vecs, L.T0.nvec, 1, g, L.T0.bg, true, c->st, vbm);
       launch_coarse_canon(cprec, cv, (char*)coarse_out + r * cone, C.perm.as<int>(), C.cg.V, C.cg.n, false, c->st);
     }
     HIPCHK(hipStreamSynchronize(c->st));

@@ -183,9 +183,15 @@ int coarse_internal_index_host(const BlockGeom& bg, int lex);
 // R: coarse[c][s*Nv+k] (+)= sign(s) sum conj(V_k) in over fine sites of parity p
 // vecs: Nv full-lattice spinors (precision prec) in internal layout
 // out_site_stride/out_row_stride are in complex elements; accumulate: add into out
+// vbm (FP32 only, optional): the block-major copy of vecs (launch_vec_blockmajor),
+// read instead of vecs with the same arithmetic (coalesced loads)
 void launch_restrict(int prec, void* out, size_t out_site_stride, size_t out_row_stride, const void* in,
                      const void* vecs, int nvec, int p, const Geom& g, const BlockGeom& bg, bool accumulate,
-                     hipStream_t st);
+                     hipStream_t st, const void* vbm = nullptr);
+// out (same size as v32) = the FP32 vectors v32 block by block: float4 chunk c of
+// the l-th site (restriction order) of parity p of block b of vector k at
+// (((k 2 + p) Vc + b) 6 + c) (bvol / 2) + l
+void launch_vec_blockmajor(void* out, const void* v32, int nvec, const Geom& g, const BlockGeom& bg, hipStream_t st);
 // P: out_p(x) = sum_k V_k(x) coarse[c(x)][s*Nv+k]
 void launch_prolong(int prec, void* out, const void* coarse, const void* vecs, int nvec, int p, const Geom& g,
                     const BlockGeom& bg, hipStream_t st);

@@ -161,6 +161,7 @@ struct FineTransfer {
   bool have_vecs = false, orth = false;
   DBuf raw;       // FP64 full spinors (as given / found by the setup)
   DBuf v64, v32;  // block-orthonormalised copies
+  DBuf vbm32;     // v32 in block-major order for the restriction
 };
 
 // transfer between coarse level l (>= 1) and level l+1; vectors in the

@@ -545,6 +545,7 @@ struct MGSolver {
 
   int nlev() const { return L.params.nlevels; }
   const void* vecs(int prec) const { return prec == WCMG_F64 ? L.T0.v64.p : L.T0.v32.p; }
+  const void* vbm(int prec) const { return prec == WCMG_F32 ? L.T0.vbm32.p : nullptr; }
   CoarseOp cop(int li) {
     CoarseOp o{L.levels[li].get(), cp, &cwork, c.st, &c.timer};
     o.timer_base = 20 + 2 * li;
@@ -762,7 +763,7 @@ struct MGSolver {
     CoarseLevel& C = *L.levels[0];
     Level& V = lv[0];
     spinor_convert(sp, r_s.p, WCMG_F64, r64, g.Vh, st);
-    launch_restrict(sp, V.cb.p, C.cg.n, 1, r_s.p, vecs(sp), L.T0.nvec, 0, g, L.T0.bg, false, st);
+    launch_restrict(sp, V.cb.p, C.cg.n, 1, r_s.p, vecs(sp), L.T0.nvec, 0, g, L.T0.bg, false, st, vbm(sp));
     coarse_solve(0, V.cc.p, V.cb.p);
     launch_prolong(sp, e_s.p, V.cc.p, vecs(sp), L.T0.nvec, 0, g, L.T0.bg, st);
     mr_smooth([&](void* o, const void* i) { op.Dr(o, i); },
@@ -904,7 +905,7 @@ struct MGSolver {
     for (int i = 0; i < nrhs; ++i) {
       spinor_convert(sp, (char*)r_s.p + i * hs, WCMG_F64, (const char*)r64 + i * h64, g.Vh, st);
       launch_restrict(sp, (char*)V.cb.p + i * na * cs, C.cg.n, 1, (char*)r_s.p + i * hs, vecs(sp), L.T0.nvec, 0, g,
-                      L.T0.bg, false, st);
+                      L.T0.bg, false, st, vbm(sp));
     }
     coarse_solve_b(0, V.cc.p, V.cb.p, nrhs);
     for (int i = 0; i < nrhs; ++i)
@@ -1369,6 +1370,8 @@ void mg_build_coarse(Ctx& c, LatticeState& L, int level) {
   for (int k = 0; k < 2 * nvec; ++k)
     spinor_convert(WCMG_F32, (char*)T.v32.p + (size_t)k * hb32, WCMG_F64, (const char*)T.v64.p + (size_t)k * hb64,
                    g.Vh, st);
+  T.vbm32.alloc((size_t)nvec * 2 * hb32);
+  launch_vec_blockmajor(T.vbm32.p, T.v32.p, nvec, g, T.bg, st);
   T.orth = true;
 
   if (L.levels.empty()) L.levels.emplace_back(new CoarseLevel());

@@ -56,10 +56,56 @@ __device__ __forceinline__ void block_sum(double (&v)[NR]) {
 // dotted with the KB vectors (the sum over the block's sites in a fixed tree)
 constexpr int kRestrictKB = 4;
 
+// site of parity p visited at step l of block clex (the order of the
+// restriction's loop over a block's half)
+__device__ __forceinline__ int block_site(const DGeom& g, const BlockGeom& bg, int clex, int p, int l) {
+  int r = clex, cc[4];
+  cc[0] = r % bg.nb[0];
+  r /= bg.nb[0];
+  cc[1] = r % bg.nb[1];
+  r /= bg.nb[1];
+  cc[2] = r % bg.nb[2];
+  cc[3] = r / bg.nb[2];
+  const int bxh = bg.b[0] / 2;
+  int lxh = l % bxh;
+  r = l / bxh;
+  int c[4];
+  c[1] = cc[1] * bg.b[1] + r % bg.b[1];
+  r /= bg.b[1];
+  c[2] = cc[2] * bg.b[2] + r % bg.b[2];
+  c[3] = cc[3] * bg.b[3] + r / bg.b[2];
+  c[0] = cc[0] * bg.b[0] + 2 * lxh + ((p + c[1] + c[2] + c[3]) & 1);
+  return cb_index(g, c);
+}
+
+// FP32 null vectors reordered block by block: float4 chunk c of the l-th
+// site of parity p of block b of vector k at (((k 2 + p) Vc + b) 6 + c) half + l,
+// so that a restriction workgroup reads each vector's block contiguously
+__global__ void k_vec_blockmajor(const float4* __restrict__ v32, float4* __restrict__ out, int nvec, DGeom g,
+                                 BlockGeom bg) {
+  const int half = bg.bvol / 2;
+  const size_t total = (size_t)nvec * 2 * bg.Vc * half;
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+    const int l = (int)(t % half);
+    size_t r = t / half;
+    const int b = (int)(r % bg.Vc);
+    r /= bg.Vc;
+    const int p = (int)(r % 2);
+    const int k = (int)(r / 2);
+    const int i = block_site(g, bg, b, p, l);
+    const float4* src = v32 + (size_t)(2 * k + p) * 6 * g.Vh;
+    float4* dst = out + ((size_t)(2 * k + p) * bg.Vc + b) * 6 * half;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) dst[(size_t)c * half + l] = src[(size_t)c * g.Vh + i];
+  }
+}
+
+// vbm (FP32 only): the block-major copy of the vectors, read in place of vecs
 template <typename S>
 __global__ void __launch_bounds__(128) k_restrict(void* out, size_t site_stride, size_t row_stride, const void* in,
                                                   const void* vecs, size_t vec_bytes, size_t half_bytes, int nvec,
-                                                  int p, DGeom g, BlockGeom bg, int accumulate) {
+                                                  int p, DGeom g, BlockGeom bg, int accumulate,
+                                                  const float4* __restrict__ vbm = nullptr) {
   using C = typename Compute<S>::T;
   using V2 = typename Vec2<C>::T;
   const int clex = blockIdx.x, k0 = blockIdx.y * kRestrictKB;
@@ -95,9 +141,25 @@ __global__ void __launch_bounds__(128) k_restrict(void* out, size_t site_stride,
 #pragma unroll
     for (int kk = 0; kk < kRestrictKB; ++kk) {
       if (kk < kb) {
-        const void* vk = reinterpret_cast<const char*>(vecs) + (size_t)(k0 + kk) * vec_bytes + (size_t)p * half_bytes;
         cpx<C> v[12];
-        SpinorIO<S>::load(vk, g.Vh, i, v);
+        if constexpr (sizeof(S) == 4) {
+          if (vbm) {
+            const float4* vb = vbm + ((size_t)(2 * (k0 + kk) + p) * bg.Vc + clex) * 6 * half;
+#pragma unroll
+            for (int cch = 0; cch < 6; ++cch) {
+              const float4 t = vb[(size_t)cch * half + l];
+              v[2 * cch] = mk((C)t.x, (C)t.y);
+              v[2 * cch + 1] = mk((C)t.z, (C)t.w);
+            }
+          } else {
+            SpinorIO<S>::load(reinterpret_cast<const char*>(vecs) + (size_t)(k0 + kk) * vec_bytes +
+                                  (size_t)p * half_bytes,
+                              g.Vh, i, v);
+          }
+        } else {
+          SpinorIO<S>::load(reinterpret_cast<const char*>(vecs) + (size_t)(k0 + kk) * vec_bytes + (size_t)p * half_bytes,
+                            g.Vh, i, v);
+        }
 #pragma unroll
         for (int a = 0; a < 12; ++a) {
           const int s = a >= 6;
@@ -329,8 +391,17 @@ int coarse_internal_index_host(const BlockGeom& bg, int clex) {
   return cp * (bg.Vc / 2) + (clex >> 1);
 }
 
+void launch_vec_blockmajor(void* out, const void* v32, int nvec, const Geom& g, const BlockGeom& bg, hipStream_t st) {
+  const size_t total = (size_t)nvec * 2 * bg.Vc * (bg.bvol / 2);
+  const int blocks = (int)std::min<size_t>((total + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_vec_blockmajor, dim3(blocks), dim3(256), 0, st, reinterpret_cast<const float4*>(v32),
+                     reinterpret_cast<float4*>(out), nvec, dgeom(g), bg);
+  HIPCHK(hipGetLastError());
+}
+
 void launch_restrict(int prec, void* out, size_t site_stride, size_t row_stride, const void* in, const void* vecs,
-                     int nvec, int p, const Geom& g, const BlockGeom& bg, bool accumulate, hipStream_t st) {
+                     int nvec, int p, const Geom& g, const BlockGeom& bg, bool accumulate, hipStream_t st,
+                     const void* vbm) {
   dim3 grid(bg.Vc, (nvec + kRestrictKB - 1) / kRestrictKB), block(128);
   size_t hb = spinor_bytes(prec, g.Vh);
   if (prec == WCMG_F64)
@@ -338,7 +409,7 @@ void launch_restrict(int prec, void* out, size_t site_stride, size_t row_stride,
                        nvec, p, dgeom(g), bg, (int)accumulate);
   else if (prec == WCMG_F32)
     hipLaunchKernelGGL(k_restrict<float>, grid, block, 0, st, out, site_stride, row_stride, in, vecs, 2 * hb, hb,
-                       nvec, p, dgeom(g), bg, (int)accumulate);
+                       nvec, p, dgeom(g), bg, (int)accumulate, reinterpret_cast<const float4*>(vbm));
   else
     hipLaunchKernelGGL(k_restrict<__half>, grid, block, 0, st, out, site_stride, row_stride, in, vecs, 2 * hb, hb,
                        nvec, p, dgeom(g), bg, (int)accumulate);
