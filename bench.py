@@ -11,10 +11,10 @@ coarse operator) happens before the timed region, as in the paper's
 speedups.  All inputs are synthetic and seeded.
 
 The smoothed synthetic field has its critical mass near m0 = -0.03, so the
-sweep's masses lie beyond it (the spectrum of D surrounds the origin) and
-plain FP64 BiCGStab stops at its iteration cap there: those speedups are
-lower bounds.  The near-critical mass m0 = -0.02, where BiCGStab converges,
-gives the equal-accuracy comparison (reported beside the headline value).
+sweep's masses lie beyond it, where plain FP64 BiCGStab's convergence is
+erratic: each comparison is marked equal-accuracy when it converged and a
+lower bound when it stopped at its iteration cap.  The near-critical mass
+m0 = -0.02 is reported beside the headline value.
 
 Prints ONE JSON line.  --gpus N with N > 1 is refused: this measures one GPU.
 """
