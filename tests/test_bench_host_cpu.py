@@ -1,0 +1,58 @@
+"""Host logic of bench.py that needs no GPU.
+
+* The committed HBM-traffic record is used only while the kernel's source is
+  byte-for-byte the one the counters were taken with: with the repository's
+  own files the dominant kernel's record is returned, and a copy of the tree
+  whose kernel source differs by one byte gets None.
+* The algorithmic byte counts per site follow the formulas the bench states
+  (compulsory links, spinors, clover records, FP16 scales).
+* --gpus N with N > 1 is refused with a message, before anything touches a GPU.
+"""
+import json
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_traffic_record_follows_the_source(tmp_path, monkeypatch):
+    rec = json.load(open(os.path.join(ROOT, "profiles", "hbm_traffic.json")))["kernels"]
+    name = "k_coarse_gcr_site<float>"
+    assert name in rec
+    assert bench.measured_traffic(name) == rec[name]["bytes_per_launch"]
+    # a tree whose kernel source differs by one byte
+    (tmp_path / "profiles").mkdir()
+    shutil.copy(os.path.join(ROOT, "profiles", "hbm_traffic.json"), tmp_path / "profiles" / "hbm_traffic.json")
+    csrc = tmp_path / "paper_1011_2775_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    src = open(os.path.join(ROOT, "paper_1011_2775_amd", "csrc", "coarse_persist.hip"), "rb").read()
+    (csrc / "coarse_persist.hip").write_bytes(src)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic(name) == rec[name]["bytes_per_launch"]
+    (csrc / "coarse_persist.hip").write_bytes(src + b"\n")
+    assert bench.measured_traffic(name) is None
+    assert bench.measured_traffic("no_such_kernel") is None
+
+
+def test_algorithmic_bytes_per_site():
+    # FP64 DIAG = 1 hop: neighbour spinor, links, output, diagonal input
+    assert bench.dslash_bytes_per_site(0, 1, False) == (24 + 144 + 24 + 24) * 8
+    # FP32 POSTINV hop: plus the 72-real clover inverse record
+    assert bench.dslash_bytes_per_site(1, 0, True) == (24 + 144 + 24 + 72) * 4
+    # FP16 DIAG = 2 hop: halves, plus one FP32 scale per spinor read or written
+    assert bench.dslash_bytes_per_site(2, 2, False) == (24 + 144 + 24 + 24 + 72) * 2 + 4 * 3
+    # a persistent coarse GCR step: both half hops and ten vector passes
+    assert bench.coarse_step_bytes(256, 48) == 256 * (2 * 8 * 48 * 48 + 10 * 48) * 8
+
+
+def test_more_than_one_gpu_is_refused():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert p.returncode != 0
+    assert "single GPU" in p.stderr and "--gpus 2" in p.stderr
