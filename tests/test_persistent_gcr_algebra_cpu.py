@@ -115,3 +115,65 @@ def test_pythagoras_fails_without_orthogonal_residual():
     gcr(lambda v: v - Ye @ (Yo @ v), b, tol=1e-300, restart=6, maxiter=6, info=info)
     ref = np.array(info.history[:7])
     assert np.max(np.abs(np.array(hist) - ref) / ref) > 1e-6
+
+
+def persistent_form_f32(Ye, Yo, b, steps):
+    """The same recurrences with every stored vector (q_k, z_k, T_k, y, r, t)
+    rounded to complex64 after each update and the hops taken in complex64,
+    as the FP32 kernel stores them; the sums behind alpha and the Gram-Schmidt
+    coefficients are formed in FP64 from the stored values.  Returns the
+    residual norms of the recurrence, the smallest Pythagorean ||q_k||^2
+    relative to the direct ||q||^2, and the final true residual."""
+    r32 = lambda v: v.astype(np.complex64)  # noqa: E731
+    Ye32, Yo32 = r32(Ye), r32(Yo)
+    r = r32(b)
+    y = np.zeros_like(r)
+    t = r32(Yo32 @ r)
+    Q, Z, T, qn = [], [], [], []
+    hist = [norm(r.astype(np.complex128))]
+    worst_ratio = np.inf
+    for k in range(steps):
+        q = r32(r - Ye32 @ t)
+        q64 = q.astype(np.complex128)
+        dots = [np.vdot(qj.astype(np.complex128), q64) for qj in Q]
+        qq_direct = np.vdot(q64, q64).real
+        qq = qq_direct - sum(abs(d) ** 2 / n for d, n in zip(dots, qn))
+        worst_ratio = min(worst_ratio, qq / qq_direct)
+        assert qq > 0.0  # no false breakdown from cancellation
+        alpha = np.vdot(q64, r.astype(np.complex128)) / qq
+        c = [d / n for d, n in zip(dots, qn)]
+        qk = r32(q64 - sum((cj * qj.astype(np.complex128) for cj, qj in zip(c, Q)), np.zeros_like(q64)))
+        zk = r32(r.astype(np.complex128) - sum((cj * zj.astype(np.complex128) for cj, zj in zip(c, Z)),
+                                               np.zeros_like(q64)))
+        Tk = r32((Yo32 @ q).astype(np.complex128) - sum((cj * Tj.astype(np.complex128) for cj, Tj in zip(c, T)),
+                                                        np.zeros(t.shape, np.complex128)))
+        y = r32(y.astype(np.complex128) + alpha * zk.astype(np.complex128))
+        r = r32(r.astype(np.complex128) - alpha * qk.astype(np.complex128))
+        t = r32(t.astype(np.complex128) - alpha * Tk.astype(np.complex128))
+        Q.append(qk)
+        Z.append(zk)
+        T.append(Tk)
+        qn.append(qq)
+        hist.append(norm(r.astype(np.complex128)))
+    y64 = y.astype(np.complex128)
+    true_res = norm(b - (y64 - Ye @ (Yo @ y64)))
+    return np.array(hist), worst_ratio, true_res
+
+
+@pytest.mark.parametrize("ne,no,scale,seed", [(96, 96, 0.8, 2), (64, 48, 0.9, 3), (200, 200, 0.95, 4)])
+def test_recurrences_in_fp32_storage_track_classical_gcr(ne, no, scale, seed):
+    """FP32 storage: the Pythagorean ||q_k||^2 stays positive and the residual
+    history tracks FP64 classical GCR down to the cycle's coarse tolerance
+    (0.05-0.3 of ||b_r||); the recurred residual agrees with the true one to
+    FP32 rounding of the cycle's start scale."""
+    Ye, Yo, b = system(ne, no, scale, seed)
+    steps = 16
+    hist, worst_ratio, true_res = persistent_form_f32(Ye, Yo, b, steps)
+    info = SolveInfo()
+    gcr(lambda v: v - Ye @ (Yo @ v), b, tol=1e-300, restart=steps, maxiter=steps, info=info)
+    ref = np.array(info.history[: steps + 1])
+    above = ref >= 0.05 * ref[0]  # the part of the history a coarse solve at tol >= 0.05 uses
+    assert above.sum() >= 3
+    assert np.max(np.abs(hist[above] - ref[above]) / ref[above]) < 1e-4
+    assert worst_ratio > 1e-6
+    assert abs(true_res - hist[-1]) < 1e-5 * hist[0]
