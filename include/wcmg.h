@@ -74,7 +74,18 @@ typedef enum { WCMG_F64 = 0, WCMG_F32 = 1, WCMG_F16 = 2 } wcmg_prec;
  *   DP    D_p = D diag(D_ee, D_oo)^-1, both parities. */
 typedef enum { WCMG_OP_FULL = 0, WCMG_OP_SCHUR = 1, WCMG_OP_DP = 2 } wcmg_op;
 
-typedef enum { WCMG_MG_GCR = 0, WCMG_GCR = 1, WCMG_BICGSTAB = 2 } wcmg_solver;
+/* MG_GCR: FP64 GCR on D_r preconditioned by the multigrid cycle (adaptive
+ * multigrid paragraph); GCR, BICGSTAB: unpreconditioned FP64 on D_r;
+ * MP_BICGSTAB: the paper's comparison solver (Implementation paragraph),
+ * BiCGStab in FP32 inside FP64 iterative refinement; CGNR: conjugate
+ * gradients on the normal equations D_r^dag D_r y = D_r^dag b_r, FP64. */
+typedef enum {
+  WCMG_MG_GCR = 0,
+  WCMG_GCR = 1,
+  WCMG_BICGSTAB = 2,
+  WCMG_MP_BICGSTAB = 3,
+  WCMG_CGNR = 4
+} wcmg_solver;
 
 typedef struct {
   int dims[4]; /* Lx, Ly, Lz, Lt; each even and >= 2 */
@@ -124,14 +135,23 @@ typedef struct {
                                        one-site kernel where it applies, as wcmg_coarse_solve
                                        launch 0); 2 the same with the strided kernel always; 1
                                        one launch per kernel of every step */
+  int plain_max_iter;               /* iteration cap of the solvers without multigrid (GCR,
+                                       BiCGStab, MP_BICGSTAB (FP32 iterations), CGNR); 0: 100000 */
+  double mp_inner_tol;              /* MP_BICGSTAB: relative tolerance of each FP32 BiCGStab solve of
+                                       the residual equation; 0: 1e-3 */
 } wcmg_mg_params;
 
 typedef struct {
   int iters;               /* outer iterations (GCR) or BiCGStab iterations */
-  double inner_iters[WCMG_MAX_LEVELS]; /* mean inner GCR iterations per call, coarse level l+1 */
+  double inner_iters[WCMG_MAX_LEVELS]; /* MG_GCR: mean inner GCR iterations per call, coarse level
+                                          l+1; MP_BICGSTAB: [0] = refinement cycles */
   double true_rel_res;     /* ||b - D x|| / ||b|| recomputed in FP64 after the solve */
   double t_solve_s;        /* wall time of the solve on the host clock */
   int status;              /* WCMG_OK or the failure code for this right-hand side */
+  int inner_status;        /* first failure an inner (coarse-level) solve of the preconditioner reported
+                              during this solve (e.g. EBREAKDOWN when the FP32 persistent coarse GCR lost
+                              its Pythagorean step norm, ENAN), else WCMG_OK; informational: the outer
+                              FP64 GCR and the true residual decide `status` */
 } wcmg_stats;
 
 /* Fill *p with the library defaults (2 levels, 4^4 blocks, Nv = 24,
@@ -190,11 +210,11 @@ int wcmg_get_coarse(void* ctx, int lat, int level, void* Y, int on_device);
 /* out = op(in) or op^dag(in) for nrhs canonical spinors (device).  prec is
  * the storage/arithmetic precision of the internal apply (F16 stores
  * fields in half precision with FP32 arithmetic).  All right-hand sides go
- * through each kernel in one batched launch.  lat = -1 (wcmg_apply_D, op
- * FULL or SCHUR, nrhs = 1): every lattice of the context (at most 4, of any
- * volumes), buffers concatenated in lattice order, each kernel one launch
- * over all lattices (a work list of per-lattice block ranges).
- * Asynchronous. */
+ * through each kernel in one batched launch.  lat = -1 (any op, D or
+ * D^dag): every lattice of the context (at most 4, of any volumes), buffers
+ * holding nrhs spinors of each lattice, concatenated in lattice order; for
+ * each right-hand side every kernel is one launch over all lattices (a work
+ * list of per-lattice block ranges).  Asynchronous. */
 int wcmg_apply_D(void* ctx, int lat, int op, int prec, void* out, const void* in, int nrhs);
 int wcmg_apply_Ddag(void* ctx, int lat, int op, int prec, void* out, const void* in, int nrhs);
 
@@ -229,7 +249,11 @@ int wcmg_apply_coarse(void* ctx, int lat, int level, int op, int prec, void* out
 int wcmg_coarse_solve(void* ctx, int lat, int level, int prec, void* x, const void* b, double tol, int max_iter,
                       int restart, int launch, wcmg_stats* stats);
 
-/* Solve D x = b for nrhs canonical right-hand sides (device).  x is the
+/* Solve D x = b for nrhs canonical right-hand sides (device).  lat = -1:
+ * every lattice of the context in one call, x, b holding nrhs spinors of
+ * each lattice in lattice order and stats nlat * nrhs entries in the same
+ * order; each lattice's right-hand sides go through its own hierarchy, and a
+ * lattice that does not converge does not stop the others.  x is the
  * initial guess on entry if nonzero.  Stops when ||b - D x|| <= tol ||b||
  * (true residual recomputed in FP64).  stats: host array of nrhs entries
  * or NULL.  MG_GCR: outer FP64 GCR on D_r preconditioned by the cycle;
@@ -283,10 +307,16 @@ int wcmg_dot(void* ctx, int prec, const void* x, const void* y, long n, double* 
 /* Per-kernel timing with HIP events on the context's stream.
  * wcmg_timer_enable(ctx, 1) resets the counters and starts recording every
  * launch of the timed kernels; wcmg_timer_read returns the launch count and
- * the summed duration in milliseconds for kernel id `which` (synchronising
- * the stream).  Ids: fine hop kernel  prec*6 + diag*2 + clover_inverse
- * (prec 0 F64, 1 F32, 2 F16; diag 0 none, 1 x, 2 A x; see the DIAG/POST
- * modes of the Dslash), coarse red-black hop 20 (F64) and 21 (F32). */
+ * the summed duration in milliseconds for kernel id `which` (0..95,
+ * synchronising the stream).  Ids: fine hop kernel prec*6 + diag*2 +
+ * clover_inverse (prec 0 F64, 1 F32, 2 F16; diag 0 none, 1 x, 2 A x; see
+ * the DIAG/POST modes of the Dslash), batched fine hops 32 + the same, FP16
+ * fields with FP32 spinors 56 + diag*2 + clover_inverse; site-local clover
+ * launches 64 + prec (batched 67 + prec, FP16 fields 70), the smoother's
+ * fused update + clover launch 72 + prec; coarse red-black hop 20 + 2 l +
+ * prec (l = 0 first coarse level, prec 0 F64 / 1 F32; batches +4), batched
+ * red-black hop on the matrix cores 50 + 2 l, persistent coarse solve
+ * 28 + l. */
 int wcmg_timer_enable(void* ctx, int on);
 int wcmg_timer_read(void* ctx, int which, long* count, double* total_ms);
 

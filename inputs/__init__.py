@@ -23,7 +23,28 @@ The flat site index is ``((t*Lz + z)*Ly + y)*Lx + x``.
 """
 from __future__ import annotations
 
+import os
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
+
+# Per-site work (3x3 eigendecompositions, products) runs over chunks of the
+# leading axis in a thread pool: NumPy's linear-algebra loops release the
+# GIL, and every matrix is computed on its own, so the chunking leaves every
+# bit of the result unchanged.
+_THREADS = max(1, min(16, os.cpu_count() or 1))
+
+
+def _chunked(fn, *arrays):
+    """fn(*chunks) over chunks of axis 0 of the arrays, results concatenated."""
+    n = arrays[0].shape[0]
+    k = min(_THREADS, max(1, n // 4096))
+    if k <= 1:
+        return fn(*arrays)
+    edges = np.linspace(0, n, k + 1).astype(int)
+    with ThreadPoolExecutor(k) as ex:
+        parts = list(ex.map(lambda i: fn(*(a[edges[i]:edges[i + 1]] for a in arrays)), range(k)))
+    return np.concatenate(parts, axis=0)
 
 __all__ = [
     "volume", "gell_mann", "random_links", "project_su3", "ape_smear",
@@ -65,9 +86,11 @@ def gell_mann():
 
 def _expi_hermitian(H, eps):
     """exp(i*eps*H) for a stack of Hermitian 3x3 matrices, via eigh."""
-    w, Q = np.linalg.eigh(H)
-    ph = np.exp(1j * eps * w)
-    return (Q * ph[..., None, :]) @ np.conj(np.swapaxes(Q, -1, -2))
+    def one(Hc):
+        w, Q = np.linalg.eigh(Hc)
+        ph = np.exp(1j * eps * w)
+        return (Q * ph[..., None, :]) @ np.conj(np.swapaxes(Q, -1, -2))
+    return _chunked(one, H)
 
 
 def random_links(dims, eps, seed):
@@ -86,6 +109,10 @@ def random_links(dims, eps, seed):
 
 def project_su3(X):
     """Polar projection onto U(3), then divide out det^{1/3} (principal root)."""
+    return _chunked(_project_su3, X)
+
+
+def _project_su3(X):
     XhX = np.conj(np.swapaxes(X, -1, -2)) @ X
     w, Q = np.linalg.eigh(XhX)
     inv_sqrt = (Q * (1.0 / np.sqrt(w))[..., None, :]) @ np.conj(np.swapaxes(Q, -1, -2))
@@ -118,12 +145,12 @@ def ape_smear(U, alpha=0.5, sweeps=5):
                 # upper: U_nu(x) U_mu(x+nu) U_nu(x+mu)^dag
                 Unu_xpm = np.roll(Unu, -1, axis=am)
                 Umu_xpn = np.roll(Umu, -1, axis=an)
-                staple += Unu @ Umu_xpn @ _dag(Unu_xpm)
+                staple += _chunked(lambda a, b, c: a @ b @ _dag(c), Unu, Umu_xpn, Unu_xpm)
                 # lower: U_nu(x-nu)^dag U_mu(x-nu) U_nu(x-nu+mu)
                 Unu_xmn = np.roll(Unu, 1, axis=an)
                 Umu_xmn = np.roll(Umu, 1, axis=an)
                 Unu_xmn_pm = np.roll(Unu_xmn, -1, axis=am)
-                staple += _dag(Unu_xmn) @ Umu_xmn @ Unu_xmn_pm
+                staple += _chunked(lambda a, b, c: _dag(a) @ b @ c, Unu_xmn, Umu_xmn, Unu_xmn_pm)
             del Umu_xpm
             new[..., mu, :, :] = project_su3((1.0 - alpha) * Umu + (alpha / 6.0) * staple)
         U = new
@@ -191,3 +218,96 @@ def config(name):
     c["source_seeds"] = [2000 + 100 * i + r for r in range(c["nrhs"])]
     c["setup_seed"] = 3000 + i
     return c
+
+
+# ----------------------------------------------------------------------------
+# The same recipe with elementwise torch operations (any device).  Lattices of
+# a few million links take minutes through NumPy's per-matrix loops; this
+# version runs the identical draws through whole-array arithmetic on a GPU in
+# seconds.  It agrees with gauge_field to rounding (a CPU test checks it), but
+# not bit for bit: every consumer of a field takes it from one of the two.
+# ----------------------------------------------------------------------------
+def _t_mm(A, B):
+    """Stacked 3x3 products by broadcasting (no batched-GEMM library call)."""
+    return (A[..., :, :, None] * B[..., None, :, :]).sum(-2)
+
+
+def _t_dag(A):
+    return A.conj().transpose(-1, -2)
+
+
+def _t_det(A):
+    return (A[..., 0, 0] * (A[..., 1, 1] * A[..., 2, 2] - A[..., 1, 2] * A[..., 2, 1])
+            - A[..., 0, 1] * (A[..., 1, 0] * A[..., 2, 2] - A[..., 1, 2] * A[..., 2, 0])
+            + A[..., 0, 2] * (A[..., 1, 0] * A[..., 2, 1] - A[..., 1, 1] * A[..., 2, 0]))
+
+
+def _t_inv(A):
+    """3x3 inverse from the adjugate."""
+    import torch
+    c = torch.empty_like(A)
+    for i in range(3):
+        for j in range(3):
+            r = [k for k in range(3) if k != j]
+            s = [k for k in range(3) if k != i]
+            minor = A[..., r[0], s[0]] * A[..., r[1], s[1]] - A[..., r[0], s[1]] * A[..., r[1], s[0]]
+            c[..., i, j] = minor if (i + j) % 2 == 0 else -minor
+    return c / _t_det(A)[..., None, None]
+
+
+def _t_project_su3(X, iters=30):
+    """Polar factor by the Newton iteration W <- (W + W^-dag)/2 (converged when
+    the update stops changing W), then divide out det^{1/3} (principal root)."""
+    import torch
+    W = X
+    for _ in range(iters):
+        Wn = 0.5 * (W + _t_dag(_t_inv(W)))
+        done = bool((Wn - W).abs().max() <= 4e-16)
+        W = Wn
+        if done:
+            break
+    root = torch.exp(1j * torch.angle(_t_det(W)) / 3.0)
+    return W / root[..., None, None]
+
+
+def _t_expi(H, eps, terms=30):
+    """exp(i eps H) by its Taylor series (|eps H| is O(1) here), then projected
+    onto SU(3) so that unitarity holds to rounding."""
+    import torch
+    A = 1j * eps * H
+    term = torch.eye(3, dtype=H.dtype, device=H.device).expand_as(H).clone()
+    out = term.clone()
+    for k in range(1, terms):
+        term = _t_mm(term, A) / k
+        out = out + term
+    return _t_project_su3(out)
+
+
+def gauge_field_torch(dims, eps, seed, ape_sweeps=0, ape_alpha=0.5, device="cpu"):
+    """gauge_field's recipe (the same PCG64 draws) as a complex128 torch tensor
+    [Lt][Lz][Ly][Lx][4][3][3] on `device`."""
+    import torch
+    V = volume(dims)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    h = torch.from_numpy(rng.standard_normal((V, 4, 8))).to(device)
+    gm = torch.from_numpy(gell_mann() * 0.5).to(device)
+    H = (h.to(torch.complex128)[..., :, None, None] * gm).sum(-3)
+    U = _t_expi(H, eps).reshape(_shape(dims) + (4, 3, 3))
+    axis = {0: 3, 1: 2, 2: 1, 3: 0}
+    for _ in range(ape_sweeps):
+        new = torch.empty_like(U)
+        for mu in range(4):
+            am = axis[mu]
+            Umu = U[..., mu, :, :]
+            staple = torch.zeros_like(Umu)
+            for nu in range(4):
+                if nu == mu:
+                    continue
+                an = axis[nu]
+                Unu = U[..., nu, :, :]
+                staple += _t_mm(_t_mm(Unu, torch.roll(Umu, -1, dims=an)), _t_dag(torch.roll(Unu, -1, dims=am)))
+                Unu_xmn = torch.roll(Unu, 1, dims=an)
+                staple += _t_mm(_t_mm(_t_dag(Unu_xmn), torch.roll(Umu, 1, dims=an)), torch.roll(Unu_xmn, -1, dims=am))
+            new[..., mu, :, :] = _t_project_su3((1.0 - ape_alpha) * Umu + (ape_alpha / 6.0) * staple)
+        U = new
+    return U

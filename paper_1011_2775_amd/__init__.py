@@ -7,25 +7,54 @@ Fields are torch tensors on the GPU (complex128, canonical layouts):
   gauge  [Lt][Lz][Ly][Lx][4][3][3]      spinor [nrhs][Lt][Lz][Ly][Lx][4][3]
   coarse [nrhs][Vc][2*Nv]               coarse operator [Vc][9][2Nv][2Nv]
 """
+import atexit
 import ctypes
+import sys
+import weakref
 
 import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (F16, F32, F64, OP_DP, OP_FULL, OP_SCHUR, MG_GCR, GCR, BICGSTAB, WcmgError, check)
+from ._lib import (F16, F32, F64, OP_DP, OP_FULL, OP_SCHUR, MG_GCR, GCR, BICGSTAB, MP_BICGSTAB, CGNR, WcmgError,
+                   check)
 
 __all__ = ["Context", "WcmgError", "F64", "F32", "F16", "OP_FULL", "OP_SCHUR", "OP_DP", "MG_GCR", "GCR",
-           "BICGSTAB", "default_params"]
+           "BICGSTAB", "MP_BICGSTAB", "CGNR", "default_params"]
 
 
-def _ptr(t):
+def _ptr(t, numel=None, name="buffer"):
+    """(pointer, on_device, keep-alive) of a complex128 buffer of `numel`
+    elements: a contiguous CUDA or CPU tensor, or anything numpy converts.
+    Keep the third value alive until the library call returns."""
     if isinstance(t, torch.Tensor):
+        if t.dtype != torch.complex128:
+            raise ValueError("%s must be complex128, not %s" % (name, t.dtype))
         if not t.is_contiguous():
-            raise ValueError("tensor must be contiguous")
-        return ctypes.c_void_p(t.data_ptr()), int(t.is_cuda)
-    a = np.ascontiguousarray(t)
-    return ctypes.c_void_p(a.ctypes.data), 0
+            raise ValueError("%s must be contiguous" % name)
+        if numel is not None and t.numel() != numel:
+            raise ValueError("%s has %d elements, expected %d" % (name, t.numel(), numel))
+        if t.is_cuda:
+            return ctypes.c_void_p(t.data_ptr()), 1, t
+        t = t.numpy()
+    a = np.ascontiguousarray(t, dtype=np.complex128)
+    if numel is not None and a.size != numel:
+        raise ValueError("%s has %d elements, expected %d" % (name, a.size, numel))
+    return ctypes.c_void_p(a.ctypes.data), 0, a
+
+
+def _dev(t, unit, name, dtype=torch.complex128):
+    """A contiguous CUDA tensor of `dtype` whose element count is a positive
+    multiple of `unit`; returns that multiple (the number of right-hand sides)."""
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError("%s must be a CUDA tensor" % name)
+    if t.dtype != dtype:
+        raise ValueError("%s must be %s, not %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if t.numel() == 0 or t.numel() % unit:
+        raise ValueError("%s has %d elements, not a positive multiple of %d" % (name, t.numel(), unit))
+    return t.numel() // unit
 
 
 def default_params(**kw):
@@ -51,6 +80,21 @@ def default_params(**kw):
     return p
 
 
+# Contexts still open when the interpreter exits are destroyed by an atexit
+# handler, while the HIP runtime is certainly alive (atexit handlers run
+# before the interpreter tears its modules down, and long before the C
+# runtime's exit handlers unload HIP).  During interpreter finalisation
+# __del__ makes no library call at all: a context reached only then is left
+# to the process exit rather than freed into a runtime that may be gone.
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_contexts():
+    for ctx in list(_LIVE):
+        ctx.close()
+
+
 class Context:
     """One library context on the current GPU and torch stream."""
 
@@ -71,13 +115,24 @@ class Context:
         check(_lib.LIB.wcmg_create(arr, len(lattices), ctypes.c_void_p(stream or 0), ctypes.byref(h)))
         self.h = h
         self.params = {}
+        _LIVE.add(self)
 
     def close(self):
+        """Destroy the library context (synchronises its stream, frees its device memory)."""
         if getattr(self, "h", None) and self.h.value:
-            _lib.LIB.wcmg_destroy(self.h)
-            self.h = ctypes.c_void_p()
+            h, self.h = self.h, ctypes.c_void_p()
+            check(_lib.LIB.wcmg_destroy(h))
+        _LIVE.discard(self)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
     def __del__(self):
+        if sys is None or sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -88,15 +143,17 @@ class Context:
 
     # -- fields ------------------------------------------------------------
     def set_gauge(self, U, lat=0):
-        p, dev = _ptr(U)
+        p, dev, keep = _ptr(U, self.volume(lat) * 36, "gauge field")
         check(_lib.LIB.wcmg_set_gauge(self.h, lat, p, dev))
+        del keep
 
     def set_clover(self, m0, csw, A=None, lat=0):
         if A is None:
             check(_lib.LIB.wcmg_set_clover(self.h, lat, float(m0), float(csw), None, 1))
         else:
-            p, dev = _ptr(A)
+            p, dev, keep = _ptr(A, self.volume(lat) * 144, "clover matrix")
             check(_lib.LIB.wcmg_set_clover(self.h, lat, float(m0), float(csw), p, dev))
+            del keep
 
     # -- multigrid -----------------------------------------------------------
     def set_mg_params(self, params, lat=0):
@@ -107,8 +164,10 @@ class Context:
         check(_lib.LIB.wcmg_build_null_vectors(self.h, lat, level))
 
     def set_null_vectors(self, v, level=0, lat=0):
-        p, dev = _ptr(v)
-        check(_lib.LIB.wcmg_set_null_vectors(self.h, lat, level, p, int(v.shape[0]), dev))
+        nv = int(v.shape[0])
+        p, dev, keep = _ptr(v, nv * int(np.prod(self._level_shape(level, lat))), "null vectors")
+        check(_lib.LIB.wcmg_set_null_vectors(self.h, lat, level, p, nv, dev))
+        del keep
 
     def get_null_vectors(self, level=0, lat=0):
         nv = self.params[lat].nvec[level]
@@ -142,9 +201,10 @@ class Context:
 
     # -- operators -------------------------------------------------------------
     def _apply(self, fn, op, prec, inp, lat):
-        out = torch.empty_like(inp)
         # lat = -1: all lattices, one right-hand side each, concatenated in lattice order
-        nrhs = 1 if lat == -1 else inp.numel() // (self.volume(lat) * 12)
+        unit = sum(self.volume(l) for l in range(len(self.dims))) * 12 if lat == -1 else self.volume(lat) * 12
+        nrhs = _dev(inp, unit, "input")
+        out = torch.empty_like(inp)
         check(fn(self.h, lat, op, prec, ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(inp.data_ptr()), nrhs))
         return out
 
@@ -157,25 +217,25 @@ class Context:
     def restrict(self, fine, level=0, prec=F64, lat=0):
         """Level level -> level+1 restriction R = P^dag gamma5 (prec: arithmetic; complex128 I/O)."""
         shp = self._level_shape(level + 1, lat)
-        nrhs = fine.numel() // int(np.prod(self._level_shape(level, lat)))
+        fine = fine.contiguous()
+        nrhs = _dev(fine, int(np.prod(self._level_shape(level, lat))), "fine vectors")
         out = torch.empty((nrhs,) + shp, dtype=torch.complex128, device=fine.device)
         check(_lib.LIB.wcmg_restrict(self.h, lat, level, prec, ctypes.c_void_p(out.data_ptr()),
-                                     ctypes.c_void_p(fine.contiguous().data_ptr()), nrhs))
+                                     ctypes.c_void_p(fine.data_ptr()), nrhs))
         return out
 
     def prolong(self, coarse, level=0, prec=F64, lat=0):
-        nrhs = coarse.shape[0] if coarse.dim() == 3 else 1
+        coarse = coarse.contiguous()
+        nrhs = _dev(coarse, int(np.prod(self._level_shape(level + 1, lat))), "coarse vectors")
         out = torch.empty((nrhs,) + self._level_shape(level, lat), dtype=torch.complex128, device=coarse.device)
         check(_lib.LIB.wcmg_prolong(self.h, lat, level, prec, ctypes.c_void_p(out.data_ptr()),
-                                    ctypes.c_void_p(coarse.contiguous().data_ptr()), nrhs))
+                                    ctypes.c_void_p(coarse.data_ptr()), nrhs))
         return out
 
     def apply_coarse(self, inp, level=1, op=OP_FULL, prec=F64, lat=0):
         inp = inp.contiguous()
+        nrhs = _dev(inp, int(np.prod(self._level_shape(level, lat))), "coarse vectors")
         out = torch.empty_like(inp)
-        n = inp.shape[-1]
-        Vc = inp.shape[-2]
-        nrhs = inp.numel() // (Vc * n)
         check(_lib.LIB.wcmg_apply_coarse(self.h, lat, level, op, prec, ctypes.c_void_p(out.data_ptr()),
                                          ctypes.c_void_p(inp.data_ptr()), nrhs))
         return out
@@ -186,6 +246,8 @@ class Context:
         one-site kernel where it applies), 1: one launch per kernel, 2: the strided
         cooperative kernel."""
         b = b.contiguous()
+        if _dev(b, int(np.prod(self._level_shape(level, lat))), "right-hand side") != 1:
+            raise ValueError("the coarse solve takes one right-hand side")
         x = torch.empty_like(b)
         st = _lib.Stats()
         check(_lib.LIB.wcmg_coarse_solve(self.h, lat, level, prec, ctypes.c_void_p(x.data_ptr()),
@@ -204,9 +266,14 @@ class Context:
 
     def _solve(self, fn, b, solver, tol, x0, lat, raise_on_error):
         b = b.contiguous()
+        # lat = -1: every lattice, nrhs right-hand sides each, concatenated in lattice order
+        nl = len(self.dims) if lat == -1 else 1
+        unit = sum(self.volume(l) for l in range(nl)) * 12 if lat == -1 else self.volume(lat) * 12
+        nrhs = _dev(b, unit, "right-hand sides")
         x = torch.zeros_like(b) if x0 is None else x0.clone().contiguous()
-        nrhs = b.numel() // (self.volume(lat) * 12)
-        st = (_lib.Stats * nrhs)()
+        if _dev(x, unit, "initial guess") != nrhs:
+            raise ValueError("initial guess and right-hand sides differ in size")
+        st = (_lib.Stats * (nl * nrhs))()
         rc = fn(self.h, lat, solver, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(b.data_ptr()), nrhs, float(tol),
                 st)
         if raise_on_error:
@@ -218,9 +285,9 @@ class Context:
         summed over the right-hand sides of psi and lam."""
         psi = psi.contiguous()
         lam = lam.contiguous()
-        if psi.shape != lam.shape or psi.dtype != torch.complex128 or lam.dtype != torch.complex128:
-            raise ValueError("psi and lam must be complex128 tensors of the same shape")
-        nrhs = psi.numel() // (self.volume(lat) * 12)
+        nrhs = _dev(psi, self.volume(lat) * 12, "psi")
+        if psi.shape != lam.shape or _dev(lam, self.volume(lat) * 12, "lam") != nrhs:
+            raise ValueError("psi and lam must have the same shape")
         dims = self.dims[lat]
         dU = torch.empty((dims[3], dims[2], dims[1], dims[0], 4, 3, 3), dtype=torch.complex128, device=psi.device)
         check(_lib.LIB.wcmg_force(self.h, lat, ctypes.c_void_p(dU.data_ptr()), ctypes.c_void_p(psi.data_ptr()),
@@ -231,6 +298,9 @@ class Context:
     def dot(self, x, y):
         """sum conj(x) y of two device tensors (complex128 or complex64), in FP64."""
         prec = F64 if x.dtype == torch.complex128 else F32
+        n = _dev(x, 1, "x", x.dtype if x.dtype in (torch.complex128, torch.complex64) else torch.complex128)
+        if _dev(y, 1, "y", x.dtype) != n:
+            raise ValueError("x and y differ in length")
         out = (ctypes.c_double * 2)()
         check(_lib.LIB.wcmg_dot(self.h, prec, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
                                 x.numel(), out))

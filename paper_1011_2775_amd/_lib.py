@@ -15,7 +15,7 @@ LIBPATH = os.path.join(HERE, "lib", "libwcmg.so")
 OK, EINVAL, EDIM, ESTATE, ENOCONV, EBREAKDOWN, ENAN, ECLOVER_NOT_PD, ERANK, ENOMEM, EHIP, ENODEV = range(12)
 F64, F32, F16 = 0, 1, 2
 OP_FULL, OP_SCHUR, OP_DP = 0, 1, 2
-MG_GCR, GCR, BICGSTAB = 0, 1, 2
+MG_GCR, GCR, BICGSTAB, MP_BICGSTAB, CGNR = 0, 1, 2, 3, 4
 MAX_LEVELS = 3
 
 ERROR_NAMES = {0: "OK", 1: "EINVAL", 2: "EDIM", 3: "ESTATE", 4: "ENOCONV", 5: "EBREAKDOWN", 6: "ENAN",
@@ -44,7 +44,9 @@ class MGParams(ctypes.Structure):
                 ("coarsest", ctypes.c_int),
                 ("cycle_mode", ctypes.c_int),
                 ("setup_prec", ctypes.c_int),
-                ("coarse_launch", ctypes.c_int)]
+                ("coarse_launch", ctypes.c_int),
+                ("plain_max_iter", ctypes.c_int),
+                ("mp_inner_tol", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -52,11 +54,13 @@ class Stats(ctypes.Structure):
                 ("inner_iters", ctypes.c_double * MAX_LEVELS),
                 ("true_rel_res", ctypes.c_double),
                 ("t_solve_s", ctypes.c_double),
-                ("status", ctypes.c_int)]
+                ("status", ctypes.c_int),
+                ("inner_status", ctypes.c_int)]
 
     def as_dict(self):
         return dict(iters=self.iters, inner_iters=list(self.inner_iters), true_rel_res=self.true_rel_res,
-                    t_solve_s=self.t_solve_s, status=ERROR_NAMES.get(self.status, self.status))
+                    t_solve_s=self.t_solve_s, status=ERROR_NAMES.get(self.status, self.status),
+                    inner_status=ERROR_NAMES.get(self.inner_status, self.inner_status))
 
 
 _vp = ctypes.c_void_p

@@ -110,6 +110,35 @@ CloverCoef clover_coef(double csw) {
   return cc;
 }
 
+// A buffer the header marks "device" must be device (or managed) memory of
+// the context's GPU, with at least `bytes` bytes from p to the end of its
+// allocation; anything else (a host pointer, another GPU's memory, a buffer
+// too short for the shape the call implies) is rejected before any launch.
+int check_dev(Ctx* c, const void* p, size_t bytes, const char* what) {
+  hipPointerAttribute_t at{};
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_err(WCMG_EINVAL, std::string(what) + ": not a device pointer");
+  }
+  if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged)
+    return set_err(WCMG_EINVAL, std::string(what) + ": host memory where device memory is required");
+  if (at.device != c->device)
+    return set_err(WCMG_EINVAL, std::string(what) + ": memory of another device than the context's");
+  void* base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, const_cast<void*>(p)) == hipSuccess && base) {
+    if ((const char*)p + bytes > (const char*)base + size)
+      return set_err(WCMG_EINVAL, std::string(what) + ": device buffer shorter than the call requires");
+  } else {
+    (void)hipGetLastError();
+  }
+  return WCMG_OK;
+}
+#define CHECK_DEV(c, p, bytes, what) \
+  do {                               \
+    if (int r_ = check_dev((c), (p), (bytes), (what))) return r_; \
+  } while (0)
+
 int check_lat(Ctx* c, int lat) {
   if (!c) return set_err(WCMG_EINVAL, "null context");
   if (lat < 0 || lat >= (int)c->lats.size()) return set_err(WCMG_EINVAL, "lattice index out of range");
@@ -199,6 +228,7 @@ int wcmg_set_gauge(void* ctx, int lat, const void* U, int on_device) {
   Ctx* c = as_ctx(ctx);
   if (int r = check_lat(c, lat)) return r;
   CHECK(U, WCMG_EINVAL, "null gauge field");
+  if (on_device) CHECK_DEV(c, U, (size_t)c->lats[lat]->F.g.V * 4 * 9 * 16, "gauge field");
   return guarded([&] {
     LatticeState& L = *c->lats[lat];
     const Geom& g = L.F.g;
@@ -220,6 +250,7 @@ int wcmg_set_clover(void* ctx, int lat, double m0, double csw, const void* A, in
   CHECK(std::isfinite(m0) && std::isfinite(csw), WCMG_EINVAL, "m0 and csw must be finite");
   LatticeState& L = *c->lats[lat];
   CHECK(A || L.F.have_gauge, WCMG_ESTATE, "gauge field not set");
+  if (A && on_device) CHECK_DEV(c, A, (size_t)L.F.g.V * 144 * 16, "clover matrix");
   return guarded([&] {
     const Geom& g = L.F.g;
     DBuf c64;
@@ -283,6 +314,8 @@ int wcmg_set_mg_params(void* ctx, int lat, const wcmg_mg_params* p) {
         "coarsest must be 0 (GCR), 1 (dense FP64 inverse) or 2 (deflated FP64 GCR)");
   CHECK(p->cycle_mode >= 0 && p->cycle_mode <= 2, WCMG_EINVAL, "cycle_mode must be 0, 1 or 2");
   CHECK(p->coarse_launch >= 0 && p->coarse_launch <= 2, WCMG_EINVAL, "coarse_launch must be 0, 1 or 2");
+  CHECK(p->plain_max_iter >= 0, WCMG_EINVAL, "plain_max_iter must be >= 0");
+  CHECK(p->mp_inner_tol >= 0 && p->mp_inner_tol < 1, WCMG_EINVAL, "mp_inner_tol must be in [0,1)");
   CHECK(p->setup_prec == WCMG_F64 || p->setup_prec == WCMG_F32 || p->setup_prec == WCMG_F16, WCMG_EINVAL,
         "setup precision must be F64, F32 or F16 (FP16 fields, FP32 arithmetic)");
   // coarse extents and degrees of freedom of every level
@@ -359,6 +392,8 @@ int wcmg_set_null_vectors(void* ctx, int lat, int level, const void* v, int nvec
   CHECK(nvec == L.params.nvec[level], WCMG_EINVAL, "nvec differs from the parameters");
   if (level == 1) {
     CHECK(!L.levels.empty() && L.levels[0]->built, WCMG_ESTATE, "first coarse level not built");
+    if (on_device)
+      CHECK_DEV(c, v, (size_t)nvec * L.levels[0]->cg.V * L.levels[0]->cg.n * 16, "null vectors");
     return guarded([&] {
       CoarseLevel& C1 = *L.levels[0];
       const size_t one = (size_t)C1.cg.V * C1.cg.n * 16;
@@ -382,6 +417,7 @@ int wcmg_set_null_vectors(void* ctx, int lat, int level, const void* v, int nvec
       L.mg.reset();
     });
   }
+  if (on_device) CHECK_DEV(c, v, (size_t)nvec * L.F.g.V * 12 * 16, "null vectors");
   return guarded([&] {
     const Geom& g = L.F.g;
     const size_t hb = spinor_bytes(WCMG_F64, g.Vh);
@@ -410,6 +446,8 @@ int wcmg_get_null_vectors(void* ctx, int lat, int level, void* v, int on_device)
   LatticeState& L = *c->lats[lat];
   if (level == 1) {
     CHECK(!L.ctr.empty() && L.ctr[0]->have_vecs && !L.levels.empty(), WCMG_ESTATE, "null vectors not available");
+    if (on_device)
+      CHECK_DEV(c, v, (size_t)L.ctr[0]->nvec * L.levels[0]->cg.V * L.levels[0]->cg.n * 16, "null vectors");
     return guarded([&] {
       CoarseLevel& C1 = *L.levels[0];
       CoarseTransfer& T = *L.ctr[0];
@@ -425,6 +463,7 @@ int wcmg_get_null_vectors(void* ctx, int lat, int level, void* v, int on_device)
     });
   }
   CHECK(L.T0.have_vecs, WCMG_ESTATE, "null vectors not available");
+  if (on_device) CHECK_DEV(c, v, (size_t)L.T0.nvec * L.F.g.V * 12 * 16, "null vectors");
   return guarded([&] {
     const Geom& g = L.F.g;
     const size_t hb = spinor_bytes(WCMG_F64, g.Vh);
@@ -454,6 +493,9 @@ int wcmg_get_coarse(void* ctx, int lat, int level, void* Y, int on_device) {
   if (int r = check_level(c, lat, level)) return r;
   LatticeState& L = *c->lats[lat];
   CHECK((int)L.levels.size() > level && L.levels[level]->built, WCMG_ESTATE, "coarse operator not built");
+  if (on_device)
+    CHECK_DEV(c, Y, (size_t)L.levels[level]->cg.V * 9 * L.levels[level]->cg.n * L.levels[level]->cg.n * 16,
+              "coarse operator");
   return guarded([&] {
     CoarseLevel& C = *L.levels[level];
     const int n = C.cg.n, V = C.cg.V;
@@ -480,13 +522,21 @@ int wcmg_get_coarse(void* ctx, int lat, int level, void* Y, int on_device) {
   });
 }
 
-// every lattice of the context, one right-hand side each, buffers concatenated in
-// lattice order: each kernel of the operator is one launch over all lattices
-static int apply_all_lattices(Ctx* c, int op, int prec, void* out, const void* in) {
+// Every lattice of the context at once (lat = -1): buffers hold, in lattice
+// order, nrhs canonical spinors of each lattice; for each right-hand side
+// every kernel of the operator is one launch over all lattices (a work list
+// of per-lattice block ranges).  D^dag = gamma5 D gamma5 and
+// D_r^dag = gamma5 (1 - A_ee^-1 H_eo A_oo^-1 H_oe) gamma5 (red-black
+// paragraph, with the gamma5-hermiticity of Eq.(1)); D_p = D A^-1 and
+// D_p^dag = A^-1 gamma5 D gamma5.
+static int apply_all_lattices(Ctx* c, int op, int prec, void* out, const void* in, int nrhs, bool dag) {
   const int nl = (int)c->lats.size();
   CHECK(nl <= kMaxMulti, WCMG_EINVAL, "too many lattices for one launch");
-  CHECK(op == WCMG_OP_FULL || op == WCMG_OP_SCHUR, WCMG_EINVAL, "all-lattice applies support FULL and SCHUR");
   for (auto& L : c->lats) CHECK(L->F.have_clover, WCMG_ESTATE, "clover not set");
+  size_t total = 0;
+  for (auto& L : c->lats) total += (size_t)nrhs * L->F.g.V * 12 * 16;
+  CHECK_DEV(c, in, total, "input spinors");
+  CHECK_DEV(c, out, total, "output spinors");
   return guarded([&] {
     std::vector<char*> ie(nl), io(nl), oe(nl), oo(nl), t1(nl), t2(nl);
     std::vector<size_t> off(nl + 1, 0);
@@ -495,8 +545,7 @@ static int apply_all_lattices(Ctx* c, int op, int prec, void* out, const void* i
       const size_t hb = spinor_bytes(prec, g.Vh);
       char** bufs[6] = {&ie[l], &io[l], &oe[l], &oo[l], &t1[l], &t2[l]};
       for (int k = 0; k < 6; ++k) *bufs[k] = (char*)c->scratch_buf(60 + 6 * l + k, hb);
-      off[l + 1] = off[l] + (size_t)g.V * 12 * 16;
-      spinor_to_internal(prec, ie[l], io[l], (const char*)in + off[l], g, false, c->st);
+      off[l + 1] = off[l] + (size_t)nrhs * g.V * 12 * 16;
     }
     auto args = [&](int l, void* o, const void* i, const void* x, int parity, double coeff) {
       FineFields& F = c->lats[l]->F;
@@ -512,43 +561,86 @@ static int apply_all_lattices(Ctx* c, int op, int prec, void* out, const void* i
       a.coeff = coeff;
       return a;
     };
-    DslashMulti m{};
-    m.nl = nl;
-    if (op == WCMG_OP_FULL) {
-      for (int l = 0; l < nl; ++l) m.a[l] = args(l, oe[l], io[l], ie[l], 0, 1.0);
-      launch_dslash_multi(prec, 2, false, m, c->st);
-      for (int l = 0; l < nl; ++l) m.a[l] = args(l, oo[l], ie[l], io[l], 1, 1.0);
-      launch_dslash_multi(prec, 2, false, m, c->st);
-    } else {
+    auto clover_all = [&](std::vector<char*>& o, std::vector<char*>& i, int parity) {
       CloverMulti cm{};
       cm.nl = nl;
-      cm.parity = 0;
+      cm.parity = parity;
       cm.kind = 1;
       for (int l = 0; l < nl; ++l) {
-        cm.out[l] = t1[l];
-        cm.in[l] = ie[l];
+        cm.out[l] = o[l];
+        cm.in[l] = i[l];
         cm.clov[l] = c->lats[l]->F.clov[prec].p;
         cm.Vh[l] = c->lats[l]->F.g.Vh;
       }
-      launch_clover_multi(prec, cm, c->st);  // z = A_ee^-1 y
-      for (int l = 0; l < nl; ++l) m.a[l] = args(l, t2[l], t1[l], nullptr, 1, 1.0);
-      launch_dslash_multi(prec, 0, true, m, c->st);  // w = A_oo^-1 H_oe z
-      for (int l = 0; l < nl; ++l) m.a[l] = args(l, oe[l], t2[l], ie[l], 0, -1.0);
-      launch_dslash_multi(prec, 1, false, m, c->st);  // out = y - H_eo w
+      launch_clover_multi(prec, cm, c->st);  // A_p^-1 on parity p
+    };
+    DslashMulti m{};
+    m.nl = nl;
+    // input converted with gamma5 for the adjoint of FULL and DP; output flipped for FULL
+    const bool g5_in = dag && op != WCMG_OP_SCHUR, g5_out = dag && op == WCMG_OP_FULL;
+    for (int r = 0; r < nrhs; ++r) {
+      for (int l = 0; l < nl; ++l) {
+        const Geom& g = c->lats[l]->F.g;
+        spinor_to_internal(prec, ie[l], io[l], (const char*)in + off[l] + (size_t)r * g.V * 12 * 16, g, g5_in,
+                           c->st);
+        if (dag && op == WCMG_OP_SCHUR) spinor_gamma5(prec, ie[l], g.Vh, c->st);
+      }
+      std::vector<char*>* re = &oe;
+      std::vector<char*>* ro = &oo;
+      if (op == WCMG_OP_FULL || (op == WCMG_OP_DP && dag)) {
+        for (int l = 0; l < nl; ++l) m.a[l] = args(l, oe[l], io[l], ie[l], 0, 1.0);
+        launch_dslash_multi(prec, 2, false, m, c->st);
+        for (int l = 0; l < nl; ++l) m.a[l] = args(l, oo[l], ie[l], io[l], 1, 1.0);
+        launch_dslash_multi(prec, 2, false, m, c->st);
+        if (op == WCMG_OP_DP) {
+          // D_p^dag = A^-1 gamma5 D gamma5
+          for (int l = 0; l < nl; ++l) {
+            spinor_gamma5(prec, oe[l], c->lats[l]->F.g.Vh, c->st);
+            spinor_gamma5(prec, oo[l], c->lats[l]->F.g.Vh, c->st);
+          }
+          clover_all(t1, oe, 0);
+          clover_all(t2, oo, 1);
+          re = &t1;
+          ro = &t2;
+        }
+      } else if (op == WCMG_OP_DP) {
+        clover_all(t1, ie, 0);
+        clover_all(t2, io, 1);
+        for (int l = 0; l < nl; ++l) m.a[l] = args(l, oe[l], t2[l], ie[l], 0, 1.0);
+        launch_dslash_multi(prec, 1, false, m, c->st);  // out_e = ie + H A_oo^-1 io
+        for (int l = 0; l < nl; ++l) m.a[l] = args(l, oo[l], t1[l], io[l], 1, 1.0);
+        launch_dslash_multi(prec, 1, false, m, c->st);
+      } else if (!dag) {
+        clover_all(t1, ie, 0);  // z = A_ee^-1 y
+        for (int l = 0; l < nl; ++l) m.a[l] = args(l, t2[l], t1[l], nullptr, 1, 1.0);
+        launch_dslash_multi(prec, 0, true, m, c->st);  // w = A_oo^-1 H_oe z
+        for (int l = 0; l < nl; ++l) m.a[l] = args(l, oe[l], t2[l], ie[l], 0, -1.0);
+        launch_dslash_multi(prec, 1, false, m, c->st);  // out = y - H_eo w
+        ro = nullptr;
+      } else {
+        for (int l = 0; l < nl; ++l) m.a[l] = args(l, t2[l], ie[l], nullptr, 1, 1.0);
+        launch_dslash_multi(prec, 0, true, m, c->st);  // A_oo^-1 H_oe (gamma5 y)
+        for (int l = 0; l < nl; ++l) m.a[l] = args(l, oe[l], t2[l], ie[l], 0, -1.0);
+        launch_dslash_multi(prec, 1, true, m, c->st);  // gamma5 y - A_ee^-1 H_eo (...)
+        for (int l = 0; l < nl; ++l) spinor_gamma5(prec, oe[l], c->lats[l]->F.g.Vh, c->st);
+        ro = nullptr;
+      }
+      for (int l = 0; l < nl; ++l) {
+        const Geom& g = c->lats[l]->F.g;
+        spinor_from_internal(prec, (char*)out + off[l] + (size_t)r * g.V * 12 * 16, (*re)[l], ro ? (*ro)[l] : nullptr,
+                             g, g5_out, c->st);
+      }
     }
-    for (int l = 0; l < nl; ++l)
-      spinor_from_internal(prec, (char*)out + off[l], oe[l], op == WCMG_OP_FULL ? oo[l] : nullptr, c->lats[l]->F.g,
-                           false, c->st);
   });
 }
 
 static int apply_common(void* ctx, int lat, int op, int prec, void* out, const void* in, int nrhs, bool dag) {
   Ctx* c = as_ctx(ctx);
-  if (lat == -1 && c && !dag) {
+  if (lat == -1 && c) {
     CHECK(out && in && out != in, WCMG_EINVAL, "null or aliased buffer");
     CHECK(valid_op(op) && valid_prec(prec), WCMG_EINVAL, "bad operator or precision");
-    CHECK(nrhs == 1, WCMG_EINVAL, "all-lattice applies take one right-hand side per lattice");
-    return apply_all_lattices(c, op, prec, out, in);
+    CHECK(nrhs >= 1, WCMG_EINVAL, "nrhs must be >= 1");
+    return apply_all_lattices(c, op, prec, out, in, nrhs, dag);
   }
   if (int r = check_lat(c, lat)) return r;
   CHECK(out && in, WCMG_EINVAL, "null buffer");
@@ -558,6 +650,8 @@ static int apply_common(void* ctx, int lat, int op, int prec, void* out, const v
   CHECK(out != in, WCMG_EINVAL, "out and in must not alias");
   LatticeState& L = *c->lats[lat];
   CHECK(L.F.have_clover, WCMG_ESTATE, "clover not set");
+  CHECK_DEV(c, in, (size_t)nrhs * L.F.g.V * 12 * 16, "input spinors");
+  CHECK_DEV(c, out, (size_t)nrhs * L.F.g.V * 12 * 16, "output spinors");
   return guarded([&] {
     const Geom& g = L.F.g;
     const size_t hb = spinor_bytes(prec, g.Vh);
@@ -618,6 +712,13 @@ static int transfer_level1(Ctx* c, LatticeState& L, int prec, void* out, const v
   CHECK(prec == WCMG_F64 || prec == WCMG_F32, WCMG_EINVAL, "coarse transfer precision must be F64 or F32");
   CHECK(L.levels.size() > 1 && L.levels[1]->built && !L.ctr.empty() && L.ctr[0]->orth, WCMG_ESTATE,
         "second coarse level not built");
+  {
+    const CoarseLevel& C1 = *L.levels[0];
+    const CoarseLevel& C2 = *L.levels[1];
+    const size_t b1 = (size_t)nrhs * C1.cg.V * C1.cg.n * 16, b2 = (size_t)nrhs * C2.cg.V * C2.cg.n * 16;
+    CHECK_DEV(c, in, to_coarse ? b1 : b2, "input vectors");
+    CHECK_DEV(c, out, to_coarse ? b2 : b1, "output vectors");
+  }
   return guarded([&] {
     CoarseLevel& C1 = *L.levels[0];
     CoarseLevel& C2 = *L.levels[1];
@@ -655,6 +756,8 @@ int wcmg_restrict(void* ctx, int lat, int level, int prec, void* coarse_out, con
   LatticeState& L = *c->lats[lat];
   if (level == 1) return transfer_level1(c, L, prec, coarse_out, fine_in, nrhs, true);
   CHECK(!L.levels.empty() && L.levels[0]->built, WCMG_ESTATE, "coarse operator not built");
+  CHECK_DEV(c, fine_in, (size_t)nrhs * L.F.g.V * 12 * 16, "fine vectors");
+  CHECK_DEV(c, coarse_out, (size_t)nrhs * L.levels[0]->cg.V * L.levels[0]->cg.n * 16, "coarse vectors");
   return guarded([&] {
     const Geom& g = L.F.g;
     CoarseLevel& C = *L.levels[0];
@@ -695,6 +798,8 @@ int wcmg_prolong(void* ctx, int lat, int level, int prec, void* fine_out, const 
   LatticeState& L = *c->lats[lat];
   if (level == 1) return transfer_level1(c, L, prec, fine_out, coarse_in, nrhs, false);
   CHECK(!L.levels.empty() && L.levels[0]->built, WCMG_ESTATE, "coarse operator not built");
+  CHECK_DEV(c, fine_out, (size_t)nrhs * L.F.g.V * 12 * 16, "fine vectors");
+  CHECK_DEV(c, coarse_in, (size_t)nrhs * L.levels[0]->cg.V * L.levels[0]->cg.n * 16, "coarse vectors");
   return guarded([&] {
     const Geom& g = L.F.g;
     CoarseLevel& C = *L.levels[0];
@@ -737,6 +842,8 @@ int wcmg_apply_coarse(void* ctx, int lat, int level, int op, int prec, void* out
   CHECK((int)L.levels.size() >= level && L.levels[level - 1]->built, WCMG_ESTATE, "coarse operator not built");
   CoarseLevel& C = *L.levels[level - 1];
   CHECK(op != WCMG_OP_SCHUR || C.cg.split, WCMG_EDIM, "coarse lattice has an odd extent: no red-black form");
+  CHECK_DEV(c, in, (size_t)nrhs * C.cg.V * C.cg.n * 16, "input vectors");
+  CHECK_DEV(c, out, (size_t)nrhs * C.cg.V * C.cg.n * 16, "output vectors");
   return guarded([&] {
     // all right-hand sides in one batched application (FP32 red-black batches
     // run on the matrix cores)
@@ -778,6 +885,8 @@ int wcmg_coarse_solve(void* ctx, int lat, int level, int prec, void* x, const vo
   CHECK((int)L.levels.size() >= level && L.levels[level - 1]->built, WCMG_ESTATE, "coarse operator not built");
   CoarseLevel& C = *L.levels[level - 1];
   CHECK(C.cg.split, WCMG_EDIM, "coarse lattice has an odd extent: no red-black form");
+  CHECK_DEV(c, b, (size_t)C.cg.V * C.cg.n * 16, "right-hand side");
+  CHECK_DEV(c, x, (size_t)C.cg.V * C.cg.n * 16, "solution");
   return guarded([&] {
     const size_t cs = prec == WCMG_F64 ? 16 : 8;
     const size_t nall = (size_t)C.cg.V * C.cg.n;
@@ -824,19 +933,21 @@ int wcmg_coarse_solve(void* ctx, int lat, int level, int prec, void* x, const vo
   });
 }
 
-static int solve_impl(void* ctx, int lat, int solver, void* x, const void* b, int nrhs, double tol, wcmg_stats* stats,
-               bool dag) {
+static int solve_lattice(void* ctx, int lat, int solver, void* x, const void* b, int nrhs, double tol,
+                         wcmg_stats* stats, bool dag) {
   Ctx* c = as_ctx(ctx);
   if (int r = check_lat(c, lat)) return r;
   CHECK(x && b, WCMG_EINVAL, "null buffer");
   CHECK(x != b, WCMG_EINVAL, "x and b must not alias");
-  CHECK(solver == WCMG_MG_GCR || solver == WCMG_GCR || solver == WCMG_BICGSTAB, WCMG_EINVAL, "bad solver");
+  CHECK(solver >= WCMG_MG_GCR && solver <= WCMG_CGNR, WCMG_EINVAL, "bad solver");
   CHECK(nrhs >= 1, WCMG_EINVAL, "nrhs must be >= 1");
   CHECK(tol > 0 && tol < 1, WCMG_EINVAL, "tol must be in (0,1)");
   LatticeState& L = *c->lats[lat];
   CHECK(L.F.have_clover, WCMG_ESTATE, "clover not set");
   if (solver == WCMG_MG_GCR)
     CHECK(L.have_params && !L.levels.empty() && L.levels[0]->built, WCMG_ESTATE, "multigrid hierarchy not built");
+  CHECK_DEV(c, b, (size_t)nrhs * L.F.g.V * 12 * 16, "right-hand sides");
+  CHECK_DEV(c, x, (size_t)nrhs * L.F.g.V * 12 * 16, "solutions");
   int worst = WCMG_OK;
   int rc = guarded([&] {
     const Geom& g = L.F.g;
@@ -910,6 +1021,42 @@ static int solve_impl(void* ctx, int lat, int solver, void* x, const void* b, in
   return WCMG_OK;
 }
 
+// lat = -1: every lattice of the context in lattice order, nrhs right-hand
+// sides each (buffers and stats concatenated); a lattice whose solve does not
+// converge does not stop the others, and the worst status is returned.
+static int solve_impl(void* ctx, int lat, int solver, void* x, const void* b, int nrhs, double tol, wcmg_stats* stats,
+                      bool dag) {
+  Ctx* c = as_ctx(ctx);
+  if (lat != -1) return solve_lattice(ctx, lat, solver, x, b, nrhs, tol, stats, dag);
+  CHECK(c, WCMG_EINVAL, "null context");
+  CHECK(x && b && x != b, WCMG_EINVAL, "null or aliased buffer");
+  CHECK(nrhs >= 1, WCMG_EINVAL, "nrhs must be >= 1");
+  size_t total = 0;
+  for (auto& L : c->lats) {
+    CHECK(L->F.have_clover, WCMG_ESTATE, "clover not set");
+    if (solver == WCMG_MG_GCR)
+      CHECK(L->have_params && !L->levels.empty() && L->levels[0]->built, WCMG_ESTATE,
+            "multigrid hierarchy not built");
+    total += (size_t)nrhs * L->F.g.V * 12 * 16;
+  }
+  CHECK_DEV(c, b, total, "right-hand sides");
+  CHECK_DEV(c, x, total, "solutions");
+  int worst = WCMG_OK;
+  std::string msg;
+  size_t off = 0;
+  for (int l = 0; l < (int)c->lats.size(); ++l) {
+    const int rc = solve_lattice(ctx, l, solver, (char*)x + off, (const char*)b + off, nrhs, tol,
+                                 stats ? stats + (size_t)l * nrhs : nullptr, dag);
+    if (rc != WCMG_OK && rc != WCMG_ENOCONV && rc != WCMG_EBREAKDOWN && rc != WCMG_ENAN) return rc;
+    if (rc != WCMG_OK && worst == WCMG_OK) {
+      worst = rc;
+      msg = "lattice " + std::to_string(l) + ": " + g_err;
+    }
+    off += (size_t)nrhs * c->lats[l]->F.g.V * 12 * 16;
+  }
+  return worst == WCMG_OK ? WCMG_OK : set_err(worst, msg);
+}
+
 int wcmg_solve(void* ctx, int lat, int solver, void* x, const void* b, int nrhs, double tol, wcmg_stats* stats) {
   return solve_impl(ctx, lat, solver, x, b, nrhs, tol, stats, false);
 }
@@ -929,6 +1076,9 @@ int wcmg_force(void* ctx, int lat, void* dU, const void* psi, const void* lam, i
   if (include_clover)
     CHECK(L.F.have_clover && L.F.clover_from_u, WCMG_ESTATE,
           "the clover force needs a clover term computed from the gauge field");
+  CHECK_DEV(c, psi, (size_t)nrhs * L.F.g.V * 12 * 16, "psi");
+  CHECK_DEV(c, lam, (size_t)nrhs * L.F.g.V * 12 * 16, "lam");
+  CHECK_DEV(c, dU, (size_t)L.F.g.V * 4 * 9 * 16, "gauge gradient");
   return guarded([&] {
     const Geom& g = L.F.g;
     const bool clov = include_clover && L.F.csw != 0.0;
@@ -943,6 +1093,8 @@ int wcmg_dot(void* ctx, int prec, const void* x, const void* y, long n, double* 
   CHECK(x && y && out, WCMG_EINVAL, "null buffer");
   CHECK(prec == WCMG_F64 || prec == WCMG_F32, WCMG_EINVAL, "precision must be F64 or F32");
   CHECK(n >= 1, WCMG_EINVAL, "n must be >= 1");
+  CHECK_DEV(as_ctx(ctx), x, (size_t)n * (prec == WCMG_F64 ? 16 : 8), "x");
+  CHECK_DEV(as_ctx(ctx), y, (size_t)n * (prec == WCMG_F64 ? 16 : 8), "y");
   return guarded([&] {
     Ctx* c = as_ctx(ctx);
     blas_cdot(prec, x, y, (size_t)n, c->red.out(), c->st);

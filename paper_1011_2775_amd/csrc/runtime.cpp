@@ -230,7 +230,13 @@ void FineOp::hop(void* out, const void* in, const void* x, int parity, int diag,
 }
 
 void FineOp::clover(void* out, const void* in, int parity, int kind, int nrhs) {
+  // timer ids: one right-hand side 64 + precision, batches 67 + precision, FP16 fields
+  // with FP32 spinors 70
+  const int id = fp() != prec ? 70 : (nrhs > 1 ? 67 : 64) + prec;
+  hipEvent_t e = nullptr;
+  if (ctx->timer.on) ctx->timer.begin(id, &e);
   launch_clover(prec, out, in, F->clov[fp()].p, F->g.Vh, parity, kind, st, nrhs, hb(), fp());
+  if (e) ctx->timer.end(id, e);
 }
 
 void FineOp::Dr(void* out, const void* y, int nrhs) {
@@ -259,9 +265,12 @@ bool FineOp::Dr_red(void* out, void* y, const RedOut& o, void* e, const double* 
   w->ensure(prec, F->g, 1);
   a.in = w->t2.p;
   if (e) {
-    // e += a y, y -= a out, z = A_ee^-1 y
+    // e += a y, y -= a out, z = A_ee^-1 y (timer 72 + spinor precision)
+    hipEvent_t ev0 = nullptr;
+    if (ctx->timer.on) ctx->timer.begin(72 + prec, &ev0);
     if (!launch_clover_mr(prec, w->t1.p, y, e, out, coef, F->clov[fp()].p, F->g.Vh, 0, fp(), st))
       fail(WCMG_EINVAL, "fused smoother update rejected after its checks passed");
+    if (ev0) ctx->timer.end(72 + prec, ev0);
   } else {
     clover(w->t1.p, y, 0, 1, 1);  // z = A_ee^-1 y
   }

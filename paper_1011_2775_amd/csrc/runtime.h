@@ -19,7 +19,7 @@ struct KernelTimer {
   hipStream_t st = nullptr;
   std::vector<hipEvent_t> pool;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;  // (class, (start, stop))
-  static constexpr int kIds = 64;
+  static constexpr int kIds = 96;
   long count[kIds] = {};
   double ms[kIds] = {};
   hipEvent_t get();
@@ -288,6 +288,17 @@ void persistent_launch(Ctx& c, PersistWork& w, CoarseLevel& C, int prec, void* o
                        bool general = false);
 // iterations since the last collect; status (optional) gets the first failure code
 long persistent_collect(Ctx& c, PersistWork& w, int* status = nullptr);
+// the persistent launch on caller-provided buffers (sizes as for launch_coarse_gcr_persistent;
+// ctl: kPersistCtlBytes, zeroed before its first use)
+struct PersistBufs {
+  void *Q, *Z, *T, *qraw;
+  double* part;
+  void* ctl;
+};
+void persistent_launch_bufs(Ctx& c, int grid, const PersistBufs& B, CoarseLevel& C, int prec, void* out,
+                            const void* in, void* t, void* y, void* r, void* br, double tol, int restart,
+                            int maxiter, bool fixed, bool general);
+
 KrylovResult bicgstab(Ctx& c, int prec, size_t n, const OpFn& A, void* x, const void* b, double tol,
                       double target_norm, int maxiter);
 // batched flexible GCR: A and K act on S.nrhs right-hand sides at once

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <limits>
 
 #include "random.h"
 #include "herm_eig.h"
@@ -407,12 +408,177 @@ KrylovResult bicgstab(Ctx& c, int prec, size_t n, const OpFn& A, void* x, const 
 }
 
 // ---------------------------------------------------------------------------
+// the paper's comparison solvers on the reduced system D_r y = b_r
+// ---------------------------------------------------------------------------
+// Mixed-precision BiCGStab by iterative refinement (the Implementation
+// paragraph compares the multigrid solver with a BiCGStab whose work runs in
+// single precision inside double-precision restarts): the residual
+// r = b_r - D_r y is formed in FP64, an FP32 BiCGStab solves D_r e = r from
+// zero to a relative inner_tol, and y += e in FP64, until the FP64 residual
+// meets tol * target_norm.  res.iters counts FP32 BiCGStab iterations (two
+// D_r applies each); *cycles the refinement cycles.
+KrylovResult mp_bicgstab(Ctx& c, LatticeState& L, void* y, const void* b, bool y_zero, double tol,
+                         double target_norm, int maxiter, double inner_tol, int* cycles) {
+  hipStream_t st = c.st;
+  const Geom& g = L.F.g;
+  const size_t n = (size_t)12 * g.Vh;
+  FineOp op64{&c, &L.F, WCMG_F64, &c.fw[0], st};
+  FineOp op32{&c, &L.F, WCMG_F32, &c.fw[1], st};
+  void* r = c.scratch_buf(33, spinor_bytes(WCMG_F64, g.Vh));
+  void* e = c.scratch_buf(34, spinor_bytes(WCMG_F64, g.Vh));
+  void* r32 = c.scratch_buf(35, spinor_bytes(WCMG_F32, g.Vh));
+  void* e32 = c.scratch_buf(36, spinor_bytes(WCMG_F32, g.Vh));
+  OpFn A32 = [&](void* o, const void* i) { op32.Dr(o, i); };
+  if (y_zero) blas_zero(WCMG_F64, y, n, st);
+  KrylovResult res;
+  const double target = tol * target_norm;
+  int ncyc = 0;
+  double prev = std::numeric_limits<double>::infinity();
+  for (;;) {
+    op64.Dr(r, y);
+    blas_axpby(WCMG_F64, 1.0, 0.0, b, -1.0, 0.0, r, n, st);  // r = b - D_r y
+    const double rn = std::sqrt(norm2(c, WCMG_F64, r, n));
+    res.rel_res = target_norm > 0 ? rn / target_norm : 0.0;
+    if (!finite(rn)) {
+      res.status = WCMG_ENAN;
+      break;
+    }
+    if (rn <= target) break;
+    if (res.iters >= maxiter || !(rn < prev)) {  // out of iterations, or a cycle that did not help
+      res.status = WCMG_ENOCONV;
+      break;
+    }
+    prev = rn;
+    blas_convert(WCMG_F32, r32, WCMG_F64, r, n, st);
+    blas_zero(WCMG_F32, e32, n, st);
+    // the inner solve stops at inner_tol, or at the outer target if that is looser
+    const double itol = std::max(inner_tol, 0.5 * target / rn);
+    KrylovResult k = bicgstab(c, WCMG_F32, n, A32, e32, r32, std::min(itol, 0.5), rn, maxiter - res.iters);
+    res.iters += k.iters;
+    ++ncyc;
+    if (k.status == WCMG_ENAN) {
+      res.status = WCMG_ENAN;
+      break;
+    }
+    blas_convert(WCMG_F64, e, WCMG_F32, e32, n, st);
+    blas_axpby(WCMG_F64, 1.0, 0.0, e, 1.0, 0.0, y, n, st);  // y += e
+  }
+  if (cycles) *cycles = ncyc;
+  return res;
+}
+
+// CGNR: conjugate gradients on the normal equations D_r^dag D_r y = D_r^dag b,
+// tracking the residual r = b - D_r y of the reduced system itself (the
+// other classical Krylov baseline of the Introduction's comparison); FP64.
+// Each iteration applies D_r and D_r^dag once.
+KrylovResult cgnr(Ctx& c, LatticeState& L, void* y, const void* b, bool y_zero, double tol, double target_norm,
+                  int maxiter) {
+  hipStream_t st = c.st;
+  const Geom& g = L.F.g;
+  const size_t n = (size_t)12 * g.Vh;
+  const size_t hb = spinor_bytes(WCMG_F64, g.Vh);
+  FineOp op{&c, &L.F, WCMG_F64, &c.fw[0], st};
+  void* r = c.scratch_buf(33, hb);
+  void* z = c.scratch_buf(34, hb);
+  void* p = c.scratch_buf(37, hb);
+  void* w = c.scratch_buf(38, hb);
+  Reducer& R = c.red;
+  KrylovResult res;
+  const double target = tol * target_norm;
+  if (y_zero) blas_zero(WCMG_F64, y, n, st);
+  auto restart = [&]() -> double {
+    op.Dr(r, y);
+    blas_axpby(WCMG_F64, 1.0, 0.0, b, -1.0, 0.0, r, n, st);  // r = b - D_r y
+    op.Dr_dag(z, r);
+    blas_copy(WCMG_F64, p, z, n, st);
+    return norm2(c, WCMG_F64, z, n);
+  };
+  double zz = restart();
+  double rn = std::sqrt(norm2(c, WCMG_F64, r, n));
+  int verifications = 0;
+  for (;;) {
+    res.rel_res = target_norm > 0 ? rn / target_norm : 0.0;
+    if (!finite(rn) || !finite(zz)) {
+      res.status = WCMG_ENAN;
+      break;
+    }
+    if (rn <= target) {
+      // confirm with the true residual (the recursion drifts over long runs)
+      zz = restart();
+      rn = std::sqrt(norm2(c, WCMG_F64, r, n));
+      if (rn <= target || ++verifications > 50) {
+        res.rel_res = target_norm > 0 ? rn / target_norm : 0.0;
+        if (rn > target) res.status = WCMG_ENOCONV;
+        break;
+      }
+      continue;
+    }
+    if (res.iters >= maxiter) {
+      res.status = WCMG_ENOCONV;
+      break;
+    }
+    if (!(zz > 0.0)) {
+      res.status = WCMG_EBREAKDOWN;
+      break;
+    }
+    op.Dr(w, p);
+    const double ww = norm2(c, WCMG_F64, w, n);
+    if (!(ww > 0.0)) {
+      res.status = WCMG_EBREAKDOWN;
+      break;
+    }
+    const double alpha = zz / ww;
+    blas_axpby(WCMG_F64, alpha, 0.0, p, 1.0, 0.0, y, n, st);  // y += alpha p
+    blas_axpy_norm(WCMG_F64, -alpha, 0.0, w, r, n, R.out(), st);  // r -= alpha w
+    rn = std::sqrt(R.fetch(1)[0]);
+    op.Dr_dag(z, r);
+    const double zz_new = norm2(c, WCMG_F64, z, n);
+    blas_axpby(WCMG_F64, 1.0, 0.0, z, zz_new / zz, 0.0, p, n, st);  // p = z + beta p
+    zz = zz_new;
+    ++res.iters;
+  }
+  return res;
+}
+
+// ---------------------------------------------------------------------------
 // coarse red-black GCR in one cooperative launch
 // ---------------------------------------------------------------------------
 bool persistent_available(PersistWork& w, int prec, const CoarseLevel& C, int restart) {
   if (!C.cg.split || restart < 1 || restart > kMaxRestart) return false;
   if (w.grid < 0) w.grid = coarse_gcr_persistent_grid(prec, C.cg.n, C.cg.Vh);
   return w.grid > 0;
+}
+
+void persistent_launch_bufs(Ctx& c, int grid, const PersistBufs& B, CoarseLevel& C, int prec, void* out,
+                            const void* in, void* t, void* y, void* r, void* br, double tol, int restart,
+                            int maxiter, bool fixed, bool general) {
+  CoarseGcrArgs a{};
+  const int pi = prec == WCMG_F64 ? 0 : 1;
+  a.Yt = C.Yt[pi].p;
+  a.Xinv = C.Xinv[pi].p;
+  a.nbr = C.nbr.as<int>();
+  a.b = in;
+  a.c = out;
+  a.t = t;
+  a.y = y;
+  a.r = r;
+  a.br = br;
+  a.Q = B.Q;
+  a.Z = B.Z;
+  a.T = B.T;
+  a.qraw = B.qraw;
+  a.part = B.part;
+  a.bar = reinterpret_cast<unsigned*>(B.ctl);
+  a.info = reinterpret_cast<int*>(reinterpret_cast<char*>(B.ctl) + kPersistInfoOffset);
+  a.tol = tol;
+  a.Vh = C.cg.Vh;
+  a.n = C.cg.n;
+  a.restart = restart;
+  a.maxiter = maxiter;
+  a.fixed = fixed ? 1 : 0;
+  a.grid = grid;
+  a.general = general ? 1 : 0;
+  launch_coarse_gcr_persistent(prec, a, c.st);
 }
 
 void persistent_launch(Ctx& c, PersistWork& w, CoarseLevel& C, int prec, void* out, const void* in, void* t, void* y,
@@ -429,33 +595,8 @@ void persistent_launch(Ctx& c, PersistWork& w, CoarseLevel& C, int prec, void* o
     w.ctl.alloc(kPersistCtlBytes);
     HIPCHK(hipMemsetAsync(w.ctl.p, 0, kPersistCtlBytes, c.st));
   }
-  CoarseGcrArgs a{};
-  const int pi = prec == WCMG_F64 ? 0 : 1;
-  a.Yt = C.Yt[pi].p;
-  a.Xinv = C.Xinv[pi].p;
-  a.nbr = C.nbr.as<int>();
-  a.b = in;
-  a.c = out;
-  a.t = t;
-  a.y = y;
-  a.r = r;
-  a.br = br;
-  a.Q = w.q.p;
-  a.Z = w.z.p;
-  a.T = w.t.p;
-  a.qraw = w.qraw.p;
-  a.part = w.part.as<double>();
-  a.bar = w.ctl.as<unsigned>();
-  a.info = reinterpret_cast<int*>(w.ctl.as<char>() + kPersistInfoOffset);
-  a.tol = tol;
-  a.Vh = C.cg.Vh;
-  a.n = C.cg.n;
-  a.restart = restart;
-  a.maxiter = maxiter;
-  a.fixed = fixed ? 1 : 0;
-  a.grid = w.grid;
-  a.general = general ? 1 : 0;
-  launch_coarse_gcr_persistent(prec, a, c.st);
+  PersistBufs B{w.q.p, w.z.p, w.t.p, w.qraw.p, w.part.as<double>(), w.ctl.p};
+  persistent_launch_bufs(c, w.grid, B, C, prec, out, in, t, y, r, br, tol, restart, maxiter, fixed, general);
   w.pending = true;
 }
 
@@ -661,9 +802,16 @@ struct MGSolver {
   }
 
   // iterations the persistent coarse solves counted on the device (raises
-  // if one of them lost its grid barrier)
-  void collect_device_stats() {
-    for (Level& V : lv) V.iters += persistent_collect(c, V.pw);
+  // if one of them lost its grid barrier); returns the first failure code
+  // they reported (breakdown, NaN), WCMG_OK when none did
+  int collect_device_stats() {
+    int first = WCMG_OK;
+    for (Level& V : lv) {
+      int code = WCMG_OK;
+      V.iters += persistent_collect(c, V.pw, &code);
+      if (code != WCMG_OK && first == WCMG_OK) first = code;
+    }
+    return first;
   }
 
   // MR smoothing of e towards D_r e = r on the even half of n elements
@@ -1440,17 +1588,26 @@ void solve_rhs(Ctx& c, LatticeState& L, int solver, void* x_e, void* x_o, const 
   const wcmg_mg_params& p = L.params;
   const int restart = L.have_params ? p.outer_restart : 16;
   const int maxiter = L.have_params ? p.outer_max_iter : 100000;
+  // cap of the unpreconditioned solvers
+  const int plain_cap = L.have_params && p.plain_max_iter > 0 ? p.plain_max_iter : 100000;
   KrylovResult kr;
   if (solver == WCMG_BICGSTAB) {
     if (x_zero) blas_zero(WCMG_F64, y, n, st);
-    kr = bicgstab(c, WCMG_F64, n, Dr, y, br, tol, bn, L.have_params ? std::max(maxiter, 100000) : 100000);
+    kr = bicgstab(c, WCMG_F64, n, Dr, y, br, tol, bn, plain_cap);
+  } else if (solver == WCMG_MP_BICGSTAB) {
+    int cycles = 0;
+    const double itol = L.have_params && p.mp_inner_tol > 0 ? p.mp_inner_tol : 1e-3;
+    kr = mp_bicgstab(c, L, y, br, x_zero, tol, bn, plain_cap, itol, &cycles);
+    s.inner_iters[0] = cycles;
+  } else if (solver == WCMG_CGNR) {
+    kr = cgnr(c, L, y, br, x_zero, tol, bn, plain_cap);
   } else {
     GcrSpace& S64 = c.outer;
     S64.prec = WCMG_F64;
     S64.n = n;
     S64.bytes = hb;
     if (solver == WCMG_GCR) {
-      kr = gcr(c, S64, Dr, nullptr, y, br, x_zero, tol, bn, restart, L.have_params ? std::max(maxiter, 100000) : 100000);
+      kr = gcr(c, S64, Dr, nullptr, y, br, x_zero, tol, bn, restart, plain_cap);
     } else {
       require_hierarchy(L);
       if (!L.mg) L.mg = std::make_shared<MGSolver>(c, L);
@@ -1459,7 +1616,7 @@ void solve_rhs(Ctx& c, LatticeState& L, int solver, void* x_e, void* x_o, const 
       for (auto& lvl : mg.lv) lvl.calls = lvl.iters = 0;
       OpFn K = [&](void* o, const void* i) { mg.precondition(o, i); };
       kr = gcr(c, S64, Dr, &K, y, br, x_zero, tol, bn, restart, maxiter);
-      mg.collect_device_stats();
+      s.inner_status = mg.collect_device_stats();
       for (size_t l = 0; l < mg.lv.size() && l < 3; ++l)
         s.inner_iters[l] = mg.lv[l].calls ? (double)mg.lv[l].iters / mg.lv[l].calls : 0.0;
     }
@@ -1526,7 +1683,7 @@ void solve_batch(Ctx& c, LatticeState& L, void* x_e, void* x_o, const void* b_e,
     if (v == 0.0) v = 1.0;
   std::vector<KrylovResult> kr = gcr_b(c, outer, Dr, &K, y, br, x_zero, tol, tn.data(), p.outer_restart,
                                        p.outer_max_iter);
-  mg.collect_device_stats();
+  const int inner_status = mg.collect_device_stats();
   op.reconstruct(x_e, x_o, y, b_o, nrhs);
   // true residuals of the full system in FP64
   void* te = c.scratch_buf(2, hb * nrhs);
@@ -1542,6 +1699,7 @@ void solve_batch(Ctx& c, LatticeState& L, void* x_e, void* x_o, const void* b_e,
     wcmg_stats s{};
     s.iters = kr[i].iters;
     s.status = kr[i].status;
+    s.inner_status = inner_status;
     s.true_rel_res = bn[i] > 0 ? std::sqrt(h[i] + h[32 + i]) / bn[i] : 0.0;
     for (size_t l = 0; l < mg.lv.size() && l < 3; ++l)
       s.inner_iters[l] = mg.lv[l].calls ? (double)mg.lv[l].iters / mg.lv[l].calls : 0.0;

@@ -1,0 +1,159 @@
+"""The C ABI's all-lattice forms and the paper's comparison solvers.
+
+* lat = -1 applies (every operator form, D and D^dag, two right-hand sides):
+  one launch per kernel over all lattices, bitwise equal to the per-lattice
+  applies;
+* lat = -1 solve: every lattice and right-hand side of the context in one
+  call, bitwise equal to the per-lattice solves and at an oracle residual of
+  1e-10 (the oracle's own FP64 D);
+* the paper's comparison solvers (Implementation paragraph): mixed-precision
+  BiCGStab (FP32 BiCGStab inside FP64 iterative refinement) and CGNR reach the
+  oracle residual 1e-10 and the dense / oracle solution.
+"""
+import numpy as np
+import pytest
+import torch
+
+import inputs
+from oracle.dirac import WilsonClover
+from oracle.krylov import norm
+
+pytestmark = pytest.mark.gpu
+
+w = pytest.importorskip("paper_1011_2775_amd")
+
+SPECS = [((4, 4, 4, 8), -1), ((8, 4, 4, 8), -1), ((8, 8, 8, 8), 1)]
+
+
+def canon(v, dims, nrhs=1):
+    return torch.from_numpy(np.ascontiguousarray(v).reshape((nrhs,) + tuple(reversed(dims)) + (4, 3))).cuda()
+
+
+@pytest.fixture(scope="module")
+def multi():
+    ctx = w.Context(SPECS)
+    ops = []
+    for l, (dims, tbc) in enumerate(SPECS):
+        U = inputs.gauge_field(dims, 0.4, 1200 + l)
+        ctx.set_gauge(torch.from_numpy(U).cuda(), lat=l)
+        m0 = -0.1 - 0.05 * l
+        ctx.set_clover(m0, 1.0, lat=l)
+        ops.append(WilsonClover(dims, U, m0, 1.0, tbc))
+    yield ctx, ops
+    ctx.close()
+
+
+@pytest.mark.parametrize("op", ["FULL", "SCHUR", "DP"])
+@pytest.mark.parametrize("dag", [False, True])
+def test_all_lattice_apply_matches_per_lattice(multi, op, dag):
+    ctx, ops = multi
+    rng = np.random.default_rng(7)
+    nrhs = 2
+    parts = [rng.standard_normal((nrhs, o.lat.V, 4, 3)) + 1j * rng.standard_normal((nrhs, o.lat.V, 4, 3))
+             for o in ops]
+    flat = torch.from_numpy(np.concatenate([p.reshape(-1) for p in parts])).cuda()
+    fn = ctx.apply_Ddag if dag else ctx.apply_D
+    for prec in (w.F64, w.F32):
+        got = fn(flat, getattr(w, "OP_" + op), prec, lat=-1).cpu().numpy()
+        off = 0
+        for l, (dims, _) in enumerate(SPECS):
+            n = nrhs * ops[l].lat.V * 12
+            want = fn(canon(parts[l], dims, nrhs), getattr(w, "OP_" + op), prec, lat=l).cpu().numpy().reshape(-1)
+            assert np.array_equal(got[off:off + n], want), (op, dag, prec, l)
+            off += n
+
+
+def test_all_lattice_adjoint_matches_oracle(multi):
+    """D^dag on the all-lattice path against the oracle's explicit adjoint."""
+    ctx, ops = multi
+    rng = np.random.default_rng(8)
+    parts = [rng.standard_normal((o.lat.V, 4, 3)) + 1j * rng.standard_normal((o.lat.V, 4, 3)) for o in ops]
+    flat = torch.from_numpy(np.concatenate([p.reshape(-1) for p in parts])).cuda()
+    got = ctx.apply_Ddag(flat, w.OP_FULL, w.F64, lat=-1).cpu().numpy()
+    off = 0
+    for o, p in zip(ops, parts):
+        n = o.lat.V * 12
+        want = o.apply_Ddag(p).reshape(-1)
+        assert np.abs(got[off:off + n] - want).max() < 1e-13 * np.abs(want).max()
+        off += n
+
+
+def test_all_lattice_solve(multi):
+    ctx, ops = multi
+    nrhs = 2
+    for l, (dims, _) in enumerate(SPECS):
+        ctx.set_mg_params(w.default_params(block=[(2, 2, 2, 2)], nvec=[8], seed=3100 + l), lat=l)
+        ctx.build_null_vectors(lat=l)
+        ctx.build_coarse(lat=l)
+    bs = [np.stack([inputs.z2_source(dims, 2300 + 10 * l + r) for r in range(nrhs)]) for l, (dims, _) in
+          enumerate(SPECS)]
+    flat = torch.from_numpy(np.concatenate([b.reshape(-1) for b in bs])).cuda()
+    print("all-lattice solve: %d lattices x %d right-hand sides" % (len(SPECS), nrhs), flush=True)
+    x, st = ctx.solve(flat, w.MG_GCR, 1e-10, lat=-1)
+    assert len(st) == len(SPECS) * nrhs and all(s["status"] == "OK" for s in st)
+    x = x.cpu().numpy()
+    off = 0
+    for l, (dims, _) in enumerate(SPECS):
+        o = ops[l]
+        n = nrhs * o.lat.V * 12
+        xl, _ = ctx.solve(canon(bs[l], dims, nrhs), w.MG_GCR, 1e-10, lat=l)
+        assert np.array_equal(x[off:off + n], xl.cpu().numpy().reshape(-1)), l
+        for r in range(nrhs):
+            xr = x[off + r * o.lat.V * 12: off + (r + 1) * o.lat.V * 12].reshape(o.shape)
+            br = bs[l][r].reshape(o.shape)
+            assert norm(br - o.apply_D(xr)) / norm(br) <= 1e-10, (l, r)
+        off += n
+
+
+@pytest.fixture(scope="module")
+def c1():
+    cfg = inputs.config("c1_4x4x4x4")
+    dims = cfg["dims"]
+    U = inputs.gauge_field(dims, cfg["eps"], cfg["gauge_seed"])
+    op = WilsonClover(dims, U, cfg["m0"][0], cfg["csw"])
+    ctx = w.Context(dims)
+    ctx.set_gauge(torch.from_numpy(U).cuda())
+    ctx.set_clover(cfg["m0"][0], cfg["csw"])
+    b = inputs.z2_source(dims, cfg["source_seeds"][0])
+    xd = np.linalg.solve(op.dense(op.apply_D), b.reshape(-1)).reshape(op.shape)
+    yield cfg, op, ctx, b, xd
+    ctx.close()
+
+
+@pytest.mark.parametrize("solver", ["MP_BICGSTAB", "CGNR"])
+def test_comparison_solvers_c1(c1, solver):
+    cfg, op, ctx, b, xd = c1
+    x, st = ctx.solve(canon(b, cfg["dims"]), getattr(w, solver), 1e-10)
+    xr = x.cpu().numpy().reshape(op.shape)
+    bb = b.reshape(op.shape)
+    res = norm(bb - op.apply_D(xr)) / norm(bb)
+    print("%s: %d iterations, cycles %s, oracle residual %.2e" % (solver, st[0]["iters"], st[0]["inner_iters"][0],
+                                                                  res), flush=True)
+    assert st[0]["status"] == "OK" and res <= 1e-10
+    assert norm(xr - xd) / norm(xd) < 1e-8
+    if solver == "MP_BICGSTAB":
+        assert st[0]["inner_iters"][0] >= 2  # FP32 cannot reach 1e-10 in one refinement cycle
+
+
+@pytest.mark.parametrize("solver", ["MP_BICGSTAB", "CGNR", "BICGSTAB"])
+def test_comparison_solvers_8x8x8x8(solver):
+    cfg = inputs.config("c4_8x8x8x8")
+    dims = cfg["dims"]
+    U = inputs.gauge_field(dims, cfg["eps"], cfg["gauge_seed"], ape_sweeps=cfg["ape"])
+    m0 = cfg["m0"][0]
+    op = WilsonClover(dims, U, m0, cfg["csw"])
+    ctx = w.Context(dims)
+    try:
+        ctx.set_gauge(torch.from_numpy(U).cuda())
+        ctx.set_clover(m0, cfg["csw"])
+        ctx.set_mg_params(w.default_params(plain_max_iter=20000, mp_inner_tol=1e-4))
+        b = inputs.gaussian_source(dims, 2400)
+        x, st = ctx.solve(canon(b, dims), getattr(w, solver), 1e-10)
+        xr = x.cpu().numpy().reshape(op.shape)
+        bb = b.reshape(op.shape)
+        res = norm(bb - op.apply_D(xr)) / norm(bb)
+        print("%s 8^4: %d iterations, oracle residual %.2e" % (solver, st[0]["iters"], res), flush=True)
+        assert st[0]["status"] == "OK" and res <= 1e-10
+        assert abs(st[0]["true_rel_res"] - res) < 1e-3 * res + 1e-14
+    finally:
+        ctx.close()
