@@ -18,6 +18,10 @@ Follows the paper's description:
   relative tolerance (about 0.1 is reported best).
 * the smoother (type not given) is MR on the level's reduced operator,
   applied after the coarse correction.
+* the adaptive refinement the Setup section describes as the alphaSA idea
+  (relax with a cycle built from the vectors at hand) combined with the
+  inverse-iteration setup ("hybrid"); the paper leaves its details open, so
+  it is parity unpinned (invariants only, like the setup itself).
 
 Coarse fields are arrays [Vc][2*Nv]; coarse component s*Nv + k has chirality
 s (s = 0 for gamma5 = +1).  The coarse operator is stored as
@@ -335,6 +339,7 @@ class Hierarchy:
         self.params = params
         self.ops = [op]
         self.transfers = []
+        self.raw = []  # the vectors each level's P was built from
         for l, (blk, nv) in enumerate(zip(params.blocks, params.nvec)):
             cur = self.ops[-1]
             if vecs is not None and vecs[l] is not None:
@@ -345,6 +350,7 @@ class Hierarchy:
                                        delta=params.delta)
             T = Transfer(cur, blk, v)
             Y = coarse_operator(cur, T)
+            self.raw.append(np.asarray(v, dtype=np.complex128).reshape((-1,) + cur.shape))
             self.transfers.append(T)
             self.ops.append(CoarseOperator(T.cdims, Y))
         self.inner_iters = [0] * len(self.ops)
@@ -389,3 +395,34 @@ class Hierarchy:
         y = gcr(op.apply_Dr, br, tol=tol, target_norm=norm(b), restart=p.outer_restart,
                 maxiter=p.outer_maxiter, precond=lambda r: self.precond(0, r), info=info)
         return op.reconstruct(y, b)
+
+
+def refine_null_vectors(H, passes=1, iters=4):
+    """Adaptive refinement of the fine null vectors (Setup section; parity
+    unpinned).  Each pass relaxes every vector v with `iters` steps of GCR on
+    the homogeneous reduced system D_r y = 0, started from y = v_e and
+    preconditioned by the current cycle; the odd half then follows from
+    D_p v = 0, i.e. v_o = -D_oe D_ee^-1 v_e; the vectors are orthonormalised
+    in order (twice) and the hierarchy is rebuilt on them (coarser levels
+    keep their own vectors).  Returns the new Hierarchy."""
+    op = H.ops[0]
+    lat = op.lat
+    for _ in range(passes):
+        new = []
+        for v in H.raw[0]:
+            ye = np.zeros(op.shape, dtype=np.complex128)
+            ye[lat.even] = v[lat.even]
+            y = gcr(op.apply_Dr, np.zeros(op.shape, dtype=np.complex128), x0=ye, tol=0.0,
+                    restart=max(H.params.outer_restart, iters), maxiter=iters,
+                    precond=lambda r: H.precond(0, r))
+            w = np.zeros(op.shape, dtype=np.complex128)
+            w[lat.even] = y[lat.even]
+            z = op.apply_Ainv(w, lat.even)
+            w[lat.odd] = -op.apply_H(z, lat.odd)[lat.odd]
+            for _rep in range(2):
+                for u in new:
+                    w = w - np.vdot(u, w) * u
+            new.append(w / norm(w))
+        vecs = [np.stack(new)] + H.raw[1:]
+        H = Hierarchy(op, H.params, vecs=vecs)
+    return H
