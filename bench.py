@@ -1,20 +1,29 @@
 #!/usr/bin/env python3
 """Time-to-solution of the multigrid-preconditioned GCR against plain FP64
-BiCGStab for the Wilson-clover equation, and the fine Dslash roofline.
+BiCGStab for the Wilson-clover equation, the fine red-black Dslash against
+the HBM roofline, and the batched multi-right-hand-side solve.
 
-Workload: 16^3x32 lattice, links exp(0.5 i H) followed by 5 APE sweeps
-(alpha 0.5), csw = 1.0, m0 swept over {-0.15, -0.25, -0.30}, 4^4 blocks,
-Nv = 24, FP32 preconditioner inside an FP64 outer GCR, one Z2 source,
-stopping at a true relative residual of 1e-10.  One step = one MG-GCR solve
-of the source at every mass of the sweep; the setup (null vectors and
-coarse operator) happens before the timed region, as in the paper's
-speedups.  All inputs are synthetic and seeded.
+Headline workload (`value`): 16^3x32 lattice, links exp(0.5 i H) followed by
+5 APE sweeps (alpha 0.5), csw = 1.0, m0 swept over {-0.15, -0.25, -0.30},
+4^4 blocks, Nv = 24, FP32 preconditioner inside an FP64 outer GCR, one Z2
+source, stopping at a true relative residual of 1e-10.  One step = one
+MG-GCR solve of the source at every mass of the sweep; the setup (null
+vectors and coarse operator) happens before the timed region, as in the
+paper's speedups.  All inputs are synthetic and seeded.
 
-The smoothed synthetic field has its critical mass near m0 = -0.03, so the
-sweep's masses lie beyond it, where plain FP64 BiCGStab's convergence is
-erratic: each comparison is marked equal-accuracy when it converged and a
-lower bound when it stopped at its iteration cap.  The near-critical mass
-m0 = -0.02 is reported beside the headline value.
+Beside it, in the same JSON line:
+* the near-critical mass m0 = -0.02 of the same field (equal-accuracy
+  comparison with plain FP64 BiCGStab and the paper's comparison solver,
+  mixed-precision BiCGStab);
+* the fine D_r at 24^3x64 and 32^3x64 (F64, F32, F16; 1 and 12 right-hand
+  sides): all three kernels of one apply timed with HIP events, bandwidth
+  from the compulsory bytes per even site (4416 / 2208 / 1104 + scales B for
+  one right-hand side), against 8 TB/s and against a measured device copy;
+* the batched workload: 24^3x64, 12 Z2 sources solved in lockstep, at the
+  configuration's m0 = -0.25 (where plain BiCGStab does not converge on this
+  field: lower bound) and at m0 = -0.008, where FP64 BiCGStab converges in
+  about 2100 iterations (equal accuracy, every source);
+* the oracle (FP64 NumPy) timed on the host cores.
 
 Prints ONE JSON line.  --gpus N with N > 1 is refused: this measures one GPU.
 """
@@ -22,6 +31,7 @@ import argparse
 import json
 import os
 import resource
+import subprocess
 import sys
 import time
 
@@ -29,18 +39,42 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+PEAK_FP16_MFMA_TFLOPS = 2500.0
+BATCHED_EQUAL_ACCURACY_M0 = -0.008  # FP64 BiCGStab: about 2100 iterations on the 24^3x64 field
+
+
+def real_size(prec):
+    return {0: 8, 1: 4, 2: 2}[prec]
 
 
 def dslash_bytes_per_site(prec, diag, postinv):
     """Compulsory HBM bytes per output site of one hop launch (single RHS):
     neighbour spinor field once, all 8 links touching the site's parity
     once, the output, the DIAG input and clover blocks when used."""
-    size = {0: 8, 1: 4, 2: 2}[prec]
+    size = real_size(prec)
     reals = 24 + 144 + 24 + (24 if diag >= 1 else 0) + (72 if diag == 2 else 0) + (72 if postinv else 0)
     b = reals * size
     if prec == 2:  # one FP32 scale per spinor site read or written
         b += 4 * (2 + (1 if diag >= 1 else 0))
     return b
+
+
+def clover_bytes_per_site(prec):
+    """One site-local clover launch: spinor in and out, one 72-real record."""
+    b = (24 + 24 + 72) * real_size(prec)
+    return b + (8 if prec == 2 else 0)
+
+
+def dr_compulsory_bytes(prec, nrhs=1):
+    """Compulsory bytes of D_r per even site and right-hand side: five spinor
+    passes (y read twice is counted once per kernel that needs it: y, the
+    intermediate written and read, the output), both parities' links (8 per
+    site) and both clover records, the fields shared by nrhs right-hand
+    sides.  One RHS: FP64 4416, FP32 2208, FP16 1104 (+20 B of scales)."""
+    size = real_size(prec)
+    fields = (2 * 8 * 18 + 2 * 72) * size
+    spinors = 5 * 24 * size + (20 if prec == 2 else 0)
+    return fields / nrhs + spinors
 
 
 def dslash_flops_per_site(diag, postinv):
@@ -62,11 +96,14 @@ def coarse_step_bytes(coarse_sites_h, coarse_n, cs=8):
     return coarse_sites_h * (2 * 8 * coarse_n * coarse_n + 10 * coarse_n) * cs
 
 
+PREC_NAMES = ["double", "float", "__half"]
+
+
 def kernel_table(ctxs, vh, coarse_sites_h, coarse_n, coarse_steps=0):
     """Per timed kernel id: launches, mean duration, algorithmic bytes per launch.
     coarse_steps: GCR steps the persistent coarse solves took in total."""
     rows = []
-    for kid in list(range(18)) + [20, 21, 28]:
+    for kid in list(range(18)) + [20, 21, 28] + [64, 65, 66]:
         n, ms = 0, 0.0
         for c in ctxs:
             cn, cms = c.timer_read(kid)
@@ -77,9 +114,14 @@ def kernel_table(ctxs, vh, coarse_sites_h, coarse_n, coarse_steps=0):
         if kid < 18:
             prec, rest = divmod(kid, 6)
             diag, postinv = divmod(rest, 2)
-            name = "dslash_kernel<%s,%d,%s>" % (["double", "float", "__half"][prec], diag, str(bool(postinv)).lower())
+            name = "dslash_kernel<%s,%d,%s>" % (PREC_NAMES[prec], diag, str(bool(postinv)).lower())
             bytes_launch = dslash_bytes_per_site(prec, diag, postinv) * vh
             flops = dslash_flops_per_site(diag, postinv) * vh
+        elif kid >= 64:
+            prec = kid - 64
+            name = "clover_kernel<%s>" % PREC_NAMES[prec]
+            bytes_launch = clover_bytes_per_site(prec) * vh
+            flops = 504 * vh
         elif kid == 28:
             # the whole coarse solve in one launch: bytes and flops of its GCR steps (the
             # one-site kernel when every workgroup of the 256 owns one even site)
@@ -104,9 +146,10 @@ def kernel_table(ctxs, vh, coarse_sites_h, coarse_n, coarse_steps=0):
 KERNEL_SOURCES = {"k_coarse_gcr<float>": ["coarse_persist.hip"],
                   "k_coarse_gcr_site<float>": ["coarse_persist.hip"],
                   "k_coarse_hop<float, 1>": ["coarse.hip"]}
-for _p in ("double", "float", "__half"):
+for _p in PREC_NAMES:
     for _k in ("0,true", "1,false"):
         KERNEL_SOURCES["dslash_kernel<%s,%s>" % (_p, _k)] = ["dslash.hip"]
+    KERNEL_SOURCES["clover_kernel<%s>" % _p] = ["dslash.hip"]
 
 
 def measured_traffic(kernel):
@@ -130,91 +173,219 @@ def measured_traffic(kernel):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(dims, U, m0, csw, b, bicg_iters_gpu):
-    """Oracle (FP64 NumPy) BiCGStab on the same D_r, timed for a few iterations
-    on the host and scaled to the iteration count the solve needs."""
-    from oracle.dirac import WilsonClover
-    from oracle.krylov import bicgstab, norm, SolveInfo
-    op = WilsonClover(dims, U, m0, csw)
-    bb = b.reshape(op.shape)
-    br = op.reduced_source(bb)
-    iters = 8
-    r0 = resource.getrusage(resource.RUSAGE_SELF)
-    t0 = time.perf_counter()
-    info = SolveInfo()
-    bicgstab(op.apply_Dr, br, tol=1e-10, target_norm=norm(bb), maxiter=iters, info=info)
-    wall = time.perf_counter() - t0
-    r1 = resource.getrusage(resource.RUSAGE_SELF)
-    cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
-    per_iter = wall / max(info.iters, 1)
-    return {"value": round(per_iter * bicg_iters_gpu, 3), "unit": "s", "cores": max(1, round(cpu / wall)),
-            "kind": "oracle",
-            "sample": "%d iterations of the FP64 NumPy oracle BiCGStab on D_r (16^3x32, m0=%g) in %.1f s, scaled "
-                      "by the %d iterations the same FP64 BiCGStab needs to reach 1e-10; host has %d cores"
-                      % (info.iters, m0, wall, bicg_iters_gpu, os.cpu_count() or 0)}
-
-
-def dslash_headline(w, torch, inputs, dims=(24, 24, 24, 64)):
-    """Fine D_r applies on a lattice whose working set exceeds the 256 MB
-    Infinity Cache (24^3x64; 32^3x64 as a second point): per-launch duration
-    and compulsory-byte bandwidth.  Protocol: 10 warm-up applies, then 5
-    trials of 100 applies, the median trial reported."""
+# ---------------------------------------------------------------------------- oracle (CPU) timing
+def oracle_sample(U2=None):
+    """Timings of the FP64 NumPy oracle on the host (run in this process with
+    every BLAS/OpenMP thread, or in a child with one): the full multigrid
+    GCR solve (setup and solve) and plain BiCGStab on the 4^4 workload, and
+    -- when the 16^3x32 field is given -- one D_r apply and two BiCGStab
+    iterations on 16^3x32 at m0 = -0.25."""
     import numpy as np
-    U = inputs.random_links(dims, 0.5, 1003)
+    import inputs
+    from oracle import multigrid as mg
+    from oracle.dirac import WilsonClover
+    from oracle.krylov import SolveInfo, bicgstab, norm
+    out = {}
+    r0 = resource.getrusage(resource.RUSAGE_SELF)
+    w0 = time.perf_counter()
+    c1 = inputs.config("c1_4x4x4x4")
+    U1 = inputs.gauge_field(c1["dims"], c1["eps"], c1["gauge_seed"])
+    op1 = WilsonClover(c1["dims"], U1, c1["m0"][0], c1["csw"])
+    b1 = inputs.z2_source(c1["dims"], c1["source_seeds"][0])
+    t = time.perf_counter()
+    H = mg.Hierarchy(op1, mg.MGParams(c1["blocks"], c1["nvec"], seed=c1["setup_seed"]))
+    out["c1_mg_setup_s"] = time.perf_counter() - t
+    t = time.perf_counter()
+    info = SolveInfo()
+    x = H.solve(b1, tol=c1["tol"], info=info)
+    out["c1_mg_gcr_solve_s"] = time.perf_counter() - t
+    out["c1_mg_gcr_outer_iters"] = info.iters
+    out["c1_mg_gcr_rel_res"] = norm(b1.reshape(op1.shape) - op1.apply_D(x)) / norm(b1)
+    t = time.perf_counter()
+    info = SolveInfo()
+    bb = b1.reshape(op1.shape)
+    bicgstab(op1.apply_Dr, op1.reduced_source(bb), tol=c1["tol"], target_norm=norm(bb), maxiter=10000, info=info)
+    out["c1_bicgstab_s"] = time.perf_counter() - t
+    out["c1_bicgstab_iters"] = info.iters
+    if U2 is not None:
+        c2 = inputs.config("c2_16x16x16x32")
+        t = time.perf_counter()
+        op2 = WilsonClover(c2["dims"], U2, -0.25, c2["csw"])
+        out["c2_operator_build_s"] = time.perf_counter() - t
+        b2 = inputs.z2_source(c2["dims"], c2["source_seeds"][0]).reshape(op2.shape)
+        br = op2.reduced_source(b2)
+        t = time.perf_counter()
+        op2.apply_Dr(br)
+        out["c2_dr_apply_s"] = time.perf_counter() - t
+        info = SolveInfo()
+        t = time.perf_counter()
+        bicgstab(op2.apply_Dr, br, tol=1e-10, target_norm=norm(b2), maxiter=2, info=info)
+        out["c2_bicgstab_s_per_iter"] = (time.perf_counter() - t) / max(info.iters, 1)
+    r1 = resource.getrusage(resource.RUSAGE_SELF)
+    wall = time.perf_counter() - w0
+    out["wall_s"] = wall
+    out["threads_used"] = ((r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)) / wall
+    return out
+
+
+def cpu_baseline(U2, bicg_iters_gpu, m0):
+    """The oracle on the host: all threads in this process, one thread in a
+    child process (thread counts fixed before NumPy loads)."""
+    allc = oracle_sample(U2)
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    one = None
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--oracle-sample"], capture_output=True,
+                       text=True, env=env, timeout=600)
+    if p.returncode == 0 and p.stdout.strip():
+        one = json.loads(p.stdout.strip().splitlines()[-1])
+    per_iter = allc["c2_bicgstab_s_per_iter"]
+    return {"value": round(per_iter * bicg_iters_gpu, 2), "unit": "s", "cores": max(1, round(allc["threads_used"])),
+            "kind": "oracle",
+            "sample": "FP64 NumPy oracle on the host (%d cores visible): 2 BiCGStab iterations on D_r at 16^3x32, "
+                      "m0=%g (%.2f s each), scaled by the %d iterations the GPU's FP64 BiCGStab needs to reach "
+                      "1e-10 (extrapolated); measured in full: the 4^4 multigrid GCR solve and BiCGStab, one "
+                      "16^3x32 D_r apply" % (os.cpu_count() or 0, m0, per_iter, bicg_iters_gpu),
+            "all_threads": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in allc.items()},
+            "one_thread": ({k: (round(v, 4) if isinstance(v, float) else v) for k, v in one.items()} if one else
+                           None),
+            "c3_dr_apply_s_scaled": round(allc["c2_dr_apply_s"] * (24 ** 3 * 64) / (16 ** 3 * 32), 2),
+            "c3_dr_apply_note": "16^3x32 D_r apply scaled by the volume ratio 6.75 (the oracle's work is linear "
+                                "in the volume)"}
+
+
+# ---------------------------------------------------------------------------- bandwidth
+def copy_ceiling(torch, nbytes=1 << 30, reps=20):
+    """Achieved GB/s (bytes read + written) of a plain device copy (torch)."""
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return round(2 * nbytes / (ms * 1e-3) / 1e9, 1)
+
+
+def dslash_headline(w, torch, inputs, dims=(24, 24, 24, 64), nrhs_list=(1, 12), ceiling=None):
+    """Fine red-black operator applies on a lattice whose working set exceeds
+    the 256 MB Infinity Cache, in both forms of the reduced system: D_r
+    (three launches: clover inverse, hop with the clover inverse fused, hop
+    with the diagonal input fused) and D_r D_ee (two launches: hop with
+    D_oo^-1 fused, hop with D_ee x fused), every launch of an apply timed with
+    HIP events on the library stream; bandwidth from the compulsory bytes of
+    the reduced operator (dr_compulsory_bytes), which both forms share.
+    Protocol: 10 warm-up applies, then 5 trials of 40 applies (12 right-hand
+    sides: 3 trials of 10), the median trial."""
+    U = inputs.gauge_field_torch(dims, 0.5, 1003, device="cuda")
     ctx = w.Context(dims)
-    ctx.set_gauge(torch.from_numpy(U).cuda())
+    ctx.set_gauge(U)
     del U
     ctx.set_clover(-0.25, 1.0)
-    g = torch.Generator(device="cuda").manual_seed(1)
-    v = torch.randn((1,) + tuple(reversed(dims)) + (4, 3), dtype=torch.complex128, device="cuda", generator=g)
-    out = {}
     vh = inputs.volume(dims) // 2
-    for prec, name in ((w.F64, "f64"), (w.F32, "f32"), (w.F16, "f16")):
-        for _ in range(10):
-            ctx.apply_D(v, w.OP_SCHUR, prec)
-        torch.cuda.synchronize()
-        trials = []
-        for _ in range(5):
-            ctx.timer_enable(True)
-            for _ in range(100):
-                ctx.apply_D(v, w.OP_SCHUR, prec)
-            rows = kernel_table([ctx], vh, 0, 0)
-            ctx.timer_enable(False)
-            tot_b = sum(r["bytes_per_launch"] * r["launches"] for r in rows)
-            tot_ms = sum(r["total_ms"] for r in rows)
-            trials.append((tot_b / (tot_ms * 1e-3) / 1e9, rows))
-        trials.sort(key=lambda t: t[0])
-        gbps, rows = trials[len(trials) // 2]
-        for r in rows:
-            r["traffic_bytes_per_launch"] = measured_traffic(r["kernel"]) if dims == (24, 24, 24, 64) else None
-        out[name] = {"GBps": round(gbps, 1), "frac_of_8TBps": round(gbps / PEAK_HBM_GBS, 3),
-                     "trials_GBps": [round(t[0], 1) for t in trials],
-                     "kernels": [{k: r[k] for k in ("kernel", "avg_us", "GBps", "bytes_per_launch",
-                                                    "traffic_bytes_per_launch")} for r in rows]}
+    out = {}
+    g = torch.Generator(device="cuda").manual_seed(1)
+    for nrhs in nrhs_list:
+        v = torch.randn((nrhs,) + tuple(reversed(dims)) + (4, 3), dtype=torch.complex128, device="cuda",
+                        generator=g)
+        batch = nrhs > 1
+        base = 32 if batch else 0
+        for opname, op in (("", w.OP_SCHUR), ("x_", w.OP_SCHUR_X)):
+            for prec, name in ((w.F64, "f64"), (w.F32, "f32"), (w.F16, "f16")):
+                for _ in range(10 if not batch else 2):
+                    ctx.apply_D(v, op, prec)
+                torch.cuda.synchronize()
+                if op == w.OP_SCHUR:
+                    # clover inverse, hop with A^-1 fused (odd), hop with the diagonal input (even)
+                    ids = [base + prec * 6 + 1, base + prec * 6 + 2, (67 if batch else 64) + prec]
+                    names = ["dslash_kernel<%s,0,true>" % PREC_NAMES[prec],
+                             "dslash_kernel<%s,1,false>" % PREC_NAMES[prec], "clover_kernel<%s>" % PREC_NAMES[prec]]
+                    nbs = [dslash_bytes_per_site(prec, 0, True), dslash_bytes_per_site(prec, 1, False),
+                           clover_bytes_per_site(prec)]
+                else:
+                    # hop with A_oo^-1 fused (odd), hop with A_ee x fused (even)
+                    ids = [base + prec * 6 + 1, base + prec * 6 + 4]
+                    names = ["dslash_kernel<%s,0,true>" % PREC_NAMES[prec],
+                             "dslash_kernel<%s,2,false>" % PREC_NAMES[prec]]
+                    nbs = [dslash_bytes_per_site(prec, 0, True), dslash_bytes_per_site(prec, 2, False)]
+                trials = []
+                for _ in range(3 if batch else 5):
+                    ctx.timer_enable(True)
+                    napply = 10 if batch else 40
+                    for _ in range(napply):
+                        ctx.apply_D(v, op, prec)
+                    per = {}
+                    for kid in ids:
+                        per[kid] = ctx.timer_read(kid)
+                    ctx.timer_enable(False)
+                    tot_ms = sum(ms for _, ms in per.values()) / napply
+                    trials.append((tot_ms, per, napply))
+                trials.sort(key=lambda t: t[0])
+                tot_ms, per, napply = trials[len(trials) // 2]
+                comp = dr_compulsory_bytes(prec, nrhs) * nrhs * vh
+                gbps = comp / (tot_ms * 1e-3) / 1e9
+                kern = []
+                for kid, nm, nb in zip(ids, names, nbs):
+                    n, ms = per[kid]
+                    us = ms / n * 1e3 if n else None
+                    if batch:
+                        # links and clover are read once per group of right-hand sides: time only
+                        kern.append({"kernel": nm, "launches_per_apply": n / napply, "avg_us": round(us, 2)})
+                    else:
+                        bl = nb * vh
+                        kern.append({"kernel": nm, "avg_us": round(us, 2), "bytes_per_launch": bl,
+                                     "GBps": round(bl / (us * 1e-6) / 1e9, 1),
+                                     "traffic_bytes_per_launch": measured_traffic(nm) if dims == (24, 24, 24, 64)
+                                     else None})
+                rec = {"form": "D_r, 3 launches" if op == w.OP_SCHUR else "D_r D_ee (variable x = D_ee^-1 y), "
+                       "2 launches", "dr_us": round(tot_ms * 1e3, 2),
+                       "compulsory_bytes_per_even_site_per_rhs": round(dr_compulsory_bytes(prec, nrhs), 1),
+                       "GBps": round(gbps, 1), "frac_of_8TBps": round(gbps / PEAK_HBM_GBS, 3), "kernels": kern,
+                       "trials_us": [round(t[0] * 1e3, 2) for t in trials]}
+                if ceiling:
+                    rec["frac_of_copy"] = round(gbps / ceiling, 3)
+                out["%s%s_rhs%d" % (opname, name, nrhs)] = rec
+        del v
     ctx.close()
     return out
 
 
-def batched_leg(w, torch, inputs, np, m0=None):
-    """24^3x64, 12 Z2 sources (m0 = -0.25 unless given): lockstep
-    multi-right-hand-side MG-GCR (batched fine kernels, coarse stencil on the
-    matrix cores) against the same 12 right-hand sides solved one at a time
-    and against plain FP64 BiCGStab; every solution checked against a true
-    relative residual of 1e-10 in FP64."""
+# ---------------------------------------------------------------------------- batched 24^3x64
+def mg_params(w, cfg, **kw):
+    """Multigrid parameters used for the timed solves.  The paper reports the
+    best parameter set per case with per-level tolerances of order 0.1; these
+    were chosen by sweeps on the 16^3x32 workload: 60 GCR steps per
+    relaxation and at most 5 relaxations per vector in the setup, a coarse
+    GCR(30) to a relative 0.2 capped at 100 iterations, 4 MR post-smoothing
+    steps (coarse tolerance 0.05-0.3 x smoothing 2-8 at the three masses: 0.2
+    with 4 steps is 11% faster in total than 0.1, once the coarse solve is
+    one launch)."""
+    return w.default_params(block=cfg["blocks"], nvec=cfg["nvec"], seed=cfg["setup_seed"], setup_relax=60,
+                            setup_max_steps=5, restart=[30], max_iter=[100], tol=[0.2], nu_post=4, **kw)
+
+
+def batched_leg(w, torch, inputs, np, U, m0, baseline_rhs, bicg_cap):
+    """24^3x64, 12 Z2 sources at mass m0: lockstep multi-right-hand-side
+    MG-GCR (batched fine kernels, coarse stencil on the matrix cores) against
+    the same sources solved one at a time, plain FP64 BiCGStab and the
+    mixed-precision BiCGStab (on the first `baseline_rhs` sources), every
+    solution checked against a true relative residual of 1e-10 in FP64."""
     cfg = inputs.config("c3_24x24x24x64")
     dims = cfg["dims"]
-    m0 = cfg["m0"][0] if m0 is None else m0
-    U = inputs.gauge_field(dims, cfg["eps"], cfg["gauge_seed"], ape_sweeps=cfg["ape"])
     ctx = w.Context(dims)
-    ctx.set_gauge(torch.from_numpy(U).cuda())
+    ctx.set_gauge(U)
     ctx.set_clover(m0, cfg["csw"])
-    ctx.set_mg_params(mg_params(w, cfg))
+    ctx.set_mg_params(mg_params(w, cfg, plain_max_iter=bicg_cap))
     t = time.perf_counter()
     ctx.build_null_vectors()
     ctx.build_coarse()
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t
-    print("batched leg: setup %.1f s" % setup_s, file=sys.stderr, flush=True)
+    print("batched leg m0=%g: setup %.1f s" % (m0, setup_s), file=sys.stderr, flush=True)
     nrhs = cfg["nrhs"]
     b = np.stack([inputs.z2_source(dims, s) for s in cfg["source_seeds"][:nrhs]])
     bt = torch.from_numpy(b.reshape((nrhs,) + tuple(reversed(dims)) + (4, 3))).cuda()
@@ -231,16 +402,21 @@ def batched_leg(w, torch, inputs, np, m0=None):
     n = 2 * cfg["nvec"][0]
     vch = int(np.prod(dims)) // int(np.prod(cfg["blocks"][0])) // 2
     k = nrhs
-    bytes_dr = 2 * vch * (8 * n * n * 4 + k * (9 * n + n) * 8)
+    # per red-black apply: both half hops read the 8 FP16 hop blocks of every site once, and
+    # move 9 neighbour + 1 own vector in and one out per right-hand side (FP32 complex)
+    bytes_dr = 2 * vch * (8 * n * n * 4 + k * (10 * n + n) * 8)
     flops_dr = 2 * vch * 8 * n * n * 8 * k
+    roof = min(PEAK_FP16_MFMA_TFLOPS, flops_dr / bytes_dr * PEAK_HBM_GBS / 1e3)
     mfma = None
     if n_dr:
         us = ms_dr / n_dr * 1e3
-        mfma = {"kernel": "k_coarse_hop_mfma<%d>" % (n // 16), "applies": n_dr, "avg_apply_us": round(us, 2),
-                "GBps": round(bytes_dr / (us * 1e-6) / 1e9, 1), "TFLOPs": round(flops_dr / (us * 1e-6) / 1e12, 2),
-                "mfma_utilisation_vs_fp16_dense_2500": round(flops_dr / (us * 1e-6) / 1e12 / 2500.0, 4),
+        tf = flops_dr / (us * 1e-6) / 1e12
+        mfma = {"kernel": "k_coarse_hop_mfma (2 launches per red-black apply)", "applies": n_dr,
+                "avg_apply_us": round(us, 2), "GBps": round(bytes_dr / (us * 1e-6) / 1e9, 1),
+                "TFLOPs": round(tf, 2), "roofline_TFLOPs": round(roof, 1), "frac_of_roofline": round(tf / roof, 3),
+                "mfma_utilisation_vs_fp16_dense": round(tf / PEAK_FP16_MFMA_TFLOPS, 4),
                 "bytes_per_apply": bytes_dr, "flops_per_apply": flops_dr}
-    print("batched leg: lockstep %.2f s" % batched_s, file=sys.stderr, flush=True)
+    print("batched leg m0=%g: lockstep %.2f s" % (m0, batched_s), file=sys.stderr, flush=True)
     t = time.perf_counter()
     single = []
     for r in range(nrhs):
@@ -248,73 +424,202 @@ def batched_leg(w, torch, inputs, np, m0=None):
         single.append(s1[0])
     torch.cuda.synchronize()
     single_s = time.perf_counter() - t
-    print("batched leg: one at a time %.2f s" % single_s, file=sys.stderr, flush=True)
-    # plain FP64 BiCGStab on the first source; it has no batched form, so the
-    # batch costs nrhs such solves
-    t = time.perf_counter()
-    xb1, sb1 = ctx.solve(bt[:1].contiguous(), w.BICGSTAB, cfg["tol"], raise_on_error=False)
-    torch.cuda.synchronize()
-    bicg_s = time.perf_counter() - t
-    bicg_ok = sb1[0]["status"] == "OK"
-    diff = float(torch.linalg.vector_norm(xb[:1] - xb1) / torch.linalg.vector_norm(xb1))
-    print("batched leg: BiCGStab %.2f s, %d iterations, %s" % (bicg_s, sb1[0]["iters"], sb1[0]["status"]),
-          file=sys.stderr, flush=True)
+    print("batched leg m0=%g: one at a time %.2f s" % (m0, single_s), file=sys.stderr, flush=True)
+    base = {}
+    for solver, name in ((w.BICGSTAB, "bicgstab_fp64"), (w.MP_BICGSTAB, "mp_bicgstab")):
+        ts, its, res, stat, diffs = [], [], [], [], []
+        for r in range(baseline_rhs):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            xr, sr = ctx.solve(bt[r:r + 1].contiguous(), solver, cfg["tol"], raise_on_error=False)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+            its.append(sr[0]["iters"])
+            res.append(sr[0]["true_rel_res"])
+            stat.append(sr[0]["status"])
+            diffs.append(float(torch.linalg.vector_norm(xb[r:r + 1] - xr) / torch.linalg.vector_norm(xr)))
+        conv = all(s == "OK" for s in stat)
+        per_src = float(np.mean(ts))
+        mg_per_src = batched_s / nrhs
+        base[name] = {"sources": baseline_rhs, "s_per_source": round(per_src, 3), "iters": its,
+                      "break_even_rhs": round(setup_s / (per_src - mg_per_src), 2) if per_src > mg_per_src else None,
+                      "max_true_rel_res": max(res), "status": sorted(set(stat)),
+                      "max_rel_diff_vs_mg": max(diffs),
+                      "speedup_of_batched_mg": round(nrhs * per_src / batched_s, 2),
+                      "speedup_kind": "equal accuracy" if conv else
+                      "lower bound: the solver stopped at its iteration cap above the tolerance"}
+        print("batched leg m0=%g: %s %.2f s per source, iterations %s, %s" % (m0, name, per_src, its, stat),
+              file=sys.stderr, flush=True)
     ctx.close()
-    return {"workload": "24^3x64, m0=%g, 12 Z2 sources, 4^4 blocks, Nv=24" % m0,
+    return {"workload": "24^3x64, m0=%g, 12 Z2 sources, 4^4 blocks, Nv=24, FP32 cycle, FP16 coarse operands" % m0,
             "setup_s": round(setup_s, 2), "lockstep_s": round(batched_s, 3),
-            "one_at_a_time_s": round(single_s, 3), "speedup": round(single_s / batched_s, 2),
+            "lockstep_s_per_source": round(batched_s / nrhs, 4),
+            "one_at_a_time_s": round(single_s, 3), "speedup_lockstep_vs_one_at_a_time": round(single_s / batched_s, 2),
             "lockstep_outer_iters": [s["iters"] for s in sb],
             "one_at_a_time_outer_iters": [s["iters"] for s in single],
             "max_true_rel_res": max(max(s["true_rel_res"] for s in sb), max(s["true_rel_res"] for s in single)),
-            "bicgstab_one_rhs_s": round(bicg_s, 3), "bicgstab_iters": sb1[0]["iters"],
-            "bicgstab_true_rel_res": sb1[0]["true_rel_res"], "bicgstab_status": sb1[0]["status"],
-            "rel_diff_mg_vs_bicgstab": diff,
-            "speedup_vs_bicgstab": round(nrhs * bicg_s / batched_s, 1),
-            "speedup_vs_bicgstab_kind": "equal accuracy" if bicg_ok else
-            "lower bound: BiCGStab stopped at its iteration cap above the tolerance",
-            "coarse_stencil_matrix_cores": mfma}
+            "baselines": base, "coarse_stencil_matrix_cores": mfma}
 
 
-def mg_params(w, cfg):
-    """Multigrid parameters used for the timed solves.  The paper reports the
-    best parameter set per case with per-level tolerances of order 0.1; these
-    were chosen by sweeps on this workload: 60 GCR steps per relaxation and
-    at most 5 relaxations per vector in the setup, a coarse GCR(30) to a
-    relative 0.2 capped at 100 iterations, 4 MR post-smoothing steps (coarse
-    tolerance 0.05-0.3 x smoothing 2-8 at the three masses: 0.2 with 4 steps
-    is 11% faster in total than 0.1, once the coarse solve is one launch)."""
-    return w.default_params(block=cfg["blocks"], nvec=cfg["nvec"], seed=cfg["setup_seed"], setup_relax=60,
-                            setup_max_steps=5, restart=[30], max_iter=[100], tol=[0.2], nu_post=4)
+# ---------------------------------------------------------------------------- studies
+def _c2_context(w, torch, inputs, m0, **kw):
+    cfg = inputs.config("c2_16x16x16x32")
+    U = inputs.gauge_field_torch(cfg["dims"], cfg["eps"], cfg["gauge_seed"], ape_sweeps=cfg["ape"], device="cuda")
+    ctx = w.Context(cfg["dims"])
+    ctx.set_gauge(U)
+    ctx.set_clover(m0, cfg["csw"])
+    ctx.set_mg_params(mg_params(w, cfg, **kw))
+    return cfg, ctx
 
 
+def _timed_solve(torch, ctx, b, solver, tol):
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    x, st = ctx.solve(b, solver, tol, raise_on_error=False)
+    torch.cuda.synchronize()
+    return x, st[0], time.perf_counter() - t
+
+
+def study_tolerance(w, torch, inputs, m0=-0.02, tols=(1e-4, 1e-6, 1e-8, 1e-10, 1e-12)):
+    """Speedup of MG-GCR over plain FP64 BiCGStab and the mixed-precision
+    BiCGStab against the requested relative residual (Results section, the
+    speedup-versus-tolerance figure), 16^3x32 at one mass."""
+    cfg, ctx = _c2_context(w, torch, inputs, m0)
+    ctx.build_null_vectors()
+    ctx.build_coarse()
+    b = torch.from_numpy(inputs.z2_source(cfg["dims"], cfg["source_seeds"][0])[None]).cuda()
+    ctx.solve(b, w.MG_GCR, 1e-10)  # warm-up
+    rows = []
+    for tol in tols:
+        _, smg, tmg = _timed_solve(torch, ctx, b, w.MG_GCR, tol)
+        _, sbi, tbi = _timed_solve(torch, ctx, b, w.BICGSTAB, tol)
+        _, smp, tmp = _timed_solve(torch, ctx, b, w.MP_BICGSTAB, tol)
+        rows.append(dict(tol=tol, mg_s=round(tmg, 4), mg_iters=smg["iters"], bicgstab_s=round(tbi, 4),
+                         bicgstab_iters=sbi["iters"], mp_bicgstab_s=round(tmp, 4),
+                         speedup_vs_bicgstab=round(tbi / tmg, 2), speedup_vs_mp_bicgstab=round(tmp / tmg, 2),
+                         status=[smg["status"], sbi["status"], smp["status"]]))
+        print("tolerance study: %s" % rows[-1], file=sys.stderr, flush=True)
+    ctx.close()
+    return {"workload": "16^3x32, m0=%g, one Z2 source" % m0, "rows": rows}
+
+
+def study_setup(w, torch, inputs, m0=-0.02, efforts=((10, 1), (20, 2), (30, 3), (60, 5), (60, 8)), refine=(1, 2)):
+    """Solver speedup against the setup's cost in BiCGStab solves (Results
+    section, the setup-cost figure) and the number of right-hand sides at
+    which the setup pays for itself (break-even), 16^3x32 at one mass: the
+    inverse-iteration setup at several efforts (relaxation steps x passes per
+    vector), and the cheapest one refined by the multigrid cycle (Setup
+    section, adaptive refinement)."""
+    cfg, ctx = _c2_context(w, torch, inputs, m0)
+    b = torch.from_numpy(inputs.z2_source(cfg["dims"], cfg["source_seeds"][0])[None]).cuda()
+    _, sbi, tbi = _timed_solve(torch, ctx, b, w.BICGSTAB, cfg["tol"])
+    rows = []
+
+    def measure(label, setup_s):
+        ctx.solve(b, w.MG_GCR, cfg["tol"])  # warm-up
+        ts = []
+        for _ in range(3):
+            _, smg, tmg = _timed_solve(torch, ctx, b, w.MG_GCR, cfg["tol"])
+            ts.append(tmg)
+        tmg = sorted(ts)[1]
+        row = dict(setup=label, setup_s=round(setup_s, 3), setup_in_bicgstab_solves=round(setup_s / tbi, 2),
+                   mg_s=round(tmg, 4), mg_outer_iters=smg["iters"], speedup=round(tbi / tmg, 2),
+                   break_even_rhs=(round(setup_s / (tbi - tmg), 2) if tbi > tmg else None))
+        rows.append(row)
+        print("setup study: %s" % row, file=sys.stderr, flush=True)
+
+    for relax, steps in efforts:
+        ctx.set_mg_params(w.default_params(block=cfg["blocks"], nvec=cfg["nvec"], seed=cfg["setup_seed"],
+                                           setup_relax=relax, setup_max_steps=steps, restart=[30], max_iter=[100],
+                                           tol=[0.2], nu_post=4))
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ctx.build_null_vectors()
+        ctx.build_coarse()
+        torch.cuda.synchronize()
+        measure("inverse iteration: %d GCR steps x at most %d relaxations" % (relax, steps), time.perf_counter() - t)
+        if (relax, steps) == efforts[0]:
+            for passes in refine:
+                ctx.set_mg_params(w.default_params(block=cfg["blocks"], nvec=cfg["nvec"], seed=cfg["setup_seed"],
+                                                   setup_relax=relax, setup_max_steps=steps, restart=[30],
+                                                   max_iter=[100], tol=[0.2], nu_post=4))
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                ctx.build_null_vectors()
+                ctx.build_coarse()
+                ctx.refine_null_vectors(passes=passes, iters=4)
+                torch.cuda.synchronize()
+                measure("the same, then %d refinement pass(es) with the cycle (4 steps per vector)" % passes,
+                        time.perf_counter() - t)
+    ctx.close()
+    return {"workload": "16^3x32, m0=%g, one Z2 source" % m0, "bicgstab_s": round(tbi, 4),
+            "bicgstab_iters": sbi["iters"], "rows": rows}
+
+
+def study_error(w, torch, inputs, m0=-0.02, tols=(1e-4, 1e-6, 1e-8, 1e-10)):
+    """Error against residual with a known solution (Results section, the
+    error/residual figure): x0 = D^-1 (point source at the origin, spin 0,
+    colour 0) solved to 1e-13, b = D x0, so b is close to a point source and
+    its exact solution is x0; for MG-GCR and plain BiCGStab at each tolerance
+    the ratio ||x - x0|| / ||x0|| over ||b - D x|| / ||b||."""
+    cfg, ctx = _c2_context(w, torch, inputs, m0)
+    ctx.build_null_vectors()
+    ctx.build_coarse()
+    dims = cfg["dims"]
+    pt = torch.zeros((1,) + tuple(reversed(dims)) + (4, 3), dtype=torch.complex128, device="cuda")
+    pt[0, 0, 0, 0, 0, 0, 0] = 1.0
+    x0, _ = ctx.solve(pt, w.MG_GCR, 1e-13)
+    b = ctx.apply_D(x0)
+    rows = []
+    nx0 = float(torch.linalg.vector_norm(x0))
+    for tol in tols:
+        for solver, name in ((w.MG_GCR, "mg_gcr"), (w.BICGSTAB, "bicgstab")):
+            x, st = ctx.solve(b, solver, tol, raise_on_error=False)
+            err = float(torch.linalg.vector_norm(x - x0)) / nx0
+            res = st[0]["true_rel_res"]
+            rows.append(dict(tol=tol, solver=name, rel_error=err, rel_residual=res,
+                             error_over_residual=round(err / res, 2), iters=st[0]["iters"]))
+            print("error study: %s" % rows[-1], file=sys.stderr, flush=True)
+    ctx.close()
+    return {"workload": "16^3x32, m0=%g, b = D x0 with x0 = D^-1 (point source)" % m0, "rows": rows}
+
+
+# ---------------------------------------------------------------------------- main
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-headline", action="store_true", help="skip the 24^3x64 Dslash measurement")
+    ap.add_argument("--no-headline", action="store_true", help="skip the Dslash bandwidth measurements")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 24^3x64 multi-right-hand-side leg")
     ap.add_argument("--no-bicgstab", action="store_true",
-                    help="skip the BiCGStab comparison (short runs under a profiler)")
+                    help="skip the BiCGStab comparisons (short runs under a profiler)")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the 24^3x64 Dslash measurement (runs under a profiler)")
     ap.add_argument("--dslash-32", action="store_true",
                     help="only the 32^3x64 Dslash measurement (the second bandwidth point)")
-    ap.add_argument("--batched", action="store_true",
-                    help="add the 24^3x64 multi-right-hand-side leg: 12 Z2 sources in lockstep vs one at a time")
+    ap.add_argument("--batched-only", action="store_true", help="only the 24^3x64 multi-right-hand-side leg")
     ap.add_argument("--batched-masses", type=str, default=None,
-                    help="comma-separated masses of the --batched leg (default: -0.25 and the near-critical masses)")
+                    help="comma-separated masses of the batched leg (default: -0.25 and %g)"
+                         % BATCHED_EQUAL_ACCURACY_M0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (the reference kernel of the traffic counters)")
     ap.add_argument("--masses", type=str, default=None, help="comma-separated subset of the m0 sweep")
     ap.add_argument("--near-critical", type=str, default="-0.02",
                     help="comma-separated supplementary masses close to the critical mass of this ensemble, "
                          "where plain BiCGStab still converges (empty: none)")
+    ap.add_argument("--study", choices=["tol", "setup", "error"], default=None,
+                    help="run one of the Results-section studies on 16^3x32 instead of the benchmark")
+    ap.add_argument("--oracle-sample", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures a single GPU: --gpus %d is not supported (the path shards by right-hand side or "
               "by 4D domain decomposition, which is not built here)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.oracle_sample:
+        print(json.dumps(oracle_sample()))
+        return
 
     import numpy as np
     import torch
@@ -333,18 +638,45 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if args.headline_only:
-        print(json.dumps({"dslash_24x24x24x64": dslash_headline(w, torch, inputs)}))
+        print(json.dumps({"dslash_24x24x24x64": dslash_headline(w, torch, inputs, nrhs_list=(1,))}))
         return
     if args.dslash_32:
-        print(json.dumps({"dslash_32x32x32x64": dslash_headline(w, torch, inputs, (32, 32, 32, 64))}))
+        print(json.dumps({"dslash_32x32x32x64": dslash_headline(w, torch, inputs, (32, 32, 32, 64), (1,))}))
         return
+    batched_masses = ([-0.25, BATCHED_EQUAL_ACCURACY_M0] if args.batched_masses is None else
+                      [float(m) for m in args.batched_masses.split(",") if m.strip()])
+
+    def run_batched():
+        cfg3 = inputs.config("c3_24x24x24x64")
+        t = time.perf_counter()
+        U3 = inputs.gauge_field_torch(cfg3["dims"], cfg3["eps"], cfg3["gauge_seed"], ape_sweeps=cfg3["ape"],
+                                      device="cuda")
+        torch.cuda.synchronize()
+        print("batched leg: gauge field %.1f s" % (time.perf_counter() - t), file=sys.stderr, flush=True)
+        res = {}
+        for m in batched_masses:
+            # at the configuration's mass plain BiCGStab does not converge on this field: one source,
+            # capped (a lower bound); at the equal-accuracy mass every source
+            eq = m != -0.25
+            res[str(m)] = batched_leg(w, torch, inputs, np, U3, m, 12 if eq else 1, 50000 if eq else 20000)
+        del U3
+        return res
+
+    if args.study:
+        fn = {"tol": study_tolerance, "setup": study_setup, "error": study_error}[args.study]
+        print(json.dumps({"study_" + args.study: fn(w, torch, inputs)}))
+        return
+    if args.batched_only:
+        print(json.dumps({"batched_24x24x24x64": run_batched()}))
+        return
+
     cfg = inputs.config("c2_16x16x16x32")
     dims = cfg["dims"]
     t = time.perf_counter()
-    U = inputs.gauge_field(dims, cfg["eps"], cfg["gauge_seed"], ape_sweeps=cfg["ape"])
+    Ut = inputs.gauge_field_torch(dims, cfg["eps"], cfg["gauge_seed"], ape_sweeps=cfg["ape"], device="cuda")
     b = inputs.z2_source(dims, cfg["source_seeds"][0])
+    torch.cuda.synchronize()
     t_inputs = time.perf_counter() - t
-    Ut = torch.from_numpy(U).cuda()
     bt = torch.from_numpy(b[None]).cuda()
     masses = cfg["m0"] if args.masses is None else [float(m) for m in args.masses.split(",")]
     near = [float(m) for m in args.near_critical.split(",") if m.strip()]
@@ -365,8 +697,9 @@ def main():
     print("setup done %s" % {k: round(v, 2) for k, v in setup.items()}, file=sys.stderr, flush=True)
 
     # plain FP64 BiCGStab on the same D_r, same stopping rule (one solve per
-    # mass: at 1e4-1e5 iterations a warm-up solve changes nothing)
-    bicg = {}
+    # mass: at 1e4-1e5 iterations a warm-up solve changes nothing); at the
+    # near-critical masses also the paper's mixed-precision BiCGStab
+    bicg, mpbicg = {}, {}
     for m0, ctx in zip(all_masses, ctxs if not args.no_bicgstab else []):
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -376,6 +709,13 @@ def main():
                         status=st[0]["status"], x=xb)
         print("bicgstab m0=%g: %.2f s, %d iterations, %s" % (m0, bicg[m0]["s"], bicg[m0]["iters"],
                                                             bicg[m0]["status"]), file=sys.stderr, flush=True)
+        if m0 in near:
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            xm, sm = ctx.solve(bt, w.MP_BICGSTAB, cfg["tol"], raise_on_error=False)
+            torch.cuda.synchronize()
+            mpbicg[m0] = dict(s=time.perf_counter() - t, iters=sm[0]["iters"], cycles=sm[0]["inner_iters"][0],
+                              res=sm[0]["true_rel_res"], status=sm[0]["status"])
 
     for _ in range(args.warmup):
         for ctx in ctxs:
@@ -428,44 +768,53 @@ def main():
     def mass_row(m0):
         x, st = last[m0]
         mg_s = float(np.median(per[m0]))
+        row = dict(mg_s=round(mg_s, 4), mg_outer_iters=st["iters"],
+                   mg_inner_iters_mean=round(st["inner_iters"][0], 2), mg_true_rel_res=st["true_rel_res"],
+                   mg_inner_status=st["inner_status"], setup_s=round(setup[m0], 3))
         if m0 not in bicg:
-            return dict(mg_s=round(mg_s, 4), mg_outer_iters=st["iters"],
-                        mg_inner_iters_mean=round(st["inner_iters"][0], 2), mg_true_rel_res=st["true_rel_res"],
-                        setup_s=round(setup[m0], 3))
+            return row
         xb = bicg[m0]["x"]
         conv = bicg[m0]["status"] == "OK"
         diff = float(torch.linalg.vector_norm(x - xb) / torch.linalg.vector_norm(xb))
-        return dict(mg_s=round(mg_s, 4), mg_outer_iters=st["iters"],
-                    mg_inner_iters_mean=round(st["inner_iters"][0], 2),
-                    mg_true_rel_res=st["true_rel_res"], bicgstab_s=round(bicg[m0]["s"], 4),
-                    bicgstab_iters=bicg[m0]["iters"], bicgstab_true_rel_res=bicg[m0]["res"],
-                    bicgstab_status=bicg[m0]["status"], bicgstab_converged=conv,
-                    speedup=round(bicg[m0]["s"] / mg_s, 2),
-                    speedup_kind="equal accuracy" if conv else
-                    "lower bound: BiCGStab stopped at its iteration cap above the tolerance",
-                    setup_s=round(setup[m0], 3),
-                    setup_in_bicgstab_solves=round(setup[m0] / bicg[m0]["s"], 2),
-                    rel_diff_mg_vs_bicgstab=diff)
+        row.update(bicgstab_s=round(bicg[m0]["s"], 4),
+                   bicgstab_iters=bicg[m0]["iters"], bicgstab_true_rel_res=bicg[m0]["res"],
+                   bicgstab_status=bicg[m0]["status"], bicgstab_converged=conv,
+                   speedup=round(bicg[m0]["s"] / mg_s, 2),
+                   speedup_kind="equal accuracy" if conv else
+                   "lower bound: BiCGStab stopped at its iteration cap above the tolerance",
+                   setup_in_bicgstab_solves=round(setup[m0] / bicg[m0]["s"], 2),
+                   # right-hand sides after which setup + n MG solves beat n BiCGStab solves
+                   break_even_rhs=(round(setup[m0] / (bicg[m0]["s"] - mg_s), 2) if bicg[m0]["s"] > mg_s else None),
+                   rel_diff_mg_vs_bicgstab=diff)
+        if m0 in mpbicg:
+            mp = mpbicg[m0]
+            row.update(mp_bicgstab_s=round(mp["s"], 4), mp_bicgstab_fp32_iters=mp["iters"],
+                       mp_bicgstab_refinement_cycles=mp["cycles"], mp_bicgstab_true_rel_res=mp["res"],
+                       mp_bicgstab_status=mp["status"], speedup_vs_mp_bicgstab=round(mp["s"] / mg_s, 2))
+        return row
 
     mass_rows = {str(m0): mass_row(m0) for m0 in masses}
     near_rows = {str(m0): mass_row(m0) for m0 in all_masses[len(masses):]}
+    for ctx in ctxs:
+        ctx.close()
+    del ctxs, main_ctxs
 
-    headline = None if args.no_headline else dslash_headline(w, torch, inputs)
-    headline32 = None if args.no_headline else dslash_headline(w, torch, inputs, (32, 32, 32, 64))
-    batched = None
-    if args.batched:
-        # the workload's mass, then the near-critical masses (where plain BiCGStab converges)
-        bm = ([inputs.config("c3_24x24x24x64")["m0"][0]] + near if args.batched_masses is None else
-              [float(m) for m in args.batched_masses.split(",") if m.strip()])
-        batched = {str(m): batched_leg(w, torch, inputs, np, m) for m in bm}
+    ceiling = copy_ceiling(torch)
+    headline = None if args.no_headline else dslash_headline(w, torch, inputs, ceiling=ceiling)
+    headline32 = None if args.no_headline else dslash_headline(w, torch, inputs, (32, 32, 32, 64), (1,), ceiling)
+    batched = None if args.no_batched else run_batched()
     cpu = None
     if not args.no_cpu and bicg:
-        conv_m = [m for m in all_masses if bicg[m]["status"] == "OK"]
-        mref = conv_m[0] if conv_m else all_masses[0]
-        cpu = cpu_baseline(dims, U, mref, cfg["csw"], b, bicg[mref]["iters"])
+        conv_m = [m for m in masses if bicg[m]["status"] == "OK"]
+        mref = -0.25 if -0.25 in conv_m else (conv_m[0] if conv_m else masses[0])
+        cpu = cpu_baseline(Ut.cpu().numpy(), bicg[mref]["iters"], mref)
 
     steps_solves = args.steps * len(masses)
     value = elapsed / steps_solves
+    dr = None
+    if headline:
+        dr = {k: {"GBps": v["GBps"], "frac_of_8TBps": v["frac_of_8TBps"], "frac_of_copy": v.get("frac_of_copy")}
+              for k, v in headline.items()}
     line = {
         "metric": "time-to-solution @ rel.res 1e-10 (MG vs plain BiCGStab); Dslash GB/s",
         "value": round(value, 5),
@@ -494,14 +843,14 @@ def main():
         "near_critical": near_rows,
         "roofline": roofline,
         "kernels": rows[:8],
+        "copy_ceiling_GBps": ceiling,
+        "fine_dr_summary": dr,
         "dslash_24x24x24x64": headline,
         "dslash_32x32x32x64": headline32,
         "batched_24x24x24x64": batched,
         "cpu_baseline": cpu,
         "inputs_s": round(t_inputs, 2),
     }
-    for ctx in ctxs:
-        ctx.close()
     print(json.dumps(line))
 
 

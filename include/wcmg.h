@@ -68,11 +68,16 @@ enum {
 typedef enum { WCMG_F64 = 0, WCMG_F32 = 1, WCMG_F16 = 2 } wcmg_prec;
 
 /* operator forms (red-black paragraph, Eqs.(2)-(3)):
- *   FULL  D of Eq.(1), both parities;
- *   SCHUR D_r = 1 - D_eo D_oo^-1 D_oe D_ee^-1 acting on even sites (odd
- *         sites of the input are ignored, odd sites of the output are zero);
- *   DP    D_p = D diag(D_ee, D_oo)^-1, both parities. */
-typedef enum { WCMG_OP_FULL = 0, WCMG_OP_SCHUR = 1, WCMG_OP_DP = 2 } wcmg_op;
+ *   FULL     D of Eq.(1), both parities;
+ *   SCHUR    D_r = 1 - D_eo D_oo^-1 D_oe D_ee^-1 acting on even sites (odd
+ *            sites of the input are ignored, odd sites of the output are
+ *            zero); three launches (A_ee^-1, then the two hops);
+ *   DP       D_p = D diag(D_ee, D_oo)^-1, both parities;
+ *   SCHUR_X  D_r D_ee = D_ee - D_eo D_oo^-1 D_oe, the same reduced system in
+ *            the variable x_e = D_ee^-1 y_e of Eq.(3) (fine operators only);
+ *            two launches, each field read once: the odd hop with D_oo^-1
+ *            fused, then the even hop with D_ee x fused. */
+typedef enum { WCMG_OP_FULL = 0, WCMG_OP_SCHUR = 1, WCMG_OP_DP = 2, WCMG_OP_SCHUR_X = 3 } wcmg_op;
 
 /* MG_GCR: FP64 GCR on D_r preconditioned by the multigrid cycle (adaptive
  * multigrid paragraph); GCR, BICGSTAB: unpreconditioned FP64 on D_r;
@@ -139,6 +144,10 @@ typedef struct {
                                        BiCGStab, MP_BICGSTAB (FP32 iterations), CGNR); 0: 100000 */
   double mp_inner_tol;              /* MP_BICGSTAB: relative tolerance of each FP32 BiCGStab solve of
                                        the residual equation; 0: 1e-3 */
+  int coarse_fp16;                  /* 1: the persistent coarsest solve reads its red-black hop blocks
+                                       in FP16 (FP32 vectors and arithmetic; with one site per
+                                       workgroup the even site's blocks stay in LDS for the whole
+                                       solve); 0: FP32 blocks */
 } wcmg_mg_params;
 
 typedef struct {
@@ -199,6 +208,28 @@ int wcmg_build_null_vectors(void* ctx, int lat, int level);
 int wcmg_set_null_vectors(void* ctx, int lat, int level, const void* v, int nvec, int on_device);
 int wcmg_get_null_vectors(void* ctx, int lat, int level, void* v, int on_device);
 
+/* The random start vectors of the setup (Setup section) as the library draws
+ * them: entry m of vector k on level l is one complex Gaussian (re, im) by
+ * Box-Muller from Philox4x32-10 with counter (m mod 2^32, m div 2^32, k, l)
+ * and key (seed mod 2^32, seed div 2^32); m = lex_site * 12 + spin * 3 +
+ * colour on the fine level, lex_site * 2Nv + component on coarse level l.
+ * Vectors k0 .. k0 + nvec - 1 go to out (device): canonical fine spinors for
+ * level 0, coarse vectors of level l (which must be built) otherwise.  For
+ * parity checks of the setup, and for callers running their own relaxation.
+ * Asynchronous. */
+int wcmg_setup_start_vectors(void* ctx, int lat, int level, uint64_t seed, int k0, int nvec, void* out);
+
+/* Adaptive refinement of the fine null vectors (Setup section: relaxing with
+ * a multigrid cycle built from the vectors already found, as in adaptive
+ * smoothed aggregation, combined with the inverse-iteration setup -- the
+ * hybrid the paper plans for the clover case).  Needs a built hierarchy.
+ * Each of `passes` rounds relaxes every fine null vector v with `iters` steps
+ * of the multigrid-preconditioned FP64 GCR on the homogeneous reduced system
+ * D_r y = 0 from y = v_e, completes the odd half from D_p v = 0, orthonormalises
+ * the vectors in order (twice) and rebuilds P and every coarse operator (the
+ * coarse levels' own vectors are kept).  Synchronises. */
+int wcmg_refine_null_vectors(void* ctx, int lat, int passes, int iters);
+
 /* Coarse operator of level+1: block x chirality split and orthonormalise
  * the level's vectors (P), then Yhat = R D_p P with R = P^dag gamma5
  * (red-black paragraph), its site-block inverses and the red-black
@@ -242,7 +273,10 @@ int wcmg_apply_coarse(void* ctx, int lat, int level, int op, int prec, void* out
  * most one even site per workgroup the one-site kernel (Krylov basis in LDS,
  * a neighbour wait in place of the second grid barrier of a step), else sites
  * strided over the workgroups; launch 2: the strided kernel always (the same
- * bits); launch 1: one launch per kernel of every step.  stats (optional):
+ * bits); launch 1: one launch per kernel of every step; launch 3 and 4: as 0
+ * and 2 with the hop blocks read in FP16 (prec F32; FP32 arithmetic; the
+ * one-site kernel keeps its even site's blocks in LDS for the whole solve
+ * when they fit; 3 and 4 give the same bits).  stats (optional):
  * iters, status, and
  * true_rel_res = ||b - Yhat x|| / ||b|| of the full coarse system in prec.
  * Requires a lattice with every coarse extent even (EDIM otherwise). */
@@ -287,7 +321,8 @@ int wcmg_force(void* ctx, int lat, void* dU, const void* psi, const void* lam, i
 /* Project autotuner (on != 0: enable, 0: disable; choices are kept): the
  * first launch of each fine hop kernel variant for a given lattice,
  * precision and batch size times every candidate launch shape (64/128/256
- * threads per block x 1/2/4 right-hand sides per thread) on the context
+ * threads per block x 1/2/4 right-hand sides per thread, or -1: one per
+ * thread with the workgroups of a site block's right-hand sides adjacent) on the context
  * stream and keeps the fastest.  Every candidate gives bitwise the same
  * result, so tuning never changes an answer.  Not during graph capture. */
 int wcmg_autotune(void* ctx, int on);

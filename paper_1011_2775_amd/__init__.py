@@ -16,10 +16,10 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (F16, F32, F64, OP_DP, OP_FULL, OP_SCHUR, MG_GCR, GCR, BICGSTAB, MP_BICGSTAB, CGNR, WcmgError,
+from ._lib import (F16, F32, F64, OP_DP, OP_FULL, OP_SCHUR, OP_SCHUR_X, MG_GCR, GCR, BICGSTAB, MP_BICGSTAB, CGNR, WcmgError,
                    check)
 
-__all__ = ["Context", "WcmgError", "F64", "F32", "F16", "OP_FULL", "OP_SCHUR", "OP_DP", "MG_GCR", "GCR",
+__all__ = ["Context", "WcmgError", "F64", "F32", "F16", "OP_FULL", "OP_SCHUR", "OP_DP", "OP_SCHUR_X", "MG_GCR", "GCR",
            "BICGSTAB", "MP_BICGSTAB", "CGNR", "default_params"]
 
 
@@ -174,6 +174,17 @@ class Context:
         out = torch.empty((nv,) + self._level_shape(level, lat), dtype=torch.complex128, device="cuda")
         check(_lib.LIB.wcmg_get_null_vectors(self.h, lat, level, ctypes.c_void_p(out.data_ptr()), 1))
         return out
+
+    def setup_start_vectors(self, seed, nvec, k0=0, level=0, lat=0):
+        """The setup's Philox start vectors k0 .. k0+nvec-1 of `level` (canonical, complex128)."""
+        out = torch.empty((nvec,) + self._level_shape(level, lat), dtype=torch.complex128, device="cuda")
+        check(_lib.LIB.wcmg_setup_start_vectors(self.h, lat, level, int(seed), int(k0), int(nvec),
+                                                ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def refine_null_vectors(self, passes=1, iters=4, lat=0):
+        """Relax the fine null vectors with the current multigrid cycle and rebuild the hierarchy."""
+        check(_lib.LIB.wcmg_refine_null_vectors(self.h, lat, int(passes), int(iters)))
 
     def build_coarse(self, level=0, lat=0):
         check(_lib.LIB.wcmg_build_coarse(self.h, lat, level))

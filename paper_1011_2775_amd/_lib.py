@@ -14,7 +14,7 @@ LIBPATH = os.path.join(HERE, "lib", "libwcmg.so")
 
 OK, EINVAL, EDIM, ESTATE, ENOCONV, EBREAKDOWN, ENAN, ECLOVER_NOT_PD, ERANK, ENOMEM, EHIP, ENODEV = range(12)
 F64, F32, F16 = 0, 1, 2
-OP_FULL, OP_SCHUR, OP_DP = 0, 1, 2
+OP_FULL, OP_SCHUR, OP_DP, OP_SCHUR_X = 0, 1, 2, 3
 MG_GCR, GCR, BICGSTAB, MP_BICGSTAB, CGNR = 0, 1, 2, 3, 4
 MAX_LEVELS = 3
 
@@ -46,7 +46,8 @@ class MGParams(ctypes.Structure):
                 ("setup_prec", ctypes.c_int),
                 ("coarse_launch", ctypes.c_int),
                 ("plain_max_iter", ctypes.c_int),
-                ("mp_inner_tol", ctypes.c_double)]
+                ("mp_inner_tol", ctypes.c_double),
+                ("coarse_fp16", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -78,6 +79,8 @@ SIGNATURES = {
     "wcmg_set_null_vectors": [_vp, _i, _i, _vp, _i, _i],
     "wcmg_get_null_vectors": [_vp, _i, _i, _vp, _i],
     "wcmg_build_coarse": [_vp, _i, _i],
+    "wcmg_refine_null_vectors": [_vp, _i, _i, _i],
+    "wcmg_setup_start_vectors": [_vp, _i, _i, ctypes.c_uint64, _i, _i, _vp],
     "wcmg_get_coarse": [_vp, _i, _i, _vp, _i],
     "wcmg_apply_D": [_vp, _i, _i, _i, _vp, _vp, _i],
     "wcmg_apply_Ddag": [_vp, _i, _i, _i, _vp, _vp, _i],

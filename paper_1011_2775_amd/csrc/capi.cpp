@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 
+#include "random.h"
 #include "runtime.h"
 
 using namespace wcmg;
@@ -43,7 +44,7 @@ int guarded(F&& f) {
 Ctx* as_ctx(void* p) { return reinterpret_cast<Ctx*>(p); }
 
 bool valid_prec(int p) { return p == WCMG_F64 || p == WCMG_F32 || p == WCMG_F16; }
-bool valid_op(int o) { return o == WCMG_OP_FULL || o == WCMG_OP_SCHUR || o == WCMG_OP_DP; }
+bool valid_op(int o) { return o == WCMG_OP_FULL || o == WCMG_OP_SCHUR || o == WCMG_OP_DP || o == WCMG_OP_SCHUR_X; }
 
 // copies `bytes` of host or device data into a device scratch slot
 const void* to_device(Ctx& c, int slot, const void* src, size_t bytes, int on_device) {
@@ -479,6 +480,48 @@ int wcmg_get_null_vectors(void* ctx, int lat, int level, void* v, int on_device)
   });
 }
 
+int wcmg_setup_start_vectors(void* ctx, int lat, int level, uint64_t seed, int k0, int nvec, void* out) {
+  Ctx* c = as_ctx(ctx);
+  if (int r = check_lat(c, lat)) return r;
+  CHECK(out, WCMG_EINVAL, "null output");
+  CHECK(k0 >= 0 && nvec >= 1, WCMG_EINVAL, "k0 must be >= 0 and nvec >= 1");
+  LatticeState& L = *c->lats[lat];
+  const Geom& g = L.F.g;
+  if (level == 0) {
+    CHECK_DEV(c, out, (size_t)nvec * g.V * 12 * 16, "start vectors");
+    return guarded([&] {
+      const size_t hb = spinor_bytes(WCMG_F64, g.Vh);
+      char* v = (char*)c->scratch_buf(41, 2 * hb);
+      for (int k = 0; k < nvec; ++k) {
+        random_fine_vector(v, seed, k0 + k, 0, g, c->st);
+        spinor_from_internal(WCMG_F64, (char*)out + (size_t)k * g.V * 12 * 16, v, v + hb, g, false, c->st);
+      }
+    });
+  }
+  CHECK(level >= 1 && (int)L.levels.size() >= level && L.levels[level - 1]->built, WCMG_ESTATE,
+        "coarse level not built");
+  const CoarseLevel& C = *L.levels[level - 1];
+  CHECK_DEV(c, out, (size_t)nvec * C.cg.V * C.cg.n * 16, "start vectors");
+  return guarded([&] {
+    const size_t one = (size_t)C.cg.V * C.cg.n * 16;
+    void* v = c->scratch_buf(41, one);
+    for (int k = 0; k < nvec; ++k) {
+      random_coarse_vector(v, seed, k0 + k, level, C.perm.as<int>(), C.cg.V, C.cg.n, c->st);
+      launch_coarse_canon(WCMG_F64, v, (char*)out + (size_t)k * one, C.perm.as<int>(), C.cg.V, C.cg.n, false, c->st);
+    }
+  });
+}
+
+int wcmg_refine_null_vectors(void* ctx, int lat, int passes, int iters) {
+  Ctx* c = as_ctx(ctx);
+  if (int r = check_lat(c, lat)) return r;
+  CHECK(passes >= 1 && iters >= 1 && iters <= 1000, WCMG_EINVAL, "passes must be >= 1 and iters in 1..1000");
+  LatticeState& L = *c->lats[lat];
+  CHECK(L.have_params && !L.levels.empty() && L.levels[0]->built && L.T0.have_vecs, WCMG_ESTATE,
+        "multigrid hierarchy not built");
+  return guarded([&] { mg_refine_null_vectors(*c, L, passes, iters); });
+}
+
 int wcmg_build_coarse(void* ctx, int lat, int level) {
   Ctx* c = as_ctx(ctx);
   if (int r = check_lat(c, lat)) return r;
@@ -577,7 +620,7 @@ static int apply_all_lattices(Ctx* c, int op, int prec, void* out, const void* i
     DslashMulti m{};
     m.nl = nl;
     // input converted with gamma5 for the adjoint of FULL and DP; output flipped for FULL
-    const bool g5_in = dag && op != WCMG_OP_SCHUR, g5_out = dag && op == WCMG_OP_FULL;
+    const bool g5_in = dag && op != WCMG_OP_SCHUR, g5_out = dag && (op == WCMG_OP_FULL || op == WCMG_OP_SCHUR_X);
     for (int r = 0; r < nrhs; ++r) {
       for (int l = 0; l < nl; ++l) {
         const Geom& g = c->lats[l]->F.g;
@@ -603,6 +646,13 @@ static int apply_all_lattices(Ctx* c, int op, int prec, void* out, const void* i
           re = &t1;
           ro = &t2;
         }
+      } else if (op == WCMG_OP_SCHUR_X) {
+        // D_ee x - H_eo D_oo^-1 H_oe x (the adjoint: the same between gamma5s)
+        for (int l = 0; l < nl; ++l) m.a[l] = args(l, t2[l], ie[l], nullptr, 1, 1.0);
+        launch_dslash_multi(prec, 0, true, m, c->st);  // w = A_oo^-1 H_oe x
+        for (int l = 0; l < nl; ++l) m.a[l] = args(l, oe[l], t2[l], ie[l], 0, -1.0);
+        launch_dslash_multi(prec, 2, false, m, c->st);  // out = A_ee x - H_eo w
+        ro = nullptr;
       } else if (op == WCMG_OP_DP) {
         clover_all(t1, ie, 0);
         clover_all(t2, io, 1);
@@ -686,6 +736,10 @@ static int apply_common(void* ctx, int lat, int op, int prec, void* out, const v
         re = ie;
         ro = io;
       }
+    } else if (op == WCMG_OP_SCHUR_X) {
+      fo.Mx(oe, ie, nrhs);  // adjoint: input converted with gamma5 above, output flipped below
+      flip_out = dag;
+      ro = nullptr;
     } else {
       if (!dag)
         fo.Dr(oe, ie, nrhs);
@@ -834,7 +888,7 @@ int wcmg_apply_coarse(void* ctx, int lat, int level, int op, int prec, void* out
   if (int r = check_lat(c, lat)) return r;
   CHECK(out && in, WCMG_EINVAL, "null buffer");
   CHECK(out != in, WCMG_EINVAL, "out and in must not alias");
-  CHECK(valid_op(op), WCMG_EINVAL, "bad operator");
+  CHECK(valid_op(op) && op != WCMG_OP_SCHUR_X, WCMG_EINVAL, "bad operator for a coarse level");
   CHECK(prec == WCMG_F64 || prec == WCMG_F32, WCMG_EINVAL, "coarse precision must be F64 or F32");
   CHECK(nrhs >= 1, WCMG_EINVAL, "nrhs must be >= 1");
   LatticeState& L = *c->lats[lat];
@@ -879,7 +933,8 @@ int wcmg_coarse_solve(void* ctx, int lat, int level, int prec, void* x, const vo
   CHECK(tol > 0 && tol < 1, WCMG_EINVAL, "tol must be in (0,1)");
   CHECK(max_iter >= 1 && restart >= 1 && restart <= kMaxRestart, WCMG_EINVAL,
         "max_iter must be >= 1 and restart in 1..64");
-  CHECK(launch >= 0 && launch <= 2, WCMG_EINVAL, "launch must be 0, 1 or 2");
+  CHECK(launch >= 0 && launch <= 4, WCMG_EINVAL, "launch must be 0..4");
+  CHECK(launch < 3 || prec == WCMG_F32, WCMG_EINVAL, "FP16 hop blocks (launch 3, 4) go with F32");
   LatticeState& L = *c->lats[lat];
   CHECK(L.have_params && level >= 1 && level <= L.params.nlevels, WCMG_EINVAL, "level out of range");
   CHECK((int)L.levels.size() >= level && L.levels[level - 1]->built, WCMG_ESTATE, "coarse operator not built");
@@ -904,7 +959,8 @@ int wcmg_coarse_solve(void* ctx, int lat, int level, int prec, void* x, const vo
       PersistWork pw;
       if (!persistent_available(pw, prec, C, restart))
         fail(WCMG_ENODEV, "the device cannot run the persistent coarse solve");
-      persistent_launch(*c, pw, C, prec, vx, vb, t, y, r, br, tol, restart, max_iter, false, launch == 2);
+      persistent_launch(*c, pw, C, prec, vx, vb, t, y, r, br, tol, restart, max_iter, false,
+                        launch == 2 || launch == 4, launch >= 3);
       int code = WCMG_OK;
       s.iters = (int)persistent_collect(*c, pw, &code);
       s.status = code;

@@ -64,6 +64,15 @@ __device__ __forceinline__ void ld2(const double2* p, cpx<double>& e0, cpx<doubl
   e0 = mk(t0.x, t0.y);
   e1 = mk(t1.x, t1.y);
 }
+// FP16 hop blocks (the coarse_fp16 storage): two complex halves in 8 bytes,
+// widened exactly to FP32
+__device__ __forceinline__ void ld2(const __half2* p, cpx<float>& e0, cpx<float>& e1) {
+  const uint2 t = *reinterpret_cast<const uint2*>(p);
+  const float2 a = __half22float2(__builtin_bit_cast(__half2, t.x));
+  const float2 b = __half22float2(__builtin_bit_cast(__half2, t.y));
+  e0 = mk(a.x, a.y);
+  e1 = mk(b.x, b.y);
+}
 
 // Device-coherent access (relaxed atomics at agent scope: write-through
 // stores, loads that do not hit stale lines of another compute unit or XCD)
@@ -281,8 +290,9 @@ struct PArgs {
   unsigned* lflags;  // neighbour-wait lines of the one-site kernel, one per workgroup
   double tol;
   int Vh, n, restart, maxiter, fixed, G, stride;
-  int sbytes;  // one-site kernel: LDS bytes before the Krylov basis
-  int pl;      // one-site kernel: hop matrix column rounds staged in LDS
+  int sbytes;   // one-site kernel: LDS bytes before the Krylov basis
+  int pl;       // one-site kernel: hop matrix column rounds staged in LDS
+  int res_off;  // one-site kernel: LDS byte offset of the even site's resident hop blocks (-1: none)
 };
 
 // largest power of two below G (0 for G = 1): first step of the tree that adds
@@ -331,8 +341,9 @@ __device__ __forceinline__ void site_matvec(const V2* M, const cpx<C>* v, int n,
 
 // out(c) = xd(c) + coeff * sum_d Yt_d(c) in(nb(c, d))     (xd may be null)
 // and, with Xl, out(c) = Xl(c) [ ... ] instead; with q, the neighbour values
-// are in - alpha q (rounded as the owner rounds them)
-template <typename S>
+// are in - alpha q (rounded as the owner rounds them).  MT: storage of the hop
+// blocks (the vector type, or __half2 for FP16 blocks with FP32 arithmetic).
+template <typename S, typename MT>
 __device__ void site_hop(const PArgs& a, int c, const void* in_, const void* xd_, double coeff, const void* Xl_,
                          void* out_, cpx<typename Compute<S>::T>* vin, cpx<typename Compute<S>::T>* part,
                          const void* q_ = nullptr, cpx<double> alpha = cpx<double>{0.0, 0.0}) {
@@ -357,7 +368,7 @@ __device__ void site_hop(const PArgs& a, int c, const void* in_, const void* xd_
   }
   __syncthreads();
   cpx<C> o[2];
-  site_matvec<C, V2>(reinterpret_cast<const V2*>(a.Yt) + (size_t)c * 8 * n * n, vin, n, 8 * n, a.G, part, o[0],
+  site_matvec<C, MT>(reinterpret_cast<const MT*>(a.Yt) + (size_t)c * 8 * n * n, vin, n, 8 * n, a.G, part, o[0],
                      o[1]);
   const int R2 = n >> 1;
   const int g = threadIdx.x / R2, rp = threadIdx.x - g * R2;
@@ -434,7 +445,7 @@ __device__ void site_local(const PArgs& a, int c, const void* in_, const void* X
   }
 }
 
-template <typename S>
+template <typename S, typename MT>
 __global__ void __launch_bounds__(kPT) k_coarse_gcr(PArgs a) {
   using C = typename Compute<S>::T;
   using V2 = typename Vec2<S>::T;
@@ -467,7 +478,7 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr(PArgs a) {
   auto Zv = [&](int j) { return reinterpret_cast<V2*>(a.Z) + (size_t)j * hv; };
 
   // reduced source, r = b_r, y = 0, ||b_r||^2
-  for (int i = w; i < Vh; i += W) site_hop<S>(a, i, a.b, a.b, -1.0, nullptr, a.br, vin, hp);
+  for (int i = w; i < Vh; i += W) site_hop<S, MT>(a, i, a.b, a.b, -1.0, nullptr, a.br, vin, hp);
   __syncthreads();
   V2* r = reinterpret_cast<V2*>(a.r);
   V2* qraw = reinterpret_cast<V2*>(a.qraw);
@@ -497,7 +508,7 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr(PArgs a) {
   __shared__ double salpha[3];  // alpha (re, im) and ||q_k||^2 of the current step
   while (!conv && iters < a.maxiter) {
     // cycle start: z_0 = r, t = Ytilde_oe r
-    for (int i = w; i < Vh; i += W) site_hop<S>(a, Vh + i, r, nullptr, 1.0, nullptr, a.t, vin, hp);
+    for (int i = w; i < Vh; i += W) site_hop<S, MT>(a, Vh + i, r, nullptr, 1.0, nullptr, a.t, vin, hp);
     for (int idx = threadIdx.x; idx < nel; idx += kPT) {
       const size_t e = el(idx);
       stc(Zv(0) + e, ldc(r + e));
@@ -509,7 +520,7 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr(PArgs a) {
       V2* Zk = Zv(k);
       V2* Tk = Tv(k);
       // q = D_r z_k = r - Ytilde_eo t; <q_j, q> for j < k, ||q||^2 and <q, r> over the owned sites
-      for (int i = w; i < Vh; i += W) site_hop<S>(a, i, a.t, r, -1.0, nullptr, a.qraw, vin, hp);
+      for (int i = w; i < Vh; i += W) site_hop<S, MT>(a, i, a.t, r, -1.0, nullptr, a.qraw, vin, hp);
       __syncthreads();
       {
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -609,7 +620,7 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr(PArgs a) {
         }
       }
       // odd sites: T_k = Ytilde_oe q_k = Ytilde_oe q - sum_j c_j T_j, and t -= alpha T_k
-      for (int i = w; i < Vh; i += W) site_hop<S>(a, Vh + i, a.qraw, nullptr, 1.0, nullptr, Tk, vin, hp);
+      for (int i = w; i < Vh; i += W) site_hop<S, MT>(a, Vh + i, a.qraw, nullptr, 1.0, nullptr, Tk, vin, hp);
       __syncthreads();
       {
         cpx<double>* acc = reinterpret_cast<cpx<double>*>(smem);  // [kPT]
@@ -658,9 +669,9 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr(PArgs a) {
     }
     if (status || a.fixed) break;
     // true residual r = b_r - D_r y at the end of the cycle (q_raw as scratch)
-    for (int i = w; i < Vh; i += W) site_hop<S>(a, Vh + i, a.y, nullptr, 1.0, nullptr, a.t, vin, hp);
+    for (int i = w; i < Vh; i += W) site_hop<S, MT>(a, Vh + i, a.y, nullptr, 1.0, nullptr, a.t, vin, hp);
     if (!sync_sum(0)) return;
-    for (int i = w; i < Vh; i += W) site_hop<S>(a, i, a.t, a.y, -1.0, nullptr, a.qraw, vin, hp);
+    for (int i = w; i < Vh; i += W) site_hop<S, MT>(a, i, a.t, a.y, -1.0, nullptr, a.qraw, vin, hp);
     __syncthreads();
     {
       double v[1] = {0.0};
@@ -683,7 +694,7 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr(PArgs a) {
   // c_e = X_ee^-1 y,  c_o = X_oo^-1 (b_o - Ytilde_oe y)   (y is final and visible after the last barrier)
   for (int i = w; i < Vh; i += W) {
     site_local<S>(a, i, a.y, a.Xinv, a.c, vin, hp);
-    site_hop<S>(a, Vh + i, a.y, a.b, -1.0, a.Xinv, a.c, vin, hp);
+    site_hop<S, MT>(a, Vh + i, a.y, a.b, -1.0, a.Xinv, a.c, vin, hp);
   }
   if (w == 0 && threadIdx.x == 0) {
     a.info[0] += iters;
@@ -758,16 +769,20 @@ __device__ __forceinline__ V2 tov2(cpx<double> c) {
 // hop matrix go straight to LDS (global_load_lds, no registers) and the next
 // few into registers before the gather is issued, so the matrix stream and the
 // gather latency overlap; the rest is loaded as in site_matvec, and the sums
-// run in its order.
-template <typename S>
+// run in its order.  With Mres (the site's hop blocks resident in LDS) every
+// column comes from there and nothing is prefetched; the order of the sums is
+// the same.  MT: storage of the hop blocks (FP16 blocks are never staged by
+// global_load_lds: a.pl is 0 for them).
+template <typename S, typename MT>
 __device__ void hop1(const PArgs& a, int c, int nb, const typename Vec2<S>::T* in, const typename Vec2<S>::T* xdl,
                      const typename Vec2<S>::T* xdg, double coeff, const void* Xl, typename Vec2<S>::T* outg,
                      typename Vec2<S>::T* outl, cpx<typename Compute<S>::T>* vin,
-                     cpx<typename Compute<S>::T>* part, char* pre) {
+                     cpx<typename Compute<S>::T>* part, char* pre, const MT* Mres = nullptr) {
   using C = typename Compute<S>::T;
   using V2 = typename Vec2<S>::T;
   constexpr int NCH = sizeof(S) == 8 ? 2 : 1;  // 16-byte pieces of a thread's two entries of a column
-  const int n = a.n, G = a.G, R2 = n >> 1, ncols = 8 * n, PL = a.pl;
+  constexpr bool kStage = sizeof(MT) == sizeof(V2);  // LDS staging exists for blocks in the vector type only
+  const int n = a.n, G = a.G, R2 = n >> 1, ncols = 8 * n, PL = (kStage && !Mres) ? a.pl : 0;
   // the thread index passes through an empty asm, so that the addresses derived
   // from it are formed here and not kept live across the whole solve (register
   // pressure: the hop is inlined at seven call sites)
@@ -775,9 +790,9 @@ __device__ void hop1(const PArgs& a, int c, int nb, const typename Vec2<S>::T* i
   asm volatile("" : "+v"(tid));
   const int g = tid / R2, rp = tid - g * R2;
   const int lane = tid & 63, wv = tid >> 6, NW = (G * R2 + 63) >> 6;
-  const V2* M = reinterpret_cast<const V2*>(a.Yt) + (size_t)c * 8 * n * n + 2 * rp;
+  const MT* M = (Mres ? Mres : reinterpret_cast<const MT*>(a.Yt) + (size_t)c * 8 * n * n) + 2 * rp;
   __syncthreads();  // the previous task is done with vin, part and the prefetch area
-  if (g < G) {
+  if (kStage && g < G) {
     // piece ch of column round u of wavefront wv: 1 KiB at pre + ((u NCH + ch) NW + wv) KiB, lane order
     for (int u = 0; u < PL; ++u) {
       const int col = g + u * G;
@@ -792,14 +807,15 @@ __device__ void hop1(const PArgs& a, int c, int nb, const typename Vec2<S>::T* i
       }
     }
   }
-  // the next PR rounds into registers, also before the gather
+  // the next PR rounds into registers, also before the gather (none from LDS)
   constexpr int PR = sizeof(S) == 8 ? 1 : 4;
+  const int PRr = Mres ? 0 : PR;
   cpx<C> r0[PR], r1[PR];
   if (g < G) {
 #pragma unroll
     for (int u = 0; u < PR; ++u) {
       const int col = g + (PL + u) * G;
-      if (col < ncols) ld2(M + (size_t)col * n, r0[u], r1[u]);
+      if (u < PRr && col < ncols) ld2(M + (size_t)col * n, r0[u], r1[u]);
     }
   }
   if (tid < ncols) {
@@ -831,14 +847,14 @@ __device__ void hop1(const PArgs& a, int c, int nb, const typename Vec2<S>::T* i
 #pragma unroll
     for (int u = 0; u < PR; ++u) {
       const int col = g + (PL + u) * G;
-      if (col < ncols) {
+      if (u < PRr && col < ncols) {
         const cpx<C> x = vin[col];
         cfma(a0, r0[u], x);
         cfma(a1, r1[u], x);
       }
     }
 #pragma unroll 8
-    for (int col = g + (PL + PR) * G; col < ncols; col += G) {
+    for (int col = g + (PL + PRr) * G; col < ncols; col += G) {
       cpx<C> e0, e1;
       ld2(M + (size_t)col * n, e0, e1);
       const cpx<C> x = vin[col];
@@ -890,7 +906,7 @@ __device__ void hop1(const PArgs& a, int c, int nb, const typename Vec2<S>::T* i
   }
 }
 
-template <typename S>
+template <typename S, typename MT>
 __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
   using C = typename Compute<S>::T;
   using V2 = typename Vec2<S>::T;
@@ -931,6 +947,16 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
     for (int d = 0; d < tid; ++d)  // wait once per distinct owner
       if (a.nbr[(size_t)w * 8 + d] - Vh == nbw) nbw = -1;
   }
+  // the even site's hop blocks, resident in LDS for the whole solve when they fit
+  const MT* Mres = nullptr;
+  if (a.res_off >= 0) {
+    uint4* dst = reinterpret_cast<uint4*>(smem + a.res_off);
+    const uint4* src = reinterpret_cast<const uint4*>(reinterpret_cast<const MT*>(a.Yt) + (size_t)w * 8 * n * n);
+    const int n16 = (int)((size_t)8 * n * n * sizeof(MT) / 16);
+    for (int i = tid; i < n16; i += kPT) dst[i] = src[i];
+    Mres = reinterpret_cast<const MT*>(dst);
+    __syncthreads();
+  }
   // epochs continue from what the previous launch left (the same in every line)
   unsigned epoch = __hip_atomic_load(a.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   unsigned lep = __hip_atomic_load(a.lflags + 32 * w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -944,7 +970,7 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
   };
 
   // b_r = b_e - Ytilde_eo b_o, r = b_r, y = 0, ||b_r||^2
-  hop1<S>(a, w, nbE, b, nullptr, b, -1.0, nullptr, nullptr, bm, vin, hp, pre);
+  hop1<S, MT>(a, w, nbE, b, nullptr, b, -1.0, nullptr, nullptr, bm, vin, hp, pre, Mres);
   __syncthreads();
   {
     double v[1] = {0.0};
@@ -969,14 +995,14 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
   }
   while (!conv && iters < a.maxiter) {
     // cycle start: z_0 = r, t = Ytilde_oe r
-    hop1<S>(a, Vh + w, nbO, r, nullptr, nullptr, 1.0, nullptr, t, tm, vin, hp, pre);
+    hop1<S, MT>(a, Vh + w, nbO, r, nullptr, nullptr, 1.0, nullptr, t, tm, vin, hp, pre);
     if (tid < n) Zs[tid] = rm[tid];
     if (!sync_sum(0)) return;
     int k = 0;
     for (;;) {
       // q = D_r z_k = r - Ytilde_eo t on the even site (stored for the odd neighbours);
       // <q_j, q>, ||q||^2, <q, r> and ||r_k||^2
-      hop1<S>(a, w, nbE, t, rm, nullptr, -1.0, nullptr, qraw, qm, vin, hp, pre);
+      hop1<S, MT>(a, w, nbE, t, rm, nullptr, -1.0, nullptr, qraw, qm, vin, hp, pre, Mres);
       __syncthreads();
       {
         const int lane = tid & 63, wave = tid >> 6;
@@ -1078,7 +1104,7 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
         if (k + 1 < R) Zs[(size_t)(k + 1) * n + tid] = rv;
       }
       // odd site: T_k = Ytilde_oe q - sum_j c_j T_j, t -= alpha T_k
-      hop1<S>(a, Vh + w, nbO, qraw, nullptr, nullptr, 1.0, nullptr, nullptr, Ts + (size_t)k * n, vin, hp, pre);
+      hop1<S, MT>(a, Vh + w, nbO, qraw, nullptr, nullptr, 1.0, nullptr, nullptr, Ts + (size_t)k * n, vin, hp, pre);
       __syncthreads();
       if (k > 0 && sl < NS) {
         cpx<double> at = mk(0.0, 0.0);
@@ -1113,9 +1139,9 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
     if (!sync_sum(0)) return;
     if (status || a.fixed) break;
     // true residual r = b_r - D_r y at the end of the cycle
-    hop1<S>(a, Vh + w, nbO, y, nullptr, nullptr, 1.0, nullptr, t, tm, vin, hp, pre);
+    hop1<S, MT>(a, Vh + w, nbO, y, nullptr, nullptr, 1.0, nullptr, t, tm, vin, hp, pre);
     if (!sync_sum(0)) return;
-    hop1<S>(a, w, nbE, t, ym, nullptr, -1.0, nullptr, nullptr, qm, vin, hp, pre);
+    hop1<S, MT>(a, w, nbE, t, ym, nullptr, -1.0, nullptr, nullptr, qm, vin, hp, pre, Mres);
     __syncthreads();
     {
       double v[1] = {0.0};
@@ -1138,7 +1164,7 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
   }
   // c_e = X_ee^-1 y,  c_o = X_oo^-1 (b_o - Ytilde_oe y)   (y is complete after the last grid barrier)
   site_local<S>(a, w, a.y, a.Xinv, a.c, vin, hp);
-  hop1<S>(a, Vh + w, nbO, y, nullptr, b, -1.0, a.Xinv, reinterpret_cast<V2*>(a.c), nullptr, vin, hp, pre);
+  hop1<S, MT>(a, Vh + w, nbO, y, nullptr, b, -1.0, a.Xinv, reinterpret_cast<V2*>(a.c), nullptr, vin, hp, pre);
   if (w == 0 && tid == 0) {
     a.info[0] += iters;
     if (status) a.info[1] = status;
@@ -1169,17 +1195,15 @@ int coarse_gcr_persistent_grid(int prec, int n, int Vh) {
   const size_t shm = std::max((size_t)(8 * n + G * n) * cb, (size_t)2 * kPT * 16);
   int per = 0;
   if (prec == WCMG_F64)
-    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_coarse_gcr<double>, kPT, shm));
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_coarse_gcr<double, double2>, kPT, shm));
   else
-    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_coarse_gcr<float>, kPT, shm));
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_coarse_gcr<float, float2>, kPT, shm));
   if (per < 1) return 0;
   return std::min(std::min(ncu, Vh), 256);
 }
 
-// whether one workgroup of the one-site kernel with `bytes` of dynamic LDS fits a compute unit
-static bool site_kernel_fits(int prec, size_t bytes) {
-  const void* k = prec == WCMG_F64 ? reinterpret_cast<const void*>(k_coarse_gcr_site<double>)
-                                   : reinterpret_cast<const void*>(k_coarse_gcr_site<float>);
+// whether one workgroup of kernel k with `bytes` of dynamic LDS fits a compute unit
+static bool kernel_fits(const void* k, size_t bytes) {
   if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) {
     (void)hipGetLastError();
     return false;
@@ -1197,6 +1221,7 @@ void launch_coarse_gcr_persistent(int prec, const CoarseGcrArgs& g, hipStream_t 
   if (n % 2 || n > 256) fail(WCMG_EDIM, "coarse block size must be even and <= 256");
   if (g.restart < 1 || g.restart > kPMaxRestart) fail(WCMG_EINVAL, "coarse restart length out of range");
   if (g.grid < 1 || g.grid > 256) fail(WCMG_EINVAL, "persistent coarse solve needs 1..256 workgroups");
+  if (g.mat16 && prec != WCMG_F32) fail(WCMG_EINVAL, "FP16 hop blocks go with FP32 vectors");
   PArgs a{};
   a.Yt = g.Yt;
   a.Xinv = g.Xinv;
@@ -1221,6 +1246,7 @@ void launch_coarse_gcr_persistent(int prec, const CoarseGcrArgs& g, hipStream_t 
   a.maxiter = g.maxiter;
   a.fixed = g.fixed;
   a.stride = (int)coarse_gcr_persistent_part_doubles();
+  a.res_off = -1;
   const int G = persist_groups(n);
   a.G = G;
   const size_t cb = prec == WCMG_F64 ? 16 : 8;
@@ -1230,33 +1256,34 @@ void launch_coarse_gcr_persistent(int prec, const CoarseGcrArgs& g, hipStream_t 
   void* args[] = {&a};
   // one site per workgroup: vin, the column-group partials and as many rounds of
   // hop matrix columns as fit, overlapped by the Gram-Schmidt slice sums; then
-  // the basis [3][restart][n] and five site copies
+  // the basis [3][restart][n] and five site copies.  FP16 hop blocks: no staged
+  // rounds; instead the even site's 8 n^2 blocks stay in LDS for the whole solve
+  // when they fit.
   const size_t basis = (size_t)(3 * g.restart + 5) * n * cb;
   const size_t hopb = (size_t)(8 * n + G * n) * cb;
   const size_t round = (prec == WCMG_F64 ? 2 : 1) * (size_t)((G * (n / 2) + 63) / 64) * 1024;
   const size_t lds_cap = 160 * 1024 - 4096;  // minus the kernel's static LDS, with margin
   const int rounds = (8 * n + G - 1) / G;
   int pl = 0;
-  if (lds_cap > basis + hopb) pl = (int)std::min<size_t>(rounds, (lds_cap - basis - hopb) / round);
+  if (!g.mat16 && lds_cap > basis + hopb) pl = (int)std::min<size_t>(rounds, (lds_cap - basis - hopb) / round);
   const size_t sb = std::max(hopb + (size_t)pl * round, (size_t)2 * kPT * 16);
-  const size_t site_shm = sb + basis;
-  if (!g.general && g.grid == g.Vh && 8 * n <= kPT && site_shm <= lds_cap && site_kernel_fits(prec, site_shm)) {
+  const size_t res = g.mat16 ? (size_t)8 * n * n * 4 : 0;
+  const bool resident = g.mat16 && sb + basis + res <= lds_cap;
+  const size_t site_shm = sb + basis + (resident ? res : 0);
+  const void* ks = prec == WCMG_F64 ? reinterpret_cast<const void*>(k_coarse_gcr_site<double, double2>)
+                   : g.mat16      ? reinterpret_cast<const void*>(k_coarse_gcr_site<float, __half2>)
+                                  : reinterpret_cast<const void*>(k_coarse_gcr_site<float, float2>);
+  if (!g.general && g.grid == g.Vh && 8 * n <= kPT && site_shm <= lds_cap && kernel_fits(ks, site_shm)) {
     a.sbytes = (int)sb;
     a.pl = pl;
-    if (prec == WCMG_F64)
-      HIPCHK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_coarse_gcr_site<double>), dim3(g.grid),
-                                        dim3(kPT), args, (unsigned)site_shm, st));
-    else
-      HIPCHK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_coarse_gcr_site<float>), dim3(g.grid),
-                                        dim3(kPT), args, (unsigned)site_shm, st));
+    if (resident) a.res_off = (int)(sb + basis);
+    HIPCHK(hipLaunchCooperativeKernel(ks, dim3(g.grid), dim3(kPT), args, (unsigned)site_shm, st));
     return;
   }
-  if (prec == WCMG_F64)
-    HIPCHK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_coarse_gcr<double>), dim3(g.grid), dim3(kPT),
-                                      args, (unsigned)shm, st));
-  else
-    HIPCHK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_coarse_gcr<float>), dim3(g.grid), dim3(kPT),
-                                      args, (unsigned)shm, st));
+  const void* kg = prec == WCMG_F64 ? reinterpret_cast<const void*>(k_coarse_gcr<double, double2>)
+                   : g.mat16      ? reinterpret_cast<const void*>(k_coarse_gcr<float, __half2>)
+                                  : reinterpret_cast<const void*>(k_coarse_gcr<float, float2>);
+  HIPCHK(hipLaunchCooperativeKernel(kg, dim3(g.grid), dim3(kPT), args, (unsigned)shm, st));
 }
 
 }  // namespace wcmg

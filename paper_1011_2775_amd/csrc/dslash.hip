@@ -211,12 +211,13 @@ __device__ __forceinline__ void clover_multi(const void* clov, int Vh, int p, in
 // FP32 spinors); lb: the lattice's logical block
 // RED (DIAG = 1, one right-hand side): also add <out, x> and ||out||^2 of the
 // site, in FP64 from the stored values, to red[0..3)
+// g0: first right-hand side of the thread's group (-1: blockIdx.y * NR)
 template <typename S, typename G, int DIAG, bool POSTINV, int NR, bool STREAM = false, bool RED = false>
-__device__ __forceinline__ void dslash_site(const DslashArgs& a, int lb, double* red = nullptr) {
+__device__ __forceinline__ void dslash_site(const DslashArgs& a, int lb, double* red = nullptr, int g0 = -1) {
   using C = typename Compute<S>::T;
   const int i = lb * blockDim.x + threadIdx.x;
   if (lb >= a.nblocks || i >= a.g.Vh) return;
-  const int g0 = blockIdx.y * NR;
+  if (g0 < 0) g0 = blockIdx.y * NR;
   const int nr = min(NR, a.nrhs - g0);
   const int p = a.parity;
   int c[4];
@@ -287,6 +288,18 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a) {
   dslash_site<S, G, DIAG, POSTINV, NR, STREAM>(a, xcd_block(a.nblocks));
 }
 
+// Several right-hand sides, one per thread: logical workgroup L handles site
+// block L / nrhs of right-hand side L % nrhs, so the nrhs workgroups of a site
+// block are consecutive, land on one XCD (xcd_block) and run close together:
+// the first to read a link or clover record brings it into that XCD's L2 and
+// the others find it there, while every thread keeps the register budget of
+// the single-right-hand-side kernel.
+template <typename S, typename G, int DIAG, bool POSTINV, bool STREAM>
+__global__ void __launch_bounds__(256) dslash_kernel_rhs(DslashArgs a) {
+  const int L = xcd_block(a.nblocks * a.nrhs);
+  dslash_site<S, G, DIAG, POSTINV, 1, STREAM>(a, L / a.nrhs, nullptr, L % a.nrhs);
+}
+
 // The DIAG = 1 hop of D_r with the minimal-residual sums of the smoother
 // fused in: out = x + coeff H in, and <out, x>, ||out||^2 reduced into o in
 // the same launch (every block, padding blocks included, takes part in the
@@ -324,6 +337,23 @@ __global__ void __launch_bounds__(256) clover_kernel(void* out, const void* in, 
 #pragma unroll
   for (int r = 0; r < NR; ++r)
     if (r < nr) SpinorIO<S>::store(const_cast<void*>(rhs_ptr<S>(out, rstride, g0 + r)), Vh, i, o[r]);
+}
+
+// Several right-hand sides, one per thread, in interleaved workgroups (as
+// dslash_kernel_rhs): the nrhs workgroups of a site block are consecutive, so
+// the clover records they share are read once from HBM and then from L2.
+template <typename S, typename G>
+__global__ void __launch_bounds__(256) clover_kernel_rhs(void* out, const void* in, const void* clov, int Vh, int p,
+                                                         int kind, int nrhs, size_t rstride, int nblocks) {
+  using C = typename Compute<S>::T;
+  const int L = xcd_block(nblocks * nrhs);
+  const int lb = L / nrhs, r = L - lb * nrhs;
+  const int i = lb * blockDim.x + threadIdx.x;
+  if (lb >= nblocks || i >= Vh) return;
+  cpx<C> v[1][12], o[1][12];
+  SpinorIO<S>::load(rhs_ptr<S>(in, rstride, r), Vh, i, v[0]);
+  clover_multi<G, C, 1>(clov, Vh, p, kind, i, 1, v, o);
+  SpinorIO<S>::store(const_cast<void*>(rhs_ptr<S>(out, rstride, r)), Vh, i, o[0]);
 }
 
 // The smoother's minimal-residual update of the previous step fused into the
@@ -405,7 +435,34 @@ static void launch_dslash_nr(int diag, bool postinv, DslashArgs a, hipStream_t s
 }
 
 template <typename S, typename G>
+static void launch_dslash_rhs(int diag, bool postinv, DslashArgs a, hipStream_t st) {
+  const int threads = a.threads > 0 ? a.threads : 256;
+  if (threads != 64 && threads != 128 && threads != 256) fail(WCMG_EINVAL, "unsupported Dslash block size");
+  a.nblocks = (a.g.Vh + threads - 1) / threads;
+  if ((long)a.nblocks * a.nrhs > (1L << 30)) fail(WCMG_EINVAL, "too many workgroups");
+  const dim3 grid(xcd_grid(a.nblocks * a.nrhs));
+  const bool stream = a.stream >= 0 ? a.stream != 0 : (double)a.g.Vh * 432.0 * sizeof(G) > 192.0e6;
+#define WCMG_DR(D, P)                                                                                 \
+  do {                                                                                              \
+    if (stream)                                                                                     \
+      hipLaunchKernelGGL((dslash_kernel_rhs<S, G, D, P, true>), grid, dim3(threads), 0, st, a);     \
+    else                                                                                            \
+      hipLaunchKernelGGL((dslash_kernel_rhs<S, G, D, P, false>), grid, dim3(threads), 0, st, a);    \
+  } while (0)
+  if (diag == 0 && !postinv) WCMG_DR(0, false);
+  else if (diag == 0 && postinv) WCMG_DR(0, true);
+  else if (diag == 1 && !postinv) WCMG_DR(1, false);
+  else if (diag == 1 && postinv) WCMG_DR(1, true);
+  else if (diag == 2 && !postinv) WCMG_DR(2, false);
+  else WCMG_DR(2, true);
+#undef WCMG_DR
+  HIPCHK(hipGetLastError());
+}
+
+template <typename S, typename G>
 static void launch_dslash_t(int diag, bool postinv, const DslashArgs& a, hipStream_t st) {
+  // several right-hand sides: one per thread, interleaved workgroups, unless a group size is asked for
+  if (a.nrhs > 1 && (a.group == 0 || a.group == -1)) return launch_dslash_rhs<S, G>(diag, postinv, a, st);
   int g = a.nrhs >= max_group<S>() ? max_group<S>() : (a.nrhs >= 2 ? 2 : 1);
   if (a.group > 0) g = std::min(a.group, max_group<S>());
   if (g == 1) launch_dslash_nr<S, G, 1>(diag, postinv, a, st);
@@ -460,6 +517,12 @@ static void launch_clover_nr(void* out, const void* in, const void* clov, int Vh
 template <typename S, typename G>
 static void launch_clover_t(void* out, const void* in, const void* clov, int Vh, int p, int kind, int nrhs,
                             size_t rstride, hipStream_t st) {
+  if (nrhs > 1) {
+    const int nb = (Vh + 255) / 256;
+    hipLaunchKernelGGL((clover_kernel_rhs<S, G>), dim3(xcd_grid(nb * nrhs)), dim3(256), 0, st, out, in, clov, Vh, p,
+                       kind, nrhs, rstride, nb);
+    return;
+  }
   if (nrhs >= max_group<S>()) launch_clover_nr<S, G, max_group<S>()>(out, in, clov, Vh, p, kind, nrhs, rstride, st);
   else if (nrhs >= 2) launch_clover_nr<S, G, 2>(out, in, clov, Vh, p, kind, nrhs, rstride, st);
   else launch_clover_nr<S, G, 1>(out, in, clov, Vh, p, kind, nrhs, rstride, st);

@@ -19,7 +19,8 @@ struct DslashArgs {
   int nrhs = 1;        // right-hand sides: out, in, x hold nrhs spinors
   size_t rstride = 0;  // bytes between consecutive right-hand sides
   int threads = 0;     // launch shape: threads per block (64, 128, 256; 0 = 256)
-  int group = 0;       // right-hand sides per thread (1, 2, 4; 0 = largest that fits)
+  int group = 0;       // right-hand sides per thread (1, 2, 4; 0 = default); -1: one per thread, the
+                       // right-hand sides of a site block in consecutive workgroups (fields shared in L2)
   int fprec = -1;      // storage of gauge and clover (-1: as the spinors; F16 with F32 spinors)
   int stream = -1;     // non-temporal field loads: 1 on, 0 off, -1 when the fields exceed the Infinity Cache
 };
@@ -292,6 +293,7 @@ struct CoarseGcrArgs {
   double tol;
   int Vh, n, restart, maxiter, fixed, grid;
   int general;  // always the strided kernel
+  int mat16;    // Yt holds FP16 hop blocks (FP32 vectors and arithmetic)
 };
 size_t coarse_gcr_persistent_part_doubles();
 // workgroups of the persistent coarse solve on this device (0: not available)

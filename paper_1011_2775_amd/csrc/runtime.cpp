@@ -195,8 +195,8 @@ void FineOp::hop(void* out, const void* in, const void* x, int parity, int diag,
       HIPCHK(hipEventCreate(&e1));
       const int max_g = prec == WCMG_F64 ? 2 : 4;
       for (int threads : {64, 128, 256})
-        for (int group : {1, 2, 4}) {
-          if (group > max_g || (group > 1 && group > nrhs)) continue;
+        for (int group : {-1, 1, 2, 4}) {
+          if (group > max_g || (group > 1 && group > nrhs) || (group < 0 && nrhs == 1)) continue;
           DslashArgs t = a;
           t.threads = threads;
           t.group = group;
@@ -282,6 +282,12 @@ bool FineOp::Dr_red(void* out, void* y, const RedOut& o, void* e, const double* 
   if (ev) ctx->timer.end(id, ev);
   if (!ok) fail(WCMG_EINVAL, "fused smoother hop rejected after its checks passed");
   return true;
+}
+
+void FineOp::Mx(void* out, const void* x, int nrhs) {
+  w->ensure(prec, F->g, nrhs);
+  hop(w->t2.p, x, nullptr, 1, 0, true, 1.0, nrhs);  // w = A_oo^-1 H_oe x
+  hop(out, w->t2.p, x, 0, 2, false, -1.0, nrhs);    // out = A_ee x - H_eo w
 }
 
 void FineOp::Dr_dag(void* out, const void* y, int nrhs) {

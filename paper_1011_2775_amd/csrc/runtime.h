@@ -109,6 +109,9 @@ struct FineOp {
   // D_r result) before D_r is applied to the updated y.
   bool Dr_red(void* out, void* y, const RedOut& o, void* e = nullptr, const double* coef = nullptr);
   void Dr_dag(void* out, const void* y, int nrhs = 1);
+  // the same reduced system in the variable x = A_ee^-1 y: out = A_ee x - H_eo A_oo^-1 H_oe x
+  // (two launches; its adjoint is gamma5 Mx gamma5)
+  void Mx(void* out, const void* x, int nrhs = 1);
   // full-lattice operators on (even, odd) halves
   void D(void* oe, void* oo, const void* ie, const void* io, int nrhs = 1);
   void Dp(void* oe, void* oo, const void* ie, const void* io, int nrhs = 1);
@@ -126,6 +129,7 @@ struct CoarseLevel {
   DBuf nbr, perm;              // device int arrays
   DBuf Y9;                     // FP64 [site][9][n][n]
   DBuf X[2], Xinv[2], Yhop[2], Yt[2];  // [0] FP64, [1] FP32
+  DBuf Yt16;                           // FP16 copy of Yt for the persistent coarsest solve (coarse_fp16)
   DBuf frag;              // FP16 matrix-core fragments of Yt (batched stencil)
   bool has_frag = false;
 };
@@ -285,7 +289,7 @@ bool persistent_available(PersistWork& w, int prec, const CoarseLevel& C, int re
 // out = approximate Dhat^-1 in (full coarse vectors); t: full scratch, y, r, br: >= half vectors
 void persistent_launch(Ctx& c, PersistWork& w, CoarseLevel& C, int prec, void* out, const void* in, void* t, void* y,
                        void* r, void* br, double tol, int restart, int maxiter, bool fixed,
-                       bool general = false);
+                       bool general = false, bool mat16 = false);
 // iterations since the last collect; status (optional) gets the first failure code
 long persistent_collect(Ctx& c, PersistWork& w, int* status = nullptr);
 // the persistent launch on caller-provided buffers (sizes as for launch_coarse_gcr_persistent;
@@ -297,7 +301,7 @@ struct PersistBufs {
 };
 void persistent_launch_bufs(Ctx& c, int grid, const PersistBufs& B, CoarseLevel& C, int prec, void* out,
                             const void* in, void* t, void* y, void* r, void* br, double tol, int restart,
-                            int maxiter, bool fixed, bool general);
+                            int maxiter, bool fixed, bool general, bool mat16 = false);
 
 KrylovResult bicgstab(Ctx& c, int prec, size_t n, const OpFn& A, void* x, const void* b, double tol,
                       double target_norm, int maxiter);
@@ -312,6 +316,7 @@ double norm2(Ctx& c, int prec, const void* x, size_t n);
 // multigrid driver
 void mg_setup_null_vectors(Ctx& c, LatticeState& L, int level);
 void mg_build_coarse(Ctx& c, LatticeState& L, int level);
+void mg_refine_null_vectors(Ctx& c, LatticeState& L, int passes, int iters);
 struct MGSolver;
 void solve_rhs(Ctx& c, LatticeState& L, int solver, void* x_e, void* x_o, const void* b_e, const void* b_o,
                bool x_zero, double tol, wcmg_stats* st);

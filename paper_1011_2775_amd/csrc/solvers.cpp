@@ -432,7 +432,7 @@ KrylovResult mp_bicgstab(Ctx& c, LatticeState& L, void* y, const void* b, bool y
   if (y_zero) blas_zero(WCMG_F64, y, n, st);
   KrylovResult res;
   const double target = tol * target_norm;
-  int ncyc = 0;
+  int ncyc = 0, first_iters = 0;
   double prev = std::numeric_limits<double>::infinity();
   for (;;) {
     op64.Dr(r, y);
@@ -449,19 +449,34 @@ KrylovResult mp_bicgstab(Ctx& c, LatticeState& L, void* y, const void* b, bool y
       break;
     }
     prev = rn;
-    blas_convert(WCMG_F32, r32, WCMG_F64, r, n, st);
+    spinor_convert(WCMG_F32, r32, WCMG_F64, r, g.Vh, st);  // spinor layouts differ per precision
     blas_zero(WCMG_F32, e32, n, st);
     // the inner solve stops at inner_tol, or at the outer target if that is looser
     const double itol = std::max(inner_tol, 0.5 * target / rn);
-    KrylovResult k = bicgstab(c, WCMG_F32, n, A32, e32, r32, std::min(itol, 0.5), rn, maxiter - res.iters);
+    // later cycles get at most three times the first one's iterations (an FP32
+    // solve that stagnates near the critical mass would otherwise spend the budget)
+    const int cap = ncyc == 0 ? maxiter - res.iters : std::min(maxiter - res.iters, std::max(1000, 3 * first_iters));
+    KrylovResult k = bicgstab(c, WCMG_F32, n, A32, e32, r32, std::min(itol, 0.5), rn, cap);
+    if (ncyc == 0) first_iters = k.iters;
     res.iters += k.iters;
     ++ncyc;
     if (k.status == WCMG_ENAN) {
       res.status = WCMG_ENAN;
       break;
     }
-    blas_convert(WCMG_F64, e, WCMG_F32, e32, n, st);
+    spinor_convert(WCMG_F64, e, WCMG_F32, e32, g.Vh, st);
     blas_axpby(WCMG_F64, 1.0, 0.0, e, 1.0, 0.0, y, n, st);  // y += e
+    // a correction that does not lower the FP64 residual (an FP32 solve that
+    // diverged) is taken back, and the refinement stops there
+    op64.Dr(r, y);
+    blas_axpby(WCMG_F64, 1.0, 0.0, b, -1.0, 0.0, r, n, st);
+    const double rn_new = std::sqrt(norm2(c, WCMG_F64, r, n));
+    if (!(rn_new < rn)) {
+      blas_axpby(WCMG_F64, -1.0, 0.0, e, 1.0, 0.0, y, n, st);  // y -= e
+      res.rel_res = target_norm > 0 ? rn / target_norm : 0.0;
+      res.status = WCMG_ENOCONV;
+      break;
+    }
   }
   if (cycles) *cycles = ncyc;
   return res;
@@ -551,10 +566,12 @@ bool persistent_available(PersistWork& w, int prec, const CoarseLevel& C, int re
 
 void persistent_launch_bufs(Ctx& c, int grid, const PersistBufs& B, CoarseLevel& C, int prec, void* out,
                             const void* in, void* t, void* y, void* r, void* br, double tol, int restart,
-                            int maxiter, bool fixed, bool general) {
+                            int maxiter, bool fixed, bool general, bool mat16) {
   CoarseGcrArgs a{};
   const int pi = prec == WCMG_F64 ? 0 : 1;
-  a.Yt = C.Yt[pi].p;
+  if (mat16 && (prec != WCMG_F32 || !C.Yt16.p)) fail(WCMG_EINVAL, "FP16 hop blocks need FP32 vectors");
+  a.Yt = mat16 ? C.Yt16.p : C.Yt[pi].p;
+  a.mat16 = mat16 ? 1 : 0;
   a.Xinv = C.Xinv[pi].p;
   a.nbr = C.nbr.as<int>();
   a.b = in;
@@ -582,7 +599,8 @@ void persistent_launch_bufs(Ctx& c, int grid, const PersistBufs& B, CoarseLevel&
 }
 
 void persistent_launch(Ctx& c, PersistWork& w, CoarseLevel& C, int prec, void* out, const void* in, void* t, void* y,
-                       void* r, void* br, double tol, int restart, int maxiter, bool fixed, bool general) {
+                       void* r, void* br, double tol, int restart, int maxiter, bool fixed, bool general,
+                       bool mat16) {
   const size_t cs = prec == WCMG_F64 ? 16 : 8;
   const size_t hv = (size_t)C.cg.Vh * C.cg.n;
   restart = std::min(restart, std::max(1, maxiter));
@@ -596,7 +614,7 @@ void persistent_launch(Ctx& c, PersistWork& w, CoarseLevel& C, int prec, void* o
     HIPCHK(hipMemsetAsync(w.ctl.p, 0, kPersistCtlBytes, c.st));
   }
   PersistBufs B{w.q.p, w.z.p, w.t.p, w.qraw.p, w.part.as<double>(), w.ctl.p};
-  persistent_launch_bufs(c, w.grid, B, C, prec, out, in, t, y, r, br, tol, restart, maxiter, fixed, general);
+  persistent_launch_bufs(c, w.grid, B, C, prec, out, in, t, y, r, br, tol, restart, maxiter, fixed, general, mat16);
   w.pending = true;
 }
 
@@ -747,7 +765,8 @@ struct MGSolver {
     hipEvent_t e = nullptr;
     if (c.timer.on) c.timer.begin(id, &e);
     persistent_launch(c, V.pw, *L.levels[li], cp, out, in, V.rfull.p, V.cy.p, V.res.p, V.cbr.p, p.tol[li],
-                      p.restart[li], p.max_iter[li], fixed(), p.coarse_launch == 2);
+                      p.restart[li], p.max_iter[li], fixed(), p.coarse_launch == 2,
+                      p.coarse_fp16 != 0 && cp == WCMG_F32);
     if (e) c.timer.end(id, e);
   }
 
@@ -1261,6 +1280,8 @@ static void finalize_coarse(Ctx& c, CoarseLevel& C, int* flag) {
   launch_reals_convert(WCMG_F32, C.Xinv[1].p, C.Xinv[0].as<double>(), (size_t)V * nn * 2, st);
   launch_reals_convert(WCMG_F32, C.Yhop[1].p, C.Yhop[0].as<double>(), (size_t)V * 8 * nn * 2, st);
   launch_reals_convert(WCMG_F32, C.Yt[1].p, C.Yt[0].as<double>(), (size_t)V * 8 * nn * 2, st);
+  C.Yt16.alloc((size_t)V * 8 * nn * 4);
+  launch_reals_convert(WCMG_F16, C.Yt16.p, C.Yt[0].as<double>(), (size_t)V * 8 * nn * 2, st);
   HIPCHK(hipMemcpyAsync(hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   if (hflag[0]) fail(WCMG_ERANK, "singular coarse site block");
@@ -1557,6 +1578,69 @@ void mg_build_coarse(Ctx& c, LatticeState& L, int level) {
   if (p.nlevels == 1 && p.coarsest == 1) build_dense(c, L, 0);
   if (p.nlevels == 1 && p.coarsest == 2) build_deflation(c, L, 0);
   L.mg.reset();
+}
+
+// ---------------------------------------------------------------------------
+// adaptive refinement of the null vectors (Setup section: the alphaSA idea of
+// relaxing with a cycle built from the vectors already available, and the
+// hybrid of that with inverse iteration)
+// ---------------------------------------------------------------------------
+// With the hierarchy built from the current vectors, every fine null vector v
+// is relaxed by `iters` steps of the multigrid-preconditioned GCR on the
+// homogeneous reduced system D_r y = 0 started from y = v_e: the error that
+// survives is what the present cycle resolves worst.  The odd half follows
+// from D_p v = 0 (v_o = -H_oe A_ee^-1 v_e), the vectors are orthonormalised
+// against each other (twice, in order), and P and the coarse operator are
+// rebuilt; `passes` rounds.
+void mg_refine_null_vectors(Ctx& c, LatticeState& L, int passes, int iters) {
+  require_hierarchy(L);
+  if (passes < 1 || iters < 1) fail(WCMG_EINVAL, "passes and iters must be >= 1");
+  const wcmg_mg_params& p = L.params;
+  const Geom& g = L.F.g;
+  hipStream_t st = c.st;
+  const int nvec = L.T0.nvec;
+  const size_t hb = spinor_bytes(WCMG_F64, g.Vh);
+  const size_t ne = (size_t)12 * g.Vh, nf = 2 * ne;
+  FineOp op{&c, &L.F, WCMG_F64, &c.fw[0], st};
+  void* zero = c.scratch_buf(53, hb);
+  void* z = c.scratch_buf(54, hb);
+  std::vector<double> cf(2 * nvec);
+  for (int pass = 0; pass < passes; ++pass) {
+    if (!L.mg) L.mg = std::make_shared<MGSolver>(c, L);
+    MGSolver& mg = *L.mg;
+    OpFn Dr = [&](void* o, const void* i) { op.Dr(o, i); };
+    OpFn K = [&](void* o, const void* i) { mg.precondition(o, i); };
+    GcrSpace& S64 = c.outer;
+    S64.prec = WCMG_F64;
+    S64.n = ne;
+    S64.bytes = hb;
+    blas_zero(WCMG_F64, zero, ne, st);
+    std::vector<const void*> done;
+    for (int k = 0; k < nvec; ++k) {
+      char* v = (char*)L.T0.raw.p + (size_t)k * 2 * hb;
+      gcr(c, S64, Dr, &K, v, zero, false, 0.0, 1.0, std::min(kMaxRestart, std::max(p.outer_restart, iters)), iters,
+          true);
+      mg.collect_device_stats();
+      op.clover(z, v, 0, 1);                           // A_ee^-1 v_e
+      op.hop(v + hb, z, nullptr, 1, 0, false, -1.0);   // v_o = -H_oe A_ee^-1 v_e
+      for (int rep = 0; rep < 2 && k > 0; ++rep) {
+        blas_multi_cdot(WCMG_F64, done.data(), k, v, nf, c.red.out(), st);
+        const double* d = c.red.fetch(2 * k);
+        for (int j = 0; j < 2 * k; ++j) cf[j] = -d[j];
+        blas_multi_axpy(WCMG_F64, cf.data(), done.data(), k, v, nf, st);
+      }
+      const double nv = std::sqrt(norm2(c, WCMG_F64, v, nf));
+      if (!(nv > 0.0) || !finite(nv)) fail(WCMG_ENAN, "refined null vector vanished");
+      blas_axpby(WCMG_F64, 0.0, 0.0, v, 1.0 / nv, 0.0, v, nf, st);
+      done.push_back(v);
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    L.T0.orth = false;
+    for (auto& lv : L.levels) lv->built = false;
+    L.mg.reset();
+    mg_build_coarse(c, L, 0);
+    if (p.nlevels >= 2) mg_build_coarse(c, L, 1);
+  }
 }
 
 // ---------------------------------------------------------------------------

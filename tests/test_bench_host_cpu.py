@@ -47,6 +47,10 @@ def test_algorithmic_bytes_per_site():
     assert bench.dslash_bytes_per_site(1, 0, True) == (24 + 144 + 24 + 72) * 4
     # FP16 DIAG = 2 hop: halves, plus one FP32 scale per spinor read or written
     assert bench.dslash_bytes_per_site(2, 2, False) == (24 + 144 + 24 + 24 + 72) * 2 + 4 * 3
+    # D_r per even site: 5 spinor passes, 16 links, 2 clover records; fields shared by the batch
+    assert [bench.dr_compulsory_bytes(p) for p in (0, 1, 2)] == [4416, 2208, 1104 + 20]
+    assert bench.dr_compulsory_bytes(1, 12) == 1728 / 12 + 480
+    assert bench.clover_bytes_per_site(0) == 120 * 8
     # a persistent coarse GCR step: both half hops and ten vector passes
     assert bench.coarse_step_bytes(256, 48) == 256 * (2 * 8 * 48 * 48 + 10 * 48) * 8
 

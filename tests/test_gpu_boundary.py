@@ -43,7 +43,7 @@ def multi():
     ctx.close()
 
 
-@pytest.mark.parametrize("op", ["FULL", "SCHUR", "DP"])
+@pytest.mark.parametrize("op", ["FULL", "SCHUR", "DP", "SCHUR_X"])
 @pytest.mark.parametrize("dag", [False, True])
 def test_all_lattice_apply_matches_per_lattice(multi, op, dag):
     ctx, ops = multi
@@ -103,6 +103,25 @@ def test_all_lattice_solve(multi):
             br = bs[l][r].reshape(o.shape)
             assert norm(br - o.apply_D(xr)) / norm(br) <= 1e-10, (l, r)
         off += n
+
+
+@pytest.mark.parametrize("prec,tol", [("F64", 1e-13), ("F32", 1e-5), ("F16", 5e-3)])
+def test_schur_x_matches_oracle(multi, prec, tol):
+    """SCHUR_X = D_r D_ee = D_ee - D_eo D_oo^-1 D_oe (two launches) against the
+    oracle's D_r applied to D_ee x, and its adjoint against the oracle's
+    explicit D_r^dag composed with D_ee (D_ee is Hermitian)."""
+    ctx, ops = multi
+    rng = np.random.default_rng(9)
+    for l, (dims, _) in enumerate(SPECS):
+        o = ops[l]
+        x = rng.standard_normal(o.shape) + 1j * rng.standard_normal(o.shape)
+        want = o.apply_Dr(o.apply_A(x, o.lat.even))
+        got = ctx.apply_D(canon(x, dims), w.OP_SCHUR_X, getattr(w, prec), lat=l).cpu().numpy().reshape(o.shape)
+        assert np.abs(got - want).max() <= tol * np.abs(want).max(), (l, prec)
+        assert np.abs(got[o.lat.odd]).max() == 0.0
+        wantd = o.apply_A(o.apply_Dr_dag(x), o.lat.even)
+        gotd = ctx.apply_Ddag(canon(x, dims), w.OP_SCHUR_X, getattr(w, prec), lat=l).cpu().numpy().reshape(o.shape)
+        assert np.abs(gotd - wantd).max() <= tol * np.abs(wantd).max(), (l, prec, "dag")
 
 
 @pytest.fixture(scope="module")

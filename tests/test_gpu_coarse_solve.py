@@ -3,8 +3,8 @@
 The whole red-black GCR of a coarse level (reduced source, GCR(m) with
 classical Gram-Schmidt and a true residual at the end of every cycle,
 reconstruction) runs in one launch with grid barriers.  Checked against
-the oracle's coarse stencil, built from the operator the GPU itself
-assembled (so the test pins the solve, not the coarse build):
+the oracle's coarse stencil, which the oracle builds itself (R D_p P,
+direction resolved) from the same imported null vectors:
 
 * tight tolerance: the solution equals the dense FP64 solve of the coarse
   system (small lattice) and the full coarse residual, recomputed by the
@@ -29,7 +29,7 @@ import torch
 
 import inputs
 from oracle.dirac import WilsonClover
-from oracle.multigrid import CoarseOperator
+from oracle.multigrid import CoarseOperator, Transfer, coarse_operator
 
 pytestmark = pytest.mark.gpu
 
@@ -54,8 +54,9 @@ def build(dims, block, nvec, m0=-0.2, csw=1.0, seed=11):
     v = rng.standard_normal((nvec, V, 4, 3)) + 1j * rng.standard_normal((nvec, V, 4, 3))
     ctx.set_null_vectors(canon(v, (nvec,) + tuple(reversed(dims)) + (4, 3)), level=0)
     ctx.build_coarse(0)
-    cdims = tuple(d // b for d, b in zip(dims, block))
-    cop = CoarseOperator(cdims, ctx.get_coarse(0))
+    op = WilsonClover(dims, U, m0, csw)
+    T = Transfer(op, block, v)
+    cop = CoarseOperator(T.cdims, coarse_operator(op, T))
     return ctx, cop, U
 
 
@@ -149,6 +150,29 @@ def test_one_site_kernel_matches_strided(case, prec, tol, restart):
         (1e-5 if prec == "F32" else 0.0)
 
 
+@pytest.mark.parametrize("tol,restart", [(0.2, 30), (1e-3, 20)])
+def test_fp16_hop_blocks(case, tol, restart):
+    """launch 3 / 4: the hop blocks read in FP16 (FP32 vectors and arithmetic;
+    the one-site kernel keeps the even site's blocks in LDS).  The two kernels
+    give the same bits; the solution meets the tolerance on the oracle's FP64
+    operator up to the FP16 rounding of the blocks (about 5e-4 relative); at
+    the cycle's tolerance the step count is that of FP32 blocks within 2."""
+    ctx, cop = case
+    b = rhs(cop, 8)
+    bt = torch.from_numpy(b).cuda()
+    x3, s3 = ctx.coarse_solve(bt, prec=w.F32, tol=tol, max_iter=2000, restart=restart, launch=3)
+    x4, s4 = ctx.coarse_solve(bt, prec=w.F32, tol=tol, max_iter=2000, restart=restart, launch=4)
+    x0, s0 = ctx.coarse_solve(bt, prec=w.F32, tol=tol, max_iter=2000, restart=restart, launch=0)
+    print("FP16 blocks tol %g: iters %d / %d, FP32 blocks %d" % (tol, s3["iters"], s4["iters"], s0["iters"]),
+          flush=True)
+    assert s3["status"] == "OK" and s4["status"] == "OK"
+    assert s3["iters"] == s4["iters"] and torch.equal(x3, x4)
+    br = cop.reduced_source(b)
+    assert full_res(cop, x3.cpu().numpy(), b) <= 1.01 * tol * np.linalg.norm(br) / np.linalg.norm(b) + 2e-3
+    if tol >= 0.1:
+        assert abs(s3["iters"] - s0["iters"]) <= 2
+
+
 def test_zero_source(case):
     ctx, cop = case
     bt = torch.zeros(cop.shape, dtype=torch.complex128, device="cuda")
@@ -198,6 +222,18 @@ def test_multigrid_with_persistent_coarse_solve(nlevels):
         sols[launch] = x
     assert abs(iters[0]["iters"] - iters[1]["iters"]) <= 1
     assert iters[0]["iters"] == iters[2]["iters"] and torch.equal(sols[0], sols[2])
+    # FP16 hop blocks in the persistent coarsest solve: the same answer, outer
+    # iteration count within 1 of FP32 blocks
+    ctx.set_mg_params(w.default_params(seed=5, coarse_fp16=1, **kw))
+    for l in range(nlevels):
+        ctx.set_null_vectors(vecs[l], level=l)
+        ctx.build_coarse(l)
+    x16, s16 = ctx.solve(b, w.MG_GCR, 1e-10)
+    xv = x16.cpu().numpy().reshape(op.shape)
+    bv = b.cpu().numpy().reshape(op.shape)
+    res = np.linalg.norm(bv - op.apply_D(xv)) / np.linalg.norm(bv)
+    print("FP16 coarse blocks: outer %d, res %.2e" % (s16[0]["iters"], res), flush=True)
+    assert res <= 1.0000001e-10 and abs(s16[0]["iters"] - iters[0]["iters"]) <= 1
     last = nlevels - 1
     assert abs(iters[0]["inner_iters"][last] - iters[1]["inner_iters"][last]) <= \
         0.1 * iters[1]["inner_iters"][last] + 1

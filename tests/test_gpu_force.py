@@ -173,4 +173,4 @@ def test_autograd_finite_differences_8x8x8x8():
 
 
 def test_autograd_finite_differences_16x16x16x32():
-    _fd_check("c2_16x16x16x32", 5)
+    _fd_check("c2_16x16x16x32", 20)
