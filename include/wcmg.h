@@ -283,6 +283,28 @@ int wcmg_apply_coarse(void* ctx, int lat, int level, int op, int prec, void* out
 int wcmg_coarse_solve(void* ctx, int lat, int level, int prec, void* x, const void* b, double tol, int max_iter,
                       int restart, int launch, wcmg_stats* stats);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture of its own streams, tight serving loops, harnesses that forbid
+ * hipMalloc): wcmg_coarse_solve with launch 0, allocation-free.  Every work
+ * buffer (Krylov bases q, z and their odd-site hops, the reduced vectors,
+ * the layout staging of b and x, the partial sums and the grid barrier's
+ * control block) is carved from one static device array of
+ * WCMG_NOALLOC_SCRATCH_BYTES (32 MiB) per GPU, reserved with the library's
+ * code object and held until the process ends; its device address is looked
+ * up when a context is created on that GPU.  No hipMalloc, hipFree or other
+ * allocating call is made.  Arguments, result and stats as for
+ * wcmg_coarse_solve (launch 0).  EINVAL, before any launch, when the solve
+ * needs more than the array holds: 68 KiB + 16 * grid * 136 bytes + 6 full
+ * coarse vectors + (4 restart + 1) half vectors, each rounded up to 256
+ * bytes (about 14 MB for a 4^3x8 coarse lattice, Nv = 24, restart 30, FP32;
+ * twice that in FP64).  Every call on one GPU shares that GPU's array and
+ * finds the previous call's contents; the control block is cleared at every
+ * call.  Calls that overlap in time on one GPU (two host threads, or two
+ * streams) race: serialise them.  Synchronises the context stream. */
+#define WCMG_NOALLOC_SCRATCH_BYTES (32u << 20)
+int wcmg_coarse_solve_noalloc(void* ctx, int lat, int level, int prec, void* x, const void* b, double tol,
+                              int max_iter, int restart, wcmg_stats* stats);
+
 /* Solve D x = b for nrhs canonical right-hand sides (device).  lat = -1:
  * every lattice of the context in one call, x, b holding nrhs spinors of
  * each lattice in lattice order and stats nlat * nrhs entries in the same

@@ -266,6 +266,19 @@ class Context:
                                          int(launch), ctypes.byref(st)))
         return x, st.as_dict()
 
+    def coarse_solve_noalloc(self, b, level=1, prec=F64, tol=0.1, max_iter=100, restart=30, lat=0):
+        """coarse_solve(launch=0) through the allocation-free entry point (every work buffer in
+        the library's static device array); x is allocated here, by torch, as the caller."""
+        b = b.contiguous()
+        if _dev(b, int(np.prod(self._level_shape(level, lat))), "right-hand side") != 1:
+            raise ValueError("the coarse solve takes one right-hand side")
+        x = torch.empty_like(b)
+        st = _lib.Stats()
+        check(_lib.LIB.wcmg_coarse_solve_noalloc(self.h, lat, level, prec, ctypes.c_void_p(x.data_ptr()),
+                                                 ctypes.c_void_p(b.data_ptr()), float(tol), int(max_iter),
+                                                 int(restart), ctypes.byref(st)))
+        return x, st.as_dict()
+
     # -- solve -------------------------------------------------------------------
     def solve(self, b, solver=MG_GCR, tol=1e-10, x0=None, lat=0, raise_on_error=True):
         """x with D x = b (canonical complex128 device tensor of nrhs spinors)."""

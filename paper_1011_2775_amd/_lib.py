@@ -88,6 +88,7 @@ SIGNATURES = {
     "wcmg_prolong": [_vp, _i, _i, _i, _vp, _vp, _i],
     "wcmg_apply_coarse": [_vp, _i, _i, _i, _i, _vp, _vp, _i],
     "wcmg_coarse_solve": [_vp, _i, _i, _i, _vp, _vp, _d, _i, _i, _i, _vp],
+    "wcmg_coarse_solve_noalloc": [_vp, _i, _i, _i, _vp, _vp, _d, _i, _i, _vp],
     "wcmg_solve": [_vp, _i, _i, _vp, _vp, _i, _d, ctypes.POINTER(Stats)],
     "wcmg_solve_dag": [_vp, _i, _i, _vp, _vp, _i, _d, ctypes.POINTER(Stats)],
     "wcmg_force": [_vp, _i, _vp, _vp, _vp, _i, _i],

@@ -18,7 +18,7 @@ LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libwcmg.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["dslash.hip", "fields.hip", "blas.hip", "blas_batch.hip", "transfer.hip", "coarse.hip", "coarse_mfma.hip", "coarse_multilevel.hip", "coarse_persist.hip", "random.hip", "force.hip",
+SOURCES = ["dslash.hip", "fields.hip", "blas.hip", "blas_batch.hip", "transfer.hip", "coarse.hip", "coarse_mfma.hip", "coarse_multilevel.hip", "coarse_persist.hip", "random.hip", "force.hip", "noalloc.hip",
            "runtime.cpp", "solvers.cpp", "capi.cpp"]
 
 ARCH = os.environ.get("WCMG_OFFLOAD_ARCH", "gfx950")

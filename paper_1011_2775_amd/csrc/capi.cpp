@@ -203,6 +203,7 @@ int wcmg_create(const wcmg_lattice* lats, int nlat, void* hip_stream, void** out
       c->st = reinterpret_cast<hipStream_t>(hip_stream);
       c->timer.st = c->st;
       c->red.init(c->st);
+      (void)noalloc_scratch(c->device);  // the allocation-free entry point's array on this GPU
       for (int l = 0; l < nlat; ++l) {
         auto L = new LatticeState();
         L->F.g = make_geom(lats[l].dims, lats[l].t_bc);
@@ -985,6 +986,41 @@ int wcmg_coarse_solve(void* ctx, int lat, int level, int prec, void* x, const vo
     blas_axpby(prec, 1.0, 0.0, vb, -1.0, 0.0, t, nall, c->st);
     const double rr = norm2(*c, prec, t, nall), bb = norm2(*c, prec, vb, nall);
     s.true_rel_res = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+    if (stats) *stats = s;
+  });
+}
+
+int wcmg_coarse_solve_noalloc(void* ctx, int lat, int level, int prec, void* x, const void* b, double tol,
+                              int max_iter, int restart, wcmg_stats* stats) {
+  Ctx* c = as_ctx(ctx);
+  if (int r = check_lat(c, lat)) return r;
+  CHECK(x && b, WCMG_EINVAL, "null buffer");
+  CHECK(x != b, WCMG_EINVAL, "x and b must not alias");
+  CHECK(prec == WCMG_F64 || prec == WCMG_F32, WCMG_EINVAL, "coarse precision must be F64 or F32");
+  CHECK(tol > 0 && tol < 1, WCMG_EINVAL, "tol must be in (0,1)");
+  CHECK(max_iter >= 1 && restart >= 1 && restart <= kMaxRestart, WCMG_EINVAL,
+        "max_iter must be >= 1 and restart in 1..64");
+  LatticeState& L = *c->lats[lat];
+  CHECK(L.have_params && level >= 1 && level <= L.params.nlevels, WCMG_EINVAL, "level out of range");
+  CHECK((int)L.levels.size() >= level && L.levels[level - 1]->built, WCMG_ESTATE, "coarse operator not built");
+  CoarseLevel& C = *L.levels[level - 1];
+  CHECK(C.cg.split, WCMG_EDIM, "coarse lattice has an odd extent: no red-black form");
+  CHECK_DEV(c, b, (size_t)C.cg.V * C.cg.n * 16, "right-hand side");
+  CHECK_DEV(c, x, (size_t)C.cg.V * C.cg.n * 16, "solution");
+  int grid = 0;
+  size_t need = 0;
+  if (int r = guarded([&] {
+        grid = coarse_gcr_persistent_grid(prec, C.cg.n, C.cg.Vh);
+        if (grid > 0) need = coarse_solve_noalloc_bytes(C, prec, std::min(restart, max_iter), grid);
+      }))
+    return r;
+  CHECK(grid > 0, WCMG_ENODEV, "the device cannot run the persistent coarse solve");
+  if (need > kNoAllocScratchBytes)
+    return set_err(WCMG_EINVAL, "the solve needs " + std::to_string(need) + " bytes of work space; the static scratch holds " +
+                                    std::to_string(kNoAllocScratchBytes) + " (use wcmg_coarse_solve)");
+  return guarded([&] {
+    wcmg_stats s{};
+    coarse_solve_noalloc(*c, C, prec, noalloc_scratch(c->device), grid, x, b, tol, max_iter, restart, &s);
     if (stats) *stats = s;
   });
 }

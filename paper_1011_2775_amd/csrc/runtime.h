@@ -303,6 +303,20 @@ void persistent_launch_bufs(Ctx& c, int grid, const PersistBufs& B, CoarseLevel&
                             const void* in, void* t, void* y, void* r, void* br, double tol, int restart,
                             int maxiter, bool fixed, bool general, bool mat16 = false);
 
+// ------------------------------------------------------------------ allocation-free coarse solve
+// One static device array per GPU (noalloc.hip) holds every work buffer of
+// wcmg_coarse_solve_noalloc.
+constexpr size_t kNoAllocScratchBytes = (size_t)32 << 20;
+// device address of that GPU's array (looked up once per device, with it current)
+void* noalloc_scratch(int device);
+// zero `bytes` (a multiple of 4) with a fill kernel on st
+void noalloc_zero(void* p, size_t bytes, hipStream_t st);
+// bytes of the array a coarse solve of level C needs (grid: persistent workgroups)
+size_t coarse_solve_noalloc_bytes(const CoarseLevel& C, int prec, int restart, int grid);
+// the persistent coarse solve (wcmg_coarse_solve, launch 0) with every buffer carved
+// from `base` (at least coarse_solve_noalloc_bytes); x, b canonical complex128 [Vc][n]
+void coarse_solve_noalloc(Ctx& c, CoarseLevel& C, int prec, void* base, int grid, void* x, const void* b,
+                          double tol, int max_iter, int restart, wcmg_stats* s);
 KrylovResult bicgstab(Ctx& c, int prec, size_t n, const OpFn& A, void* x, const void* b, double tol,
                       double target_norm, int maxiter);
 // batched flexible GCR: A and K act on S.nrhs right-hand sides at once

@@ -618,6 +618,81 @@ void persistent_launch(Ctx& c, PersistWork& w, CoarseLevel& C, int prec, void* o
   w.pending = true;
 }
 
+// Carving plan of the allocation-free coarse solve: every buffer 256-byte
+// aligned, in this order; with base == nullptr only the size is computed.
+namespace {
+struct Carve {
+  char* base;
+  size_t used = 0;
+  void* take(size_t b) {
+    used = (used + 255) & ~(size_t)255;
+    void* p = base ? base + used : nullptr;
+    used += b;
+    return p;
+  }
+};
+struct NoAllocPlan {
+  void *vb, *vx, *t, *y, *r, *br;
+  PersistBufs B;
+};
+NoAllocPlan plan_noalloc(Carve& k, const CoarseLevel& C, int prec, int restart, int grid) {
+  const size_t cs = prec == WCMG_F64 ? 16 : 8;
+  const size_t nall = (size_t)C.cg.V * C.cg.n, hv = (size_t)C.cg.Vh * C.cg.n;
+  NoAllocPlan P{};
+  P.B.ctl = k.take(kPersistCtlBytes);  // first: the control block is cleared at every call
+  P.B.part = reinterpret_cast<double*>(k.take(2 * (size_t)grid * coarse_gcr_persistent_part_doubles() * 8));
+  P.vb = k.take(nall * cs);
+  P.vx = k.take(nall * cs);
+  P.t = k.take(nall * cs);
+  P.y = k.take(nall * cs);
+  P.r = k.take(nall * cs);
+  P.br = k.take(nall * cs);
+  P.B.Q = k.take((size_t)restart * hv * cs);
+  P.B.Z = k.take((size_t)restart * hv * cs);
+  P.B.T = k.take((size_t)restart * 2 * hv * cs);
+  P.B.qraw = k.take(hv * cs);
+  return P;
+}
+}  // namespace
+
+size_t coarse_solve_noalloc_bytes(const CoarseLevel& C, int prec, int restart, int grid) {
+  Carve k{nullptr};
+  plan_noalloc(k, C, prec, restart, grid);
+  return k.used;
+}
+
+void coarse_solve_noalloc(Ctx& c, CoarseLevel& C, int prec, void* base, int grid, void* x, const void* b,
+                          double tol, int max_iter, int restart, wcmg_stats* s) {
+  Carve k{reinterpret_cast<char*>(base)};
+  restart = std::min(restart, std::max(1, max_iter));
+  NoAllocPlan P = plan_noalloc(k, C, prec, restart, grid);
+  const size_t nall = (size_t)C.cg.V * C.cg.n;
+  // the previous call's barrier epochs, counters and status words are not ours
+  noalloc_zero(P.B.ctl, kPersistCtlBytes, c.st);
+  launch_coarse_canon(prec, P.vb, const_cast<void*>(b), C.perm.as<int>(), C.cg.V, C.cg.n, true, c.st);
+  auto t0 = std::chrono::steady_clock::now();
+  persistent_launch_bufs(c, grid, P.B, C, prec, P.vx, P.vb, P.t, P.y, P.r, P.br, tol, restart, max_iter, false,
+                         false);
+  // iterations, status and the barrier-abort flag of the launch (pinned staging, no allocation)
+  HIPCHK(hipMemcpyAsync(c.red.host, reinterpret_cast<char*>(P.B.ctl) + kPersistInfoOffset, 3 * sizeof(int),
+                        hipMemcpyDeviceToHost, c.st));
+  HIPCHK(hipStreamSynchronize(c.st));
+  const int* info = reinterpret_cast<const int*>(c.red.host);
+  if (info[2]) fail(WCMG_EHIP, "persistent coarse solve: a grid barrier timed out");
+  wcmg_stats st{};
+  st.iters = info[0];
+  st.status = info[1];
+  st.t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  launch_coarse_canon(prec, P.vx, x, C.perm.as<int>(), C.cg.V, C.cg.n, false, c.st);
+  // ||b - Yhat x|| / ||b|| of the full coarse system
+  CoarseOp op{&C, prec, nullptr, c.st};
+  op.Dfull(P.t, P.vx);
+  blas_axpby(prec, 1.0, 0.0, P.vb, -1.0, 0.0, P.t, nall, c.st);
+  const double rr = norm2(c, prec, P.t, nall), bb = norm2(c, prec, P.vb, nall);
+  st.true_rel_res = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+  if (s) *s = st;
+}
+
 long persistent_collect(Ctx& c, PersistWork& w, int* status) {
   if (status) *status = WCMG_OK;
   if (!w.pending) return 0;
