@@ -186,6 +186,20 @@ int wcmg_set_gauge(void* ctx, int lat, const void* U, int on_device);
  * with ECLOVER_NOT_PD if a block is not positive definite. */
 int wcmg_set_clover(void* ctx, int lat, double m0, double csw, const void* A, int on_device);
 
+/* Anisotropic Wilson-clover (the Results section's lattices have a finer
+ * temporal than spatial spacing): every spatial hop of Eq.(1) carries the
+ * coefficient hop_s (the bare speed of light over the bare anisotropy, > 0;
+ * temporal hops keep 1), the site-diagonal constant becomes
+ * m0 + 1 + 3 hop_s (4 + m0 when hop_s = 1), and the clover term weights the
+ * spatial planes with csw_s and the planes containing time with csw_t:
+ *   D = (m0 + 1 + 3 hop_s) - 1/2 sum_mu c_mu [hops of Eq.(1)]
+ *     + (i/4) sum_{mu != nu} c_munu sigma_mu_nu Fhat_mu_nu,
+ * c_mu = hop_s (mu spatial), 1 (t); c_munu = csw_s (both spatial), csw_t.
+ * Computed from the gauge field; every operator, solver, the multigrid setup
+ * and the force of this lattice use it from then on (wcmg_set_clover goes
+ * back to the isotropic form).  Errors as wcmg_set_clover. */
+int wcmg_set_clover_aniso(void* ctx, int lat, double m0, double hop_s, double csw_s, double csw_t);
+
 /* Fix the multigrid shape (blocks, Nv, tolerances) for a lattice. EDIM if
  * a block does not divide its level, Nv exceeds the block's degrees of
  * freedom per chirality, or (coarsest = 1) the coarsest dimension exceeds

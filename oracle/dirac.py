@@ -18,6 +18,12 @@ D_r = 1 - D_eo D_oo^-1 D_oe D_ee^-1, the reduced source of Eq.(4)
 b_r = b_e - D_eo D_oo^-1 b_o, and the reconstruction x_e = D_ee^-1 y_e,
 x_o = D_oo^-1 (b_o - D_oe x_e).
 
+Anisotropic lattices (the Results section's lattices have a finer temporal
+spacing; the paper gives no formula, this is the reading used): the spatial
+hops carry a coefficient hop_s, the site-diagonal constant is
+m0 + 1 + 3 hop_s, and the clover planes are weighted csw_s (spatial) and
+csw_t (with time); hop_s = 1 and csw_s = csw_t give the operator above.
+
 Fields are flat arrays: gauge U[V][4][3][3], spinors psi[V][4][3] (complex128).
 Half-lattice (single parity) fields are stored as full-lattice arrays that
 are zero on the other parity; every function below works that way.
@@ -37,13 +43,16 @@ def dag(M):
 # hopping term
 # ----------------------------------------------------------------------------
 
-def hop_dir(lat, U, psi, d, sites):
+def hop_dir(lat, U, psi, d, sites, hop_s=1.0):
     """Contribution of hop direction d to (H psi) at `sites`.
 
-    d = 2*mu is the forward hop  -1/2 (1-gamma_mu) U_mu(x) psi(x+mu),
-    d = 2*mu+1 the backward hop  -1/2 (1+gamma_mu) U_mu(x-mu)^dag psi(x-mu).
+    d = 2*mu is the forward hop  -1/2 c_mu (1-gamma_mu) U_mu(x) psi(x+mu),
+    d = 2*mu+1 the backward hop  -1/2 c_mu (1+gamma_mu) U_mu(x-mu)^dag psi(x-mu),
+    c_mu = hop_s for the spatial directions and 1 for time.
     """
     mu, back = divmod(d, 2)
+    if mu < 3 and hop_s != 1.0:
+        return hop_s * hop_dir(lat, U, psi, d, sites)
     if not back:
         nb = lat.fwd[mu][sites]
         ph = lat.fwd_phase[mu][sites]
@@ -57,13 +66,13 @@ def hop_dir(lat, U, psi, d, sites):
     return -0.5 * np.einsum("st,nta->nsa", I4 + GAMMA[mu], t)
 
 
-def hop(lat, U, psi, sites=None):
+def hop(lat, U, psi, sites=None, hop_s=1.0):
     """(H psi)(x) for x in `sites` (all sites if None); returns [len(sites)][4][3]."""
     if sites is None:
         sites = np.arange(lat.V)
     out = np.zeros((len(sites), 4, 3), dtype=np.complex128)
     for d in range(8):
-        out += hop_dir(lat, U, psi, d, sites)
+        out += hop_dir(lat, U, psi, d, sites, hop_s)
     return out
 
 
@@ -107,10 +116,23 @@ def field_strength(lat, U, mu, nu, sites):
     return (Q - dag(Q)) / 8.0
 
 
-def clover_term(lat, U, csw, sites=None):
-    """csw * (i/4) sum_{mu != nu} sigma_mu_nu (x) Fhat_mu_nu, as [n][12][12]."""
+def clover_term(lat, U, csw, sites=None, csw_t=None):
+    """(i/4) sum_{mu != nu} c_mu_nu sigma_mu_nu (x) Fhat_mu_nu, as [n][12][12],
+    c_mu_nu = csw on spatial planes and csw_t (default csw) on planes with time."""
     if sites is None:
         sites = np.arange(lat.V)
+    csw_t = csw if csw_t is None else csw_t
+    if csw_t != csw:
+        space = [(m, n) for m in range(3) for n in range(3) if m != n]
+        C = np.zeros((len(sites), 12, 12), dtype=np.complex128)
+        for mu in range(4):
+            for nu in range(4):
+                if mu == nu:
+                    continue
+                F = field_strength(lat, U, mu, nu, sites)
+                w = csw if (mu, nu) in space else csw_t
+                C += w * np.einsum("st,nab->nsatb", sigma_munu(mu, nu), F).reshape(len(sites), 12, 12)
+        return 0.25j * C
     C = np.zeros((len(sites), 12, 12), dtype=np.complex128)
     for mu in range(4):
         for nu in range(4):
@@ -123,10 +145,11 @@ def clover_term(lat, U, csw, sites=None):
     return csw * 0.25j * C
 
 
-def site_matrix(lat, U, m0, csw, sites=None):
-    """A(x) = (4+m0) 1 + clover term, per site [n][12][12]."""
-    C = clover_term(lat, U, csw, sites)
-    return C + (4.0 + m0) * np.eye(12)[None]
+def site_matrix(lat, U, m0, csw, sites=None, hop_s=1.0, csw_t=None):
+    """A(x) = (m0 + 1 + 3 hop_s) 1 + clover term (4 + m0 when isotropic), per site [n][12][12]."""
+    C = clover_term(lat, U, csw, sites, csw_t)
+    diag = 4.0 + m0 if hop_s == 1.0 else m0 + 1.0 + 3.0 * hop_s
+    return C + diag * np.eye(12)[None]
 
 
 # ----------------------------------------------------------------------------
@@ -136,13 +159,16 @@ def site_matrix(lat, U, m0, csw, sites=None):
 class WilsonClover:
     """D = A + H on a lattice, with the red-black pieces of Eqs.(2)-(4)."""
 
-    def __init__(self, dims, U, m0, csw, t_bc=-1, A=None):
+    def __init__(self, dims, U, m0, csw, t_bc=-1, A=None, hop_s=1.0, csw_t=None):
         self.lat = Lattice(dims, t_bc)
         V = self.lat.V
         self.U = np.ascontiguousarray(np.asarray(U).reshape(V, 4, 3, 3))
         self.m0 = float(m0)
         self.csw = float(csw)
-        self.A = site_matrix(self.lat, self.U, m0, csw) if A is None else A
+        self.csw_t = self.csw if csw_t is None else float(csw_t)
+        self.hop_s = float(hop_s)
+        self.A = (site_matrix(self.lat, self.U, m0, csw, hop_s=self.hop_s, csw_t=self.csw_t) if A is None
+                  else A)
         self.Ainv = np.linalg.inv(self.A)
         self.shape = (V, 4, 3)
         self.ncomp = 12
@@ -171,14 +197,14 @@ class WilsonClover:
         v = self.vec(v)
         out = np.zeros(self.shape, dtype=np.complex128)
         s = np.arange(self.lat.V) if sites is None else sites
-        out[s] = hop(self.lat, self.U, v, s)
+        out[s] = hop(self.lat, self.U, v, s, self.hop_s)
         return out
 
     def apply_H_dir(self, v, d, sites=None):
         v = self.vec(v)
         out = np.zeros(self.shape, dtype=np.complex128)
         s = np.arange(self.lat.V) if sites is None else sites
-        out[s] = hop_dir(self.lat, self.U, v, d, s)
+        out[s] = hop_dir(self.lat, self.U, v, d, s, self.hop_s)
         return out
 
     def nbr(self, d):
@@ -201,13 +227,14 @@ class WilsonClover:
         out = np.einsum("nji,nj->ni", np.conj(self.A), v.reshape(-1, 12)).reshape(self.shape)
         acc = np.zeros(self.shape, dtype=np.complex128)
         for mu in range(4):
-            # adjoint of the forward hop: -1/2 (1-gamma)^dag U_mu(x-mu)^dag psi(x-mu)
+            c = self.hop_s if mu < 3 else 1.0
+            # adjoint of the forward hop: -1/2 c_mu (1-gamma)^dag U_mu(x-mu)^dag psi(x-mu)
             nb = lat.bwd[mu]
             t = np.einsum("nba,nsb->nsa", np.conj(self.U[nb, mu]), v[nb]) * lat.bwd_phase[mu][:, None, None]
-            acc += np.einsum("st,nta->nsa", dag(I4 - GAMMA[mu]), t)
+            acc += c * np.einsum("st,nta->nsa", dag(I4 - GAMMA[mu]), t)
             nb = lat.fwd[mu]
             t = np.einsum("nab,nsb->nsa", self.U[:, mu], v[nb]) * lat.fwd_phase[mu][:, None, None]
-            acc += np.einsum("st,nta->nsa", dag(I4 + GAMMA[mu]), t)
+            acc += c * np.einsum("st,nta->nsa", dag(I4 + GAMMA[mu]), t)
         return out - 0.5 * acc
 
     def apply_Dp(self, v):

@@ -60,7 +60,8 @@ def hop_force(op, x, lam):
         phi = np.einsum("st,nta->nsa", I4 + GAMMA[mu], x)
         m1 = np.einsum("nsa,nsb->nab", lam, np.conj(chi))
         m2 = np.einsum("nsa,nsb->nab", phi, np.conj(lam[nb]))
-        G[:, mu] = 0.5 * (m1 + m2) * lat.fwd_phase[mu][:, None, None]
+        c = op.hop_s if mu < 3 else 1.0  # spatial hop coefficient of anisotropic lattices
+        G[:, mu] = 0.5 * c * (m1 + m2) * lat.fwd_phase[mu][:, None, None]
     return G
 
 
@@ -96,7 +97,8 @@ def clover_force(op, x, lam):
                 continue
             s = sigma_munu(mu, nu)
             xi = np.einsum("st,ntb,nsa->nba", s, x, np.conj(lam))
-            W = -op.csw * 0.25j * xi
+            w = op.csw if (mu < 3 and nu < 3) else op.csw_t  # plane weight (anisotropic lattices)
+            W = -w * 0.25j * xi
             Z = (W - dag(W)) / 8.0
             for leaf in _leaves(lat, mu, nu):
                 mats = [dag(U[st, d]) if adj else U[st, d] for st, d, adj in leaf]
@@ -116,7 +118,7 @@ def clover_force(op, x, lam):
 def force(op, x, lam, include_clover=True):
     """grad_U = hop part (+ clover part when the clover is computed from U)."""
     G = hop_force(op, x, lam)
-    if include_clover and op.csw != 0.0:
+    if include_clover and (op.csw != 0.0 or op.csw_t != 0.0):
         G = G + clover_force(op, x, lam)
     return G
 

@@ -155,6 +155,11 @@ class Context:
             check(_lib.LIB.wcmg_set_clover(self.h, lat, float(m0), float(csw), p, dev))
             del keep
 
+    def set_clover_aniso(self, m0, hop_s, csw_s, csw_t, lat=0):
+        """Anisotropic Wilson-clover: spatial hops weighted by hop_s, diagonal m0 + 1 + 3 hop_s,
+        clover planes weighted csw_s (spatial) and csw_t (with time)."""
+        check(_lib.LIB.wcmg_set_clover_aniso(self.h, lat, float(m0), float(hop_s), float(csw_s), float(csw_t)))
+
     # -- multigrid -----------------------------------------------------------
     def set_mg_params(self, params, lat=0):
         self.params[lat] = params

@@ -74,6 +74,7 @@ SIGNATURES = {
     "wcmg_destroy": [_vp],
     "wcmg_set_gauge": [_vp, _i, _vp, _i],
     "wcmg_set_clover": [_vp, _i, _d, _d, _vp, _i],
+    "wcmg_set_clover_aniso": [_vp, _i, _d, _d, _d, _d],
     "wcmg_set_mg_params": [_vp, _i, ctypes.POINTER(MGParams)],
     "wcmg_build_null_vectors": [_vp, _i, _i],
     "wcmg_set_null_vectors": [_vp, _i, _i, _vp, _i, _i],

@@ -54,7 +54,8 @@ const void* to_device(Ctx& c, int slot, const void* src, size_t bytes, int on_de
   return d;
 }
 
-CloverCoef clover_coef(double csw) {
+// per plane: csw_s on the spatial planes, csw_t on the planes with time
+CloverCoef clover_coef(double csw_s, double csw_t) {
   // chiral gamma basis: gamma_k = [[0,-i s_k],[i s_k,0]], gamma_4 = [[0,1],[1,0]]
   typedef double cd[2];
   auto cm = [](const cd a, const cd b, cd o) {
@@ -84,6 +85,7 @@ CloverCoef clover_coef(double csw) {
   int plane = 0;
   for (int mu = 0; mu < 4; ++mu)
     for (int nu = mu + 1; nu < 4; ++nu, ++plane) {
+      const double csw = nu == 3 ? csw_t : csw_s;
       // sigma = (i/2)(g_mu g_nu - g_nu g_mu); coefficient csw (i/2) -> -csw/4 (g g - g g)
       double C[4][4][2];
       for (int i = 0; i < 4; ++i)
@@ -246,10 +248,14 @@ int wcmg_set_gauge(void* ctx, int lat, const void* U, int on_device) {
   });
 }
 
-int wcmg_set_clover(void* ctx, int lat, double m0, double csw, const void* A, int on_device) {
+static int set_clover_impl(void* ctx, int lat, double m0, double hop_s, double csw, double csw_t, const void* A,
+                           int on_device) {
   Ctx* c = as_ctx(ctx);
   if (int r = check_lat(c, lat)) return r;
-  CHECK(std::isfinite(m0) && std::isfinite(csw), WCMG_EINVAL, "m0 and csw must be finite");
+  CHECK(std::isfinite(m0) && std::isfinite(csw) && std::isfinite(csw_t), WCMG_EINVAL,
+        "m0 and the clover coefficients must be finite");
+  CHECK(std::isfinite(hop_s) && hop_s > 0.0, WCMG_EINVAL, "the spatial hop coefficient must be positive");
+  CHECK(!A || hop_s == 1.0, WCMG_EINVAL, "a caller-supplied clover matrix goes with isotropic hops");
   LatticeState& L = *c->lats[lat];
   CHECK(A || L.F.have_gauge, WCMG_ESTATE, "gauge field not set");
   if (A && on_device) CHECK_DEV(c, A, (size_t)L.F.g.V * 144 * 16, "clover matrix");
@@ -263,7 +269,9 @@ int wcmg_set_clover(void* ctx, int lat, double m0, double csw, const void* A, in
       const void* src = to_device(*c, 40, A, (size_t)g.V * 144 * 16, on_device);
       clover_from_matrix(c64.p, src, g, flag, c->st);
     } else {
-      clover_compute(c64.p, L.F.gauge[WCMG_F64].p, g, m0, clover_coef(csw), flag, c->st);
+      Geom ga = L.F.g;
+      ga.hs = hop_s;
+      clover_compute(c64.p, L.F.gauge[WCMG_F64].p, ga, m0, clover_coef(csw, csw_t), flag, c->st);
     }
     int hf = 0;
     HIPCHK(hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, c->st));
@@ -276,14 +284,24 @@ int wcmg_set_clover(void* ctx, int lat, double m0, double csw, const void* A, in
       clover_relayout(p, L.F.clov[p].p, L.F.clov[WCMG_F64].as<double>(), g.Vh, c->st);
     }
     HIPCHK(hipStreamSynchronize(c->st));
+    L.F.g.hs = A ? 1.0 : hop_s;  // the spatial hops of every kernel on this lattice from now on
     L.F.m0 = m0;
     L.F.csw = csw;
+    L.F.csw_t = csw_t;
     L.F.clover_from_u = (A == nullptr);
     L.F.have_clover = true;
     L.mg.reset();  // the preconditioner (and any captured graph) holds the old clover
     for (auto& lv : L.levels) lv->built = false;
     L.mg.reset();
   });
+}
+
+int wcmg_set_clover(void* ctx, int lat, double m0, double csw, const void* A, int on_device) {
+  return set_clover_impl(ctx, lat, m0, 1.0, csw, csw, A, on_device);
+}
+
+int wcmg_set_clover_aniso(void* ctx, int lat, double m0, double hop_s, double csw_s, double csw_t) {
+  return set_clover_impl(ctx, lat, m0, hop_s, csw_s, csw_t, nullptr, 1);
 }
 
 int wcmg_set_mg_params(void* ctx, int lat, const wcmg_mg_params* p) {
@@ -1173,8 +1191,8 @@ int wcmg_force(void* ctx, int lat, void* dU, const void* psi, const void* lam, i
   CHECK_DEV(c, dU, (size_t)L.F.g.V * 4 * 9 * 16, "gauge gradient");
   return guarded([&] {
     const Geom& g = L.F.g;
-    const bool clov = include_clover && L.F.csw != 0.0;
-    const CloverCoef cc = clover_coef(L.F.csw);
+    const bool clov = include_clover && (L.F.csw != 0.0 || L.F.csw_t != 0.0);
+    const CloverCoef cc = clover_coef(L.F.csw, L.F.csw_t);
     void* z = clov ? c->scratch_buf(52, (size_t)g.V * 54 * 16) : nullptr;
     force_compute(dU, psi, lam, nrhs, L.F.gauge[WCMG_F64].p, g, clov ? &cc : nullptr, z, c->st);
   });

@@ -77,6 +77,11 @@ __device__ __forceinline__ void hop_mu(const DslashArgs& a, int p, int i, const 
 #pragma unroll
           for (int k = 0; k < 6; ++k) hu[k] = ph * hu[k];
         }
+        if (MU < 3 && g.hs != 1.0) {  // spatial hop coefficient (anisotropic lattices only)
+          const C hs = (C)g.hs;
+#pragma unroll
+          for (int k = 0; k < 6; ++k) hu[k] = hs * hu[k];
+        }
         accumulate<C, MU, false>(acc[r], hu);
         pin_acc(acc[r]);
       }
@@ -99,6 +104,11 @@ __device__ __forceinline__ void hop_mu(const DslashArgs& a, int p, int i, const 
           const C ph = (C)g.t_bc;
 #pragma unroll
           for (int k = 0; k < 6; ++k) hu[k] = ph * hu[k];
+        }
+        if (MU < 3 && g.hs != 1.0) {
+          const C hs = (C)g.hs;
+#pragma unroll
+          for (int k = 0; k < 6; ++k) hu[k] = hs * hu[k];
         }
         accumulate<C, MU, true>(acc[r], hu);
         pin_acc(acc[r]);
@@ -441,7 +451,9 @@ static void launch_dslash_rhs(int diag, bool postinv, DslashArgs a, hipStream_t 
   a.nblocks = (a.g.Vh + threads - 1) / threads;
   if ((long)a.nblocks * a.nrhs > (1L << 30)) fail(WCMG_EINVAL, "too many workgroups");
   const dim3 grid(xcd_grid(a.nblocks * a.nrhs));
-  const bool stream = a.stream >= 0 ? a.stream != 0 : (double)a.g.Vh * 432.0 * sizeof(G) > 192.0e6;
+  // the right-hand sides of a site block reuse its links and clover records
+  // from L2, so the fields are not streamed past the caches unless asked for
+  const bool stream = a.stream > 0;
 #define WCMG_DR(D, P)                                                                                 \
   do {                                                                                              \
     if (stream)                                                                                     \

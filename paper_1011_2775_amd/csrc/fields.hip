@@ -411,7 +411,8 @@ void spinor_chiral_project(int prec, void* dst, const void* src, int Vh, int chi
 void clover_compute(void* clov64, const void* gauge64, const Geom& g, double m0, const CloverCoef& cc, int* flag,
                     hipStream_t st) {
   hipLaunchKernelGGL(k_clover, grid_for(g.V, 128), dim3(128), 0, st, reinterpret_cast<double*>(clov64),
-                     reinterpret_cast<const double2*>(gauge64), dgeom(g), g.V, 4.0 + m0, cc, flag);
+                     reinterpret_cast<const double2*>(gauge64), dgeom(g), g.V,
+                     g.hs == 1.0 ? 4.0 + m0 : m0 + 1.0 + 3.0 * g.hs, cc, flag);
   HIPCHK(hipGetLastError());
 }
 

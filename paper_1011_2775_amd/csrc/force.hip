@@ -89,12 +89,13 @@ __global__ void __launch_bounds__(kT) k_hop_force(double2* G, const double2* x, 
   int c[4], n[4];
   coords_of(g.L, y, c);
   const double pht = (c[3] == g.L[3] - 1) ? g.t_bc : 1.0;
+  // spatial hops carry the coefficient g.hs (1 on isotropic lattices)
   shift(g.L, c, 0, 1, n);
-  hop_force_mu<0>(x, lam, nrhs, V, y, lex_of(g.L, n), 1.0, G);
+  hop_force_mu<0>(x, lam, nrhs, V, y, lex_of(g.L, n), g.hs, G);
   shift(g.L, c, 1, 1, n);
-  hop_force_mu<1>(x, lam, nrhs, V, y, lex_of(g.L, n), 1.0, G);
+  hop_force_mu<1>(x, lam, nrhs, V, y, lex_of(g.L, n), g.hs, G);
   shift(g.L, c, 2, 1, n);
-  hop_force_mu<2>(x, lam, nrhs, V, y, lex_of(g.L, n), 1.0, G);
+  hop_force_mu<2>(x, lam, nrhs, V, y, lex_of(g.L, n), g.hs, G);
   shift(g.L, c, 3, 1, n);
   hop_force_mu<3>(x, lam, nrhs, V, y, lex_of(g.L, n), pht, G);
 }

@@ -72,7 +72,7 @@ struct FineFields {
   Geom g;
   bool have_gauge = false, have_clover = false;
   bool clover_from_u = false;  // clover computed from the gauge field (not a caller matrix)
-  double m0 = 0.0, csw = 0.0;
+  double m0 = 0.0, csw = 0.0, csw_t = 0.0;  // csw: spatial planes (all planes when isotropic)
   DBuf gauge[3];   // per precision
   DBuf clov[3];    // per precision, packed A and A^-1
 };

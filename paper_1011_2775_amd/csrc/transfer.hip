@@ -335,6 +335,8 @@ __device__ __forceinline__ void split_mu(const SplitArgs& a, int p, int i, const
       link_mul<double, false>(U, h, hu);
       if (MU == 3 && c[3] == g.L[3] - 1)
         for (int k = 0; k < 6; ++k) hu[k] = g.t_bc * hu[k];
+      if (MU < 3)
+        for (int k = 0; k < 6; ++k) hu[k] = g.hs * hu[k];
       accumulate<double, MU, false>(hd, hu);
       cross = coarse_extent && (c[MU] % a.bg.b[MU] == a.bg.b[MU] - 1);
     } else {
@@ -346,6 +348,8 @@ __device__ __forceinline__ void split_mu(const SplitArgs& a, int p, int i, const
       link_mul<double, true>(U, h, hu);
       if (MU == 3 && c[3] == 0)
         for (int k = 0; k < 6; ++k) hu[k] = g.t_bc * hu[k];
+      if (MU < 3)
+        for (int k = 0; k < 6; ++k) hu[k] = g.hs * hu[k];
       accumulate<double, MU, true>(hd, hu);
       cross = coarse_extent && (c[MU] % a.bg.b[MU] == 0);
     }

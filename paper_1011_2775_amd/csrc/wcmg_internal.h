@@ -55,6 +55,7 @@ struct Geom {
   int Vh;       // sites per parity
   int Lxh;      // Lx / 2
   double t_bc;  // fermion phase on hops that wrap around t (fine level)
+  double hs = 1.0;  // coefficient of the spatial hops (anisotropic lattices; 1: isotropic)
 };
 
 Geom make_geom(const int dims[4], int t_bc);
@@ -378,6 +379,7 @@ struct DGeom {
   int Lxh;
   int Vh;
   double t_bc;
+  double hs;  // spatial hop coefficient
 };
 
 inline DGeom dgeom(const Geom& g) {
@@ -386,6 +388,7 @@ inline DGeom dgeom(const Geom& g) {
   d.Lxh = g.Lxh;
   d.Vh = g.Vh;
   d.t_bc = g.t_bc;
+  d.hs = g.hs;
   return d;
 }
 

