@@ -31,8 +31,7 @@
 // removes what rounding these recurrences add.
 //
 // The grid barrier is a flag barrier: every workgroup stores the barrier's
-// epoch to a cache line of its own, workgroup 0 waits for all of them and
-// then stores the epoch to the generation word that the others wait for, so
+// epoch to a cache line of its own and waits until every line holds it, so
 // no address takes more than one write per barrier.  Every wait is bounded;
 // past the bound it raises an abort flag that every waiting workgroup also
 // polls, so all workgroups leave the kernel and the host reports the failure.
@@ -121,39 +120,33 @@ __device__ __forceinline__ void std_(V2* p, size_t i, cpx<double> c) {
   stc(p + i, v);
 }
 
-// Flag barrier over ctl: generation word ctl[0], arrival flag of workgroup w
-// at ctl[32 (w + 1)] (one 128-byte line each).  Epochs increase by one per
-// barrier from the generation found at kernel start.  Returns false when a
-// wait timed out or another workgroup aborted.
-__device__ bool grid_barrier(unsigned* ctl, int* abort_flag, unsigned epoch) {
-  __shared__ int ok_s;
+// Flag barrier over ctl: arrival flag of workgroup w at ctl[32 (w + 1)] (one
+// 128-byte line each), generation word ctl[0].  Epochs increase by one per
+// barrier from the generation found at kernel start.  Split in two: arrival
+// (the workgroup's coherent stores complete, then its flag) and completion
+// (every workgroup waits for every flag itself: one round trip once all have
+// arrived, where a leader that collects the flags and releases the others
+// would add a second, and would start collecting only when it is itself done
+// with the work placed between arrival and completion), so that work that
+// needs only some workgroups' arrival can run in between.  Workgroup 0 keeps
+// the generation word at the latest epoch for the next launch.  Completion
+// returns false when a wait timed out or another workgroup aborted.
+__device__ void barrier_arrive(unsigned* ctl, unsigned epoch) {
   // every wave: its coherent stores have completed (the memory clobber keeps
   // the compiler from moving memory accesses across the wait)
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
-  if (threadIdx.x == 0) {
-    ok_s = 1;
-    __hip_atomic_store(ctl + 32 * (blockIdx.x + 1), epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  if (blockIdx.x == 0) {
-    __syncthreads();
-    for (int q = threadIdx.x; q < (int)gridDim.x; q += blockDim.x) {
-      unsigned spins = 0;
-      while (__hip_atomic_load(ctl + 32 * (q + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
-        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || ++spins > kSpinLimit) {
-          __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          ok_s = 0;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0 && ok_s) __hip_atomic_store(ctl, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  if (threadIdx.x == 0 && ok_s) {
+  if (threadIdx.x == 0) __hip_atomic_store(ctl + 32 * (blockIdx.x + 1), epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ bool barrier_complete(unsigned* ctl, int* abort_flag, unsigned epoch) {
+  __shared__ int ok_s;
+  if (threadIdx.x == 0) ok_s = 1;
+  __syncthreads();
+  for (int q = threadIdx.x; q < (int)gridDim.x; q += blockDim.x) {
     unsigned spins = 0;
-    while (__hip_atomic_load(ctl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+    // flags only grow; a workgroup may already have arrived at a later barrier
+    while ((int)(__hip_atomic_load(ctl + 32 * (q + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - epoch) < 0) {
       if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || ++spins > kSpinLimit) {
         __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         ok_s = 0;
@@ -163,7 +156,36 @@ __device__ bool grid_barrier(unsigned* ctl, int* abort_flag, unsigned epoch) {
     }
   }
   __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x == 0 && ok_s)
+    __hip_atomic_store(ctl, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return ok_s != 0;
+}
+
+__device__ bool grid_barrier(unsigned* ctl, int* abort_flag, unsigned epoch) {
+  barrier_arrive(ctl, epoch);
+  return barrier_complete(ctl, abort_flag, epoch);
+}
+
+// Wait until workgroup own (a distinct one per thread, -1 for none) has
+// arrived at barrier `epoch` of ctl (its stores before the arrival are then
+// visible to coherent loads).  false on time-out or abort.
+__device__ bool arrival_wait(const unsigned* ctl, int* abort_flag, int own, unsigned epoch) {
+  __shared__ int oka;
+  if (threadIdx.x == 0) oka = 1;
+  __syncthreads();
+  if (own >= 0) {
+    unsigned spins = 0;
+    while ((int)(__hip_atomic_load(ctl + 32 * (own + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - epoch) < 0) {
+      if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || ++spins > kSpinLimit) {
+        __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        oka = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  __syncthreads();
+  return oka != 0;
 }
 
 // complex product evaluated under this file's no-contraction rule (the
@@ -937,7 +959,7 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
   const size_t eo = (size_t)w * n, oo = (size_t)(Vh + w) * n;  // owned even / odd elements
   int* abort_flag = a.info + 2;
   // neighbours of the owned sites; owners of the odd neighbours of the even site
-  int nbE = 0, nbO = 0, nbw = -1;
+  int nbE = 0, nbO = 0, nbw = -1, nbq = -1;
   if (tid < 8 * n) {
     nbE = a.nbr[(size_t)w * 8 + tid / n];
     nbO = a.nbr[(size_t)(Vh + w) * 8 + tid / n];
@@ -946,6 +968,10 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
     nbw = a.nbr[(size_t)w * 8 + tid] - Vh;
     for (int d = 0; d < tid; ++d)  // wait once per distinct owner
       if (a.nbr[(size_t)w * 8 + d] - Vh == nbw) nbw = -1;
+    // owners of the odd site's even neighbours (whose q the odd hop reads)
+    nbq = a.nbr[(size_t)(Vh + w) * 8 + tid];
+    for (int d = 0; d < tid; ++d)
+      if (a.nbr[(size_t)(Vh + w) * 8 + d] == nbq) nbq = -1;
   }
   // the even site's hop blocks, resident in LDS for the whole solve when they fit
   const MT* Mres = nullptr;
@@ -1034,7 +1060,17 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
         else
           block_partial<4>(v, mine() + 2 * k, sh);
       }
-      if (!sync_sum(2 * k + 4)) return;
+      // arrive at the step's barrier, then build the odd site's raw hop
+      // T_k = Ytilde_oe q while the rest of the grid arrives: it needs only the
+      // owners of the odd site's even neighbours (q is overwritten no earlier
+      // than their next step, which waits for this workgroup's t), and is
+      // unused when the step ends the cycle
+      barrier_arrive(a.bar, ++epoch);
+      if (!arrival_wait(a.bar, abort_flag, nbq, epoch)) return;
+      hop1<S, MT>(a, Vh + w, nbO, qraw, nullptr, nullptr, 1.0, nullptr, nullptr, Ts + (size_t)k * n, vin, hp, pre);
+      if (!barrier_complete(a.bar, abort_flag, epoch)) return;
+      grid_sum(a.part + (size_t)cur * W * a.stride, a.stride, 2 * k + 4, sv, sh);
+      cur ^= 1;
       if (k > 0) {  // r_k, the residual after the previous step
         const double rn2 = sv[2 * k + 3];
         if (!isfinite(rn2)) {
@@ -1103,8 +1139,9 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
         rm[tid] = rv;
         if (k + 1 < R) Zs[(size_t)(k + 1) * n + tid] = rv;
       }
-      // odd site: T_k = Ytilde_oe q - sum_j c_j T_j, t -= alpha T_k
-      hop1<S, MT>(a, Vh + w, nbO, qraw, nullptr, nullptr, 1.0, nullptr, nullptr, Ts + (size_t)k * n, vin, hp, pre);
+      // odd site: T_k = Ytilde_oe q - sum_j c_j T_j, t -= alpha T_k (the raw hop
+      // is in Ts[k]; the barrier keeps the slice sums of q and z read above apart
+      // from the slice sums of T written into the same LDS below)
       __syncthreads();
       if (k > 0 && sl < NS) {
         cpx<double> at = mk(0.0, 0.0);

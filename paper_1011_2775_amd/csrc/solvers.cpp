@@ -428,6 +428,7 @@ KrylovResult mp_bicgstab(Ctx& c, LatticeState& L, void* y, const void* b, bool y
   void* e = c.scratch_buf(34, spinor_bytes(WCMG_F64, g.Vh));
   void* r32 = c.scratch_buf(35, spinor_bytes(WCMG_F32, g.Vh));
   void* e32 = c.scratch_buf(36, spinor_bytes(WCMG_F32, g.Vh));
+  void* y_prev = c.scratch_buf(37, spinor_bytes(WCMG_F64, g.Vh));
   OpFn A32 = [&](void* o, const void* i) { op32.Dr(o, i); };
   if (y_zero) blas_zero(WCMG_F64, y, n, st);
   KrylovResult res;
@@ -453,9 +454,12 @@ KrylovResult mp_bicgstab(Ctx& c, LatticeState& L, void* y, const void* b, bool y
     blas_zero(WCMG_F32, e32, n, st);
     // the inner solve stops at inner_tol, or at the outer target if that is looser
     const double itol = std::max(inner_tol, 0.5 * target / rn);
-    // later cycles get at most three times the first one's iterations (an FP32
-    // solve that stagnates near the critical mass would otherwise spend the budget)
-    const int cap = ncyc == 0 ? maxiter - res.iters : std::min(maxiter - res.iters, std::max(1000, 3 * first_iters));
+    // the first cycle gets an eighth of the budget, later ones at most three times
+    // the first one's iterations (an FP32 solve that stagnates near the critical
+    // mass would otherwise spend the whole budget in one cycle); a capped cycle's
+    // correction is still taken when it lowers the FP64 residual
+    const int left = maxiter - res.iters;
+    const int cap = std::min(left, std::max(1000, ncyc == 0 ? maxiter / 8 : 3 * first_iters));
     KrylovResult k = bicgstab(c, WCMG_F32, n, A32, e32, r32, std::min(itol, 0.5), rn, cap);
     if (ncyc == 0) first_iters = k.iters;
     res.iters += k.iters;
@@ -465,14 +469,16 @@ KrylovResult mp_bicgstab(Ctx& c, LatticeState& L, void* y, const void* b, bool y
       break;
     }
     spinor_convert(WCMG_F64, e, WCMG_F32, e32, g.Vh, st);
+    blas_copy(WCMG_F64, y_prev, y, n, st);
     blas_axpby(WCMG_F64, 1.0, 0.0, e, 1.0, 0.0, y, n, st);  // y += e
     // a correction that does not lower the FP64 residual (an FP32 solve that
-    // diverged) is taken back, and the refinement stops there
+    // diverged) is taken back exactly (from the copy: subtracting a huge e again
+    // would not restore y), and the refinement stops there
     op64.Dr(r, y);
     blas_axpby(WCMG_F64, 1.0, 0.0, b, -1.0, 0.0, r, n, st);
     const double rn_new = std::sqrt(norm2(c, WCMG_F64, r, n));
     if (!(rn_new < rn)) {
-      blas_axpby(WCMG_F64, -1.0, 0.0, e, 1.0, 0.0, y, n, st);  // y -= e
+      blas_copy(WCMG_F64, y, y_prev, n, st);
       res.rel_res = target_norm > 0 ? rn / target_norm : 0.0;
       res.status = WCMG_ENOCONV;
       break;
