@@ -97,13 +97,15 @@ typedef struct {
   int t_bc;    /* -1 antiperiodic (default), +1 periodic */
 } wcmg_lattice;
 
-#define WCMG_MAX_LEVELS 3
+#define WCMG_MAX_LEVELS 4
 
 /* Multigrid parameters (Implementation paragraph, Table 1, Setup section).
  * Level l = 0 is the fine lattice; coarse level l+1 is built from level l
  * with block[l] and nvec[l]. */
 typedef struct {
-  int nlevels;                      /* number of coarse levels: 1 (two-level) or 2 (three-level) */
+  int nlevels;                      /* number of coarse levels: 1 (two-level), 2 (three-level) or 3
+                                       (four-level; the fourth level the Results section anticipates
+                                       for large volumes) */
   int block[WCMG_MAX_LEVELS][4];    /* aggregate (block) extents per level */
   int nvec[WCMG_MAX_LEVELS];        /* null vectors per level (coarse dim 2*nvec) */
   double tol[WCMG_MAX_LEVELS];      /* relative tolerance of the GCR on coarse level l+1 */
@@ -378,16 +380,16 @@ int wcmg_dot(void* ctx, int prec, const void* x, const void* y, long n, double* 
 /* Per-kernel timing with HIP events on the context's stream.
  * wcmg_timer_enable(ctx, 1) resets the counters and starts recording every
  * launch of the timed kernels; wcmg_timer_read returns the launch count and
- * the summed duration in milliseconds for kernel id `which` (0..95,
+ * the summed duration in milliseconds for kernel id `which` (0..127,
  * synchronising the stream).  Ids: fine hop kernel prec*6 + diag*2 +
  * clover_inverse (prec 0 F64, 1 F32, 2 F16; diag 0 none, 1 x, 2 A x; see
  * the DIAG/POST modes of the Dslash), batched fine hops 32 + the same, FP16
  * fields with FP32 spinors 56 + diag*2 + clover_inverse; site-local clover
  * launches 64 + prec (batched 67 + prec, FP16 fields 70), the smoother's
- * fused update + clover launch 72 + prec; coarse red-black hop 20 + 2 l +
- * prec (l = 0 first coarse level, prec 0 F64 / 1 F32; batches +4), batched
- * red-black hop on the matrix cores 50 + 2 l, persistent coarse solve
- * 28 + l. */
+ * fused update + clover launch 72 + prec; coarse red-black hop b + prec
+ * with b = 20 + 2 l for l = 0, 1 and 96 + 2 (l - 2) beyond (l = 0 first
+ * coarse level, prec 0 F64 / 1 F32; batches +4), batched red-black hop on
+ * the matrix cores b + 30, persistent coarse solve 28 + l. */
 int wcmg_timer_enable(void* ctx, int on);
 int wcmg_timer_read(void* ctx, int which, long* count, double* total_ms);
 

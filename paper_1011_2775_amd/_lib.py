@@ -16,7 +16,7 @@ OK, EINVAL, EDIM, ESTATE, ENOCONV, EBREAKDOWN, ENAN, ECLOVER_NOT_PD, ERANK, ENOM
 F64, F32, F16 = 0, 1, 2
 OP_FULL, OP_SCHUR, OP_DP, OP_SCHUR_X = 0, 1, 2, 3
 MG_GCR, GCR, BICGSTAB, MP_BICGSTAB, CGNR = 0, 1, 2, 3, 4
-MAX_LEVELS = 3
+MAX_LEVELS = 4
 
 ERROR_NAMES = {0: "OK", 1: "EINVAL", 2: "EDIM", 3: "ESTATE", 4: "ENOCONV", 5: "EBREAKDOWN", 6: "ENAN",
                7: "ECLOVER_NOT_PD", 8: "ERANK", 9: "ENOMEM", 10: "EHIP", 11: "ENODEV"}

@@ -309,7 +309,8 @@ int wcmg_set_mg_params(void* ctx, int lat, const wcmg_mg_params* p) {
   if (int r = check_lat(c, lat)) return r;
   CHECK(p, WCMG_EINVAL, "null params");
   CHECK(p->nlevels >= 1 && p->nlevels <= WCMG_MAX_LEVELS, WCMG_EINVAL, "nlevels out of range");
-  CHECK(p->nlevels <= 2, WCMG_EINVAL, "at most two coarse levels (nlevels <= 2) are available");
+  CHECK(p->nlevels <= WCMG_MAX_LEVELS - 1, WCMG_EINVAL,
+        "at most three coarse levels (nvec[nlevels] holds the deflation count)");
   LatticeState& L = *c->lats[lat];
   const Geom& g = L.F.g;
   for (int k = 0; k < 4; ++k) {
@@ -410,15 +411,15 @@ int wcmg_set_null_vectors(void* ctx, int lat, int level, const void* v, int nvec
   if (int r = check_level(c, lat, level)) return r;
   LatticeState& L = *c->lats[lat];
   CHECK(nvec == L.params.nvec[level], WCMG_EINVAL, "nvec differs from the parameters");
-  if (level == 1) {
-    CHECK(!L.levels.empty() && L.levels[0]->built, WCMG_ESTATE, "first coarse level not built");
+  if (level >= 1) {
+    CHECK((int)L.levels.size() >= level && L.levels[level - 1]->built, WCMG_ESTATE, "coarse level not built");
     if (on_device)
-      CHECK_DEV(c, v, (size_t)nvec * L.levels[0]->cg.V * L.levels[0]->cg.n * 16, "null vectors");
+      CHECK_DEV(c, v, (size_t)nvec * L.levels[level - 1]->cg.V * L.levels[level - 1]->cg.n * 16, "null vectors");
     return guarded([&] {
-      CoarseLevel& C1 = *L.levels[0];
+      CoarseLevel& C1 = *L.levels[level - 1];
       const size_t one = (size_t)C1.cg.V * C1.cg.n * 16;
-      if (L.ctr.empty()) L.ctr.emplace_back(new CoarseTransfer());
-      CoarseTransfer& T = *L.ctr[0];
+      while ((int)L.ctr.size() < level) L.ctr.emplace_back(new CoarseTransfer());
+      CoarseTransfer& T = *L.ctr[level - 1];
       T.nf = C1.cg.n;
       T.nsites = C1.cg.V;
       T.raw.alloc((size_t)nvec * one);
@@ -432,7 +433,7 @@ int wcmg_set_null_vectors(void* ctx, int lat, int level, const void* v, int nvec
       T.nvec = nvec;
       T.have_vecs = true;
       T.orth = false;
-      if (L.levels.size() > 1) L.levels[1]->built = false;
+      for (size_t l = level; l < L.levels.size(); ++l) L.levels[l]->built = false;
       L.dense_n = 0;
       L.mg.reset();
     });
@@ -464,13 +465,15 @@ int wcmg_get_null_vectors(void* ctx, int lat, int level, void* v, int on_device)
   CHECK(v, WCMG_EINVAL, "null vectors pointer");
   if (int r = check_level(c, lat, level)) return r;
   LatticeState& L = *c->lats[lat];
-  if (level == 1) {
-    CHECK(!L.ctr.empty() && L.ctr[0]->have_vecs && !L.levels.empty(), WCMG_ESTATE, "null vectors not available");
+  if (level >= 1) {
+    CHECK((int)L.ctr.size() >= level && L.ctr[level - 1]->have_vecs && (int)L.levels.size() >= level, WCMG_ESTATE,
+          "null vectors not available");
     if (on_device)
-      CHECK_DEV(c, v, (size_t)L.ctr[0]->nvec * L.levels[0]->cg.V * L.levels[0]->cg.n * 16, "null vectors");
+      CHECK_DEV(c, v, (size_t)L.ctr[level - 1]->nvec * L.levels[level - 1]->cg.V * L.levels[level - 1]->cg.n * 16,
+                "null vectors");
     return guarded([&] {
-      CoarseLevel& C1 = *L.levels[0];
-      CoarseTransfer& T = *L.ctr[0];
+      CoarseLevel& C1 = *L.levels[level - 1];
+      CoarseTransfer& T = *L.ctr[level - 1];
       const size_t one = (size_t)C1.cg.V * C1.cg.n * 16;
       for (int k = 0; k < T.nvec; ++k) {
         void* dst = on_device ? (char*)v + (size_t)k * one : c->scratch_buf(41, one);
@@ -780,22 +783,25 @@ int wcmg_apply_Ddag(void* ctx, int lat, int op, int prec, void* out, const void*
   return apply_common(ctx, lat, op, prec, out, in, nrhs, true);
 }
 
-// restrict (to_coarse) or prolong between coarse level 1 and level 2, canonical layouts
-static int transfer_level1(Ctx* c, LatticeState& L, int prec, void* out, const void* in, int nrhs, bool to_coarse) {
+// restrict (to_coarse) or prolong between coarse level `level` (>= 1) and
+// coarse level level + 1, canonical layouts
+static int transfer_coarse(Ctx* c, LatticeState& L, int level, int prec, void* out, const void* in, int nrhs,
+                           bool to_coarse) {
   CHECK(prec == WCMG_F64 || prec == WCMG_F32, WCMG_EINVAL, "coarse transfer precision must be F64 or F32");
-  CHECK(L.levels.size() > 1 && L.levels[1]->built && !L.ctr.empty() && L.ctr[0]->orth, WCMG_ESTATE,
-        "second coarse level not built");
+  CHECK((int)L.levels.size() > level && L.levels[level]->built && (int)L.ctr.size() >= level &&
+            L.ctr[level - 1]->orth,
+        WCMG_ESTATE, "next coarse level not built");
   {
-    const CoarseLevel& C1 = *L.levels[0];
-    const CoarseLevel& C2 = *L.levels[1];
+    const CoarseLevel& C1 = *L.levels[level - 1];
+    const CoarseLevel& C2 = *L.levels[level];
     const size_t b1 = (size_t)nrhs * C1.cg.V * C1.cg.n * 16, b2 = (size_t)nrhs * C2.cg.V * C2.cg.n * 16;
     CHECK_DEV(c, in, to_coarse ? b1 : b2, "input vectors");
     CHECK_DEV(c, out, to_coarse ? b2 : b1, "output vectors");
   }
   return guarded([&] {
-    CoarseLevel& C1 = *L.levels[0];
-    CoarseLevel& C2 = *L.levels[1];
-    CoarseTransfer& T = *L.ctr[0];
+    CoarseLevel& C1 = *L.levels[level - 1];
+    CoarseLevel& C2 = *L.levels[level];
+    CoarseTransfer& T = *L.ctr[level - 1];
     const size_t one1 = (size_t)C1.cg.V * C1.cg.n, one2 = (size_t)C2.cg.V * C2.cg.n;
     const size_t cs = 16;  // canonical side is complex128
     void* a = c->scratch_buf(46, one1 * 16);
@@ -827,7 +833,7 @@ int wcmg_restrict(void* ctx, int lat, int level, int prec, void* coarse_out, con
   CHECK(valid_prec(prec), WCMG_EINVAL, "bad precision");
   CHECK(nrhs >= 1, WCMG_EINVAL, "nrhs must be >= 1");
   LatticeState& L = *c->lats[lat];
-  if (level == 1) return transfer_level1(c, L, prec, coarse_out, fine_in, nrhs, true);
+  if (level >= 1) return transfer_coarse(c, L, level, prec, coarse_out, fine_in, nrhs, true);
   CHECK(!L.levels.empty() && L.levels[0]->built, WCMG_ESTATE, "coarse operator not built");
   CHECK_DEV(c, fine_in, (size_t)nrhs * L.F.g.V * 12 * 16, "fine vectors");
   CHECK_DEV(c, coarse_out, (size_t)nrhs * L.levels[0]->cg.V * L.levels[0]->cg.n * 16, "coarse vectors");
@@ -869,7 +875,7 @@ int wcmg_prolong(void* ctx, int lat, int level, int prec, void* fine_out, const 
   CHECK(valid_prec(prec), WCMG_EINVAL, "bad precision");
   CHECK(nrhs >= 1, WCMG_EINVAL, "nrhs must be >= 1");
   LatticeState& L = *c->lats[lat];
-  if (level == 1) return transfer_level1(c, L, prec, fine_out, coarse_in, nrhs, false);
+  if (level >= 1) return transfer_coarse(c, L, level, prec, fine_out, coarse_in, nrhs, false);
   CHECK(!L.levels.empty() && L.levels[0]->built, WCMG_ESTATE, "coarse operator not built");
   CHECK_DEV(c, fine_out, (size_t)nrhs * L.F.g.V * 12 * 16, "fine vectors");
   CHECK_DEV(c, coarse_in, (size_t)nrhs * L.levels[0]->cg.V * L.levels[0]->cg.n * 16, "coarse vectors");

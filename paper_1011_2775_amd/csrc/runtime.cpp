@@ -350,7 +350,7 @@ void CoarseOp::Dr(void* out, const void* y, int nrhs) {
   w->ensure(nall() * csize() * nrhs);
   if (prec == WCMG_F32 && nrhs >= 2 && C->has_frag) {
     // batches run on the matrix cores (FP16 operands, FP32 accumulation)
-    const int id = timer_base + 30;  // 50 (level 1), 52 (level 2)
+    const int id = timer_base + 30;  // 50 (level 1), 52 (level 2), 126 (level 3)
     hipEvent_t e = nullptr;
     if (timer && timer->on) timer->begin(id, &e);
     launch_coarse_hop_mfma(w->t1.p, y, nullptr, C->frag.p, 1.0, 1, C->cg, C->nbr.as<int>(), nrhs, nall(), st);
@@ -358,7 +358,7 @@ void CoarseOp::Dr(void* out, const void* y, int nrhs) {
     if (e) timer->end(id, e);
     return;
   }
-  // single right-hand side: 20 + 2 level + precision; batches: 24 + 2 level + precision
+  // single right-hand side: timer_base + precision; batches: timer_base + 4 + precision
   const int id = timer_base + pi() + (nrhs > 1 ? 4 : 0);
   hipEvent_t e = nullptr;
   if (timer && timer->on) timer->begin(id, &e);

@@ -19,7 +19,7 @@ struct KernelTimer {
   hipStream_t st = nullptr;
   std::vector<hipEvent_t> pool;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;  // (class, (start, stop))
-  static constexpr int kIds = 96;
+  static constexpr int kIds = 128;
   long count[kIds] = {};
   double ms[kIds] = {};
   hipEvent_t get();

@@ -105,6 +105,9 @@ KrylovResult gcr(Ctx& c, GcrSpace& S, const OpFn& A, const OpFn* K, void* x, con
       const double* o = R.fetch_from(qa + 4 * kk, 4);  // one host round trip: {||q||^2, <q,r>, ||r||^2}
       const double qq = o[0];
       rn2 = o[3];
+      if (log_level() >= 3 && n > 100000)
+        std::fprintf(stderr, "[wcmg] gcr n=%zu iter %d rel.res %.3e\n", n, res.iters + 1,
+                     target_norm > 0 ? std::sqrt(rn2) / target_norm : 0.0);
       if (!(qq > 0.0) || !finite(qq)) {
         res.status = finite(qq) ? WCMG_EBREAKDOWN : WCMG_ENAN;
         break;
@@ -135,6 +138,9 @@ KrylovResult gcr(Ctx& c, GcrSpace& S, const OpFn& A, const OpFn* K, void* x, con
   }
   res.rel_res = target_norm > 0 ? std::sqrt(rn2) / target_norm : 0.0;
   if (!fixed && !converged && res.status == WCMG_OK) res.status = WCMG_ENOCONV;
+  if (log_level() >= 3 && n <= 100000)
+    std::fprintf(stderr, "[wcmg] gcr n=%zu done: %d iterations, rel.res %.3e, status %d\n", n, res.iters,
+                 res.rel_res, res.status);
   return res;
 }
 
@@ -788,7 +794,7 @@ struct MGSolver {
   const void* vbm(int prec) const { return prec == WCMG_F32 ? L.T0.vbm32.p : nullptr; }
   CoarseOp cop(int li) {
     CoarseOp o{L.levels[li].get(), cp, &cwork, c.st, &c.timer};
-    o.timer_base = 20 + 2 * li;
+    o.timer_base = li < 2 ? 20 + 2 * li : 96 + 2 * (li - 2);
     return o;
   }
 
@@ -1179,22 +1185,23 @@ static void require_hierarchy(LatticeState& L) {
 // ---------------------------------------------------------------------------
 // setup: inverse iteration on D_p with Rayleigh-quotient monitoring
 // ---------------------------------------------------------------------------
-// inverse iteration on the level-1 Dhat_p = Dhat X^-1 for the level-2 vectors
-static void mg_setup_null_vectors_level1(Ctx& c, LatticeState& L) {
+// inverse iteration on the coarse operator Dhat_p = Dhat X^-1 of coarse level
+// `level` (>= 1) for the vectors that build coarse level level + 1
+static void mg_setup_null_vectors_coarse(Ctx& c, LatticeState& L, int level) {
   const wcmg_mg_params& p = L.params;
-  if (p.nlevels < 2) fail(WCMG_EINVAL, "the parameters have a single coarse level");
-  if (L.levels.empty() || !L.levels[0]->built) fail(WCMG_ESTATE, "first coarse level not built");
+  if (level >= p.nlevels) fail(WCMG_EINVAL, "the parameters have no coarse level below this one");
+  if ((int)L.levels.size() < level || !L.levels[level - 1]->built) fail(WCMG_ESTATE, "coarse level not built");
   hipStream_t st = c.st;
-  CoarseLevel& C1 = *L.levels[0];
-  const int nvec = p.nvec[1];
+  CoarseLevel& C1 = *L.levels[level - 1];
+  const int nvec = p.nvec[level];
   const size_t n = (size_t)C1.cg.V * C1.cg.n;
   // coarse levels have no half-precision operator: F16 runs as F32 here
   const int sp = p.setup_prec == WCMG_F64 ? WCMG_F64 : WCMG_F32;
   const size_t cs = sp == WCMG_F64 ? 16 : 8;
   CoarseOp cop{&C1, sp, &c.cw[sp == WCMG_F64 ? 0 : 1], st};
   OpFn Dp = [&](void* o, const void* i) { cop.Dp(o, i); };
-  if (L.ctr.empty()) L.ctr.emplace_back(new CoarseTransfer());
-  CoarseTransfer& T = *L.ctr[0];
+  while ((int)L.ctr.size() < level) L.ctr.emplace_back(new CoarseTransfer());
+  CoarseTransfer& T = *L.ctr[level - 1];
   T.nf = C1.cg.n;
   T.nsites = C1.cg.V;
   T.raw.alloc((size_t)nvec * n * 16);
@@ -1207,7 +1214,7 @@ static void mg_setup_null_vectors_level1(Ctx& c, LatticeState& L) {
   std::vector<const void*> found;
   std::vector<double> cf(2 * nvec);
   for (int k = 0; k < nvec; ++k) {
-    random_coarse_vector(v64, p.seed, k, 1, C1.perm.as<int>(), C1.cg.V, C1.cg.n, st);
+    random_coarse_vector(v64, p.seed, k, level, C1.perm.as<int>(), C1.cg.V, C1.cg.n, st);
     reals_convert(sp, v, reinterpret_cast<const double*>(v64), 2 * n, st);
     double rho_old = -1.0;
     for (int step = 0; step < p.setup_max_steps; ++step) {
@@ -1237,13 +1244,13 @@ static void mg_setup_null_vectors_level1(Ctx& c, LatticeState& L) {
   T.nvec = nvec;
   T.have_vecs = true;
   T.orth = false;
-  if (L.levels.size() > 1) L.levels[1]->built = false;
+  for (size_t l = level; l < L.levels.size(); ++l) L.levels[l]->built = false;
   L.dense_n = 0;
   L.mg.reset();
 }
 
 void mg_setup_null_vectors(Ctx& c, LatticeState& L, int level) {
-  if (level == 1) return mg_setup_null_vectors_level1(c, L);
+  if (level >= 1) return mg_setup_null_vectors_coarse(c, L, level);
   if (level != 0) fail(WCMG_EINVAL, "level out of range");
   if (!L.F.have_clover) fail(WCMG_ESTATE, "clover not set");
   if (!L.have_params) fail(WCMG_ESTATE, "multigrid parameters not set");
@@ -1510,20 +1517,21 @@ static void build_deflation(Ctx& c, LatticeState& L, int li) {
 }
 
 // level-2 operator R2 Dhat_p P2 from the level-1 stencil (direction resolved)
-static void mg_build_coarse_level1(Ctx& c, LatticeState& L) {
+// coarse level level + 1 (level >= 1) from coarse level `level` and its vectors
+static void mg_build_coarse_next(Ctx& c, LatticeState& L, int level) {
   const wcmg_mg_params& p = L.params;
-  if (p.nlevels < 2) fail(WCMG_EINVAL, "the parameters have a single coarse level");
-  if (L.levels.empty() || !L.levels[0]->built) fail(WCMG_ESTATE, "first coarse level not built");
-  if (L.ctr.empty() || !L.ctr[0]->have_vecs) fail(WCMG_ESTATE, "level-1 null vectors not set");
+  if (level >= p.nlevels) fail(WCMG_EINVAL, "the parameters have no coarse level below this one");
+  if ((int)L.levels.size() < level || !L.levels[level - 1]->built) fail(WCMG_ESTATE, "coarse level not built");
+  if ((int)L.ctr.size() < level || !L.ctr[level - 1]->have_vecs) fail(WCMG_ESTATE, "coarse-level null vectors not set");
   hipStream_t st = c.st;
-  CoarseLevel& C1 = *L.levels[0];
-  CoarseTransfer& T = *L.ctr[0];
-  T.bg = make_block_geom(C1.cg.L, p.block[1]);
-  T.nvec = p.nvec[1];
+  CoarseLevel& C1 = *L.levels[level - 1];
+  CoarseTransfer& T = *L.ctr[level - 1];
+  T.bg = make_block_geom(C1.cg.L, p.block[level]);
+  T.nvec = p.nvec[level];
   T.nf = C1.cg.n;
   T.nsites = C1.cg.V;
-  if (L.levels.size() < 2) L.levels.emplace_back(new CoarseLevel());
-  CoarseLevel& C2 = *L.levels[1];
+  while ((int)L.levels.size() <= level) L.levels.emplace_back(new CoarseLevel());
+  CoarseLevel& C2 = *L.levels[level];
   C2.bg = T.bg;
   C2.nvec = T.nvec;
   C2.cg = make_coarse_geom(T.bg, T.nvec);
@@ -1559,7 +1567,7 @@ static void mg_build_coarse_level1(Ctx& c, LatticeState& L) {
   int hflag = 0;
   HIPCHK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  if (hflag) fail(WCMG_ERANK, "level-1 null vectors are linearly dependent on a block");
+  if (hflag) fail(WCMG_ERANK, "coarse-level null vectors are linearly dependent on a block");
   T.v32.alloc((size_t)T.nvec * T.vstride() * 8);
   launch_reals_convert(WCMG_F32, T.v32.p, T.v64.as<double>(), (size_t)T.nvec * T.vstride() * 2, st);
   T.orth = true;
@@ -1586,13 +1594,14 @@ static void mg_build_coarse_level1(Ctx& c, LatticeState& L) {
   }
   finalize_coarse(c, C2, flag);
   C2.built = true;
-  if (p.coarsest == 1) build_dense(c, L, 1);
-  if (p.coarsest == 2) build_deflation(c, L, 1);
+  for (size_t l = level + 1; l < L.levels.size(); ++l) L.levels[l]->built = false;
+  if (level + 1 == p.nlevels && p.coarsest == 1) build_dense(c, L, level);
+  if (level + 1 == p.nlevels && p.coarsest == 2) build_deflation(c, L, level);
   L.mg.reset();
 }
 
 void mg_build_coarse(Ctx& c, LatticeState& L, int level) {
-  if (level == 1) return mg_build_coarse_level1(c, L);
+  if (level >= 1) return mg_build_coarse_next(c, L, level);
   if (level != 0) fail(WCMG_EINVAL, "level out of range");
   if (!L.F.have_clover) fail(WCMG_ESTATE, "clover not set");
   if (!L.have_params) fail(WCMG_ESTATE, "multigrid parameters not set");
@@ -1719,8 +1728,7 @@ void mg_refine_null_vectors(Ctx& c, LatticeState& L, int passes, int iters) {
     L.T0.orth = false;
     for (auto& lv : L.levels) lv->built = false;
     L.mg.reset();
-    mg_build_coarse(c, L, 0);
-    if (p.nlevels >= 2) mg_build_coarse(c, L, 1);
+    for (int l = 0; l < p.nlevels; ++l) mg_build_coarse(c, L, l);
   }
 }
 
@@ -1782,7 +1790,7 @@ void solve_rhs(Ctx& c, LatticeState& L, int solver, void* x_e, void* x_o, const 
       OpFn K = [&](void* o, const void* i) { mg.precondition(o, i); };
       kr = gcr(c, S64, Dr, &K, y, br, x_zero, tol, bn, restart, maxiter);
       s.inner_status = mg.collect_device_stats();
-      for (size_t l = 0; l < mg.lv.size() && l < 3; ++l)
+      for (size_t l = 0; l < mg.lv.size() && l < WCMG_MAX_LEVELS; ++l)
         s.inner_iters[l] = mg.lv[l].calls ? (double)mg.lv[l].iters / mg.lv[l].calls : 0.0;
     }
   }
@@ -1866,7 +1874,7 @@ void solve_batch(Ctx& c, LatticeState& L, void* x_e, void* x_o, const void* b_e,
     s.status = kr[i].status;
     s.inner_status = inner_status;
     s.true_rel_res = bn[i] > 0 ? std::sqrt(h[i] + h[32 + i]) / bn[i] : 0.0;
-    for (size_t l = 0; l < mg.lv.size() && l < 3; ++l)
+    for (size_t l = 0; l < mg.lv.size() && l < WCMG_MAX_LEVELS; ++l)
       s.inner_iters[l] = mg.lv[l].calls ? (double)mg.lv[l].iters / mg.lv[l].calls : 0.0;
     if (s.status == WCMG_OK && !(s.true_rel_res <= tol * 1.0000001)) s.status = WCMG_ENOCONV;
     s.t_solve_s = dt;

@@ -230,3 +230,27 @@ def test_mg_three_levels_and_lu_coarsest():
     info = SolveInfo()
     x2 = H.solve(b, tol=1e-10, info=info)
     assert info.converged and norm(x2 - x) / norm(x) < 1e-8
+
+
+def test_four_levels_galerkin_at_every_coarse_level():
+    """Three coarse levels (8^4 -> 4^4 -> 2x2x4x4 -> 2^4, blocks of extent 1 in
+    some directions): every coarse operator the hierarchy builds from a
+    coarse level equals the brute-force R Dhat_p P of that level, and the
+    four-level solve reaches the tolerance."""
+    dims = (8, 8, 8, 8)
+    op = WilsonClover(dims, inputs.gauge_field(dims, 0.4, 35), -0.1, 1.0)
+    blocks = [(2, 2, 2, 2), (2, 2, 1, 1), (1, 1, 2, 2)]
+    nvec = [4, 4, 4]
+    V1, V2 = op.lat.V // 16, op.lat.V // 64
+    vecs = [rand_vecs(4, op.shape, 36), rand_vecs(4, (V1, 8), 37), rand_vecs(4, (V2, 8), 38)]
+    H = mg.Hierarchy(op, mg.MGParams(blocks, nvec), vecs=vecs)
+    assert [o.lat.dims for o in H.ops[1:]] == [(4, 4, 4, 4), (2, 2, 4, 4), (2, 2, 2, 2)]
+    for l in (1, 2):
+        Ybf = mg.coarse_operator_brute_force(H.ops[l], H.transfers[l])
+        Yd = H.ops[l + 1].dense()
+        assert np.abs(Yd - Ybf).max() < 1e-12 * np.abs(Ybf).max(), l
+    b = inputs.z2_source(dims, 39).reshape(op.shape)
+    info = SolveInfo()
+    x = H.solve(b, tol=1e-8, info=info)
+    assert info.converged and norm(b - op.apply_D(x)) / norm(b) <= 1e-8
+    assert H.inner_calls[3] > 0
