@@ -284,6 +284,125 @@ __device__ void grid_sum(const double* part, int stride, int nv, double* out, do
   __syncthreads();
 }
 
+// Tagged slots: 16 bytes {tag, payload lo, payload hi, tag}, written and read
+// whole with one coherent (agent-scope, the same cache bit as the relaxed
+// agent-scope atomics) 16-byte buffer access.  A reader accepts a slot only
+// when both tags equal the version it expects, so data that carries its own
+// version needs no separate flag, no wait for the writer's stores to
+// complete before a flag, and no barrier round trip: the read itself waits.
+// A copy torn anywhere between the first and the last word shows two
+// different tags and is read again.
+typedef unsigned int tag_u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kCohAux = 16;  // cache-policy operand of the buffer builtins: the sc1 bit
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tag_rsrc(void* base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ void tag_store(__amdgpu_buffer_rsrc_t r, unsigned slot, unsigned tag, unsigned lo,
+                                          unsigned hi) {
+  tag_u32x4 v = {tag, lo, hi, tag};
+  __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)(slot * 16u), 0, kCohAux);
+}
+__device__ __forceinline__ tag_u32x4 tag_load(__amdgpu_buffer_rsrc_t r, unsigned slot) {
+  return __builtin_amdgcn_raw_buffer_load_b128(r, (int)(slot * 16u), 0, kCohAux);
+}
+// reload slot until it carries `tag` (bounded; on time-out or abort raises the
+// abort flag and returns what it has)
+__device__ __forceinline__ tag_u32x4 tag_wait(__amdgpu_buffer_rsrc_t r, unsigned slot, unsigned tag, tag_u32x4 v,
+                                              int* abort_flag) {
+  unsigned spins = 0;
+  while (!(v.x == tag && v.w == tag)) {
+    if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || ++spins > kSpinLimit) {
+      __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+    __builtin_amdgcn_s_sleep(1);
+    v = tag_load(r, slot);
+  }
+  return v;
+}
+__device__ __forceinline__ double tag_double(tag_u32x4 v) {
+  return __longlong_as_double((long long)(((unsigned long long)v.z << 32) | v.y));
+}
+__device__ __forceinline__ void tag_store_double(__amdgpu_buffer_rsrc_t r, unsigned slot, unsigned tag, double x) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  tag_store(r, slot, tag, (unsigned)u, (unsigned)(u >> 32));
+}
+
+// grid_sum over tagged partials (slot base + w stride + v of workgroup w, tag
+// `tag`): the same order of additions; each load is repeated until its slot
+// carries the tag.  false when a wait timed out or another workgroup aborted.
+__device__ bool grid_sum_tagged(__amdgpu_buffer_rsrc_t rp, unsigned base, int stride, int nv, unsigned tag,
+                                double* out, double* scratch, int* abort_flag) {
+  if (nv <= 0) return true;
+  int tpv = 1;
+  while (tpv * 2 * nv <= (int)blockDim.x && tpv < (int)gridDim.x) tpv *= 2;
+  const int t = threadIdx.x, v = t / tpv, j = t - v * tpv;
+  double s = 0.0;
+  if (v < nv) {
+    const int W = gridDim.x;
+    int b = j;
+    for (; b + 7 * tpv < W; b += 8 * tpv) {
+      tag_u32x4 p[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) p[u] = tag_load(rp, base + (unsigned)((b + u * tpv) * stride + v));
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        s += tag_double(tag_wait(rp, base + (unsigned)((b + u * tpv) * stride + v), tag, p[u], abort_flag));
+    }
+    for (; b < W; b += tpv) {
+      const unsigned slot = base + (unsigned)(b * stride + v);
+      s += tag_double(tag_wait(rp, slot, tag, tag_load(rp, slot), abort_flag));
+    }
+  }
+  const int width = tpv < 64 ? tpv : 64;
+  for (int off = width >> 1; off > 0; off >>= 1) s += __shfl_down(s, off, width);
+  if (tpv <= 64) {
+    if (v < nv && j == 0) out[v] = s;
+  } else {
+    const int lane = t & 63, wave = t >> 6;
+    if (lane == 0) scratch[wave] = s;
+    __syncthreads();
+    if (v < nv && j == 0) {
+      double u = 0.0;
+      for (int q = 0; q < tpv / 64; ++q) u += scratch[wave + q];
+      out[v] = u;
+    }
+  }
+  __syncthreads();
+  return __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+}
+
+// block_partial / wave0_partial into tagged slots slot0 + k
+template <int NR>
+__device__ __forceinline__ void block_partial_tag(double (&v)[NR], __amdgpu_buffer_rsrc_t rp, unsigned slot0,
+                                                  unsigned tag, double* sh) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    double s = wave_sum(v[k]);
+    if (lane == 0) sh[k * kPWaves + wave] = s;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < NR) {
+    double s = 0.0;
+    for (int q = 0; q < kPWaves; ++q) s += sh[threadIdx.x * kPWaves + q];
+    tag_store_double(rp, slot0 + threadIdx.x, tag, s);
+  }
+  __syncthreads();
+}
+template <int NR>
+__device__ __forceinline__ void wave0_partial_tag(double (&v)[NR], __amdgpu_buffer_rsrc_t rp, unsigned slot0,
+                                                  unsigned tag) {
+  if (threadIdx.x < 64) {
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      const double s = wave_sum(v[k]);
+      if (threadIdx.x == 0) tag_store_double(rp, slot0 + k, tag, s);
+    }
+  }
+}
+
 // plain (cacheable) load of data this workgroup wrote itself
 template <typename V2>
 __device__ __forceinline__ cpx<double> ldo(const V2* p, size_t i) {
@@ -315,6 +434,9 @@ struct PArgs {
   int sbytes;   // one-site kernel: LDS bytes before the Krylov basis
   int pl;       // one-site kernel: hop matrix column rounds staged in LDS
   int res_off;  // one-site kernel: LDS byte offset of the even site's resident hop blocks (-1: none)
+  void* tags;   // one-site kernel, FP32 vectors: tagged slots, t [V][n], then q [V][n], then the
+                // partial sums [2][W][stride] (nullptr: flags and barriers instead)
+  unsigned tag_bytes;
 };
 
 // largest power of two below G (0 for G = 1): first step of the tree that adds
@@ -799,7 +921,8 @@ template <typename S, typename MT>
 __device__ void hop1(const PArgs& a, int c, int nb, const typename Vec2<S>::T* in, const typename Vec2<S>::T* xdl,
                      const typename Vec2<S>::T* xdg, double coeff, const void* Xl, typename Vec2<S>::T* outg,
                      typename Vec2<S>::T* outl, cpx<typename Compute<S>::T>* vin,
-                     cpx<typename Compute<S>::T>* part, char* pre, const MT* Mres = nullptr) {
+                     cpx<typename Compute<S>::T>* part, char* pre, const MT* Mres = nullptr, int tin = -1,
+                     unsigned tin_tag = 0, int tout = -1, unsigned tout_tag = 0) {
   using C = typename Compute<S>::T;
   using V2 = typename Vec2<S>::T;
   constexpr int NCH = sizeof(S) == 8 ? 2 : 1;  // 16-byte pieces of a thread's two entries of a column
@@ -841,8 +964,21 @@ __device__ void hop1(const PArgs& a, int c, int nb, const typename Vec2<S>::T* i
     }
   }
   if (tid < ncols) {
-    const V2 v = ldc(in + (size_t)nb * n + (tid - (tid / n) * n));
-    vin[tid] = mk((C)v.x, (C)v.y);
+    if constexpr (sizeof(S) == 4) {
+      if (tin >= 0) {
+        // tagged input (tin: 0 t, 1 q): each slot is read until it carries tin_tag
+        const __amdgpu_buffer_rsrc_t rt = tag_rsrc(a.tags, a.tag_bytes);
+        const unsigned slot = (unsigned)(tin * 2 * a.Vh * n + nb * n + (tid - (tid / n) * n));
+        const tag_u32x4 q = tag_wait(rt, slot, tin_tag, tag_load(rt, slot), a.info + 2);
+        vin[tid] = mk((C)__uint_as_float(q.y), (C)__uint_as_float(q.z));
+      } else {
+        const V2 v = ldc(in + (size_t)nb * n + (tid - (tid / n) * n));
+        vin[tid] = mk((C)v.x, (C)v.y);
+      }
+    } else {
+      const V2 v = ldc(in + (size_t)nb * n + (tid - (tid / n) * n));
+      vin[tid] = mk((C)v.x, (C)v.y);
+    }
   }
   __syncthreads();
   if (g < G) {
@@ -922,7 +1058,15 @@ __device__ void hop1(const PArgs& a, int c, int nb, const typename Vec2<S>::T* i
       V2 w;
       w.x = (S)s[k].r;
       w.y = (S)s[k].i;
-      if (outg) stc(outg + (size_t)c * n + 2 * rp + k, w);
+      if constexpr (sizeof(S) == 4) {
+        if (tout >= 0)
+          tag_store(tag_rsrc(a.tags, a.tag_bytes), (unsigned)(tout * 2 * a.Vh * n + c * n + 2 * rp + k), tout_tag,
+                    __float_as_uint(w.x), __float_as_uint(w.y));
+        else if (outg)
+          stc(outg + (size_t)c * n + 2 * rp + k, w);
+      } else {
+        if (outg) stc(outg + (size_t)c * n + 2 * rp + k, w);
+      }
       if (outl) outl[2 * rp + k] = w;
     }
   }
@@ -988,6 +1132,13 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
   unsigned lep = __hip_atomic_load(a.lflags + 32 * w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   int cur = 0;
   auto mine = [&]() { return a.part + ((size_t)cur * W + w) * a.stride; };
+  // FP32 vectors with a tag area: t, q and the step's partial sums travel in
+  // tagged slots (versions tver, qver, epoch), so a step has no flag wait and
+  // no barrier; versions start above anything an earlier launch left
+  const bool tagged = sizeof(S) == 4 && a.tags != nullptr;
+  unsigned tver = epoch, qver = epoch;
+  const unsigned pslot = (unsigned)(4 * Vh * n);  // first partial-sum slot
+  const __amdgpu_buffer_rsrc_t rtag = tag_rsrc(a.tags, a.tag_bytes);
   auto sync_sum = [&](int nv) -> bool {
     if (!grid_barrier(a.bar, abort_flag, ++epoch)) return false;
     if (nv > 0) grid_sum(a.part + (size_t)cur * W * a.stride, a.stride, nv, sv, sh);
@@ -1021,15 +1172,21 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
   }
   while (!conv && iters < a.maxiter) {
     // cycle start: z_0 = r, t = Ytilde_oe r
-    hop1<S, MT>(a, Vh + w, nbO, r, nullptr, nullptr, 1.0, nullptr, t, tm, vin, hp, pre);
+    if (tagged) ++tver;
+    hop1<S, MT>(a, Vh + w, nbO, r, nullptr, nullptr, 1.0, nullptr, t, tm, vin, hp, pre, nullptr, -1, 0,
+                tagged ? 0 : -1, tver);
     if (tid < n) Zs[tid] = rm[tid];
     if (!sync_sum(0)) return;
     int k = 0;
     for (;;) {
       // q = D_r z_k = r - Ytilde_eo t on the even site (stored for the odd neighbours);
       // <q_j, q>, ||q||^2, <q, r> and ||r_k||^2
-      hop1<S, MT>(a, w, nbE, t, rm, nullptr, -1.0, nullptr, qraw, qm, vin, hp, pre, Mres);
+      if (tagged) ++qver;
+      hop1<S, MT>(a, w, nbE, t, rm, nullptr, -1.0, nullptr, qraw, qm, vin, hp, pre, Mres, tagged ? 0 : -1, tver,
+                  tagged ? 1 : -1, qver);
       __syncthreads();
+      const unsigned ep = epoch + 1;  // the step's sum
+      const unsigned pbase = pslot + (unsigned)((cur * W + w) * a.stride);
       {
         const int lane = tid & 63, wave = tid >> 6;
         for (int j = wave; j < k; j += kPWaves) {
@@ -1043,8 +1200,13 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
           sr = wave_sum(sr);
           si = wave_sum(si);
           if (lane == 0) {
-            stc(mine() + 2 * j, sr);
-            stc(mine() + 2 * j + 1, si);
+            if (tagged) {
+              tag_store_double(rtag, pbase + 2 * j, ep, sr);
+              tag_store_double(rtag, pbase + 2 * j + 1, ep, si);
+            } else {
+              stc(mine() + 2 * j, sr);
+              stc(mine() + 2 * j + 1, si);
+            }
           }
         }
         double v[4] = {0.0, 0.0, 0.0, 0.0};
@@ -1055,21 +1217,40 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
           v[2] += qv.r * rr.i - qv.i * rr.r;
           v[3] += rr.r * rr.r + rr.i * rr.i;
         }
-        if (n <= 64)
+        if (tagged) {
+          if (n <= 64)
+            wave0_partial_tag<4>(v, rtag, pbase + 2 * k, ep);
+          else
+            block_partial_tag<4>(v, rtag, pbase + 2 * k, ep, sh);
+        } else if (n <= 64) {
           wave0_partial<4>(v, mine() + 2 * k);
-        else
+        } else {
           block_partial<4>(v, mine() + 2 * k, sh);
+        }
       }
       // arrive at the step's barrier, then build the odd site's raw hop
       // T_k = Ytilde_oe q while the rest of the grid arrives: it needs only the
       // owners of the odd site's even neighbours (q is overwritten no earlier
       // than their next step, which waits for this workgroup's t), and is
       // unused when the step ends the cycle
-      barrier_arrive(a.bar, ++epoch);
-      if (!arrival_wait(a.bar, abort_flag, nbq, epoch)) return;
-      hop1<S, MT>(a, Vh + w, nbO, qraw, nullptr, nullptr, 1.0, nullptr, nullptr, Ts + (size_t)k * n, vin, hp, pre);
-      if (!barrier_complete(a.bar, abort_flag, epoch)) return;
-      grid_sum(a.part + (size_t)cur * W * a.stride, a.stride, 2 * k + 4, sv, sh);
+      // (tagged: the hop's reads of q and the sum's reads of the partials wait
+      // for their versions themselves)
+      if (tagged) {
+        epoch = ep;
+        hop1<S, MT>(a, Vh + w, nbO, qraw, nullptr, nullptr, 1.0, nullptr, nullptr, Ts + (size_t)k * n, vin, hp, pre,
+                    nullptr, 1, qver);
+        __syncthreads();
+        if (!grid_sum_tagged(rtag, pslot + (unsigned)(cur * W * a.stride), a.stride, 2 * k + 4, ep, sv, sh,
+                             abort_flag))
+          return;
+      } else {
+        barrier_arrive(a.bar, ++epoch);
+        if (!arrival_wait(a.bar, abort_flag, nbq, epoch)) return;
+        hop1<S, MT>(a, Vh + w, nbO, qraw, nullptr, nullptr, 1.0, nullptr, nullptr, Ts + (size_t)k * n, vin, hp,
+                    pre);
+        if (!barrier_complete(a.bar, abort_flag, epoch)) return;
+        grid_sum(a.part + (size_t)cur * W * a.stride, a.stride, 2 * k + 4, sv, sh);
+      }
       cur ^= 1;
       if (k > 0) {  // r_k, the residual after the previous step
         const double rn2 = sv[2 * k + 3];
@@ -1152,6 +1333,7 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
         acc[tid] = at;
       }
       __syncthreads();
+      if (tagged) ++tver;
       if (tid < n) {
         cpx<double> tk = cvt(Ts[(size_t)k * n + tid]);
         if (k > 0) {
@@ -1163,22 +1345,28 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
         Ts[(size_t)k * n + tid] = tov2<V2>(tks);
         const V2 tv = tov2<V2>(cvt(tm[tid]) - cmul(alpha, tks));
         tm[tid] = tv;
-        stc(t + oo + tid, tv);
+        if (tagged)
+          tag_store(rtag, (unsigned)(oo + tid), tver, __float_as_uint((float)tv.x), __float_as_uint((float)tv.y));
+        else
+          stc(t + oo + tid, tv);
       }
       if (tid == 0) sqq[k] = qq;
       ++k;
       ++iters;
       if (k >= R || iters >= a.maxiter) break;
       // t of the owned odd site is published; the next even hop reads the neighbours' t
-      if (!neighbour_wait(a.lflags, abort_flag, nbw, ++lep)) return;
+      // (tagged: that read waits for the version itself)
+      if (!tagged && !neighbour_wait(a.lflags, abort_flag, nbw, ++lep)) return;
     }
     // y and t complete everywhere
     if (!sync_sum(0)) return;
     if (status || a.fixed) break;
     // true residual r = b_r - D_r y at the end of the cycle
-    hop1<S, MT>(a, Vh + w, nbO, y, nullptr, nullptr, 1.0, nullptr, t, tm, vin, hp, pre);
+    if (tagged) ++tver;
+    hop1<S, MT>(a, Vh + w, nbO, y, nullptr, nullptr, 1.0, nullptr, t, tm, vin, hp, pre, nullptr, -1, 0,
+                tagged ? 0 : -1, tver);
     if (!sync_sum(0)) return;
-    hop1<S, MT>(a, w, nbE, t, ym, nullptr, -1.0, nullptr, nullptr, qm, vin, hp, pre, Mres);
+    hop1<S, MT>(a, w, nbE, t, ym, nullptr, -1.0, nullptr, nullptr, qm, vin, hp, pre, Mres, tagged ? 0 : -1, tver);
     __syncthreads();
     {
       double v[1] = {0.0};
@@ -1211,6 +1399,11 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
 }  // namespace
 
 size_t coarse_gcr_persistent_part_doubles() { return 2 * kPMaxRestart + 8; }
+
+size_t coarse_gcr_persistent_tag_bytes(int n, int Vh, int grid) {
+  // t and q over all sites, then two buffers of partial sums per workgroup
+  return ((size_t)4 * Vh * n + (size_t)2 * grid * coarse_gcr_persistent_part_doubles()) * 16;
+}
 
 // column groups of the hop: a power of two (at most 64) with G * n / 2 <= kPT (a
 // power of two measured faster than using every thread, e.g. 32 rather than 42
@@ -1284,6 +1477,8 @@ void launch_coarse_gcr_persistent(int prec, const CoarseGcrArgs& g, hipStream_t 
   a.fixed = g.fixed;
   a.stride = (int)coarse_gcr_persistent_part_doubles();
   a.res_off = -1;
+  a.tags = nullptr;
+  a.tag_bytes = 0;
   const int G = persist_groups(n);
   a.G = G;
   const size_t cb = prec == WCMG_F64 ? 16 : 8;
@@ -1314,6 +1509,12 @@ void launch_coarse_gcr_persistent(int prec, const CoarseGcrArgs& g, hipStream_t 
     a.sbytes = (int)sb;
     a.pl = pl;
     if (resident) a.res_off = (int)(sb + basis);
+    // FP32 vectors: t, q and the step sums in tagged slots (no flag waits or barriers per step)
+    if (prec == WCMG_F32 && g.tags && g.tag_bytes >= coarse_gcr_persistent_tag_bytes(n, g.Vh, g.grid) &&
+        g.tag_bytes < ((size_t)1 << 31)) {
+      a.tags = g.tags;
+      a.tag_bytes = (unsigned)g.tag_bytes;
+    }
     HIPCHK(hipLaunchCooperativeKernel(ks, dim3(g.grid), dim3(kPT), args, (unsigned)site_shm, st));
     return;
   }

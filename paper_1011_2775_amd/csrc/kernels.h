@@ -294,8 +294,13 @@ struct CoarseGcrArgs {
   int Vh, n, restart, maxiter, fixed, grid;
   int general;  // always the strided kernel
   int mat16;    // Yt holds FP16 hop blocks (FP32 vectors and arithmetic)
+  void* tags;   // tagged slots of the one-site FP32 kernel (coarse_gcr_persistent_tag_bytes; zeroed
+                // whenever the barrier lines are; nullptr: flags and barriers at every step)
+  size_t tag_bytes;
 };
 size_t coarse_gcr_persistent_part_doubles();
+// bytes of the tagged slots for a coarse level of Vh sites per parity, n components, grid workgroups
+size_t coarse_gcr_persistent_tag_bytes(int n, int Vh, int grid);
 // workgroups of the persistent coarse solve on this device (0: not available)
 int coarse_gcr_persistent_grid(int prec, int n, int Vh);
 void launch_coarse_gcr_persistent(int prec, const CoarseGcrArgs& a, hipStream_t st);

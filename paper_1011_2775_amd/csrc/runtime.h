@@ -282,6 +282,7 @@ KrylovResult gcr(Ctx& c, GcrSpace& S, const OpFn& A, const OpFn* K, void* x, con
 // and read back by persistent_collect (one host synchronisation).
 struct PersistWork {
   DBuf q, z, t, qraw, part, ctl;  // Krylov bases, odd-site hops of q, partial sums, barrier lines + info
+  DBuf tags;                      // tagged slots of t, q and the step sums (cleared with ctl)
   int grid = -1;         // workgroups (0: not available; -1: not yet queried)
   bool pending = false;  // device counters not yet read back
 };
@@ -298,6 +299,8 @@ struct PersistBufs {
   void *Q, *Z, *T, *qraw;
   double* part;
   void* ctl;
+  void* tags = nullptr;  // coarse_gcr_persistent_tag_bytes, zeroed with ctl (nullptr: no tagged steps)
+  size_t tag_bytes = 0;
 };
 void persistent_launch_bufs(Ctx& c, int grid, const PersistBufs& B, CoarseLevel& C, int prec, void* out,
                             const void* in, void* t, void* y, void* r, void* br, double tol, int restart,

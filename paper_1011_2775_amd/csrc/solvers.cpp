@@ -607,6 +607,8 @@ void persistent_launch_bufs(Ctx& c, int grid, const PersistBufs& B, CoarseLevel&
   a.fixed = fixed ? 1 : 0;
   a.grid = grid;
   a.general = general ? 1 : 0;
+  a.tags = B.tags;
+  a.tag_bytes = B.tag_bytes;
   launch_coarse_gcr_persistent(prec, a, c.st);
 }
 
@@ -620,12 +622,16 @@ void persistent_launch(Ctx& c, PersistWork& w, CoarseLevel& C, int prec, void* o
   w.z.alloc((size_t)restart * hv * cs);
   w.t.alloc((size_t)restart * 2 * hv * cs);
   w.qraw.alloc(hv * cs);
-  if (!w.ctl.p) {
+  const size_t tb = coarse_gcr_persistent_tag_bytes(C.cg.n, C.cg.Vh, w.grid);
+  if (!w.ctl.p || w.tags.n < tb) {
+    // the barrier epochs restart from zero together with every tag
     w.part.alloc(2 * (size_t)w.grid * coarse_gcr_persistent_part_doubles() * sizeof(double));
     w.ctl.alloc(kPersistCtlBytes);
+    w.tags.alloc(tb);
     HIPCHK(hipMemsetAsync(w.ctl.p, 0, kPersistCtlBytes, c.st));
+    HIPCHK(hipMemsetAsync(w.tags.p, 0, w.tags.n, c.st));
   }
-  PersistBufs B{w.q.p, w.z.p, w.t.p, w.qraw.p, w.part.as<double>(), w.ctl.p};
+  PersistBufs B{w.q.p, w.z.p, w.t.p, w.qraw.p, w.part.as<double>(), w.ctl.p, w.tags.p, tb};
   persistent_launch_bufs(c, w.grid, B, C, prec, out, in, t, y, r, br, tol, restart, maxiter, fixed, general, mat16);
   w.pending = true;
 }
@@ -663,6 +669,8 @@ NoAllocPlan plan_noalloc(Carve& k, const CoarseLevel& C, int prec, int restart, 
   P.B.Z = k.take((size_t)restart * hv * cs);
   P.B.T = k.take((size_t)restart * 2 * hv * cs);
   P.B.qraw = k.take(hv * cs);
+  P.B.tag_bytes = coarse_gcr_persistent_tag_bytes(C.cg.n, C.cg.Vh, grid);
+  P.B.tags = k.take(P.B.tag_bytes);
   return P;
 }
 }  // namespace
@@ -679,8 +687,9 @@ void coarse_solve_noalloc(Ctx& c, CoarseLevel& C, int prec, void* base, int grid
   restart = std::min(restart, std::max(1, max_iter));
   NoAllocPlan P = plan_noalloc(k, C, prec, restart, grid);
   const size_t nall = (size_t)C.cg.V * C.cg.n;
-  // the previous call's barrier epochs, counters and status words are not ours
+  // the previous call's barrier epochs, counters, status words and tags are not ours
   noalloc_zero(P.B.ctl, kPersistCtlBytes, c.st);
+  noalloc_zero(P.B.tags, P.B.tag_bytes, c.st);
   launch_coarse_canon(prec, P.vb, const_cast<void*>(b), C.perm.as<int>(), C.cg.V, C.cg.n, true, c.st);
   auto t0 = std::chrono::steady_clock::now();
   persistent_launch_bufs(c, grid, P.B, C, prec, P.vx, P.vb, P.t, P.y, P.r, P.br, tol, restart, max_iter, false,
