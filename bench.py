@@ -88,20 +88,23 @@ def dslash_flops_per_site(diag, postinv):
     return f
 
 
-def coarse_step_bytes(coarse_sites_h, coarse_n, cs=8):
+def coarse_step_bytes(coarse_sites_h, coarse_n, cs=8, mat_cs=None):
     """Algorithmic bytes of one step of the red-black coarse GCR: the two
-    half hops read the 8 hop blocks (n x n complex) of every site once, and
-    the step makes about ten passes over length-Vh/2*n vectors (gathers,
-    the new basis pair, the update of x and r)."""
-    return coarse_sites_h * (2 * 8 * coarse_n * coarse_n + 10 * coarse_n) * cs
+    half hops read the 8 hop blocks (n x n complex, mat_cs bytes each: 8 for
+    FP32, 4 for FP16 storage) of every site once, and the step makes about
+    ten passes over length-Vh/2*n vectors of cs-byte complexes (gathers, the
+    new basis pair, the update of x and r)."""
+    mat_cs = cs if mat_cs is None else mat_cs
+    return coarse_sites_h * (2 * 8 * coarse_n * coarse_n * mat_cs + 10 * coarse_n * cs)
 
 
 PREC_NAMES = ["double", "float", "__half"]
 
 
-def kernel_table(ctxs, vh, coarse_sites_h, coarse_n, coarse_steps=0):
+def kernel_table(ctxs, vh, coarse_sites_h, coarse_n, coarse_steps=0, coarse_fp16=False):
     """Per timed kernel id: launches, mean duration, algorithmic bytes per launch.
-    coarse_steps: GCR steps the persistent coarse solves took in total."""
+    coarse_steps: GCR steps the persistent coarse solves took in total;
+    coarse_fp16: the persistent solve read FP16 hop blocks."""
     rows = []
     for kid in list(range(18)) + [20, 21, 28] + [64, 65, 66]:
         n, ms = 0, 0.0
@@ -125,9 +128,10 @@ def kernel_table(ctxs, vh, coarse_sites_h, coarse_n, coarse_steps=0):
         elif kid == 28:
             # the whole coarse solve in one launch: bytes and flops of its GCR steps (the
             # one-site kernel when every workgroup of the 256 owns one even site)
-            name = "k_coarse_gcr_site<float>" if coarse_sites_h <= 256 else "k_coarse_gcr<float>"
+            name = ("k_coarse_gcr_site" if coarse_sites_h <= 256 else "k_coarse_gcr") + \
+                ("<float,__half2>" if coarse_fp16 else "<float>")
             steps = coarse_steps / n
-            bytes_launch = steps * coarse_step_bytes(coarse_sites_h, coarse_n)
+            bytes_launch = steps * coarse_step_bytes(coarse_sites_h, coarse_n, 8, 4 if coarse_fp16 else 8)
             flops = steps * 2 * coarse_sites_h * 8 * coarse_n * coarse_n * 8
         else:
             cs = 16 if kid == 20 else 8
@@ -145,9 +149,11 @@ def kernel_table(ctxs, vh, coarse_sites_h, coarse_n, coarse_steps=0):
 # kernel -> source files whose text the traffic counters were taken with
 KERNEL_SOURCES = {"k_coarse_gcr<float>": ["coarse_persist.hip"],
                   "k_coarse_gcr_site<float>": ["coarse_persist.hip"],
+                  "k_coarse_gcr<float,__half2>": ["coarse_persist.hip"],
+                  "k_coarse_gcr_site<float,__half2>": ["coarse_persist.hip"],
                   "k_coarse_hop<float, 1>": ["coarse.hip"]}
 for _p in PREC_NAMES:
-    for _k in ("0,true", "1,false"):
+    for _k in ("0,true", "1,false", "2,false"):
         KERNEL_SOURCES["dslash_kernel<%s,%s>" % (_p, _k)] = ["dslash.hip"]
     KERNEL_SOURCES["clover_kernel<%s>" % _p] = ["dslash.hip"]
 
@@ -758,7 +764,8 @@ def main():
     vc = inputs.volume(dims) // int(np.prod(bl))
     # coarse GCR steps of the timed solves (one coarse solve per outer iteration)
     coarse_steps = sum(st["inner_iters"][0] * st["iters"] for st in timed_stats)
-    rows = kernel_table(main_ctxs, vh, vc // 2, 2 * cfg["nvec"][0], coarse_steps)
+    rows = kernel_table(main_ctxs, vh, vc // 2, 2 * cfg["nvec"][0], coarse_steps,
+                        coarse_fp16=bool(mg_params(w, cfg).coarse_fp16))
     for ctx in main_ctxs:
         ctx.timer_enable(False)
     dom = rows[0]
@@ -766,7 +773,10 @@ def main():
                 "unit": "GB/s", "frac": round(dom["GBps"] / PEAK_HBM_GBS, 4),
                 "traffic": measured_traffic(dom["kernel"]),
                 "bytes_per_launch": dom["bytes_per_launch"], "avg_launch_us": dom["avg_us"],
-                "note": "working set fits the 256 MB Infinity Cache at 16^3x32; see dslash_24x24x24x64"}
+                "note": "one launch = one whole coarse red-black GCR solve (a chain of dependent grid-wide "
+                        "reductions and neighbour exchanges, latency-bound); its operator fits the 256 MB "
+                        "Infinity Cache and, for the even sites, LDS; the HBM-bound fine operator is in "
+                        "dslash_24x24x24x64"}
 
     def mass_row(m0):
         x, st = last[m0]
