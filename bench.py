@@ -234,6 +234,13 @@ def oracle_sample(U2=None):
     return out
 
 
+def _round_sample(k, v):
+    """Times to 0.1 ms; residuals keep their significant digits."""
+    if not isinstance(v, float):
+        return v
+    return float("%.3e" % v) if k.endswith("_res") else round(v, 4)
+
+
 def cpu_baseline(U2, bicg_iters_gpu, m0):
     """The oracle on the host: all threads in this process, one thread in a
     child process (thread counts fixed before NumPy loads)."""
@@ -251,9 +258,8 @@ def cpu_baseline(U2, bicg_iters_gpu, m0):
                       "m0=%g (%.2f s each), scaled by the %d iterations the GPU's FP64 BiCGStab needs to reach "
                       "1e-10 (extrapolated); measured in full: the 4^4 multigrid GCR solve and BiCGStab, one "
                       "16^3x32 D_r apply" % (os.cpu_count() or 0, m0, per_iter, bicg_iters_gpu),
-            "all_threads": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in allc.items()},
-            "one_thread": ({k: (round(v, 4) if isinstance(v, float) else v) for k, v in one.items()} if one else
-                           None),
+            "all_threads": {k: _round_sample(k, v) for k, v in allc.items()},
+            "one_thread": ({k: _round_sample(k, v) for k, v in one.items()} if one else None),
             "c3_dr_apply_s_scaled": round(allc["c2_dr_apply_s"] * (24 ** 3 * 64) / (16 ** 3 * 32), 2),
             "c3_dr_apply_note": "16^3x32 D_r apply scaled by the volume ratio 6.75 (the oracle's work is linear "
                                 "in the volume)"}
