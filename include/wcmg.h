@@ -131,7 +131,11 @@ typedef struct {
   int cycle_mode;                   /* 0: inner GCRs stop at their tolerance (paper); 1: every inner
                                        GCR runs exactly max_iter[l] steps with no host round trip;
                                        2: as 1, with the whole preconditioner captured once into a
-                                       HIP graph and replayed at every outer iteration */
+                                       HIP graph and replayed at every outer iteration; 3: as 0, with
+                                       the preconditioner captured and replayed as in 2 when it is a
+                                       pure sequence of kernels (one coarse level solved by the
+                                       persistent launch, whose tolerance test runs on the device),
+                                       eagerly otherwise or where the capture is refused */
   wcmg_prec setup_prec;             /* arithmetic of the null-vector setup (inverse iteration, Setup
                                        section): F32 (default), F64, or F16 (FP32 vectors and
                                        arithmetic with half-precision links and clover); the
@@ -379,7 +383,9 @@ int wcmg_dot(void* ctx, int prec, const void* x, const void* y, long n, double* 
 
 /* Per-kernel timing with HIP events on the context's stream.
  * wcmg_timer_enable(ctx, 1) resets the counters and starts recording every
- * launch of the timed kernels; wcmg_timer_read returns the launch count and
+ * launch of the timed kernels (2: only the persistent coarse solves, whose
+ * launches are long, so that recording them costs the solve almost nothing;
+ * 0: off); wcmg_timer_read returns the launch count and
  * the summed duration in milliseconds for kernel id `which` (0..127,
  * synchronising the stream).  Ids: fine hop kernel prec*6 + diag*2 +
  * clover_inverse (prec 0 F64, 1 F32, 2 F16; diag 0 none, 1 x, 2 A x; see

@@ -352,7 +352,8 @@ class Context:
 
     # -- timing --------------------------------------------------------------------
     def timer_enable(self, on=True):
-        check(_lib.LIB.wcmg_timer_enable(self.h, int(bool(on))))
+        """True / 1: time every timed kernel; 2: only the persistent coarse solves; False / 0: off."""
+        check(_lib.LIB.wcmg_timer_enable(self.h, 2 if on == 2 and on is not True else int(bool(on))))
 
     def timer_read(self, which=0):
         n = ctypes.c_long()

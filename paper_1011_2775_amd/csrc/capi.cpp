@@ -333,7 +333,7 @@ int wcmg_set_mg_params(void* ctx, int lat, const wcmg_mg_params* p) {
   CHECK(p->setup_relax >= 1 && p->setup_max_steps >= 1, WCMG_EINVAL, "setup iteration counts must be >= 1");
   CHECK(p->coarsest >= 0 && p->coarsest <= 2, WCMG_EINVAL,
         "coarsest must be 0 (GCR), 1 (dense FP64 inverse) or 2 (deflated FP64 GCR)");
-  CHECK(p->cycle_mode >= 0 && p->cycle_mode <= 2, WCMG_EINVAL, "cycle_mode must be 0, 1 or 2");
+  CHECK(p->cycle_mode >= 0 && p->cycle_mode <= 3, WCMG_EINVAL, "cycle_mode must be 0, 1, 2 or 3");
   CHECK(p->coarse_launch >= 0 && p->coarse_launch <= 2, WCMG_EINVAL, "coarse_launch must be 0, 1 or 2");
   CHECK(p->plain_max_iter >= 0, WCMG_EINVAL, "plain_max_iter must be >= 0");
   CHECK(p->mp_inner_tol >= 0 && p->mp_inner_tol < 1, WCMG_EINVAL, "mp_inner_tol must be in [0,1)");
@@ -1242,10 +1242,12 @@ int wcmg_autotune_report(void* ctx, char* buf, int len) {
 
 int wcmg_timer_enable(void* ctx, int on) {
   CHECK(ctx, WCMG_EINVAL, "null context");
+  CHECK(on >= 0 && on <= 2, WCMG_EINVAL, "timer mode must be 0, 1 or 2");
   return guarded([&] {
     Ctx* c = as_ctx(ctx);
     c->timer.reset();
     c->timer.on = on != 0;
+    c->timer.only_persistent = on == 2;
   });
 }
 

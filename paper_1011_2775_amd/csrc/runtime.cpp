@@ -81,7 +81,10 @@ hipEvent_t KernelTimer::get() {
   return e;
 }
 void KernelTimer::begin(int cls, hipEvent_t* a) {
-  (void)cls;
+  if (only_persistent && (cls < 28 || cls > 30)) {
+    *a = nullptr;  // the caller then records no end either
+    return;
+  }
   *a = get();
   HIPCHK(hipEventRecord(*a, st));
 }

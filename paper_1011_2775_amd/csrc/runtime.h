@@ -16,6 +16,7 @@ namespace wcmg {
 // HIP-event timing of selected kernel classes on the context stream.
 struct KernelTimer {
   bool on = false;
+  bool only_persistent = false;  // record only the persistent coarse solves (ids 28-30)
   hipStream_t st = nullptr;
   std::vector<hipEvent_t> pool;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;  // (class, (start, stop))

@@ -772,7 +772,8 @@ struct MGSolver {
     if (graph) (void)hipGraphDestroy(graph);
     if (cap) (void)hipStreamDestroy(cap);
   }
-  bool fixed() const { return L.params.cycle_mode > 0; }
+  bool fixed() const { return L.params.cycle_mode == 1 || L.params.cycle_mode == 2; }
+  bool graph_failed = false;  // cycle_mode 3: the capture was refused; the body runs eagerly
 
   MGSolver(Ctx& ctx, LatticeState& lat) : c(ctx), L(lat) {
     sp = L.params.smoother_prec == WCMG_F64 ? WCMG_F64 : WCMG_F32;
@@ -850,7 +851,7 @@ struct MGSolver {
   // capture (cycle_mode 2), and only where the device runs the whole grid at once
   bool persistent_ok(int li) {
     const wcmg_mg_params& p = L.params;
-    if (p.coarse_launch == 1 || p.cycle_mode == 2) return false;
+    if (p.coarse_launch == 1 || p.cycle_mode == 2) return false;  // cycle_mode 3 captures it
     return persistent_available(lv[li].pw, cp, *L.levels[li], p.restart[li]);
   }
 
@@ -984,7 +985,18 @@ struct MGSolver {
   // K(r_e): even part of P (coarse solve) R (r_e, 0), then MR smoothing on D_r
   void precondition(void* z64, const void* r64) {
     if (L.params.cycle_mode == 2) return precondition_graph(z64, r64);
+    if (L.params.cycle_mode == 3 && graph_ready()) return precondition_graph(z64, r64);
     precondition_body(z64, r64);
+  }
+
+  // cycle_mode 3: the body is a pure sequence of kernels -- no host read --
+  // when the only coarse level is solved by the persistent launch, whose
+  // adaptive tolerance lives on the device; then it is captured and replayed
+  // like cycle_mode 2 (anything else runs eagerly)
+  bool graph_ready() {
+    const wcmg_mg_params& p = L.params;
+    if (graph_failed || p.nlevels != 1 || p.coarsest != 0 || !L.levels[0]->cg.split) return false;
+    return persistent_ok(0);
   }
 
   // cycle_mode 2: the body (kernels only: fixed inner lengths, device
@@ -1006,16 +1018,42 @@ struct MGSolver {
       c.timer.on = false;
       c.st = cap;
       HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-      precondition_body(g_z.p, g_r.p);
+      bool body_ok = true;
+      Error body_err{WCMG_OK, ""};
+      try {
+        precondition_body(g_z.p, g_r.p);
+      } catch (const Error& err) {
+        body_ok = false;
+        body_err = err;
+      }
       hipError_t e = hipStreamEndCapture(cap, &graph);
       c.st = keep;
       c.timer.on = timer_on;
-      HIPCHK(e);
-      HIPCHK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+      if (body_ok && e == hipSuccess) e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+      if (!body_ok || e != hipSuccess) {
+        (void)hipGetLastError();
+        if (graph) (void)hipGraphDestroy(graph);
+        graph = nullptr;
+        gexec = nullptr;
+        // cycle_mode 2 needs the graph; cycle_mode 3 runs the same body eagerly instead
+        if (L.params.cycle_mode == 2) {
+          if (!body_ok) throw body_err;
+          HIPCHK(e);
+        }
+        graph_failed = true;
+        precondition_body(z64, r64);
+        return;
+      }
     }
     blas_copy(WCMG_F64, g_r.p, r64, n, c.st);
     HIPCHK(hipGraphLaunch(gexec, c.st));
     blas_copy(WCMG_F64, z64, g_z.p, n, c.st);
+    ++calls;
+    if (L.params.cycle_mode == 3) {
+      // the replayed persistent launch counts its steps on the device as the eager one does
+      ++lv[0].calls;
+      lv[0].pw.pending = true;
+    }
   }
 
   void precondition_body(void* z64, const void* r64) {
