@@ -211,15 +211,29 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// NR wavefront sums at once: the same tree for every value, its levels
+// interleaved across the values so that their shuffles overlap instead of
+// running one chain after another (each result bitwise that of wave_sum)
+template <int NR>
+__device__ __forceinline__ void wave_sum_n(double (&v)[NR]) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    double t[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) t[k] = __shfl_down(v[k], off);
+#pragma unroll
+    for (int k = 0; k < NR; ++k) v[k] += t[k];
+  }
+}
+
 // Block sum of NR values into part[0..NR), fixed order (lanes, then waves).
 template <int NR>
 __device__ __forceinline__ void block_partial(double (&v)[NR], double* part, double* sh) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  wave_sum_n<NR>(v);
 #pragma unroll
-  for (int k = 0; k < NR; ++k) {
-    double s = wave_sum(v[k]);
-    if (lane == 0) sh[k * kPWaves + wave] = s;
-  }
+  for (int k = 0; k < NR; ++k)
+    if (lane == 0) sh[k * kPWaves + wave] = v[k];
   __syncthreads();
   if ((int)threadIdx.x < NR) {
     double s = 0.0;
@@ -235,11 +249,10 @@ __device__ __forceinline__ void block_partial(double (&v)[NR], double* part, dou
 template <int NR>
 __device__ __forceinline__ void wave0_partial(double (&v)[NR], double* part) {
   if (threadIdx.x < 64) {
+    wave_sum_n<NR>(v);
 #pragma unroll
-    for (int k = 0; k < NR; ++k) {
-      const double s = wave_sum(v[k]);
-      if (threadIdx.x == 0) stc(part + k, s);
-    }
+    for (int k = 0; k < NR; ++k)
+      if (threadIdx.x == 0) stc(part + k, v[k]);
   }
 }
 
@@ -378,11 +391,10 @@ template <int NR>
 __device__ __forceinline__ void block_partial_tag(double (&v)[NR], __amdgpu_buffer_rsrc_t rp, unsigned slot0,
                                                   unsigned tag, double* sh) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  wave_sum_n<NR>(v);
 #pragma unroll
-  for (int k = 0; k < NR; ++k) {
-    double s = wave_sum(v[k]);
-    if (lane == 0) sh[k * kPWaves + wave] = s;
-  }
+  for (int k = 0; k < NR; ++k)
+    if (lane == 0) sh[k * kPWaves + wave] = v[k];
   __syncthreads();
   if ((int)threadIdx.x < NR) {
     double s = 0.0;
@@ -395,11 +407,10 @@ template <int NR>
 __device__ __forceinline__ void wave0_partial_tag(double (&v)[NR], __amdgpu_buffer_rsrc_t rp, unsigned slot0,
                                                   unsigned tag) {
   if (threadIdx.x < 64) {
+    wave_sum_n<NR>(v);
 #pragma unroll
-    for (int k = 0; k < NR; ++k) {
-      const double s = wave_sum(v[k]);
-      if (threadIdx.x == 0) tag_store_double(rp, slot0 + k, tag, s);
-    }
+    for (int k = 0; k < NR; ++k)
+      if (threadIdx.x == 0) tag_store_double(rp, slot0 + k, tag, v[k]);
   }
 }
 
@@ -677,8 +688,10 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr(PArgs a) {
             sr += u.r * qv.r + u.i * qv.i;
             si += u.r * qv.i - u.i * qv.r;
           }
-          sr = wave_sum(sr);
-          si = wave_sum(si);
+          double p2[2] = {sr, si};
+          wave_sum_n<2>(p2);
+          sr = p2[0];
+          si = p2[1];
           if (lane == 0) {
             stc(mine() + 2 * j, sr);
             stc(mine() + 2 * j + 1, si);
@@ -1197,8 +1210,10 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
             sr += u.r * qv.r + u.i * qv.i;
             si += u.r * qv.i - u.i * qv.r;
           }
-          sr = wave_sum(sr);
-          si = wave_sum(si);
+          double p2[2] = {sr, si};
+          wave_sum_n<2>(p2);
+          sr = p2[0];
+          si = p2[1];
           if (lane == 0) {
             if (tagged) {
               tag_store_double(rtag, pbase + 2 * j, ep, sr);
