@@ -290,7 +290,7 @@ __device__ __forceinline__ void dslash_site(const DslashArgs& a, int lb, double*
 #pragma unroll
   for (int r = 0; r < NR; ++r)
     if (r < nr)
-      SpinorIO<S>::store(const_cast<void*>(rhs_ptr<S>(a.out, a.rstride, g0 + r)), a.g.Vh, i, out[r]);
+      SpinorIO<S>::template store<STREAM>(const_cast<void*>(rhs_ptr<S>(a.out, a.rstride, g0 + r)), a.g.Vh, i, out[r]);
 }
 
 template <typename S, typename G, int DIAG, bool POSTINV, int NR, bool STREAM>
@@ -424,8 +424,8 @@ static void launch_dslash_nr(int diag, bool postinv, DslashArgs a, hipStream_t s
   if (threads != 64 && threads != 128 && threads != 256) fail(WCMG_EINVAL, "unsupported Dslash block size");
   a.nblocks = (a.g.Vh + threads - 1) / threads;
   dim3 grid(xcd_grid(a.nblocks), (a.nrhs + NR - 1) / NR);
-  // stream the fields when they (links and both clover records, both parities) exceed
-  // three quarters of the 256 MB Infinity Cache
+  // stream the fields and the output past the caches when the fields (links and both
+  // clover records, both parities) exceed three quarters of the 256 MB Infinity Cache
   const bool stream = a.stream >= 0 ? a.stream != 0 : (double)a.g.Vh * 432.0 * sizeof(G) > 192.0e6;
 #define WCMG_DS(D, P)                                                                                  \
   do {                                                                                               \
