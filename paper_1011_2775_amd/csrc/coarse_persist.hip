@@ -204,26 +204,50 @@ __device__ __forceinline__ cpx<double> axpy_round(cpx<double> r, cpx<double> a, 
   return mk((double)(S)vr, (double)(S)vi);
 }
 
-// wavefront sum, the result valid in lane 0 (fixed shuffle tree)
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+// sum over the 8 lanes of a lane octet (lane % 8), the same bits in all 8: the
+// DPP (data-parallel primitive) butterfly (pairs, quads, then the half-row mirror
+// that meets the other quad); a + b = b + a keeps the partners equal
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f(double v) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)u, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <typename C>
+__device__ __forceinline__ C sum8(C v) {
+  v = v + dpp_f<0xB1>(v);   // quad_perm [1,0,3,2]
+  v = v + dpp_f<0x4E>(v);   // quad_perm [2,3,0,1]
+  v = v + dpp_f<0x141>(v);  // row_half_mirror
   return v;
 }
 
-// NR wavefront sums at once: the same tree for every value, its levels
-// interleaved across the values so that their shuffles overlap instead of
-// running one chain after another (each result bitwise that of wave_sum)
+// wavefront sum, the same bits in every lane (all 64 lanes must be active):
+// the octet butterfly of sum8, the two octets of each row of 16 lanes (row
+// rotation by 8), then the four row sums read from lanes 0, 16, 32 and 48
+// and added as (r0 + r1) + (r2 + r3).  Cross-lane moves inside the ALU
+// instead of LDS permutes.
+__device__ __forceinline__ double rdlane(double v, int l) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)u, l), hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double wave_sum(double v) {
+  v = sum8(v);
+  v = v + dpp_f<0x128>(v);  // row_ror:8
+  return (rdlane(v, 0) + rdlane(v, 16)) + (rdlane(v, 32) + rdlane(v, 48));
+}
+
+// NR wavefront sums at once (independent chains the compiler interleaves;
+// each result bitwise that of wave_sum)
 template <int NR>
 __device__ __forceinline__ void wave_sum_n(double (&v)[NR]) {
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    double t[NR];
-#pragma unroll
-    for (int k = 0; k < NR; ++k) t[k] = __shfl_down(v[k], off);
-#pragma unroll
-    for (int k = 0; k < NR; ++k) v[k] += t[k];
-  }
+  for (int k = 0; k < NR; ++k) v[k] = wave_sum(v[k]);
 }
 
 // Block sum of NR values into part[0..NR), fixed order (lanes, then waves).
@@ -256,43 +280,26 @@ __device__ __forceinline__ void wave0_partial(double (&v)[NR], double* part) {
   }
 }
 
-// out[v] (LDS) = sum over workgroups of part[w * stride + v], v < nv: TPV
-// threads per value (a power of two) each add a fixed strided subset of the
-// workgroups, then a fixed shuffle tree (and, past one wavefront, LDS) adds
-// the TPV subtotals; the same order in every workgroup
-__device__ void grid_sum(const double* part, int stride, int nv, double* out, double* scratch) {
-  if (nv <= 0) return;
-  int tpv = 1;
-  while (tpv * 2 * nv <= (int)blockDim.x && tpv < (int)gridDim.x) tpv *= 2;
-  const int t = threadIdx.x, v = t / tpv, j = t - v * tpv;
-  double s = 0.0;
-  if (v < nv) {
-    // eight loads in flight, then added in workgroup order
-    const int W = gridDim.x;
-    int b = j;
-    for (; b + 7 * tpv < W; b += 8 * tpv) {
+// out[v] (LDS) = sum over workgroups of part[w * stride + v], v < nv, in the
+// one order that every grid sum of this file uses: lane l of a wavefront adds
+// the partials of workgroups l, l + 64, l + 128, ... in turn (eight loads in
+// flight), then the fixed shuffle tree adds the 64 lane sums.  Wavefront q
+// sums the values q, q + 16, ...
+__device__ void grid_sum(const double* part, int stride, int nv, double* out, double* /*scratch*/) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, NWv = blockDim.x >> 6, W = gridDim.x;
+  for (int v = wave; v < nv; v += NWv) {
+    double s = 0.0;
+    for (int b0 = lane; b0 < W; b0 += 8 * 64) {
       double p[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) p[u] = ldc(part + (size_t)(b + u * tpv) * stride + v);
+      for (int u = 0; u < 8; ++u)
+        if (b0 + 64 * u < W) p[u] = ldc(part + (size_t)(b0 + 64 * u) * stride + v);
 #pragma unroll
-      for (int u = 0; u < 8; ++u) s += p[u];
+      for (int u = 0; u < 8; ++u)
+        if (b0 + 64 * u < W) s += p[u];
     }
-    for (; b < W; b += tpv) s += ldc(part + (size_t)b * stride + v);
-  }
-  const int width = tpv < 64 ? tpv : 64;
-  for (int off = width >> 1; off > 0; off >>= 1) s += __shfl_down(s, off, width);
-  if (tpv <= 64) {
-    if (v < nv && j == 0) out[v] = s;
-  } else {
-    // tpv / 64 wavefronts per value: their lane-0 subtotals in wave order
-    const int lane = t & 63, wave = t >> 6;
-    if (lane == 0) scratch[wave] = s;
-    __syncthreads();
-    if (v < nv && j == 0) {
-      double u = 0.0;
-      for (int q = 0; q < tpv / 64; ++q) u += scratch[wave + q];
-      out[v] = u;
-    }
+    s = wave_sum(s);
+    if (lane == 0) out[v] = s;
   }
   __syncthreads();
 }
@@ -342,46 +349,35 @@ __device__ __forceinline__ void tag_store_double(__amdgpu_buffer_rsrc_t r, unsig
   tag_store(r, slot, tag, (unsigned)u, (unsigned)(u >> 32));
 }
 
-// grid_sum over tagged partials (slot base + w stride + v of workgroup w, tag
-// `tag`): the same order of additions; each load is repeated until its slot
-// carries the tag.  false when a wait timed out or another workgroup aborted.
-__device__ bool grid_sum_tagged(__amdgpu_buffer_rsrc_t rp, unsigned base, int stride, int nv, unsigned tag,
-                                double* out, double* scratch, int* abort_flag) {
-  if (nv <= 0) return true;
-  int tpv = 1;
-  while (tpv * 2 * nv <= (int)blockDim.x && tpv < (int)gridDim.x) tpv *= 2;
-  const int t = threadIdx.x, v = t / tpv, j = t - v * tpv;
-  double s = 0.0;
-  if (v < nv) {
-    const int W = gridDim.x;
-    int b = j;
-    for (; b + 7 * tpv < W; b += 8 * tpv) {
+// grid_sum over tagged partials (slot pbase + w stride + v of workgroup w, tag
+// `tag`), in two stages so that no workgroup reads every partial: value v is
+// summed once, in the order of grid_sum, by one wavefront of workgroup v mod W,
+// which publishes the total in slot tbase + v; then every workgroup reads the
+// nv totals into out.  Each load is repeated until its slot carries the tag.
+// The values of a step are summed before any workgroup can publish partials
+// of a later step into the same slots (it needs every total of the step in
+// between, whose summing workgroups finish this step's sums first).  false
+// when a wait timed out or another workgroup aborted.
+__device__ bool grid_sum_tagged(__amdgpu_buffer_rsrc_t rp, unsigned pbase, unsigned tbase, int stride, int nv,
+                                unsigned tag, double* out, int* abort_flag) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, NWv = blockDim.x >> 6, W = gridDim.x;
+  for (int v = (int)blockIdx.x + W * wave; v < nv; v += W * NWv) {
+    double s = 0.0;
+    for (int b0 = lane; b0 < W; b0 += 8 * 64) {
       tag_u32x4 p[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) p[u] = tag_load(rp, base + (unsigned)((b + u * tpv) * stride + v));
+      for (int u = 0; u < 8; ++u)
+        if (b0 + 64 * u < W) p[u] = tag_load(rp, pbase + (unsigned)((b0 + 64 * u) * stride + v));
 #pragma unroll
       for (int u = 0; u < 8; ++u)
-        s += tag_double(tag_wait(rp, base + (unsigned)((b + u * tpv) * stride + v), tag, p[u], abort_flag));
+        if (b0 + 64 * u < W)
+          s += tag_double(tag_wait(rp, pbase + (unsigned)((b0 + 64 * u) * stride + v), tag, p[u], abort_flag));
     }
-    for (; b < W; b += tpv) {
-      const unsigned slot = base + (unsigned)(b * stride + v);
-      s += tag_double(tag_wait(rp, slot, tag, tag_load(rp, slot), abort_flag));
-    }
+    s = wave_sum(s);
+    if (lane == 0) tag_store_double(rp, tbase + (unsigned)v, tag, s);
   }
-  const int width = tpv < 64 ? tpv : 64;
-  for (int off = width >> 1; off > 0; off >>= 1) s += __shfl_down(s, off, width);
-  if (tpv <= 64) {
-    if (v < nv && j == 0) out[v] = s;
-  } else {
-    const int lane = t & 63, wave = t >> 6;
-    if (lane == 0) scratch[wave] = s;
-    __syncthreads();
-    if (v < nv && j == 0) {
-      double u = 0.0;
-      for (int q = 0; q < tpv / 64; ++q) u += scratch[wave + q];
-      out[v] = u;
-    }
-  }
+  for (int v = threadIdx.x; v < nv; v += blockDim.x)
+    out[v] = tag_double(tag_wait(rp, tbase + (unsigned)v, tag, tag_load(rp, tbase + (unsigned)v), abort_flag));
   __syncthreads();
   return __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
 }
@@ -445,53 +441,81 @@ struct PArgs {
   int sbytes;   // one-site kernel: LDS bytes before the Krylov basis
   int pl;       // one-site kernel: hop matrix column rounds staged in LDS
   int res_off;  // one-site kernel: LDS byte offset of the even site's resident hop blocks (-1: none)
+  int res_ms;   // column stride (elements) of the resident copy: padded so that the eight columns
+                // a wavefront reads at once fall into different LDS banks
   void* tags;   // one-site kernel, FP32 vectors: tagged slots, t [V][n], then q [V][n], then the
                 // partial sums [2][W][stride] (nullptr: flags and barriers instead)
   unsigned tag_bytes;
 };
 
-// largest power of two below G (0 for G = 1): first step of the tree that adds
-// the G column-group partials
-__device__ __forceinline__ int tree_top(int G) {
-  int h = 1;
-  while (2 * h < G) h *= 2;
-  return G > 1 ? h : 0;
+// Thread layout of the site matrix-vector products (n rows, R2 = n / 2 row
+// pairs): a wavefront holds 8 row pairs (lane / 8) x 8 column lanes
+// (lane % 8); wavefront w takes row block w % NRB and column wave w / NRB, so
+// the column groups are G = 8 CW and a thread owns columns cg, cg + G, ... of
+// rows 2 rp, 2 rp + 1.  The 8 column lanes of a row pair are added inside the
+// wavefront, the CW column waves through LDS after one barrier.
+__host__ __device__ constexpr int mv_row_blocks(int n) { return (n / 2 + 7) / 8; }
+__host__ __device__ constexpr int mv_col_waves(int n) { return kPWaves / mv_row_blocks(n); }
+
+struct MvLayout {
+  int rp, cg, cw, G, CW;
+  bool active;  // the wavefront takes part (wave-uniform)
+  bool rows;    // the row pair exists
+  bool out;     // the thread returns the result of its row pair
+};
+__device__ __forceinline__ MvLayout mv_layout(int n, int tid) {
+  const int NRB = mv_row_blocks(n), wave = tid >> 6, lane = tid & 63;
+  MvLayout L;
+  L.CW = mv_col_waves(n);
+  L.G = 8 * L.CW;
+  L.cw = wave / NRB;
+  L.rp = (wave - L.cw * NRB) * 8 + (lane >> 3);
+  L.cg = L.cw * 8 + (lane & 7);
+  L.active = L.cw < L.CW;
+  L.rows = L.rp < (n >> 1);
+  L.out = L.active && L.rows && L.cw == 0 && (lane & 7) == 0;
+  return L;
 }
 
-// Rows of M v for one site (M: n x ncols column-major, v in LDS): lanes with
-// column group 0 return rows 2rp, 2rp + 1; every lane of the block must call.
+// Rows of M v for one site (M: n x ncols, column col at M + col * ms; v in
+// LDS): true in the threads that hold rows 2 L.rp, 2 L.rp + 1 (o0, o1); every
+// thread of the block must call.  part: CW n complex of LDS.
 template <typename C, typename V2>
-__device__ __forceinline__ void site_matvec(const V2* M, const cpx<C>* v, int n, int ncols, int G, cpx<C>* part,
+__device__ __forceinline__ bool site_matvec(const V2* M, int ms, const cpx<C>* v, int n, int ncols, cpx<C>* part,
                                             cpx<C>& o0, cpx<C>& o1) {
-  const int R2 = n >> 1;
-  const int g = threadIdx.x / R2, rp = threadIdx.x - g * R2;
-  if (g < G) {
+  const MvLayout L = mv_layout(n, threadIdx.x);
+  if (L.active) {
     cpx<C> a0 = mk((C)0, (C)0), a1 = a0;
-    const V2* m = M + 2 * rp;
+    if (L.rows) {
+      const V2* m = M + 2 * L.rp;
 #pragma unroll 8
-    for (int col = g; col < ncols; col += G) {
-      cpx<C> e0, e1;
-      ld2(m + (size_t)col * n, e0, e1);
-      const cpx<C> x = v[col];
-      cfma(a0, e0, x);
-      cfma(a1, e1, x);
+      for (int col = L.cg; col < ncols; col += L.G) {
+        cpx<C> e0, e1;
+        ld2(m + (size_t)col * ms, e0, e1);
+        const cpx<C> x = v[col];
+        cfma(a0, e0, x);
+        cfma(a1, e1, x);
+      }
     }
-    part[g * n + 2 * rp] = a0;
-    part[g * n + 2 * rp + 1] = a1;
-  }
-  for (int h = tree_top(G); h > 0; h >>= 1) {
-    __syncthreads();
-    if (g < h && g + h < G) {
-      part[g * n + 2 * rp] = part[g * n + 2 * rp] + part[(g + h) * n + 2 * rp];
-      part[g * n + 2 * rp + 1] = part[g * n + 2 * rp + 1] + part[(g + h) * n + 2 * rp + 1];
+    a0 = mk(sum8(a0.r), sum8(a0.i));
+    a1 = mk(sum8(a1.r), sum8(a1.i));
+    if ((threadIdx.x & 7) == 0 && L.rows) {
+      part[L.cw * n + 2 * L.rp] = a0;
+      part[L.cw * n + 2 * L.rp + 1] = a1;
     }
   }
+  __syncthreads();
   o0 = mk((C)0, (C)0);
   o1 = o0;
-  if (g == 0) {
-    o0 = part[2 * rp];
-    o1 = part[2 * rp + 1];
+  if (L.out) {
+    o0 = part[2 * L.rp];
+    o1 = part[2 * L.rp + 1];
+    for (int q = 1; q < L.CW; ++q) {
+      o0 = o0 + part[q * n + 2 * L.rp];
+      o1 = o1 + part[q * n + 2 * L.rp + 1];
+    }
   }
+  return L.out;
 }
 
 // out(c) = xd(c) + coeff * sum_d Yt_d(c) in(nb(c, d))     (xd may be null)
@@ -523,12 +547,11 @@ __device__ void site_hop(const PArgs& a, int c, const void* in_, const void* xd_
   }
   __syncthreads();
   cpx<C> o[2];
-  site_matvec<C, MT>(reinterpret_cast<const MT*>(a.Yt) + (size_t)c * 8 * n * n, vin, n, 8 * n, a.G, part, o[0],
-                     o[1]);
-  const int R2 = n >> 1;
-  const int g = threadIdx.x / R2, rp = threadIdx.x - g * R2;
+  const bool own = site_matvec<C, MT>(reinterpret_cast<const MT*>(a.Yt) + (size_t)c * 8 * n * n, n, vin, n, 8 * n,
+                                      part, o[0], o[1]);
+  const int rp = mv_layout(n, threadIdx.x).rp;
   cpx<C> s[2];
-  if (g == 0) {
+  if (own) {
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       const int i = 2 * rp + k;
@@ -540,7 +563,7 @@ __device__ void site_hop(const PArgs& a, int c, const void* in_, const void* xd_
     }
   }
   if (!Xl_) {
-    if (g == 0) {
+    if (own) {
 #pragma unroll
       for (int k = 0; k < 2; ++k) {
         V2 w;
@@ -553,13 +576,13 @@ __device__ void site_hop(const PArgs& a, int c, const void* in_, const void* xd_
   }
   // local matrix on the hop result: stage it in vin (rounded to storage precision)
   __syncthreads();
-  if (g == 0) {
+  if (own) {
 #pragma unroll
     for (int k = 0; k < 2; ++k) vin[2 * rp + k] = mk((C)(S)s[k].r, (C)(S)s[k].i);
   }
   __syncthreads();
-  site_matvec<C, V2>(reinterpret_cast<const V2*>(Xl_) + (size_t)c * n * n, vin, n, n, a.G, part, o[0], o[1]);
-  if (g == 0) {
+  site_matvec<C, V2>(reinterpret_cast<const V2*>(Xl_) + (size_t)c * n * n, n, vin, n, n, part, o[0], o[1]);
+  if (own) {
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       V2 w;
@@ -586,10 +609,10 @@ __device__ void site_local(const PArgs& a, int c, const void* in_, const void* X
   }
   __syncthreads();
   cpx<C> o[2];
-  site_matvec<C, V2>(reinterpret_cast<const V2*>(Xl_) + (size_t)c * n * n, vin, n, n, a.G, part, o[0], o[1]);
-  const int R2 = n >> 1;
-  const int g = threadIdx.x / R2, rp = threadIdx.x - g * R2;
-  if (g == 0) {
+  const bool own = site_matvec<C, V2>(reinterpret_cast<const V2*>(Xl_) + (size_t)c * n * n, n, vin, n, n, part, o[0],
+                                      o[1]);
+  const int rp = mv_layout(n, threadIdx.x).rp;
+  if (own) {
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       V2 w;
@@ -606,7 +629,7 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr(PArgs a) {
   using V2 = typename Vec2<S>::T;
   extern __shared__ char smem[];  // hop operands, or the slice sums of the Gram-Schmidt step
   cpx<C>* vin = reinterpret_cast<cpx<C>*>(smem);  // 8n
-  cpx<C>* hp = vin + 8 * a.n;                     // G * n
+  cpx<C>* hp = vin + 8 * a.n;                     // CW * n (column-wave partials)
   __shared__ double sv[2 * kPMaxRestart + 8];      // grid sums
   __shared__ double sqq[kPMaxRestart];             // ||q_j||^2
   __shared__ double sh[4 * kPWaves];
@@ -940,22 +963,24 @@ __device__ void hop1(const PArgs& a, int c, int nb, const typename Vec2<S>::T* i
   using V2 = typename Vec2<S>::T;
   constexpr int NCH = sizeof(S) == 8 ? 2 : 1;  // 16-byte pieces of a thread's two entries of a column
   constexpr bool kStage = sizeof(MT) == sizeof(V2);  // LDS staging exists for blocks in the vector type only
-  const int n = a.n, G = a.G, R2 = n >> 1, ncols = 8 * n, PL = (kStage && !Mres) ? a.pl : 0;
+  const int n = a.n, ncols = 8 * n, PL = (kStage && !Mres) ? a.pl : 0;
   // the thread index passes through an empty asm, so that the addresses derived
   // from it are formed here and not kept live across the whole solve (register
   // pressure: the hop is inlined at seven call sites)
   int tid = threadIdx.x;
   asm volatile("" : "+v"(tid));
-  const int g = tid / R2, rp = tid - g * R2;
-  const int lane = tid & 63, wv = tid >> 6, NW = (G * R2 + 63) >> 6;
-  const MT* M = (Mres ? Mres : reinterpret_cast<const MT*>(a.Yt) + (size_t)c * 8 * n * n) + 2 * rp;
+  const MvLayout L = mv_layout(n, tid);
+  const int G = L.G, lane = tid & 63, wv = tid >> 6, NW = mv_row_blocks(n) * L.CW;
+  const bool mine = L.active && L.rows;  // the thread has matrix entries
+  const int ms = Mres ? a.res_ms : n;    // column stride of the blocks
+  const MT* M = (Mres ? Mres : reinterpret_cast<const MT*>(a.Yt) + (size_t)c * 8 * n * n) + 2 * L.rp;
   __syncthreads();  // the previous task is done with vin, part and the prefetch area
-  if (kStage && g < G) {
+  if (kStage && mine) {
     // piece ch of column round u of wavefront wv: 1 KiB at pre + ((u NCH + ch) NW + wv) KiB, lane order
     for (int u = 0; u < PL; ++u) {
-      const int col = g + u * G;
+      const int col = L.cg + u * G;
       if (col < ncols) {
-        const char* src = reinterpret_cast<const char*>(M + (size_t)col * n);
+        const char* src = reinterpret_cast<const char*>(M + (size_t)col * ms);
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch)
           __builtin_amdgcn_global_load_lds(
@@ -969,11 +994,11 @@ __device__ void hop1(const PArgs& a, int c, int nb, const typename Vec2<S>::T* i
   constexpr int PR = sizeof(S) == 8 ? 1 : 4;
   const int PRr = Mres ? 0 : PR;
   cpx<C> r0[PR], r1[PR];
-  if (g < G) {
+  if (mine) {
 #pragma unroll
     for (int u = 0; u < PR; ++u) {
-      const int col = g + (PL + u) * G;
-      if (u < PRr && col < ncols) ld2(M + (size_t)col * n, r0[u], r1[u]);
+      const int col = L.cg + (PL + u) * G;
+      if (u < PRr && col < ncols) ld2(M + (size_t)col * ms, r0[u], r1[u]);
     }
   }
   if (tid < ncols) {
@@ -994,60 +1019,67 @@ __device__ void hop1(const PArgs& a, int c, int nb, const typename Vec2<S>::T* i
     }
   }
   __syncthreads();
-  if (g < G) {
+  if (L.active) {
     cpx<C> a0 = mk((C)0, (C)0), a1 = a0;
-    // this thread's own pieces: complete once its wavefront's loads have returned
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    for (int u = 0; u < PL; ++u) {
-      const int col = g + u * G;
-      if (col < ncols) {
-        cpx<C> e0, e1;
-        const V2* q = reinterpret_cast<const V2*>(pre + ((size_t)(u * NCH * NW + wv) << 10) + 16 * lane);
-        if (NCH == 1) {
-          ld2(q, e0, e1);
-        } else {
-          const V2* q1 = reinterpret_cast<const V2*>(pre + ((size_t)((u * NCH + 1) * NW + wv) << 10) + 16 * lane);
-          e0 = mk((C)q[0].x, (C)q[0].y);
-          e1 = mk((C)q1[0].x, (C)q1[0].y);
+    if (L.rows) {
+      // this thread's own staged pieces: complete once its wavefront's loads have returned
+      if (PL > 0) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      for (int u = 0; u < PL; ++u) {
+        const int col = L.cg + u * G;
+        if (col < ncols) {
+          cpx<C> e0, e1;
+          const V2* q = reinterpret_cast<const V2*>(pre + ((size_t)(u * NCH * NW + wv) << 10) + 16 * lane);
+          if (NCH == 1) {
+            ld2(q, e0, e1);
+          } else {
+            const V2* q1 = reinterpret_cast<const V2*>(pre + ((size_t)((u * NCH + 1) * NW + wv) << 10) + 16 * lane);
+            e0 = mk((C)q[0].x, (C)q[0].y);
+            e1 = mk((C)q1[0].x, (C)q1[0].y);
+          }
+          const cpx<C> x = vin[col];
+          cfma(a0, e0, x);
+          cfma(a1, e1, x);
         }
+      }
+#pragma unroll
+      for (int u = 0; u < PR; ++u) {
+        const int col = L.cg + (PL + u) * G;
+        if (u < PRr && col < ncols) {
+          const cpx<C> x = vin[col];
+          cfma(a0, r0[u], x);
+          cfma(a1, r1[u], x);
+        }
+      }
+#pragma unroll 8
+      for (int col = L.cg + (PL + PRr) * G; col < ncols; col += G) {
+        cpx<C> e0, e1;
+        ld2(M + (size_t)col * ms, e0, e1);
         const cpx<C> x = vin[col];
         cfma(a0, e0, x);
         cfma(a1, e1, x);
       }
     }
-#pragma unroll
-    for (int u = 0; u < PR; ++u) {
-      const int col = g + (PL + u) * G;
-      if (u < PRr && col < ncols) {
-        const cpx<C> x = vin[col];
-        cfma(a0, r0[u], x);
-        cfma(a1, r1[u], x);
-      }
-    }
-#pragma unroll 8
-    for (int col = g + (PL + PRr) * G; col < ncols; col += G) {
-      cpx<C> e0, e1;
-      ld2(M + (size_t)col * n, e0, e1);
-      const cpx<C> x = vin[col];
-      cfma(a0, e0, x);
-      cfma(a1, e1, x);
-    }
-    part[g * n + 2 * rp] = a0;
-    part[g * n + 2 * rp + 1] = a1;
-  }
-  for (int h = tree_top(G); h > 0; h >>= 1) {
-    __syncthreads();
-    if (g < h && g + h < G) {
-      part[g * n + 2 * rp] = part[g * n + 2 * rp] + part[(g + h) * n + 2 * rp];
-      part[g * n + 2 * rp + 1] = part[g * n + 2 * rp + 1] + part[(g + h) * n + 2 * rp + 1];
+    a0 = mk(sum8(a0.r), sum8(a0.i));
+    a1 = mk(sum8(a1.r), sum8(a1.i));
+    if ((lane & 7) == 0 && L.rows) {
+      part[L.cw * n + 2 * L.rp] = a0;
+      part[L.cw * n + 2 * L.rp + 1] = a1;
     }
   }
+  __syncthreads();
+  const int rp = L.rp;
   cpx<C> s[2];
-  if (g == 0) {
+  if (L.out) {
+    cpx<C> o0 = part[2 * rp], o1 = part[2 * rp + 1];
+    for (int q = 1; q < L.CW; ++q) {
+      o0 = o0 + part[q * n + 2 * rp];
+      o1 = o1 + part[q * n + 2 * rp + 1];
+    }
+    s[0] = (C)coeff * o0;
+    s[1] = (C)coeff * o1;
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       const int i = 2 * rp + k;
-      s[k] = (C)coeff * part[i];
       if (xdl) s[k] = s[k] + mk((C)xdl[i].x, (C)xdl[i].y);
       if (xdg) {
         const V2 w = ldc(xdg + (size_t)c * n + i);
@@ -1058,14 +1090,14 @@ __device__ void hop1(const PArgs& a, int c, int nb, const typename Vec2<S>::T* i
   if (Xl) {
     // local matrix on the hop result, staged in vin (rounded to storage precision)
     __syncthreads();
-    if (g == 0) {
+    if (L.out) {
 #pragma unroll
       for (int k = 0; k < 2; ++k) vin[2 * rp + k] = mk((C)(S)s[k].r, (C)(S)s[k].i);
     }
     __syncthreads();
-    site_matvec<C, V2>(reinterpret_cast<const V2*>(Xl) + (size_t)c * n * n, vin, n, n, G, part, s[0], s[1]);
+    site_matvec<C, V2>(reinterpret_cast<const V2*>(Xl) + (size_t)c * n * n, n, vin, n, n, part, s[0], s[1]);
   }
-  if (g == 0) {
+  if (L.out) {
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       V2 w;
@@ -1092,8 +1124,8 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
   extern __shared__ char smem[];  // hop operands or Gram-Schmidt slice sums, then basis and copies
   const int n = a.n, Vh = a.Vh, R = a.restart, w = blockIdx.x, W = gridDim.x, tid = threadIdx.x;
   cpx<C>* vin = reinterpret_cast<cpx<C>*>(smem);  // 8n
-  cpx<C>* hp = vin + 8 * n;                       // G * n
-  char* pre = reinterpret_cast<char*>(hp + (size_t)a.G * n);  // hop matrix columns (a.pl rounds)
+  cpx<C>* hp = vin + 8 * n;                       // CW * n (column-wave partials)
+  char* pre = reinterpret_cast<char*>(hp + (size_t)mv_col_waves(n) * n);  // hop matrix columns (a.pl rounds)
   V2* Qs = reinterpret_cast<V2*>(smem + a.sbytes);  // [R][n] q_j (even site)
   V2* Zs = Qs + (size_t)R * n;                      // [R][n] z_j (even site)
   V2* Ts = Zs + (size_t)R * n;                      // [R][n] T_j (odd site)
@@ -1107,7 +1139,6 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
   __shared__ double sh[4 * kPWaves];
   __shared__ double salpha[3];
   __shared__ cpx<double> scj[kPMaxRestart];  // Gram-Schmidt coefficients of the step
-  __shared__ double sterm[kPMaxRestart];
   const V2* b = reinterpret_cast<const V2*>(a.b);
   V2* y = reinterpret_cast<V2*>(a.y);
   V2* r = reinterpret_cast<V2*>(a.r);
@@ -1133,11 +1164,23 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
   // the even site's hop blocks, resident in LDS for the whole solve when they fit
   const MT* Mres = nullptr;
   if (a.res_off >= 0) {
-    uint4* dst = reinterpret_cast<uint4*>(smem + a.res_off);
-    const uint4* src = reinterpret_cast<const uint4*>(reinterpret_cast<const MT*>(a.Yt) + (size_t)w * 8 * n * n);
-    const int n16 = (int)((size_t)8 * n * n * sizeof(MT) / 16);
-    for (int i = tid; i < n16; i += kPT) dst[i] = src[i];
-    Mres = reinterpret_cast<const MT*>(dst);
+    MT* dst = reinterpret_cast<MT*>(smem + a.res_off);
+    const MT* src = reinterpret_cast<const MT*>(a.Yt) + (size_t)w * 8 * n * n;
+    const int ms = a.res_ms;
+    if ((n * sizeof(MT)) % 16 == 0 && (ms * sizeof(MT)) % 16 == 0) {
+      // 16-byte pieces: u16 per column
+      const int u16 = (int)(n * sizeof(MT) / 16), d16 = (int)(ms * sizeof(MT) / 16);
+      for (int i = tid; i < 8 * n * u16; i += kPT) {
+        const int col = i / u16, j = i - col * u16;
+        reinterpret_cast<uint4*>(dst)[(size_t)col * d16 + j] = reinterpret_cast<const uint4*>(src)[i];
+      }
+    } else {
+      for (int i = tid; i < 8 * n * n; i += kPT) {
+        const int col = i / n, j = i - col * n;
+        dst[(size_t)col * ms + j] = src[i];
+      }
+    }
+    Mres = dst;
     __syncthreads();
   }
   // epochs continue from what the previous launch left (the same in every line)
@@ -1150,7 +1193,8 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
   // no barrier; versions start above anything an earlier launch left
   const bool tagged = sizeof(S) == 4 && a.tags != nullptr;
   unsigned tver = epoch, qver = epoch;
-  const unsigned pslot = (unsigned)(4 * Vh * n);  // first partial-sum slot
+  const unsigned pslot = (unsigned)(4 * Vh * n);              // first partial-sum slot
+  const unsigned tslot = pslot + (unsigned)(2 * W * a.stride);  // first total slot
   const __amdgpu_buffer_rsrc_t rtag = tag_rsrc(a.tags, a.tag_bytes);
   auto sync_sum = [&](int nv) -> bool {
     if (!grid_barrier(a.bar, abort_flag, ++epoch)) return false;
@@ -1255,8 +1299,8 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
         hop1<S, MT>(a, Vh + w, nbO, qraw, nullptr, nullptr, 1.0, nullptr, nullptr, Ts + (size_t)k * n, vin, hp, pre,
                     nullptr, 1, qver);
         __syncthreads();
-        if (!grid_sum_tagged(rtag, pslot + (unsigned)(cur * W * a.stride), a.stride, 2 * k + 4, ep, sv, sh,
-                             abort_flag))
+        if (!grid_sum_tagged(rtag, pslot + (unsigned)(cur * W * a.stride), tslot + (unsigned)(cur * a.stride),
+                             a.stride, 2 * k + 4, ep, sv, abort_flag))
           return;
       } else {
         barrier_arrive(a.bar, ++epoch);
@@ -1275,21 +1319,24 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
         }
         if (!a.fixed && sqrt(rn2) <= target) break;
       }
-      // per j < k in parallel: c_j = <q_j, q> / ||q_j||^2 and |<q_j, q>|^2 / ||q_j||^2
-      // (the same divisions as the strided kernel, done once instead of per thread)
-      if (tid < k) {
-        const double d = sqq[tid];
-        scj[tid] = d > 0.0 ? mk(sv[2 * tid] / d, sv[2 * tid + 1] / d) : mk(0.0, 0.0);
-        sterm[tid] = d > 0.0 ? (sv[2 * tid] * sv[2 * tid] + sv[2 * tid + 1] * sv[2 * tid + 1]) / d : 0.0;
-      }
-      __syncthreads();
-      if (tid == 0) {
+      // wavefront 0, lane j < k: c_j = <q_j, q> / ||q_j||^2 and |<q_j, q>|^2 / ||q_j||^2
+      // (the same divisions as the strided kernel, done once instead of per
+      // thread); then ||q_k||^2 = ||q||^2 - those terms, subtracted in order of j
+      // from the lanes' registers (a zero term for ||q_j||^2 <= 0 leaves it as is)
+      if (tid < 64) {
+        double st = 0.0;
+        if (tid < k) {
+          const double d = sqq[tid];
+          scj[tid] = d > 0.0 ? mk(sv[2 * tid] / d, sv[2 * tid + 1] / d) : mk(0.0, 0.0);
+          st = d > 0.0 ? (sv[2 * tid] * sv[2 * tid] + sv[2 * tid + 1] * sv[2 * tid + 1]) / d : 0.0;
+        }
         double qq = sv[2 * k];
-        for (int j = 0; j < k; ++j)
-          if (sqq[j] > 0.0) qq -= sterm[j];
-        salpha[2] = qq;
-        salpha[0] = qq > 0.0 ? sv[2 * k + 1] / qq : 0.0;
-        salpha[1] = qq > 0.0 ? sv[2 * k + 2] / qq : 0.0;
+        for (int j = 0; j < k; ++j) qq -= rdlane(st, j);
+        if (tid == 0) {
+          salpha[2] = qq;
+          salpha[0] = qq > 0.0 ? sv[2 * k + 1] / qq : 0.0;
+          salpha[1] = qq > 0.0 ? sv[2 * k + 2] / qq : 0.0;
+        }
       }
       __syncthreads();
       const double qq = salpha[2];
@@ -1328,9 +1375,7 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
         const cpx<double> qs = mk((double)(S)q.r, (double)(S)q.i), zs = mk((double)(S)z.r, (double)(S)z.i);
         Qs[(size_t)k * n + tid] = tov2<V2>(qs);
         Zs[(size_t)k * n + tid] = tov2<V2>(zs);
-        const V2 yv = tov2<V2>(cvt(ym[tid]) + cmul(alpha, zs));
-        ym[tid] = yv;
-        stc(y + eo + tid, yv);
+        ym[tid] = tov2<V2>(cvt(ym[tid]) + cmul(alpha, zs));  // to global memory at the end of the cycle
         const V2 rv = tov2<V2>(axpy_round<S>(cvt(rm[tid]), alpha, qs));
         rm[tid] = rv;
         if (k + 1 < R) Zs[(size_t)(k + 1) * n + tid] = rv;
@@ -1374,6 +1419,7 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
       if (!tagged && !neighbour_wait(a.lflags, abort_flag, nbw, ++lep)) return;
     }
     // y and t complete everywhere
+    if (tid < n) stc(y + eo + tid, ym[tid]);
     if (!sync_sum(0)) return;
     if (status || a.fixed) break;
     // true residual r = b_r - D_r y at the end of the cycle
@@ -1416,17 +1462,21 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
 size_t coarse_gcr_persistent_part_doubles() { return 2 * kPMaxRestart + 8; }
 
 size_t coarse_gcr_persistent_tag_bytes(int n, int Vh, int grid) {
-  // t and q over all sites, then two buffers of partial sums per workgroup
-  return ((size_t)4 * Vh * n + (size_t)2 * grid * coarse_gcr_persistent_part_doubles()) * 16;
+  // t and q over all sites, then two buffers of partial sums per workgroup and
+  // two of totals
+  return ((size_t)4 * Vh * n + (size_t)2 * (grid + 1) * coarse_gcr_persistent_part_doubles()) * 16;
 }
 
-// column groups of the hop: a power of two (at most 64) with G * n / 2 <= kPT (a
-// power of two measured faster than using every thread, e.g. 32 rather than 42
-// groups for n = 48)
-static int persist_groups(int n) {
-  int G = 1;
-  while (G < 64 && 2 * G * (n / 2) <= kPT) G *= 2;
-  return G;
+// column groups of the site matrix-vector products (eight per column wave)
+static int persist_groups(int n) { return 8 * mv_col_waves(n); }
+
+// column stride of the resident hop blocks: the first at least n whose byte
+// length is 16 modulo 32, so that the eight columns a wavefront reads at once
+// (at consecutive column indices) start in different LDS banks
+static int resident_stride(int n, size_t elem) {
+  int ms = n;
+  while ((ms * elem) % 32 != 16) ++ms;
+  return ms;
 }
 
 int coarse_gcr_persistent_grid(int prec, int n, int Vh) {
@@ -1437,7 +1487,8 @@ int coarse_gcr_persistent_grid(int prec, int n, int Vh) {
   if (!coop || n % 2 || n > 256 || Vh <= 0) return 0;
   const size_t cb = prec == WCMG_F64 ? 16 : 8;
   const int G = persist_groups(n);
-  const size_t shm = std::max((size_t)(8 * n + G * n) * cb, (size_t)2 * kPT * 16);
+  const size_t shm = std::max((size_t)(8 * n + mv_col_waves(n) * n) * cb, (size_t)2 * kPT * 16);
+  (void)G;
   int per = 0;
   if (prec == WCMG_F64)
     HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_coarse_gcr<double, double2>, kPT, shm));
@@ -1497,7 +1548,7 @@ void launch_coarse_gcr_persistent(int prec, const CoarseGcrArgs& g, hipStream_t 
   const int G = persist_groups(n);
   a.G = G;
   const size_t cb = prec == WCMG_F64 ? 16 : 8;
-  const size_t shm = std::max((size_t)(8 * n + G * n) * cb, (size_t)2 * kPT * 16);
+  const size_t shm = std::max((size_t)(8 * n + mv_col_waves(n) * n) * cb, (size_t)2 * kPT * 16);
   a.lflags = reinterpret_cast<unsigned*>(reinterpret_cast<char*>(g.bar) + kPersistLocalOffset);
   a.sbytes = (int)shm;
   void* args[] = {&a};
@@ -1507,14 +1558,15 @@ void launch_coarse_gcr_persistent(int prec, const CoarseGcrArgs& g, hipStream_t 
   // rounds; instead the even site's 8 n^2 blocks stay in LDS for the whole solve
   // when they fit.
   const size_t basis = (size_t)(3 * g.restart + 5) * n * cb;
-  const size_t hopb = (size_t)(8 * n + G * n) * cb;
-  const size_t round = (prec == WCMG_F64 ? 2 : 1) * (size_t)((G * (n / 2) + 63) / 64) * 1024;
+  const size_t hopb = (size_t)(8 * n + mv_col_waves(n) * n) * cb;
+  const size_t round = (prec == WCMG_F64 ? 2 : 1) * (size_t)(mv_row_blocks(n) * mv_col_waves(n)) * 1024;
   const size_t lds_cap = 160 * 1024 - 4096;  // minus the kernel's static LDS, with margin
   const int rounds = (8 * n + G - 1) / G;
   int pl = 0;
   if (!g.mat16 && lds_cap > basis + hopb) pl = (int)std::min<size_t>(rounds, (lds_cap - basis - hopb) / round);
   const size_t sb = std::max(hopb + (size_t)pl * round, (size_t)2 * kPT * 16);
-  const size_t res = g.mat16 ? (size_t)8 * n * n * 4 : 0;
+  const int ms = resident_stride(n, 4);
+  const size_t res = g.mat16 ? (size_t)8 * n * ms * 4 : 0;
   const bool resident = g.mat16 && sb + basis + res <= lds_cap;
   const size_t site_shm = sb + basis + (resident ? res : 0);
   const void* ks = prec == WCMG_F64 ? reinterpret_cast<const void*>(k_coarse_gcr_site<double, double2>)
@@ -1523,7 +1575,10 @@ void launch_coarse_gcr_persistent(int prec, const CoarseGcrArgs& g, hipStream_t 
   if (!g.general && g.grid == g.Vh && 8 * n <= kPT && site_shm <= lds_cap && kernel_fits(ks, site_shm)) {
     a.sbytes = (int)sb;
     a.pl = pl;
-    if (resident) a.res_off = (int)(sb + basis);
+    if (resident) {
+      a.res_off = (int)(sb + basis);
+      a.res_ms = ms;
+    }
     // FP32 vectors: t, q and the step sums in tagged slots (no flag waits or barriers per step)
     if (prec == WCMG_F32 && g.tags && g.tag_bytes >= coarse_gcr_persistent_tag_bytes(n, g.Vh, g.grid) &&
         g.tag_bytes < ((size_t)1 << 31)) {
