@@ -1001,21 +1001,26 @@ __device__ void hop1(const PArgs& a, int c, int nb, const typename Vec2<S>::T* i
       if (u < PRr && col < ncols) ld2(M + (size_t)col * ms, r0[u], r1[u]);
     }
   }
-  if (tid < ncols) {
+  // the gather runs in the wavefronts just below the last one, which never
+  // stores: a wavefront's wait for its loads also waits for its earlier
+  // coherent stores to complete, and the publishing stores of the solve come
+  // from the last wavefront and the first ones
+  const int gt = tid - max(0, kPT - 64 - ncols);
+  if (gt >= 0 && gt < ncols) {
     if constexpr (sizeof(S) == 4) {
       if (tin >= 0) {
         // tagged input (tin: 0 t, 1 q): each slot is read until it carries tin_tag
         const __amdgpu_buffer_rsrc_t rt = tag_rsrc(a.tags, a.tag_bytes);
-        const unsigned slot = (unsigned)(tin * 2 * a.Vh * n + nb * n + (tid - (tid / n) * n));
+        const unsigned slot = (unsigned)(tin * 2 * a.Vh * n + nb * n + (gt - (gt / n) * n));
         const tag_u32x4 q = tag_wait(rt, slot, tin_tag, tag_load(rt, slot), a.info + 2);
-        vin[tid] = mk((C)__uint_as_float(q.y), (C)__uint_as_float(q.z));
+        vin[gt] = mk((C)__uint_as_float(q.y), (C)__uint_as_float(q.z));
       } else {
-        const V2 v = ldc(in + (size_t)nb * n + (tid - (tid / n) * n));
-        vin[tid] = mk((C)v.x, (C)v.y);
+        const V2 v = ldc(in + (size_t)nb * n + (gt - (gt / n) * n));
+        vin[gt] = mk((C)v.x, (C)v.y);
       }
     } else {
-      const V2 v = ldc(in + (size_t)nb * n + (tid - (tid / n) * n));
-      vin[tid] = mk((C)v.x, (C)v.y);
+      const V2 v = ldc(in + (size_t)nb * n + (gt - (gt / n) * n));
+      vin[gt] = mk((C)v.x, (C)v.y);
     }
   }
   __syncthreads();
@@ -1139,6 +1144,7 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
   __shared__ double sh[4 * kPWaves];
   __shared__ double salpha[3];
   __shared__ cpx<double> scj[kPMaxRestart];  // Gram-Schmidt coefficients of the step
+  __shared__ double spart[2 * kPMaxRestart + 4];  // the step's partial sums, before they are published
   const V2* b = reinterpret_cast<const V2*>(a.b);
   V2* y = reinterpret_cast<V2*>(a.y);
   V2* r = reinterpret_cast<V2*>(a.r);
@@ -1146,11 +1152,14 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
   V2* qraw = reinterpret_cast<V2*>(a.qraw);
   const size_t eo = (size_t)w * n, oo = (size_t)(Vh + w) * n;  // owned even / odd elements
   int* abort_flag = a.info + 2;
-  // neighbours of the owned sites; owners of the odd neighbours of the even site
+  // neighbours of the owned sites (for the gathering threads of hop1);
+  // owners of the odd neighbours of the even site
   int nbE = 0, nbO = 0, nbw = -1, nbq = -1;
-  if (tid < 8 * n) {
-    nbE = a.nbr[(size_t)w * 8 + tid / n];
-    nbO = a.nbr[(size_t)(Vh + w) * 8 + tid / n];
+  const int gt = tid - max(0, kPT - 64 - 8 * n);
+  const int lane = tid & 63, wave = tid >> 6;
+  if (gt >= 0 && gt < 8 * n) {
+    nbE = a.nbr[(size_t)w * 8 + gt / n];
+    nbO = a.nbr[(size_t)(Vh + w) * 8 + gt / n];
   }
   if (tid < 8) {
     nbw = a.nbr[(size_t)w * 8 + tid] - Vh;
@@ -1239,13 +1248,58 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
       // q = D_r z_k = r - Ytilde_eo t on the even site (stored for the odd neighbours);
       // <q_j, q>, ||q||^2, <q, r> and ||r_k||^2
       if (tagged) ++qver;
-      hop1<S, MT>(a, w, nbE, t, rm, nullptr, -1.0, nullptr, qraw, qm, vin, hp, pre, Mres, tagged ? 0 : -1, tver,
-                  tagged ? 1 : -1, qver);
+      hop1<S, MT>(a, w, nbE, t, rm, nullptr, -1.0, nullptr, tagged ? nullptr : qraw, qm, vin, hp, pre, Mres,
+                  tagged ? 0 : -1, tver);
       __syncthreads();
       const unsigned ep = epoch + 1;  // the step's sum
       const unsigned pbase = pslot + (unsigned)((cur * W + w) * a.stride);
-      {
-        const int lane = tid & 63, wave = tid >> 6;
+      if (tagged && n <= 64) {
+        // the last wavefront publishes q and, once the other wavefronts have
+        // left their dot products in LDS, all the step's partial sums
+        if (wave == kPWaves - 1) {
+          if (lane < n)
+            tag_store(rtag, (unsigned)(2 * Vh * n + w * n + lane), qver, __float_as_uint((float)qm[lane].x),
+                      __float_as_uint((float)qm[lane].y));
+          double v[4] = {0.0, 0.0, 0.0, 0.0};
+          if (lane < n) {
+            const cpx<double> qv = cvt(qm[lane]), rr = cvt(rm[lane]);
+            v[0] += qv.r * qv.r + qv.i * qv.i;
+            v[1] += qv.r * rr.r + qv.i * rr.i;
+            v[2] += qv.r * rr.i - qv.i * rr.r;
+            v[3] += rr.r * rr.r + rr.i * rr.i;
+          }
+          wave_sum_n<4>(v);
+          if (lane == 0) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) spart[2 * k + m] = v[m];
+          }
+        } else {
+          for (int j = wave; j < k; j += kPWaves - 1) {
+            const V2* Qj = Qs + (size_t)j * n;
+            double sr = 0.0, si = 0.0;
+            if (lane < n) {
+              const cpx<double> u = cvt(Qj[lane]), qv = cvt(qm[lane]);
+              sr += u.r * qv.r + u.i * qv.i;
+              si += u.r * qv.i - u.i * qv.r;
+            }
+            double p2[2] = {sr, si};
+            wave_sum_n<2>(p2);
+            if (lane == 0) {
+              spart[2 * j] = p2[0];
+              spart[2 * j + 1] = p2[1];
+            }
+          }
+        }
+        __syncthreads();
+        if (wave == kPWaves - 1)
+          for (int l = lane; l < 2 * k + 4; l += 64) tag_store_double(rtag, pbase + l, ep, spart[l]);
+      } else {
+        if (tagged) {
+          // q published by the threads that hold it
+          for (int i = tid; i < n; i += kPT)
+            tag_store(rtag, (unsigned)(2 * Vh * n + w * n + i), qver, __float_as_uint((float)qm[i].x),
+                      __float_as_uint((float)qm[i].y));
+        }
         for (int j = wave; j < k; j += kPWaves) {
           const V2* Qj = Qs + (size_t)j * n;
           double sr = 0.0, si = 0.0;
@@ -1394,21 +1448,22 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
       }
       __syncthreads();
       if (tagged) ++tver;
-      if (tid < n) {
-        cpx<double> tk = cvt(Ts[(size_t)k * n + tid]);
+      // (in the last wavefront, which publishes t)
+      for (int i = tid - (kPT - 64); i >= 0 && i < n; i += 64) {
+        cpx<double> tk = cvt(Ts[(size_t)k * n + i]);
         if (k > 0) {
-          cpx<double> st = acc[tid];
-          for (int u = 1; u < NS; ++u) st = st + acc[u * n + tid];
+          cpx<double> st = acc[i];
+          for (int u = 1; u < NS; ++u) st = st + acc[u * n + i];
           tk = tk - st;
         }
         const cpx<double> tks = mk((double)(S)tk.r, (double)(S)tk.i);
-        Ts[(size_t)k * n + tid] = tov2<V2>(tks);
-        const V2 tv = tov2<V2>(cvt(tm[tid]) - cmul(alpha, tks));
-        tm[tid] = tv;
+        Ts[(size_t)k * n + i] = tov2<V2>(tks);
+        const V2 tv = tov2<V2>(cvt(tm[i]) - cmul(alpha, tks));
+        tm[i] = tv;
         if (tagged)
-          tag_store(rtag, (unsigned)(oo + tid), tver, __float_as_uint((float)tv.x), __float_as_uint((float)tv.y));
+          tag_store(rtag, (unsigned)(oo + i), tver, __float_as_uint((float)tv.x), __float_as_uint((float)tv.y));
         else
-          stc(t + oo + tid, tv);
+          stc(t + oo + i, tv);
       }
       if (tid == 0) sqq[k] = qq;
       ++k;
