@@ -53,7 +53,7 @@ __device__ __forceinline__ const void* rhs_ptr(const void* base, size_t stride, 
   return reinterpret_cast<const char*>(base) + (size_t)r * stride;
 }
 
-template <typename S, typename G, int MU, int NR, bool STREAM>
+template <typename S, typename G, int MU, int NR, bool STREAM, bool PIN = true>
 __device__ __forceinline__ void hop_mu(const DslashArgs& a, int p, int i, const int c[4], int g0, int nr,
                                        cpx<typename Compute<S>::T> (&acc)[NR][12]) {
   using C = typename Compute<S>::T;
@@ -83,7 +83,7 @@ __device__ __forceinline__ void hop_mu(const DslashArgs& a, int p, int i, const 
           for (int k = 0; k < 6; ++k) hu[k] = hs * hu[k];
         }
         accumulate<C, MU, false>(acc[r], hu);
-        pin_acc(acc[r]);
+        if constexpr (PIN) pin_acc(acc[r]);
       }
     }
   }
@@ -111,7 +111,7 @@ __device__ __forceinline__ void hop_mu(const DslashArgs& a, int p, int i, const 
           for (int k = 0; k < 6; ++k) hu[k] = hs * hu[k];
         }
         accumulate<C, MU, true>(acc[r], hu);
-        pin_acc(acc[r]);
+        if constexpr (PIN) pin_acc(acc[r]);
       }
     }
   }
@@ -222,7 +222,8 @@ __device__ __forceinline__ void clover_multi(const void* clov, int Vh, int p, in
 // RED (DIAG = 1, one right-hand side): also add <out, x> and ||out||^2 of the
 // site, in FP64 from the stored values, to red[0..3)
 // g0: first right-hand side of the thread's group (-1: blockIdx.y * NR)
-template <typename S, typename G, int DIAG, bool POSTINV, int NR, bool STREAM = false, bool RED = false>
+template <typename S, typename G, int DIAG, bool POSTINV, int NR, bool STREAM = false, bool RED = false,
+          bool PIN = true>
 __device__ __forceinline__ void dslash_site(const DslashArgs& a, int lb, double* red = nullptr, int g0 = -1) {
   using C = typename Compute<S>::T;
   const int i = lb * blockDim.x + threadIdx.x;
@@ -238,10 +239,10 @@ __device__ __forceinline__ void dslash_site(const DslashArgs& a, int lb, double*
   for (int r = 0; r < NR; ++r)
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[r][k] = mk((C)0, (C)0);
-  hop_mu<S, G, 0, NR, STREAM>(a, p, i, c, g0, nr, acc);
-  hop_mu<S, G, 1, NR, STREAM>(a, p, i, c, g0, nr, acc);
-  hop_mu<S, G, 2, NR, STREAM>(a, p, i, c, g0, nr, acc);
-  hop_mu<S, G, 3, NR, STREAM>(a, p, i, c, g0, nr, acc);
+  hop_mu<S, G, 0, NR, STREAM, PIN>(a, p, i, c, g0, nr, acc);
+  hop_mu<S, G, 1, NR, STREAM, PIN>(a, p, i, c, g0, nr, acc);
+  hop_mu<S, G, 2, NR, STREAM, PIN>(a, p, i, c, g0, nr, acc);
+  hop_mu<S, G, 3, NR, STREAM, PIN>(a, p, i, c, g0, nr, acc);
 
   const C f = (C)(-0.5 * a.coeff);
 #pragma unroll
@@ -298,6 +299,16 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs a) {
   dslash_site<S, G, DIAG, POSTINV, NR, STREAM>(a, xcd_block(a.nblocks));
 }
 
+// Small lattices (a few workgroups per compute unit, so one or two wavefronts
+// per SIMD whatever the register count): the directions are not pinned, so
+// the compiler may issue the loads of all eight hops before their arithmetic
+// and more of the gather is in flight at once.  Same arithmetic, same order,
+// same bits as dslash_kernel.
+template <typename S, typename G, int DIAG, bool POSTINV, bool STREAM>
+__global__ void __launch_bounds__(256) dslash_kernel_wide(DslashArgs a) {
+  dslash_site<S, G, DIAG, POSTINV, 1, STREAM, false, false>(a, xcd_block(a.nblocks));
+}
+
 // Several right-hand sides, one per thread: logical workgroup L handles site
 // block L / nrhs of right-hand side L % nrhs, so the nrhs workgroups of a site
 // block are consecutive, land on one XCD (xcd_block) and run close together:
@@ -314,10 +325,10 @@ __global__ void __launch_bounds__(256) dslash_kernel_rhs(DslashArgs a) {
 // fused in: out = x + coeff H in, and <out, x>, ||out||^2 reduced into o in
 // the same launch (every block, padding blocks included, takes part in the
 // reduction; the last to arrive finishes it).
-template <typename S, typename G, bool STREAM>
+template <typename S, typename G, bool STREAM, bool PIN = true>
 __global__ void __launch_bounds__(256) dslash_red_kernel(DslashArgs a, RedOut o) {
   double v[3] = {0.0, 0.0, 0.0};
-  dslash_site<S, G, 1, false, 1, STREAM, true>(a, xcd_block(a.nblocks), v);
+  dslash_site<S, G, 1, false, 1, STREAM, true, PIN>(a, xcd_block(a.nblocks), v);
   blas_detail::block_reduce<3>(v, o);
 }
 
@@ -418,12 +429,48 @@ constexpr int max_group() {
   return sizeof(S) == 8 ? 2 : 4;
 }
 
+// compute units of the current device (queried once)
+static int device_cus() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, n = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev));
+    cus = n > 0 ? n : 1;
+  }
+  return cus;
+}
+
+// a single-right-hand-side grid of at most two 256-thread workgroups per compute unit
+static bool small_grid(const DslashArgs& a) { return a.nrhs == 1 && (a.g.Vh + 255) / 256 <= 2 * device_cus(); }
+
 template <typename S, typename G, int NR>
 static void launch_dslash_nr(int diag, bool postinv, DslashArgs a, hipStream_t st) {
   const int threads = a.threads > 0 ? a.threads : 256;
   if (threads != 64 && threads != 128 && threads != 256) fail(WCMG_EINVAL, "unsupported Dslash block size");
   a.nblocks = (a.g.Vh + threads - 1) / threads;
   dim3 grid(xcd_grid(a.nblocks), (a.nrhs + NR - 1) / NR);
+  if constexpr (NR == 1) {
+    if (small_grid(a)) {
+      const bool stream = a.stream > 0;
+#define WCMG_DW(D, P)                                                                               \
+  do {                                                                                            \
+    if (stream)                                                                                   \
+      hipLaunchKernelGGL((dslash_kernel_wide<S, G, D, P, true>), grid, dim3(threads), 0, st, a);  \
+    else                                                                                          \
+      hipLaunchKernelGGL((dslash_kernel_wide<S, G, D, P, false>), grid, dim3(threads), 0, st, a); \
+  } while (0)
+      if (diag == 0 && !postinv) WCMG_DW(0, false);
+      else if (diag == 0 && postinv) WCMG_DW(0, true);
+      else if (diag == 1 && !postinv) WCMG_DW(1, false);
+      else if (diag == 1 && postinv) WCMG_DW(1, true);
+      else if (diag == 2 && !postinv) WCMG_DW(2, false);
+      else WCMG_DW(2, true);
+#undef WCMG_DW
+      HIPCHK(hipGetLastError());
+      return;
+    }
+  }
   // stream the fields and the output past the caches when the fields (links and both
   // clover records, both parities) exceed three quarters of the 256 MB Infinity Cache
   const bool stream = a.stream >= 0 ? a.stream != 0 : (double)a.g.Vh * 432.0 * sizeof(G) > 192.0e6;
@@ -496,10 +543,16 @@ template <typename S, typename G>
 static void launch_dslash_red_t(DslashArgs a, const RedOut& o, hipStream_t st) {
   const bool stream = a.stream >= 0 ? a.stream != 0 : (double)a.g.Vh * 432.0 * sizeof(G) > 192.0e6;
   dim3 grid(xcd_grid(a.nblocks));
-  if (stream)
+  if (small_grid(a)) {
+    if (stream)
+      hipLaunchKernelGGL((dslash_red_kernel<S, G, true, false>), grid, dim3(256), 0, st, a, o);
+    else
+      hipLaunchKernelGGL((dslash_red_kernel<S, G, false, false>), grid, dim3(256), 0, st, a, o);
+  } else if (stream) {
     hipLaunchKernelGGL((dslash_red_kernel<S, G, true>), grid, dim3(256), 0, st, a, o);
-  else
+  } else {
     hipLaunchKernelGGL((dslash_red_kernel<S, G, false>), grid, dim3(256), 0, st, a, o);
+  }
   HIPCHK(hipGetLastError());
 }
 
