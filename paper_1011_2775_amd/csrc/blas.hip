@@ -219,6 +219,108 @@ __global__ void k_gcr_update_x_dev(MultiArgs m, int k, void* x, size_t n, const 
   }
 }
 
+// value of c after a store in T and a load back (rounding to T)
+template <typename T>
+__device__ __forceinline__ cpx<double> rnd(cpx<double> c) {
+  return mk((double)(T)c.r, (double)(T)c.i);
+}
+
+// One GCR step after the multi-dot: beta[2j] = <q_j, y> for the ktot basis
+// slots, beta[2 ktot] = <y, y>, beta[2 ktot + 2] = <r, y>.  This launch takes
+// the slots j0 .. j0 + k - 1 (m.v): y -= sum_j c_j q_j, c_j = <q_j, y> /
+// ||q_j||^2.  The last launch of the step (last = 1) also forms
+//   ||y_orth||^2 = <y, y> - sum_j |<q_j, y>|^2 / ||q_j||^2   (in order of j),
+//   <y_orth, r>  = <y, r>                                    (r is orthogonal to every q_j),
+// applies r -= alpha y_orth with alpha = <y_orth, r> / ||y_orth||^2, reduces
+// ||r||^2 into o, and (block 0) writes {||y_orth||^2, <y_orth, r>} to
+// qa[4 ktot ..] and the c_j to cj[0 .. ktot).
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_gcr_step_dev(MultiArgs m, int j0, int k, int ktot, void* y, void* r,
+                                                           size_t n, const double* beta, double* qa, double* cj,
+                                                           int last, const RedOut o) {
+  cpx<double> c[kMaxK];
+#pragma unroll
+  for (int j = 0; j < kMaxK; ++j) {
+    const double d = j < k ? qa[4 * (j0 + j)] : 0.0;
+    c[j] = (j < k && d > 0.0) ? mk(beta[2 * (j0 + j)] / d, beta[2 * (j0 + j) + 1] / d) : mk(0.0, 0.0);
+  }
+  cpx<double> alpha = mk(0.0, 0.0);
+  double qq = 0.0;
+  cpx<double> qr = mk(0.0, 0.0);
+  if (last) {
+    qq = beta[2 * ktot];
+    for (int j = 0; j < ktot; ++j) {
+      const double d = qa[4 * j];
+      if (d > 0.0) {
+        const double br = beta[2 * j], bi = beta[2 * j + 1];
+        qq -= (br * br + bi * bi) / d;
+      }
+    }
+    qr = mk(beta[2 * ktot + 2], -beta[2 * ktot + 3]);
+    if (qq > 0.0) alpha = mk(qr.r / qq, qr.i / qq);
+    if (blockIdx.x == 0) {
+      if (threadIdx.x == 0) {
+        qa[4 * ktot] = qq;
+        qa[4 * ktot + 1] = qr.r;
+        qa[4 * ktot + 2] = qr.i;
+      }
+      for (int j = threadIdx.x; j < ktot; j += blockDim.x) {
+        const double d = qa[4 * j];
+        cj[2 * j] = d > 0.0 ? beta[2 * j] / d : 0.0;
+        cj[2 * j + 1] = d > 0.0 ? beta[2 * j + 1] / d : 0.0;
+      }
+    }
+  }
+  double v[1] = {0.0};
+  GRID_STRIDE(i, n) {
+    cpx<double> a = ld<T>(y, i);
+#pragma unroll
+    for (int j = 0; j < kMaxK; ++j)
+      if (j < k) a = a - c[j] * ld<T>(m.v[j], i);
+    st<T>(y, i, a);
+    if (last) {
+      const cpx<double> b = ld<T>(r, i) - alpha * rnd<T>(a);
+      st<T>(r, i, b);
+      const cpx<double> bs = rnd<T>(b);
+      v[0] += bs.r * bs.r + bs.i * bs.i;
+    }
+  }
+  if (last) block_reduce<1>(v, o);
+}
+
+// Coefficients of the solution update of a GCR cycle whose directions are kept
+// as the raw preconditioned vectors z_j: with z~_j = z_j - sum_{i<j} c_ij z~_i
+// (c_ij in cmat[j][i], complex) and x += sum_j alpha_j z~_j, x += sum_j y_j z_j
+// where y solves (I + C) y = alpha by back substitution (alpha_j = 0 for the
+// nf fixed slots, whose vectors are not orthogonalised).  One thread.
+__global__ void k_gcr_coef_solve(const double* qa, const double* cmat, int ldc, double* y, int nf, int kt) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int i = kt - 1; i >= 0; --i) {
+    cpx<double> s = i < nf ? mk(0.0, 0.0) : gcr_alpha(qa + 4 * i);
+    for (int j = (i + 1 > nf ? i + 1 : nf); j < kt; ++j) {
+      const cpx<double> cij = mk(cmat[2 * ((size_t)j * ldc + i)], cmat[2 * ((size_t)j * ldc + i) + 1]);
+      s = s - cij * mk(y[2 * j], y[2 * j + 1]);
+    }
+    y[2 * i] = s.r;
+    y[2 * i + 1] = s.i;
+  }
+}
+
+// x += sum_j coef_j v_j (coef: complex, device)
+template <typename T>
+__global__ void k_multi_axpy_dev(MultiArgs m, int k, void* x, size_t n, const double* coef) {
+  cpx<double> c[kMaxK];
+#pragma unroll
+  for (int j = 0; j < kMaxK; ++j) c[j] = j < k ? mk(coef[2 * j], coef[2 * j + 1]) : mk(0.0, 0.0);
+  GRID_STRIDE(i, n) {
+    cpx<double> acc = ld<T>(x, i);
+#pragma unroll
+    for (int j = 0; j < kMaxK; ++j)
+      if (j < k) acc = acc + c[j] * ld<T>(m.v[j], i);
+    st<T>(x, i, acc);
+  }
+}
+
 // MR step with alpha = <Ar, r> / ||Ar||^2 read from coef = [re, im, ||Ar||^2]
 template <typename T>
 __global__ void k_mr_update_dev(const double* coef, void* x, void* r, const void* Ar, size_t n) {
@@ -353,6 +455,35 @@ void blas_gcr_update_x_dev(int prec, const void* const* z, int k, void* x, size_
     MultiArgs m{};
     for (int j = 0; j < kk; ++j) m.v[j] = z[j0 + j];
     DISPATCH(prec, k_gcr_update_x_dev, ew_grid(n), m, kk, x, n, qa + 4 * j0);
+  }
+}
+
+void blas_gcr_step_dev(int prec, const void* const* q, int k, void* y, void* r, size_t n, const double* beta,
+                       double* qa, double* cj, const RedOut& o, hipStream_t st) {
+  if (k == 0) {
+    MultiArgs m{};
+    DISPATCH(prec, k_gcr_step_dev, red_grid(n), m, 0, 0, 0, y, r, n, beta, qa, cj, 1, o);
+    return;
+  }
+  for (int j0 = 0; j0 < k; j0 += kMaxK) {
+    const int kk = std::min(kMaxK, k - j0);
+    MultiArgs m{};
+    for (int j = 0; j < kk; ++j) m.v[j] = q[j0 + j];
+    const int last = j0 + kk == k;
+    DISPATCH(prec, k_gcr_step_dev, red_grid(n), m, j0, kk, k, y, r, n, beta, qa, cj, last, o);
+  }
+}
+
+void blas_gcr_update_x_raw(int prec, const void* const* z, int nf, int kt, void* x, size_t n, const double* qa,
+                           const double* cmat, int ldc, double* y, hipStream_t st) {
+  if (kt <= 0) return;
+  hipLaunchKernelGGL(k_gcr_coef_solve, dim3(1), dim3(64), 0, st, qa, cmat, ldc, y, nf, kt);
+  HIPCHK(hipGetLastError());
+  for (int j0 = 0; j0 < kt; j0 += kMaxK) {
+    const int kk = std::min(kMaxK, kt - j0);
+    MultiArgs m{};
+    for (int j = 0; j < kk; ++j) m.v[j] = z[j0 + j];
+    DISPATCH(prec, k_multi_axpy_dev, ew_grid(n), m, kk, x, n, y + 2 * j0);
   }
 }
 

@@ -143,6 +143,18 @@ void blas_gcr_update_r_dev(int prec, const void* q, void* r, size_t n, const dou
 void blas_defl_coefs(const double* dots, double* qa, int K, hipStream_t st);
 void blas_gcr_update_x_dev(int prec, const void* const* z, int k, void* x, size_t n, const double* qa,
                            hipStream_t st);
+// One step of the GCR kept with raw preconditioned directions, after
+// blas_multi_cdot of y against {q_0 .. q_{k-1}, y, r} into beta: y -= sum_j
+// (beta_j/||q_j||^2) q_j; ||y||^2 by the Pythagorean sum and <y, r> (r is
+// orthogonal to every q_j) into qa[4k], qa[4k+1..2]; r -= alpha y; ||r||^2
+// into o; the coefficients beta_j/||q_j||^2 into cj[0 .. 2k)
+void blas_gcr_step_dev(int prec, const void* const* q, int k, void* y, void* r, size_t n, const double* beta,
+                       double* qa, double* cj, const RedOut& o, hipStream_t st);
+// x += sum_j alpha_j z~_j for a cycle of kt slots (nf fixed ones first) kept as
+// raw z_j: z~_j = z_j - sum_{i<j} c_ij z~_i with c_ij = cmat[2 (j ldc + i) ..];
+// y (2 kt doubles of device scratch) receives the coefficients on the raw z_j
+void blas_gcr_update_x_raw(int prec, const void* const* z, int nf, int kt, void* x, size_t n, const double* qa,
+                           const double* cmat, int ldc, double* y, hipStream_t st);
 // MR with alpha = coef[0..1] / coef[2] (the output of blas_cdot_norm(Ar, r))
 void blas_mr_update_dev(int prec, const double* coef, void* x, void* r, const void* Ar, size_t n, hipStream_t st);
 

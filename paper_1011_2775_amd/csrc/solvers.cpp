@@ -23,7 +23,11 @@ void GcrSpace::ensure(int restart) {
     if (Q[k].n < bytes) Q[k].alloc(bytes);
   }
   if (r.n < bytes) r.alloc(bytes);
-  if (!scal.p) scal.alloc((2 * (kMaxRestart + 16) + 4 * kMaxRestart) * sizeof(double));
+  // beta, qa, the orthogonalisation coefficients [slot][slot] (complex) and the
+  // solution-update coefficients of a cycle
+  if (!scal.p)
+    scal.alloc((2 * (kMaxRestart + 16) + 4 * kMaxRestart + 2 * kMaxRestart * kMaxRestart + 2 * kMaxRestart) *
+               sizeof(double));
 }
 
 static bool finite(double v) { return std::isfinite(v); }
@@ -71,9 +75,14 @@ KrylovResult gcr(Ctx& c, GcrSpace& S, const OpFn& A, const OpFn* K, void* x, con
   }
   // device scalars: beta (multi-dot results) and per-step {||q||^2, <q,r>, ||r||^2};
   // slots 0..nf-1 belong to the fixed pairs (alpha 0: r is orthogonal to them)
+  // the directions are kept as the raw preconditioned vectors z_j (only q_j =
+  // A z~_j is orthogonalised); cmat holds the orthogonalisation coefficients,
+  // from which the solution update of a cycle is recovered
   double* beta = S.scal.as<double>();
   double* qa = beta + 2 * (kMaxRestart + 16);
-  std::vector<const void*> Qp(nf + restart), Zp(nf + restart);
+  double* cmat = qa + 4 * kMaxRestart;
+  double* ycoef = cmat + 2 * kMaxRestart * kMaxRestart;
+  std::vector<const void*> Qp(nf + restart), Zp(nf + restart), Dp(nf + restart + 2);
   for (int j = 0; j < nf; ++j) {
     Qp[j] = defl->Q[j];
     Zp[j] = defl->Z[j];
@@ -93,9 +102,14 @@ KrylovResult gcr(Ctx& c, GcrSpace& S, const OpFn& A, const OpFn* K, void* x, con
       else
         blas_copy(prec, z, r, n, st);
       A(q, z);
-      if (kk > 0) blas_multi_cdot(prec, Qp.data(), kk, q, n, R.out(beta), st);
-      blas_gcr_orth_dev(prec, Qp.data(), Zp.data(), kk, q, z, r, n, beta, qa, R.out(qa + 4 * kk), st);
-      blas_gcr_update_r_dev(prec, q, r, n, qa + 4 * kk, R.out(qa + 4 * kk + 3), st);
+      // <q_j, q> for the basis, <q, q> and <r, q> in one pass; then one pass
+      // orthogonalises q and updates r
+      for (int j = 0; j < kk; ++j) Dp[j] = Qp[j];
+      Dp[kk] = q;
+      Dp[kk + 1] = r;
+      blas_multi_cdot(prec, Dp.data(), kk + 2, q, n, R.out(beta), st);
+      blas_gcr_step_dev(prec, Qp.data(), kk, q, r, n, beta, qa, cmat + (size_t)2 * kMaxRestart * kk,
+                        R.out(qa + 4 * kk + 3), st);
       if (fixed) {
         ++k;
         ++res.iters;
@@ -120,7 +134,7 @@ KrylovResult gcr(Ctx& c, GcrSpace& S, const OpFn& A, const OpFn* K, void* x, con
       }
       if ((!fixed && std::sqrt(rn2) <= target) || res.iters >= maxiter) break;
     }
-    if (k > 0) blas_gcr_update_x_dev(prec, Zp.data() + nf, k, x, n, qa + 4 * nf, st);
+    if (k > 0) blas_gcr_update_x_raw(prec, Zp.data(), nf, nf + k, x, n, qa, cmat, kMaxRestart, ycoef, st);
     if (res.status != WCMG_OK) break;
     if (fixed) break;
     // true residual at the end of every cycle
