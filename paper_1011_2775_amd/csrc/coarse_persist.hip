@@ -352,14 +352,14 @@ __device__ __forceinline__ void tag_store_double(__amdgpu_buffer_rsrc_t r, unsig
 // grid_sum over tagged partials (slot pbase + w stride + v of workgroup w, tag
 // `tag`), in two stages so that no workgroup reads every partial: value v is
 // summed once, in the order of grid_sum, by one wavefront of workgroup v mod W,
-// which publishes the total in slot tbase + v; then every workgroup reads the
-// nv totals into out.  Each load is repeated until its slot carries the tag.
-// The values of a step are summed before any workgroup can publish partials
-// of a later step into the same slots (it needs every total of the step in
-// between, whose summing workgroups finish this step's sums first).  false
-// when a wait timed out or another workgroup aborted.
-__device__ bool grid_sum_tagged(__amdgpu_buffer_rsrc_t rp, unsigned pbase, unsigned tbase, int stride, int nv,
-                                unsigned tag, double* out, int* abort_flag) {
+// which publishes the total in slot tbase + v (grid_sum_publish); every
+// workgroup then reads the nv totals (grid_sum_read).  Each load is repeated
+// until its slot carries the tag.  The values of a step are summed before any
+// workgroup can publish partials of a later step into the same slots (it
+// needs every total of the step in between, whose summing workgroups finish
+// this step's sums first).
+__device__ void grid_sum_publish(__amdgpu_buffer_rsrc_t rp, unsigned pbase, unsigned tbase, int stride, int nv,
+                                 unsigned tag, int* abort_flag) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, NWv = blockDim.x >> 6, W = gridDim.x;
   for (int v = (int)blockIdx.x + W * wave; v < nv; v += W * NWv) {
     double s = 0.0;
@@ -376,6 +376,10 @@ __device__ bool grid_sum_tagged(__amdgpu_buffer_rsrc_t rp, unsigned pbase, unsig
     s = wave_sum(s);
     if (lane == 0) tag_store_double(rp, tbase + (unsigned)v, tag, s);
   }
+}
+// false when a wait timed out or another workgroup aborted
+__device__ bool grid_sum_read(__amdgpu_buffer_rsrc_t rp, unsigned tbase, int nv, unsigned tag, double* out,
+                              int* abort_flag) {
   for (int v = threadIdx.x; v < nv; v += blockDim.x)
     out[v] = tag_double(tag_wait(rp, tbase + (unsigned)v, tag, tag_load(rp, tbase + (unsigned)v), abort_flag));
   __syncthreads();
@@ -1349,13 +1353,16 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
       // (tagged: the hop's reads of q and the sum's reads of the partials wait
       // for their versions themselves)
       if (tagged) {
+        // the summing workgroups sum right away (their wait for the last
+        // partials overlaps the odd hop's wait for q), so that the totals are
+        // out when the others finish the odd hop
         epoch = ep;
+        grid_sum_publish(rtag, pslot + (unsigned)(cur * W * a.stride), tslot + (unsigned)(cur * a.stride), a.stride,
+                         2 * k + 4, ep, abort_flag);
         hop1<S, MT>(a, Vh + w, nbO, qraw, nullptr, nullptr, 1.0, nullptr, nullptr, Ts + (size_t)k * n, vin, hp, pre,
                     nullptr, 1, qver);
         __syncthreads();
-        if (!grid_sum_tagged(rtag, pslot + (unsigned)(cur * W * a.stride), tslot + (unsigned)(cur * a.stride),
-                             a.stride, 2 * k + 4, ep, sv, abort_flag))
-          return;
+        if (!grid_sum_read(rtag, tslot + (unsigned)(cur * a.stride), 2 * k + 4, ep, sv, abort_flag)) return;
       } else {
         barrier_arrive(a.bar, ++epoch);
         if (!arrival_wait(a.bar, abort_flag, nbq, epoch)) return;
