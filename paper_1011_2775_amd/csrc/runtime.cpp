@@ -127,6 +127,8 @@ void Reducer::init(hipStream_t s) {
   counter.alloc(256);
   HIPCHK(hipMemset(counter.p, 0, 256));
   HIPCHK(hipHostMalloc((void**)&host, 256 * sizeof(double), hipHostMallocDefault));
+  HIPCHK(hipHostMalloc((void**)&host2, 16 * sizeof(double), hipHostMallocDefault));
+  for (auto& e : ev2) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   part_b.alloc((size_t)kMaxBatch * kRedBlocks * 32 * sizeof(double));
 }
 const double* Reducer::fetch_rows(const double* dev, size_t pitch, int width, int rows) {
@@ -144,7 +146,19 @@ const double* Reducer::fetch_from(const double* dev, int n) {
   HIPCHK(hipStreamSynchronize(st));
   return host;
 }
+void Reducer::fetch_async(const double* dev, int n, int slot) {
+  if (n > 8 || slot < 0 || slot > 1) fail(WCMG_EINVAL, "asynchronous fetch: at most 8 scalars in slot 0 or 1");
+  HIPCHK(hipMemcpyAsync(host2 + 8 * slot, dev, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipEventRecord(ev2[slot], st));
+}
+const double* Reducer::fetch_wait(int slot) {
+  HIPCHK(hipEventSynchronize(ev2[slot]));
+  return host2 + 8 * slot;
+}
 Reducer::~Reducer() {
+  for (auto& e : ev2)
+    if (e) (void)hipEventDestroy(e);
+  if (host2) (void)hipHostFree(host2);
   if (host) (void)hipHostFree(host);
 }
 

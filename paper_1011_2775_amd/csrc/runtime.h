@@ -62,6 +62,12 @@ struct Reducer {
   const double* fetch_from(const double* dev, int n);
   // rows doubles at dev + r * pitch (r < rows), `width` each, packed to host[r * width]
   const double* fetch_rows(const double* dev, size_t pitch, int width, int rows);
+  // two-slot asynchronous form: the copy of n <= 8 doubles is ordered on the
+  // stream and completes while later work runs; fetch_wait blocks for it
+  double* host2 = nullptr;
+  hipEvent_t ev2[2] = {nullptr, nullptr};
+  void fetch_async(const double* dev, int n, int slot);
+  const double* fetch_wait(int slot);
   RedB outb(double* dst, size_t rs) { return RedB{dst, rs, part_b.as<double>()}; }
   ~Reducer();
 };

@@ -88,35 +88,60 @@ KrylovResult gcr(Ctx& c, GcrSpace& S, const OpFn& A, const OpFn* K, void* x, con
     Zp[j] = defl->Z[j];
   }
   if (nf) blas_copy(WCMG_F64, qa, defl->qa, (size_t)2 * nf, st);
+  // one step of the cycle: z_k = K r, q_k = A z_k, then <q_j, q> for the
+  // basis, <q, q> and <r, q> in one pass and one pass that orthogonalises q
+  // and updates r
+  auto enqueue_step = [&](int k) {
+    void* z = S.Z[k].p;
+    void* q = S.Q[k].p;
+    const int kk = nf + k;  // basis slot of this step
+    Qp[kk] = q;
+    Zp[kk] = z;
+    if (K)
+      (*K)(z, r);
+    else
+      blas_copy(prec, z, r, n, st);
+    A(q, z);
+    for (int j = 0; j < kk; ++j) Dp[j] = Qp[j];
+    Dp[kk] = q;
+    Dp[kk + 1] = r;
+    blas_multi_cdot(prec, Dp.data(), kk + 2, q, n, R.out(beta), st);
+    blas_gcr_step_dev(prec, Qp.data(), kk, q, r, n, beta, qa, cmat + (size_t)2 * kMaxRestart * kk,
+                      R.out(qa + 4 * kk + 3), st);
+  };
+  // The top-level solve reads each step's scalars back asynchronously and,
+  // while the residual is still far from the target, queues the next step
+  // before that read completes, so that the device does not wait for the
+  // host.  A queued step that turns out not to be needed only writes the next
+  // basis slot and r, which the cycle end recomputes from x.
+  const bool pipelined = !fixed && &S == &c.outer;
+  double rn_prev = std::sqrt(rn2), ratio = 0.5;
   bool converged = false;
   while (res.iters < maxiter) {
     int k = 0;
+    bool queued = false;  // step k already queued (with its scalars' copy into slot qslot)
+    int qslot = 0;
     for (; k < restart;) {
-      void* z = S.Z[k].p;
-      void* q = S.Q[k].p;
-      const int kk = nf + k;  // basis slot of this step
-      Qp[kk] = q;
-      Zp[kk] = z;
-      if (K)
-        (*K)(z, r);
-      else
-        blas_copy(prec, z, r, n, st);
-      A(q, z);
-      // <q_j, q> for the basis, <q, q> and <r, q> in one pass; then one pass
-      // orthogonalises q and updates r
-      for (int j = 0; j < kk; ++j) Dp[j] = Qp[j];
-      Dp[kk] = q;
-      Dp[kk + 1] = r;
-      blas_multi_cdot(prec, Dp.data(), kk + 2, q, n, R.out(beta), st);
-      blas_gcr_step_dev(prec, Qp.data(), kk, q, r, n, beta, qa, cmat + (size_t)2 * kMaxRestart * kk,
-                        R.out(qa + 4 * kk + 3), st);
+      const int kk = nf + k;
+      if (!queued) {
+        enqueue_step(k);
+        if (pipelined) R.fetch_async(qa + 4 * kk, 4, k & 1);
+      }
+      queued = false;
       if (fixed) {
         ++k;
         ++res.iters;
         if (res.iters >= maxiter) break;
         continue;
       }
-      const double* o = R.fetch_from(qa + 4 * kk, 4);  // one host round trip: {||q||^2, <q,r>, ||r||^2}
+      if (pipelined && k + 1 < restart && res.iters + 1 < maxiter && rn_prev * ratio * 0.25 > target) {
+        enqueue_step(k + 1);
+        qslot = (k + 1) & 1;
+        R.fetch_async(qa + 4 * (kk + 1), 4, qslot);
+        queued = true;
+      }
+      // {||q||^2, <q,r>, ||r||^2} of step k
+      const double* o = pipelined ? R.fetch_wait(k & 1) : R.fetch_from(qa + 4 * kk, 4);
       const double qq = o[0];
       rn2 = o[3];
       if (log_level() >= 3 && n > 100000)
@@ -133,6 +158,13 @@ KrylovResult gcr(Ctx& c, GcrSpace& S, const OpFn& A, const OpFn* K, void* x, con
         break;
       }
       if ((!fixed && std::sqrt(rn2) <= target) || res.iters >= maxiter) break;
+      if (rn_prev > 0.0) ratio = std::min(1.0, std::sqrt(rn2) / rn_prev);
+      rn_prev = std::sqrt(rn2);
+    }
+    if (queued) {
+      // the step queued past the end of this run: its scalars' copy must be
+      // complete before the slot is reused
+      (void)R.fetch_wait(qslot);
     }
     if (k > 0) blas_gcr_update_x_raw(prec, Zp.data(), nf, nf + k, x, n, qa, cmat, kMaxRestart, ycoef, st);
     if (res.status != WCMG_OK) break;
@@ -149,6 +181,7 @@ KrylovResult gcr(Ctx& c, GcrSpace& S, const OpFn& A, const OpFn* K, void* x, con
       converged = true;
       break;
     }
+    rn_prev = std::sqrt(rn2);
   }
   res.rel_res = target_norm > 0 ? std::sqrt(rn2) / target_norm : 0.0;
   if (!fixed && !converged && res.status == WCMG_OK) res.status = WCMG_ENOCONV;
