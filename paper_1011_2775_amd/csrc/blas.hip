@@ -160,52 +160,6 @@ __device__ __forceinline__ cpx<double> gcr_alpha(const double* qa) {
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_gcr_orth_dev(MultiArgs m, int k, void* y, void* z, const void* r,
-                                                           size_t n, const double* beta, const double* qa,
-                                                           int do_red, const RedOut o) {
-  double v[3] = {0.0, 0.0, 0.0};
-  cpx<double> c[kMaxK];
-#pragma unroll
-  for (int j = 0; j < kMaxK; ++j) {
-    double d = j < k ? qa[4 * j] : 0.0;
-    c[j] = (j < k && d > 0.0) ? mk(beta[2 * j] / d, beta[2 * j + 1] / d) : mk(0.0, 0.0);
-  }
-  GRID_STRIDE(i, n) {
-    cpx<double> a = ld<T>(y, i), b = ld<T>(z, i);
-#pragma unroll
-    for (int j = 0; j < kMaxK; ++j) {
-      if (j < k) {
-        a = a - c[j] * ld<T>(m.v[j], i);
-        b = b - c[j] * ld<T>(m.w[j], i);
-      }
-    }
-    st<T>(y, i, a);
-    st<T>(z, i, b);
-    if (do_red) {
-      cpx<double> as = ld<T>(y, i), rr = ld<T>(r, i);
-      v[0] += as.r * as.r + as.i * as.i;
-      v[1] += as.r * rr.r + as.i * rr.i;
-      v[2] += as.r * rr.i - as.i * rr.r;
-    }
-  }
-  if (do_red) block_reduce<3>(v, o);
-}
-
-template <typename T>
-__global__ void __launch_bounds__(kThreads) k_gcr_update_r_dev(const void* q, void* r, size_t n, const double* qa,
-                                                               const RedOut o) {
-  double v[1] = {0.0};
-  cpx<double> a = gcr_alpha(qa);
-  GRID_STRIDE(i, n) {
-    cpx<double> b = ld<T>(r, i) - a * ld<T>(q, i);
-    st<T>(r, i, b);
-    cpx<double> bs = ld<T>(r, i);
-    v[0] += bs.r * bs.r + bs.i * bs.i;
-  }
-  block_reduce<1>(v, o);
-}
-
-template <typename T>
 __global__ void k_gcr_update_x_dev(MultiArgs m, int k, void* x, size_t n, const double* qa) {
   cpx<double> c[kMaxK];
 #pragma unroll
@@ -422,30 +376,6 @@ void blas_bicg_p(int prec, double br, double bi, double wr, double wi, const voi
 }
 void blas_mr_update(int prec, double ar, double ai, void* x, void* r, const void* Ar, size_t n, hipStream_t st) {
   DISPATCH(prec, k_mr_update, ew_grid(n), ar, ai, x, r, Ar, n);
-}
-
-void blas_gcr_orth_dev(int prec, const void* const* q, const void* const* w, int k, void* y, void* z, const void* r,
-                       size_t n, const double* beta, const double* qa, const RedOut& o, hipStream_t st) {
-  if (k == 0) {
-    MultiArgs m{};
-    DISPATCH(prec, k_gcr_orth_dev, red_grid(n), m, 0, y, z, r, n, beta, qa, 1, o);
-    return;
-  }
-  for (int j0 = 0; j0 < k; j0 += kMaxK) {
-    int kk = std::min(kMaxK, k - j0);
-    MultiArgs m{};
-    for (int j = 0; j < kk; ++j) {
-      m.v[j] = q[j0 + j];
-      m.w[j] = w[j0 + j];
-    }
-    int last = (j0 + kk == k);
-    DISPATCH(prec, k_gcr_orth_dev, red_grid(n), m, kk, y, z, r, n, beta + 2 * j0, qa + 4 * j0, last, o);
-  }
-}
-
-void blas_gcr_update_r_dev(int prec, const void* q, void* r, size_t n, const double* qa_k, const RedOut& o,
-                           hipStream_t st) {
-  DISPATCH(prec, k_gcr_update_r_dev, red_grid(n), q, r, n, qa_k, o);
 }
 
 void blas_gcr_update_x_dev(int prec, const void* const* z, int k, void* x, size_t n, const double* qa,

@@ -131,12 +131,6 @@ void blas_mr_update(int prec, double ar, double ai, void* x, void* r, const void
 
 // Device-resident GCR coefficients: slot j of qa holds {||q_j||^2, <q_j,r>, ||r||^2
 // after step j}; beta holds the multi-dot <q_j, y>.  No host round trip.
-// y -= sum_j (beta_j/||q_j||^2) q_j, z likewise with w_j; res = {||y||^2, <y,r>}
-void blas_gcr_orth_dev(int prec, const void* const* q, const void* const* w, int k, void* y, void* z, const void* r,
-                       size_t n, const double* beta, const double* qa, const RedOut& o, hipStream_t st);
-// r -= alpha_k q with alpha_k = <q,r>/||q||^2 from qa_k; res[0] = ||r||^2
-void blas_gcr_update_r_dev(int prec, const void* q, void* r, size_t n, const double* qa_k, const RedOut& o,
-                           hipStream_t st);
 // x += sum_j alpha_j z_j
 // qa[4j..4j+3] = {1, dots[2j], dots[2j+1], 0} for j < K (coefficients x += sum_j dots_j z_j
 // for blas_gcr_update_x_dev)
