@@ -406,44 +406,6 @@ __device__ __forceinline__ int cb_index(const DGeom& g, const int c[4]) {
   return (((c[3] * g.L[2] + c[2]) * g.L[1] + c[1]) * g.L[0] + c[0]) >> 1;
 }
 
-// sum over the 8 lanes of a lane octet (lane % 8), the same bits in all 8: the
-// DPP (data-parallel primitive) butterfly (pairs, quads, then the half-row mirror
-// that meets the other quad); a + b = b + a keeps the partners equal
-template <int CTRL>
-__device__ __forceinline__ float dpp_f(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-template <int CTRL>
-__device__ __forceinline__ double dpp_f(double v) {
-  const long long u = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)u, CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, 0xF, 0xF, false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-template <typename C>
-__device__ __forceinline__ C sum8(C v) {
-  v = v + dpp_f<0xB1>(v);   // quad_perm [1,0,3,2]
-  v = v + dpp_f<0x4E>(v);   // quad_perm [2,3,0,1]
-  v = v + dpp_f<0x141>(v);  // row_half_mirror
-  return v;
-}
-
-// wavefront sum, the same bits in every lane (all 64 lanes must be active):
-// the octet butterfly of sum8, the two octets of each row of 16 lanes (row
-// rotation by 8), then the four row sums read from lanes 0, 16, 32 and 48
-// and added as (r0 + r1) + (r2 + r3).  Cross-lane moves inside the ALU
-// instead of LDS permutes.
-__device__ __forceinline__ double rdlane(double v, int l) {
-  const long long u = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)u, l), hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-__device__ __forceinline__ double wave_sum(double v) {
-  v = sum8(v);
-  v = v + dpp_f<0x128>(v);  // row_ror:8
-  return (rdlane(v, 0) + rdlane(v, 16)) + (rdlane(v, 32) + rdlane(v, 48));
-}
-
 // Map a launch block index onto a logical block so that each of the 8 XCDs
 // (which receive workgroups round-robin) works on one contiguous range of
 // sites; neighbours in z and t then hit the same L2.
