@@ -376,9 +376,11 @@ def mg_params(w, cfg, **kw):
     steps (coarse tolerance 0.05-0.3 x smoothing 2-8 at the three masses: 0.2
     with 4 steps is 11% faster in total than 0.1, once the coarse solve is
     one launch).  The coarse hop blocks are stored in FP16 (the persistent
-    coarse solve reads half the bytes; outer iteration counts unchanged on the
-    16^3x32 masses)."""
+    coarse solve reads half the bytes), and so are the copies of the null
+    vectors the cycle restricts and prolongs with (outer iteration counts
+    unchanged on the 16^3x32 masses in both cases)."""
     kw.setdefault("coarse_fp16", 1)
+    kw.setdefault("transfer_fp16", 1)
     kw.setdefault("setup_relax", 60)
     kw.setdefault("setup_max_steps", 5)
     return w.default_params(block=cfg["blocks"], nvec=cfg["nvec"], seed=cfg["setup_seed"], restart=[30],

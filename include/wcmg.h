@@ -154,6 +154,10 @@ typedef struct {
                                        in FP16 (FP32 vectors and arithmetic; with one site per
                                        workgroup the even site's blocks stay in LDS for the whole
                                        solve); 0: FP32 blocks */
+  int transfer_fp16;                /* 1: the FP32 cycle restricts and prolongs with FP16 copies of
+                                       the first level's null vectors (FP32 arithmetic, half the
+                                       bytes of P; the coarse operator is still built from the FP64
+                                       vectors); 0: FP32 copies */
 } wcmg_mg_params;
 
 typedef struct {

@@ -47,7 +47,8 @@ class MGParams(ctypes.Structure):
                 ("coarse_launch", ctypes.c_int),
                 ("plain_max_iter", ctypes.c_int),
                 ("mp_inner_tol", ctypes.c_double),
-                ("coarse_fp16", ctypes.c_int)]
+                ("coarse_fp16", ctypes.c_int),
+                ("transfer_fp16", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):

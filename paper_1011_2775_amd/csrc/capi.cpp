@@ -335,6 +335,8 @@ int wcmg_set_mg_params(void* ctx, int lat, const wcmg_mg_params* p) {
         "coarsest must be 0 (GCR), 1 (dense FP64 inverse) or 2 (deflated FP64 GCR)");
   CHECK(p->cycle_mode >= 0 && p->cycle_mode <= 3, WCMG_EINVAL, "cycle_mode must be 0, 1, 2 or 3");
   CHECK(p->coarse_launch >= 0 && p->coarse_launch <= 2, WCMG_EINVAL, "coarse_launch must be 0, 1 or 2");
+  CHECK(p->coarse_fp16 == 0 || p->coarse_fp16 == 1, WCMG_EINVAL, "coarse_fp16 must be 0 or 1");
+  CHECK(p->transfer_fp16 == 0 || p->transfer_fp16 == 1, WCMG_EINVAL, "transfer_fp16 must be 0 or 1");
   CHECK(p->plain_max_iter >= 0, WCMG_EINVAL, "plain_max_iter must be >= 0");
   CHECK(p->mp_inner_tol >= 0 && p->mp_inner_tol < 1, WCMG_EINVAL, "mp_inner_tol must be in [0,1)");
   CHECK(p->setup_prec == WCMG_F64 || p->setup_prec == WCMG_F32 || p->setup_prec == WCMG_F16, WCMG_EINVAL,

@@ -191,17 +191,21 @@ int coarse_internal_index_host(const BlockGeom& bg, int lex);
 // vecs: Nv full-lattice spinors (precision prec) in internal layout
 // out_site_stride/out_row_stride are in complex elements; accumulate: add into out
 // vbm (FP32 only, optional): the block-major copy of vecs (launch_vec_blockmajor),
-// read instead of vecs with the same arithmetic (coalesced loads)
+// read instead of vecs with the same arithmetic (coalesced loads); vbm16 (FP32
+// only, optional): the FP16 copy of vbm (launch_chunks_to_half), read instead of both
 void launch_restrict(int prec, void* out, size_t out_site_stride, size_t out_row_stride, const void* in,
                      const void* vecs, int nvec, int p, const Geom& g, const BlockGeom& bg, bool accumulate,
-                     hipStream_t st, const void* vbm = nullptr);
+                     hipStream_t st, const void* vbm = nullptr, const void* vbm16 = nullptr);
 // out (same size as v32) = the FP32 vectors v32 block by block: float4 chunk c of
 // the l-th site (restriction order) of parity p of block b of vector k at
 // (((k 2 + p) Vc + b) 6 + c) (bvol / 2) + l
 void launch_vec_blockmajor(void* out, const void* v32, int nvec, const Geom& g, const BlockGeom& bg, hipStream_t st);
-// P: out_p(x) = sum_k V_k(x) coarse[c(x)][s*Nv+k]
+// P: out_p(x) = sum_k V_k(x) coarse[c(x)][s*Nv+k]; v16 (FP32 only, optional): the FP16
+// copy of the FP32 vectors (launch_chunks_to_half), read instead of vecs
 void launch_prolong(int prec, void* out, const void* coarse, const void* vecs, int nvec, int p, const Geom& g,
-                    const BlockGeom& bg, hipStream_t st);
+                    const BlockGeom& bg, hipStream_t st, const void* v16 = nullptr);
+// FP16 copy of nchunks float4 chunks (two complex FP32 each): uint2 per chunk
+void launch_chunks_to_half(void* out, const void* in32, size_t nchunks, hipStream_t st);
 // block x chirality Gram-Schmidt (twice) of Nv full-lattice FP64 spinors in place
 void launch_block_orthonormalize(void* vecs, int nvec, const Geom& g, const BlockGeom& bg, int* flag,
                                  hipStream_t st);

@@ -173,6 +173,7 @@ struct FineTransfer {
   DBuf raw;       // FP64 full spinors (as given / found by the setup)
   DBuf v64, v32;  // block-orthonormalised copies
   DBuf vbm32;     // v32 in block-major order for the restriction
+  DBuf v16, vbm16;  // FP16 copies of v32 and vbm32 (the cycle's transfers with transfer_fp16)
 };
 
 // transfer between coarse level l (>= 1) and level l+1; vectors in the

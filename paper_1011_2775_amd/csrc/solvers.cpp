@@ -849,6 +849,9 @@ struct MGSolver {
   int nlev() const { return L.params.nlevels; }
   const void* vecs(int prec) const { return prec == WCMG_F64 ? L.T0.v64.p : L.T0.v32.p; }
   const void* vbm(int prec) const { return prec == WCMG_F32 ? L.T0.vbm32.p : nullptr; }
+  bool half_transfer(int prec) const { return prec == WCMG_F32 && L.params.transfer_fp16 != 0 && L.T0.v16.p; }
+  const void* v16(int prec) const { return half_transfer(prec) ? L.T0.v16.p : nullptr; }
+  const void* vbm16(int prec) const { return half_transfer(prec) ? L.T0.vbm16.p : nullptr; }
   CoarseOp cop(int li) {
     CoarseOp o{L.levels[li].get(), cp, &cwork, c.st, &c.timer};
     o.timer_base = li < 2 ? 20 + 2 * li : 96 + 2 * (li - 2);
@@ -1111,9 +1114,10 @@ struct MGSolver {
     CoarseLevel& C = *L.levels[0];
     Level& V = lv[0];
     spinor_convert(sp, r_s.p, WCMG_F64, r64, g.Vh, st);
-    launch_restrict(sp, V.cb.p, C.cg.n, 1, r_s.p, vecs(sp), L.T0.nvec, 0, g, L.T0.bg, false, st, vbm(sp));
+    launch_restrict(sp, V.cb.p, C.cg.n, 1, r_s.p, vecs(sp), L.T0.nvec, 0, g, L.T0.bg, false, st, vbm(sp),
+                    vbm16(sp));
     coarse_solve(0, V.cc.p, V.cb.p);
-    launch_prolong(sp, e_s.p, V.cc.p, vecs(sp), L.T0.nvec, 0, g, L.T0.bg, st);
+    launch_prolong(sp, e_s.p, V.cc.p, vecs(sp), L.T0.nvec, 0, g, L.T0.bg, st, v16(sp));
     mr_smooth([&](void* o, const void* i) { op.Dr(o, i); },
               [&](void* o, void* i, const RedOut& ro, void* ee, const double* cf) {
                 return op.Dr_red(o, i, ro, ee, cf);
@@ -1253,12 +1257,12 @@ struct MGSolver {
     for (int i = 0; i < nrhs; ++i) {
       spinor_convert(sp, (char*)r_s.p + i * hs, WCMG_F64, (const char*)r64 + i * h64, g.Vh, st);
       launch_restrict(sp, (char*)V.cb.p + i * na * cs, C.cg.n, 1, (char*)r_s.p + i * hs, vecs(sp), L.T0.nvec, 0, g,
-                      L.T0.bg, false, st, vbm(sp));
+                      L.T0.bg, false, st, vbm(sp), vbm16(sp));
     }
     coarse_solve_b(0, V.cc.p, V.cb.p, nrhs);
     for (int i = 0; i < nrhs; ++i)
       launch_prolong(sp, (char*)e_s.p + i * hs, (char*)V.cc.p + i * na * cs, vecs(sp), L.T0.nvec, 0, g, L.T0.bg,
-                     st);
+                     st, v16(sp));
     mr_smooth_b([&](void* o, const void* i) { op.Dr(o, i, nrhs); }, sp, e_s.p, r_s.p, res_s.p, Ar_s.p, n, n, nrhs);
     for (int i = 0; i < nrhs; ++i)
       spinor_convert(WCMG_F64, (char*)z64 + i * h64, sp, (char*)e_s.p + i * hs, g.Vh, st);
@@ -1725,6 +1729,14 @@ void mg_build_coarse(Ctx& c, LatticeState& L, int level) {
                    g.Vh, st);
   T.vbm32.alloc((size_t)nvec * 2 * hb32);
   launch_vec_blockmajor(T.vbm32.p, T.v32.p, nvec, g, T.bg, st);
+  {
+    // FP16 copies for the cycle's transfers (transfer_fp16): four halves per float4 chunk
+    const size_t nch = (size_t)nvec * 2 * hb32 / 16;
+    T.v16.alloc(nch * 8);
+    T.vbm16.alloc(nch * 8);
+    launch_chunks_to_half(T.v16.p, T.v32.p, nch, st);
+    launch_chunks_to_half(T.vbm16.p, T.vbm32.p, nch, st);
+  }
   T.orth = true;
 
   if (L.levels.empty()) L.levels.emplace_back(new CoarseLevel());

@@ -100,12 +100,29 @@ __global__ void k_vec_blockmajor(const float4* __restrict__ v32, float4* __restr
   }
 }
 
-// vbm (FP32 only): the block-major copy of the vectors, read in place of vecs
+// FP16 copy of FP32 vector chunks: float4 (two complex) -> uint2 (four halves)
+__global__ void k_chunks_to_half(uint2* __restrict__ out, const float4* __restrict__ in, size_t n) {
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+    const float4 v = in[t];
+    const __half2 a = __floats2half2_rn(v.x, v.y), b = __floats2half2_rn(v.z, v.w);
+    out[t] = make_uint2(*reinterpret_cast<const unsigned*>(&a), *reinterpret_cast<const unsigned*>(&b));
+  }
+}
+__device__ __forceinline__ void unpack_half_chunk(uint2 t, cpx<float>& e0, cpx<float>& e1) {
+  const float2 a = __half22float2(*reinterpret_cast<const __half2*>(&t.x));
+  const float2 b = __half22float2(*reinterpret_cast<const __half2*>(&t.y));
+  e0 = mk(a.x, a.y);
+  e1 = mk(b.x, b.y);
+}
+
+// vbm (FP32 only): the block-major copy of the vectors, read in place of vecs;
+// vbm16 (FP32 only): its FP16 copy, read in place of both
 template <typename S>
 __global__ void __launch_bounds__(128) k_restrict(void* out, size_t site_stride, size_t row_stride, const void* in,
                                                   const void* vecs, size_t vec_bytes, size_t half_bytes, int nvec,
                                                   int p, DGeom g, BlockGeom bg, int accumulate,
-                                                  const float4* __restrict__ vbm = nullptr) {
+                                                  const float4* __restrict__ vbm = nullptr,
+                                                  const uint2* __restrict__ vbm16 = nullptr) {
   using C = typename Compute<S>::T;
   using V2 = typename Vec2<C>::T;
   const int clex = blockIdx.x, k0 = blockIdx.y * kRestrictKB;
@@ -143,7 +160,16 @@ __global__ void __launch_bounds__(128) k_restrict(void* out, size_t site_stride,
       if (kk < kb) {
         cpx<C> v[12];
         if constexpr (sizeof(S) == 4) {
-          if (vbm) {
+          if (vbm16) {
+            const uint2* vb = vbm16 + ((size_t)(2 * (k0 + kk) + p) * bg.Vc + clex) * 6 * half;
+#pragma unroll
+            for (int cch = 0; cch < 6; ++cch) {
+              cpx<float> e0, e1;
+              unpack_half_chunk(vb[(size_t)cch * half + l], e0, e1);
+              v[2 * cch] = mk((C)e0.r, (C)e0.i);
+              v[2 * cch + 1] = mk((C)e1.r, (C)e1.i);
+            }
+          } else if (vbm) {
             const float4* vb = vbm + ((size_t)(2 * (k0 + kk) + p) * bg.Vc + clex) * 6 * half;
 #pragma unroll
             for (int cch = 0; cch < 6; ++cch) {
@@ -189,9 +215,11 @@ __global__ void __launch_bounds__(128) k_restrict(void* out, size_t site_stride,
   }
 }
 
+// v16 (FP32 only): FP16 copy of the vectors' chunks, read in place of vecs
 template <typename S>
 __global__ void __launch_bounds__(256) k_prolong(void* out, const void* coarse, const void* vecs, size_t vec_bytes,
-                                                 size_t half_bytes, int nvec, int p, DGeom g, BlockGeom bg) {
+                                                 size_t half_bytes, int nvec, int p, DGeom g, BlockGeom bg,
+                                                 const uint2* __restrict__ v16 = nullptr) {
   using C = typename Compute<S>::T;
   using V2 = typename Vec2<C>::T;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -205,8 +233,24 @@ __global__ void __launch_bounds__(256) k_prolong(void* out, const void* coarse, 
   for (int a = 0; a < 12; ++a) o[a] = mk((C)0, (C)0);
   for (int k = 0; k < nvec; ++k) {
     cpx<C> v[12];
-    const void* vk = reinterpret_cast<const char*>(vecs) + (size_t)k * vec_bytes + (size_t)p * half_bytes;
-    SpinorIO<S>::load(vk, g.Vh, i, v);
+    if constexpr (sizeof(S) == 4) {
+      if (v16) {
+        const uint2* vk = v16 + (size_t)(2 * k + p) * 6 * g.Vh;
+#pragma unroll
+        for (int cch = 0; cch < 6; ++cch) {
+          cpx<float> e0, e1;
+          unpack_half_chunk(vk[(size_t)cch * g.Vh + i], e0, e1);
+          v[2 * cch] = mk((C)e0.r, (C)e0.i);
+          v[2 * cch + 1] = mk((C)e1.r, (C)e1.i);
+        }
+      } else {
+        SpinorIO<S>::load(reinterpret_cast<const char*>(vecs) + (size_t)k * vec_bytes + (size_t)p * half_bytes, g.Vh,
+                          i, v);
+      }
+    } else {
+      SpinorIO<S>::load(reinterpret_cast<const char*>(vecs) + (size_t)k * vec_bytes + (size_t)p * half_bytes, g.Vh, i,
+                        v);
+    }
     V2 a0 = cv[k], a1 = cv[nvec + k];
     cpx<C> c0 = mk((C)a0.x, (C)a0.y), c1 = mk((C)a1.x, (C)a1.y);
 #pragma unroll
@@ -405,7 +449,7 @@ void launch_vec_blockmajor(void* out, const void* v32, int nvec, const Geom& g, 
 
 void launch_restrict(int prec, void* out, size_t site_stride, size_t row_stride, const void* in, const void* vecs,
                      int nvec, int p, const Geom& g, const BlockGeom& bg, bool accumulate, hipStream_t st,
-                     const void* vbm) {
+                     const void* vbm, const void* vbm16) {
   dim3 grid(bg.Vc, (nvec + kRestrictKB - 1) / kRestrictKB), block(128);
   size_t hb = spinor_bytes(prec, g.Vh);
   if (prec == WCMG_F64)
@@ -413,7 +457,8 @@ void launch_restrict(int prec, void* out, size_t site_stride, size_t row_stride,
                        nvec, p, dgeom(g), bg, (int)accumulate);
   else if (prec == WCMG_F32)
     hipLaunchKernelGGL(k_restrict<float>, grid, block, 0, st, out, site_stride, row_stride, in, vecs, 2 * hb, hb,
-                       nvec, p, dgeom(g), bg, (int)accumulate, reinterpret_cast<const float4*>(vbm));
+                       nvec, p, dgeom(g), bg, (int)accumulate, reinterpret_cast<const float4*>(vbm),
+                       reinterpret_cast<const uint2*>(vbm16));
   else
     hipLaunchKernelGGL(k_restrict<__half>, grid, block, 0, st, out, site_stride, row_stride, in, vecs, 2 * hb, hb,
                        nvec, p, dgeom(g), bg, (int)accumulate);
@@ -421,15 +466,23 @@ void launch_restrict(int prec, void* out, size_t site_stride, size_t row_stride,
 }
 
 void launch_prolong(int prec, void* out, const void* coarse, const void* vecs, int nvec, int p, const Geom& g,
-                    const BlockGeom& bg, hipStream_t st) {
+                    const BlockGeom& bg, hipStream_t st, const void* v16) {
   dim3 grid((g.Vh + 255) / 256), block(256);
   size_t hb = spinor_bytes(prec, g.Vh);
   if (prec == WCMG_F64)
     hipLaunchKernelGGL(k_prolong<double>, grid, block, 0, st, out, coarse, vecs, 2 * hb, hb, nvec, p, dgeom(g), bg);
   else if (prec == WCMG_F32)
-    hipLaunchKernelGGL(k_prolong<float>, grid, block, 0, st, out, coarse, vecs, 2 * hb, hb, nvec, p, dgeom(g), bg);
+    hipLaunchKernelGGL(k_prolong<float>, grid, block, 0, st, out, coarse, vecs, 2 * hb, hb, nvec, p, dgeom(g), bg,
+                       reinterpret_cast<const uint2*>(v16));
   else
     hipLaunchKernelGGL(k_prolong<__half>, grid, block, 0, st, out, coarse, vecs, 2 * hb, hb, nvec, p, dgeom(g), bg);
+  HIPCHK(hipGetLastError());
+}
+
+void launch_chunks_to_half(void* out, const void* in32, size_t nchunks, hipStream_t st) {
+  const size_t blocks = std::min<size_t>((nchunks + 255) / 256, 65535);
+  hipLaunchKernelGGL(k_chunks_to_half, dim3((unsigned)blocks), dim3(256), 0, st, reinterpret_cast<uint2*>(out),
+                     reinterpret_cast<const float4*>(in32), nchunks);
   HIPCHK(hipGetLastError());
 }
 

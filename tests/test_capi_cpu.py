@@ -84,11 +84,11 @@ def test_struct_layout_matches_header(tmp_path):
 #include "wcmg.h"
 int main(void) {
   printf("%zu %zu %zu\\n", sizeof(wcmg_lattice), sizeof(wcmg_mg_params), sizeof(wcmg_stats));
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", offsetof(wcmg_mg_params, tol), offsetof(wcmg_mg_params, nu_post),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", offsetof(wcmg_mg_params, tol), offsetof(wcmg_mg_params, nu_post),
          offsetof(wcmg_mg_params, setup_rq_tol), offsetof(wcmg_mg_params, seed), offsetof(wcmg_mg_params, coarsest),
          offsetof(wcmg_mg_params, cycle_mode), offsetof(wcmg_mg_params, setup_prec),
          offsetof(wcmg_mg_params, coarse_launch), offsetof(wcmg_mg_params, plain_max_iter), offsetof(wcmg_mg_params, mp_inner_tol),
-         offsetof(wcmg_mg_params, coarse_fp16));
+         offsetof(wcmg_mg_params, coarse_fp16), offsetof(wcmg_mg_params, transfer_fp16));
   printf("%zu %zu %zu %zu\\n", offsetof(wcmg_stats, inner_iters), offsetof(wcmg_stats, true_rel_res),
          offsetof(wcmg_stats, status), offsetof(wcmg_stats, inner_status));
   return 0;
@@ -103,7 +103,7 @@ int main(void) {
     M = _lib.MGParams
     assert offs == [M.tol.offset, M.nu_post.offset, M.setup_rq_tol.offset, M.seed.offset, M.coarsest.offset,
                     M.cycle_mode.offset, M.setup_prec.offset, M.coarse_launch.offset, M.plain_max_iter.offset,
-                    M.mp_inner_tol.offset, M.coarse_fp16.offset]
+                    M.mp_inner_tol.offset, M.coarse_fp16.offset, M.transfer_fp16.offset]
     offs = [int(v) for v in lines[2].split()]
     S = _lib.Stats
     assert offs == [S.inner_iters.offset, S.true_rel_res.offset, S.status.offset, S.inner_status.offset]

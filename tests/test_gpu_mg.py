@@ -290,3 +290,36 @@ def test_fp16_field_smoother_16x16x16x32():
     print("outer iterations F32 / F16 fields:", its, flush=True)
     assert its[w.F16] <= its[w.F32] + 3
     ctx.close()
+
+
+def test_fp16_transfer_vectors_16x16x16x32():
+    """Restriction and prolongation of the FP32 cycle with FP16 copies of the
+    null vectors (transfer_fp16 = 1; the coarse operator is still built from
+    the FP64 vectors): single and batched solves reach 1e-10 by the oracle's
+    FP64 residual, within two outer iterations of FP32 copies."""
+    cfg = inputs.config("c2_16x16x16x32")
+    dims = cfg["dims"]
+    op, ctx = make(dims, cfg["eps"], cfg["gauge_seed"], -0.25, cfg["csw"], ape=cfg["ape"])
+    base = dict(block=cfg["blocks"], nvec=cfg["nvec"], seed=cfg["setup_seed"])
+    ctx.set_mg_params(w.default_params(**base))
+    ctx.build_null_vectors()
+    ctx.build_coarse()
+    vecs = ctx.get_null_vectors()
+    s0 = cfg["source_seeds"][0]
+    b = np.stack([inputs.z2_source(dims, s) for s in (s0, s0 + 1)])
+    its = {}
+    for tf in (0, 1):
+        ctx.set_mg_params(w.default_params(transfer_fp16=tf, **base))
+        ctx.set_null_vectors(vecs)
+        ctx.build_coarse()
+        x, st = ctx.solve(canon(b[0], dims), w.MG_GCR, 1e-10)
+        res = norm(b[0].reshape(op.shape) - op.apply_D(x.cpu().numpy().reshape(op.shape))) / norm(b[0])
+        assert st[0]["status"] == "OK" and res <= 1e-10, (tf, res)
+        its[tf] = st[0]["iters"]
+        xb, stb = ctx.solve(canon(b, dims, 2), w.MG_GCR, 1e-10)
+        for r in range(2):
+            rr = norm(b[r].reshape(op.shape) - op.apply_D(xb[r].cpu().numpy().reshape(op.shape))) / norm(b[r])
+            assert stb[r]["status"] == "OK" and rr <= 1e-10, (tf, r, rr)
+    print("outer iterations FP32 / FP16 transfer vectors:", its, flush=True)
+    assert its[1] <= its[0] + 2
+    ctx.close()
