@@ -99,67 +99,96 @@ __device__ __forceinline__ cpx<double> alpha_of(const double* qa) {
   return d > 0.0 ? mk(qa[1] / d, qa[2] / d) : mk(0.0, 0.0);
 }
 
-// y -= sum_j (beta_j / ||q_j||^2) q_j, z likewise with w_j; optionally
-// partials of {||y||^2, <y, r>}
+// The single-vector GCR step (k_gcr_step_dev) for every right-hand side (row
+// r of beta, qa and cj at beta + r bs, qa + r qs, cj + r cjs); the last
+// launch of a step leaves the partials of ||r||^2
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_gcr_orth_b(MultiB m, int k, void* y, void* z, const void* r, size_t vs,
-                                                         size_t n, const double* beta, size_t bs, const double* qa,
-                                                         size_t qs, int do_red, RedB o) {
+__global__ void __launch_bounds__(kThreads) k_gcr_step_b(MultiB m, int j0, int k, int ktot, void* y, void* r,
+                                                         size_t vs, size_t n, const double* beta, size_t bs,
+                                                         double* qa, size_t qs, double* cj, size_t cjs, int last,
+                                                         RedB o) {
   const double* be = beta + (size_t)blockIdx.y * bs;
-  const double* q4 = qa + (size_t)blockIdx.y * qs;
+  double* q4 = qa + (size_t)blockIdx.y * qs;
   cpx<double> c[kMaxK];
 #pragma unroll
   for (int j = 0; j < kMaxK; ++j) {
-    const double d = j < k ? q4[4 * j] : 0.0;
-    c[j] = (j < k && d > 0.0) ? mk(be[2 * j] / d, be[2 * j + 1] / d) : mk(0.0, 0.0);
+    const double d = j < k ? q4[4 * (j0 + j)] : 0.0;
+    c[j] = (j < k && d > 0.0) ? mk(be[2 * (j0 + j)] / d, be[2 * (j0 + j) + 1] / d) : mk(0.0, 0.0);
   }
-  double v[3] = {0.0, 0.0, 0.0};
-  void* yr = row<T>(y, vs);
-  void* zr = row<T>(z, vs);
-  const void* rr = row<T>(r, vs);
-  GRID_STRIDE(i, n) {
-    cpx<double> a = ld<T>(yr, i), b = ld<T>(zr, i);
-#pragma unroll
-    for (int j = 0; j < kMaxK; ++j) {
-      if (j < k) {
-        a = a - c[j] * ld<T>(row<T>(m.v[j], vs), i);
-        b = b - c[j] * ld<T>(row<T>(m.w[j], vs), i);
+  cpx<double> alpha = mk(0.0, 0.0);
+  if (last) {
+    double qq = be[2 * ktot];
+    for (int j = 0; j < ktot; ++j) {
+      const double d = q4[4 * j];
+      if (d > 0.0) {
+        const double br = be[2 * j], bi = be[2 * j + 1];
+        qq -= (br * br + bi * bi) / d;
       }
     }
-    st<T>(yr, i, a);
-    st<T>(zr, i, b);
-    if (do_red) {
-      cpx<double> as = ld<T>(yr, i), rv = ld<T>(rr, i);
-      v[0] += as.r * as.r + as.i * as.i;
-      v[1] += as.r * rv.r + as.i * rv.i;
-      v[2] += as.r * rv.i - as.i * rv.r;
+    const cpx<double> qr = mk(be[2 * ktot + 2], -be[2 * ktot + 3]);
+    if (qq > 0.0) alpha = mk(qr.r / qq, qr.i / qq);
+    if (blockIdx.x == 0) {
+      if (threadIdx.x == 0) {
+        q4[4 * ktot] = qq;
+        q4[4 * ktot + 1] = qr.r;
+        q4[4 * ktot + 2] = qr.i;
+      }
+      double* cr = cj + (size_t)blockIdx.y * cjs;
+      for (int j = threadIdx.x; j < ktot; j += blockDim.x) {
+        const double d = q4[4 * j];
+        cr[2 * j] = d > 0.0 ? be[2 * j] / d : 0.0;
+        cr[2 * j + 1] = d > 0.0 ? be[2 * j + 1] / d : 0.0;
+      }
     }
   }
-  if (do_red) block_reduce_to<3>(v, part_row(o, 3));
-}
-
-template <typename T>
-__global__ void __launch_bounds__(kThreads) k_gcr_update_r_b(const void* q, void* r, size_t vs, size_t n,
-                                                             const double* qa, size_t qs, RedB o) {
-  const cpx<double> a = alpha_of(qa + (size_t)blockIdx.y * qs);
   double v[1] = {0.0};
-  const void* qr = row<T>(q, vs);
+  void* yr = row<T>(y, vs);
   void* rr = row<T>(r, vs);
   GRID_STRIDE(i, n) {
-    st<T>(rr, i, ld<T>(rr, i) - a * ld<T>(qr, i));
-    cpx<double> bs = ld<T>(rr, i);
-    v[0] += bs.r * bs.r + bs.i * bs.i;
+    cpx<double> a = ld<T>(yr, i);
+#pragma unroll
+    for (int j = 0; j < kMaxK; ++j)
+      if (j < k) a = a - c[j] * ld<T>(row<T>(m.v[j], vs), i);
+    st<T>(yr, i, a);
+    if (last) {
+      const cpx<double> as = mk((double)(T)a.r, (double)(T)a.i);
+      const cpx<double> b = ld<T>(rr, i) - alpha * as;
+      st<T>(rr, i, b);
+      const cpx<double> bs2 = mk((double)(T)b.r, (double)(T)b.i);
+      v[0] += bs2.r * bs2.r + bs2.i * bs2.i;
+    }
   }
-  block_reduce_to<1>(v, part_row(o, 1));
+  if (last) block_reduce_to<1>(v, part_row(o, 1));
 }
 
-// x += sum_j alpha_j z_j with alpha_j from qa slot j
+// per right-hand side (one thread each): (I + C) y = alpha by back
+// substitution, C from cmat row r (cmat + r cms, column j at 2 j ldc), alpha
+// from qa row r; y row r at y + r ys
+__global__ void k_gcr_coef_solve_b(const double* qa, size_t qs, const double* cmat, size_t cms, int ldc, double* y,
+                                   size_t ys, int kt, int nrhs) {
+  const int rr = blockIdx.x * blockDim.x + threadIdx.x;
+  if (rr >= nrhs) return;
+  const double* q4 = qa + (size_t)rr * qs;
+  const double* cm = cmat + (size_t)rr * cms;
+  double* yv = y + (size_t)rr * ys;
+  for (int i = kt - 1; i >= 0; --i) {
+    cpx<double> s = alpha_of(q4 + 4 * i);
+    for (int j = i + 1; j < kt; ++j) {
+      const cpx<double> cij = mk(cm[2 * ((size_t)j * ldc + i)], cm[2 * ((size_t)j * ldc + i) + 1]);
+      s = s - cij * mk(yv[2 * j], yv[2 * j + 1]);
+    }
+    yv[2 * i] = s.r;
+    yv[2 * i + 1] = s.i;
+  }
+}
+
+// x += sum_j coef_j z_j per right-hand side (coef row r at coef + r cs)
 template <typename T>
-__global__ void k_gcr_update_x_b(MultiB m, int k, void* x, size_t vs, size_t n, const double* qa, size_t qs) {
-  const double* q4 = qa + (size_t)blockIdx.y * qs;
+__global__ void k_multi_axpy_b(MultiB m, int k, void* x, size_t vs, size_t n, const double* coef, size_t cs) {
+  const double* cf = coef + (size_t)blockIdx.y * cs;
   cpx<double> c[kMaxK];
 #pragma unroll
-  for (int j = 0; j < kMaxK; ++j) c[j] = j < k ? alpha_of(q4 + 4 * j) : mk(0.0, 0.0);
+  for (int j = 0; j < kMaxK; ++j) c[j] = j < k ? mk(cf[2 * j], cf[2 * j + 1]) : mk(0.0, 0.0);
   void* xr = row<T>(x, vs);
   GRID_STRIDE(i, n) {
     cpx<double> acc = ld<T>(xr, i);
@@ -234,45 +263,39 @@ void blas_multi_cdot_b(int prec, const void* const* v, int k, const void* y, siz
   }
 }
 
-void blas_gcr_orth_b(int prec, const void* const* q, const void* const* w, int k, void* y, void* z, const void* r,
-                     size_t vs, size_t n, int nrhs, const double* beta, size_t bs, const double* qa, size_t qs,
-                     const RedB& o, hipStream_t st) {
+void blas_gcr_step_b(int prec, const void* const* q, int k, void* y, void* r, size_t vs, size_t n, int nrhs,
+                     const double* beta, size_t bs, double* qa, size_t qs, double* cj, size_t cjs, const RedB& o,
+                     hipStream_t st) {
   check_batch(nrhs);
   if (k == 0) {
     MultiB m{};
-    DISPATCH_B(prec, k_gcr_orth_b, red_grid_b(n, nrhs), m, 0, y, z, r, vs, n, beta, bs, qa, qs, 1, o);
-    finalize_b(o, 3, 3, n, nrhs, st);
+    DISPATCH_B(prec, k_gcr_step_b, red_grid_b(n, nrhs), m, 0, 0, 0, y, r, vs, n, beta, bs, qa, qs, cj, cjs, 1, o);
+    finalize_b(o, 1, 1, n, nrhs, st);
     return;
   }
   for (int j0 = 0; j0 < k; j0 += kMaxK) {
     const int kk = std::min(kMaxK, k - j0);
     MultiB m{};
-    for (int j = 0; j < kk; ++j) {
-      m.v[j] = q[j0 + j];
-      m.w[j] = w[j0 + j];
-    }
+    for (int j = 0; j < kk; ++j) m.v[j] = q[j0 + j];
     const int last = j0 + kk == k;
-    DISPATCH_B(prec, k_gcr_orth_b, red_grid_b(n, nrhs), m, kk, y, z, r, vs, n, beta + 2 * j0, bs, qa + 4 * j0, qs,
-               last, o);
-    if (last) finalize_b(o, 3, 3, n, nrhs, st);
+    DISPATCH_B(prec, k_gcr_step_b, red_grid_b(n, nrhs), m, j0, kk, k, y, r, vs, n, beta, bs, qa, qs, cj, cjs, last,
+               o);
+    if (last) finalize_b(o, 1, 1, n, nrhs, st);
   }
 }
 
-void blas_gcr_update_r_b(int prec, const void* q, void* r, size_t vs, size_t n, int nrhs, const double* qa_k,
-                         size_t qs, const RedB& o, hipStream_t st) {
+void blas_gcr_update_x_raw_b(int prec, const void* const* z, int kt, void* x, size_t vs, size_t n, int nrhs,
+                             const double* qa, size_t qs, const double* cmat, size_t cms, int ldc, double* y,
+                             size_t ys, hipStream_t st) {
   check_batch(nrhs);
-  DISPATCH_B(prec, k_gcr_update_r_b, red_grid_b(n, nrhs), q, r, vs, n, qa_k, qs, o);
-  finalize_b(o, 1, 1, n, nrhs, st);
-}
-
-void blas_gcr_update_x_b(int prec, const void* const* z, int k, void* x, size_t vs, size_t n, int nrhs,
-                         const double* qa, size_t qs, hipStream_t st) {
-  check_batch(nrhs);
-  for (int j0 = 0; j0 < k; j0 += kMaxK) {
-    const int kk = std::min(kMaxK, k - j0);
+  if (kt <= 0) return;
+  hipLaunchKernelGGL(k_gcr_coef_solve_b, dim3(1), dim3(64), 0, st, qa, qs, cmat, cms, ldc, y, ys, kt, nrhs);
+  HIPCHK(hipGetLastError());
+  for (int j0 = 0; j0 < kt; j0 += kMaxK) {
+    const int kk = std::min(kMaxK, kt - j0);
     MultiB m{};
     for (int j = 0; j < kk; ++j) m.v[j] = z[j0 + j];
-    DISPATCH_B(prec, k_gcr_update_x_b, ew_grid_b(n, nrhs), m, kk, x, vs, n, qa + 4 * j0, qs);
+    DISPATCH_B(prec, k_multi_axpy_b, ew_grid_b(n, nrhs), m, kk, x, vs, n, y + 2 * j0, ys);
   }
 }
 

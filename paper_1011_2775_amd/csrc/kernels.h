@@ -166,13 +166,14 @@ void blas_cdot_norm_b(int prec, const void* x, const void* y, size_t vs, size_t 
                       hipStream_t st);
 void blas_multi_cdot_b(int prec, const void* const* v, int k, const void* y, size_t vs, size_t n, int nrhs,
                        const RedB& o, hipStream_t st);
-void blas_gcr_orth_b(int prec, const void* const* q, const void* const* w, int k, void* y, void* z, const void* r,
-                     size_t vs, size_t n, int nrhs, const double* beta, size_t bs, const double* qa, size_t qs,
-                     const RedB& o, hipStream_t st);
-void blas_gcr_update_r_b(int prec, const void* q, void* r, size_t vs, size_t n, int nrhs, const double* qa_k,
-                         size_t qs, const RedB& o, hipStream_t st);
-void blas_gcr_update_x_b(int prec, const void* const* z, int k, void* x, size_t vs, size_t n, int nrhs,
-                         const double* qa, size_t qs, hipStream_t st);
+// blas_gcr_step_dev / blas_gcr_update_x_raw for every right-hand side (rows of
+// beta, qa, cj / cmat and y bs, qs, cjs / cms and ys doubles apart)
+void blas_gcr_step_b(int prec, const void* const* q, int k, void* y, void* r, size_t vs, size_t n, int nrhs,
+                     const double* beta, size_t bs, double* qa, size_t qs, double* cj, size_t cjs, const RedB& o,
+                     hipStream_t st);
+void blas_gcr_update_x_raw_b(int prec, const void* const* z, int kt, void* x, size_t vs, size_t n, int nrhs,
+                             const double* qa, size_t qs, const double* cmat, size_t cms, int ldc, double* y,
+                             size_t ys, hipStream_t st);
 void blas_mr_update_b(int prec, const double* coef, size_t cs, void* x, void* r, const void* Ar, size_t vs, size_t n,
                       int nrhs, hipStream_t st);
 

@@ -242,6 +242,7 @@ struct GcrSpaceB {
   int nrhs = 0;
   std::vector<DBuf> Z, Q;
   DBuf r, scal;
+  DBuf cm;  // per right-hand side: orthogonalisation coefficients [slot][slot], then update coefficients
   size_t bytes() const { return (size_t)nrhs * vs * (prec == WCMG_F64 ? 16 : 8); }
   void ensure(int restart);
 };

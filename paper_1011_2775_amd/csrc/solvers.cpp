@@ -213,6 +213,8 @@ void GcrSpaceB::ensure(int restart) {
   if (r.n < b) r.alloc(b);
   const size_t sb = (size_t)kMaxBatch * kGcrCoefs * sizeof(double);
   if (scal.n < sb) scal.alloc(sb);
+  const size_t cb = (size_t)kMaxBatch * (2 * kMaxRestart * kMaxRestart + 2 * kMaxRestart) * sizeof(double);
+  if (cm.n < cb) cm.alloc(cb);
 }
 
 std::vector<KrylovResult> gcr_b(Ctx& c, GcrSpaceB& S, const OpFn& A, const OpFn* K, void* x, const void* b,
@@ -262,7 +264,11 @@ std::vector<KrylovResult> gcr_b(Ctx& c, GcrSpaceB& S, const OpFn& A, const OpFn*
   double* beta = cbase;
   double* qa = cbase + 2 * (kMaxRestart + 16);
   const size_t cs = kGcrCoefs;
-  std::vector<const void*> Qp(restart), Zp(restart);
+  // directions kept raw, as in gcr(): per right-hand side the orthogonalisation
+  // coefficients [slot][slot] and then the cycle's update coefficients
+  double* cmb = S.cm.as<double>();
+  const size_t cms = 2 * kMaxRestart * kMaxRestart + 2 * kMaxRestart;
+  std::vector<const void*> Qp(restart), Zp(restart), Dp(restart + 2);
   int iters = 0;
   if (!(all && !fixed)) {
     while (iters < maxiter) {
@@ -278,10 +284,12 @@ std::vector<KrylovResult> gcr_b(Ctx& c, GcrSpaceB& S, const OpFn& A, const OpFn*
         else
           each([&](int, size_t o) { blas_copy(prec, (char*)z + o, (const char*)r + o, n, st); });
         A(q, z);
-        if (k > 0) blas_multi_cdot_b(prec, Qp.data(), k, q, vs, n, nr, R.outb(beta, cs), st);
-        blas_gcr_orth_b(prec, Qp.data(), Zp.data(), k, q, z, r, vs, n, nr, beta, cs, qa, cs, R.outb(qa + 4 * k, cs),
-                        st);
-        blas_gcr_update_r_b(prec, q, r, vs, n, nr, qa + 4 * k, cs, R.outb(qa + 4 * k + 3, cs), st);
+        for (int j = 0; j < k; ++j) Dp[j] = Qp[j];
+        Dp[k] = q;
+        Dp[k + 1] = r;
+        blas_multi_cdot_b(prec, Dp.data(), k + 2, q, vs, n, nr, R.outb(beta, cs), st);
+        blas_gcr_step_b(prec, Qp.data(), k, q, r, vs, n, nr, beta, cs, qa, cs, cmb + (size_t)2 * kMaxRestart * k, cms,
+                        R.outb(qa + 4 * k + 3, cs), st);
         ++k;
         ++iters;
         if (fixed) {
@@ -316,7 +324,9 @@ std::vector<KrylovResult> gcr_b(Ctx& c, GcrSpaceB& S, const OpFn& A, const OpFn*
           break;
         }
       }
-      if (k > 0) blas_gcr_update_x_b(prec, Zp.data(), k, x, vs, n, nr, qa, cs, st);
+      if (k > 0)
+        blas_gcr_update_x_raw_b(prec, Zp.data(), k, x, vs, n, nr, qa, cs, cmb, cms, kMaxRestart,
+                                cmb + (size_t)2 * kMaxRestart * kMaxRestart, cms, st);
       if (fixed) break;
       // true residuals at the end of every cycle
       A(r, x);
