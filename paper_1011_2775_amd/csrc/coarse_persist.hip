@@ -442,6 +442,7 @@ struct PArgs {
   unsigned* lflags;  // neighbour-wait lines of the one-site kernel, one per workgroup
   double tol;
   int Vh, n, restart, maxiter, fixed, G, stride;
+  int trust;  // a cycle that met the tolerance by its recurrence residual ends the solve (no true residual)
   int sbytes;   // one-site kernel: LDS bytes before the Krylov basis
   int pl;       // one-site kernel: hop matrix column rounds staged in LDS
   int res_off;  // one-site kernel: LDS byte offset of the even site's resident hop blocks (-1: none)
@@ -697,6 +698,7 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr(PArgs a) {
     }
     if (!sync_sum(0)) return;
     int k = 0;
+    bool rec_conv = false;  // the cycle met the tolerance by its recurrence residual
     for (;;) {
       V2* Qk = Qv(k);
       V2* Zk = Zv(k);
@@ -849,9 +851,17 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr(PArgs a) {
         status = WCMG_ENAN;
         break;
       }
-      if (k >= a.restart || iters >= a.maxiter || (!a.fixed && sqrt(rn2) <= target)) break;
+      if (!a.fixed && sqrt(rn2) <= target) {
+        rec_conv = true;
+        break;
+      }
+      if (k >= a.restart || iters >= a.maxiter) break;
     }
     if (status || a.fixed) break;
+    if (a.trust && rec_conv) {
+      conv = true;
+      break;
+    }
     // true residual r = b_r - D_r y at the end of the cycle (q_raw as scratch)
     for (int i = w; i < Vh; i += W) site_hop<S, MT>(a, Vh + i, a.y, nullptr, 1.0, nullptr, a.t, vin, hp);
     if (!sync_sum(0)) return;
@@ -1248,6 +1258,7 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
     if (tid < n) Zs[tid] = rm[tid];
     if (!sync_sum(0)) return;
     int k = 0;
+    bool rec_conv = false;  // the cycle met the tolerance by its recurrence residual
     for (;;) {
       // q = D_r z_k = r - Ytilde_eo t on the even site (stored for the odd neighbours);
       // <q_j, q>, ||q||^2, <q, r> and ||r_k||^2
@@ -1378,7 +1389,10 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
           status = WCMG_ENAN;
           break;
         }
-        if (!a.fixed && sqrt(rn2) <= target) break;
+        if (!a.fixed && sqrt(rn2) <= target) {
+          rec_conv = true;
+          break;
+        }
       }
       // wavefront 0, lane j < k: c_j = <q_j, q> / ||q_j||^2 and |<q_j, q>|^2 / ||q_j||^2
       // (the same divisions as the strided kernel, done once instead of per
@@ -1484,6 +1498,10 @@ __global__ void __launch_bounds__(kPT) k_coarse_gcr_site(PArgs a) {
     if (tid < n) stc(y + eo + tid, ym[tid]);
     if (!sync_sum(0)) return;
     if (status || a.fixed) break;
+    if (a.trust && rec_conv) {
+      conv = true;
+      break;
+    }
     // true residual r = b_r - D_r y at the end of the cycle
     if (tagged) ++tver;
     hop1<S, MT>(a, Vh + w, nbO, y, nullptr, nullptr, 1.0, nullptr, t, tm, vin, hp, pre, nullptr, -1, 0,
@@ -1603,6 +1621,7 @@ void launch_coarse_gcr_persistent(int prec, const CoarseGcrArgs& g, hipStream_t 
   a.restart = g.restart;
   a.maxiter = g.maxiter;
   a.fixed = g.fixed;
+  a.trust = g.trust;
   a.stride = (int)coarse_gcr_persistent_part_doubles();
   a.res_off = -1;
   a.tags = nullptr;

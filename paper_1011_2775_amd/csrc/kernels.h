@@ -304,6 +304,8 @@ struct CoarseGcrArgs {
   double tol;
   int Vh, n, restart, maxiter, fixed, grid;
   int general;  // always the strided kernel
+  int trust;    // a cycle that met the tolerance by its recurrence residual ends the solve without
+                // recomputing the true residual (for a preconditioner's loose tolerance)
   int mat16;    // Yt holds FP16 hop blocks (FP32 vectors and arithmetic)
   void* tags;   // tagged slots of the one-site FP32 kernel (coarse_gcr_persistent_tag_bytes; zeroed
                 // whenever the barrier lines are; nullptr: flags and barriers at every step)

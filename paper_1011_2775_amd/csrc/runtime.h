@@ -299,7 +299,7 @@ bool persistent_available(PersistWork& w, int prec, const CoarseLevel& C, int re
 // out = approximate Dhat^-1 in (full coarse vectors); t: full scratch, y, r, br: >= half vectors
 void persistent_launch(Ctx& c, PersistWork& w, CoarseLevel& C, int prec, void* out, const void* in, void* t, void* y,
                        void* r, void* br, double tol, int restart, int maxiter, bool fixed,
-                       bool general = false, bool mat16 = false);
+                       bool general = false, bool mat16 = false, bool trust = false);
 // iterations since the last collect; status (optional) gets the first failure code
 long persistent_collect(Ctx& c, PersistWork& w, int* status = nullptr);
 // the persistent launch on caller-provided buffers (sizes as for launch_coarse_gcr_persistent;
@@ -313,7 +313,7 @@ struct PersistBufs {
 };
 void persistent_launch_bufs(Ctx& c, int grid, const PersistBufs& B, CoarseLevel& C, int prec, void* out,
                             const void* in, void* t, void* y, void* r, void* br, double tol, int restart,
-                            int maxiter, bool fixed, bool general, bool mat16 = false);
+                            int maxiter, bool fixed, bool general, bool mat16 = false, bool trust = false);
 
 // ------------------------------------------------------------------ allocation-free coarse solve
 // One static device array per GPU (noalloc.hip) holds every work buffer of

@@ -635,7 +635,7 @@ bool persistent_available(PersistWork& w, int prec, const CoarseLevel& C, int re
 
 void persistent_launch_bufs(Ctx& c, int grid, const PersistBufs& B, CoarseLevel& C, int prec, void* out,
                             const void* in, void* t, void* y, void* r, void* br, double tol, int restart,
-                            int maxiter, bool fixed, bool general, bool mat16) {
+                            int maxiter, bool fixed, bool general, bool mat16, bool trust) {
   CoarseGcrArgs a{};
   const int pi = prec == WCMG_F64 ? 0 : 1;
   if (mat16 && (prec != WCMG_F32 || !C.Yt16.p)) fail(WCMG_EINVAL, "FP16 hop blocks need FP32 vectors");
@@ -664,6 +664,7 @@ void persistent_launch_bufs(Ctx& c, int grid, const PersistBufs& B, CoarseLevel&
   a.fixed = fixed ? 1 : 0;
   a.grid = grid;
   a.general = general ? 1 : 0;
+  a.trust = trust ? 1 : 0;
   a.tags = B.tags;
   a.tag_bytes = B.tag_bytes;
   launch_coarse_gcr_persistent(prec, a, c.st);
@@ -671,7 +672,7 @@ void persistent_launch_bufs(Ctx& c, int grid, const PersistBufs& B, CoarseLevel&
 
 void persistent_launch(Ctx& c, PersistWork& w, CoarseLevel& C, int prec, void* out, const void* in, void* t, void* y,
                        void* r, void* br, double tol, int restart, int maxiter, bool fixed, bool general,
-                       bool mat16) {
+                       bool mat16, bool trust) {
   const size_t cs = prec == WCMG_F64 ? 16 : 8;
   const size_t hv = (size_t)C.cg.Vh * C.cg.n;
   restart = std::min(restart, std::max(1, maxiter));
@@ -689,7 +690,8 @@ void persistent_launch(Ctx& c, PersistWork& w, CoarseLevel& C, int prec, void* o
     HIPCHK(hipMemsetAsync(w.tags.p, 0, w.tags.n, c.st));
   }
   PersistBufs B{w.q.p, w.z.p, w.t.p, w.qraw.p, w.part.as<double>(), w.ctl.p, w.tags.p, tb};
-  persistent_launch_bufs(c, w.grid, B, C, prec, out, in, t, y, r, br, tol, restart, maxiter, fixed, general, mat16);
+  persistent_launch_bufs(c, w.grid, B, C, prec, out, in, t, y, r, br, tol, restart, maxiter, fixed, general, mat16,
+                         trust);
   w.pending = true;
 }
 
@@ -923,7 +925,7 @@ struct MGSolver {
     if (c.timer.on) c.timer.begin(id, &e);
     persistent_launch(c, V.pw, *L.levels[li], cp, out, in, V.rfull.p, V.cy.p, V.res.p, V.cbr.p, p.tol[li],
                       p.restart[li], p.max_iter[li], fixed(), p.coarse_launch == 2,
-                      p.coarse_fp16 != 0 && cp == WCMG_F32);
+                      p.coarse_fp16 != 0 && cp == WCMG_F32, true);
     if (e) c.timer.end(id, e);
   }
 
