@@ -5,12 +5,14 @@
 //
 //   b_r = b_e - Ytilde_eo b_o
 //   GCR(m) on D_r_hat = 1 - Ytilde_eo Ytilde_oe, y_0 = 0, stopping at
-//   ||r|| <= tol ||b_r|| (true residual recomputed at the end of every cycle)
+//   ||r|| <= tol ||b_r|| (true residual recomputed at the end of every cycle,
+//   except in a launch that trusts a recurrence residual which met the
+//   tolerance: the multigrid cycle's coarse solves)
 //   c_e = X_ee^-1 y,  c_o = X_oo^-1 (b_o - Ytilde_oe y)
 //
 // Every workgroup owns the even sites w, w + W, w + 2W, ... (W workgroups)
 // and the odd sites at the same offsets; the hops of a site are computed by
-// its whole workgroup (column groups as in the stand-alone stencil), and
+// its whole workgroup (in the thread layout of site_matvec), and
 // the BLAS-1 work of a step touches only the workgroup's own sites, so the
 // hop output of a site is consumed by the workgroup that wrote it.  Global
 // sums go through per-workgroup partials: after a grid barrier every
@@ -28,7 +30,8 @@
 // T_k = Ytilde_oe q_k = Ytilde_oe q - sum_j c_j T_j (the hop of q reads the
 // neighbours' q, complete after the first barrier); the second barrier
 // publishes t and ||r||^2.  The true residual at the end of every cycle
-// removes what rounding these recurrences add.
+// removes what rounding these recurrences add (a launch for a
+// preconditioner's loose tolerance may end on the recurrence residual).
 //
 // The grid barrier is a flag barrier: every workgroup stores the barrier's
 // epoch to a cache line of its own and waits until every line holds it, so
