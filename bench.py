@@ -101,6 +101,9 @@ def coarse_step_bytes(coarse_sites_h, coarse_n, cs=8, mat_cs=None):
 PREC_NAMES = ["double", "float", "__half"]
 
 
+MI355X_CUS = 256
+
+
 def kernel_table(ctxs, vh, coarse_sites_h, coarse_n, coarse_steps=0, coarse_fp16=False):
     """Per timed kernel id: launches, mean duration, algorithmic bytes per launch.
     coarse_steps: GCR steps the persistent coarse solves took in total;
@@ -117,7 +120,10 @@ def kernel_table(ctxs, vh, coarse_sites_h, coarse_n, coarse_steps=0, coarse_fp16
         if kid < 18:
             prec, rest = divmod(kid, 6)
             diag, postinv = divmod(rest, 2)
-            name = "dslash_kernel<%s,%d,%s>" % (PREC_NAMES[prec], diag, str(bool(postinv)).lower())
+            # the library runs its unpinned variant on grids of at most two 256-thread
+            # workgroups per compute unit (MI355X: 256 compute units)
+            base = "dslash_kernel_wide" if (vh + 255) // 256 <= 2 * MI355X_CUS else "dslash_kernel"
+            name = "%s<%s,%d,%s>" % (base, PREC_NAMES[prec], diag, str(bool(postinv)).lower())
             bytes_launch = dslash_bytes_per_site(prec, diag, postinv) * vh
             flops = dslash_flops_per_site(diag, postinv) * vh
         elif kid >= 64:

@@ -65,3 +65,15 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert p.returncode != 0
     assert "single GPU" in p.stderr and "--gpus 2" in p.stderr
+
+
+def test_kernel_table_names_the_launched_hop_variant():
+    """The hop rows name the kernel the library launches at that volume: the
+    unpinned small-grid variant at 16^3x32, the pinned one at 24^3x64."""
+    class Ctx:
+        def timer_read(self, kid):
+            return (4, 0.1) if kid in (7, 8) else (0, 0.0)
+    small = bench.kernel_table([Ctx()], 16 ** 3 * 32 // 2, 256, 48)
+    large = bench.kernel_table([Ctx()], 24 ** 3 * 64 // 2, 256, 48)
+    assert {r["kernel"] for r in small} == {"dslash_kernel_wide<float,0,true>", "dslash_kernel_wide<float,1,false>"}
+    assert {r["kernel"] for r in large} == {"dslash_kernel<float,0,true>", "dslash_kernel<float,1,false>"}
