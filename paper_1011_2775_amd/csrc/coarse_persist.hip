@@ -444,7 +444,7 @@ struct PArgs {
   int* info;         // [0] iterations (accumulated), [1] status, [2] abort
   unsigned* lflags;  // neighbour-wait lines of the one-site kernel, one per workgroup
   double tol;
-  int Vh, n, restart, maxiter, fixed, G, stride;
+  int Vh, n, restart, maxiter, fixed, stride;
   int trust;  // a cycle that met the tolerance by its recurrence residual ends the solve (no true residual)
   int sbytes;   // one-site kernel: LDS bytes before the Krylov basis
   int pl;       // one-site kernel: hop matrix column rounds staged in LDS
@@ -1569,9 +1569,7 @@ int coarse_gcr_persistent_grid(int prec, int n, int Vh) {
   HIPCHK(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
   if (!coop || n % 2 || n > 256 || Vh <= 0) return 0;
   const size_t cb = prec == WCMG_F64 ? 16 : 8;
-  const int G = persist_groups(n);
   const size_t shm = std::max((size_t)(8 * n + mv_col_waves(n) * n) * cb, (size_t)2 * kPT * 16);
-  (void)G;
   int per = 0;
   if (prec == WCMG_F64)
     HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_coarse_gcr<double, double2>, kPT, shm));
@@ -1630,7 +1628,6 @@ void launch_coarse_gcr_persistent(int prec, const CoarseGcrArgs& g, hipStream_t 
   a.tags = nullptr;
   a.tag_bytes = 0;
   const int G = persist_groups(n);
-  a.G = G;
   const size_t cb = prec == WCMG_F64 ? 16 : 8;
   const size_t shm = std::max((size_t)(8 * n + mv_col_waves(n) * n) * cb, (size_t)2 * kPT * 16);
   a.lflags = reinterpret_cast<unsigned*>(reinterpret_cast<char*>(g.bar) + kPersistLocalOffset);
